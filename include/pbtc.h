@@ -1,0 +1,242 @@
+/*
+ * pbtc.h -- C interface of libpbtc, a treecode-accelerated boundary-element
+ * Poisson-Boltzmann solver for AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv:1309.4018 (Cooper, Bardhan, Barba).  The problem statement
+ * follows sec. 2.1 (Eq. pde: Poisson with point charges inside the molecule,
+ * linearized Poisson-Boltzmann with inverse Debye length kappa in the
+ * solvent, continuity of the potential and of eps d phi/dn on every
+ * interface) and sec. 2.2 (single- and multi-surface problems: Stern layers
+ * and solvent-filled cavities add surfaces).  The discrete operator is the
+ * constant-element, centroid-collocation BEM of sec. 2.2 (Eqs. nBEM_disc,
+ * matrix, matel), evaluated by the Cartesian-Taylor treecode of sec. 2.3
+ * (Eqs. nbody, taylor, multexp, MAC) with semi-analytic self integrals and a
+ * K_fine-point rule in the near-singular zone; the system is solved by GMRES
+ * (sec. 2.3, one operator evaluation per iteration, tree and lists built
+ * once) and the solvation energy follows Eqs. reac_integral and solv.
+ *
+ * Conventions
+ *   Units: angstrom, elementary charge e, kJ/mol.
+ *   Regions: permittivity eps > 0 and kappa >= 0 (kappa = 0: Laplace).
+ *   Surfaces: closed triangulations, each separating an inner region from an
+ *     outer region; triangles counter-clockwise seen from the outer region,
+ *     so the normal points from the inner into the outer region.
+ *   Unknowns of surface s: phi_s (potential at each panel centre) and
+ *     psi_s = d phi / d n on the inner side; the outer-side derivative is
+ *     (eps_inner / eps_outer) psi_s.
+ *   Unknown vector layout (pbtc_matvec): for each surface in creation order,
+ *     [phi_s (n_s), psi_s (n_s)], FP64.
+ *
+ * Ownership
+ *   Host input arrays belong to the caller and are copied during the call.
+ *   Output buffers are caller-allocated.  All device memory is ONE workspace
+ *   that the caller allocates (any device allocation >= the size that
+ *   pbtc_plan_create reports) and passes to every device call together with
+ *   a hipStream_t (NULL = the default stream).  The library never calls
+ *   hipMalloc/hipFree.  A workspace holds the plan's device state between
+ *   calls (tree, lists, near-field tables, solution); passing a different
+ *   workspace pointer makes the next call rebuild that state.
+ *
+ * Errors
+ *   Every int-returning function returns PBTC_OK (0) or a negative code.
+ *   pbtc_last_error(plan) returns the message of the plan's last error
+ *   (pbtc_last_error(NULL): the calling thread's last error of a call that
+ *   has no plan).  No C++ exception crosses this interface.
+ *
+ * Threading
+ *   A plan or problem must not be used by two threads at once; different
+ *   plans are independent.  Device work is issued on the caller's stream;
+ *   calls that return host results synchronise that stream.
+ */
+#ifndef PBTC_H
+#define PBTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PBTC_VERSION_MAJOR 1
+#define PBTC_VERSION_MINOR 0
+
+#define PBTC_OK 0
+#define PBTC_EINVAL -1     /* bad argument, NaN/Inf, unknown id, bad call order */
+#define PBTC_EMESH -2      /* degenerate panel, open or mis-oriented surface */
+#define PBTC_ECHARGE -3    /* a charge is not inside its region */
+#define PBTC_EWORKSPACE -4 /* workspace too small; pbtc_result.workspace_needed */
+#define PBTC_EDEVICE -5    /* HIP runtime error */
+#define PBTC_ENOCONV -6    /* GMRES hit max_iter; outputs hold the last iterate */
+
+/* Arithmetic of the operator kernels (tree passes, P2P, M2P, near field). */
+#define PBTC_FP64 0         /* everything in FP64 */
+#define PBTC_FP32_REFINED 1 /* FP32 operator inside FP64 iterative refinement */
+#define PBTC_FP32 2         /* FP32 operator, FP64 Krylov; no refinement */
+
+/* How the operator is evaluated. */
+#define PBTC_OP_TREECODE 0 /* Taylor treecode: M2P where the MAC holds, P2P else */
+#define PBTC_OP_DIRECT 1   /* every pair by the K-point rule (dense, O(N^2)) */
+
+typedef struct pbtc_problem pbtc_problem;
+typedef struct pbtc_plan pbtc_plan;
+
+typedef struct {
+  /* discretisation (sec. 3, parameter tables) */
+  int K;         /* Gauss points per panel: 1, 3, 4 or 7 */
+  int K_fine;    /* points of the near-singular rule: 7 or 19 */
+  int N_k;       /* Gauss-Legendre points per sub-triangle of the self term */
+  double thres;  /* near-singular zone: |x - centre_j| < thres * L_j, L = sqrt(2A) */
+  /* treecode (sec. 2.3) */
+  double theta;  /* MAC: accept a cell when theta * r_tb > r_b */
+  int P;         /* Taylor order: 2, 4, 6, 8 or 10 */
+  int ncrit;     /* split a cell holding >= ncrit sources; 0 = automatic */
+  int direct_below; /* a MAC-accepted cell with fewer sources goes to P2P; -1 = auto */
+  /* solver (sec. 2.3: Krylov; tolerance from the parameter tables) */
+  double tol;       /* stop at ||b - A x|| / ||b|| <= tol */
+  int restart;      /* GMRES restart length m (<= 256) */
+  int max_iter;     /* total GMRES iterations (all restarts, all refinements) */
+  int precision;    /* PBTC_FP64, PBTC_FP32_REFINED or PBTC_FP32 */
+  int op;           /* PBTC_OP_TREECODE or PBTC_OP_DIRECT */
+  double inner_tol; /* FP32_REFINED: relative tolerance floor of inner solves */
+  int max_refine;   /* FP32_REFINED: maximum outer refinement steps */
+  int validate_charges; /* 1: check every charge lies inside its region */
+} pbtc_params;
+
+typedef struct {
+  double energy_kJmol;   /* solvation energy, Eq. solv */
+  int n_iter;            /* GMRES iterations (all restarts / refinements) */
+  int converged;         /* 1 if the explicit residual met tol */
+  double final_rel_res;  /* explicit ||b - A x|| / ||b|| (FP64 operator) */
+  int n_matvec_fp32;     /* operator evaluations in FP32 */
+  int n_matvec_fp64;     /* operator evaluations in FP64 */
+  int n_refine;          /* outer refinement steps (FP32_REFINED) */
+  double t_setup_s;      /* device set-up: geometry, tree, lists, near field, RHS */
+  double t_solve_s;      /* Krylov solve incl. refinement */
+  double t_energy_s;     /* reaction potential + energy */
+  double n_p2p_pairs;    /* per operator evaluation: (target, Gauss point) pairs in P2P */
+  double n_m2p_evals;    /* per operator evaluation: (target, cell) Taylor evaluations */
+  double n_dense_equiv;  /* per operator evaluation: sum over regions of targets x sources */
+  double n_near_entries; /* near-field correction entries */
+  size_t workspace_needed; /* bytes (set on PBTC_EWORKSPACE and on success) */
+} pbtc_result;
+
+/* Library version; never fails. */
+int pbtc_version(int* major, int* minor);
+
+/* Problem description (host only). */
+int pbtc_problem_create(pbtc_problem** out);
+void pbtc_problem_destroy(pbtc_problem* p);
+/* Adds a region; ids are 0, 1, 2, ... in call order.  EINVAL: eps <= 0,
+ * kappa < 0 or not finite. */
+int pbtc_add_region(pbtc_problem* p, double eps, double kappa, int* region_id);
+/* Adds a closed surface: verts (nv x 3, row-major), tris (np x 3 vertex
+ * indices, counter-clockwise seen from outer_region).  The arrays are copied.
+ * EINVAL: unknown or equal region ids, sizes < 1, indices out of range. */
+int pbtc_add_surface(pbtc_problem* p, const double* verts, int64_t nv, const int32_t* tris,
+                     int64_t np, int inner_region, int outer_region, int* surface_id);
+/* Sets (replaces) the point charges of one region: xyz (nq x 3), q (nq). */
+int pbtc_set_charges(pbtc_problem* p, int region_id, const double* xyz, const double* q,
+                     int64_t nq);
+
+/* Defaults: K=4, K_fine=19, N_k=5, thres=2.0, theta=0.5, P=6, ncrit=0,
+ * direct_below=-1, tol=1e-5, restart=100, max_iter=1000,
+ * precision=PBTC_FP32_REFINED, op=PBTC_OP_TREECODE, inner_tol=1e-6,
+ * max_refine=10, validate_charges=1. */
+int pbtc_params_default(pbtc_params* prm);
+
+/* Host-side checks only (no device work): parameter ranges; every region is
+ * bounded by a surface; every surface closed (each directed edge matched by
+ * its reverse exactly once), non-degenerate and oriented with its normal
+ * toward the outer region (positive enclosed volume for an outer region
+ * that contains infinity or encloses the surface); every charge finite and
+ * (if validate_charges) inside its region (ray parity against the region's
+ * bounding surfaces).  Returns EINVAL, EMESH or ECHARGE with a message. */
+int pbtc_validate(const pbtc_problem* p, const pbtc_params* prm);
+
+/* Validates, fixes the block structure (which surface pairs interact in
+ * which region) and returns the workspace size for pbtc_setup/pbtc_solve.
+ * The size includes an estimate for the interaction lists; pbtc_setup
+ * returns EWORKSPACE with the exact need if the estimate was low. */
+int pbtc_plan_create(const pbtc_problem* p, const pbtc_params* prm, pbtc_plan** out,
+                     size_t* workspace_bytes);
+void pbtc_plan_destroy(pbtc_plan* plan);
+
+/* Unknowns (2 * total panels), charges, surfaces and regions of a plan. */
+int pbtc_plan_sizes(const pbtc_plan* plan, int64_t* n_unknowns, int64_t* n_charges,
+                    int* n_surfaces, int* n_regions);
+
+/* Device set-up on the caller's workspace and stream, once per geometry
+ * (sec. 2.3: the tree and interaction lists are built once and reused by
+ * every iteration): copies the inputs to the device, forms panel geometry
+ * and Gauss points, sorts them in Morton order, builds one octree per
+ * surface, the interaction lists, the near-singular correction tables and
+ * the Coulomb right-hand side.  Synchronises the stream.  res may be NULL. */
+int pbtc_setup(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream,
+               pbtc_result* res);
+
+/* Solves the BEM system by GMRES and evaluates the solvation energy.  Runs
+ * pbtc_setup first when the workspace is not set up (or force_setup != 0).
+ * Returns ENOCONV (outputs valid) when max_iter is reached. */
+int pbtc_solve(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream,
+               int force_setup, pbtc_result* res);
+
+/* After pbtc_solve: phi (n_s) and d phi/dn on the inner side (n_s) of one
+ * surface in its triangle order (host buffers). */
+int pbtc_get_surface(const pbtc_plan* plan, int surface_id, double* phi, double* dphidn_inner);
+/* Reaction potential at every charge (regions in id order, charges in the
+ * order given), host buffer of n_charges. */
+int pbtc_get_phi_reac(const pbtc_plan* plan, double* phi_reac);
+/* GMRES implicit relative residual per iteration (host buffer). */
+int pbtc_get_history(const pbtc_plan* plan, double* rel_res, int cap, int* n_iter);
+
+/* y = A x with the plan's operator (sec. 2.2 Eq. matrix and its
+ * multi-surface form), x and y DEVICE pointers to n_unknowns FP64 values,
+ * evaluated in `precision` (PBTC_FP64 or PBTC_FP32) with the plan's op.
+ * Requires pbtc_setup on the same workspace.  Does not synchronise. */
+int pbtc_matvec(pbtc_plan* plan, void* d_workspace, void* hip_stream, const double* d_x,
+                double* d_y, int precision);
+/* y = A^T x (exact transpose of the same discrete operator).  Device
+ * pointers as for pbtc_matvec. */
+int pbtc_matvec_transpose(pbtc_plan* plan, void* d_workspace, void* hip_stream,
+                          const double* d_x, double* d_y, int precision);
+/* The Coulomb right-hand side b (Eq. matel Q) into a device buffer of
+ * n_unknowns FP64 values. */
+int pbtc_rhs(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* d_b);
+
+/* Gradients of the solvation energy by the adjoint method: solves
+ * A^T lambda = S^T q (S: unknowns -> reaction potential at the charges)
+ * with GMRES on the transposed operator, then
+ *   dE/dq_k     = 1/2 C (S x + B^T lambda)_k,
+ *   dE/dkappa_r = 1/2 C [q^T S'_r x - lambda^T A'_r x + lambda^T B'_r q],
+ *   dE/deps_r   likewise with the eps derivatives,
+ * C = 4 pi k_e.  Requires a converged pbtc_solve on the same workspace.
+ * Host outputs: dE_dq (n_charges), dE_dkappa and dE_deps (n_regions); any
+ * may be NULL.  The energy is scaled by gE (dL/dE of a caller's loss). */
+int pbtc_backward(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream,
+                  double gE, double* dE_dq, double* dE_dkappa, double* dE_deps,
+                  pbtc_result* res);
+
+/* Solves n independent plans together: every operator evaluation of every
+ * unconverged plan goes into one launch per kernel, GMRES runs per plan.
+ * Each plan has its own workspace (d_workspaces[i], bytes[i]).  res: n
+ * entries.  Returns the first error, or ENOCONV if any plan did not
+ * converge. */
+int pbtc_solve_batch(pbtc_plan** plans, int n, void** d_workspaces, const size_t* bytes,
+                     void* hip_stream, pbtc_result* res);
+
+/* Host-side tables used by the library (no device work), for checking:
+ * barycentric points (K x 3) and weights (K) of the K-point triangle rule;
+ * Gauss-Legendre nodes and weights on [-1, 1]. */
+int pbtc_triangle_rule(int K, double* bary, double* weights);
+int pbtc_gauss_legendre(int n, double* nodes, double* weights);
+
+/* Message of the last error of `plan` (or of the calling thread when plan
+ * is NULL).  The pointer stays valid until the next call on that plan. */
+const char* pbtc_last_error(const pbtc_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBTC_H */

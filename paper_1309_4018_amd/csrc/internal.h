@@ -1,0 +1,214 @@
+// Internal structures of libpbtc shared by the host driver and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pbtc.h"
+
+namespace pbtc {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
+// k_e = e^2 N_A / (4 pi eps_0 * 1 angstrom) in kJ A / (mol e^2)
+constexpr double kCoulomb = 1389.35458;
+
+constexpr int kMaxP = 10;
+constexpr int kGroup = 64;       // targets per target group (one wavefront)
+constexpr int kMaxLevels = 21;   // 63-bit Morton keys, 21 bits per axis
+constexpr int kMaxNk = 32;
+constexpr int kMaxRule = 19;
+
+__host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// Kernel sets evaluated by one block: up to two distinct Green's functions.
+enum KernelSet : int { KS_L = 0, KS_Y = 1, KS_LY = 2, KS_YY = 3, KS_COUNT = 4 };
+
+// ---------------------------------------------------------------- host model
+struct Region {
+  double eps = 1.0, kappa = 0.0;
+};
+
+struct Surface {
+  std::vector<double> v;    // nv x 3
+  std::vector<int32_t> t;   // np x 3
+  int inner = -1, outer = -1;
+  int64_t nv() const { return (int64_t)v.size() / 3; }
+  int64_t np() const { return (int64_t)t.size() / 3; }
+};
+
+struct ChargeSet {
+  std::vector<double> xyz, q;
+  int64_t n() const { return (int64_t)q.size(); }
+};
+
+}  // namespace pbtc
+
+struct pbtc_problem {
+  std::vector<pbtc::Region> regions;
+  std::vector<pbtc::Surface> surfaces;
+  std::vector<pbtc::ChargeSet> charges;  // one per region
+};
+
+namespace pbtc {
+
+// A target set is either the collocation points of one surface or the
+// charges of one region.
+struct TargetSet {
+  int kind = 0;  // 0 surface, 1 charges
+  int id = 0;    // surface id or region id
+  int64_t off = 0, n = 0;          // global target index range
+  int64_t grp_off = 0, ngrp = 0;   // global target-group range
+};
+
+// Interaction of one target set with the Gauss points of one source surface,
+// for one or two Green's functions.
+struct Block {
+  int t = 0, s = 0;
+  int ks = KS_L;
+  int nk = 1;
+  double kappa[2] = {0.0, 0.0};
+  int64_t out[2] = {0, 0};   // offsets of this block's S/D outputs per kernel
+  bool reaction = false;     // targets are charges (evaluated after the solve)
+  int64_t item_off = 0;      // first (block, group) item
+  int64_t nf_row = 0;        // first near-field correction row
+};
+
+struct RowTerm {
+  int block = 0, kidx = 0;
+  double sigma_c = 0.0, sigma = 0.0;
+};
+
+// Rows of surface t seen from region r (or, for reaction rows, the charges
+// of region r).
+struct RowBlock {
+  int t = 0, r = 0;
+  int64_t row_off = 0, n = 0, phi_off = 0;
+  std::vector<RowTerm> terms;
+};
+
+// --------------------------------------------------------- device structures
+struct DevBlock {
+  int t, s, ks, nk;
+  double kappa0, kappa1;
+  long long out0, out1;
+  long long tgt_off, ntgt;   // global target range of the target set
+  long long grp_off;         // first global group of the target set
+  long long gp_off, gp_n;    // sorted Gauss-point segment of the source surface
+  long long pan_off;         // first panel of the source surface
+  long long item_off;        // first (block, group) item
+  long long nf_row;          // first near-field row (one row per target)
+  int root;                  // root cell of the source surface
+  int self;                  // 1 if the target set is the source surface itself
+  int tkind;                 // 0: surface collocation points, 1: charges
+  int pad;
+};
+
+struct DevRowBlock {
+  long long row_off, n, phi_off;
+  int term_off, nterms;
+  double half;  // 1/2 for surface rows, 0 for reaction rows
+  double sign;  // -1 for surface rows (1/2 phi - sum), +1 for reaction rows
+};
+
+struct DevRowTerm {
+  long long out;       // offset into the S and D arrays
+  double sigma_c, sigma;
+};
+
+struct Cell {
+  double cx, cy, cz;  // box centre (expansion centre y_c)
+  double h;           // half edge of the box
+  double rb;          // max distance from the centre to a source
+  int begin, count;   // sorted Gauss-point range (global index)
+  int child, nchild;  // first child cell, number of children (0: leaf)
+  int level, surf;
+};
+
+// Workspace layout: byte offsets of every device array.
+struct Layout {
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    size_t o = (total + 255) & ~size_t(255);
+    total = o + bytes;
+    return o;
+  }
+};
+
+struct Timer;
+
+}  // namespace pbtc
+
+// Plan: everything the host knows about a problem plus the device layout.
+struct pbtc_plan {
+  pbtc_problem prob;
+  pbtc_params prm;
+  std::string err;
+
+  // sizes
+  int nsurf = 0, nreg = 0, P = 6, ncrit = 64, direct_below = 0;
+  int64_t np_tot = 0, nv_tot = 0, ngp = 0, nq = 0, ntgt = 0, ngrp = 0, nunk = 0;
+  std::vector<int64_t> pan_off, v_off, gp_off, unk_off, q_off_region;
+  std::vector<pbtc::TargetSet> tsets;
+  std::vector<int> tset_of_surface, tset_of_region;
+  std::vector<pbtc::Block> blocks;
+  std::vector<pbtc::RowBlock> rows, reac_rows;
+  int64_t nout = 0;      // S/D values over all blocks and kernels
+  int64_t nitems = 0;    // (block, group) pairs
+  std::vector<double> cube;  // per surface: cx, cy, cz, half
+  std::vector<double> max_len, max_reach;  // per surface: max L, max centroid-vertex distance
+  double rule_b[3 * pbtc::kMaxRule], rule_w[pbtc::kMaxRule];
+  double fine_b[3 * pbtc::kMaxRule], fine_w[pbtc::kMaxRule];
+  double gl_x[pbtc::kMaxNk], gl_w[pbtc::kMaxNk];
+
+  // capacities (grown after a failed set-up)
+  int64_t cap_cells = 0, cap_near = 0, cap_far = 0, cap_nf = 0;
+
+  // device offsets
+  size_t o_verts, o_tris, o_pan_surf, o_qxyz, o_q, o_qreg;
+  size_t o_cx, o_cy, o_cz, o_nx, o_ny, o_nz, o_area, o_len;      // panels, FP64
+  size_t o_pidx;                                                 // per panel: phi, psi index (int2)
+  size_t o_tx, o_ty, o_tz, o_tidx;                               // sorted targets (FP64) + perm
+  size_t o_txf, o_tyf, o_tzf;                                    // sorted targets FP32
+  size_t o_grp;                                                  // group spheres (4 doubles)
+  size_t o_gx, o_gy, o_gz, o_gw, o_gpid, o_gkey, o_gtmpk, o_gtmpv, o_gidx;  // Gauss points
+  size_t o_src64, o_src32;                                       // source records per matvec
+  size_t o_keys2, o_hist;                                        // sort scratch
+  size_t o_cells, o_cnt, o_scan;                                 // tree
+  size_t o_mom64, o_mom32;                                       // moments
+  size_t o_near_ptr, o_far_ptr, o_near, o_far;                   // lists (CSR over items)
+  size_t o_nf_ptr, o_nf_col, o_nf_v64, o_nf_v32;                 // near-field correction
+  size_t o_S, o_D;                                               // block outputs (FP64)
+  size_t o_blocks, o_rows, o_terms, o_reac_rows, o_reac_terms;   // descriptors
+  size_t o_items;                                                // item -> block (int2)
+  size_t o_b, o_x, o_r, o_w, o_tmp, o_V, o_H, o_givens, o_scal, o_red;  // Krylov
+  size_t o_phi_reac, o_energy;
+  size_t o_lam, o_adj_rhs;
+  size_t fixed_bytes = 0;
+  size_t ws_bytes = 0;
+
+  // device state
+  void* ws = nullptr;
+  bool setup_done = false;
+  int n_levels = 0;
+  std::vector<int> level_begin;  // cell index where each level starts (+ end)
+  int64_t n_cells = 0, n_near = 0, n_far = 0, n_nf = 0;
+  // item ids grouped by kernel set, for forward (0) and reaction (1) blocks
+  std::vector<int> item_list[2][pbtc::KS_COUNT];
+  size_t o_item_list[2][pbtc::KS_COUNT];
+  std::vector<int> item_block;    // item -> block
+  std::vector<double> tcube;      // per target set: cx, cy, cz, half
+  int64_t nf_rows = 0, nf_fwd_rows = 0;
+  size_t o_nf_rowblk = 0;                          // near-field row -> block (int)
+  size_t o_grp_tab = 0;                            // group target offsets and counts
+  size_t o_tkey = 0, o_tkey2 = 0, o_tval = 0, o_tval2 = 0;  // target sort buffers
+  double p2p_pairs = 0, m2p_evals = 0, dense_equiv = 0;
+  bool solved = false;
+
+  // host results
+  std::vector<double> x_host, phi_reac_host, history;
+  double energy = 0.0;
+};

@@ -1,0 +1,611 @@
+// One evaluation of the BEM operator by the treecode (sec. 2.3).
+//
+// The matrix-vector product is an N-body sum (Eq. nbody) whose sources are
+// the Gauss points of every panel weighted by the panel unknowns and whose
+// targets are the collocation points (sec. 2.3, treecode-accelerated BEM).
+// For every block (target set t, source surface s) and each of its Green's
+// functions G the kernels accumulate, at every target x,
+//   S(x) = sum_y W_y psi_j(y) G(x, y)           (single layer, V psi)
+//   D(x) = sum_y W_y phi_j(y) n_j . grad_y G(x, y)  (double layer, K phi)
+// with G = 1/(4 pi R) or exp(-kappa R)/(4 pi R) (Eq. nBEM, Eq. matel):
+//   prep      source records (y, W psi, W phi n) from the unknown vector
+//   p2m, m2m  moments of every cell: P2M at the leaves, shifted to the
+//             parents (sec. 2.3: moments formed at the twigs, then shifted
+//             and added upward)
+//   p2p       direct sums over the cells of a group's near list (R = 0
+//             pairs -- a target on its own centroid Gauss point -- skipped)
+//   m2p       Taylor coefficients by recurrence contracted with the cell
+//             moments (Eq. multexp) over the group's far list
+//   near      FP64-built corrections for the self and near-singular panels
+//   combine   1/2 phi_t - sum_s sigma_rs (c_rs S - D) per row block
+#include <algorithm>
+
+#include "device_util.h"
+#include "taylor.h"
+
+namespace pbtc {
+
+template <typename real>
+struct alignas(16) Src {
+  real x, y, z, q, px, py, pz, pad;
+};
+
+namespace {
+
+template <typename real>
+__device__ __forceinline__ real rsqrt_(real v);
+template <>
+__device__ __forceinline__ float rsqrt_(float v) {
+  return __builtin_amdgcn_rsqf(v);
+}
+template <>
+__device__ __forceinline__ double rsqrt_(double v) {
+  return 1.0 / sqrt(v);
+}
+
+template <typename real>
+__device__ __forceinline__ real exp_neg(real v);  // exp(-v)
+template <>
+__device__ __forceinline__ float exp_neg(float v) {
+  return __builtin_amdgcn_exp2f(-1.4426950408889634f * v);
+}
+template <>
+__device__ __forceinline__ double exp_neg(double v) {
+  return exp(-v);
+}
+
+// ------------------------------------------------------------------- prep
+template <typename real>
+__global__ void k_prep(int64_t ngp, const double* __restrict__ gx, const double* __restrict__ gy,
+                       const double* __restrict__ gz, const double* __restrict__ gw,
+                       const int* __restrict__ gpid, const int* __restrict__ pidx,
+                       const double* __restrict__ nx, const double* __restrict__ ny,
+                       const double* __restrict__ nz, const double* __restrict__ x,
+                       Src<real>* __restrict__ src) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ngp) return;
+  const int p = gpid[j];
+  const double w = gw[j];
+  const double phi = x[pidx[2 * p]], psi = x[pidx[2 * p + 1]];
+  Src<real> s;
+  s.x = (real)gx[j];
+  s.y = (real)gy[j];
+  s.z = (real)gz[j];
+  s.q = (real)(w * psi);
+  s.px = (real)(w * phi * nx[p]);
+  s.py = (real)(w * phi * ny[p]);
+  s.pz = (real)(w * phi * nz[p]);
+  s.pad = (real)0;
+  src[j] = s;
+}
+
+// -------------------------------------------------------------- p2m / m2m
+constexpr int kP2MThreads = 128;
+
+template <int P>
+struct Binom {
+  int c[P + 1][P + 1];
+  constexpr Binom() : c() {
+    for (int n = 0; n <= P; ++n) {
+      c[n][0] = 1;
+      for (int k = 1; k <= n; ++k) c[n][k] = c[n - 1][k - 1] + (k <= n - 1 ? c[n - 1][k] : 0);
+    }
+  }
+};
+
+// Moments of a leaf: M_SL[k] = sum q (y - c)^k,
+// M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d).
+template <typename real, int P>
+__global__ __launch_bounds__(kP2MThreads) void k_p2m(const Cell* __restrict__ cells, int c0,
+                                                     const Src<real>* __restrict__ src,
+                                                     real* __restrict__ mom) {
+  constexpr int N = ncoef(P);
+  constexpr MultiIndex<P> T{};
+  __shared__ real pw[kP2MThreads][3][P + 1];
+  __shared__ real sq[kP2MThreads][4];
+  const int c = c0 + blockIdx.x;
+  const Cell cl = cells[c];
+  if (cl.nchild != 0) return;
+  const int k = threadIdx.x;
+  const int k1 = k < N ? T.k1[k] : 0, k2 = k < N ? T.k2[k] : 0, k3 = k < N ? T.k3[k] : 0;
+  const real cx = (real)cl.cx, cy = (real)cl.cy, cz = (real)cl.cz;
+  real ms = 0, md = 0;
+  for (int base = cl.begin; base < cl.begin + cl.count; base += kP2MThreads) {
+    const int j = base + threadIdx.x;
+    const int nj = min(kP2MThreads, cl.begin + cl.count - base);
+    if (threadIdx.x < nj) {
+      const Src<real> s = src[j];
+      const real d[3] = {s.x - cx, s.y - cy, s.z - cz};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        real v = 1;
+#pragma unroll
+        for (int e = 0; e <= P; ++e) {
+          pw[threadIdx.x][a][e] = v;
+          v *= d[a];
+        }
+      }
+      sq[threadIdx.x][0] = s.q;
+      sq[threadIdx.x][1] = s.px;
+      sq[threadIdx.x][2] = s.py;
+      sq[threadIdx.x][3] = s.pz;
+    }
+    __syncthreads();
+    if (k < N) {
+      for (int t = 0; t < nj; ++t) {
+        const real X = pw[t][0][k1], Y = pw[t][1][k2], Z = pw[t][2][k3];
+        ms += sq[t][0] * X * Y * Z;
+        real dl = 0;
+        if (k1) dl += sq[t][1] * real(k1) * pw[t][0][k1 - 1] * Y * Z;
+        if (k2) dl += sq[t][2] * real(k2) * X * pw[t][1][k2 - 1] * Z;
+        if (k3) dl += sq[t][3] * real(k3) * X * Y * pw[t][2][k3 - 1];
+        md += dl;
+      }
+    }
+    __syncthreads();
+  }
+  if (k < N) {
+    mom[(size_t)c * 2 * N + k] = ms;
+    mom[(size_t)c * 2 * N + N + k] = md;
+  }
+}
+
+// Shift the children's moments to the parent's centre:
+// M_p[k] = sum_{j <= k} C(k, j) (c_child - c_parent)^(k - j) M_child[j].
+template <typename real, int P>
+__global__ __launch_bounds__(kP2MThreads) void k_m2m(const Cell* __restrict__ cells, int c0,
+                                                     real* __restrict__ mom) {
+  constexpr int N = ncoef(P);
+  constexpr MultiIndex<P> T{};
+  constexpr Binom<P> B{};
+  const int c = c0 + blockIdx.x;
+  const Cell cl = cells[c];
+  if (cl.nchild == 0) return;
+  const int k = threadIdx.x;
+  if (k >= N) return;
+  const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
+  real ms = 0, md = 0;
+  for (int ch = cl.child; ch < cl.child + cl.nchild; ++ch) {
+    const Cell cc = cells[ch];
+    const real d[3] = {(real)(cc.cx - cl.cx), (real)(cc.cy - cl.cy), (real)(cc.cz - cl.cz)};
+    real pw[3][P + 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      real v = 1;
+#pragma unroll
+      for (int e = 0; e <= P; ++e) {
+        pw[a][e] = v;
+        v *= d[a];
+      }
+    }
+    const real* M = mom + (size_t)ch * 2 * N;
+    for (int j1 = 0; j1 <= k1; ++j1)
+      for (int j2 = 0; j2 <= k2; ++j2)
+        for (int j3 = 0; j3 <= k3; ++j3) {
+          const real coef = real(B.c[k1][j1] * B.c[k2][j2] * B.c[k3][j3]) * pw[0][k1 - j1] *
+                            pw[1][k2 - j2] * pw[2][k3 - j3];
+          const int j = mindex(j1, j2, j3);
+          ms += coef * M[j];
+          md += coef * M[N + j];
+        }
+  }
+  mom[(size_t)c * 2 * N + k] = ms;
+  mom[(size_t)c * 2 * N + N + k] = md;
+}
+
+// ------------------------------------------------------------------- p2p
+constexpr int kItemThreads = 256;  // 4 wavefronts share one group of 64 targets
+constexpr int kWaves = kItemThreads / 64;
+
+struct ItemArgs {
+  const int* list;  // item ids of this launch
+  const int* item_block;
+  const DevBlock* blocks;
+  const long long* ptr;
+  const int* cells_list;
+  const Cell* cells;
+  const int* tidx;
+  double* S;
+  double* D;
+};
+
+template <typename real, int KS>
+__device__ __forceinline__ void pair(real x, real y, real z, const Src<real>& s, real k0, real k1,
+                                     real (&acc)[4]) {
+  const real dx = x - s.x, dy = y - s.y, dz = z - s.z;
+  const real r2 = dx * dx + dy * dy + dz * dz;
+  const real rinv = r2 > real(0) ? rsqrt_(r2) : real(0);
+  const real pd = s.px * dx + s.py * dy + s.pz * dz;
+  const real r3 = rinv * rinv * rinv;
+  if (KS == KS_L || KS == KS_LY) {
+    acc[0] += s.q * rinv;
+    acc[1] += pd * r3;
+  }
+  if (KS == KS_Y || KS == KS_LY || KS == KS_YY) {
+    const real kap = KS == KS_LY ? k1 : k0;
+    const real r = r2 * rinv;
+    const real e = exp_neg(kap * r);
+    const int o = KS == KS_LY ? 2 : 0;
+    acc[o] += s.q * e * rinv;
+    acc[o + 1] += pd * r3 * e * (real(1) + kap * r);
+  }
+  if (KS == KS_YY) {
+    const real r = r2 * rinv;
+    const real e = exp_neg(k1 * r);
+    acc[2] += s.q * e * rinv;
+    acc[3] += pd * r3 * e * (real(1) + k1 * r);
+  }
+}
+
+template <int KS>
+constexpr int nacc() {
+  return KS == KS_L || KS == KS_Y ? 2 : 4;
+}
+
+// Writes (mode 0) or adds (mode 1) the group's sums, scaled by 1/(4 pi).
+template <typename real, int KS>
+__device__ __forceinline__ void item_store(const ItemArgs& a, const DevBlock& b, int64_t t0, int nt,
+                                           real (&acc)[4], int mode) {
+  __shared__ real red[kWaves][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < nacc<KS>(); ++q) red[w][q][lane] = acc[q];
+  __syncthreads();
+  if (w == 0 && lane < nt) {
+    const int64_t i = a.tidx[t0 + lane] - b.tgt_off;
+#pragma unroll
+    for (int q = 0; q < nacc<KS>(); ++q) {
+      real v = 0;
+#pragma unroll
+      for (int u = 0; u < kWaves; ++u) v += red[u][q][lane];
+      const double val = (double)v * kInv4Pi;
+      const long long out = (q < 2 ? b.out0 : b.out1) + i;
+      double* dst = (q & 1) ? a.D : a.S;
+      if (mode == 0)
+        dst[out] = val;
+      else
+        dst[out] += val;
+    }
+  }
+}
+
+template <typename real, int KS>
+__global__ __launch_bounds__(kItemThreads) void k_p2p(ItemArgs a, const real* __restrict__ tx,
+                                                      const real* __restrict__ ty,
+                                                      const real* __restrict__ tz,
+                                                      const Src<real>* __restrict__ src) {
+  const int item = a.list[blockIdx.x];
+  const DevBlock b = a.blocks[a.item_block[item]];
+  const int64_t g = item - b.item_off;
+  const int64_t t0 = b.tgt_off + g * kGroup;
+  const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t ti = t0 + min(lane, nt - 1);
+  const real x = tx[ti], y = ty[ti], z = tz[ti];
+  const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
+  real acc[4] = {0, 0, 0, 0};
+  const long long e0 = a.ptr[item], e1 = a.ptr[item + 1];
+  for (long long e = e0 + w; e < e1; e += kWaves) {
+    const Cell cl = a.cells[a.cells_list[e]];
+    for (int j = cl.begin; j < cl.begin + cl.count; ++j) {
+      const Src<real> s = src[j];
+      pair<real, KS>(x, y, z, s, k0, k1, acc);
+    }
+  }
+  item_store<real, KS>(a, b, t0, nt, acc, 0);
+}
+
+// ------------------------------------------------------------------- m2p
+template <typename real, int P, int KS>
+__global__ __launch_bounds__(kItemThreads) void k_m2p(ItemArgs a, const real* __restrict__ tx,
+                                                      const real* __restrict__ ty,
+                                                      const real* __restrict__ tz,
+                                                      const real* __restrict__ mom) {
+  constexpr int N = ncoef(P);
+  const int item = a.list[blockIdx.x];
+  const DevBlock b = a.blocks[a.item_block[item]];
+  const int64_t g = item - b.item_off;
+  const int64_t t0 = b.tgt_off + g * kGroup;
+  const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t ti = t0 + min(lane, nt - 1);
+  const real x = tx[ti], y = ty[ti], z = tz[ti];
+  const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
+  real acc[4] = {0, 0, 0, 0};
+  const long long e0 = a.ptr[item], e1 = a.ptr[item + 1];
+  for (long long e = e0 + w; e < e1; e += kWaves) {
+    const int c = a.cells_list[e];
+    const Cell cl = a.cells[c];
+    const real dx = x - (real)cl.cx, dy = y - (real)cl.cy, dz = z - (real)cl.cz;
+    const real rinv = rsqrt_(dx * dx + dy * dy + dz * dz);
+    const real* M = mom + (size_t)c * 2 * N;
+    if (KS == KS_L || KS == KS_LY) taylor_laplace<P, real>(dx, dy, dz, rinv, M, acc[0], acc[1]);
+    if (KS == KS_Y || KS == KS_LY || KS == KS_YY) {
+      const real kap = KS == KS_LY ? k1 : k0;
+      const real r = (dx * dx + dy * dy + dz * dz) * rinv;
+      const int o = KS == KS_LY ? 2 : 0;
+      taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(kap * r), kap, M, acc[o], acc[o + 1]);
+    }
+    if (KS == KS_YY) {
+      const real r = (dx * dx + dy * dy + dz * dz) * rinv;
+      taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(k1 * r), k1, M, acc[2], acc[3]);
+    }
+  }
+  item_store<real, KS>(a, b, t0, nt, acc, 1);
+}
+
+// ----------------------------------------------------------- near field
+// S[out_k + i] += sum_e dV_k(e) psi(col), D[out_k + i] += sum_e dK_k(e) phi(col)
+template <typename real>
+__global__ void k_near_apply(long long r0, long long r1, const int* __restrict__ row_block,
+                             const DevBlock* __restrict__ blocks, const long long* __restrict__ ptr,
+                             const int* __restrict__ col, const real* __restrict__ val,
+                             const int* __restrict__ pidx, const double* __restrict__ x,
+                             double* __restrict__ S, double* __restrict__ D) {
+  const long long row = r0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= r1) return;
+  const DevBlock b = blocks[row_block[row]];
+  const long long i = row - b.nf_row;
+  real s0 = 0, d0 = 0, s1 = 0, d1 = 0;
+  for (long long e = ptr[row]; e < ptr[row + 1]; ++e) {
+    const int p = col[e];
+    const real phi = (real)x[pidx[2 * p]], psi = (real)x[pidx[2 * p + 1]];
+    s0 += val[4 * e] * psi;
+    d0 += val[4 * e + 1] * phi;
+    if (b.nk == 2) {
+      s1 += val[4 * e + 2] * psi;
+      d1 += val[4 * e + 3] * phi;
+    }
+  }
+  S[b.out0 + i] += (double)s0;
+  D[b.out0 + i] += (double)d0;
+  if (b.nk == 2) {
+    S[b.out1 + i] += (double)s1;
+    D[b.out1 + i] += (double)d1;
+  }
+}
+
+// ------------------------------------------------------------- combine
+__global__ void k_combine(const DevRowBlock* __restrict__ rows, const DevRowTerm* __restrict__ terms,
+                          const double* __restrict__ x, const double* __restrict__ S,
+                          const double* __restrict__ D, double* __restrict__ y) {
+  const DevRowBlock rb = rows[blockIdx.y];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rb.n) return;
+  double acc = 0.0;
+  for (int t = rb.term_off; t < rb.term_off + rb.nterms; ++t) {
+    const DevRowTerm tm = terms[t];
+    acc += tm.sigma_c * S[tm.out + i] - tm.sigma * D[tm.out + i];
+  }
+  y[rb.row_off + i] = rb.half * (rb.half != 0.0 ? x[rb.phi_off + i] : 0.0) + rb.sign * acc;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ host side
+template <typename real>
+static int launch_moments(pbtc_plan& pl, hipStream_t st, real* mom, const Src<real>* src) {
+  const Cell* cells = wsp<Cell>(pl, pl.o_cells);
+  const int nc = (int)pl.n_cells;
+#define PBTC_MOM(PP)                                                                         \
+  case PP:                                                                                   \
+    hipLaunchKernelGGL((k_p2m<real, PP>), dim3(nc), dim3(kP2MThreads), 0, st, cells, 0, src, \
+                       mom);                                                                 \
+    for (int l = pl.n_levels - 1; l >= 0; --l) {                                             \
+      const int lb = pl.level_begin[l], le = pl.level_begin[l + 1];                          \
+      if (le > lb)                                                                           \
+        hipLaunchKernelGGL((k_m2m<real, PP>), dim3(le - lb), dim3(kP2MThreads), 0, st, cells, \
+                           lb, mom);                                                         \
+    }                                                                                        \
+    break;
+  switch (pl.P) {
+    PBTC_MOM(2)
+    PBTC_MOM(4)
+    PBTC_MOM(6)
+    PBTC_MOM(8)
+    PBTC_MOM(10)
+    default:
+      pl.err = "unsupported P";
+      return PBTC_EINVAL;
+  }
+#undef PBTC_MOM
+  PBTC_LAUNCH_CHECK();
+  return PBTC_OK;
+}
+
+template <typename real, int KS>
+static void launch_m2p_ks(pbtc_plan& pl, hipStream_t st, const ItemArgs& a, int n, const real* tx,
+                          const real* ty, const real* tz, const real* mom) {
+#define PBTC_M2P(PP)                                                                       \
+  case PP:                                                                                 \
+    hipLaunchKernelGGL((k_m2p<real, PP, KS>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, \
+                       tz, mom);                                                           \
+    break;
+  switch (pl.P) {
+    PBTC_M2P(2)
+    PBTC_M2P(4)
+    PBTC_M2P(6)
+    PBTC_M2P(8)
+    PBTC_M2P(10)
+    default:
+      break;
+  }
+#undef PBTC_M2P
+}
+
+// y = A x (phase 0) or phi_reac = S x (phase 1) in precision `prec`.
+template <typename real>
+static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int phase) {
+  const int T = 256;
+  Src<real>* src = wsp<Src<real>>(pl, sizeof(real) == 4 ? pl.o_src32 : pl.o_src64);
+  real* mom = wsp<real>(pl, sizeof(real) == 4 ? pl.o_mom32 : pl.o_mom64);
+  const real* tx = wsp<real>(pl, sizeof(real) == 4 ? pl.o_txf : pl.o_tx);
+  const real* ty = wsp<real>(pl, sizeof(real) == 4 ? pl.o_tyf : pl.o_ty);
+  const real* tz = wsp<real>(pl, sizeof(real) == 4 ? pl.o_tzf : pl.o_tz);
+  hipLaunchKernelGGL(k_prep<real>, dim3(nblocks(pl.ngp, T)), dim3(T), 0, st, pl.ngp,
+                     wsp<double>(pl, pl.o_gx), wsp<double>(pl, pl.o_gy), wsp<double>(pl, pl.o_gz),
+                     wsp<double>(pl, pl.o_gw), wsp<int>(pl, pl.o_gpid), wsp<int>(pl, pl.o_pidx),
+                     wsp<double>(pl, pl.o_nx), wsp<double>(pl, pl.o_ny), wsp<double>(pl, pl.o_nz), x,
+                     src);
+  PBTC_LAUNCH_CHECK();
+  const bool tree = pl.prm.op == PBTC_OP_TREECODE;
+  if (tree) {
+    int rc = launch_moments<real>(pl, st, mom, src);
+    if (rc) return rc;
+  }
+  ItemArgs a;
+  a.item_block = wsp<int>(pl, pl.o_items);
+  a.blocks = wsp<DevBlock>(pl, pl.o_blocks);
+  a.cells = wsp<Cell>(pl, pl.o_cells);
+  a.tidx = wsp<int>(pl, pl.o_tidx);
+  a.S = wsp<double>(pl, pl.o_S);
+  a.D = wsp<double>(pl, pl.o_D);
+  for (int ks = 0; ks < KS_COUNT; ++ks) {
+    const int n = (int)pl.item_list[phase][ks].size();
+    if (n == 0) continue;
+    a.list = wsp<int>(pl, pl.o_item_list[phase][ks]);
+    a.ptr = wsp<long long>(pl, pl.o_near_ptr);
+    a.cells_list = wsp<int>(pl, pl.o_near);
+    switch (ks) {
+      case KS_L:
+        hipLaunchKernelGGL((k_p2p<real, KS_L>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, tz, src);
+        break;
+      case KS_Y:
+        hipLaunchKernelGGL((k_p2p<real, KS_Y>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, tz, src);
+        break;
+      case KS_LY:
+        hipLaunchKernelGGL((k_p2p<real, KS_LY>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, tz, src);
+        break;
+      case KS_YY:
+        hipLaunchKernelGGL((k_p2p<real, KS_YY>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, tz, src);
+        break;
+    }
+    PBTC_LAUNCH_CHECK();
+    if (tree && pl.n_far > 0) {
+      a.ptr = wsp<long long>(pl, pl.o_far_ptr);
+      a.cells_list = wsp<int>(pl, pl.o_far);
+      switch (ks) {
+        case KS_L: launch_m2p_ks<real, KS_L>(pl, st, a, n, tx, ty, tz, mom); break;
+        case KS_Y: launch_m2p_ks<real, KS_Y>(pl, st, a, n, tx, ty, tz, mom); break;
+        case KS_LY: launch_m2p_ks<real, KS_LY>(pl, st, a, n, tx, ty, tz, mom); break;
+        case KS_YY: launch_m2p_ks<real, KS_YY>(pl, st, a, n, tx, ty, tz, mom); break;
+      }
+      PBTC_LAUNCH_CHECK();
+    }
+  }
+  // near-field corrections of this phase's blocks
+  const long long r0 = phase == 0 ? 0 : pl.nf_fwd_rows;
+  const long long r1 = phase == 0 ? pl.nf_fwd_rows : pl.nf_rows;
+  if (r1 > r0) {
+    hipLaunchKernelGGL(k_near_apply<real>, dim3(nblocks(r1 - r0, T)), dim3(T), 0, st, r0, r1,
+                       wsp<int>(pl, pl.o_nf_rowblk), wsp<DevBlock>(pl, pl.o_blocks),
+                       wsp<long long>(pl, pl.o_nf_ptr), wsp<int>(pl, pl.o_nf_col),
+                       wsp<real>(pl, sizeof(real) == 4 ? pl.o_nf_v32 : pl.o_nf_v64),
+                       wsp<int>(pl, pl.o_pidx), x, a.S, a.D);
+    PBTC_LAUNCH_CHECK();
+  }
+  // combine
+  const auto& rows = phase == 0 ? pl.rows : pl.reac_rows;
+  if (!rows.empty()) {
+    int64_t nmax = 0;
+    for (const auto& r : rows) nmax = std::max(nmax, r.n);
+    dim3 grid(nblocks(nmax, T), (unsigned)rows.size());
+    hipLaunchKernelGGL(k_combine, grid, dim3(T), 0, st,
+                       wsp<DevRowBlock>(pl, phase == 0 ? pl.o_rows : pl.o_reac_rows),
+                       wsp<DevRowTerm>(pl, phase == 0 ? pl.o_terms : pl.o_reac_terms), x, a.S, a.D,
+                       y);
+    PBTC_LAUNCH_CHECK();
+  }
+  return PBTC_OK;
+}
+
+int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+                   int phase) {
+  if (precision == PBTC_FP64) return apply_impl<double>(pl, st, x, y, phase);
+  return apply_impl<float>(pl, st, x, y, phase);
+}
+
+// Descriptor tables (blocks, rows, item lists) to the device.
+int upload_descriptors(pbtc_plan& pl, hipStream_t st) {
+  std::vector<DevBlock> db(pl.blocks.size());
+  for (size_t i = 0; i < pl.blocks.size(); ++i) {
+    const Block& b = pl.blocks[i];
+    const TargetSet& ts = pl.tsets[b.t];
+    DevBlock& d = db[i];
+    d.t = b.t;
+    d.s = b.s;
+    d.ks = b.ks;
+    d.nk = b.nk;
+    d.kappa0 = b.kappa[0];
+    d.kappa1 = b.kappa[1];
+    d.out0 = b.out[0];
+    d.out1 = b.out[1];
+    d.tgt_off = ts.off;
+    d.ntgt = ts.n;
+    d.grp_off = ts.grp_off;
+    d.gp_off = pl.gp_off[b.s];
+    d.gp_n = pl.gp_off[b.s + 1] - pl.gp_off[b.s];
+    d.pan_off = pl.pan_off[b.s];
+    d.item_off = b.item_off;
+    d.nf_row = b.nf_row;
+    d.root = b.s;  // roots are cells 0 .. nsurf-1
+    d.self = (ts.kind == 0 && ts.id == b.s) ? 1 : 0;
+    d.tkind = ts.kind;
+    d.pad = 0;
+  }
+  PBTC_HIP(hipMemcpyAsync(wsp<DevBlock>(pl, pl.o_blocks), db.data(), sizeof(DevBlock) * db.size(),
+                          hipMemcpyHostToDevice, st));
+  auto rows_to_dev = [&](const std::vector<RowBlock>& rows, bool surf, size_t orow,
+                         size_t oterm) -> int {
+    std::vector<DevRowBlock> r(rows.size());
+    std::vector<DevRowTerm> t;
+    for (size_t i = 0; i < rows.size(); ++i) {
+      r[i].row_off = rows[i].row_off;
+      r[i].n = rows[i].n;
+      r[i].phi_off = rows[i].phi_off;
+      r[i].term_off = (int)t.size();
+      r[i].nterms = (int)rows[i].terms.size();
+      r[i].half = surf ? 0.5 : 0.0;
+      r[i].sign = surf ? -1.0 : 1.0;
+      for (const RowTerm& rt : rows[i].terms) {
+        DevRowTerm d;
+        d.out = pl.blocks[rt.block].out[rt.kidx];
+        d.sigma_c = rt.sigma_c;
+        d.sigma = rt.sigma;
+        t.push_back(d);
+      }
+    }
+    if (!r.empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<DevRowBlock>(pl, orow), r.data(), sizeof(DevRowBlock) * r.size(),
+                              hipMemcpyHostToDevice, st));
+    if (!t.empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<DevRowTerm>(pl, oterm), t.data(), sizeof(DevRowTerm) * t.size(),
+                              hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipStreamSynchronize(st));
+    return PBTC_OK;
+  };
+  int rc = rows_to_dev(pl.rows, true, pl.o_rows, pl.o_terms);
+  if (rc) return rc;
+  rc = rows_to_dev(pl.reac_rows, false, pl.o_reac_rows, pl.o_reac_terms);
+  if (rc) return rc;
+  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_items), pl.item_block.data(), 4 * pl.item_block.size(),
+                          hipMemcpyHostToDevice, st));
+  for (int ph = 0; ph < 2; ++ph)
+    for (int ks = 0; ks < KS_COUNT; ++ks)
+      if (!pl.item_list[ph][ks].empty())
+        PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_item_list[ph][ks]), pl.item_list[ph][ks].data(),
+                                4 * pl.item_list[ph][ks].size(), hipMemcpyHostToDevice, st));
+  {
+    std::vector<int> rb(pl.nf_rows);
+    for (size_t bi = 0; bi < pl.blocks.size(); ++bi) {
+      const Block& b = pl.blocks[bi];
+      for (int64_t i = 0; i < pl.tsets[b.t].n; ++i) rb[b.nf_row + i] = (int)bi;
+    }
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_nf_rowblk), rb.data(), 4 * rb.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipStreamSynchronize(st));
+  }
+  return PBTC_OK;
+}
+
+}  // namespace pbtc

@@ -1,0 +1,949 @@
+// Device set-up, once per geometry (sec. 2.3: the tree and the interaction
+// list are built once and reused by every GMRES iteration).
+//
+//   panels      centroid (collocation point), unit normal, area, L = sqrt(2A)
+//               of every flat triangle (sec. 2.2, Eq. nBEM_disc)
+//   gauss       K quadrature points per panel, weight w_g * A (sec. 2.3:
+//               the Gauss points are the treecode's sources)
+//   sort        63-bit Morton keys, stable radix sort per surface
+//   tree        octree per surface; a box holding >= ncrit sources is split
+//               into its non-empty octants (sec. 2.3: twigs hold fewer than
+//               ncrit sources); expansion centre = box centre, r_b = largest
+//               centre-to-source distance
+//   lists       per (block, group of 64 targets): cells where the MAC
+//               theta * r_tb > r_b holds for the whole group (M2P) and cells
+//               handled directly (P2P), Eq. MAC
+//   near field  FP64 corrections (rule value minus the K-point sum) for the
+//               self panel (semi-analytic) and panels with
+//               |x - centre_j| < thres * L_j (K_fine rule), sec. 2.3 and the
+//               lysozyme parameter table of sec. 3
+//   rhs         Coulomb right-hand side (Eq. matel, Q)
+#include <algorithm>
+#include <cmath>
+
+#include "device_util.h"
+
+namespace pbtc {
+
+namespace {
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffff;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t quant(double v, double lo, double inv) {
+  double f = (v - lo) * inv;
+  f = fmin(fmax(f, 0.0), 2097151.0);
+  return (uint32_t)f;
+}
+
+// digit of a level-l box: x bit 2, y bit 1, z bit 0
+__device__ __forceinline__ uint64_t morton(double x, double y, double z, double cx, double cy,
+                                           double cz, double h) {
+  const double inv = 2097152.0 / (2.0 * h);
+  return (spread3(quant(x, cx - h, inv)) << 2) | (spread3(quant(y, cy - h, inv)) << 1) |
+         spread3(quant(z, cz - h, inv));
+}
+
+struct SetupArgs {
+  const double* verts;
+  const int* tris;
+  const int* pan_surf;
+  const long long* vbase;  // per surface: first vertex
+  double *cx, *cy, *cz, *nx, *ny, *nz, *area, *len;
+};
+
+__global__ void k_panels(SetupArgs a, int64_t np) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const long long vb = a.vbase[a.pan_surf[p]];
+  const double* A = a.verts + 3 * (vb + a.tris[3 * p + 0]);
+  const double* B = a.verts + 3 * (vb + a.tris[3 * p + 1]);
+  const double* C = a.verts + 3 * (vb + a.tris[3 * p + 2]);
+  const double e1x = B[0] - A[0], e1y = B[1] - A[1], e1z = B[2] - A[2];
+  const double e2x = C[0] - A[0], e2y = C[1] - A[1], e2z = C[2] - A[2];
+  const double nxv = e1y * e2z - e1z * e2y, nyv = e1z * e2x - e1x * e2z,
+               nzv = e1x * e2y - e1y * e2x;
+  const double nn = sqrt(nxv * nxv + nyv * nyv + nzv * nzv);
+  a.nx[p] = nxv / nn;
+  a.ny[p] = nyv / nn;
+  a.nz[p] = nzv / nn;
+  a.area[p] = 0.5 * nn;
+  a.len[p] = sqrt(nn);  // sqrt(2 A)
+  a.cx[p] = (A[0] + B[0] + C[0]) / 3.0;
+  a.cy[p] = (A[1] + B[1] + C[1]) / 3.0;
+  a.cz[p] = (A[2] + B[2] + C[2]) / 3.0;
+}
+
+struct Rule {
+  double b[3 * kMaxRule];
+  double w[kMaxRule];
+  int k;
+};
+
+// Point g of a panel: the centroid point is formed exactly like the
+// collocation point so that the self pair has R = 0 exactly.
+__device__ __forceinline__ void rule_point(const Rule& r, int g, const double* A, const double* B,
+                                           const double* C, double cx, double cy, double cz,
+                                           double& x, double& y, double& z) {
+  const double b0 = r.b[3 * g], b1 = r.b[3 * g + 1], b2 = r.b[3 * g + 2];
+  if (b0 == b1 && b1 == b2) {
+    x = cx;
+    y = cy;
+    z = cz;
+  } else {
+    x = b0 * A[0] + b1 * B[0] + b2 * C[0];
+    y = b0 * A[1] + b1 * B[1] + b2 * C[1];
+    z = b0 * A[2] + b1 * B[2] + b2 * C[2];
+  }
+}
+
+__global__ void k_gauss(SetupArgs a, Rule r, int64_t np, const double* __restrict__ cube,
+                        const long long* __restrict__ gp_off, const long long* __restrict__ pan_off,
+                        uint64_t* __restrict__ key, int* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np * r.k) return;
+  const int64_t p = i / r.k;
+  const int g = (int)(i - p * r.k);
+  const int s = a.pan_surf[p];
+  const long long vb = a.vbase[s];
+  const double* A = a.verts + 3 * (vb + a.tris[3 * p + 0]);
+  const double* B = a.verts + 3 * (vb + a.tris[3 * p + 1]);
+  const double* C = a.verts + 3 * (vb + a.tris[3 * p + 2]);
+  double x, y, z;
+  rule_point(r, g, A, B, C, a.cx[p], a.cy[p], a.cz[p], x, y, z);
+  const double* cb = cube + 4 * s;
+  // gp are stored panel-major: global index = pan_off-relative within surface segment
+  const int64_t gi = gp_off[s] + (p - pan_off[s]) * r.k + g;
+  key[gi] = morton(x, y, z, cb[0], cb[1], cb[2], cb[3]);
+  idx[gi] = (int)gi;
+}
+
+// Gather Gauss points into Morton order; gidx keeps the original index
+// (panel-major), from which the panel and the rule slot follow.
+__global__ void k_gauss_gather(SetupArgs a, Rule r, int64_t ngp, const int* __restrict__ order,
+                               const int* __restrict__ gp2pan, double* __restrict__ gx,
+                               double* __restrict__ gy, double* __restrict__ gz,
+                               double* __restrict__ gw, int* __restrict__ gpid,
+                               int* __restrict__ gidx) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ngp) return;
+  const int o = order[j];
+  const int p = gp2pan[o];
+  const int g = o % r.k;  // surfaces start on multiples of K
+  const long long vb = a.vbase[a.pan_surf[p]];
+  const double* A = a.verts + 3 * (vb + a.tris[3 * p + 0]);
+  const double* B = a.verts + 3 * (vb + a.tris[3 * p + 1]);
+  const double* C = a.verts + 3 * (vb + a.tris[3 * p + 2]);
+  double x, y, z;
+  rule_point(r, g, A, B, C, a.cx[p], a.cy[p], a.cz[p], x, y, z);
+  gx[j] = x;
+  gy[j] = y;
+  gz[j] = z;
+  gw[j] = r.w[g] * a.area[p];
+  gpid[j] = p;
+  gidx[j] = o;
+}
+
+__global__ void k_gp2pan(int64_t ngp, int K, int* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ngp) out[i] = (int)(i / K);
+}
+
+// target keys: surfaces use panel centroids, charge sets the charges
+__global__ void k_target_keys(int64_t off, int64_t n, const double* __restrict__ x,
+                              const double* __restrict__ y, const double* __restrict__ z, int stride,
+                              double cx, double cy, double cz, double h, uint64_t* __restrict__ key,
+                              int* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = morton(x[i * stride], y[i * stride], z[i * stride], cx, cy, cz, h);
+  idx[i] = (int)(off + i);
+}
+
+__global__ void k_target_gather(int64_t off, int64_t n, const int* __restrict__ idx,
+                                const double* __restrict__ x, const double* __restrict__ y,
+                                const double* __restrict__ z, int stride, int64_t src_off,
+                                double* __restrict__ tx, double* __restrict__ ty,
+                                double* __restrict__ tz, float* __restrict__ txf,
+                                float* __restrict__ tyf, float* __restrict__ tzf,
+                                int* __restrict__ tidx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t g = idx[i];          // global target index
+  const int64_t l = g - off;         // index within the target set
+  const int64_t k = (src_off + l) * stride;
+  tx[off + i] = x[k];
+  ty[off + i] = y[k];
+  tz[off + i] = z[k];
+  txf[off + i] = (float)x[k];
+  tyf[off + i] = (float)y[k];
+  tzf[off + i] = (float)z[k];
+  tidx[off + i] = (int)g;
+}
+
+// bounding sphere of every target group: centre of the box, max distance
+__global__ void k_group_spheres(int64_t ngrp_total, const long long* __restrict__ grp_tgt_off,
+                                const long long* __restrict__ grp_tgt_n,
+                                const double* __restrict__ tx, const double* __restrict__ ty,
+                                const double* __restrict__ tz, double* __restrict__ grp) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngrp_total) return;
+  const long long o = grp_tgt_off[g];
+  const int n = (int)grp_tgt_n[g];
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int i = 0; i < n; ++i) {
+    lo[0] = fmin(lo[0], tx[o + i]);
+    hi[0] = fmax(hi[0], tx[o + i]);
+    lo[1] = fmin(lo[1], ty[o + i]);
+    hi[1] = fmax(hi[1], ty[o + i]);
+    lo[2] = fmin(lo[2], tz[o + i]);
+    hi[2] = fmax(hi[2], tz[o + i]);
+  }
+  const double c[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+  double r2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double dx = tx[o + i] - c[0], dy = ty[o + i] - c[1], dz = tz[o + i] - c[2];
+    r2 = fmax(r2, dx * dx + dy * dy + dz * dz);
+  }
+  grp[4 * g + 0] = c[0];
+  grp[4 * g + 1] = c[1];
+  grp[4 * g + 2] = c[2];
+  grp[4 * g + 3] = sqrt(r2) * (1.0 + 1e-12);
+}
+
+// --------------------------------------------------------------------- tree
+__device__ __forceinline__ int digit_of(uint64_t key, int level) {
+  return (int)((key >> (3 * (kMaxLevels - 1 - level))) & 7);
+}
+
+// first index in [b, e) whose digit at `level` is >= d
+__device__ int lower_digit(const uint64_t* key, int b, int e, int level, int d) {
+  while (b < e) {
+    const int m = (b + e) >> 1;
+    if (digit_of(key[m], level) < d)
+      b = m + 1;
+    else
+      e = m;
+  }
+  return b;
+}
+
+__global__ void k_split_count(Cell* __restrict__ cells, int lb, int le, int ncrit,
+                              const uint64_t* __restrict__ key, long long* __restrict__ cnt) {
+  const int c = lb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= le) return;
+  const Cell cl = cells[c];
+  int n = 0;
+  if (cl.count >= ncrit && cl.level < kMaxLevels && key[cl.begin] != key[cl.begin + cl.count - 1]) {
+    const int e = cl.begin + cl.count;
+    int lo = cl.begin;
+    for (int d = 0; d < 8; ++d) {
+      const int hi = lower_digit(key, lo, e, cl.level, d + 1);
+      n += hi > lo;
+      lo = hi;
+    }
+  }
+  cnt[c - lb] = n;
+}
+
+__global__ void k_split_write(Cell* __restrict__ cells, int lb, int le,
+                              const uint64_t* __restrict__ key, const long long* __restrict__ off) {
+  const int c = lb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= le) return;
+  Cell cl = cells[c];
+  const int first = le + (int)off[c - lb];
+  const int n = (int)(off[c - lb + 1] - off[c - lb]);
+  cl.child = first;
+  cl.nchild = n;
+  cells[c] = cl;
+  if (n == 0) return;
+  const int e = cl.begin + cl.count;
+  int lo = cl.begin, k = 0;
+  const double hh = 0.5 * cl.h;
+  for (int d = 0; d < 8; ++d) {
+    const int hi = lower_digit(key, lo, e, cl.level, d + 1);
+    if (hi > lo) {
+      Cell ch;
+      ch.cx = cl.cx + ((d & 4) ? hh : -hh);
+      ch.cy = cl.cy + ((d & 2) ? hh : -hh);
+      ch.cz = cl.cz + ((d & 1) ? hh : -hh);
+      ch.h = hh;
+      ch.rb = 0.0;
+      ch.begin = lo;
+      ch.count = hi - lo;
+      ch.child = 0;
+      ch.nchild = 0;
+      ch.level = cl.level + 1;
+      ch.surf = cl.surf;
+      cells[first + k++] = ch;
+    }
+    lo = hi;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cell_radius(Cell* __restrict__ cells, int ncell,
+                                                     const double* __restrict__ gx,
+                                                     const double* __restrict__ gy,
+                                                     const double* __restrict__ gz) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  if (c >= ncell) return;
+  const Cell cl = cells[c];
+  double m = 0.0;
+  for (int i = cl.begin + threadIdx.x; i < cl.begin + cl.count; i += 256) {
+    const double dx = gx[i] - cl.cx, dy = gy[i] - cl.cy, dz = gz[i] - cl.cz;
+    m = fmax(m, dx * dx + dy * dy + dz * dz);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cells[c].rb = sqrt(red[0]) * (1.0 + 1e-12);
+}
+
+// -------------------------------------------------------------------- lists
+constexpr int kStack = 8 * kMaxLevels + 16;
+
+// One thread per (block, group) item.  mode 0: count, mode 1: fill.
+__global__ void k_lists(int64_t nitems, const int* __restrict__ item_block,
+                        const DevBlock* __restrict__ blocks, const Cell* __restrict__ cells,
+                        const double* __restrict__ grp, double theta, int direct, int direct_below,
+                        int mode, long long* __restrict__ near_ptr, long long* __restrict__ far_ptr,
+                        int* __restrict__ near, int* __restrict__ far, long long cap_near,
+                        long long cap_far) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitems) return;
+  const DevBlock b = blocks[item_block[it]];
+  const int64_t g = b.grp_off + (it - b.item_off);
+  const double gxc = grp[4 * g], gyc = grp[4 * g + 1], gzc = grp[4 * g + 2], gr = grp[4 * g + 3];
+  long long nn = 0, nf = 0;
+  long long pn = 0, pf = 0;
+  if (mode == 1) {
+    pn = near_ptr[it];
+    pf = far_ptr[it];
+  }
+  if (direct) {
+    if (mode == 1 && pn < cap_near) near[pn] = b.root;
+    nn = 1;
+  } else {
+    int stack[kStack];
+    int sp = 0;
+    stack[sp++] = b.root;
+    while (sp > 0) {
+      const int c = stack[--sp];
+      const Cell cl = cells[c];
+      if (cl.count == 0) continue;
+      const double dx = gxc - cl.cx, dy = gyc - cl.cy, dz = gzc - cl.cz;
+      const double rtb = sqrt(dx * dx + dy * dy + dz * dz) - gr;
+      if (theta * rtb > cl.rb) {
+        if (cl.count < direct_below) {
+          if (mode == 1 && pn + nn < cap_near) near[pn + nn] = c;
+          ++nn;
+        } else {
+          if (mode == 1 && pf + nf < cap_far) far[pf + nf] = c;
+          ++nf;
+        }
+      } else if (cl.nchild == 0) {
+        if (mode == 1 && pn + nn < cap_near) near[pn + nn] = c;
+        ++nn;
+      } else {
+        for (int k = cl.nchild - 1; k >= 0 && sp < kStack; --k) stack[sp++] = cl.child + k;
+      }
+    }
+  }
+  if (mode == 0) {
+    near_ptr[it] = nn;
+    far_ptr[it] = nf;
+  }
+}
+
+// ---------------------------------------------------------------- near field
+struct NearArgs {
+  const DevBlock* blocks;
+  const Cell* cells;
+  const double *gx, *gy, *gz;
+  const int *gpid, *gidx;
+  const double *cx, *cy, *cz, *nx, *ny, *nz, *area, *len;
+  const double* qxyz;
+  const int* nf_row_block;  // near-field row -> block
+  long long np_tot;
+  int K;
+  double thres;
+  const double* reach;  // per surface: query radius
+  const long long* gp_first;  // per surface: first original gp index
+};
+
+__device__ __forceinline__ void target_point(const NearArgs& a, const DevBlock& b, int64_t i,
+                                             double& x, double& y, double& z, int64_t& self_pan) {
+  // i: index within the target set (natural order)
+  if (b.tkind == 0) {
+    // surface target sets: global target index == global panel index
+    const int64_t gpan = b.tgt_off + i;
+    x = a.cx[gpan];
+    y = a.cy[gpan];
+    z = a.cz[gpan];
+    self_pan = b.self ? gpan : -1;
+  } else {
+    const int64_t k = b.tgt_off + i - a.np_tot;  // charges follow the panels in target order
+    x = a.qxyz[3 * k];
+    y = a.qxyz[3 * k + 1];
+    z = a.qxyz[3 * k + 2];
+    self_pan = -1;
+  }
+}
+
+// One thread per near-field row.  mode 0: count, mode 1: fill columns.
+__global__ void k_near_rows(NearArgs a, int64_t nrows, int mode, long long* __restrict__ ptr,
+                            int* __restrict__ col, long long cap) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  const int bi = (int)a.nf_row_block[row];
+  const DevBlock b = a.blocks[bi];
+  const int64_t i = row - b.nf_row;
+  double x, y, z;
+  int64_t self_pan;
+  target_point(a, b, i, x, y, z, self_pan);
+  const double R = a.reach[b.s];
+  long long n = 0, base = mode == 1 ? ptr[row] : 0;
+  int stack[kStack];
+  int sp = 0;
+  stack[sp++] = b.root;
+  while (sp > 0) {
+    const Cell cl = a.cells[stack[--sp]];
+    if (cl.count == 0) continue;
+    const double dx = x - cl.cx, dy = y - cl.cy, dz = z - cl.cz;
+    const double d = sqrt(dx * dx + dy * dy + dz * dz);
+    if (d - cl.rb > R) continue;
+    if (cl.nchild > 0) {
+      for (int k = cl.nchild - 1; k >= 0 && sp < kStack; --k) stack[sp++] = cl.child + k;
+      continue;
+    }
+    for (int j = cl.begin; j < cl.begin + cl.count; ++j) {
+      const int og = a.gidx[j];
+      if ((og - a.gp_first[b.s]) % a.K != 0) continue;  // one test per panel
+      const int p = a.gpid[j];
+      bool take = (p == self_pan);
+      if (!take) {
+        const double ex = x - a.cx[p], ey = y - a.cy[p], ez = z - a.cz[p];
+        take = ex * ex + ey * ey + ez * ez < (a.thres * a.len[p]) * (a.thres * a.len[p]);
+      }
+      if (take) {
+        if (mode == 1 && base + n < cap) col[base + n] = p;
+        ++n;
+      }
+    }
+  }
+  if (mode == 0) ptr[row] = n;
+}
+
+struct Tables {
+  double kb[3 * kMaxRule], kw[kMaxRule];  // K-point rule
+  double fb[3 * kMaxRule], fw[kMaxRule];  // K_fine rule
+  double glx[kMaxNk], glw[kMaxNk];
+  int K, Kf, Nk;
+};
+
+// Green's function and n . grad_y G (both without 1/(4 pi)) for one kernel
+__device__ __forceinline__ void kern64(double kappa, double dx, double dy, double dz, double nx,
+                                       double ny, double nz, double& g, double& gd) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  if (r2 == 0.0) {
+    g = gd = 0.0;
+    return;
+  }
+  const double r = sqrt(r2);
+  const double ir = 1.0 / r;
+  const double e = kappa == 0.0 ? 1.0 : exp(-kappa * r);
+  g = e * ir;
+  gd = (nx * dx + ny * dy + nz * dz) * (1.0 + kappa * r) * e * ir * ir * ir;
+}
+
+// semi-analytic self integral of G over panel p at its centroid (sec. 2.3,
+// singular integrals after Zhu et al.): three sub-triangles at the centroid,
+// closed-form radial integral, N_k-point Gauss-Legendre in the angle
+__device__ double self_integral(const Tables& T, const double* A, const double* B, const double* C,
+                                double cx, double cy, double cz, double kappa) {
+  const double* v[3] = {A, B, C};
+  double total = 0.0;
+  for (int e = 0; e < 3; ++e) {
+    const double* P0 = v[e];
+    const double* P1 = v[(e + 1) % 3];
+    double ex = P1[0] - P0[0], ey = P1[1] - P0[1], ez = P1[2] - P0[2];
+    const double lab = sqrt(ex * ex + ey * ey + ez * ez);
+    ex /= lab;
+    ey /= lab;
+    ez /= lab;
+    const double t = (cx - P0[0]) * ex + (cy - P0[1]) * ey + (cz - P0[2]) * ez;
+    const double fx = P0[0] + t * ex - cx, fy = P0[1] + t * ey - cy, fz = P0[2] + t * ez - cz;
+    const double h = sqrt(fx * fx + fy * fy + fz * fz);
+    const double ta = atan2(-t, h), tb = atan2(lab - t, h);
+    const double half = 0.5 * (tb - ta), mid = 0.5 * (tb + ta);
+    double s = 0.0;
+    for (int k = 0; k < T.Nk; ++k) {
+      const double th = mid + half * T.glx[k];
+      const double rho = h / cos(th);
+      const double rad = kappa == 0.0 ? rho : -expm1(-kappa * rho) / kappa;
+      s += T.glw[k] * rad;
+    }
+    total += half * s;
+  }
+  return total;  // int G r dr dtheta without 1/(4 pi)
+}
+
+// One thread per near-field entry: correction = rule value - K-point sum,
+// for each kernel of the block (FP64), times 1/(4 pi).
+__global__ void k_near_values(NearArgs a, Tables T, int64_t nrows, const long long* __restrict__ ptr,
+                              const int* __restrict__ col, const int* __restrict__ verts_tri,
+                              const double* __restrict__ verts, const long long* __restrict__ vbase,
+                              const int* __restrict__ pan_surf, double* __restrict__ v64,
+                              float* __restrict__ v32) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  const int bi = (int)a.nf_row_block[row];
+  const DevBlock b = a.blocks[bi];
+  const int64_t i = row - b.nf_row;
+  double x, y, z;
+  int64_t self_pan;
+  target_point(a, b, i, x, y, z, self_pan);
+  for (long long e = ptr[row]; e < ptr[row + 1]; ++e) {
+    const int p = col[e];
+    const long long vb = vbase[pan_surf[p]];
+    const double* A = verts + 3 * (vb + verts_tri[3 * p + 0]);
+    const double* B = verts + 3 * (vb + verts_tri[3 * p + 1]);
+    const double* C = verts + 3 * (vb + verts_tri[3 * p + 2]);
+    const double cx = a.cx[p], cy = a.cy[p], cz = a.cz[p];
+    const double nx = a.nx[p], ny = a.ny[p], nz = a.nz[p], ar = a.area[p];
+    for (int k = 0; k < b.nk; ++k) {
+      const double kappa = k == 0 ? b.kappa0 : b.kappa1;
+      // K-point sum exactly as the treecode forms it (R = 0 pair skipped)
+      double vK = 0.0, dK = 0.0;
+      for (int g = 0; g < T.K; ++g) {
+        double px, py, pz;
+        const double b0 = T.kb[3 * g], b1 = T.kb[3 * g + 1], b2 = T.kb[3 * g + 2];
+        if (b0 == b1 && b1 == b2) {
+          px = cx;
+          py = cy;
+          pz = cz;
+        } else {
+          px = b0 * A[0] + b1 * B[0] + b2 * C[0];
+          py = b0 * A[1] + b1 * B[1] + b2 * C[1];
+          pz = b0 * A[2] + b1 * B[2] + b2 * C[2];
+        }
+        double gg, gd;
+        kern64(kappa, x - px, y - py, z - pz, nx, ny, nz, gg, gd);
+        vK += T.kw[g] * ar * gg;
+        dK += T.kw[g] * ar * gd;
+      }
+      double vR = 0.0, dR = 0.0;
+      if (p == self_pan) {
+        vR = self_integral(T, A, B, C, cx, cy, cz, kappa);
+        dR = 0.0;  // flat panel: n . (x - y) = 0
+      } else {
+        for (int g = 0; g < T.Kf; ++g) {
+          const double b0 = T.fb[3 * g], b1 = T.fb[3 * g + 1], b2 = T.fb[3 * g + 2];
+          const double px = b0 * A[0] + b1 * B[0] + b2 * C[0];
+          const double py = b0 * A[1] + b1 * B[1] + b2 * C[1];
+          const double pz = b0 * A[2] + b1 * B[2] + b2 * C[2];
+          double gg, gd;
+          kern64(kappa, x - px, y - py, z - pz, nx, ny, nz, gg, gd);
+          vR += T.fw[g] * ar * gg;
+          dR += T.fw[g] * ar * gd;
+        }
+      }
+      const double dv = (vR - vK) * kInv4Pi, dd = (dR - dK) * kInv4Pi;
+      v64[4 * e + 2 * k] = dv;
+      v64[4 * e + 2 * k + 1] = dd;
+      v32[4 * e + 2 * k] = (float)dv;
+      v32[4 * e + 2 * k + 1] = (float)dd;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------- rhs
+// b[row_off + i] = sum_k q_k / eps_r G_r(x_i, x_k) over the charges of r.
+__global__ void k_coulomb(int64_t n, long long row_off, long long pan_first,
+                          const double* __restrict__ cx, const double* __restrict__ cy,
+                          const double* __restrict__ cz, const double* __restrict__ qxyz,
+                          const double* __restrict__ q, long long q0, long long nq, double inv_eps,
+                          double kappa, double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = cx[pan_first + i], y = cy[pan_first + i], z = cz[pan_first + i];
+  double s = 0.0;
+  for (long long k = q0; k < q0 + nq; ++k) {
+    const double dx = x - qxyz[3 * k], dy = y - qxyz[3 * k + 1], dz = z - qxyz[3 * k + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    s += q[k] * (kappa == 0.0 ? 1.0 : exp(-kappa * r)) / r;
+  }
+  b[row_off + i] = s * inv_eps * kInv4Pi;
+}
+
+__global__ void k_fill_int(int* p, int64_t n, int v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+int upload_descriptors(pbtc_plan& pl, hipStream_t st);
+
+// Builds every once-per-geometry structure on the plan's workspace.
+int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
+  *need_retry = 0;
+  const pbtc_problem& P = pl.prob;
+  const int T = 256;
+  // ---- inputs
+  std::vector<double> verts(3 * pl.nv_tot);
+  std::vector<int> tris(3 * pl.np_tot), pan_surf(pl.np_tot), pidx(2 * pl.np_tot);
+  for (int s = 0; s < pl.nsurf; ++s) {
+    std::copy(P.surfaces[s].v.begin(), P.surfaces[s].v.end(), verts.begin() + 3 * pl.v_off[s]);
+    std::copy(P.surfaces[s].t.begin(), P.surfaces[s].t.end(), tris.begin() + 3 * pl.pan_off[s]);
+    const int64_t ns = pl.pan_off[s + 1] - pl.pan_off[s];
+    for (int64_t p = pl.pan_off[s]; p < pl.pan_off[s + 1]; ++p) {
+      pan_surf[p] = s;
+      pidx[2 * p] = (int)(pl.unk_off[s] + (p - pl.pan_off[s]));
+      pidx[2 * p + 1] = (int)(pl.unk_off[s] + ns + (p - pl.pan_off[s]));
+    }
+  }
+  std::vector<double> qxyz(3 * std::max<int64_t>(pl.nq, 1)), q(std::max<int64_t>(pl.nq, 1));
+  std::vector<int> qreg(std::max<int64_t>(pl.nq, 1));
+  for (int r = 0; r < pl.nreg; ++r) {
+    const ChargeSet& c = P.charges[r];
+    std::copy(c.xyz.begin(), c.xyz.end(), qxyz.begin() + 3 * pl.q_off_region[r]);
+    std::copy(c.q.begin(), c.q.end(), q.begin() + pl.q_off_region[r]);
+    for (int64_t k = pl.q_off_region[r]; k < pl.q_off_region[r + 1]; ++k) qreg[k] = r;
+  }
+  PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_verts), verts.data(), 8 * verts.size(),
+                          hipMemcpyHostToDevice, st));
+  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_tris), tris.data(), 4 * tris.size(),
+                          hipMemcpyHostToDevice, st));
+  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_pan_surf), pan_surf.data(), 4 * pan_surf.size(),
+                          hipMemcpyHostToDevice, st));
+  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_pidx), pidx.data(), 4 * pidx.size(),
+                          hipMemcpyHostToDevice, st));
+  PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_qxyz), qxyz.data(), 8 * qxyz.size(),
+                          hipMemcpyHostToDevice, st));
+  PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_q), q.data(), 8 * q.size(), hipMemcpyHostToDevice, st));
+  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_qreg), qreg.data(), 4 * qreg.size(),
+                          hipMemcpyHostToDevice, st));
+  int rc = upload_descriptors(pl, st);
+  if (rc) return rc;
+  // small per-surface tables live in the reduction scratch during set-up
+  long long* vbase = wsp<long long>(pl, pl.o_red);
+  long long* gp_off = vbase + pl.nsurf + 1;
+  long long* pan_off = gp_off + pl.nsurf + 1;
+  double* cube = reinterpret_cast<double*>(pan_off + pl.nsurf + 1);
+  double* reach = cube + 4 * pl.nsurf;
+  long long* gp_first = reinterpret_cast<long long*>(reach + pl.nsurf);
+  long long* scan_scratch = gp_first + pl.nsurf + 1;
+  {
+    std::vector<long long> tab(3 * (pl.nsurf + 1));
+    for (int s = 0; s <= pl.nsurf; ++s) {
+      tab[s] = pl.v_off[s];
+      tab[pl.nsurf + 1 + s] = pl.gp_off[s];
+      tab[2 * (pl.nsurf + 1) + s] = pl.pan_off[s];
+    }
+    PBTC_HIP(hipMemcpyAsync(vbase, tab.data(), 8 * tab.size(), hipMemcpyHostToDevice, st));
+    std::vector<double> cr(5 * pl.nsurf);
+    for (int s = 0; s < pl.nsurf; ++s) {
+      for (int d = 0; d < 4; ++d) cr[4 * s + d] = pl.cube[4 * s + d];
+      // a panel j with |x - centre_j| < thres L_j has its first Gauss point
+      // within thres * L_max + reach of x
+      cr[4 * pl.nsurf + s] = pl.prm.thres * pl.max_len[s] + pl.max_reach[s] + 1e-9;
+    }
+    PBTC_HIP(hipMemcpyAsync(cube, cr.data(), 8 * cr.size(), hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(gp_first, tab.data() + pl.nsurf + 1, 8 * (pl.nsurf + 1),
+                            hipMemcpyHostToDevice, st));
+  }
+  SetupArgs sa;
+  sa.verts = wsp<double>(pl, pl.o_verts);
+  sa.tris = wsp<int>(pl, pl.o_tris);
+  sa.pan_surf = wsp<int>(pl, pl.o_pan_surf);
+  sa.vbase = vbase;
+  sa.cx = wsp<double>(pl, pl.o_cx);
+  sa.cy = wsp<double>(pl, pl.o_cy);
+  sa.cz = wsp<double>(pl, pl.o_cz);
+  sa.nx = wsp<double>(pl, pl.o_nx);
+  sa.ny = wsp<double>(pl, pl.o_ny);
+  sa.nz = wsp<double>(pl, pl.o_nz);
+  sa.area = wsp<double>(pl, pl.o_area);
+  sa.len = wsp<double>(pl, pl.o_len);
+  hipLaunchKernelGGL(k_panels, dim3(nblocks(pl.np_tot, T)), dim3(T), 0, st, sa, pl.np_tot);
+  PBTC_LAUNCH_CHECK();
+
+  // ---- Gauss points in Morton order per surface
+  Rule rule;
+  rule.k = pl.prm.K;
+  for (int i = 0; i < 3 * pl.prm.K; ++i) rule.b[i] = pl.rule_b[i];
+  for (int i = 0; i < pl.prm.K; ++i) rule.w[i] = pl.rule_w[i];
+  uint64_t* key = wsp<uint64_t>(pl, pl.o_gkey);
+  int* order = wsp<int>(pl, pl.o_keys2);
+  hipLaunchKernelGGL(k_gauss, dim3(nblocks(pl.ngp, T)), dim3(T), 0, st, sa, rule, pl.np_tot, cube,
+                     gp_off, pan_off, key, order);
+  PBTC_LAUNCH_CHECK();
+  for (int s = 0; s < pl.nsurf; ++s) {
+    const int64_t o = pl.gp_off[s], n = pl.gp_off[s + 1] - o;
+    radix_sort64(key + o, order + o, wsp<uint64_t>(pl, pl.o_gtmpk), wsp<int>(pl, pl.o_gtmpv),
+                 wsp<int>(pl, pl.o_hist), n, st);
+  }
+  int* gp2pan = wsp<int>(pl, pl.o_gtmpv);
+  hipLaunchKernelGGL(k_gp2pan, dim3(nblocks(pl.ngp, T)), dim3(T), 0, st, pl.ngp, pl.prm.K, gp2pan);
+  hipLaunchKernelGGL(k_gauss_gather, dim3(nblocks(pl.ngp, T)), dim3(T), 0, st, sa, rule, pl.ngp,
+                     order, gp2pan, wsp<double>(pl, pl.o_gx), wsp<double>(pl, pl.o_gy),
+                     wsp<double>(pl, pl.o_gz), wsp<double>(pl, pl.o_gw), wsp<int>(pl, pl.o_gpid),
+                     wsp<int>(pl, pl.o_gidx));
+  PBTC_LAUNCH_CHECK();
+
+  // ---- targets in Morton order per target set
+  uint64_t* tkey = wsp<uint64_t>(pl, pl.o_tkey);
+  int* tord = wsp<int>(pl, pl.o_tval);
+  for (size_t ti = 0; ti < pl.tsets.size(); ++ti) {
+    const TargetSet& ts = pl.tsets[ti];
+    const double* c = &pl.tcube[4 * ti];
+    const double *X, *Y, *Z;
+    int stride;
+    int64_t src_off;
+    if (ts.kind == 0) {
+      X = sa.cx + pl.pan_off[ts.id];
+      Y = sa.cy + pl.pan_off[ts.id];
+      Z = sa.cz + pl.pan_off[ts.id];
+      stride = 1;
+      src_off = 0;
+    } else {
+      const double* qx = wsp<double>(pl, pl.o_qxyz) + 3 * pl.q_off_region[ts.id];
+      X = qx;
+      Y = qx + 1;
+      Z = qx + 2;
+      stride = 3;
+      src_off = 0;
+    }
+    hipLaunchKernelGGL(k_target_keys, dim3(nblocks(ts.n, T)), dim3(T), 0, st, ts.off, ts.n, X, Y, Z,
+                       stride, c[0], c[1], c[2], c[3], tkey, tord);
+    radix_sort64(tkey, tord, wsp<uint64_t>(pl, pl.o_tkey2), wsp<int>(pl, pl.o_tval2),
+                 wsp<int>(pl, pl.o_hist), ts.n, st);
+    hipLaunchKernelGGL(k_target_gather, dim3(nblocks(ts.n, T)), dim3(T), 0, st, ts.off, ts.n, tord,
+                       X, Y, Z, stride, src_off, wsp<double>(pl, pl.o_tx), wsp<double>(pl, pl.o_ty),
+                       wsp<double>(pl, pl.o_tz), wsp<float>(pl, pl.o_txf), wsp<float>(pl, pl.o_tyf),
+                       wsp<float>(pl, pl.o_tzf), wsp<int>(pl, pl.o_tidx));
+    PBTC_LAUNCH_CHECK();
+  }
+  {
+    std::vector<long long> go(pl.ngrp), gn(pl.ngrp);
+    for (const TargetSet& ts : pl.tsets)
+      for (int64_t g = 0; g < ts.ngrp; ++g) {
+        go[ts.grp_off + g] = ts.off + g * kGroup;
+        gn[ts.grp_off + g] = std::min<int64_t>(kGroup, ts.n - g * kGroup);
+      }
+    long long* dgo = wsp<long long>(pl, pl.o_grp_tab);
+    PBTC_HIP(hipMemcpyAsync(dgo, go.data(), 8 * go.size(), hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(dgo + pl.ngrp, gn.data(), 8 * gn.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_group_spheres, dim3(nblocks(pl.ngrp, T)), dim3(T), 0, st, pl.ngrp, dgo,
+                       dgo + pl.ngrp, wsp<double>(pl, pl.o_tx), wsp<double>(pl, pl.o_ty),
+                       wsp<double>(pl, pl.o_tz), wsp<double>(pl, pl.o_grp));
+    PBTC_LAUNCH_CHECK();
+    PBTC_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
+  }
+
+  // ---- octree per surface, level by level
+  Cell* cells = wsp<Cell>(pl, pl.o_cells);
+  {
+    std::vector<Cell> roots(pl.nsurf);
+    for (int s = 0; s < pl.nsurf; ++s) {
+      Cell& c = roots[s];
+      c.cx = pl.cube[4 * s];
+      c.cy = pl.cube[4 * s + 1];
+      c.cz = pl.cube[4 * s + 2];
+      c.h = pl.cube[4 * s + 3];
+      c.rb = 0.0;
+      c.begin = (int)pl.gp_off[s];
+      c.count = (int)(pl.gp_off[s + 1] - pl.gp_off[s]);
+      c.child = c.nchild = 0;
+      c.level = 0;
+      c.surf = s;
+    }
+    PBTC_HIP(hipMemcpyAsync(cells, roots.data(), sizeof(Cell) * roots.size(), hipMemcpyHostToDevice,
+                            st));
+    PBTC_HIP(hipStreamSynchronize(st));
+  }
+  pl.level_begin.assign(1, 0);
+  int lb = 0, le = pl.nsurf;
+  long long* cnt = wsp<long long>(pl, pl.o_cnt);
+  for (int level = 0; level <= kMaxLevels; ++level) {
+    pl.level_begin.push_back(le);
+    const int n = le - lb;
+    hipLaunchKernelGGL(k_split_count, dim3(nblocks(n, T)), dim3(T), 0, st, cells, lb, le, pl.ncrit,
+                       key, cnt);
+    scan_exclusive<long long>(cnt, n, scan_scratch, st);
+    long long total = 0;
+    PBTC_HIP(hipMemcpyAsync(&total, cnt + n, 8, hipMemcpyDeviceToHost, st));
+    PBTC_HIP(hipStreamSynchronize(st));
+    if (le + total > pl.cap_cells) {
+      pl.cap_cells = (int64_t)((le + total) * 2 + 1024);
+      *need_retry = 1;
+      pl.err = "tree larger than the workspace estimate";
+      return PBTC_EWORKSPACE;
+    }
+    hipLaunchKernelGGL(k_split_write, dim3(nblocks(n, T)), dim3(T), 0, st, cells, lb, le, key, cnt);
+    PBTC_LAUNCH_CHECK();
+    if (total == 0) break;
+    lb = le;
+    le = le + (int)total;
+  }
+  pl.n_cells = le;
+  pl.n_levels = (int)pl.level_begin.size() - 1;
+  hipLaunchKernelGGL(k_cell_radius, dim3((unsigned)pl.n_cells), dim3(256), 0, st, cells,
+                     (int)pl.n_cells, wsp<double>(pl, pl.o_gx), wsp<double>(pl, pl.o_gy),
+                     wsp<double>(pl, pl.o_gz));
+  PBTC_LAUNCH_CHECK();
+
+  // ---- interaction lists
+  const int direct = pl.prm.op == PBTC_OP_DIRECT;
+  long long* near_ptr = wsp<long long>(pl, pl.o_near_ptr);
+  long long* far_ptr = wsp<long long>(pl, pl.o_far_ptr);
+  int* item_block = wsp<int>(pl, pl.o_items);
+  hipLaunchKernelGGL(k_lists, dim3(nblocks(pl.nitems, 64)), dim3(64), 0, st, pl.nitems, item_block,
+                     wsp<DevBlock>(pl, pl.o_blocks), cells, wsp<double>(pl, pl.o_grp),
+                     pl.prm.theta, direct, pl.direct_below, 0, near_ptr, far_ptr, (int*)nullptr,
+                     (int*)nullptr, (long long)0, (long long)0);
+  PBTC_LAUNCH_CHECK();
+  scan_exclusive<long long>(near_ptr, pl.nitems, scan_scratch, st);
+  scan_exclusive<long long>(far_ptr, pl.nitems, scan_scratch, st);
+  long long tot[2] = {0, 0};
+  PBTC_HIP(hipMemcpyAsync(&tot[0], near_ptr + pl.nitems, 8, hipMemcpyDeviceToHost, st));
+  PBTC_HIP(hipMemcpyAsync(&tot[1], far_ptr + pl.nitems, 8, hipMemcpyDeviceToHost, st));
+  PBTC_HIP(hipStreamSynchronize(st));
+  if (tot[0] > pl.cap_near || tot[1] > pl.cap_far) {
+    pl.cap_near = std::max<int64_t>(pl.cap_near, tot[0] + tot[0] / 8 + 1024);
+    pl.cap_far = std::max<int64_t>(pl.cap_far, tot[1] + tot[1] / 8 + 1024);
+    *need_retry = 1;
+    pl.err = "interaction lists larger than the workspace estimate";
+    return PBTC_EWORKSPACE;
+  }
+  pl.n_near = tot[0];
+  pl.n_far = tot[1];
+  hipLaunchKernelGGL(k_lists, dim3(nblocks(pl.nitems, 64)), dim3(64), 0, st, pl.nitems, item_block,
+                     wsp<DevBlock>(pl, pl.o_blocks), cells, wsp<double>(pl, pl.o_grp),
+                     pl.prm.theta, direct, pl.direct_below, 1, near_ptr, far_ptr,
+                     wsp<int>(pl, pl.o_near), wsp<int>(pl, pl.o_far), (long long)pl.cap_near,
+                     (long long)pl.cap_far);
+  PBTC_LAUNCH_CHECK();
+
+  // ---- near-field correction tables
+  NearArgs na;
+  na.blocks = wsp<DevBlock>(pl, pl.o_blocks);
+  na.cells = cells;
+  na.gx = wsp<double>(pl, pl.o_gx);
+  na.gy = wsp<double>(pl, pl.o_gy);
+  na.gz = wsp<double>(pl, pl.o_gz);
+  na.gpid = wsp<int>(pl, pl.o_gpid);
+  na.gidx = wsp<int>(pl, pl.o_gidx);
+  na.cx = sa.cx;
+  na.cy = sa.cy;
+  na.cz = sa.cz;
+  na.nx = sa.nx;
+  na.ny = sa.ny;
+  na.nz = sa.nz;
+  na.area = sa.area;
+  na.len = sa.len;
+  na.qxyz = wsp<double>(pl, pl.o_qxyz);  // charge k is target np_tot + k
+  na.K = pl.prm.K;
+  na.thres = pl.prm.thres;
+  na.reach = reach;
+  na.gp_first = gp_first;
+  na.nf_row_block = wsp<int>(pl, pl.o_nf_rowblk);  // uploaded with the descriptors
+  na.np_tot = pl.np_tot;
+  long long* nf_ptr = wsp<long long>(pl, pl.o_nf_ptr);
+  hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nf_rows, 64)), dim3(64), 0, st, na, pl.nf_rows, 0,
+                     nf_ptr, (int*)nullptr, (long long)0);
+  PBTC_LAUNCH_CHECK();
+  scan_exclusive<long long>(nf_ptr, pl.nf_rows, scan_scratch, st);
+  long long nnz = 0;
+  PBTC_HIP(hipMemcpyAsync(&nnz, nf_ptr + pl.nf_rows, 8, hipMemcpyDeviceToHost, st));
+  PBTC_HIP(hipStreamSynchronize(st));
+  if (nnz > pl.cap_nf) {
+    pl.cap_nf = nnz + nnz / 8 + 1024;
+    *need_retry = 1;
+    pl.err = "near-field table larger than the workspace estimate";
+    return PBTC_EWORKSPACE;
+  }
+  pl.n_nf = nnz;
+  hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nf_rows, 64)), dim3(64), 0, st, na, pl.nf_rows, 1,
+                     nf_ptr, wsp<int>(pl, pl.o_nf_col), (long long)pl.cap_nf);
+  PBTC_LAUNCH_CHECK();
+  Tables tb;
+  tb.K = pl.prm.K;
+  tb.Kf = pl.prm.K_fine;
+  tb.Nk = pl.prm.N_k;
+  for (int i = 0; i < 3 * tb.K; ++i) tb.kb[i] = pl.rule_b[i];
+  for (int i = 0; i < tb.K; ++i) tb.kw[i] = pl.rule_w[i];
+  for (int i = 0; i < 3 * tb.Kf; ++i) tb.fb[i] = pl.fine_b[i];
+  for (int i = 0; i < tb.Kf; ++i) tb.fw[i] = pl.fine_w[i];
+  for (int i = 0; i < tb.Nk; ++i) {
+    tb.glx[i] = pl.gl_x[i];
+    tb.glw[i] = pl.gl_w[i];
+  }
+  hipLaunchKernelGGL(k_near_values, dim3(nblocks(pl.nf_rows, 64)), dim3(64), 0, st, na, tb,
+                     pl.nf_rows, nf_ptr, wsp<int>(pl, pl.o_nf_col), wsp<int>(pl, pl.o_tris),
+                     wsp<double>(pl, pl.o_verts), vbase, wsp<int>(pl, pl.o_pan_surf),
+                     wsp<double>(pl, pl.o_nf_v64), wsp<float>(pl, pl.o_nf_v32));
+  PBTC_LAUNCH_CHECK();
+
+  // ---- Coulomb right-hand side (Eq. matel, Q; multi-surface: charges of the
+  //      row's region, scaled by 1/eps of that region)
+  double* b = wsp<double>(pl, pl.o_b);
+  hipLaunchKernelGGL(k_fill_f64, dim3(nblocks(pl.nunk, T)), dim3(T), 0, st, b, pl.nunk, 0.0);
+  for (const RowBlock& rb : pl.rows) {
+    const int r = rb.r;
+    const int64_t nq = P.charges[r].n();
+    if (nq == 0) continue;
+    hipLaunchKernelGGL(k_coulomb, dim3(nblocks(rb.n, T)), dim3(T), 0, st, rb.n,
+                       (long long)rb.row_off, (long long)pl.pan_off[rb.t], sa.cx, sa.cy, sa.cz,
+                       wsp<double>(pl, pl.o_qxyz), wsp<double>(pl, pl.o_q),
+                       (long long)pl.q_off_region[r], (long long)nq, 1.0 / P.regions[r].eps,
+                       P.regions[r].kappa, b);
+    PBTC_LAUNCH_CHECK();
+  }
+  PBTC_HIP(hipStreamSynchronize(st));
+
+  // ---- interaction counts for the report
+  {
+    std::vector<long long> np_(pl.nitems + 1), fp_(pl.nitems + 1);
+    std::vector<int> nl(pl.n_near);
+    std::vector<Cell> hc(pl.n_cells);
+    PBTC_HIP(hipMemcpy(np_.data(), near_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost));
+    PBTC_HIP(hipMemcpy(fp_.data(), far_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost));
+    if (pl.n_near) PBTC_HIP(hipMemcpy(nl.data(), wsp<int>(pl, pl.o_near), 4 * pl.n_near, hipMemcpyDeviceToHost));
+    PBTC_HIP(hipMemcpy(hc.data(), cells, sizeof(Cell) * pl.n_cells, hipMemcpyDeviceToHost));
+    double pairs = 0.0, m2p = 0.0;
+    for (int64_t it = 0; it < pl.nitems; ++it) {
+      const Block& bl = pl.blocks[pl.item_block[it]];
+      if (bl.reaction) continue;
+      const TargetSet& ts = pl.tsets[bl.t];
+      const int64_t g = it - bl.item_off;
+      const double ntg = (double)std::min<int64_t>(kGroup, ts.n - g * kGroup);
+      double src = 0.0;
+      for (long long e = np_[it]; e < np_[it + 1]; ++e) src += hc[nl[e]].count;
+      pairs += ntg * src * bl.nk;
+      m2p += ntg * (double)(fp_[it + 1] - fp_[it]) * bl.nk;
+    }
+    pl.p2p_pairs = pairs;
+    pl.m2p_evals = m2p;
+  }
+  return PBTC_OK;
+}
+
+}  // namespace pbtc

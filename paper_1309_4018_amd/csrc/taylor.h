@@ -1,0 +1,141 @@
+// Cartesian Taylor expansions of the treecode (sec. 2.3, Eqs. taylor and
+// multexp).
+//
+// For a source cluster with centre y_c and a target x, with d = x - y_c and
+// R = |d|, the Green's function expands in powers of (y - y_c):
+//   G(x, y) = sum_{|k| <= P} a_k (y - y_c)^k,   a_k = (1/k!) D_y^k G(x, y_c),
+// so that  sum_j q_j G(x, y_j) = sum_k a_k m_k  with moments
+// m_k = sum_j q_j (y_j - y_c)^k, and the double layer
+// sum_j q_j n_j . grad_y G(x, y_j) = sum_k a_k sum_j q_j n_j . grad (y_j - y_c)^k.
+//
+// The coefficients follow from the differential identities of the kernels.
+// Laplace, 1/R (recurrence after Duan and Krasny): with n = |k|,
+//   n R^2 a_k = (2n - 1) sum_i d_i a_{k-e_i} - (n - 1) sum_i a_{k-2e_i},
+//   a_0 = 1/R.
+// Yukawa, exp(-kappa R)/R (two-sequence recurrence after Li, Johnston and
+// Krasny), with b_k the coefficients of exp(-kappa R):
+//   n b_k = kappa (sum_i d_i a_{k-e_i} - sum_i a_{k-2e_i}),
+//   n R^2 a_k = (2n - 1) sum_i d_i a_{k-e_i} - (n - 1) sum_i a_{k-2e_i}
+//               + kappa (sum_i d_i b_{k-e_i} - sum_i b_{k-2e_i}),
+//   a_0 = exp(-kappa R)/R, b_0 = exp(-kappa R).
+// Both follow from R^2 grad_y g = -(y - x)(...) written for the Taylor
+// series in (y - y_c); terms with a negative index are zero.
+//
+// Multi-indices k = (k1, k2, k3) with |k| <= P are stored by total degree,
+// then k1 descending, then k2 descending.
+#pragma once
+
+#include "internal.h"
+
+namespace pbtc {
+
+__host__ __device__ constexpr int mindex(int a, int b, int c) {
+  return (a + b + c) * (a + b + c + 1) * (a + b + c + 2) / 6 +
+         (b + c) * (b + c + 1) / 2 + c;
+}
+
+template <int P>
+struct MultiIndex {
+  static constexpr int N = ncoef(P);
+  int n[N], k1[N], k2[N], k3[N];
+  int m1[N][3];  // index of k - e_i, or -1
+  int m2[N][3];  // index of k - 2 e_i, or -1
+  constexpr MultiIndex() : n(), k1(), k2(), k3(), m1(), m2() {
+    for (int deg = 0; deg <= P; ++deg)
+      for (int a = deg; a >= 0; --a)
+        for (int b = deg - a; b >= 0; --b) {
+          const int c = deg - a - b;
+          const int i = mindex(a, b, c);
+          n[i] = deg;
+          k1[i] = a;
+          k2[i] = b;
+          k3[i] = c;
+          m1[i][0] = a >= 1 ? mindex(a - 1, b, c) : -1;
+          m1[i][1] = b >= 1 ? mindex(a, b - 1, c) : -1;
+          m1[i][2] = c >= 1 ? mindex(a, b, c - 1) : -1;
+          m2[i][0] = a >= 2 ? mindex(a - 2, b, c) : -1;
+          m2[i][1] = b >= 2 ? mindex(a, b - 2, c) : -1;
+          m2[i][2] = c >= 2 ? mindex(a, b, c - 2) : -1;
+        }
+  }
+};
+
+// sum_k a_k M[k] and sum_k a_k M[N + k] for the Laplace kernel 1/R.
+template <int P, typename real>
+__device__ __forceinline__ void taylor_laplace(real dx, real dy, real dz, real rinv,
+                                               const real* __restrict__ M, real& s, real& d) {
+  constexpr MultiIndex<P> T{};
+  constexpr int N = MultiIndex<P>::N;
+  const real r2inv = rinv * rinv;
+  real a[N];
+  a[0] = rinv;
+  s += a[0] * M[0];
+  d += a[0] * M[N];
+#pragma unroll
+  for (int k = 1; k < N; ++k) {
+    const int n = T.n[k];
+    real s1 = real(0), s2 = real(0);
+    if (T.m1[k][0] >= 0) s1 += dx * a[T.m1[k][0]];
+    if (T.m1[k][1] >= 0) s1 += dy * a[T.m1[k][1]];
+    if (T.m1[k][2] >= 0) s1 += dz * a[T.m1[k][2]];
+    if (T.m2[k][0] >= 0) s2 += a[T.m2[k][0]];
+    if (T.m2[k][1] >= 0) s2 += a[T.m2[k][1]];
+    if (T.m2[k][2] >= 0) s2 += a[T.m2[k][2]];
+    const real c1 = real(2 * n - 1) / real(n), c2 = real(n - 1) / real(n);
+    a[k] = (c1 * s1 - c2 * s2) * r2inv;
+    s += a[k] * M[k];
+    d += a[k] * M[N + k];
+  }
+}
+
+// Same for the Yukawa kernel exp(-kappa R)/R; e = exp(-kappa R).
+template <int P, typename real>
+__device__ __forceinline__ void taylor_yukawa(real dx, real dy, real dz, real rinv, real e,
+                                              real kappa, const real* __restrict__ M, real& s,
+                                              real& d) {
+  constexpr MultiIndex<P> T{};
+  constexpr int N = MultiIndex<P>::N;
+  const real r2inv = rinv * rinv;
+  real a[N], b[N];
+  a[0] = e * rinv;
+  b[0] = e;
+  s += a[0] * M[0];
+  d += a[0] * M[N];
+#pragma unroll
+  for (int k = 1; k < N; ++k) {
+    const int n = T.n[k];
+    real s1 = real(0), s2 = real(0), t1 = real(0), t2 = real(0);
+    if (T.m1[k][0] >= 0) {
+      s1 += dx * a[T.m1[k][0]];
+      t1 += dx * b[T.m1[k][0]];
+    }
+    if (T.m1[k][1] >= 0) {
+      s1 += dy * a[T.m1[k][1]];
+      t1 += dy * b[T.m1[k][1]];
+    }
+    if (T.m1[k][2] >= 0) {
+      s1 += dz * a[T.m1[k][2]];
+      t1 += dz * b[T.m1[k][2]];
+    }
+    if (T.m2[k][0] >= 0) {
+      s2 += a[T.m2[k][0]];
+      t2 += b[T.m2[k][0]];
+    }
+    if (T.m2[k][1] >= 0) {
+      s2 += a[T.m2[k][1]];
+      t2 += b[T.m2[k][1]];
+    }
+    if (T.m2[k][2] >= 0) {
+      s2 += a[T.m2[k][2]];
+      t2 += b[T.m2[k][2]];
+    }
+    const real inv_n = real(1) / real(n);
+    const real c1 = real(2 * n - 1) / real(n), c2 = real(n - 1) / real(n);
+    b[k] = kappa * inv_n * (s1 - s2);
+    a[k] = (c1 * s1 - c2 * s2 + kappa * inv_n * (t1 - t2)) * r2inv;
+    s += a[k] * M[k];
+    d += a[k] * M[N + k];
+  }
+}
+
+}  // namespace pbtc
