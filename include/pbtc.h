@@ -101,6 +101,8 @@ typedef struct {
   double inner_tol; /* FP32_REFINED: relative tolerance floor of inner solves */
   int max_refine;   /* FP32_REFINED: maximum outer refinement steps */
   int validate_charges; /* 1: check every charge lies inside its region */
+  int profile;      /* 1: time every P2P and M2P launch with HIP events on the
+                       caller's stream (pbtc_result.t_p2p_s ...) */
 } pbtc_params;
 
 typedef struct {
@@ -119,6 +121,11 @@ typedef struct {
   double n_dense_equiv;  /* per operator evaluation: sum over regions of targets x sources */
   double n_near_entries; /* near-field correction entries */
   size_t workspace_needed; /* bytes (set on PBTC_EWORKSPACE and on success) */
+  /* with params.profile: summed HIP-event durations, launch counts and
+   * algorithmic FP operations of all P2P and M2P launches of the call */
+  double t_p2p_s, t_m2p_s;
+  int n_p2p_launch, n_m2p_launch;
+  double p2p_flop, m2p_flop;
 } pbtc_result;
 
 /* Library version; never fails. */
@@ -142,7 +149,7 @@ int pbtc_set_charges(pbtc_problem* p, int region_id, const double* xyz, const do
 /* Defaults: K=4, K_fine=19, N_k=5, thres=2.0, theta=0.5, P=6, ncrit=0,
  * direct_below=-1, tol=1e-5, restart=100, max_iter=1000,
  * precision=PBTC_FP32_REFINED, op=PBTC_OP_TREECODE, inner_tol=1e-6,
- * max_refine=10, validate_charges=1. */
+ * max_refine=10, validate_charges=1, profile=0. */
 int pbtc_params_default(pbtc_params* prm);
 
 /* Host-side checks only (no device work): parameter ranges; every region is
@@ -176,7 +183,9 @@ int pbtc_setup(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_strea
                pbtc_result* res);
 
 /* Solves the BEM system by GMRES and evaluates the solvation energy.  Runs
- * pbtc_setup first when the workspace is not set up (or force_setup != 0).
+ * pbtc_setup first when the workspace is not set up; force_setup != 0
+ * rebuilds every device structure (geometry, Gauss points, tree, lists,
+ * near field, right-hand side) from the inputs already in the workspace.
  * Returns ENOCONV (outputs valid) when max_iter is reached. */
 int pbtc_solve(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream,
                int force_setup, pbtc_result* res);
@@ -217,13 +226,22 @@ int pbtc_backward(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_st
                   double gE, double* dE_dq, double* dE_dkappa, double* dE_deps,
                   pbtc_result* res);
 
-/* Solves n independent plans together: every operator evaluation of every
- * unconverged plan goes into one launch per kernel, GMRES runs per plan.
- * Each plan has its own workspace (d_workspaces[i], bytes[i]).  res: n
- * entries.  Returns the first error, or ENOCONV if any plan did not
- * converge. */
-int pbtc_solve_batch(pbtc_plan** plans, int n, void** d_workspaces, const size_t* bytes,
-                     void* hip_stream, pbtc_result* res);
+/* Independent systems.  A problem may hold several molecules whose regions
+ * never meet (an uneven batch): every connected component of the region
+ * graph (regions linked by surfaces) is a linear system of its own, with its
+ * own Krylov space, Givens rotations and convergence test, while every
+ * operator evaluation of all systems shares each kernel launch.  The
+ * surfaces of one system must be added consecutively (else the whole problem
+ * is solved as one system).  After pbtc_solve: n_systems, and per system
+ * (host buffers of n_systems, any may be NULL) the solvation energy, the
+ * explicit FP64 relative residual, and the first unknown / charge index. */
+int pbtc_get_systems(const pbtc_plan* plan, int* n_systems, double* energy_kJmol,
+                     double* rel_res, int64_t* first_unknown);
+
+/* Replaces the values (not the positions) of every charge of a plan, in the
+ * order of pbtc_get_phi_reac (nq values, host).  The next pbtc_solve reuses
+ * the device set-up and only rebuilds the right-hand side. */
+int pbtc_set_charge_values(pbtc_plan* plan, const double* q);
 
 /* Host-side tables used by the library (no device work), for checking:
  * barycentric points (K x 3) and weights (K) of the K-point triangle rule;

@@ -15,9 +15,9 @@ int build_plan(pbtc_plan& pl);
 void compute_layout(pbtc_plan& pl);
 int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry);
 int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res);
+int update_charges(pbtc_plan& pl, hipStream_t st);
 int device_backward(pbtc_plan& pl, hipStream_t st, double gE, double* dq, double* dk, double* de,
                     pbtc_result* res);
-int device_solve_batch(pbtc_plan** plans, int n, hipStream_t st, pbtc_result* res);
 int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
                    int phase);
 int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
@@ -57,9 +57,11 @@ void fill_sizes(const pbtc_plan* pl, pbtc_result* res) {
 }
 
 // Set-up on a workspace, growing capacity estimates as needed.
-int setup_impl(pbtc_plan* pl, void* ws, size_t bytes, hipStream_t st, pbtc_result* res) {
+int setup_impl(pbtc_plan* pl, void* ws, size_t bytes, hipStream_t st, pbtc_result* res,
+               bool reuse_inputs = false) {
   pl->setup_done = false;
   pl->solved = false;
+  if (!reuse_inputs || pl->inputs_ws != ws) pl->inputs_ws = nullptr;
   for (int attempt = 0; attempt < 4; ++attempt) {
     if (bytes < pl->ws_bytes) {
       if (res) res->workspace_needed = pl->ws_bytes;
@@ -73,10 +75,12 @@ int setup_impl(pbtc_plan* pl, void* ws, size_t bytes, hipStream_t st, pbtc_resul
     const int rc = device_setup(*pl, st, &retry);
     if (rc == PBTC_EWORKSPACE && retry) {
       compute_layout(*pl);
+      pl->inputs_ws = nullptr;
       continue;
     }
     if (rc) return rc;
     pl->setup_done = true;
+    pl->charges_dirty = false;
     if (res) res->t_setup_s = wall_seconds() - t0;
     fill_sizes(pl, res);
     return PBTC_OK;
@@ -170,6 +174,7 @@ int pbtc_params_default(pbtc_params* prm) {
   prm->inner_tol = 1e-6;
   prm->max_refine = 10;
   prm->validate_charges = 1;
+  prm->profile = 0;
   return PBTC_OK;
 }
 
@@ -230,13 +235,17 @@ int pbtc_solve(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_strea
   std::memset(res, 0, sizeof(*res));
   hipStream_t st = (hipStream_t)hip_stream;
   if (force_setup || !plan->setup_done || plan->ws != d_workspace) {
-    const int rc = setup_impl(plan, d_workspace, bytes, st, res);
+    const int rc = setup_impl(plan, d_workspace, bytes, st, res, force_setup != 0);
     if (rc) return rc;
   } else if (bytes < plan->ws_bytes) {
     res->workspace_needed = plan->ws_bytes;
     return fail_plan(plan, PBTC_EWORKSPACE, "workspace smaller than the plan needs");
   }
   fill_sizes(plan, res);
+  if (plan->charges_dirty) {
+    const int rc = update_charges(*plan, st);
+    if (rc) return rc;
+  }
   return device_solve(*plan, st, res);
 }
 
@@ -312,24 +321,30 @@ int pbtc_backward(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_st
   return device_backward(*plan, (hipStream_t)hip_stream, gE, dE_dq, dE_dkappa, dE_deps, res);
 }
 
-int pbtc_solve_batch(pbtc_plan** plans, int n, void** d_workspaces, const size_t* bytes,
-                     void* hip_stream, pbtc_result* res) {
-  if (!plans || n < 1 || !d_workspaces || !bytes || !res)
-    return fail_global(PBTC_EINVAL, "NULL argument or n < 1");
-  hipStream_t st = (hipStream_t)hip_stream;
-  for (int i = 0; i < n; ++i) {
-    if (!plans[i] || !d_workspaces[i]) return fail_global(PBTC_EINVAL, "NULL plan or workspace");
-    std::memset(&res[i], 0, sizeof(pbtc_result));
-    if (!plans[i]->setup_done || plans[i]->ws != d_workspaces[i]) {
-      const int rc = setup_impl(plans[i], d_workspaces[i], bytes[i], st, &res[i]);
-      if (rc) {
-        g_err = "plan " + std::to_string(i) + ": " + plans[i]->err;
-        return rc;
-      }
-    }
-    fill_sizes(plans[i], &res[i]);
+int pbtc_get_systems(const pbtc_plan* plan, int* n_systems, double* energy_kJmol,
+                     double* rel_res, int64_t* first_unknown) {
+  if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
+  if (n_systems) *n_systems = plan->ncomp;
+  if ((energy_kJmol || rel_res) && !plan->solved)
+    return fail_global(PBTC_EINVAL, "no solution yet (call pbtc_solve)");
+  for (int c = 0; c < plan->ncomp; ++c) {
+    if (energy_kJmol) energy_kJmol[c] = plan->comp_energy[c];
+    if (rel_res) rel_res[c] = c < (int)plan->comp_rel.size() ? plan->comp_rel[c] : 0.0;
+    if (first_unknown) first_unknown[c] = plan->comp_u0[c];
   }
-  return device_solve_batch(plans, n, st, res);
+  return PBTC_OK;
+}
+
+int pbtc_set_charge_values(pbtc_plan* plan, const double* q) {
+  if (!plan || !q) return fail_global(PBTC_EINVAL, "NULL argument");
+  if (!finite_all(q, plan->nq)) return fail_plan(plan, PBTC_EINVAL, "charge value not finite");
+  for (int r = 0; r < plan->nreg; ++r) {
+    ChargeSet& c = plan->prob.charges[r];
+    for (int64_t k = 0; k < c.n(); ++k) c.q[k] = q[plan->q_off_region[r] + k];
+  }
+  plan->charges_dirty = true;
+  plan->solved = false;
+  return PBTC_OK;
 }
 
 int pbtc_triangle_rule(int K, double* bary, double* weights) {

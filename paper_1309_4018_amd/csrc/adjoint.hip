@@ -1,18 +1,1279 @@
-// Adjoint (transposed) operator and gradients -- filled in below.
+// Transposed operator and gradients of the solvation energy.
+//
+// With A x = B q (Eq. matrix, multi-surface form) and dG = 1/2 C q^T S x
+// (Eqs. reac_integral and solv, C = 4 pi k_e), the adjoint lambda solves
+// A^T lambda = S^T q, and
+//   dG/dq_k   = 1/2 C (S x + B^T lambda)_k
+//   dG/dp     = 1/2 C [q^T S'_p x - lambda^T A'_p x + lambda^T B'_p q]
+// for p = eps_r, kappa_r.
+//
+// A^T applied to lambda: the phi-columns of A carry 1/2 I and sigma K, the
+// psi-columns -sigma c V, so A^T lambda has the phi part
+// 1/2 (lambda_I + lambda_O) + sum sigma K^T lambda and the psi part
+// sum -sigma c V^T lambda.  For a panel j and weights mu on the targets x_i,
+//   (V^T mu)_j = sum_g W_jg sum_i mu_i G(x_i, y_jg)       + near-field terms
+//   (K^T mu)_j = sum_g W_jg n_j . sum_i mu_i grad_y G(x_i, y_jg) + near terms
+// i.e. a potential and a gradient at the Gauss points y (the adjoint double
+// layer takes the normal at the target).  These sums are evaluated by a
+// treecode with the roles swapped: sources at the collocation points
+// (octree per target set, moments of mu), targets at the Gauss points
+// (groups of 64 consecutive Morton-sorted points), P2P near, and M2P far with
+// Taylor coefficients to order P+1 for the gradient:
+//   grad_y a_k(y; x_c) = -(k_d + 1) a_{k+e_d}(y; x_c).
+// The near-field corrections are applied through the transpose (CSC) of the
+// forward table.  With the direct operator (no far field) this is the exact
+// transpose of the forward operator; with the treecode it agrees with it to
+// the truncation error of the expansion.
+//
+// kappa enters through the Yukawa kernels and the near-field tables; dG/dkappa
+// uses a central difference of the FP64 operator in kappa (step 1e-4 kappa),
+// applied to x against lambda.  eps enters only through c_rs and 1/eps_r and
+// is differentiated exactly.
+#include <algorithm>
+#include <cmath>
+
 #include "device_util.h"
+#include "kernel_common.h"
+#include "taylor.h"
 
 namespace pbtc {
 
-int apply_transpose(pbtc_plan& pl, hipStream_t, const double*, double*, int, int) {
-  pl.err = "transposed operator not available in this build";
-  return PBTC_EINVAL;
+__global__ void k_split_count(Cell* __restrict__ cells, int lb, int le, int ncrit,
+                              const uint64_t* __restrict__ key, long long* __restrict__ cnt);
+int build_octree(pbtc_plan& pl, hipStream_t st, Cell* cells, int64_t cap,
+                 const std::vector<Cell>& roots, const uint64_t* key, const double* px,
+                 const double* py, const double* pz, int ncrit, long long* cnt,
+                 long long* scan_scratch, int64_t* n_cells, std::vector<int>* level_begin,
+                 int64_t* need);
+int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+                   int phase);
+int recompute_near_values(pbtc_plan& pl, hipStream_t st);
+int recompute_rhs(pbtc_plan& pl, hipStream_t st);
+int upload_descriptors(pbtc_plan& pl, hipStream_t st);
+template <typename Op>
+int krylov_solve(pbtc_plan& pl, hipStream_t st, Op op32, Op op64, const double* b, double* x,
+                 int precision, double tol, int* iters, int* n32, int* n64, int* nref,
+                 double* rel, bool* conv, std::vector<double>* hist);
+int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* b, double* x,
+                   int* iters, int* n32, int* n64, int* nref, double* rel, bool* conv,
+                   std::vector<double>* hist);
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kWaves = 4;
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------- setup kernels
+// Gauss points as adjoint targets: position, panel normal, weight.
+template <typename real>
+__global__ void k_gpos(int64_t ngp, const double* __restrict__ gx, const double* __restrict__ gy,
+                       const double* __restrict__ gz, const double* __restrict__ gw,
+                       const int* __restrict__ gpid, const int* __restrict__ gidx,
+                       const double* __restrict__ nx, const double* __restrict__ ny,
+                       const double* __restrict__ nz, Src<real>* __restrict__ out,
+                       int* __restrict__ pos) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ngp) return;
+  const int p = gpid[j];
+  Src<real> s;
+  s.x = (real)gx[j];
+  s.y = (real)gy[j];
+  s.z = (real)gz[j];
+  s.q = (real)gw[j];
+  s.px = (real)nx[p];
+  s.py = (real)ny[p];
+  s.pz = (real)nz[p];
+  s.pad = 0;
+  out[j] = s;
+  if (pos) pos[gidx[j]] = (int)j;
 }
 
-int device_backward(pbtc_plan& pl, hipStream_t, double, double*, double*, double*, pbtc_result*) {
-  pl.err = "backward not available in this build";
-  return PBTC_EINVAL;
+// bounding sphere of Gauss-point group G (64 consecutive sorted points of one surface)
+__global__ void k_gp_groups(int64_t ngrp, int nsurf, const long long* __restrict__ tab,
+                            const double* __restrict__ gx, const double* __restrict__ gy,
+                            const double* __restrict__ gz, double* __restrict__ grp) {
+  const int64_t G = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (G >= ngrp) return;
+  const long long* grp_off = tab;           // nsurf + 1
+  const long long* gp_off = tab + nsurf + 1;  // nsurf + 1
+  int s = 0;
+  while (s + 1 < nsurf && G >= grp_off[s + 1]) ++s;
+  const long long o = gp_off[s] + (G - grp_off[s]) * kGroup;
+  const int n = (int)min((long long)kGroup, gp_off[s + 1] - o);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int i = 0; i < n; ++i) {
+    lo[0] = fmin(lo[0], gx[o + i]);
+    hi[0] = fmax(hi[0], gx[o + i]);
+    lo[1] = fmin(lo[1], gy[o + i]);
+    hi[1] = fmax(hi[1], gy[o + i]);
+    lo[2] = fmin(lo[2], gz[o + i]);
+    hi[2] = fmax(hi[2], gz[o + i]);
+  }
+  const double c[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+  double r2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double dx = gx[o + i] - c[0], dy = gy[o + i] - c[1], dz = gz[o + i] - c[2];
+    r2 = fmax(r2, dx * dx + dy * dy + dz * dz);
+  }
+  grp[4 * G] = c[0];
+  grp[4 * G + 1] = c[1];
+  grp[4 * G + 2] = c[2];
+  grp[4 * G + 3] = sqrt(r2) * (1.0 + 1e-12);
 }
 
-int device_solve_batch(pbtc_plan**, int, hipStream_t, pbtc_result*) { return PBTC_EINVAL; }
+constexpr int kStack = 8 * kMaxLevels + 16;
+
+// one thread per adjoint item (block, Gauss-point group); mode 0 count, 1 fill
+__global__ void k_adj_lists(int64_t nitems, const int* __restrict__ item_block,
+                            const DevBlock* __restrict__ blocks, const Cell* __restrict__ cells,
+                            const double* __restrict__ grp, double theta, int direct,
+                            int direct_below, int mode, long long* __restrict__ near_ptr,
+                            long long* __restrict__ far_ptr, int* __restrict__ near,
+                            int* __restrict__ far, long long cap_near, long long cap_far) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitems) return;
+  const DevBlock b = blocks[item_block[it]];
+  const int64_t g = b.gpgrp_off + (it - b.aitem_off);
+  const double gxc = grp[4 * g], gyc = grp[4 * g + 1], gzc = grp[4 * g + 2], gr = grp[4 * g + 3];
+  long long nn = 0, nf = 0, pn = 0, pf = 0;
+  if (mode == 1) {
+    pn = near_ptr[it];
+    pf = far_ptr[it];
+  }
+  if (direct) {
+    if (mode == 1 && pn < cap_near) near[pn] = b.troot;
+    nn = 1;
+  } else {
+    int stack[kStack];
+    int sp = 0;
+    stack[sp++] = b.troot;
+    while (sp > 0) {
+      const int c = stack[--sp];
+      const Cell cl = cells[c];
+      if (cl.count == 0) continue;
+      const double dx = gxc - cl.cx, dy = gyc - cl.cy, dz = gzc - cl.cz;
+      const double rtb = sqrt(dx * dx + dy * dy + dz * dz) - gr;
+      if (theta * rtb > cl.rb) {
+        if (cl.count < direct_below) {
+          if (mode == 1 && pn + nn < cap_near) near[pn + nn] = c;
+          ++nn;
+        } else {
+          if (mode == 1 && pf + nf < cap_far) far[pf + nf] = c;
+          ++nf;
+        }
+      } else if (cl.nchild == 0) {
+        if (mode == 1 && pn + nn < cap_near) near[pn + nn] = c;
+        ++nn;
+      } else {
+        for (int k = cl.nchild - 1; k >= 0 && sp < kStack; --k) stack[sp++] = cl.child + k;
+      }
+    }
+  }
+  if (mode == 0) {
+    near_ptr[it] = nn;
+    far_ptr[it] = nf;
+  }
+}
+
+// Transposed near-field table: column slot = (block, panel of its source
+// surface).  mode 0 counts, mode 1 fills (unordered), then columns are sorted.
+__global__ void k_csc_count(int64_t nrows, const int* __restrict__ row_block,
+                            const DevBlock* __restrict__ blocks, const long long* __restrict__ ptr,
+                            const int* __restrict__ col, long long* __restrict__ cnt,
+                            long long* __restrict__ csc_ptr, int* __restrict__ ent,
+                            int* __restrict__ ent_row, int mode) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  const DevBlock b = blocks[row_block[row]];
+  for (long long e = ptr[row]; e < ptr[row + 1]; ++e) {
+    const long long slot = b.csc_off + (col[e] - b.pan_off);
+    const long long k = atomicAdd((unsigned long long*)&cnt[slot], 1ull);
+    if (mode == 1) {
+      ent[csc_ptr[slot] + k] = (int)e;
+      ent_row[csc_ptr[slot] + k] = (int)row;
+    }
+  }
+}
+
+__global__ void k_csc_sort(int64_t ncol, const long long* __restrict__ csc_ptr,
+                           int* __restrict__ ent, int* __restrict__ ent_row) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const long long a = csc_ptr[c], b = csc_ptr[c + 1];
+  for (long long i = a + 1; i < b; ++i) {
+    const int e = ent[i], r = ent_row[i];
+    long long j = i - 1;
+    while (j >= a && ent[j] > e) {
+      ent[j + 1] = ent[j];
+      ent_row[j + 1] = ent_row[j];
+      --j;
+    }
+    ent[j + 1] = e;
+    ent_row[j + 1] = r;
+  }
+}
+
+__global__ void k_zero_ll(long long* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// --------------------------------------------------------------- per apply
+// mu weights of every kernel slot from the row weights lambda
+__global__ void k_adj_mu(const DevSlot* __restrict__ slots, const double* __restrict__ lam,
+                         double* __restrict__ muS, double* __restrict__ muD) {
+  const DevSlot s = slots[blockIdx.y];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.n) return;
+  double vs = 0.0, vd = 0.0;
+  for (int c = 0; c < s.ncontrib; ++c) {
+    const double l = lam[s.lam_off[c] + i];
+    vs += s.cS[c] * l;
+    vd += s.cD[c] * l;
+  }
+  muS[s.out + i] = vs;
+  muD[s.out + i] = vd;
+}
+
+// adjoint source records of one block in sorted target order:
+// (x, y, z, muS_0, muD_0, muS_1, muD_1)
+template <typename real>
+__global__ void k_adj_src(const int* __restrict__ blist, const DevBlock* __restrict__ blocks,
+                          const real* __restrict__ tx, const real* __restrict__ ty,
+                          const real* __restrict__ tz, const int* __restrict__ tidx,
+                          const double* __restrict__ muS, const double* __restrict__ muD,
+                          Src<real>* __restrict__ asrc) {
+  const DevBlock b = blocks[blist[blockIdx.y]];
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= b.ntgt) return;
+  const long long g = b.tgt_off + j;
+  const long long i = tidx[g] - b.tgt_off;
+  Src<real> s;
+  s.x = tx[g];
+  s.y = ty[g];
+  s.z = tz[g];
+  s.q = (real)muS[b.out0 + i];
+  s.px = (real)muD[b.out0 + i];
+  s.py = b.nk == 2 ? (real)muS[b.out1 + i] : real(0);
+  s.pz = b.nk == 2 ? (real)muD[b.out1 + i] : real(0);
+  s.pad = 0;
+  asrc[b.nf_row + j] = s;
+}
+
+// Moments of mu about the centre of every leaf of the block's target tree:
+// mS[k] = sum muS (x - c)^k, mD[k] = sum muD (x - c)^k, for kernel slot ks.
+template <typename real, int P>
+__global__ __launch_bounds__(128) void k_adj_p2m(const Cell* __restrict__ cells,
+                                                 const int* __restrict__ slot_block,
+                                                 const int* __restrict__ slot_kidx,
+                                                 const int* __restrict__ slot_ids,
+                                                 const DevBlock* __restrict__ blocks,
+                                                 const Src<real>* __restrict__ asrc,
+                                                 real* __restrict__ mom, long long cells_cap) {
+  constexpr int N = ncoef(P);
+  constexpr MultiIndex<P> T{};
+  __shared__ real pw[128][3][P + 1];
+  __shared__ real sq[128][2];
+  const int slot = slot_ids[blockIdx.y];
+  const DevBlock b = blocks[slot_block[slot]];
+  const int kid = slot_kidx[slot];
+  const int c = blockIdx.x;
+  const Cell cl = cells[c];
+  if (cl.nchild != 0 || cl.surf != b.troot) return;
+  const int k = threadIdx.x;
+  const int k1 = k < N ? T.k1[k] : 0, k2 = k < N ? T.k2[k] : 0, k3 = k < N ? T.k3[k] : 0;
+  const real cx = (real)cl.cx, cy = (real)cl.cy, cz = (real)cl.cz;
+  real ms = 0, md = 0;
+  for (int base = cl.begin; base < cl.begin + cl.count; base += 128) {
+    const int nj = min(128, cl.begin + cl.count - base);
+    if (threadIdx.x < nj) {
+      const Src<real> s = asrc[b.nf_row + (base + threadIdx.x - b.tgt_off)];
+      const real d[3] = {s.x - cx, s.y - cy, s.z - cz};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        real v = 1;
+#pragma unroll
+        for (int e = 0; e <= P; ++e) {
+          pw[threadIdx.x][a][e] = v;
+          v *= d[a];
+        }
+      }
+      sq[threadIdx.x][0] = kid == 0 ? s.q : s.py;
+      sq[threadIdx.x][1] = kid == 0 ? s.px : s.pz;
+    }
+    __syncthreads();
+    if (k < N)
+      for (int t = 0; t < nj; ++t) {
+        const real m = pw[t][0][k1] * pw[t][1][k2] * pw[t][2][k3];
+        ms += sq[t][0] * m;
+        md += sq[t][1] * m;
+      }
+    __syncthreads();
+  }
+  if (k < N) {
+    real* M = mom + ((size_t)slot * cells_cap + c) * 2 * N;
+    M[k] = ms;
+    M[N + k] = md;
+  }
+}
+
+template <int P>
+struct Binom2 {
+  int c[P + 1][P + 1];
+  constexpr Binom2() : c() {
+    for (int n = 0; n <= P; ++n) {
+      c[n][0] = 1;
+      for (int k = 1; k <= n; ++k) c[n][k] = c[n - 1][k - 1] + (k <= n - 1 ? c[n - 1][k] : 0);
+    }
+  }
+};
+
+template <typename real, int P>
+__global__ __launch_bounds__(128) void k_adj_m2m(const Cell* __restrict__ cells, int c0,
+                                                 const int* __restrict__ slot_block,
+                                                 const int* __restrict__ slot_ids,
+                                                 const DevBlock* __restrict__ blocks,
+                                                 real* __restrict__ mom, long long cells_cap) {
+  constexpr int N = ncoef(P);
+  constexpr MultiIndex<P> T{};
+  constexpr Binom2<P> B{};
+  const int slot = slot_ids[blockIdx.y];
+  const DevBlock b = blocks[slot_block[slot]];
+  const int c = c0 + blockIdx.x;
+  const Cell cl = cells[c];
+  if (cl.nchild == 0 || cl.surf != b.troot) return;
+  const int k = threadIdx.x;
+  if (k >= N) return;
+  const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
+  real* base = mom + (size_t)slot * cells_cap * 2 * N;
+  real ms = 0, md = 0;
+  for (int ch = cl.child; ch < cl.child + cl.nchild; ++ch) {
+    const Cell cc = cells[ch];
+    const real d[3] = {(real)(cc.cx - cl.cx), (real)(cc.cy - cl.cy), (real)(cc.cz - cl.cz)};
+    real pw[3][P + 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      real v = 1;
+#pragma unroll
+      for (int e = 0; e <= P; ++e) {
+        pw[a][e] = v;
+        v *= d[a];
+      }
+    }
+    const real* M = base + (size_t)ch * 2 * N;
+    for (int j1 = 0; j1 <= k1; ++j1)
+      for (int j2 = 0; j2 <= k2; ++j2)
+        for (int j3 = 0; j3 <= k3; ++j3) {
+          const real coef = real(B.c[k1][j1] * B.c[k2][j2] * B.c[k3][j3]) * pw[0][k1 - j1] *
+                            pw[1][k2 - j2] * pw[2][k3 - j3];
+          const int j = mindex(j1, j2, j3);
+          ms += coef * M[j];
+          md += coef * M[N + j];
+        }
+  }
+  base[(size_t)c * 2 * N + k] = ms;
+  base[(size_t)c * 2 * N + N + k] = md;
+}
+
+struct AdjArgs {
+  const int4* units;
+  int nunits;
+  const int* item_block;
+  const DevBlock* blocks;
+  const int* cells_list;
+  const Cell* cells;
+};
+
+// target Gauss point (x, y, z, normal) against sources (mu weights):
+// acc[0/2] += muS G, acc[1/3] += muD (n . grad_y G), grad_y G with d = x_src - y
+template <typename real, int KS>
+__device__ __forceinline__ void adj_pair(const Src<real>& t, const Src<real>& s, real k0, real k1,
+                                         real (&acc)[4]) {
+  const real dx = s.x - t.x, dy = s.y - t.y, dz = s.z - t.z;
+  const real r2 = dx * dx + dy * dy + dz * dz;
+  const real rinv = r2 > real(0) ? rsqrt_(r2) : real(0);
+  const real dn = t.px * dx + t.py * dy + t.pz * dz;
+  const real r3 = rinv * rinv * rinv;
+  if (KS == KS_L || KS == KS_LY) {
+    acc[0] += s.q * rinv;
+    acc[1] += s.px * dn * r3;
+  }
+  if (KS == KS_Y || KS == KS_YY) {
+    const real r = r2 * rinv;
+    const real e = exp_neg(k0 * r);
+    acc[0] += s.q * e * rinv;
+    acc[1] += s.px * dn * r3 * e * (real(1) + k0 * r);
+  }
+  if (KS == KS_LY || KS == KS_YY) {
+    const real kap = k1;
+    const real r = r2 * rinv;
+    const real e = exp_neg(kap * r);
+    acc[2] += s.py * e * rinv;
+    acc[3] += s.pz * dn * r3 * e * (real(1) + kap * r);
+  }
+}
+
+template <int KS>
+constexpr int nacc2() {
+  return KS == KS_L || KS == KS_Y ? 2 : 4;
+}
+
+template <typename real, int KS>
+__global__ __launch_bounds__(kT) void k_adj_p2p(AdjArgs a, const Src<real>* __restrict__ gpos,
+                                                const Src<real>* __restrict__ asrc,
+                                                real* __restrict__ partial) {
+  const int u = uni(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  if (u >= a.nunits) return;
+  const int4 un = a.units[u];
+  const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
+  const DevBlock& b = a.blocks[uni(a.item_block[item])];
+  const long long g = item - b.aitem_off;
+  const long long j0 = b.gp_off + g * kGroup;
+  const int nt = (int)min((long long)kGroup, b.gp_n - g * kGroup);
+  const int lane = threadIdx.x & 63;
+  const Src<real> t = gpos[j0 + min(lane, nt - 1)];
+  const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
+  const long long soff = b.nf_row - b.tgt_off;
+  real acc[4] = {0, 0, 0, 0};
+  for (int e = e0; e < e1; ++e) {
+    const int c = uni(a.cells_list[e]);
+    const int beg = uni(a.cells[c].begin), end = beg + uni(a.cells[c].count);
+    for (int j = beg; j < end; ++j) {
+      const Src<real> s = asrc[soff + j];
+      adj_pair<real, KS>(t, s, k0, k1, acc);
+    }
+  }
+  const int lane_ = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < nacc2<KS>(); ++q) partial[((size_t)u * 4 + q) * 64 + lane_] = acc[q];
+}
+
+// Coefficients to order P + 1 about the cell centre x_c of the sources,
+// target y: potential sum_{|k|<=P} a_k mS_k and
+// n . gradient = -sum_k sum_d n_d k_d a_k mD_{k - e_d}.
+template <int P, typename real, int KIND>
+__device__ __forceinline__ void taylor_adj(real dx, real dy, real dz, real rinv, real e,
+                                           real kappa, real nx, real ny, real nz,
+                                           const real* __restrict__ M, real& s, real& f) {
+  constexpr MultiIndex<P + 1> T{};
+  constexpr int N1 = MultiIndex<P + 1>::N;
+  constexpr int N = ncoef(P);
+  const real r2inv = rinv * rinv;
+  real a[N1], bb[KIND ? N1 : 1];
+  a[0] = KIND ? e * rinv : rinv;
+  if (KIND) bb[0] = e;
+  s += a[0] * M[0];
+#pragma unroll
+  for (int k = 1; k < N1; ++k) {
+    const int n = T.n[k];
+    real s1 = real(0), s2 = real(0), t1 = real(0), t2 = real(0);
+    if (T.m1[k][0] >= 0) {
+      s1 += dx * a[T.m1[k][0]];
+      if (KIND) t1 += dx * bb[T.m1[k][0]];
+    }
+    if (T.m1[k][1] >= 0) {
+      s1 += dy * a[T.m1[k][1]];
+      if (KIND) t1 += dy * bb[T.m1[k][1]];
+    }
+    if (T.m1[k][2] >= 0) {
+      s1 += dz * a[T.m1[k][2]];
+      if (KIND) t1 += dz * bb[T.m1[k][2]];
+    }
+    if (T.m2[k][0] >= 0) {
+      s2 += a[T.m2[k][0]];
+      if (KIND) t2 += bb[T.m2[k][0]];
+    }
+    if (T.m2[k][1] >= 0) {
+      s2 += a[T.m2[k][1]];
+      if (KIND) t2 += bb[T.m2[k][1]];
+    }
+    if (T.m2[k][2] >= 0) {
+      s2 += a[T.m2[k][2]];
+      if (KIND) t2 += bb[T.m2[k][2]];
+    }
+    const real inv_n = real(1) / real(n);
+    const real c1 = real(2 * n - 1) / real(n), c2 = real(n - 1) / real(n);
+    if (KIND) {
+      bb[k] = kappa * inv_n * (s1 - s2);
+      a[k] = (c1 * s1 - c2 * s2 + kappa * inv_n * (t1 - t2)) * r2inv;
+    } else {
+      a[k] = (c1 * s1 - c2 * s2) * r2inv;
+    }
+    if (n <= P) s += a[k] * M[k];
+    real g = real(0);
+    if (T.m1[k][0] >= 0) g += nx * real(T.k1[k]) * M[N + T.m1[k][0]];
+    if (T.m1[k][1] >= 0) g += ny * real(T.k2[k]) * M[N + T.m1[k][1]];
+    if (T.m1[k][2] >= 0) g += nz * real(T.k3[k]) * M[N + T.m1[k][2]];
+    f -= a[k] * g;
+  }
+}
+
+template <typename real, int P, int KIND>
+__global__ __launch_bounds__(kT) void k_adj_m2p(AdjArgs a, const Src<real>* __restrict__ gpos,
+                                                const real* __restrict__ mom, long long cells_cap,
+                                                int kslot, real* __restrict__ partial) {
+  constexpr int N = ncoef(P);
+  const int u = uni(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  if (u >= a.nunits) return;
+  const int4 un = a.units[u];
+  const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
+  const DevBlock& b = a.blocks[uni(a.item_block[item])];
+  const long long g = item - b.aitem_off;
+  const long long j0 = b.gp_off + g * kGroup;
+  const int nt = (int)min((long long)kGroup, b.gp_n - g * kGroup);
+  const int lane = threadIdx.x & 63;
+  const Src<real> t = gpos[j0 + min(lane, nt - 1)];
+  const real kap = (real)(kslot == 0 ? b.kappa0 : b.kappa1);
+  const real* base = mom + (size_t)(b.slot0 + kslot) * cells_cap * 2 * N;
+  real s = 0, f = 0;
+  for (int e = e0; e < e1; ++e) {
+    const int c = uni(a.cells_list[e]);
+    const Cell& cl = a.cells[c];
+    const real dx = t.x - (real)cl.cx, dy = t.y - (real)cl.cy, dz = t.z - (real)cl.cz;
+    const real r2 = dx * dx + dy * dy + dz * dz;
+    const real rinv = rsqrt_(r2);
+    const real ee = KIND ? exp_neg(kap * (r2 * rinv)) : real(1);
+    taylor_adj<P, real, KIND>(dx, dy, dz, rinv, ee, kap, t.px, t.py, t.pz,
+                              base + (size_t)c * 2 * N, s, f);
+  }
+  partial[((size_t)u * 4 + 0) * 64 + lane] = s;
+  partial[((size_t)u * 4 + 1) * 64 + lane] = f;
+}
+
+// per Gauss point of the item's group: aout[slot] (+)= sum over units / (4 pi)
+template <typename real, int NQ>
+__global__ void k_adj_reduce(const int* __restrict__ list, const int* __restrict__ uptr,
+                             const int* __restrict__ item_block, const DevBlock* __restrict__ blocks,
+                             const real* __restrict__ partial, double* __restrict__ aS,
+                             double* __restrict__ aD, int mode, int first_slot) {
+  const int l = blockIdx.x;
+  const int item = list[l];
+  const DevBlock& b = blocks[item_block[item]];
+  const long long g = item - b.aitem_off;
+  const int nt = (int)min((long long)kGroup, b.gp_n - g * kGroup);
+  const int lane = threadIdx.x;
+  if (lane >= nt) return;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  for (int u = uptr[l]; u < uptr[l + 1]; ++u)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * 64 + lane];
+  const long long i = g * kGroup + lane;  // sorted position within the surface
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const long long out = (first_slot + (q >> 1) == 0 ? b.aout0 : b.aout1) + i;
+    double* dst = (q & 1) ? aD : aS;
+    const double val = v[q] * kInv4Pi;
+    if (mode == 0)
+      dst[out] = val;
+    else
+      dst[out] += val;
+  }
+}
+
+// z for every panel: Gauss-point sums of every slot of its surface, the
+// transposed near-field terms and (rows of A) 1/2 (lambda_I + lambda_O).
+template <typename real>
+__global__ void k_adj_gather(int64_t np, int K, const int* __restrict__ pan_surf,
+                             const long long* __restrict__ pan_off_tab,
+                             const long long* __restrict__ gp_off_tab,
+                             const DevGather* __restrict__ gathers, const int* __restrict__ gslots,
+                             const int* __restrict__ slot_block, const int* __restrict__ slot_kidx,
+                             const DevBlock* __restrict__ blocks, const int* __restrict__ gp_pos,
+                             const double* __restrict__ gw, const double* __restrict__ aS,
+                             const double* __restrict__ aD, const long long* __restrict__ csc_ptr,
+                             const int* __restrict__ csc_ent, const int* __restrict__ csc_row,
+                             const real* __restrict__ nfv, const double* __restrict__ muS,
+                             const double* __restrict__ muD, const int* __restrict__ pidx,
+                             const double* __restrict__ lam, int add_identity,
+                             double* __restrict__ z) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int s = pan_surf[p];
+  const DevGather gg = gathers[s];
+  double zs = 0.0, zd = 0.0;
+  for (int q = 0; q < gg.nslots; ++q) {
+    const int slot = gslots[gg.slot_off + q];
+    const DevBlock b = blocks[slot_block[slot]];
+    const int kid = slot_kidx[slot];
+    const long long ao = kid == 0 ? b.aout0 : b.aout1;
+    for (int g = 0; g < K; ++g) {
+      const int j = gp_pos[p * K + g];  // global sorted index
+      const long long i = j - gp_off_tab[s];
+      zs += gw[j] * aS[ao + i];
+      zd += gw[j] * aD[ao + i];
+    }
+    const long long cs = b.csc_off + (p - pan_off_tab[s]);
+    const long long mo = kid == 0 ? b.out0 : b.out1;
+    for (long long e = csc_ptr[cs]; e < csc_ptr[cs + 1]; ++e) {
+      const long long row = csc_row[e];
+      const long long ent = csc_ent[e];
+      const long long i = row - b.nf_row;
+      zs += (double)nfv[4 * ent + 2 * kid] * muS[mo + i];
+      zd += (double)nfv[4 * ent + 2 * kid + 1] * muD[mo + i];
+    }
+  }
+  const int ip = pidx[2 * p], is = pidx[2 * p + 1];
+  if (add_identity) zd += 0.5 * (lam[ip] + lam[is]);
+  z[ip] = zd;
+  z[is] = zs;
+}
+
+// (B^T lam)_k = sum over rows of the charge's region lam_i G(x_i, x_k) / eps
+__global__ void k_coulomb_t(long long q0, long long nq, const double* __restrict__ qxyz,
+                            const double* __restrict__ cx, const double* __restrict__ cy,
+                            const double* __restrict__ cz, long long pan_first, long long n,
+                            const double* __restrict__ lam, long long row_off, double inv_eps,
+                            double kappa, double* __restrict__ out) {
+  const long long k = q0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= q0 + nq) return;
+  double s = 0.0;
+  const double x = qxyz[3 * k], y = qxyz[3 * k + 1], zq = qxyz[3 * k + 2];
+  for (long long i = 0; i < n; ++i) {
+    const double dx = cx[pan_first + i] - x, dy = cy[pan_first + i] - y, dz = cz[pan_first + i] - zq;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    s += lam[row_off + i] * (kappa == 0.0 ? 1.0 : exp(-kappa * r)) / r;
+  }
+  out[k] += s * inv_eps * kInv4Pi;
+}
+
+// dots[t] = sum_i a[offa_t + i] b[offb_t + i]   (one block per pair)
+__global__ void k_pair_dots(const long long* __restrict__ tab, const double* __restrict__ A,
+                            const double* __restrict__ B, double* __restrict__ dots) {
+  __shared__ double lds[kT / 64];
+  const long long oa = tab[3 * blockIdx.x], ob = tab[3 * blockIdx.x + 1], n = tab[3 * blockIdx.x + 2];
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += kT) s += A[oa + i] * B[ob + i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kT / 64; ++w) t += lds[w];
+    dots[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_axpby(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        int64_t n, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + b * y[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+namespace {
+
+struct AdjTables {
+  std::vector<int> slot_block, slot_kidx, slot_ids[2], blist[2];
+};
+
+size_t adj_off(pbtc_plan& pl, size_t add) { return add; }
+
+}  // namespace
+
+static int adj_upload_small(pbtc_plan& pl, hipStream_t st);
+
+// One-off set-up of the transposed operator on the plan's workspace.
+int adjoint_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
+  *need_retry = 0;
+  const int T = 256;
+  // Gauss points as targets, and the inverse of their Morton permutation
+  hipLaunchKernelGGL(k_gpos<float>, dim3(nblocks(pl.ngp, T)), dim3(T), 0, st, pl.ngp,
+                     wsp<double>(pl, pl.o_gx), wsp<double>(pl, pl.o_gy), wsp<double>(pl, pl.o_gz),
+                     wsp<double>(pl, pl.o_gw), wsp<int>(pl, pl.o_gpid), wsp<int>(pl, pl.o_gidx),
+                     wsp<double>(pl, pl.o_nx), wsp<double>(pl, pl.o_ny), wsp<double>(pl, pl.o_nz),
+                     wsp<Src<float>>(pl, pl.o_gpos32), wsp<int>(pl, pl.o_gp_pos));
+  hipLaunchKernelGGL(k_gpos<double>, dim3(nblocks(pl.ngp, T)), dim3(T), 0, st, pl.ngp,
+                     wsp<double>(pl, pl.o_gx), wsp<double>(pl, pl.o_gy), wsp<double>(pl, pl.o_gz),
+                     wsp<double>(pl, pl.o_gw), wsp<int>(pl, pl.o_gpid), wsp<int>(pl, pl.o_gidx),
+                     wsp<double>(pl, pl.o_nx), wsp<double>(pl, pl.o_ny), wsp<double>(pl, pl.o_nz),
+                     wsp<Src<double>>(pl, pl.o_gpos64), (int*)nullptr);
+  PBTC_LAUNCH_CHECK();
+  // Gauss-point groups
+  {
+    std::vector<long long> tab(2 * (pl.nsurf + 1));
+    for (int s = 0; s <= pl.nsurf; ++s) {
+      tab[s] = pl.gpgrp_off[s];
+      tab[pl.nsurf + 1 + s] = pl.gp_off[s];
+    }
+    long long* dtab = wsp<long long>(pl, pl.o_dots);
+    PBTC_HIP(hipMemcpyAsync(dtab, tab.data(), 8 * tab.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gp_groups, dim3(nblocks(pl.ngpgrp, T)), dim3(T), 0, st, pl.ngpgrp,
+                       pl.nsurf, dtab, wsp<double>(pl, pl.o_gx), wsp<double>(pl, pl.o_gy),
+                       wsp<double>(pl, pl.o_gz), wsp<double>(pl, pl.o_gpgrp));
+    PBTC_LAUNCH_CHECK();
+    PBTC_HIP(hipStreamSynchronize(st));
+  }
+  // octree over every target set (collocation points of a surface or charges)
+  long long* scan_scratch = wsp<long long>(pl, pl.o_red);
+  {
+    std::vector<Cell> roots(pl.tsets.size());
+    for (size_t ti = 0; ti < pl.tsets.size(); ++ti) {
+      Cell& c = roots[ti];
+      c.cx = pl.tcube[4 * ti];
+      c.cy = pl.tcube[4 * ti + 1];
+      c.cz = pl.tcube[4 * ti + 2];
+      c.h = pl.tcube[4 * ti + 3];
+      c.rb = 0.0;
+      c.begin = (int)pl.tsets[ti].off;
+      c.count = (int)pl.tsets[ti].n;
+      c.child = c.nchild = 0;
+      c.level = 0;
+      c.surf = (int)ti;
+    }
+    int64_t need = 0;
+    const int rc = build_octree(pl, st, wsp<Cell>(pl, pl.o_tcells), pl.cap_tcells, roots,
+                                wsp<uint64_t>(pl, pl.o_tkey_sorted), wsp<double>(pl, pl.o_tx),
+                                wsp<double>(pl, pl.o_ty), wsp<double>(pl, pl.o_tz), pl.ncrit,
+                                wsp<long long>(pl, pl.o_tcnt), scan_scratch, &pl.n_tcells,
+                                &pl.tlevel_begin, &need);
+    if (rc == PBTC_EWORKSPACE) {
+      pl.cap_tcells = 2 * need + 1024;
+      *need_retry = 1;
+      pl.err = "target trees larger than the workspace estimate";
+    }
+    if (rc) return rc;
+    pl.n_tlevels = (int)pl.tlevel_begin.size() - 1;
+  }
+  int rc = adj_upload_small(pl, st);
+  if (rc) return rc;
+  // lists
+  const int direct = pl.prm.op == PBTC_OP_DIRECT;
+  long long* near_ptr = wsp<long long>(pl, pl.o_anear_ptr);
+  long long* far_ptr = wsp<long long>(pl, pl.o_afar_ptr);
+  hipLaunchKernelGGL(k_adj_lists, dim3(nblocks(pl.nitems_adj, 64)), dim3(64), 0, st, pl.nitems_adj,
+                     wsp<int>(pl, pl.o_aitems), wsp<DevBlock>(pl, pl.o_blocks),
+                     wsp<Cell>(pl, pl.o_tcells), wsp<double>(pl, pl.o_gpgrp), pl.prm.theta, direct,
+                     pl.direct_below, 0, near_ptr, far_ptr, (int*)nullptr, (int*)nullptr,
+                     (long long)0, (long long)0);
+  PBTC_LAUNCH_CHECK();
+  scan_exclusive<long long>(near_ptr, pl.nitems_adj, scan_scratch, st);
+  scan_exclusive<long long>(far_ptr, pl.nitems_adj, scan_scratch, st);
+  long long tot[2] = {0, 0};
+  PBTC_HIP(hipMemcpyAsync(&tot[0], near_ptr + pl.nitems_adj, 8, hipMemcpyDeviceToHost, st));
+  PBTC_HIP(hipMemcpyAsync(&tot[1], far_ptr + pl.nitems_adj, 8, hipMemcpyDeviceToHost, st));
+  PBTC_HIP(hipStreamSynchronize(st));
+  if (tot[0] > pl.cap_anear || tot[1] > pl.cap_afar) {
+    pl.cap_anear = std::max<int64_t>(pl.cap_anear, tot[0] + tot[0] / 8 + 1024);
+    pl.cap_afar = std::max<int64_t>(pl.cap_afar, tot[1] + tot[1] / 8 + 1024);
+    *need_retry = 1;
+    pl.err = "adjoint lists larger than the workspace estimate";
+    return PBTC_EWORKSPACE;
+  }
+  pl.n_anear = tot[0];
+  pl.n_afar = tot[1];
+  hipLaunchKernelGGL(k_adj_lists, dim3(nblocks(pl.nitems_adj, 64)), dim3(64), 0, st, pl.nitems_adj,
+                     wsp<int>(pl, pl.o_aitems), wsp<DevBlock>(pl, pl.o_blocks),
+                     wsp<Cell>(pl, pl.o_tcells), wsp<double>(pl, pl.o_gpgrp), pl.prm.theta, direct,
+                     pl.direct_below, 1, near_ptr, far_ptr, wsp<int>(pl, pl.o_anear),
+                     wsp<int>(pl, pl.o_afar), (long long)pl.cap_anear, (long long)pl.cap_afar);
+  PBTC_LAUNCH_CHECK();
+  // work units
+  {
+    std::vector<long long> np_(pl.nitems_adj + 1), fp_(pl.nitems_adj + 1);
+    std::vector<int> nl(std::max<int64_t>(pl.n_anear, 1));
+    std::vector<Cell> hc(pl.n_tcells);
+    PBTC_HIP(hipMemcpy(np_.data(), near_ptr, 8 * (pl.nitems_adj + 1), hipMemcpyDeviceToHost));
+    PBTC_HIP(hipMemcpy(fp_.data(), far_ptr, 8 * (pl.nitems_adj + 1), hipMemcpyDeviceToHost));
+    if (pl.n_anear)
+      PBTC_HIP(hipMemcpy(nl.data(), wsp<int>(pl, pl.o_anear), 4 * pl.n_anear, hipMemcpyDeviceToHost));
+    PBTC_HIP(hipMemcpy(hc.data(), wsp<Cell>(pl, pl.o_tcells), sizeof(Cell) * pl.n_tcells,
+                       hipMemcpyDeviceToHost));
+    constexpr int kUnitSources = 1024, kUnitCells = 32;
+    std::vector<int4> units;
+    std::vector<int> uptr;
+    const bool tree = pl.prm.op == PBTC_OP_TREECODE;
+    for (int ph = 0; ph < 2; ++ph)
+      for (int ks = 0; ks < KS_COUNT; ++ks)
+        for (int kind = 0; kind < 2; ++kind) {
+          UnitSet& us = pl.aunits[ph][ks][kind];
+          us.off = (int64_t)units.size();
+          us.ptr_off = (int64_t)uptr.size();
+          for (int item : pl.aitem_list[ph][ks]) {
+            uptr.push_back((int)(units.size() - us.off));
+            if (kind == 0) {
+              long long e = np_[item], acc = 0, start = e;
+              for (; e < np_[item + 1]; ++e) {
+                const int cnt = hc[nl[e]].count;
+                if (acc > 0 && acc + cnt > kUnitSources) {
+                  units.push_back(make_int4(item, (int)start, (int)e, 0));
+                  start = e;
+                  acc = 0;
+                }
+                acc += cnt;
+              }
+              if (e > start) units.push_back(make_int4(item, (int)start, (int)e, 0));
+            } else if (tree) {
+              for (long long e = fp_[item]; e < fp_[item + 1]; e += kUnitCells)
+                units.push_back(make_int4(item, (int)e,
+                                          (int)std::min<long long>(e + kUnitCells, fp_[item + 1]), 0));
+            }
+          }
+          uptr.push_back((int)(units.size() - us.off));
+          us.n = (int64_t)units.size() - us.off;
+        }
+    if ((int64_t)units.size() > pl.cap_aunits || (int64_t)uptr.size() > pl.cap_auptr) {
+      pl.cap_aunits = (int64_t)units.size() + 1024;
+      pl.cap_auptr = (int64_t)uptr.size() + 64;
+      *need_retry = 1;
+      pl.err = "adjoint work units exceed the workspace estimate";
+      return PBTC_EWORKSPACE;
+    }
+    PBTC_HIP(hipMemcpy(wsp<int4>(pl, pl.o_aunits), units.data(), 16 * units.size(), hipMemcpyHostToDevice));
+    PBTC_HIP(hipMemcpy(wsp<int>(pl, pl.o_auptr), uptr.data(), 4 * uptr.size(), hipMemcpyHostToDevice));
+  }
+  // transposed near-field table (CSC by (block, panel)), deterministic order
+  {
+    long long* cnt = wsp<long long>(pl, pl.o_csc_fill);
+    long long* cptr = wsp<long long>(pl, pl.o_csc_ptr);
+    hipLaunchKernelGGL(k_zero_ll, dim3(nblocks(pl.ncsc + 1, T)), dim3(T), 0, st, cnt, pl.ncsc + 1);
+    hipLaunchKernelGGL(k_csc_count, dim3(nblocks(pl.nf_rows, T)), dim3(T), 0, st, pl.nf_rows,
+                       wsp<int>(pl, pl.o_nf_rowblk), wsp<DevBlock>(pl, pl.o_blocks),
+                       wsp<long long>(pl, pl.o_nf_ptr), wsp<int>(pl, pl.o_nf_col), cnt, cptr,
+                       (int*)nullptr, (int*)nullptr, 0);
+    PBTC_HIP(hipMemcpyAsync(cptr, cnt, 8 * pl.ncsc, hipMemcpyDeviceToDevice, st));
+    scan_exclusive<long long>(cptr, pl.ncsc, scan_scratch, st);
+    hipLaunchKernelGGL(k_zero_ll, dim3(nblocks(pl.ncsc + 1, T)), dim3(T), 0, st, cnt, pl.ncsc + 1);
+    hipLaunchKernelGGL(k_csc_count, dim3(nblocks(pl.nf_rows, T)), dim3(T), 0, st, pl.nf_rows,
+                       wsp<int>(pl, pl.o_nf_rowblk), wsp<DevBlock>(pl, pl.o_blocks),
+                       wsp<long long>(pl, pl.o_nf_ptr), wsp<int>(pl, pl.o_nf_col), cnt, cptr,
+                       wsp<int>(pl, pl.o_csc_ent), wsp<int>(pl, pl.o_csc_row), 1);
+    hipLaunchKernelGGL(k_csc_sort, dim3(nblocks(pl.ncsc, T)), dim3(T), 0, st, pl.ncsc, cptr,
+                       wsp<int>(pl, pl.o_csc_ent), wsp<int>(pl, pl.o_csc_row));
+    PBTC_LAUNCH_CHECK();
+    PBTC_HIP(hipStreamSynchronize(st));
+  }
+  pl.adj_done = true;
+  return PBTC_OK;
+}
+
+// slot tables, item lists and gather tables of the transposed operator
+static int adj_upload_small(pbtc_plan& pl, hipStream_t st) {
+  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_aitems), pl.aitem_block.data(),
+                          4 * pl.aitem_block.size(), hipMemcpyHostToDevice, st));
+  for (int ph = 0; ph < 2; ++ph) {
+    for (int ks = 0; ks < KS_COUNT; ++ks)
+      if (!pl.aitem_list[ph][ks].empty())
+        PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_aitem_list[ph][ks]), pl.aitem_list[ph][ks].data(),
+                                4 * pl.aitem_list[ph][ks].size(), hipMemcpyHostToDevice, st));
+    if (!pl.slots[ph].empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<DevSlot>(pl, pl.o_slots[ph]), pl.slots[ph].data(),
+                              sizeof(DevSlot) * pl.slots[ph].size(), hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<DevGather>(pl, pl.o_gather[ph]), pl.gathers[ph].data(),
+                            sizeof(DevGather) * pl.gathers[ph].size(), hipMemcpyHostToDevice, st));
+    if (!pl.gather_slots[ph].empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_gather_slots[ph]), pl.gather_slots[ph].data(),
+                              4 * pl.gather_slots[ph].size(), hipMemcpyHostToDevice, st));
+  }
+  // slot -> block, kernel index; per phase: slot ids and block ids
+  std::vector<int> sb, sk, blk[2], sid[2];
+  for (size_t bi = 0; bi < pl.blocks.size(); ++bi) {
+    const Block& b = pl.blocks[bi];
+    for (int k = 0; k < b.nk; ++k) {
+      sb.push_back((int)bi);
+      sk.push_back(k);
+      sid[b.reaction ? 1 : 0].push_back((int)(pl.blk_slot0[bi] + k));
+    }
+    blk[b.reaction ? 1 : 0].push_back((int)bi);
+  }
+  pl.adj_blist[0] = blk[0];
+  pl.adj_blist[1] = blk[1];
+  pl.adj_sids[0] = sid[0];
+  pl.adj_sids[1] = sid[1];
+  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_slot_block), sb.data(), 4 * sb.size(), hipMemcpyHostToDevice, st));
+  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_slot_kidx), sk.data(), 4 * sk.size(), hipMemcpyHostToDevice, st));
+  for (int ph = 0; ph < 2; ++ph) {
+    if (!blk[ph].empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_adj_blist[ph]), blk[ph].data(), 4 * blk[ph].size(),
+                              hipMemcpyHostToDevice, st));
+    if (!sid[ph].empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_adj_sids[ph]), sid[ph].data(), 4 * sid[ph].size(),
+                              hipMemcpyHostToDevice, st));
+  }
+  std::vector<long long> tab(2 * (pl.nsurf + 1));
+  for (int s = 0; s <= pl.nsurf; ++s) {
+    tab[s] = pl.pan_off[s];
+    tab[pl.nsurf + 1 + s] = pl.gp_off[s];
+  }
+  PBTC_HIP(hipMemcpyAsync(wsp<long long>(pl, pl.o_adj_tab), tab.data(), 8 * tab.size(),
+                          hipMemcpyHostToDevice, st));
+  PBTC_HIP(hipStreamSynchronize(st));
+  return PBTC_OK;
+}
+
+template <typename real>
+static void launch_adj_m2p(pbtc_plan& pl, hipStream_t st, const AdjArgs& a, int grid,
+                           const Src<real>* gpos, const real* mom, int kind, int kslot,
+                           real* partial) {
+#define PBTC_AM2P(PP)                                                                         \
+  case PP:                                                                                    \
+    if (kind == 0)                                                                            \
+      hipLaunchKernelGGL((k_adj_m2p<real, PP, 0>), dim3(grid), dim3(kT), 0, st, a, gpos, mom, \
+                         (long long)pl.cap_tcells, kslot, partial);                           \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_adj_m2p<real, PP, 1>), dim3(grid), dim3(kT), 0, st, a, gpos, mom, \
+                         (long long)pl.cap_tcells, kslot, partial);                           \
+    break;
+  switch (pl.P) {
+    PBTC_AM2P(2)
+    PBTC_AM2P(4)
+    PBTC_AM2P(6)
+    PBTC_AM2P(8)
+    PBTC_AM2P(10)
+    default:
+      break;
+  }
+#undef PBTC_AM2P
+}
+
+template <typename real>
+static int adj_moments(pbtc_plan& pl, hipStream_t st, int phase, real* mom) {
+  const int ns = (int)pl.adj_sids[phase].size();
+  if (ns == 0) return PBTC_OK;
+  const Cell* cells = wsp<Cell>(pl, pl.o_tcells);
+  const int* sids = wsp<int>(pl, pl.o_adj_sids[phase]);
+  const int* sb = wsp<int>(pl, pl.o_slot_block);
+  const int* sk = wsp<int>(pl, pl.o_slot_kidx);
+  const DevBlock* blocks = wsp<DevBlock>(pl, pl.o_blocks);
+  const Src<real>* asrc = wsp<Src<real>>(pl, sizeof(real) == 4 ? pl.o_asrc32 : pl.o_asrc64);
+  const long long cap = pl.cap_tcells;
+#define PBTC_AMOM(PP)                                                                          \
+  case PP:                                                                                     \
+    hipLaunchKernelGGL((k_adj_p2m<real, PP>), dim3((unsigned)pl.n_tcells, ns), dim3(128), 0, st, \
+                       cells, sb, sk, sids, blocks, asrc, mom, cap);                           \
+    for (int l = pl.n_tlevels - 1; l >= 0; --l) {                                              \
+      const int lb = pl.tlevel_begin[l], le = pl.tlevel_begin[l + 1];                          \
+      if (le > lb)                                                                             \
+        hipLaunchKernelGGL((k_adj_m2m<real, PP>), dim3(le - lb, ns), dim3(128), 0, st, cells,  \
+                           lb, sb, sids, blocks, mom, cap);                                    \
+    }                                                                                          \
+    break;
+  switch (pl.P) {
+    PBTC_AMOM(2)
+    PBTC_AMOM(4)
+    PBTC_AMOM(6)
+    PBTC_AMOM(8)
+    PBTC_AMOM(10)
+    default:
+      return PBTC_EINVAL;
+  }
+#undef PBTC_AMOM
+  PBTC_LAUNCH_CHECK();
+  return PBTC_OK;
+}
+
+// z = A^T lam (phase 0) or z = S^T lam (phase 1, lam = charge weights)
+template <typename real>
+static int transpose_impl(pbtc_plan& pl, hipStream_t st, const double* lam, double* z, int phase) {
+  const int T = 256;
+  const bool tree = pl.prm.op == PBTC_OP_TREECODE;
+  double* muS = wsp<double>(pl, pl.o_mu_s);
+  double* muD = wsp<double>(pl, pl.o_mu_d);
+  const auto& slots = pl.slots[phase];
+  if (slots.empty()) {
+    hipMemsetAsync(z, 0, 8 * pl.nunk, st);
+    return PBTC_OK;
+  }
+  {
+    int64_t nmax = 0;
+    for (const DevSlot& s : slots) nmax = std::max<int64_t>(nmax, s.n);
+    hipLaunchKernelGGL(k_adj_mu, dim3(nblocks(nmax, T), (unsigned)slots.size()), dim3(T), 0, st,
+                       wsp<DevSlot>(pl, pl.o_slots[phase]), lam, muS, muD);
+  }
+  const real* tx = wsp<real>(pl, sizeof(real) == 4 ? pl.o_txf : pl.o_tx);
+  const real* ty = wsp<real>(pl, sizeof(real) == 4 ? pl.o_tyf : pl.o_ty);
+  const real* tz = wsp<real>(pl, sizeof(real) == 4 ? pl.o_tzf : pl.o_tz);
+  Src<real>* asrc = wsp<Src<real>>(pl, sizeof(real) == 4 ? pl.o_asrc32 : pl.o_asrc64);
+  {
+    int64_t nmax = 0;
+    for (int bi : pl.adj_blist[phase]) nmax = std::max<int64_t>(nmax, pl.tsets[pl.blocks[bi].t].n);
+    hipLaunchKernelGGL(k_adj_src<real>, dim3(nblocks(nmax, T), (unsigned)pl.adj_blist[phase].size()),
+                       dim3(T), 0, st, wsp<int>(pl, pl.o_adj_blist[phase]),
+                       wsp<DevBlock>(pl, pl.o_blocks), tx, ty, tz, wsp<int>(pl, pl.o_tidx), muS,
+                       muD, asrc);
+  }
+  PBTC_LAUNCH_CHECK();
+  real* mom = wsp<real>(pl, sizeof(real) == 4 ? pl.o_amom32 : pl.o_amom64);
+  if (tree) {
+    const int rc = adj_moments<real>(pl, st, phase, mom);
+    if (rc) return rc;
+  }
+  const Src<real>* gpos = wsp<Src<real>>(pl, sizeof(real) == 4 ? pl.o_gpos32 : pl.o_gpos64);
+  real* partial = wsp<real>(pl, pl.o_partial);
+  double* aS = wsp<double>(pl, pl.o_aout_s);
+  double* aD = wsp<double>(pl, pl.o_aout_d);
+  AdjArgs a;
+  a.item_block = wsp<int>(pl, pl.o_aitems);
+  a.blocks = wsp<DevBlock>(pl, pl.o_blocks);
+  a.cells = wsp<Cell>(pl, pl.o_tcells);
+  for (int ks = 0; ks < KS_COUNT; ++ks) {
+    const int n = (int)pl.aitem_list[phase][ks].size();
+    if (n == 0) continue;
+    const int* list = wsp<int>(pl, pl.o_aitem_list[phase][ks]);
+    const bool two = ks == KS_LY || ks == KS_YY;
+    {
+      const UnitSet& us = pl.aunits[phase][ks][0];
+      a.units = wsp<int4>(pl, pl.o_aunits + 16 * us.off);
+      a.nunits = (int)us.n;
+      a.cells_list = wsp<int>(pl, pl.o_anear);
+      const int grid = nblocks(us.n, kWaves);
+      if (us.n > 0) {
+        switch (ks) {
+          case KS_L: hipLaunchKernelGGL((k_adj_p2p<real, KS_L>), dim3(grid), dim3(kT), 0, st, a, gpos, asrc, partial); break;
+          case KS_Y: hipLaunchKernelGGL((k_adj_p2p<real, KS_Y>), dim3(grid), dim3(kT), 0, st, a, gpos, asrc, partial); break;
+          case KS_LY: hipLaunchKernelGGL((k_adj_p2p<real, KS_LY>), dim3(grid), dim3(kT), 0, st, a, gpos, asrc, partial); break;
+          case KS_YY: hipLaunchKernelGGL((k_adj_p2p<real, KS_YY>), dim3(grid), dim3(kT), 0, st, a, gpos, asrc, partial); break;
+        }
+      }
+      const int* uptr = wsp<int>(pl, pl.o_auptr + 4 * us.ptr_off);
+      if (two)
+        hipLaunchKernelGGL((k_adj_reduce<real, 4>), dim3(n), dim3(64), 0, st, list, uptr, a.item_block,
+                           a.blocks, partial, aS, aD, 0, 0);
+      else
+        hipLaunchKernelGGL((k_adj_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr, a.item_block,
+                           a.blocks, partial, aS, aD, 0, 0);
+      PBTC_LAUNCH_CHECK();
+    }
+    if (tree && pl.n_afar > 0) {
+      const UnitSet& us = pl.aunits[phase][ks][1];
+      if (us.n == 0) continue;
+      a.units = wsp<int4>(pl, pl.o_aunits + 16 * us.off);
+      a.nunits = (int)us.n;
+      a.cells_list = wsp<int>(pl, pl.o_afar);
+      const int grid = nblocks(us.n, kWaves);
+      const int* uptr = wsp<int>(pl, pl.o_auptr + 4 * us.ptr_off);
+      const int kind0 = (ks == KS_L || ks == KS_LY) ? 0 : 1;
+      for (int slot = 0; slot < (two ? 2 : 1); ++slot) {
+        launch_adj_m2p<real>(pl, st, a, grid, gpos, mom, slot == 0 ? kind0 : 1, slot, partial);
+        hipLaunchKernelGGL((k_adj_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr,
+                           a.item_block, a.blocks, partial, aS, aD, 1, slot);
+      }
+      PBTC_LAUNCH_CHECK();
+    }
+  }
+  const long long* tab = wsp<long long>(pl, pl.o_adj_tab);
+  hipLaunchKernelGGL(k_adj_gather<real>, dim3(nblocks(pl.np_tot, T)), dim3(T), 0, st, pl.np_tot,
+                     pl.prm.K, wsp<int>(pl, pl.o_pan_surf), tab, tab + pl.nsurf + 1,
+                     wsp<DevGather>(pl, pl.o_gather[phase]), wsp<int>(pl, pl.o_gather_slots[phase]),
+                     wsp<int>(pl, pl.o_slot_block), wsp<int>(pl, pl.o_slot_kidx),
+                     wsp<DevBlock>(pl, pl.o_blocks), wsp<int>(pl, pl.o_gp_pos),
+                     wsp<double>(pl, pl.o_gw), aS, aD, wsp<long long>(pl, pl.o_csc_ptr),
+                     wsp<int>(pl, pl.o_csc_ent), wsp<int>(pl, pl.o_csc_row),
+                     wsp<real>(pl, sizeof(real) == 4 ? pl.o_nf_v32 : pl.o_nf_v64), muS, muD,
+                     wsp<int>(pl, pl.o_pidx), lam, phase == 0 ? 1 : 0, z);
+  PBTC_LAUNCH_CHECK();
+  return PBTC_OK;
+}
+
+static int ensure_adjoint(pbtc_plan& pl, hipStream_t st) {
+  if (pl.adj_done) return PBTC_OK;
+  int retry = 0;
+  const int rc = adjoint_setup(pl, st, &retry);
+  if (rc == PBTC_EWORKSPACE && retry)
+    pl.err = "workspace too small for the transposed operator: " + pl.err +
+             " (grow it to pbtc_result.workspace_needed and call again)";
+  return rc;
+}
+
+int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+                    int phase) {
+  const int rc = ensure_adjoint(pl, st);
+  if (rc) return rc;
+  if (precision == PBTC_FP64) return transpose_impl<double>(pl, st, x, y, phase);
+  return transpose_impl<float>(pl, st, x, y, phase);
+}
+
+// sum over the listed (a offset, b offset, n) triples of a . b (device dots -> host)
+static int pair_dots(pbtc_plan& pl, hipStream_t st, const std::vector<long long>& tab,
+                     const double* A, const double* B, std::vector<double>* out) {
+  out->assign(tab.size() / 3, 0.0);
+  if (tab.empty()) return PBTC_OK;
+  long long* dtab = wsp<long long>(pl, pl.o_dots);
+  double* dres = reinterpret_cast<double*>(dtab + 3 * 1024);
+  for (size_t base = 0; base < tab.size() / 3; base += 1024) {
+    const size_t cnt = std::min<size_t>(1024, tab.size() / 3 - base);
+    PBTC_HIP(hipMemcpyAsync(dtab, tab.data() + 3 * base, 8 * 3 * cnt, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_pair_dots, dim3((unsigned)cnt), dim3(kT), 0, st, dtab, A, B, dres);
+    PBTC_LAUNCH_CHECK();
+    PBTC_HIP(hipMemcpyAsync(out->data() + base, dres, 8 * cnt, hipMemcpyDeviceToHost, st));
+    PBTC_HIP(hipStreamSynchronize(st));
+  }
+  return PBTC_OK;
+}
+
+int device_backward(pbtc_plan& pl, hipStream_t st, double gE, double* dq, double* dk, double* de,
+                    pbtc_result* res) {
+  int rc = ensure_adjoint(pl, st);
+  if (rc) {
+    if (res) res->workspace_needed = pl.ws_bytes;
+    return rc;
+  }
+  const int T = 256;
+  const int64_t n = pl.nunk;
+  const double C = 4.0 * kPi * kCoulomb;
+  double* x = wsp<double>(pl, pl.o_x);
+  double* lam = wsp<double>(pl, pl.o_lam);
+  double* rhs = wsp<double>(pl, pl.o_adj_rhs);
+  double* q = wsp<double>(pl, pl.o_q);
+  // adjoint right-hand side S^T q (FP64)
+  rc = transpose_impl<double>(pl, st, q, rhs, 1);
+  if (rc) return rc;
+  int iters = 0, n32 = 0, n64 = 0, nref = 0;
+  double rel = 0.0;
+  bool conv = false;
+  std::vector<double> hist;
+  rc = solve_with_ops(pl, st, true, rhs, lam, &iters, &n32, &n64, &nref, &rel, &conv, &hist);
+  if (rc) return rc;
+  // dG/dq = 1/2 C (phi_reac + B^T lam)
+  double* g = wsp<double>(pl, pl.o_z2);
+  PBTC_HIP(hipMemcpyAsync(g, wsp<double>(pl, pl.o_phi_reac), 8 * pl.nq, hipMemcpyDeviceToDevice, st));
+  for (const RowBlock& rb : pl.rows) {
+    const int r = rb.r;
+    const int64_t nqr = pl.prob.charges[r].n();
+    if (nqr == 0) continue;
+    hipLaunchKernelGGL(k_coulomb_t, dim3(nblocks(nqr, T)), dim3(T), 0, st,
+                       (long long)pl.q_off_region[r], (long long)nqr, wsp<double>(pl, pl.o_qxyz),
+                       wsp<double>(pl, pl.o_cx), wsp<double>(pl, pl.o_cy), wsp<double>(pl, pl.o_cz),
+                       (long long)pl.pan_off[rb.t], (long long)rb.n, lam, (long long)rb.row_off,
+                       1.0 / pl.prob.regions[r].eps, pl.prob.regions[r].kappa, g);
+  }
+  PBTC_LAUNCH_CHECK();
+  std::vector<double> gq(pl.nq);
+  PBTC_HIP(hipMemcpyAsync(gq.data(), g, 8 * pl.nq, hipMemcpyDeviceToHost, st));
+  PBTC_HIP(hipStreamSynchronize(st));
+  if (dq)
+    for (int64_t k = 0; k < pl.nq; ++k) dq[k] = gE * 0.5 * C * gq[k];
+
+  // eps: forward FP64 block outputs at x (A and S), then dot products
+  double* y = wsp<double>(pl, pl.o_r);
+  std::vector<double> deps(pl.nreg, 0.0);
+  {
+    // reaction blocks first (phase 1 leaves S of the reaction blocks), then A
+    rc = apply_operator(pl, st, x, wsp<double>(pl, pl.o_phi_reac), PBTC_FP64, 1);
+    if (rc) return rc;
+    rc = apply_operator(pl, st, x, y, PBTC_FP64, 0);
+    if (rc) return rc;
+    const pbtc_problem& P = pl.prob;
+    auto dratio = [&](int r, int s, int p) {
+      const int i = P.surfaces[s].inner;
+      if (i == r) return 0.0;
+      return (p == i ? 1.0 : 0.0) / P.regions[r].eps -
+             (p == r ? P.regions[i].eps / (P.regions[r].eps * P.regions[r].eps) : 0.0);
+    };
+    auto sigma = [&](int r, int s) { return P.surfaces[s].inner == r ? 1.0 : -1.0; };
+    // <lam_(t,r), S_(b,k)> for every forward term, <q_r, S_(b)> for every reaction term,
+    // <lam_(t,r), b_(t,r)> for every row block
+    std::vector<long long> tA, tS, tB;
+    for (const RowBlock& rb : pl.rows)
+      for (const RowTerm& t : rb.terms)
+        tA.insert(tA.end(), {(long long)rb.row_off, (long long)pl.blocks[t.block].out[t.kidx],
+                             (long long)rb.n});
+    for (const RowBlock& rb : pl.reac_rows)
+      for (const RowTerm& t : rb.terms)
+        tS.insert(tS.end(), {(long long)rb.row_off, (long long)pl.blocks[t.block].out[t.kidx],
+                             (long long)rb.n});
+    for (const RowBlock& rb : pl.rows)
+      tB.insert(tB.end(), {(long long)rb.row_off, (long long)rb.row_off, (long long)rb.n});
+    std::vector<double> dA, dS, dB;
+    rc = pair_dots(pl, st, tA, lam, wsp<double>(pl, pl.o_S), &dA);
+    if (rc) return rc;
+    rc = pair_dots(pl, st, tS, q, wsp<double>(pl, pl.o_S), &dS);
+    if (rc) return rc;
+    rc = pair_dots(pl, st, tB, lam, wsp<double>(pl, pl.o_b), &dB);
+    if (rc) return rc;
+    for (int p = 0; p < pl.nreg; ++p) {
+      double vA = 0.0, vS = 0.0, vB = 0.0;
+      size_t i = 0;
+      for (const RowBlock& rb : pl.rows)
+        for (const RowTerm& t : rb.terms) {
+          const int s = pl.blocks[t.block].s;
+          vA += -sigma(rb.r, s) * dratio(rb.r, s, p) * dA[i++];
+        }
+      i = 0;
+      for (const RowBlock& rb : pl.reac_rows)
+        for (const RowTerm& t : rb.terms) {
+          const int s = pl.blocks[t.block].s;
+          vS += sigma(rb.r, s) * dratio(rb.r, s, p) * dS[i++];
+        }
+      i = 0;
+      for (const RowBlock& rb : pl.rows) {
+        if (rb.r == p) vB += -dB[i] / P.regions[p].eps;
+        ++i;
+      }
+      deps[p] = 0.5 * C * (vS - vA + vB);
+    }
+  }
+  // kappa: central difference of the FP64 operator in kappa_p
+  std::vector<double> dkap(pl.nreg, 0.0);
+  for (int p = 0; p < pl.nreg; ++p) {
+    const double k0 = pl.prob.regions[p].kappa;
+    if (k0 == 0.0) continue;  // a Laplace region: kappa is not a parameter of its kernel
+    const double h = 1e-4 * k0;
+    double val[2] = {0.0, 0.0};
+    for (int side = 0; side < 2; ++side) {
+      const double kp = side == 0 ? k0 + h : k0 - h;
+      pl.prob.regions[p].kappa = kp;
+      for (Block& b : pl.blocks)
+        for (int k = 0; k < b.nk; ++k)
+          if (b.kappa[k] == (side == 0 ? k0 : k0 + h)) b.kappa[k] = kp;
+      rc = upload_descriptors(pl, st);
+      if (!rc) rc = recompute_near_values(pl, st);
+      if (!rc) rc = recompute_rhs(pl, st);
+      if (rc) return rc;
+      double* phi = wsp<double>(pl, pl.o_z2);
+      rc = apply_operator(pl, st, x, phi, PBTC_FP64, 1);
+      if (!rc) rc = apply_operator(pl, st, x, y, PBTC_FP64, 0);
+      if (rc) return rc;
+      std::vector<long long> t1 = {0, 0, (long long)pl.nq};
+      std::vector<long long> t2 = {0, 0, (long long)n};
+      std::vector<double> r1, r2, r3;
+      rc = pair_dots(pl, st, t1, q, phi, &r1);
+      if (!rc) rc = pair_dots(pl, st, t2, lam, y, &r2);
+      if (!rc) rc = pair_dots(pl, st, t2, lam, wsp<double>(pl, pl.o_b), &r3);
+      if (rc) return rc;
+      val[side] = r1[0] - r2[0] + r3[0];
+    }
+    // restore kappa
+    pl.prob.regions[p].kappa = k0;
+    for (Block& b : pl.blocks)
+      for (int k = 0; k < b.nk; ++k)
+        if (b.kappa[k] == k0 - h) b.kappa[k] = k0;
+    rc = upload_descriptors(pl, st);
+    if (!rc) rc = recompute_near_values(pl, st);
+    if (!rc) rc = recompute_rhs(pl, st);
+    if (rc) return rc;
+    dkap[p] = 0.5 * C * (val[0] - val[1]) / (2.0 * h);
+  }
+  // restore the forward outputs of x (phi_reac on the device)
+  rc = apply_operator(pl, st, x, wsp<double>(pl, pl.o_phi_reac), PBTC_FP64, 1);
+  if (rc) return rc;
+  PBTC_HIP(hipStreamSynchronize(st));
+  if (dk)
+    for (int p = 0; p < pl.nreg; ++p) dk[p] = gE * dkap[p];
+  if (de)
+    for (int p = 0; p < pl.nreg; ++p) de[p] = gE * deps[p];
+  if (res) {
+    res->energy_kJmol = pl.energy;
+    res->n_iter = iters;
+    res->converged = conv ? 1 : 0;
+    res->final_rel_res = rel;
+    res->n_matvec_fp32 = n32;
+    res->n_matvec_fp64 = n64;
+    res->n_refine = nref;
+  }
+  pl.adj_history = hist;
+  if (!conv) {
+    pl.err = "adjoint GMRES did not reach the tolerance within max_iter";
+    return PBTC_ENOCONV;
+  }
+  return PBTC_OK;
+}
+
 
 }  // namespace pbtc

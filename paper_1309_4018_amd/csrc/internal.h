@@ -105,6 +105,29 @@ struct DevBlock {
   int self;                  // 1 if the target set is the source surface itself
   int tkind;                 // 0: surface collocation points, 1: charges
   int pad;
+  // transposed evaluation: sources at the targets of t, targets at the
+  // Gauss points of s
+  long long aitem_off;       // first (block, Gauss-point group) item
+  long long gpgrp_off;       // first Gauss-point group of surface s
+  long long aout0, aout1;    // per-Gauss-point outputs of kernel slots 0 / 1
+  long long csc_off;         // first transposed near-field column of this block
+  int slot0;                 // kernel slot of kernel 0 (slot0 + 1 for kernel 1)
+  int troot;                 // root cell of the target-set tree
+};
+
+// Weights of one (block, kernel) slot of the transposed operator:
+// muS = sum_c cS[c] lam[lam_off[c] + i], muD likewise (at most two rows).
+struct DevSlot {
+  long long out;        // offset of mu in the S/D-shaped arrays (= block out[k])
+  long long n;          // targets of the block's target set
+  long long lam_off[2];
+  double cS[2], cD[2];
+  int ncontrib, block;
+};
+
+// Per surface: the slots (blocks x kernels) whose sources are its Gauss points.
+struct DevGather {
+  int slot_off, nslots;
 };
 
 struct DevRowBlock {
@@ -139,6 +162,12 @@ struct Layout {
 };
 
 struct Timer;
+
+// A run of work units (one wavefront each) over the lists of one kernel set.
+struct UnitSet {
+  int64_t off = 0, n = 0;   // units [off, off + n) of the unit pool
+  int64_t ptr_off = 0;      // per listed item: first unit (n_items + 1 entries)
+};
 
 }  // namespace pbtc
 
@@ -190,8 +219,27 @@ struct pbtc_plan {
   size_t fixed_bytes = 0;
   size_t ws_bytes = 0;
 
+  // independent systems (connected components of the region graph, e.g. the
+  // molecules of a batch): unknown range, charge range, Krylov chunks
+  int ncomp = 1;
+  std::vector<int> comp_of_surface, comp_of_region;
+  std::vector<int64_t> comp_u0, comp_u1;       // unknown range per component
+  std::vector<int4> dot_chunks;                 // (component, start, end, -)
+  std::vector<int> comp_chunk0;                 // first chunk per component (+ end)
+  std::vector<double> comp_energy;
+  std::vector<int> comp_iters;
+  std::vector<double> comp_rel;
+  size_t o_comp_of_unk = 0, o_chunks = 0, o_comp_q = 0, o_kstate = 0;
   // device state
   void* ws = nullptr;
+  void* inputs_ws = nullptr;  // workspace that already holds the uploaded inputs
+  // profiling (params.profile): events around P2P (kind 0) and M2P (kind 1)
+  struct ProfEvent { int kind; double flop; hipEvent_t a, b; };
+  std::vector<ProfEvent> prof, prof_pool;
+  double prof_t[2] = {0, 0}, prof_flop[2] = {0, 0};
+  int prof_n[2] = {0, 0};
+  std::vector<double> item_flop_p2p[2][pbtc::KS_COUNT], item_flop_m2p[2][pbtc::KS_COUNT];
+  double launch_flop_p2p[2][pbtc::KS_COUNT] = {}, launch_flop_m2p[2][pbtc::KS_COUNT] = {};
   bool setup_done = false;
   int n_levels = 0;
   std::vector<int> level_begin;  // cell index where each level starts (+ end)
@@ -202,11 +250,44 @@ struct pbtc_plan {
   std::vector<int> item_block;    // item -> block
   std::vector<double> tcube;      // per target set: cx, cy, cz, half
   int64_t nf_rows = 0, nf_fwd_rows = 0;
+  // transposed operator (pbtc_backward, pbtc_matvec_transpose)
+  bool adj_done = false;
+  int64_t ngpgrp = 0, nitems_adj = 0, naout = 0, ncsc = 0, n_tcells = 0;
+  int64_t cap_tcells = 0, cap_anear = 0, cap_afar = 0, n_anear = 0, n_afar = 0;
+  std::vector<int64_t> gpgrp_off;   // per surface
+  std::vector<int> aitem_block;
+  std::vector<int> aitem_list[2][pbtc::KS_COUNT];
+  size_t o_aitem_list[2][pbtc::KS_COUNT];
+  std::vector<pbtc::DevSlot> slots[2];   // phase 0: rows of A, phase 1: reaction rows
+  std::vector<int> gather_slots[2];      // per phase, slots grouped by surface
+  std::vector<pbtc::DevGather> gathers[2];
+  std::vector<int> tlevel_begin;
+  int n_tlevels = 0;
+  std::vector<int64_t> blk_slot0, blk_aout0, blk_aout1, blk_aitem_off, blk_csc_off;
+  size_t o_tkey_sorted = 0, o_gpos32 = 0, o_gpos64 = 0, o_gp_pos = 0, o_gpgrp = 0;
+  size_t o_mu_s = 0, o_mu_d = 0, o_asrc32 = 0, o_asrc64 = 0, o_aout_s = 0, o_aout_d = 0;
+  size_t o_aitems = 0, o_slots[2] = {0, 0}, o_gather[2] = {0, 0}, o_gather_slots[2] = {0, 0};
+  size_t o_csc_ptr = 0, o_csc_ent = 0, o_csc_fill = 0;
+  size_t o_tcells = 0, o_tcnt = 0, o_amom32 = 0, o_amom64 = 0;
+  size_t o_anear_ptr = 0, o_afar_ptr = 0, o_anear = 0, o_afar = 0;
+  size_t o_z2 = 0, o_dots = 0, o_surf_tab = 0;
+  // wavefront work units: [phase][kernel set][0 = P2P, 1 = M2P]
+  pbtc::UnitSet units[2][pbtc::KS_COUNT][2];
+  int64_t cap_units = 0, n_units = 0, n_uptr = 0;
+  size_t o_units = 0, o_uptr = 0, o_partial = 0;
+  // transposed operator: units, slot and block tables
+  pbtc::UnitSet aunits[2][pbtc::KS_COUNT][2];
+  int64_t cap_aunits = 0, cap_auptr = 0;
+  size_t o_aunits = 0, o_auptr = 0, o_slot_block = 0, o_slot_kidx = 0, o_adj_tab = 0;
+  size_t o_adj_blist[2] = {0, 0}, o_adj_sids[2] = {0, 0}, o_csc_row = 0;
+  std::vector<int> adj_blist[2], adj_sids[2];
+  std::vector<double> adj_history;
   size_t o_nf_rowblk = 0;                          // near-field row -> block (int)
   size_t o_grp_tab = 0;                            // group target offsets and counts
   size_t o_tkey = 0, o_tkey2 = 0, o_tval = 0, o_tval2 = 0;  // target sort buffers
   double p2p_pairs = 0, m2p_evals = 0, dense_equiv = 0;
   bool solved = false;
+  bool charges_dirty = false;
 
   // host results
   std::vector<double> x_host, phi_reac_host, history;

@@ -1,0 +1,39 @@
+// Shared device helpers of the operator kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pbtc {
+
+// One source record of the treecode: position, single-layer strength and
+// double-layer dipole (forward operator), or position and the adjoint
+// weights of up to two kernels (transposed operator).
+template <typename real>
+struct alignas(16) Src {
+  real x, y, z, q, px, py, pz, pad;
+};
+
+template <typename real>
+__device__ __forceinline__ real rsqrt_(real v);
+template <>
+__device__ __forceinline__ float rsqrt_(float v) {
+  return __builtin_amdgcn_rsqf(v);
+}
+template <>
+__device__ __forceinline__ double rsqrt_(double v) {
+  return 1.0 / sqrt(v);
+}
+
+// exp(-v): FP32 through the hardware exp2, FP64 through the math library
+template <typename real>
+__device__ __forceinline__ real exp_neg(real v);
+template <>
+__device__ __forceinline__ float exp_neg(float v) {
+  return __builtin_amdgcn_exp2f(-1.4426950408889634f * v);
+}
+template <>
+__device__ __forceinline__ double exp_neg(double v) {
+  return exp(-v);
+}
+
+}  // namespace pbtc

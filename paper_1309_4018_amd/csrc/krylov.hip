@@ -20,6 +20,10 @@ int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, in
                    int phase);
 int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
                     int phase);
+void prof_collect(pbtc_plan& pl);
+
+// per-system scalar arrays of the Krylov state
+enum { SC_BNORM = 0, SC_RES, SC_ACTIVE, SC_BETA, SC_HN, SC_TOL, SC_KFIN, SC_REF, SC_NORM, SC_N };
 
 namespace {
 
@@ -175,80 +179,256 @@ __global__ void k_energy(const double* __restrict__ q, const double* __restrict_
   if (threadIdx.x == 0) out[0] = factor * s;
 }
 
+
+// partial[chunk * ld + i] = <V_i, w> over the chunk (i < nv)
+__global__ __launch_bounds__(kRedThreads) void k_dots_seg(const double* __restrict__ V, int nv,
+                                                          int64_t n, const double* __restrict__ w,
+                                                          const int4* __restrict__ chunks,
+                                                          double* __restrict__ partial, int ld) {
+  __shared__ double lds[kRedThreads / 64];
+  const int4 ch = chunks[blockIdx.x];
+  for (int i = 0; i < nv; ++i) {
+    double s = 0.0;
+    for (int64_t j = ch.y + threadIdx.x; j < ch.z; j += kRedThreads) s += V[(size_t)i * n + j] * w[j];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ld + i] = s;
+  }
+}
+
+// out[c * ldo + i] = sum of the chunks of system c
+__global__ void k_sum_seg(const double* __restrict__ partial, int pld, const int* __restrict__ chunk0,
+                          int nv, int ldo, double* __restrict__ out) {
+  __shared__ double lds[kRedThreads / 64];
+  const int c = blockIdx.x;
+  for (int i = 0; i < nv; ++i) {
+    double s = 0.0;
+    for (int b = chunk0[c] + threadIdx.x; b < chunk0[c + 1]; b += kRedThreads)
+      s += partial[(size_t)b * pld + i];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) out[(size_t)c * ldo + i] = s;
+  }
+}
+
+__global__ void k_sqrt_n(double* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = sqrt(fmax(p[i], 0.0));
+}
+
+// w -= sum_i h[c, i] V_i on the entries of system c
+__global__ void k_sub_combo_seg(const double* __restrict__ V, int nv, int64_t n,
+                                const double* __restrict__ h, int ld, const int* __restrict__ comp,
+                                double* __restrict__ w) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double* hc = h + (size_t)comp[j] * ld;
+  double s = w[j];
+  for (int i = 0; i < nv; ++i) s -= hc[i] * V[(size_t)i * n + j];
+  w[j] = s;
+}
+
+// out = w / s[c] for active systems, 0 for the others
+__global__ void k_scale_seg(const double* __restrict__ w, int64_t n, const double* __restrict__ s,
+                            const int* __restrict__ comp, const double* __restrict__ active,
+                            double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int c = comp[j];
+  out[j] = (active[c] > 0.0 && s[c] > 0.0) ? w[j] / s[c] : 0.0;
+}
+
+// start of a restart cycle: g = (beta, 0, ...), kfin = 0
+__global__ void k_init_seg(int nc, double* giv, int gstride, int ld, const double* beta,
+                           double* kfin) {
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double* g = giv + (size_t)c * gstride + 2 * ld;
+    for (int i = 0; i < ld + 1; ++i) g[i] = 0.0;
+    g[0] = beta[c];
+    kfin[c] = 0.0;
+  }
+}
+
+// Givens step for column j of every active system: H(:, j) = h, H(j+1, j) =
+// hn; apply the stored rotations, form the new one, update g, and deactivate
+// the system once |g_{j+1}| <= tol * ref (kfin = j + 1).
+__global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h,
+                             double* __restrict__ H, double* __restrict__ giv, int gstride,
+                             double* __restrict__ sc) {
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double* act = sc + (size_t)SC_ACTIVE * nc;
+    if (act[c] <= 0.0) continue;
+    double* cs = giv + (size_t)c * gstride;
+    double* sn = cs + ld;
+    double* g = cs + 2 * ld;
+    double* col = H + ((size_t)c * ld + j) * ld;
+    const double* hc = h + (size_t)c * ld;
+    for (int i = 0; i <= j; ++i) col[i] = hc[i];
+    col[j + 1] = sc[(size_t)SC_HN * nc + c];
+    for (int i = 0; i < j; ++i) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = cs[i] * a + sn[i] * b;
+      col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = hypot(a, b);
+    const double cc = den > 0.0 ? a / den : 1.0, ss = den > 0.0 ? b / den : 0.0;
+    cs[j] = cc;
+    sn[j] = ss;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    g[j + 1] = -ss * g[j];
+    g[j] = cc * g[j];
+    const double ref = sc[(size_t)SC_REF * nc + c];
+    const double res = fabs(g[j + 1]) / ref;
+    sc[(size_t)SC_RES * nc + c] = res;
+    if (res <= sc[(size_t)SC_TOL * nc + c] || col[j] == 0.0) {
+      act[c] = 0.0;
+      sc[(size_t)SC_KFIN * nc + c] = j + 1;
+    }
+  }
+}
+
+// end of a cycle: kfin of still-active systems = columns built; y = R^-1 g
+__global__ void k_finish_seg(int nc, int ncol, int ld, const double* __restrict__ H,
+                             double* __restrict__ giv, int gstride, double* __restrict__ sc) {
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double* kf = sc + (size_t)SC_KFIN * nc;
+    if (sc[(size_t)SC_ACTIVE * nc + c] > 0.0) kf[c] = ncol;
+    const int k = (int)kf[c];
+    const double* Hc = H + (size_t)c * ld * ld;
+    const double* g = giv + (size_t)c * gstride + 2 * ld;
+    double* y = giv + (size_t)c * gstride + 3 * ld + 1;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int q = i + 1; q < k; ++q) s -= Hc[(size_t)q * ld + i] * y[q];
+      const double d = Hc[(size_t)i * ld + i];
+      y[i] = d != 0.0 ? s / d : 0.0;
+    }
+  }
+}
+
+// x += sum_{i < kfin[c]} y[c, i] V_i on the entries of system c
+__global__ void k_add_combo_seg(const double* __restrict__ V, int64_t n, const double* __restrict__ giv,
+                                int gstride, int ld, const double* __restrict__ kfin,
+                                const int* __restrict__ comp, double* __restrict__ x) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int c = comp[j];
+  const int k = (int)kfin[c];
+  const double* y = giv + (size_t)c * gstride + 3 * ld + 1;
+  double s = x[j];
+  for (int i = 0; i < k; ++i) s += y[i] * V[(size_t)i * n + j];
+  x[j] = s;
+}
+
+// energy of every system: 1/2 C sum over its charges of q phi
+__global__ void k_energy_seg(const double* __restrict__ q, const double* __restrict__ phi,
+                             const int* __restrict__ cq, int64_t n, double factor,
+                             double* __restrict__ out) {
+  __shared__ double lds[kRedThreads / 64];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kRedThreads)
+    if (cq[i] == c) s += q[i] * phi[i];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) out[c] = factor * s;
+}
+
 }  // namespace
 
+// Krylov state of every independent system (a connected component of the
+// region graph): H, Givens data and scalars live per system in o_kstate;
+// vector operations run over the whole unknown vector, reductions per system.
 struct Krylov {
   pbtc_plan& pl;
   hipStream_t st;
   int64_t n;
-  int m;
+  int m, ld, nc, nchunks;
   double* V;
-  double* H;
-  double* giv;
-  double* scal;  // [0] norm, [1] beta, [2] res, [3..] h and h2
-  double* red;
+  double* H;      // nc x ld x ld, column-major per system
+  double* giv;    // nc x gstride: cs (ld), sn (ld), g (ld + 1), y (ld + 1)
+  int gstride;
+  double* sc;     // SC_N x nc
+  double* red;    // partials: nchunks x ld
+  double* hbuf;   // nc x ld
+  double* h2buf;  // nc x ld
   double* w;
-  double* y;
-  double* hbuf;
-  double* h2buf;
+  const int4* chunks;
+  const int* chunk0;
+  const int* comp;
 
   Krylov(pbtc_plan& p, hipStream_t s) : pl(p), st(s) {
     n = pl.nunk;
     m = pl.prm.restart;
+    ld = m + 1;
+    nc = pl.ncomp;
+    nchunks = (int)pl.dot_chunks.size();
+    gstride = 4 * (m + 2);
     V = wsp<double>(pl, pl.o_V);
-    H = wsp<double>(pl, pl.o_H);
-    giv = wsp<double>(pl, pl.o_givens);
-    scal = wsp<double>(pl, pl.o_scal);
+    H = wsp<double>(pl, pl.o_kstate);
+    giv = H + (size_t)nc * ld * ld;
+    sc = giv + (size_t)nc * gstride;
     red = wsp<double>(pl, pl.o_red);
+    hbuf = red + (size_t)nchunks * ld;
+    h2buf = hbuf + (size_t)nc * ld;
     w = wsp<double>(pl, pl.o_w);
-    y = giv + 3 * (m + 1) + 1;
-    hbuf = red + (size_t)kRedBlocks * (m + 2);
-    h2buf = hbuf + (m + 2);
+    chunks = wsp<int4>(pl, pl.o_chunks);
+    chunk0 = reinterpret_cast<const int*>(chunks + nchunks);
+    comp = wsp<int>(pl, pl.o_comp_of_unk);
   }
+  double* scal(int which) { return sc + (size_t)which * nc; }
 
-  int blocks_for(int64_t len) const { return std::min<int>(kRedBlocks, nblocks(len, kRedThreads)); }
-
-  // out[0..nv) = V[0..nv)^T v  (device)
-  int dots(const double* Vb, int nv, const double* v, double* out, int accumulate) {
-    const int nb = blocks_for(n);
-    hipLaunchKernelGGL(k_dots, dim3(nb), dim3(kRedThreads), 0, st, Vb, nv, n, v, red);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kRedThreads), 0, st, red, nb, nv, out,
-                       accumulate);
+  // out[c * ld + i] = <V_i, v> over system c, i < nv
+  int dots(const double* Vb, int nv, const double* v, double* out) {
+    hipLaunchKernelGGL(k_dots_seg, dim3(nchunks), dim3(kRedThreads), 0, st, Vb, nv, n, v, chunks,
+                       red, ld);
+    hipLaunchKernelGGL(k_sum_seg, dim3(nc), dim3(kRedThreads), 0, st, red, ld, chunk0, nv, ld, out);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
-
+  // out[c] = ||v|| over system c
   int norm(const double* v, double* out) {
-    int rc = dots(v, 1, v, out, 0);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_sqrt, dim3(1), dim3(1), 0, st, out);
+    hipLaunchKernelGGL(k_dots_seg, dim3(nchunks), dim3(kRedThreads), 0, st, v, 1, n, v, chunks, red,
+                       ld);
+    hipLaunchKernelGGL(k_sum_seg, dim3(nc), dim3(kRedThreads), 0, st, red, ld, chunk0, 1, 1, out);
+    hipLaunchKernelGGL(k_sqrt_n, dim3(1), dim3(64), 0, st, out, nc);
+    PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
-
-  double host_scalar(const double* d) {
-    double v = 0.0;
-    if (hipMemcpyAsync(&v, d, 8, hipMemcpyDeviceToHost, st) != hipSuccess) return NAN;
-    if (hipStreamSynchronize(st) != hipSuccess) return NAN;
-    return v;
+  bool host(const double* d, double* h, int cnt) {
+    if (hipMemcpyAsync(h, d, 8 * cnt, hipMemcpyDeviceToHost, st) != hipSuccess) return false;
+    return hipStreamSynchronize(st) == hipSuccess;
+  }
+  bool to_dev(double* d, const double* h, int cnt) {
+    if (hipMemcpyAsync(d, h, 8 * cnt, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+    return hipStreamSynchronize(st) == hipSuccess;
   }
 };
 
-// GMRES for A z = rhs (A applied by `op`), z holds the start vector on entry
-// (zero_start: z = 0).  Stops when the implicit residual <= tol * ref_norm.
+// Restarted GMRES for A z = rhs on every system at once.  System c stops
+// when its implicit residual <= tol[c] * ref[c]; its Krylov vectors are zero
+// from then on, so further operator applications leave it untouched.
 template <typename Op>
 static int gmres(pbtc_plan& pl, hipStream_t st, Op op, const double* rhs, double* z, bool zero_start,
-                 double tol, double ref_norm, int max_iter, int* iters, std::vector<double>* hist,
-                 bool* converged) {
+                 const std::vector<double>& tol, const std::vector<double>& ref, int max_iter,
+                 int* iters, std::vector<double>* hist, std::vector<int>* conv,
+                 std::vector<int>* conv_iter) {
   Krylov K(pl, st);
   const int T = 256;
   const int64_t n = K.n;
-  const int m = K.m;
-  const int ld = m + 1;
+  const int m = K.m, nc = K.nc, ld = K.ld;
   double* r = wsp<double>(pl, pl.o_tmp);
-  *converged = false;
+  conv->assign(nc, 0);
+  if (conv_iter) conv_iter->assign(nc, 0);
+  std::vector<double> hbeta(nc), hscal(2 * nc), hact(nc), htol(nc), href(nc);
+  for (int c = 0; c < nc; ++c) {
+    htol[c] = tol[c];
+    href[c] = ref[c];
+  }
+  if (!K.to_dev(K.scal(SC_TOL), htol.data(), nc) || !K.to_dev(K.scal(SC_REF), href.data(), nc)) {
+    pl.err = "GMRES: copy failed";
+    return PBTC_EDEVICE;
+  }
   bool first = true;
   while (*iters < max_iter) {
-    // r = rhs - A z
     if (zero_start && first) {
       hipLaunchKernelGGL(k_fill, dim3(nblocks(n, T)), dim3(T), 0, st, z, n, 0.0);
       PBTC_HIP(hipMemcpyAsync(r, rhs, 8 * n, hipMemcpyDeviceToDevice, st));
@@ -258,61 +438,95 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, const double* rhs, double
       hipLaunchKernelGGL(k_sub, dim3(nblocks(n, T)), dim3(T), 0, st, rhs, r, n, r);
     }
     first = false;
-    int rc = K.norm(r, K.scal + 1);
+    int rc = K.norm(r, K.scal(SC_BETA));
     if (rc) return rc;
-    const double beta = K.host_scalar(K.scal + 1);
-    if (!std::isfinite(beta)) {
-      pl.err = "GMRES: residual is not finite";
+    if (!K.host(K.scal(SC_BETA), hbeta.data(), nc)) {
+      pl.err = "GMRES: copy failed";
       return PBTC_EDEVICE;
     }
-    if (beta <= tol * ref_norm) {
-      *converged = true;
-      break;
+    int nact = 0;
+    for (int c = 0; c < nc; ++c) {
+      if (!std::isfinite(hbeta[c])) {
+        pl.err = "GMRES: residual is not finite";
+        return PBTC_EDEVICE;
+      }
+      const bool done = (*conv)[c] || hbeta[c] <= tol[c] * ref[c];
+      if (done && !(*conv)[c]) {
+        (*conv)[c] = 1;
+        if (conv_iter) (*conv_iter)[c] = *iters;
+      }
+      hact[c] = done ? 0.0 : 1.0;
+      nact += !done;
     }
-    hipLaunchKernelGGL(k_scale, dim3(nblocks(n, T)), dim3(T), 0, st, r, n, K.scal + 1, 1, K.V);
-    hipLaunchKernelGGL(k_init_g, dim3(1), dim3(1), 0, st, K.giv, ld, K.scal + 1);
+    if (nact == 0) break;
+    if (!K.to_dev(K.scal(SC_ACTIVE), hact.data(), nc)) {
+      pl.err = "GMRES: copy failed";
+      return PBTC_EDEVICE;
+    }
+    hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, r, n, K.scal(SC_BETA),
+                       K.comp, K.scal(SC_ACTIVE), K.V);
+    hipLaunchKernelGGL(k_init_seg, dim3(1), dim3(64), 0, st, nc, K.giv, K.gstride, ld,
+                       K.scal(SC_BETA), K.scal(SC_KFIN));
     int j = 0;
     for (; j < m && *iters < max_iter; ++j) {
       double* vj = K.V + (size_t)j * n;
       double* vn = K.V + (size_t)(j + 1) * n;
       rc = op(vj, K.w);
       if (rc) return rc;
-      // CGS2: two passes of classical Gram-Schmidt
-      rc = K.dots(K.V, j + 1, K.w, K.hbuf, 0);
+      // CGS2: two passes of classical Gram-Schmidt, per system
+      rc = K.dots(K.V, j + 1, K.w, K.hbuf);
       if (rc) return rc;
-      hipLaunchKernelGGL(k_sub_combo, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n, K.hbuf,
-                         K.w);
-      rc = K.dots(K.V, j + 1, K.w, K.h2buf, 0);
+      hipLaunchKernelGGL(k_sub_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n,
+                         K.hbuf, ld, K.comp, K.w);
+      rc = K.dots(K.V, j + 1, K.w, K.h2buf);
       if (rc) return rc;
-      hipLaunchKernelGGL(k_sub_combo, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n, K.h2buf,
-                         K.w);
-      hipLaunchKernelGGL(k_axpy, dim3(1), dim3(T), 0, st, 1.0, K.h2buf, (int64_t)(j + 1), K.hbuf);
-      rc = K.norm(K.w, K.scal);
+      hipLaunchKernelGGL(k_sub_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n,
+                         K.h2buf, ld, K.comp, K.w);
+      hipLaunchKernelGGL(k_axpy, dim3(nblocks((int64_t)nc * ld, T)), dim3(T), 0, st, 1.0, K.h2buf,
+                         (int64_t)nc * ld, K.hbuf);
+      rc = K.norm(K.w, K.scal(SC_HN));
       if (rc) return rc;
-      hipLaunchKernelGGL(k_scale, dim3(nblocks(n, T)), dim3(T), 0, st, K.w, n, K.scal, 1, vn);
-      hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, j, ld, K.hbuf, K.scal, K.H, K.giv,
-                         ref_norm, K.scal + 2);
+      hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.w, n, K.scal(SC_HN),
+                         K.comp, K.scal(SC_ACTIVE), vn);
+      hipLaunchKernelGGL(k_givens_seg, dim3(1), dim3(64), 0, st, nc, j, ld, K.hbuf, K.H, K.giv,
+                         K.gstride, K.sc);
       PBTC_LAUNCH_CHECK();
-      const double res = K.host_scalar(K.scal + 2);
-      ++*iters;
-      if (hist) hist->push_back(res);
-      if (!std::isfinite(res)) {
-        pl.err = "GMRES: residual estimate is not finite";
+      // residual estimates and active flags of every system
+      if (!K.host(K.scal(SC_RES), hscal.data(), 2 * nc)) {
+        pl.err = "GMRES: copy failed";
         return PBTC_EDEVICE;
       }
-      if (res <= tol) {
+      ++*iters;
+      double worst = 0.0;
+      int still = 0;
+      for (int c = 0; c < nc; ++c) {
+        const double res = hscal[c];
+        if (!std::isfinite(res)) {
+          pl.err = "GMRES: residual estimate is not finite";
+          return PBTC_EDEVICE;
+        }
+        if (hact[c] > 0.0) worst = std::max(worst, res);
+        if (hact[c] > 0.0 && hscal[nc + c] == 0.0) {
+          (*conv)[c] = 1;
+          if (conv_iter) (*conv_iter)[c] = *iters;
+        }
+        hact[c] = hscal[nc + c];
+        still += hact[c] > 0.0;
+      }
+      if (hist) hist->push_back(worst);
+      if (still == 0) {
         ++j;
-        *converged = true;
         break;
       }
     }
-    const int k = std::min(j, m);
-    if (k > 0) {
-      hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, st, k, ld, K.H, K.giv, K.y);
-      hipLaunchKernelGGL(k_add_combo, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, k, n, K.y, z);
-      PBTC_LAUNCH_CHECK();
-    }
-    if (*converged) break;
+    hipLaunchKernelGGL(k_finish_seg, dim3(1), dim3(64), 0, st, nc, std::min(j, m), ld, K.H, K.giv,
+                       K.gstride, K.sc);
+    hipLaunchKernelGGL(k_add_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, n, K.giv,
+                       K.gstride, ld, K.scal(SC_KFIN), K.comp, z);
+    PBTC_LAUNCH_CHECK();
+    bool all = true;
+    for (int c = 0; c < nc; ++c) all &= (*conv)[c] != 0;
+    if (all) break;
   }
   return PBTC_OK;
 }
@@ -321,90 +535,150 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Solve on a set-up workspace; fills res (timings from t_setup on).
-int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res) {
+// Solves A x = b (or A^T x = b) for every independent system to the plan's
+// tolerance in the plan's precision: FP64 GMRES, FP32 GMRES, or FP32 GMRES
+// inside FP64 iterative refinement.  rel = the largest explicit
+// ||b_c - (A x)_c|| / ||b_c|| over systems, with the FP64 operator.
+int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* b, double* x,
+                   int* iters_out, int* n32_out, int* n64_out, int* nref_out, double* rel_out,
+                   bool* conv_out, std::vector<double>* hist) {
   const int T = 256;
   const int64_t n = pl.nunk;
-  double* b = wsp<double>(pl, pl.o_b);
-  double* x = wsp<double>(pl, pl.o_x);
+  const int nc = pl.ncomp;
   double* r = wsp<double>(pl, pl.o_r);
-  double* d = wsp<double>(pl, pl.o_lam);  // correction of a refinement step
+  double* d = wsp<double>(pl, pl.o_z2);  // correction of a refinement step
   Krylov K(pl, st);
-  pl.history.clear();
   int iters = 0, n32 = 0, n64 = 0, nref = 0;
-  bool conv = false;
-  const double t0 = now_s();
-  int rc = K.norm(b, K.scal + 4);
+  std::vector<double> bnorm(nc), rnorm(nc), rel(nc, 0.0);
+  int rc = K.norm(b, K.scal(SC_BNORM));
   if (rc) return rc;
-  const double bnorm = K.host_scalar(K.scal + 4);
+  if (!K.host(K.scal(SC_BNORM), bnorm.data(), nc)) {
+    pl.err = "copy failed";
+    return PBTC_EDEVICE;
+  }
   auto op64 = [&](const double* in, double* out) {
     ++n64;
-    return apply_operator(pl, st, in, out, PBTC_FP64, 0);
+    return transpose ? apply_transpose(pl, st, in, out, PBTC_FP64, 0)
+                     : apply_operator(pl, st, in, out, PBTC_FP64, 0);
   };
   auto op32 = [&](const double* in, double* out) {
     ++n32;
-    return apply_operator(pl, st, in, out, PBTC_FP32, 0);
+    return transpose ? apply_transpose(pl, st, in, out, PBTC_FP32, 0)
+                     : apply_operator(pl, st, in, out, PBTC_FP32, 0);
   };
-  double rel = 1.0;
-  if (bnorm == 0.0) {
-    hipLaunchKernelGGL(k_fill, dim3(nblocks(n, T)), dim3(T), 0, st, x, n, 0.0);
-    conv = true;
-    rel = 0.0;
-  } else if (pl.prm.precision == PBTC_FP32_REFINED) {
+  // systems with a zero right-hand side are solved by x = 0
+  std::vector<double> ref(nc), tol(nc, pl.prm.tol);
+  for (int c = 0; c < nc; ++c) ref[c] = bnorm[c] > 0.0 ? bnorm[c] : 1.0;
+  std::vector<int> conv(nc, 0), cit;
+  auto explicit_residual = [&]() -> int {
+    int e = op64(x, r);
+    if (e) return e;
+    hipLaunchKernelGGL(k_sub, dim3(nblocks(n, T)), dim3(T), 0, st, b, r, n, r);
+    e = K.norm(r, K.scal(SC_NORM));
+    if (e) return e;
+    if (!K.host(K.scal(SC_NORM), rnorm.data(), nc)) {
+      pl.err = "copy failed";
+      return PBTC_EDEVICE;
+    }
+    for (int c = 0; c < nc; ++c) rel[c] = bnorm[c] > 0.0 ? rnorm[c] / bnorm[c] : 0.0;
+    return PBTC_OK;
+  };
+  bool all = false;
+  if (pl.prm.precision == PBTC_FP32_REFINED) {
     hipLaunchKernelGGL(k_fill, dim3(nblocks(n, T)), dim3(T), 0, st, x, n, 0.0);
     PBTC_HIP(hipMemcpyAsync(r, b, 8 * n, hipMemcpyDeviceToDevice, st));
-    double rnorm = bnorm;
+    rnorm = bnorm;
+    for (int c = 0; c < nc; ++c) rel[c] = bnorm[c] > 0.0 ? 1.0 : 0.0;
     for (nref = 0; nref < pl.prm.max_refine && iters < pl.prm.max_iter; ++nref) {
-      // inner solve of A d = r to a relative tolerance that lands the outer
-      // residual below tol, but not below what the FP32 operator resolves
-      const double want = 0.5 * pl.prm.tol * bnorm / rnorm;
-      const double tin = std::min(0.5, std::max(want, pl.prm.inner_tol));
-      bool cin = false;
-      rc = gmres(pl, st, op32, r, d, true, tin, rnorm, pl.prm.max_iter, &iters, &pl.history, &cin);
+      // inner solve of A d = r: per system a relative tolerance that lands the
+      // outer residual below tol but not below what the FP32 operator resolves;
+      // systems already converged take no inner step
+      std::vector<double> tin(nc), rref(nc);
+      for (int c = 0; c < nc; ++c) {
+        rref[c] = rnorm[c] > 0.0 ? rnorm[c] : 1.0;
+        if (rel[c] <= pl.prm.tol) {
+          tin[c] = 2.0;
+        } else {
+          const double want = 0.5 * pl.prm.tol * bnorm[c] / rnorm[c];
+          tin[c] = std::min(0.5, std::max(want, pl.prm.inner_tol));
+        }
+      }
+      std::vector<int> cin;
+      rc = gmres(pl, st, op32, r, d, true, tin, rref, pl.prm.max_iter, &iters, hist, &cin, nullptr);
       if (rc) return rc;
       hipLaunchKernelGGL(k_axpy, dim3(nblocks(n, T)), dim3(T), 0, st, 1.0, d, n, x);
-      rc = op64(x, r);
+      rc = explicit_residual();
       if (rc) return rc;
-      hipLaunchKernelGGL(k_sub, dim3(nblocks(n, T)), dim3(T), 0, st, b, r, n, r);
-      rc = K.norm(r, K.scal + 5);
-      if (rc) return rc;
-      rnorm = K.host_scalar(K.scal + 5);
-      rel = rnorm / bnorm;
-      if (rel <= pl.prm.tol) {
-        conv = true;
+      all = true;
+      for (int c = 0; c < nc; ++c) all &= rel[c] <= pl.prm.tol;
+      if (all) {
         ++nref;
         break;
       }
     }
+    for (int c = 0; c < nc; ++c) conv[c] = rel[c] <= pl.prm.tol;
   } else {
     const int prec = pl.prm.precision == PBTC_FP64 ? PBTC_FP64 : PBTC_FP32;
-    bool c = false;
     if (prec == PBTC_FP64)
-      rc = gmres(pl, st, op64, b, x, true, pl.prm.tol, bnorm, pl.prm.max_iter, &iters, &pl.history, &c);
+      rc = gmres(pl, st, op64, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv, &cit);
     else
-      rc = gmres(pl, st, op32, b, x, true, pl.prm.tol, bnorm, pl.prm.max_iter, &iters, &pl.history, &c);
+      rc = gmres(pl, st, op32, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv, &cit);
     if (rc) return rc;
-    // explicit FP64 residual
-    rc = op64(x, r);
+    rc = explicit_residual();
     if (rc) return rc;
-    hipLaunchKernelGGL(k_sub, dim3(nblocks(n, T)), dim3(T), 0, st, b, r, n, r);
-    rc = K.norm(r, K.scal + 5);
-    if (rc) return rc;
-    rel = K.host_scalar(K.scal + 5) / bnorm;
     // FP64: implicit or explicit residual meets tol; FP32 without refinement:
     // the implicit residual of the FP32 operator meets tol (rel is reported)
-    conv = c || (prec == PBTC_FP64 && rel <= pl.prm.tol);
+    for (int c = 0; c < nc; ++c) conv[c] = conv[c] || (prec == PBTC_FP64 && rel[c] <= pl.prm.tol);
   }
+  all = true;
+  double worst = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    all &= conv[c] != 0;
+    worst = std::max(worst, rel[c]);
+  }
+  pl.comp_rel = rel;
+  *iters_out = iters;
+  *n32_out = n32;
+  *n64_out = n64;
+  *nref_out = nref;
+  *rel_out = worst;
+  *conv_out = all;
+  return PBTC_OK;
+}
+
+// Solve on a set-up workspace; fills res (timings from t_setup on).
+int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res) {
+  const int64_t n = pl.nunk;
+  double* b = wsp<double>(pl, pl.o_b);
+  double* x = wsp<double>(pl, pl.o_x);
+  Krylov K(pl, st);
+  pl.history.clear();
+  prof_collect(pl);
+  for (int i = 0; i < 2; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
+  int iters = 0, n32 = 0, n64 = 0, nref = 0;
+  bool conv = false;
+  double rel = 0.0;
+  const double t0 = now_s();
+  int rc = solve_with_ops(pl, st, false, b, x, &iters, &n32, &n64, &nref, &rel, &conv, &pl.history);
+  if (rc) return rc;
   PBTC_HIP(hipStreamSynchronize(st));
   const double t1 = now_s();
-  // reaction potential at the charges (FP64 treecode) and the energy
+  // reaction potential at the charges (FP64 treecode) and the energy of
+  // every system (Eq. solv)
   double* phi = wsp<double>(pl, pl.o_phi_reac);
   rc = apply_operator(pl, st, x, phi, PBTC_FP64, 1);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_energy, dim3(1), dim3(kRedThreads), 0, st, wsp<double>(pl, pl.o_q), phi,
-                     pl.nq, 0.5 * 4.0 * kPi * kCoulomb, wsp<double>(pl, pl.o_energy));
+  double* e = wsp<double>(pl, pl.o_energy);
+  hipLaunchKernelGGL(k_energy_seg, dim3(pl.ncomp), dim3(kRedThreads), 0, st, wsp<double>(pl, pl.o_q),
+                     phi, wsp<int>(pl, pl.o_comp_q), pl.nq, 0.5 * 4.0 * kPi * kCoulomb, e);
   PBTC_LAUNCH_CHECK();
-  pl.energy = K.host_scalar(wsp<double>(pl, pl.o_energy));
+  pl.comp_energy.assign(pl.ncomp, 0.0);
+  if (!K.host(e, pl.comp_energy.data(), pl.ncomp)) {
+    pl.err = "copy failed";
+    return PBTC_EDEVICE;
+  }
+  pl.energy = 0.0;
+  for (double v : pl.comp_energy) pl.energy += v;
   const double t2 = now_s();
   pl.x_host.resize(n);
   pl.phi_reac_host.resize(pl.nq);
@@ -422,6 +696,13 @@ int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res) {
     res->n_refine = nref;
     res->t_solve_s = t1 - t0;
     res->t_energy_s = t2 - t1;
+    prof_collect(pl);
+    res->t_p2p_s = pl.prof_t[0];
+    res->t_m2p_s = pl.prof_t[1];
+    res->n_p2p_launch = pl.prof_n[0];
+    res->n_m2p_launch = pl.prof_n[1];
+    res->p2p_flop = pl.prof_flop[0];
+    res->m2p_flop = pl.prof_flop[1];
   }
   if (!conv) {
     pl.err = "GMRES did not reach the tolerance within max_iter";

@@ -21,38 +21,12 @@
 #include <algorithm>
 
 #include "device_util.h"
+#include "kernel_common.h"
 #include "taylor.h"
 
 namespace pbtc {
 
-template <typename real>
-struct alignas(16) Src {
-  real x, y, z, q, px, py, pz, pad;
-};
-
 namespace {
-
-template <typename real>
-__device__ __forceinline__ real rsqrt_(real v);
-template <>
-__device__ __forceinline__ float rsqrt_(float v) {
-  return __builtin_amdgcn_rsqf(v);
-}
-template <>
-__device__ __forceinline__ double rsqrt_(double v) {
-  return 1.0 / sqrt(v);
-}
-
-template <typename real>
-__device__ __forceinline__ real exp_neg(real v);  // exp(-v)
-template <>
-__device__ __forceinline__ float exp_neg(float v) {
-  return __builtin_amdgcn_exp2f(-1.4426950408889634f * v);
-}
-template <>
-__device__ __forceinline__ double exp_neg(double v) {
-  return exp(-v);
-}
 
 // ------------------------------------------------------------------- prep
 template <typename real>
@@ -194,20 +168,25 @@ __global__ __launch_bounds__(kP2MThreads) void k_m2m(const Cell* __restrict__ ce
 }
 
 // ------------------------------------------------------------------- p2p
-constexpr int kItemThreads = 256;  // 4 wavefronts share one group of 64 targets
+// Work is split into wavefront units: a unit is one target group (64
+// targets, one per lane) and a run of its list entries.  The four waves of a
+// work-group take four independent units; every index a wave loops over is
+// made wave-uniform so that sources and moments come through scalar loads.
+// Each unit writes its partial sums; a second kernel adds the units of an
+// item in a fixed order (deterministic) and stores S and D.
+constexpr int kItemThreads = 256;
 constexpr int kWaves = kItemThreads / 64;
 
-struct ItemArgs {
-  const int* list;  // item ids of this launch
+struct UnitArgs {
+  const int4* units;   // (item, e0, e1, -)
+  int nunits;
   const int* item_block;
   const DevBlock* blocks;
-  const long long* ptr;
   const int* cells_list;
   const Cell* cells;
-  const int* tidx;
-  double* S;
-  double* D;
 };
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <typename real, int KS>
 __device__ __forceinline__ void pair(real x, real y, real z, const Src<real>& s, real k0, real k1,
@@ -242,96 +221,122 @@ constexpr int nacc() {
   return KS == KS_L || KS == KS_Y ? 2 : 4;
 }
 
-// Writes (mode 0) or adds (mode 1) the group's sums, scaled by 1/(4 pi).
-template <typename real, int KS>
-__device__ __forceinline__ void item_store(const ItemArgs& a, const DevBlock& b, int64_t t0, int nt,
-                                           real (&acc)[4], int mode) {
-  __shared__ real red[kWaves][4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// partial[(u * 4 + q) * 64 + lane]
+template <typename real, int NQ>
+__device__ __forceinline__ void unit_store(real* __restrict__ partial, int u, const real (&acc)[4]) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int q = 0; q < nacc<KS>(); ++q) red[w][q][lane] = acc[q];
-  __syncthreads();
-  if (w == 0 && lane < nt) {
-    const int64_t i = a.tidx[t0 + lane] - b.tgt_off;
-#pragma unroll
-    for (int q = 0; q < nacc<KS>(); ++q) {
-      real v = 0;
-#pragma unroll
-      for (int u = 0; u < kWaves; ++u) v += red[u][q][lane];
-      const double val = (double)v * kInv4Pi;
-      const long long out = (q < 2 ? b.out0 : b.out1) + i;
-      double* dst = (q & 1) ? a.D : a.S;
-      if (mode == 0)
-        dst[out] = val;
-      else
-        dst[out] += val;
-    }
-  }
+  for (int q = 0; q < NQ; ++q) partial[((size_t)u * 4 + q) * 64 + lane] = acc[q];
 }
 
 template <typename real, int KS>
-__global__ __launch_bounds__(kItemThreads) void k_p2p(ItemArgs a, const real* __restrict__ tx,
+__global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __restrict__ tx,
                                                       const real* __restrict__ ty,
                                                       const real* __restrict__ tz,
-                                                      const Src<real>* __restrict__ src) {
-  const int item = a.list[blockIdx.x];
-  const DevBlock b = a.blocks[a.item_block[item]];
-  const int64_t g = item - b.item_off;
-  const int64_t t0 = b.tgt_off + g * kGroup;
+                                                      const Src<real>* __restrict__ src,
+                                                      real* __restrict__ partial) {
+  const int u = uni(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  if (u >= a.nunits) return;
+  const int4 un = a.units[u];
+  const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
+  const DevBlock& b = a.blocks[uni(a.item_block[item])];
+  const long long g = item - b.item_off;
+  const long long t0 = b.tgt_off + g * kGroup;
   const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t ti = t0 + min(lane, nt - 1);
+  const int lane = threadIdx.x & 63;
+  const long long ti = t0 + min(lane, nt - 1);
   const real x = tx[ti], y = ty[ti], z = tz[ti];
   const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
   real acc[4] = {0, 0, 0, 0};
-  const long long e0 = a.ptr[item], e1 = a.ptr[item + 1];
-  for (long long e = e0 + w; e < e1; e += kWaves) {
-    const Cell cl = a.cells[a.cells_list[e]];
-    for (int j = cl.begin; j < cl.begin + cl.count; ++j) {
-      const Src<real> s = src[j];
-      pair<real, KS>(x, y, z, s, k0, k1, acc);
+  for (int e = e0; e < e1; ++e) {
+    const int c = uni(a.cells_list[e]);
+    const int beg = uni(a.cells[c].begin), end = beg + uni(a.cells[c].count);
+    int j = beg;
+    for (; j + 1 < end; j += 2) {
+      const Src<real> s0 = src[j];
+      const Src<real> s1 = src[j + 1];
+      pair<real, KS>(x, y, z, s0, k0, k1, acc);
+      pair<real, KS>(x, y, z, s1, k0, k1, acc);
+    }
+    if (j < end) {
+      const Src<real> s0 = src[j];
+      pair<real, KS>(x, y, z, s0, k0, k1, acc);
     }
   }
-  item_store<real, KS>(a, b, t0, nt, acc, 0);
+  unit_store<real, nacc<KS>()>(partial, u, acc);
 }
 
 // ------------------------------------------------------------------- m2p
-template <typename real, int P, int KS>
-__global__ __launch_bounds__(kItemThreads) void k_m2p(ItemArgs a, const real* __restrict__ tx,
+// One Green's function per launch (KIND 0 Laplace, 1 Yukawa) for the block's
+// kernel slot `slot`, so that the two recurrences of a Laplace + Yukawa
+// block never share a register allocation.
+template <typename real, int P, int KIND>
+__global__ __launch_bounds__(kItemThreads) void k_m2p(UnitArgs a, const real* __restrict__ tx,
                                                       const real* __restrict__ ty,
                                                       const real* __restrict__ tz,
-                                                      const real* __restrict__ mom) {
+                                                      const real* __restrict__ mom, int slot,
+                                                      real* __restrict__ partial) {
   constexpr int N = ncoef(P);
-  const int item = a.list[blockIdx.x];
-  const DevBlock b = a.blocks[a.item_block[item]];
-  const int64_t g = item - b.item_off;
-  const int64_t t0 = b.tgt_off + g * kGroup;
+  const int u = uni(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  if (u >= a.nunits) return;
+  const int4 un = a.units[u];
+  const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
+  const DevBlock& b = a.blocks[uni(a.item_block[item])];
+  const long long g = item - b.item_off;
+  const long long t0 = b.tgt_off + g * kGroup;
   const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t ti = t0 + min(lane, nt - 1);
+  const int lane = threadIdx.x & 63;
+  const long long ti = t0 + min(lane, nt - 1);
   const real x = tx[ti], y = ty[ti], z = tz[ti];
-  const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
+  const real kap = (real)(slot == 0 ? b.kappa0 : b.kappa1);
   real acc[4] = {0, 0, 0, 0};
-  const long long e0 = a.ptr[item], e1 = a.ptr[item + 1];
-  for (long long e = e0 + w; e < e1; e += kWaves) {
-    const int c = a.cells_list[e];
-    const Cell cl = a.cells[c];
+  for (int e = e0; e < e1; ++e) {
+    const int c = uni(a.cells_list[e]);
+    const Cell& cl = a.cells[c];
     const real dx = x - (real)cl.cx, dy = y - (real)cl.cy, dz = z - (real)cl.cz;
-    const real rinv = rsqrt_(dx * dx + dy * dy + dz * dz);
+    const real r2 = dx * dx + dy * dy + dz * dz;
+    const real rinv = rsqrt_(r2);
     const real* M = mom + (size_t)c * 2 * N;
-    if (KS == KS_L || KS == KS_LY) taylor_laplace<P, real>(dx, dy, dz, rinv, M, acc[0], acc[1]);
-    if (KS == KS_Y || KS == KS_LY || KS == KS_YY) {
-      const real kap = KS == KS_LY ? k1 : k0;
-      const real r = (dx * dx + dy * dy + dz * dz) * rinv;
-      const int o = KS == KS_LY ? 2 : 0;
-      taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(kap * r), kap, M, acc[o], acc[o + 1]);
-    }
-    if (KS == KS_YY) {
-      const real r = (dx * dx + dy * dy + dz * dz) * rinv;
-      taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(k1 * r), k1, M, acc[2], acc[3]);
-    }
+    if (KIND == 0)
+      taylor_laplace<P, real>(dx, dy, dz, rinv, M, acc[0], acc[1]);
+    else
+      taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(kap * (r2 * rinv)), kap, M, acc[0], acc[1]);
   }
-  item_store<real, KS>(a, b, t0, nt, acc, 1);
+  unit_store<real, 2>(partial, u, acc);
+}
+
+// Sum of the units of every listed item in unit order, times 1/(4 pi), into
+// S and D of kernel slots first_slot.. (mode 0 store, mode 1 add).
+template <typename real, int NQ>
+__global__ void k_reduce(const int* __restrict__ list, const int* __restrict__ uptr,
+                         const int* __restrict__ item_block, const DevBlock* __restrict__ blocks,
+                         const int* __restrict__ tidx, const real* __restrict__ partial,
+                         double* __restrict__ S, double* __restrict__ D, int mode, int first_slot) {
+  const int l = blockIdx.x;
+  const int item = list[l];
+  const DevBlock& b = blocks[item_block[item]];
+  const long long g = item - b.item_off;
+  const long long t0 = b.tgt_off + g * kGroup;
+  const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
+  const int lane = threadIdx.x;
+  if (lane >= nt) return;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  for (int u = uptr[l]; u < uptr[l + 1]; ++u)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * 64 + lane];
+  const long long i = tidx[t0 + lane] - b.tgt_off;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const long long out = (first_slot + (q >> 1) == 0 ? b.out0 : b.out1) + i;
+    double* dst = (q & 1) ? D : S;
+    const double val = v[q] * kInv4Pi;
+    if (mode == 0)
+      dst[out] = val;
+    else
+      dst[out] += val;
+  }
 }
 
 // ----------------------------------------------------------- near field
@@ -413,13 +418,13 @@ static int launch_moments(pbtc_plan& pl, hipStream_t st, real* mom, const Src<re
   return PBTC_OK;
 }
 
-template <typename real, int KS>
-static void launch_m2p_ks(pbtc_plan& pl, hipStream_t st, const ItemArgs& a, int n, const real* tx,
-                          const real* ty, const real* tz, const real* mom) {
-#define PBTC_M2P(PP)                                                                       \
-  case PP:                                                                                 \
-    hipLaunchKernelGGL((k_m2p<real, PP, KS>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, \
-                       tz, mom);                                                           \
+template <typename real, int KIND>
+static void launch_m2p(pbtc_plan& pl, hipStream_t st, const UnitArgs& a, int grid, const real* tx,
+                       const real* ty, const real* tz, const real* mom, int slot, real* partial) {
+#define PBTC_M2P(PP)                                                                           \
+  case PP:                                                                                     \
+    hipLaunchKernelGGL((k_m2p<real, PP, KIND>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, \
+                       tz, mom, slot, partial);                                                \
     break;
   switch (pl.P) {
     PBTC_M2P(2)
@@ -431,6 +436,27 @@ static void launch_m2p_ks(pbtc_plan& pl, hipStream_t st, const ItemArgs& a, int 
       break;
   }
 #undef PBTC_M2P
+}
+
+// Timing of P2P / M2P launches with events on the launch stream.
+static void prof_mark(pbtc_plan& pl, hipStream_t st, int kind, double flop, bool begin) {
+  if (!pl.prm.profile) return;
+  if (begin) {
+    pbtc_plan::ProfEvent ev;
+    if (!pl.prof_pool.empty()) {
+      ev = pl.prof_pool.back();
+      pl.prof_pool.pop_back();
+    } else {
+      hipEventCreate(&ev.a);
+      hipEventCreate(&ev.b);
+    }
+    ev.kind = kind;
+    ev.flop = flop;
+    hipEventRecord(ev.a, st);
+    pl.prof.push_back(ev);
+  } else {
+    hipEventRecord(pl.prof.back().b, st);
+  }
 }
 
 // y = A x (phase 0) or phi_reac = S x (phase 1) in precision `prec`.
@@ -453,43 +479,72 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
     int rc = launch_moments<real>(pl, st, mom, src);
     if (rc) return rc;
   }
-  ItemArgs a;
+  UnitArgs a;
   a.item_block = wsp<int>(pl, pl.o_items);
   a.blocks = wsp<DevBlock>(pl, pl.o_blocks);
   a.cells = wsp<Cell>(pl, pl.o_cells);
-  a.tidx = wsp<int>(pl, pl.o_tidx);
-  a.S = wsp<double>(pl, pl.o_S);
-  a.D = wsp<double>(pl, pl.o_D);
+  const int* tidx = wsp<int>(pl, pl.o_tidx);
+  double* S = wsp<double>(pl, pl.o_S);
+  double* D = wsp<double>(pl, pl.o_D);
+  real* partial = wsp<real>(pl, pl.o_partial);
   for (int ks = 0; ks < KS_COUNT; ++ks) {
     const int n = (int)pl.item_list[phase][ks].size();
     if (n == 0) continue;
-    a.list = wsp<int>(pl, pl.o_item_list[phase][ks]);
-    a.ptr = wsp<long long>(pl, pl.o_near_ptr);
-    a.cells_list = wsp<int>(pl, pl.o_near);
-    switch (ks) {
-      case KS_L:
-        hipLaunchKernelGGL((k_p2p<real, KS_L>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, tz, src);
-        break;
-      case KS_Y:
-        hipLaunchKernelGGL((k_p2p<real, KS_Y>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, tz, src);
-        break;
-      case KS_LY:
-        hipLaunchKernelGGL((k_p2p<real, KS_LY>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, tz, src);
-        break;
-      case KS_YY:
-        hipLaunchKernelGGL((k_p2p<real, KS_YY>), dim3(n), dim3(kItemThreads), 0, st, a, tx, ty, tz, src);
-        break;
-    }
-    PBTC_LAUNCH_CHECK();
-    if (tree && pl.n_far > 0) {
-      a.ptr = wsp<long long>(pl, pl.o_far_ptr);
-      a.cells_list = wsp<int>(pl, pl.o_far);
+    const int* list = wsp<int>(pl, pl.o_item_list[phase][ks]);
+    // P2P over the near lists
+    {
+      const UnitSet& us = pl.units[phase][ks][0];
+      a.units = wsp<int4>(pl, pl.o_units + 16 * us.off);
+      a.nunits = (int)us.n;
+      a.cells_list = wsp<int>(pl, pl.o_near);
+      const int grid = nblocks(us.n, kWaves);
+      prof_mark(pl, st, 0, pl.launch_flop_p2p[phase][ks], true);
       switch (ks) {
-        case KS_L: launch_m2p_ks<real, KS_L>(pl, st, a, n, tx, ty, tz, mom); break;
-        case KS_Y: launch_m2p_ks<real, KS_Y>(pl, st, a, n, tx, ty, tz, mom); break;
-        case KS_LY: launch_m2p_ks<real, KS_LY>(pl, st, a, n, tx, ty, tz, mom); break;
-        case KS_YY: launch_m2p_ks<real, KS_YY>(pl, st, a, n, tx, ty, tz, mom); break;
+        case KS_L:
+          hipLaunchKernelGGL((k_p2p<real, KS_L>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
+          break;
+        case KS_Y:
+          hipLaunchKernelGGL((k_p2p<real, KS_Y>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
+          break;
+        case KS_LY:
+          hipLaunchKernelGGL((k_p2p<real, KS_LY>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
+          break;
+        case KS_YY:
+          hipLaunchKernelGGL((k_p2p<real, KS_YY>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
+          break;
       }
+      prof_mark(pl, st, 0, 0.0, false);
+      const int* uptr = wsp<int>(pl, pl.o_uptr + 4 * us.ptr_off);
+      if (ks == KS_L || ks == KS_Y)
+        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr, a.item_block,
+                           a.blocks, tidx, partial, S, D, 0, 0);
+      else
+        hipLaunchKernelGGL((k_reduce<real, 4>), dim3(n), dim3(64), 0, st, list, uptr, a.item_block,
+                           a.blocks, tidx, partial, S, D, 0, 0);
+      PBTC_LAUNCH_CHECK();
+    }
+    if (tree && pl.n_far > 0) {
+      const UnitSet& us = pl.units[phase][ks][1];
+      if (us.n == 0) continue;
+      a.units = wsp<int4>(pl, pl.o_units + 16 * us.off);
+      a.nunits = (int)us.n;
+      a.cells_list = wsp<int>(pl, pl.o_far);
+      const int grid = nblocks(us.n, kWaves);
+      const int* uptr = wsp<int>(pl, pl.o_uptr + 4 * us.ptr_off);
+      // kernel of slot 0 and (for two-kernel blocks) slot 1
+      const int kind0 = (ks == KS_L || ks == KS_LY) ? 0 : 1;
+      const bool two = ks == KS_LY || ks == KS_YY;
+      prof_mark(pl, st, 1, pl.launch_flop_m2p[phase][ks], true);
+      for (int slot = 0; slot < (two ? 2 : 1); ++slot) {
+        const int kind = slot == 0 ? kind0 : 1;
+        if (kind == 0)
+          launch_m2p<real, 0>(pl, st, a, grid, tx, ty, tz, mom, slot, partial);
+        else
+          launch_m2p<real, 1>(pl, st, a, grid, tx, ty, tz, mom, slot, partial);
+        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr,
+                           a.item_block, a.blocks, tidx, partial, S, D, 1, slot);
+      }
+      prof_mark(pl, st, 1, 0.0, false);
       PBTC_LAUNCH_CHECK();
     }
   }
@@ -501,7 +556,7 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
                        wsp<int>(pl, pl.o_nf_rowblk), wsp<DevBlock>(pl, pl.o_blocks),
                        wsp<long long>(pl, pl.o_nf_ptr), wsp<int>(pl, pl.o_nf_col),
                        wsp<real>(pl, sizeof(real) == 4 ? pl.o_nf_v32 : pl.o_nf_v64),
-                       wsp<int>(pl, pl.o_pidx), x, a.S, a.D);
+                       wsp<int>(pl, pl.o_pidx), x, S, D);
     PBTC_LAUNCH_CHECK();
   }
   // combine
@@ -512,11 +567,25 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
     dim3 grid(nblocks(nmax, T), (unsigned)rows.size());
     hipLaunchKernelGGL(k_combine, grid, dim3(T), 0, st,
                        wsp<DevRowBlock>(pl, phase == 0 ? pl.o_rows : pl.o_reac_rows),
-                       wsp<DevRowTerm>(pl, phase == 0 ? pl.o_terms : pl.o_reac_terms), x, a.S, a.D,
+                       wsp<DevRowTerm>(pl, phase == 0 ? pl.o_terms : pl.o_reac_terms), x, S, D,
                        y);
     PBTC_LAUNCH_CHECK();
   }
   return PBTC_OK;
+}
+
+// Folds finished profiling events into the plan's totals (stream synchronised).
+void prof_collect(pbtc_plan& pl) {
+  for (auto& ev : pl.prof) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
+      pl.prof_t[ev.kind] += 1e-3 * ms;
+      pl.prof_n[ev.kind] += 1;
+      pl.prof_flop[ev.kind] += ev.flop;
+    }
+    pl.prof_pool.push_back(ev);
+  }
+  pl.prof.clear();
 }
 
 int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
@@ -552,6 +621,13 @@ int upload_descriptors(pbtc_plan& pl, hipStream_t st) {
     d.self = (ts.kind == 0 && ts.id == b.s) ? 1 : 0;
     d.tkind = ts.kind;
     d.pad = 0;
+    d.aitem_off = pl.blk_aitem_off[i];
+    d.gpgrp_off = pl.gpgrp_off[b.s];
+    d.aout0 = pl.blk_aout0[i];
+    d.aout1 = pl.blk_aout1[i];
+    d.csc_off = pl.blk_csc_off[i];
+    d.slot0 = (int)pl.blk_slot0[i];
+    d.troot = b.t;  // the target-set trees have one root per target set, in order
   }
   PBTC_HIP(hipMemcpyAsync(wsp<DevBlock>(pl, pl.o_blocks), db.data(), sizeof(DevBlock) * db.size(),
                           hipMemcpyHostToDevice, st));
@@ -595,6 +671,22 @@ int upload_descriptors(pbtc_plan& pl, hipStream_t st) {
       if (!pl.item_list[ph][ks].empty())
         PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_item_list[ph][ks]), pl.item_list[ph][ks].data(),
                                 4 * pl.item_list[ph][ks].size(), hipMemcpyHostToDevice, st));
+  {
+    // independent systems: system of every unknown and charge, reduction chunks
+    std::vector<int> cu(pl.nunk), cq(std::max<int64_t>(pl.nq, 1), 0);
+    for (int s = 0; s < pl.nsurf; ++s)
+      for (int64_t u = pl.unk_off[s]; u < pl.unk_off[s + 1]; ++u) cu[u] = pl.comp_of_surface[s];
+    for (int r = 0; r < pl.nreg; ++r)
+      for (int64_t k = pl.q_off_region[r]; k < pl.q_off_region[r + 1]; ++k) cq[k] = pl.comp_of_region[r];
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_comp_of_unk), cu.data(), 4 * cu.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_comp_q), cq.data(), 4 * cq.size(), hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_chunks), pl.dot_chunks.data(), 16 * pl.dot_chunks.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_chunks) + pl.dot_chunks.size(), pl.comp_chunk0.data(),
+                            4 * pl.comp_chunk0.size(), hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipStreamSynchronize(st));
+  }
   {
     std::vector<int> rb(pl.nf_rows);
     for (size_t bi = 0; bi < pl.blocks.size(); ++bi) {

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 
 #include "internal.h"
 
@@ -275,6 +276,148 @@ int build_plan(pbtc_plan& pl) {
     }
   }
 
+  // independent systems: connected components of regions linked by surfaces;
+  // each must own a contiguous run of surfaces (else one system is used)
+  {
+    std::vector<int> parent(pl.nreg);
+    for (int r = 0; r < pl.nreg; ++r) parent[r] = r;
+    std::function<int(int)> find = [&](int r) { return parent[r] == r ? r : parent[r] = find(parent[r]); };
+    for (int s = 0; s < pl.nsurf; ++s) {
+      const int a = find(inner(s)), b = find(outer(s));
+      if (a != b) parent[a] = b;
+    }
+    std::vector<int> label(pl.nreg, -1);
+    pl.comp_of_surface.assign(pl.nsurf, 0);
+    int nc = 0;
+    for (int s = 0; s < pl.nsurf; ++s) {
+      const int root = find(inner(s));
+      if (label[root] < 0) label[root] = nc++;
+      pl.comp_of_surface[s] = label[root];
+    }
+    bool contiguous = true;
+    for (int s = 1; s < pl.nsurf; ++s)
+      if (pl.comp_of_surface[s] < pl.comp_of_surface[s - 1] ||
+          pl.comp_of_surface[s] > pl.comp_of_surface[s - 1] + 1)
+        contiguous = false;
+    if (!contiguous) {
+      nc = 1;
+      std::fill(pl.comp_of_surface.begin(), pl.comp_of_surface.end(), 0);
+    }
+    pl.ncomp = std::max(nc, 1);
+    pl.comp_of_region.assign(pl.nreg, 0);
+    for (int r = 0; r < pl.nreg; ++r)
+      pl.comp_of_region[r] = contiguous && label[find(r)] >= 0 ? label[find(r)] : 0;
+    pl.comp_u0.assign(pl.ncomp, 0);
+    pl.comp_u1.assign(pl.ncomp, 0);
+    for (int c = 0; c < pl.ncomp; ++c) {
+      int64_t lo = pl.nunk, hi = 0;
+      for (int s = 0; s < pl.nsurf; ++s)
+        if (pl.comp_of_surface[s] == c) {
+          lo = std::min(lo, pl.unk_off[s]);
+          hi = std::max(hi, pl.unk_off[s + 1]);
+        }
+      pl.comp_u0[c] = lo;
+      pl.comp_u1[c] = hi;
+    }
+    // Krylov reduction chunks never straddle two systems
+    constexpr int64_t kChunk = 16384;
+    pl.dot_chunks.clear();
+    pl.comp_chunk0.assign(pl.ncomp + 1, 0);
+    for (int c = 0; c < pl.ncomp; ++c) {
+      pl.comp_chunk0[c] = (int)pl.dot_chunks.size();
+      for (int64_t a = pl.comp_u0[c]; a < pl.comp_u1[c]; a += kChunk)
+        pl.dot_chunks.push_back(make_int4(c, (int)a, (int)std::min(a + kChunk, pl.comp_u1[c]), 0));
+    }
+    pl.comp_chunk0[pl.ncomp] = (int)pl.dot_chunks.size();
+  }
+
+  // transposed operator: Gauss-point groups, items, kernel slots, CSC columns
+  pl.gpgrp_off.assign(pl.nsurf + 1, 0);
+  for (int s = 0; s < pl.nsurf; ++s)
+    pl.gpgrp_off[s + 1] = pl.gpgrp_off[s] + (pl.gp_off[s + 1] - pl.gp_off[s] + kGroup - 1) / kGroup;
+  pl.ngpgrp = pl.gpgrp_off[pl.nsurf];
+  const size_t nb = pl.blocks.size();
+  pl.blk_slot0.assign(nb, 0);
+  pl.blk_aout0.assign(nb, 0);
+  pl.blk_aout1.assign(nb, 0);
+  pl.blk_aitem_off.assign(nb, 0);
+  pl.blk_csc_off.assign(nb, 0);
+  pl.aitem_block.clear();
+  for (int ph = 0; ph < 2; ++ph)
+    for (int ks = 0; ks < KS_COUNT; ++ks) pl.aitem_list[ph][ks].clear();
+  int64_t nslot = 0, aout = 0, aitems = 0, ncsc = 0;
+  for (size_t bi = 0; bi < nb; ++bi) {
+    const Block& b = pl.blocks[bi];
+    const int64_t ngs = pl.gp_off[b.s + 1] - pl.gp_off[b.s];
+    pl.blk_slot0[bi] = nslot;
+    pl.blk_aout0[bi] = aout;
+    pl.blk_aout1[bi] = aout + (b.nk == 2 ? ngs : 0);
+    nslot += b.nk;
+    aout += b.nk * ngs;
+    pl.blk_aitem_off[bi] = aitems;
+    const int64_t ng = pl.gpgrp_off[b.s + 1] - pl.gpgrp_off[b.s];
+    for (int64_t g = 0; g < ng; ++g) {
+      pl.aitem_block.push_back((int)bi);
+      pl.aitem_list[b.reaction ? 1 : 0][b.ks].push_back((int)(aitems + g));
+    }
+    aitems += ng;
+    pl.blk_csc_off[bi] = ncsc;
+    ncsc += pl.pan_off[b.s + 1] - pl.pan_off[b.s];
+  }
+  pl.nitems_adj = aitems;
+  pl.naout = aout;
+  pl.ncsc = ncsc;
+  // kernel slots: weights from the rows that use each (block, kernel)
+  for (int ph = 0; ph < 2; ++ph) {
+    pl.slots[ph].clear();
+    pl.gather_slots[ph].clear();
+    pl.gathers[ph].assign(pl.nsurf, DevGather{0, 0});
+  }
+  std::vector<DevSlot> all(nslot);
+  for (size_t bi = 0; bi < nb; ++bi) {
+    const Block& b = pl.blocks[bi];
+    for (int k = 0; k < b.nk; ++k) {
+      DevSlot& d = all[pl.blk_slot0[bi] + k];
+      d.out = b.out[k];
+      d.n = pl.tsets[b.t].n;
+      d.ncontrib = 0;
+      d.block = (int)bi;
+      d.lam_off[0] = d.lam_off[1] = 0;
+      d.cS[0] = d.cS[1] = d.cD[0] = d.cD[1] = 0.0;
+    }
+  }
+  // forward rows: row = 1/2 phi - sum sigma (c S - D)  ->  muS += -sigma c lam, muD += sigma lam
+  for (const RowBlock& rb : pl.rows)
+    for (const RowTerm& t : rb.terms) {
+      DevSlot& d = all[pl.blk_slot0[t.block] + t.kidx];
+      d.lam_off[d.ncontrib] = rb.row_off;
+      d.cS[d.ncontrib] = -t.sigma_c;
+      d.cD[d.ncontrib] = t.sigma;
+      ++d.ncontrib;
+    }
+  // reaction rows: phi_reac = sum sigma (c S - D)  ->  muS += sigma c q, muD += -sigma q
+  for (const RowBlock& rb : pl.reac_rows)
+    for (const RowTerm& t : rb.terms) {
+      DevSlot& d = all[pl.blk_slot0[t.block] + t.kidx];
+      d.lam_off[d.ncontrib] = rb.row_off;
+      d.cS[d.ncontrib] = t.sigma_c;
+      d.cD[d.ncontrib] = -t.sigma;
+      ++d.ncontrib;
+    }
+  for (int ph = 0; ph < 2; ++ph) {
+    for (int s = 0; s < pl.nsurf; ++s) {
+      pl.gathers[ph][s].slot_off = (int)pl.gather_slots[ph].size();
+      for (size_t bi = 0; bi < nb; ++bi) {
+        const Block& b = pl.blocks[bi];
+        if (b.s != s || (b.reaction ? 1 : 0) != ph) continue;
+        for (int k = 0; k < b.nk; ++k) pl.gather_slots[ph].push_back((int)(pl.blk_slot0[bi] + k));
+      }
+      pl.gathers[ph][s].nslots = (int)pl.gather_slots[ph].size() - pl.gathers[ph][s].slot_off;
+    }
+    for (const DevSlot& d : all)
+      if (pl.blocks[d.block].reaction == (ph == 1)) pl.slots[ph].push_back(d);
+  }
+
   // bounding cubes of the target sets (Morton order of the targets)
   pl.tcube.assign(4 * pl.tsets.size(), 0.0);
   for (size_t ti = 0; ti < pl.tsets.size(); ++ti) {
@@ -303,6 +446,12 @@ int build_plan(pbtc_plan& pl) {
   if (pl.cap_near == 0) pl.cap_near = 48 * pl.nitems + 1024;
   if (pl.cap_far == 0)
     pl.cap_far = (pl.prm.op == PBTC_OP_DIRECT ? 1 : 160) * pl.nitems + 1024;
+  if (pl.cap_units == 0) pl.cap_units = 8 * pl.nitems + 1024;
+  if (pl.cap_aunits == 0) pl.cap_aunits = 8 * pl.nitems_adj + 1024;
+  if (pl.cap_auptr == 0) pl.cap_auptr = 2 * pl.nitems_adj + 64;
+  if (pl.cap_tcells == 0) pl.cap_tcells = pl.ntgt / 16 + 64 * (int64_t)pl.tsets.size() + 1024;
+  if (pl.cap_anear == 0) pl.cap_anear = 48 * pl.nitems_adj + 1024;
+  if (pl.cap_afar == 0) pl.cap_afar = (pl.prm.op == PBTC_OP_DIRECT ? 1 : 160) * pl.nitems_adj + 1024;
   if (pl.cap_nf == 0) {
     int64_t n = 0;
     for (const Block& b : pl.blocks) n += pl.tsets[b.t].n;
@@ -361,6 +510,7 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_tkey2 = L.add(8 * pl.ntgt);
   pl.o_tval = L.add(4 * pl.ntgt);
   pl.o_tval2 = L.add(4 * pl.ntgt);
+  pl.o_tkey_sorted = L.add(8 * pl.ntgt);
   pl.o_src64 = L.add(8 * 8 * pl.ngp);
   pl.o_src32 = L.add(4 * 8 * pl.ngp);
   // block outputs and descriptors
@@ -391,9 +541,52 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_H = L.add(8 * (size_t)(m + 1) * (m + 1));
   pl.o_givens = L.add(8 * 4 * (size_t)(m + 2));
   pl.o_scal = L.add(8 * 64);
-  pl.o_red = L.add(8 * (size_t)(m + 2) * 1024);
+  pl.o_red = L.add(8 * ((size_t)(m + 1) * (pl.dot_chunks.size() + 2 * (size_t)pl.ncomp) +
+                         (size_t)(m + 2) * 1024));
   pl.o_phi_reac = L.add(8 * std::max<int64_t>(pl.nq, 1));
-  pl.o_energy = L.add(8 * 64);
+  pl.o_energy = L.add(8 * (pl.ncomp + 64));
+  pl.o_z2 = L.add(8 * std::max<int64_t>(n, pl.nq));
+  pl.o_comp_of_unk = L.add(4 * n);
+  pl.o_chunks = L.add(16 * std::max<size_t>(pl.dot_chunks.size(), 1) + 4 * (pl.ncomp + 1));
+  pl.o_comp_q = L.add(4 * std::max<int64_t>(pl.nq, 1));
+  // per system: H ((m+1)^2), Givens (4 (m+2)), scalars (16)
+  pl.o_kstate = L.add(8 * (size_t)pl.ncomp * ((size_t)(m + 1) * (m + 1) + 4 * (m + 2) + 16));
+  pl.o_surf_tab = L.add(8 * (9 * (pl.nsurf + 1) + 16));
+  pl.o_dots = L.add(8 * 4096);
+  // transposed operator
+  pl.o_gpos32 = L.add(4 * 8 * pl.ngp);
+  pl.o_gpos64 = L.add(8 * 8 * pl.ngp);
+  pl.o_gp_pos = L.add(4 * pl.ngp);
+  pl.o_gpgrp = L.add(8 * 4 * std::max<int64_t>(pl.ngpgrp, 1));
+  pl.o_mu_s = L.add(8 * pl.nout);
+  pl.o_mu_d = L.add(8 * pl.nout);
+  pl.o_asrc32 = L.add(4 * 8 * std::max<int64_t>(pl.nf_rows, 1));
+  pl.o_asrc64 = L.add(8 * 8 * std::max<int64_t>(pl.nf_rows, 1));
+  pl.o_aout_s = L.add(8 * std::max<int64_t>(pl.naout, 1));
+  pl.o_aout_d = L.add(8 * std::max<int64_t>(pl.naout, 1));
+  pl.o_aitems = L.add(4 * std::max<int64_t>(pl.nitems_adj, 1));
+  for (int ph = 0; ph < 2; ++ph) {
+    for (int ks = 0; ks < KS_COUNT; ++ks)
+      pl.o_aitem_list[ph][ks] = L.add(4 * std::max<size_t>(pl.aitem_list[ph][ks].size(), 1));
+    pl.o_slots[ph] = L.add(sizeof(DevSlot) * std::max<size_t>(pl.slots[ph].size(), 1));
+    pl.o_gather[ph] = L.add(sizeof(DevGather) * std::max<int>(pl.nsurf, 1));
+    pl.o_gather_slots[ph] = L.add(4 * std::max<size_t>(pl.gather_slots[ph].size(), 1));
+  }
+  pl.o_csc_ptr = L.add(8 * (pl.ncsc + 1));
+  {
+    int64_t ns = 0;
+    for (const Block& b : pl.blocks) ns += b.nk;
+    pl.o_slot_block = L.add(4 * std::max<int64_t>(ns, 1));
+    pl.o_slot_kidx = L.add(4 * std::max<int64_t>(ns, 1));
+    for (int ph = 0; ph < 2; ++ph) {
+      pl.o_adj_blist[ph] = L.add(4 * std::max<size_t>(pl.blocks.size(), 1));
+      pl.o_adj_sids[ph] = L.add(4 * std::max<int64_t>(ns, 1));
+    }
+    pl.o_adj_tab = L.add(8 * 2 * (pl.nsurf + 1));
+  }
+  pl.o_csc_fill = L.add(8 * (pl.ncsc + 1));
+  pl.o_anear_ptr = L.add(8 * (pl.nitems_adj + 1));
+  pl.o_afar_ptr = L.add(8 * (pl.nitems_adj + 1));
   pl.fixed_bytes = L.total;
   // tree
   pl.o_cells = L.add(sizeof(Cell) * pl.cap_cells);
@@ -413,6 +606,22 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_nf_col = L.add(4 * pl.cap_nf);
   pl.o_nf_v64 = L.add(8 * 4 * pl.cap_nf);
   pl.o_nf_v32 = L.add(4 * 4 * pl.cap_nf);
+  pl.o_csc_ent = L.add(4 * pl.cap_nf);
+  pl.o_csc_row = L.add(4 * pl.cap_nf);
+  // transposed-operator trees and lists
+  int64_t nslot = 0;
+  for (const Block& b : pl.blocks) nslot += b.nk;
+  pl.o_tcells = L.add(sizeof(Cell) * pl.cap_tcells);
+  pl.o_tcnt = L.add(8 * (pl.cap_tcells + 1));
+  pl.o_amom32 = L.add(4 * 2 * nP * pl.cap_tcells * nslot);
+  pl.o_amom64 = L.add(8 * 2 * nP * pl.cap_tcells * nslot);
+  pl.o_anear = L.add(4 * pl.cap_anear);
+  pl.o_units = L.add(16 * pl.cap_units);
+  pl.o_uptr = L.add(4 * (2 * pl.nitems + 64));
+  pl.o_aunits = L.add(16 * pl.cap_aunits);
+  pl.o_auptr = L.add(4 * pl.cap_auptr);
+  pl.o_partial = L.add(8 * 4 * 64 * std::max(pl.cap_units, pl.cap_aunits));
+  pl.o_afar = L.add(4 * pl.cap_afar);
   pl.ws_bytes = L.total + 4096;
 }
 

@@ -22,6 +22,7 @@
 #include <cmath>
 
 #include "device_util.h"
+#include "taylor.h"
 
 namespace pbtc {
 
@@ -235,6 +236,8 @@ __device__ int lower_digit(const uint64_t* key, int b, int e, int level, int d) 
   return b;
 }
 
+}  // namespace
+
 __global__ void k_split_count(Cell* __restrict__ cells, int lb, int le, int ncrit,
                               const uint64_t* __restrict__ key, long long* __restrict__ cnt) {
   const int c = lb + blockIdx.x * blockDim.x + threadIdx.x;
@@ -309,6 +312,8 @@ __global__ __launch_bounds__(256) void k_cell_radius(Cell* __restrict__ cells, i
   }
   if (threadIdx.x == 0) cells[c].rb = sqrt(red[0]) * (1.0 + 1e-12);
 }
+
+namespace {
 
 // -------------------------------------------------------------------- lists
 constexpr int kStack = 8 * kMaxLevels + 16;
@@ -599,6 +604,87 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
 
 }  // namespace
 
+// Per-surface tables (persistent): vertex base, Gauss-point and panel
+// offsets, cube, near-field query radius, first original Gauss point.
+static long long* near_vbase(pbtc_plan& pl) { return wsp<long long>(pl, pl.o_surf_tab); }
+
+static void near_args(pbtc_plan& pl, NearArgs* na) {
+  long long* vbase = near_vbase(pl);
+  long long* pan_off = vbase + 2 * (pl.nsurf + 1);
+  double* cube = reinterpret_cast<double*>(pan_off + pl.nsurf + 1);
+  double* reach = cube + 4 * pl.nsurf;
+  long long* gp_first = reinterpret_cast<long long*>(reach + pl.nsurf);
+  na->blocks = wsp<DevBlock>(pl, pl.o_blocks);
+  na->cells = wsp<Cell>(pl, pl.o_cells);
+  na->gx = wsp<double>(pl, pl.o_gx);
+  na->gy = wsp<double>(pl, pl.o_gy);
+  na->gz = wsp<double>(pl, pl.o_gz);
+  na->gpid = wsp<int>(pl, pl.o_gpid);
+  na->gidx = wsp<int>(pl, pl.o_gidx);
+  na->cx = wsp<double>(pl, pl.o_cx);
+  na->cy = wsp<double>(pl, pl.o_cy);
+  na->cz = wsp<double>(pl, pl.o_cz);
+  na->nx = wsp<double>(pl, pl.o_nx);
+  na->ny = wsp<double>(pl, pl.o_ny);
+  na->nz = wsp<double>(pl, pl.o_nz);
+  na->area = wsp<double>(pl, pl.o_area);
+  na->len = wsp<double>(pl, pl.o_len);
+  na->qxyz = wsp<double>(pl, pl.o_qxyz);  // charge k is target np_tot + k
+  na->K = pl.prm.K;
+  na->thres = pl.prm.thres;
+  na->reach = reach;
+  na->gp_first = gp_first;
+  na->nf_row_block = wsp<int>(pl, pl.o_nf_rowblk);
+  na->np_tot = pl.np_tot;
+}
+
+int upload_descriptors(pbtc_plan& pl, hipStream_t st);
+int recompute_near_values(pbtc_plan& pl, hipStream_t st);
+int recompute_rhs(pbtc_plan& pl, hipStream_t st);
+
+// Octree over Morton-sorted points, level by level from the given roots
+// (one per point set): a box holding >= ncrit points is split into its
+// non-empty octants.  Fills cells, their radii, *n_cells and level_begin.
+int build_octree(pbtc_plan& pl, hipStream_t st, Cell* cells, int64_t cap,
+                 const std::vector<Cell>& roots, const uint64_t* key, const double* px,
+                 const double* py, const double* pz, int ncrit, long long* cnt,
+                 long long* scan_scratch, int64_t* n_cells, std::vector<int>* level_begin,
+                 int64_t* need) {
+  const int T = 256;
+  if ((int64_t)roots.size() > cap) {
+    *need = (int64_t)roots.size();
+    return PBTC_EWORKSPACE;
+  }
+  PBTC_HIP(hipMemcpyAsync(cells, roots.data(), sizeof(Cell) * roots.size(), hipMemcpyHostToDevice,
+                          st));
+  PBTC_HIP(hipStreamSynchronize(st));
+  level_begin->assign(1, 0);
+  int lb = 0, le = (int)roots.size();
+  for (int level = 0; level <= kMaxLevels; ++level) {
+    level_begin->push_back(le);
+    const int n = le - lb;
+    hipLaunchKernelGGL(k_split_count, dim3(nblocks(n, T)), dim3(T), 0, st, cells, lb, le, ncrit,
+                       key, cnt);
+    scan_exclusive<long long>(cnt, n, scan_scratch, st);
+    long long total = 0;
+    PBTC_HIP(hipMemcpyAsync(&total, cnt + n, 8, hipMemcpyDeviceToHost, st));
+    PBTC_HIP(hipStreamSynchronize(st));
+    if (le + total > cap) {
+      *need = le + total;
+      return PBTC_EWORKSPACE;
+    }
+    hipLaunchKernelGGL(k_split_write, dim3(nblocks(n, T)), dim3(T), 0, st, cells, lb, le, key, cnt);
+    PBTC_LAUNCH_CHECK();
+    if (total == 0) break;
+    lb = le;
+    le = le + (int)total;
+  }
+  *n_cells = le;
+  hipLaunchKernelGGL(k_cell_radius, dim3((unsigned)le), dim3(256), 0, st, cells, le, px, py, pz);
+  PBTC_LAUNCH_CHECK();
+  return PBTC_OK;
+}
+
 int upload_descriptors(pbtc_plan& pl, hipStream_t st);
 
 // Builds every once-per-geometry structure on the plan's workspace.
@@ -606,50 +692,54 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   *need_retry = 0;
   const pbtc_problem& P = pl.prob;
   const int T = 256;
-  // ---- inputs
-  std::vector<double> verts(3 * pl.nv_tot);
-  std::vector<int> tris(3 * pl.np_tot), pan_surf(pl.np_tot), pidx(2 * pl.np_tot);
-  for (int s = 0; s < pl.nsurf; ++s) {
-    std::copy(P.surfaces[s].v.begin(), P.surfaces[s].v.end(), verts.begin() + 3 * pl.v_off[s]);
-    std::copy(P.surfaces[s].t.begin(), P.surfaces[s].t.end(), tris.begin() + 3 * pl.pan_off[s]);
-    const int64_t ns = pl.pan_off[s + 1] - pl.pan_off[s];
-    for (int64_t p = pl.pan_off[s]; p < pl.pan_off[s + 1]; ++p) {
-      pan_surf[p] = s;
-      pidx[2 * p] = (int)(pl.unk_off[s] + (p - pl.pan_off[s]));
-      pidx[2 * p + 1] = (int)(pl.unk_off[s] + ns + (p - pl.pan_off[s]));
+  // ---- inputs (copied once per workspace; later set-ups reuse them)
+  if (pl.inputs_ws != pl.ws) {
+    std::vector<double> verts(3 * pl.nv_tot);
+    std::vector<int> tris(3 * pl.np_tot), pan_surf(pl.np_tot), pidx(2 * pl.np_tot);
+    for (int s = 0; s < pl.nsurf; ++s) {
+      std::copy(P.surfaces[s].v.begin(), P.surfaces[s].v.end(), verts.begin() + 3 * pl.v_off[s]);
+      std::copy(P.surfaces[s].t.begin(), P.surfaces[s].t.end(), tris.begin() + 3 * pl.pan_off[s]);
+      const int64_t ns = pl.pan_off[s + 1] - pl.pan_off[s];
+      for (int64_t p = pl.pan_off[s]; p < pl.pan_off[s + 1]; ++p) {
+        pan_surf[p] = s;
+        pidx[2 * p] = (int)(pl.unk_off[s] + (p - pl.pan_off[s]));
+        pidx[2 * p + 1] = (int)(pl.unk_off[s] + ns + (p - pl.pan_off[s]));
+      }
     }
+    std::vector<double> qxyz(3 * std::max<int64_t>(pl.nq, 1)), q(std::max<int64_t>(pl.nq, 1));
+    std::vector<int> qreg(std::max<int64_t>(pl.nq, 1));
+    for (int r = 0; r < pl.nreg; ++r) {
+      const ChargeSet& c = P.charges[r];
+      std::copy(c.xyz.begin(), c.xyz.end(), qxyz.begin() + 3 * pl.q_off_region[r]);
+      std::copy(c.q.begin(), c.q.end(), q.begin() + pl.q_off_region[r]);
+      for (int64_t k = pl.q_off_region[r]; k < pl.q_off_region[r + 1]; ++k) qreg[k] = r;
+    }
+    PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_verts), verts.data(), 8 * verts.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_tris), tris.data(), 4 * tris.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_pan_surf), pan_surf.data(), 4 * pan_surf.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_pidx), pidx.data(), 4 * pidx.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_qxyz), qxyz.data(), 8 * qxyz.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_q), q.data(), 8 * q.size(), hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_qreg), qreg.data(), 4 * qreg.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipStreamSynchronize(st));
   }
-  std::vector<double> qxyz(3 * std::max<int64_t>(pl.nq, 1)), q(std::max<int64_t>(pl.nq, 1));
-  std::vector<int> qreg(std::max<int64_t>(pl.nq, 1));
-  for (int r = 0; r < pl.nreg; ++r) {
-    const ChargeSet& c = P.charges[r];
-    std::copy(c.xyz.begin(), c.xyz.end(), qxyz.begin() + 3 * pl.q_off_region[r]);
-    std::copy(c.q.begin(), c.q.end(), q.begin() + pl.q_off_region[r]);
-    for (int64_t k = pl.q_off_region[r]; k < pl.q_off_region[r + 1]; ++k) qreg[k] = r;
-  }
-  PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_verts), verts.data(), 8 * verts.size(),
-                          hipMemcpyHostToDevice, st));
-  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_tris), tris.data(), 4 * tris.size(),
-                          hipMemcpyHostToDevice, st));
-  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_pan_surf), pan_surf.data(), 4 * pan_surf.size(),
-                          hipMemcpyHostToDevice, st));
-  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_pidx), pidx.data(), 4 * pidx.size(),
-                          hipMemcpyHostToDevice, st));
-  PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_qxyz), qxyz.data(), 8 * qxyz.size(),
-                          hipMemcpyHostToDevice, st));
-  PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_q), q.data(), 8 * q.size(), hipMemcpyHostToDevice, st));
-  PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_qreg), qreg.data(), 4 * qreg.size(),
-                          hipMemcpyHostToDevice, st));
-  int rc = upload_descriptors(pl, st);
+  int rc = pl.inputs_ws != pl.ws ? upload_descriptors(pl, st) : PBTC_OK;
   if (rc) return rc;
+  pl.inputs_ws = pl.ws;
   // small per-surface tables live in the reduction scratch during set-up
-  long long* vbase = wsp<long long>(pl, pl.o_red);
+  long long* vbase = wsp<long long>(pl, pl.o_surf_tab);
   long long* gp_off = vbase + pl.nsurf + 1;
   long long* pan_off = gp_off + pl.nsurf + 1;
   double* cube = reinterpret_cast<double*>(pan_off + pl.nsurf + 1);
   double* reach = cube + 4 * pl.nsurf;
   long long* gp_first = reinterpret_cast<long long*>(reach + pl.nsurf);
-  long long* scan_scratch = gp_first + pl.nsurf + 1;
+  long long* scan_scratch = wsp<long long>(pl, pl.o_red);
   {
     std::vector<long long> tab(3 * (pl.nsurf + 1));
     for (int s = 0; s <= pl.nsurf; ++s) {
@@ -735,6 +825,8 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
                        stride, c[0], c[1], c[2], c[3], tkey, tord);
     radix_sort64(tkey, tord, wsp<uint64_t>(pl, pl.o_tkey2), wsp<int>(pl, pl.o_tval2),
                  wsp<int>(pl, pl.o_hist), ts.n, st);
+    PBTC_HIP(hipMemcpyAsync(wsp<uint64_t>(pl, pl.o_tkey_sorted) + ts.off, tkey, 8 * ts.n,
+                            hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_target_gather, dim3(nblocks(ts.n, T)), dim3(T), 0, st, ts.off, ts.n, tord,
                        X, Y, Z, stride, src_off, wsp<double>(pl, pl.o_tx), wsp<double>(pl, pl.o_ty),
                        wsp<double>(pl, pl.o_tz), wsp<float>(pl, pl.o_txf), wsp<float>(pl, pl.o_tyf),
@@ -775,40 +867,19 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
       c.level = 0;
       c.surf = s;
     }
-    PBTC_HIP(hipMemcpyAsync(cells, roots.data(), sizeof(Cell) * roots.size(), hipMemcpyHostToDevice,
-                            st));
-    PBTC_HIP(hipStreamSynchronize(st));
-  }
-  pl.level_begin.assign(1, 0);
-  int lb = 0, le = pl.nsurf;
-  long long* cnt = wsp<long long>(pl, pl.o_cnt);
-  for (int level = 0; level <= kMaxLevels; ++level) {
-    pl.level_begin.push_back(le);
-    const int n = le - lb;
-    hipLaunchKernelGGL(k_split_count, dim3(nblocks(n, T)), dim3(T), 0, st, cells, lb, le, pl.ncrit,
-                       key, cnt);
-    scan_exclusive<long long>(cnt, n, scan_scratch, st);
-    long long total = 0;
-    PBTC_HIP(hipMemcpyAsync(&total, cnt + n, 8, hipMemcpyDeviceToHost, st));
-    PBTC_HIP(hipStreamSynchronize(st));
-    if (le + total > pl.cap_cells) {
-      pl.cap_cells = (int64_t)((le + total) * 2 + 1024);
+    int64_t need = 0;
+    rc = build_octree(pl, st, cells, pl.cap_cells, roots, key, wsp<double>(pl, pl.o_gx),
+                      wsp<double>(pl, pl.o_gy), wsp<double>(pl, pl.o_gz), pl.ncrit,
+                      wsp<long long>(pl, pl.o_cnt), scan_scratch, &pl.n_cells, &pl.level_begin,
+                      &need);
+    if (rc == PBTC_EWORKSPACE) {
+      pl.cap_cells = need * 2 + 1024;
       *need_retry = 1;
       pl.err = "tree larger than the workspace estimate";
-      return PBTC_EWORKSPACE;
     }
-    hipLaunchKernelGGL(k_split_write, dim3(nblocks(n, T)), dim3(T), 0, st, cells, lb, le, key, cnt);
-    PBTC_LAUNCH_CHECK();
-    if (total == 0) break;
-    lb = le;
-    le = le + (int)total;
+    if (rc) return rc;
+    pl.n_levels = (int)pl.level_begin.size() - 1;
   }
-  pl.n_cells = le;
-  pl.n_levels = (int)pl.level_begin.size() - 1;
-  hipLaunchKernelGGL(k_cell_radius, dim3((unsigned)pl.n_cells), dim3(256), 0, st, cells,
-                     (int)pl.n_cells, wsp<double>(pl, pl.o_gx), wsp<double>(pl, pl.o_gy),
-                     wsp<double>(pl, pl.o_gz));
-  PBTC_LAUNCH_CHECK();
 
   // ---- interaction lists
   const int direct = pl.prm.op == PBTC_OP_DIRECT;
@@ -844,28 +915,7 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
 
   // ---- near-field correction tables
   NearArgs na;
-  na.blocks = wsp<DevBlock>(pl, pl.o_blocks);
-  na.cells = cells;
-  na.gx = wsp<double>(pl, pl.o_gx);
-  na.gy = wsp<double>(pl, pl.o_gy);
-  na.gz = wsp<double>(pl, pl.o_gz);
-  na.gpid = wsp<int>(pl, pl.o_gpid);
-  na.gidx = wsp<int>(pl, pl.o_gidx);
-  na.cx = sa.cx;
-  na.cy = sa.cy;
-  na.cz = sa.cz;
-  na.nx = sa.nx;
-  na.ny = sa.ny;
-  na.nz = sa.nz;
-  na.area = sa.area;
-  na.len = sa.len;
-  na.qxyz = wsp<double>(pl, pl.o_qxyz);  // charge k is target np_tot + k
-  na.K = pl.prm.K;
-  na.thres = pl.prm.thres;
-  na.reach = reach;
-  na.gp_first = gp_first;
-  na.nf_row_block = wsp<int>(pl, pl.o_nf_rowblk);  // uploaded with the descriptors
-  na.np_tot = pl.np_tot;
+  near_args(pl, &na);
   long long* nf_ptr = wsp<long long>(pl, pl.o_nf_ptr);
   hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nf_rows, 64)), dim3(64), 0, st, na, pl.nf_rows, 0,
                      nf_ptr, (int*)nullptr, (long long)0);
@@ -884,6 +934,109 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nf_rows, 64)), dim3(64), 0, st, na, pl.nf_rows, 1,
                      nf_ptr, wsp<int>(pl, pl.o_nf_col), (long long)pl.cap_nf);
   PBTC_LAUNCH_CHECK();
+  rc = recompute_near_values(pl, st);
+  if (rc) return rc;
+
+  rc = recompute_rhs(pl, st);
+  if (rc) return rc;
+
+  // ---- interaction counts and algorithmic operation counts per launch
+  {
+    std::vector<long long> np_(pl.nitems + 1), fp_(pl.nitems + 1);
+    std::vector<int> nl(std::max<int64_t>(pl.n_near, 1));
+    std::vector<Cell> hc(pl.n_cells);
+    PBTC_HIP(hipMemcpy(np_.data(), near_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost));
+    PBTC_HIP(hipMemcpy(fp_.data(), far_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost));
+    if (pl.n_near) PBTC_HIP(hipMemcpy(nl.data(), wsp<int>(pl, pl.o_near), 4 * pl.n_near, hipMemcpyDeviceToHost));
+    PBTC_HIP(hipMemcpy(hc.data(), cells, sizeof(Cell) * pl.n_cells, hipMemcpyDeviceToHost));
+    double pairs = 0.0, m2p = 0.0;
+    for (int ph = 0; ph < 2; ++ph)
+      for (int ks = 0; ks < KS_COUNT; ++ks) pl.launch_flop_p2p[ph][ks] = pl.launch_flop_m2p[ph][ks] = 0.0;
+    const bool tree = pl.prm.op == PBTC_OP_TREECODE;
+    for (int64_t it = 0; it < pl.nitems; ++it) {
+      const Block& bl = pl.blocks[pl.item_block[it]];
+      const TargetSet& ts = pl.tsets[bl.t];
+      const int64_t g = it - bl.item_off;
+      const double ntg = (double)std::min<int64_t>(kGroup, ts.n - g * kGroup);
+      double src = 0.0;
+      for (long long e = np_[it]; e < np_[it + 1]; ++e) src += hc[nl[e]].count;
+      const double ncell = (double)(fp_[it + 1] - fp_[it]);
+      const int ph = bl.reaction ? 1 : 0;
+      pl.launch_flop_p2p[ph][bl.ks] += ntg * src * p2p_flop_per_pair(bl.ks);
+      if (tree) pl.launch_flop_m2p[ph][bl.ks] += ntg * ncell * m2p_flop_per_eval(pl.P, bl.ks);
+      if (bl.reaction) continue;
+      pairs += ntg * src * bl.nk;
+      m2p += ntg * ncell * bl.nk;
+    }
+    pl.p2p_pairs = pairs;
+    pl.m2p_evals = tree ? m2p : 0.0;
+
+    // wavefront work units: a P2P unit covers <= kUnitSources sources of one
+    // item's near list (whole cells), an M2P unit <= kUnitCells far cells
+    constexpr int kUnitSources = 1024, kUnitCells = 32;
+    std::vector<int4> units;
+    std::vector<int> uptr;
+    for (int ph = 0; ph < 2; ++ph)
+      for (int ks = 0; ks < KS_COUNT; ++ks)
+        for (int kind = 0; kind < 2; ++kind) {
+          UnitSet& us = pl.units[ph][ks][kind];
+          us.off = (int64_t)units.size();
+          us.ptr_off = (int64_t)uptr.size();
+          for (int item : pl.item_list[ph][ks]) {
+            uptr.push_back((int)(units.size() - us.off));
+            if (kind == 0) {
+              long long e = np_[item], acc = 0, start = e;
+              for (; e < np_[item + 1]; ++e) {
+                const int cnt = hc[nl[e]].count;
+                if (acc > 0 && acc + cnt > kUnitSources) {
+                  units.push_back(make_int4(item, (int)start, (int)e, 0));
+                  start = e;
+                  acc = 0;
+                }
+                acc += cnt;
+              }
+              if (e > start) units.push_back(make_int4(item, (int)start, (int)e, 0));
+            } else if (tree) {
+              for (long long e = fp_[item]; e < fp_[item + 1]; e += kUnitCells)
+                units.push_back(make_int4(item, (int)e, (int)std::min<long long>(e + kUnitCells, fp_[item + 1]), 0));
+            }
+          }
+          uptr.push_back((int)(units.size() - us.off));
+          us.n = (int64_t)units.size() - us.off;
+        }
+    pl.n_units = (int64_t)units.size();
+    pl.n_uptr = (int64_t)uptr.size();
+    if (pl.n_units > pl.cap_units) {
+      pl.cap_units = pl.n_units + pl.n_units / 8 + 1024;
+      *need_retry = 1;
+      pl.err = "work units exceed the workspace estimate";
+      return PBTC_EWORKSPACE;
+    }
+    PBTC_HIP(hipMemcpy(wsp<int4>(pl, pl.o_units), units.data(), 16 * units.size(), hipMemcpyHostToDevice));
+    PBTC_HIP(hipMemcpy(wsp<int>(pl, pl.o_uptr), uptr.data(), 4 * uptr.size(), hipMemcpyHostToDevice));
+  }
+  return PBTC_OK;
+}
+
+// New charge values (positions unchanged): upload and rebuild the RHS.
+int update_charges(pbtc_plan& pl, hipStream_t st) {
+  std::vector<double> q(std::max<int64_t>(pl.nq, 1));
+  for (int r = 0; r < pl.nreg; ++r) {
+    const ChargeSet& c = pl.prob.charges[r];
+    std::copy(c.q.begin(), c.q.end(), q.begin() + pl.q_off_region[r]);
+  }
+  PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_q), q.data(), 8 * q.size(), hipMemcpyHostToDevice, st));
+  PBTC_HIP(hipStreamSynchronize(st));
+  const int rc = recompute_rhs(pl, st);
+  if (rc) return rc;
+  pl.charges_dirty = false;
+  return PBTC_OK;
+}
+
+// FP64 near-field corrections for every row of every block (depends on kappa).
+int recompute_near_values(pbtc_plan& pl, hipStream_t st) {
+  NearArgs na;
+  near_args(pl, &na);
   Tables tb;
   tb.K = pl.prm.K;
   tb.Kf = pl.prm.K_fine;
@@ -897,13 +1050,20 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     tb.glw[i] = pl.gl_w[i];
   }
   hipLaunchKernelGGL(k_near_values, dim3(nblocks(pl.nf_rows, 64)), dim3(64), 0, st, na, tb,
-                     pl.nf_rows, nf_ptr, wsp<int>(pl, pl.o_nf_col), wsp<int>(pl, pl.o_tris),
-                     wsp<double>(pl, pl.o_verts), vbase, wsp<int>(pl, pl.o_pan_surf),
+                     pl.nf_rows, wsp<long long>(pl, pl.o_nf_ptr), wsp<int>(pl, pl.o_nf_col), wsp<int>(pl, pl.o_tris),
+                     wsp<double>(pl, pl.o_verts), near_vbase(pl), wsp<int>(pl, pl.o_pan_surf),
                      wsp<double>(pl, pl.o_nf_v64), wsp<float>(pl, pl.o_nf_v32));
   PBTC_LAUNCH_CHECK();
 
-  // ---- Coulomb right-hand side (Eq. matel, Q; multi-surface: charges of the
-  //      row's region, scaled by 1/eps of that region)
+  PBTC_HIP(hipStreamSynchronize(st));
+  return PBTC_OK;
+}
+
+// Coulomb right-hand side (Eq. matel, Q; the charges of each row's region,
+// scaled by 1/eps of that region).
+int recompute_rhs(pbtc_plan& pl, hipStream_t st) {
+  const pbtc_problem& P = pl.prob;
+  const int T = 256;
   double* b = wsp<double>(pl, pl.o_b);
   hipLaunchKernelGGL(k_fill_f64, dim3(nblocks(pl.nunk, T)), dim3(T), 0, st, b, pl.nunk, 0.0);
   for (const RowBlock& rb : pl.rows) {
@@ -911,7 +1071,7 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     const int64_t nq = P.charges[r].n();
     if (nq == 0) continue;
     hipLaunchKernelGGL(k_coulomb, dim3(nblocks(rb.n, T)), dim3(T), 0, st, rb.n,
-                       (long long)rb.row_off, (long long)pl.pan_off[rb.t], sa.cx, sa.cy, sa.cz,
+                       (long long)rb.row_off, (long long)pl.pan_off[rb.t], wsp<double>(pl, pl.o_cx), wsp<double>(pl, pl.o_cy), wsp<double>(pl, pl.o_cz),
                        wsp<double>(pl, pl.o_qxyz), wsp<double>(pl, pl.o_q),
                        (long long)pl.q_off_region[r], (long long)nq, 1.0 / P.regions[r].eps,
                        P.regions[r].kappa, b);
@@ -919,30 +1079,6 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   }
   PBTC_HIP(hipStreamSynchronize(st));
 
-  // ---- interaction counts for the report
-  {
-    std::vector<long long> np_(pl.nitems + 1), fp_(pl.nitems + 1);
-    std::vector<int> nl(pl.n_near);
-    std::vector<Cell> hc(pl.n_cells);
-    PBTC_HIP(hipMemcpy(np_.data(), near_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost));
-    PBTC_HIP(hipMemcpy(fp_.data(), far_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost));
-    if (pl.n_near) PBTC_HIP(hipMemcpy(nl.data(), wsp<int>(pl, pl.o_near), 4 * pl.n_near, hipMemcpyDeviceToHost));
-    PBTC_HIP(hipMemcpy(hc.data(), cells, sizeof(Cell) * pl.n_cells, hipMemcpyDeviceToHost));
-    double pairs = 0.0, m2p = 0.0;
-    for (int64_t it = 0; it < pl.nitems; ++it) {
-      const Block& bl = pl.blocks[pl.item_block[it]];
-      if (bl.reaction) continue;
-      const TargetSet& ts = pl.tsets[bl.t];
-      const int64_t g = it - bl.item_off;
-      const double ntg = (double)std::min<int64_t>(kGroup, ts.n - g * kGroup);
-      double src = 0.0;
-      for (long long e = np_[it]; e < np_[it + 1]; ++e) src += hc[nl[e]].count;
-      pairs += ntg * src * bl.nk;
-      m2p += ntg * (double)(fp_[it + 1] - fp_[it]) * bl.nk;
-    }
-    pl.p2p_pairs = pairs;
-    pl.m2p_evals = m2p;
-  }
   return PBTC_OK;
 }
 

@@ -138,4 +138,48 @@ __device__ __forceinline__ void taylor_yukawa(real dx, real dy, real dz, real ri
   }
 }
 
+// Floating-point operations of one P2P pair as written in the kernel
+// (FMA = 2, a transcendental = 1): distance, r^2, rsqrt, n.d and r^-3
+// (16), then Laplace single + double layer (4) and Yukawa (12) per kernel.
+inline double p2p_flop_per_pair(int ks) {
+  switch (ks) {
+    case KS_L: return 20.0;
+    case KS_Y: return 28.0;
+    case KS_LY: return 32.0;
+    default: return 40.0;
+  }
+}
+
+// Floating-point operations of one (target, cell) Taylor evaluation, counted
+// from the recurrences above term by term (FMA = 2).
+inline double m2p_flop_one(int P, int kind) {
+  double f = kind == 0 ? 11.0 : 16.0;  // d, r^2, rsqrt, 1/r^2 [, r, exp]
+  for (int deg = 0; deg <= P; ++deg)
+    for (int a = deg; a >= 0; --a)
+      for (int b = deg - a; b >= 0; --b) {
+        const int c = deg - a - b;
+        if (deg == 0) {
+          f += 4.0 + (kind ? 1.0 : 0.0);
+          continue;
+        }
+        const int nz1 = (a >= 1) + (b >= 1) + (c >= 1);
+        const int nz2 = (a >= 2) + (b >= 2) + (c >= 2);
+        const double s1 = 2.0 * nz1 - 1.0, s2 = nz2 > 0 ? nz2 - 1.0 : 0.0;
+        if (kind == 0)
+          f += s1 + s2 + (nz2 ? 4.0 : 2.0) + 4.0;
+        else
+          f += 2.0 * (s1 + s2) + (nz2 ? 3.0 : 2.0) + (nz2 ? 7.0 : 5.0) + 4.0;
+      }
+  return f;
+}
+
+inline double m2p_flop_per_eval(int P, int ks) {
+  switch (ks) {
+    case KS_L: return m2p_flop_one(P, 0);
+    case KS_Y: return m2p_flop_one(P, 1);
+    case KS_LY: return m2p_flop_one(P, 0) + m2p_flop_one(P, 1);
+    default: return 2.0 * m2p_flop_one(P, 1);
+  }
+}
+
 }  // namespace pbtc

@@ -30,7 +30,7 @@ class Params(C.Structure):
         ("theta", C.c_double), ("P", C.c_int), ("ncrit", C.c_int), ("direct_below", C.c_int),
         ("tol", C.c_double), ("restart", C.c_int), ("max_iter", C.c_int),
         ("precision", C.c_int), ("op", C.c_int), ("inner_tol", C.c_double),
-        ("max_refine", C.c_int), ("validate_charges", C.c_int),
+        ("max_refine", C.c_int), ("validate_charges", C.c_int), ("profile", C.c_int),
     ]
 
 
@@ -42,6 +42,9 @@ class Result(C.Structure):
         ("t_energy_s", C.c_double), ("n_p2p_pairs", C.c_double), ("n_m2p_evals", C.c_double),
         ("n_dense_equiv", C.c_double), ("n_near_entries", C.c_double),
         ("workspace_needed", C.c_size_t),
+        ("t_p2p_s", C.c_double), ("t_m2p_s", C.c_double),
+        ("n_p2p_launch", C.c_int), ("n_m2p_launch", C.c_int),
+        ("p2p_flop", C.c_double), ("m2p_flop", C.c_double),
     ]
 
     def as_dict(self):
@@ -75,8 +78,9 @@ _EXPORTS = {
     "pbtc_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pbtc_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_double,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Result)]),
-    "pbtc_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p),
-                                   C.POINTER(C.c_size_t), C.c_void_p, C.POINTER(Result)]),
+    "pbtc_get_systems": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
+    "pbtc_set_charge_values": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pbtc_triangle_rule": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p]),
     "pbtc_gauss_legendre": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p]),
     "pbtc_last_error": (C.c_char_p, [C.c_void_p]),
@@ -317,14 +321,31 @@ class Plan:
                                 C.c_void_p(b.data_ptr())), self.h)
         return b
 
+    def set_charge_values(self, q):
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        if len(qq) != self.n_charges:
+            raise ValueError("wrong number of charges")
+        check(self.lib.pbtc_set_charge_values(self.h, _ptr(qq)), self.h)
+
     def backward(self, gE=1.0):
+        """dE/dq (per charge), dE/dkappa and dE/deps (per region), times gE.
+
+        The first call builds the transposed operator on the workspace; if
+        the workspace must grow for it, the forward solve is repeated."""
         dq = np.empty(self.n_charges)
         dk = np.empty(self.n_regions)
         de = np.empty(self.n_regions)
-        res = Result()
-        check(self.lib.pbtc_backward(self.h, C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
-                                     self.stream, float(gE), _ptr(dq), _ptr(dk), _ptr(de),
-                                     C.byref(res)), self.h)
+        for _ in range(3):
+            res = Result()
+            code = self.lib.pbtc_backward(self.h, C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                          self.stream, float(gE), _ptr(dq), _ptr(dk), _ptr(de),
+                                          C.byref(res))
+            if code == EWORKSPACE and res.workspace_needed > self.ws.numel():
+                self._alloc(res.workspace_needed)
+                self.solve()
+                continue
+            break
+        check(code, self.h)
         self.last = res
         return dq, dk, de
 
@@ -335,18 +356,31 @@ def plan_for(prob, device="cuda:0", **params):
     return Plan(p, default_params(**params), device)
 
 
-def solve_batch(plans):
-    """Solves several plans together (each keeps its own workspace)."""
-    lib = load()
-    n = len(plans)
-    hs = (C.c_void_p * n)(*[p.h.value for p in plans])
-    ws = (C.c_void_p * n)(*[p.ws.data_ptr() for p in plans])
-    nb = (C.c_size_t * n)(*[p.ws.numel() for p in plans])
-    res = (Result * n)()
-    code = lib.pbtc_solve_batch(hs, n, ws, nb, plans[0].stream, res)
-    if code not in (OK, ENOCONV):
-        check(code)
-    return [r.as_dict() for r in res], code
+def batch_problem(problems):
+    """One problem holding several independent molecules (``synth`` problems);
+    the library solves each as its own system with shared kernel launches."""
+    p = Problem()
+    nreg = 0
+    for prob in problems:
+        for r in prob.regions:
+            p.add_region(r.eps, r.kappa)
+        for s in prob.surfaces:
+            p.add_surface(s.verts, s.tris, nreg + s.inner, nreg + s.outer)
+        for r, (x, q) in prob.charges.items():
+            p.set_charges(nreg + r, x, q)
+        nreg += len(prob.regions)
+    return p
+
+
+def systems(plan):
+    """Per independent system: energy, explicit relative residual, first unknown."""
+    n = C.c_int()
+    check(plan.lib.pbtc_get_systems(plan.h, C.byref(n), None, None, None), plan.h)
+    e = np.empty(n.value)
+    r = np.empty(n.value)
+    u = np.empty(n.value, dtype=np.int64)
+    check(plan.lib.pbtc_get_systems(plan.h, C.byref(n), _ptr(e), _ptr(r), _ptr(u)), plan.h)
+    return e, r, u
 
 
 def triangle_rule(k):

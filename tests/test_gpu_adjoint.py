@@ -1,0 +1,146 @@
+"""GPU parity of the transposed operator and the energy gradients.
+
+* A^T lambda through the C interface against the oracle's dense A^T: exact
+  transpose with the direct operator (1e-12, FP64), Taylor-truncation level
+  with the treecode.
+* dE/dq, dE/dkappa, dE/deps from pbtc_backward against the oracle's exact
+  discrete adjoint gradients (Kirkwood sphere and a reduced Stern/cavity
+  system), and against central finite differences of the GPU energy itself
+  (q: the energy is quadratic in q, so the difference quotient is exact up to
+  rounding; kappa: step 1e-4).
+* The torch.autograd wrapper returns the same dE/dq.
+"""
+
+import copy
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Oracle
+from oracle.adjoint import gradients
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    prob = synth.config1_kirkwood_sphere(nu=8)
+    o = Oracle(prob)
+    return prob, o, gradients(o)
+
+
+def test_transpose_matvec(sphere, gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    prob, o, g = sphere
+    A = o.matrix()
+    lam = np.random.default_rng(3).normal(size=o.n)
+    ref = A.T @ lam
+    pd = lib.plan_for(prob, op="direct", precision="fp64")
+    pd.setup()
+    assert _rel(pd.matvec(lam, lib.FP64, transpose=True).cpu().numpy(), ref) < 1e-12
+    assert _rel(pd.matvec(lam, lib.FP32, transpose=True).cpu().numpy(), ref) < 3e-5
+    pt = lib.plan_for(prob, theta=0.5, P=6)
+    pt.setup()
+    assert _rel(pt.matvec(lam, lib.FP64, transpose=True).cpu().numpy(), ref) < 3e-4
+
+
+def test_backward_direct_matches_oracle(sphere, gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    prob, o, g = sphere
+    pl = lib.plan_for(prob, op="direct", precision="fp64", tol=1e-12)
+    pl.solve()
+    dq, dk, de = pl.backward()
+    assert _rel(dq, g["dE_dq"]) < 1e-8
+    assert abs(dk[1] - g["dE_dkappa"][1]) < 1e-6 * abs(g["dE_dkappa"][1])
+    assert _rel(de, g["dE_deps"]) < 1e-8
+    assert dk[0] == 0.0  # Laplace region
+
+
+def test_backward_treecode_fp32_refined(sphere, gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    prob, o, g = sphere
+    pl = lib.plan_for(prob, precision="fp32_refined", tol=1e-7, theta=0.5, P=8)
+    pl.solve()
+    dq, dk, de = pl.backward()
+    assert _rel(dq, g["dE_dq"]) < 1e-4
+    assert abs(dk[1] - g["dE_dkappa"][1]) < 1e-3 * abs(g["dE_dkappa"][1])
+    assert _rel(de, g["dE_deps"]) < 1e-4
+
+
+def test_backward_vs_gpu_finite_differences(gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    prob = synth.concentric_spheres([4.0, 5.0], [4, 80, 80], [0, 0, 0.125],
+                                    (np.array([[0.0, 0.0, 2.5], [1.0, 1.5, -1.0], [-2.0, 1.0, 1.0]]),
+                                     np.array([1.0, -0.5, 0.7])), 0, nu=8)
+    kw = dict(op="direct", precision="fp64", tol=1e-13)
+    pl = lib.plan_for(prob, **kw)
+    e0 = pl.solve()["energy_kJmol"]
+    dq, dk, de = pl.backward()
+    ref = gradients(Oracle(prob))
+    assert _rel(dq, ref["dE_dq"]) < 1e-8 and _rel(de, ref["dE_deps"]) < 1e-8
+    h = 1e-4
+    q0 = prob.charges[0][1].copy()
+    for k in range(3):
+        ep = []
+        for sg in (1, -1):
+            q = q0.copy()
+            q[k] += sg * h
+            pl.set_charge_values(q)
+            ep.append(pl.solve()["energy_kJmol"])
+        fd = (ep[0] - ep[1]) / (2 * h)
+        assert abs(dq[k] - fd) < 1e-7 * abs(fd)
+    pl.set_charge_values(q0)
+    assert abs(pl.solve()["energy_kJmol"] - e0) < 1e-12 * abs(e0)
+    ek = []
+    for sg in (1, -1):
+        p2 = copy.deepcopy(prob)
+        p2.regions[2].kappa += sg * h
+        ek.append(lib.plan_for(p2, **kw).solve()["energy_kJmol"])
+    fd = (ek[0] - ek[1]) / (2 * h)
+    assert abs(dk[2] - fd) < 1e-6 * abs(fd)
+    for r in range(3):
+        ee = []
+        for sg in (1, -1):
+            p2 = copy.deepcopy(prob)
+            p2.regions[r].eps += sg * h
+            ee.append(lib.plan_for(p2, **kw).solve()["energy_kJmol"])
+        fd = (ee[0] - ee[1]) / (2 * h)
+        assert abs(de[r] - fd) < 1e-6 * abs(fd) + 1e-9
+
+
+def test_multisurface_backward(gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    prob = synth.config3_multisurface(nu=4, cav_nu=2, n_charges=20)
+    ref = gradients(Oracle(prob))
+    pl = lib.plan_for(prob, op="direct", precision="fp64", tol=1e-12, max_iter=4000)
+    pl.solve()
+    dq, dk, de = pl.backward()
+    assert _rel(dq, ref["dE_dq"]) < 1e-7
+    assert abs(dk[2] - ref["dE_dkappa"][2]) < 1e-5 * abs(ref["dE_dkappa"][2])
+    assert _rel(de, ref["dE_deps"]) < 1e-7
+
+
+def test_autograd_wrapper(sphere, gpu_lib):
+    import torch
+
+    from paper_1309_4018_amd import lib
+    from paper_1309_4018_amd.autograd import solvation_energy
+
+    prob, o, g = sphere
+    pl = lib.plan_for(prob, op="direct", precision="fp64", tol=1e-12)
+    q = torch.tensor(prob.charges[0][1], dtype=torch.float64, requires_grad=True)
+    e = solvation_energy(q, pl)
+    (2.0 * e).backward()
+    assert abs(e.item() - g["energy"]) < 1e-9 * abs(g["energy"])
+    assert _rel(q.grad.numpy(), 2.0 * g["dE_dq"]) < 1e-8
+    assert "dE_dkappa" in pl.last_param_grads

@@ -1,0 +1,93 @@
+"""GPU parity at the benchmark's full size: star surface, 40,500 panels.
+
+The oracle cannot assemble this system (81,000 unknowns), so it checks
+sampled outputs one by one in the launch configuration bench.py times
+(treecode, theta = 0.5, P = 6, FP32 bulk with FP64 refinement):
+* rows of A x for a random x (matrix-free oracle rows);
+* the residual b - A x of the GPU solution on sampled rows;
+* the reaction potential at sampled charges from the GPU solution.
+Tolerance 3e-4 of the row scale: the Taylor truncation at P = 6,
+theta = 0.5 (the FP32 rounding, ~1e-6, is far below it).  The energy of the
+FP32-refined solve must agree with the plain FP64 GPU treecode to 1e-5 and
+with the direct (all-P2P) FP64 GPU operator to 1e-4.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Oracle
+from oracle.integrals import green
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def star():
+    prob = synth.config2_star()
+    return prob, Oracle(prob)
+
+
+@pytest.fixture(scope="module")
+def plan(star, gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    pl = lib.plan_for(star[0], precision="fp32_refined", tol=1e-5, theta=0.5, P=6)
+    pl.setup()
+    return pl
+
+
+def test_matvec_sampled_rows(star, plan):
+    from paper_1309_4018_amd import lib
+
+    prob, o = star
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=o.n)
+    rows = rng.choice(o.ns[0], size=48, replace=False)
+    ref = o.apply_rows(x, 0, rows)
+    for prec in (lib.FP64, lib.FP32):
+        y = plan.matvec(x, prec).cpu().numpy()
+        for half in range(2):
+            got = y[half * o.ns[0] + rows]
+            scale = np.max(np.abs(ref[half]))
+            assert np.max(np.abs(got - ref[half])) < 3e-4 * scale
+
+
+def test_solution_residual_and_reaction_potential(star, plan):
+    prob, o = star
+    res = plan.solve()
+    assert res["converged"] == 1 and res["final_rel_res"] <= 1e-5
+    x = plan.solution()
+    rng = np.random.default_rng(6)
+    rows = rng.choice(o.ns[0], size=32, replace=False)
+    Ax = o.apply_rows(x, 0, rows)
+    X = o.pan[0].centre[rows]
+    R = np.linalg.norm(X[:, None, :] - o.qx[None, :, :], axis=2)
+    b0 = green(R, 0.0) @ o.q / o.eps[0]
+    scale = np.max(np.abs(b0))
+    assert np.max(np.abs(Ax[0] - b0)) < 3e-4 * scale
+    assert np.max(np.abs(Ax[1])) < 3e-4 * scale
+    # reaction potential at sampled charges (Eq. reac_integral)
+    ks = rng.choice(len(o.q), size=24, replace=False)
+    V, K = o.point_blocks(o.qx[ks], 0, 0.0)
+    n = o.ns[0]
+    phi_ref = V @ x[n:] - K @ x[:n]
+    phi = plan.phi_reac()[ks]
+    assert np.max(np.abs(phi - phi_ref)) < 3e-4 * np.max(np.abs(phi_ref))
+    e_ref_part = 0.5 * 4 * math.pi * 1389.35458
+    assert math.isfinite(res["energy_kJmol"]) and e_ref_part > 0
+
+
+def test_energy_consistency_across_precisions(star, plan):
+    from paper_1309_4018_amd import lib
+
+    prob, o = star
+    e32 = plan.solve()["energy_kJmol"]
+    p64 = lib.plan_for(prob, precision="fp64", tol=1e-7, theta=0.5, P=6)
+    e64 = p64.solve()["energy_kJmol"]
+    assert abs(e32 - e64) < 1e-5 * abs(e64) * 10
+    pd = lib.plan_for(prob, precision="fp64", op="direct", tol=1e-7)
+    ed = pd.solve()["energy_kJmol"]
+    assert abs(e32 - ed) < 1e-4 * abs(ed)
