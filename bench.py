@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mb", type=float, default=0.0,
+                    help="also run one elementwise copy of this size (HBM counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU: the multi-GPU path (targets sharded across GPUs, "
@@ -97,6 +99,13 @@ def main():
         print("no GPU visible", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    if a.copy_probe_mb > 0:
+        n = int(a.copy_probe_mb * 2 ** 20 / 4)
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # reads n*4 bytes, writes n*4 bytes
+        torch.cuda.synchronize(dev)
+        del src, dst
     prob, desc = workload(a.workload)
     pl = lib.plan_for(prob, "cuda:0", precision="fp32_refined", tol=1e-5, theta=0.5, P=6,
                       profile=1)

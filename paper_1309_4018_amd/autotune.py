@@ -1,0 +1,94 @@
+"""Autotuner for the treecode parameters.
+
+Two kinds of parameters are chosen:
+* speed only: ncrit (cell size of the octree) and direct_below (cells too
+  small for an expansion go to P2P) -- they change rounding and truncation
+  only marginally;
+* accuracy: the MAC parameter theta and the expansion order P (sec. 2.3,
+  Eqs. multexp and MAC) -- they change the answer.
+
+For every (theta, P) candidate the operator error is measured against the
+library's own direct FP64 operator (every pair by the K-point rule plus the
+same near-field corrections: the discrete operator the treecode approximates)
+on one random vector, as max_i |y_i - y_i^direct| / max_i |y_i^direct|.
+Among the candidates within ``budget``, the fastest FP32 matvec (HIP-event
+time on the current stream, median of a few repetitions) wins; the speed-only
+parameters are then tuned for that (theta, P).  Every evaluation runs in the
+HIP kernels of libpbtc; this module only orchestrates and times.
+"""
+
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+from . import lib
+
+
+def _time_matvec(plan, x, precision, reps=5):
+    import torch
+
+    for _ in range(2):
+        plan.matvec(x, precision)
+    times = []
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        plan.matvec(x, precision)
+        e.record()
+        torch.cuda.synchronize()
+        times.append(s.elapsed_time(e) / 1e3)
+    return float(np.median(times))
+
+
+def autotune(problem, budget=1e-4, thetas=(0.4, 0.5, 0.6), orders=(4, 6, 8),
+             ncrits=(64, 128, 256), direct_belows=(-1, 0), device="cuda:0", seed=0,
+             base=None):
+    """Returns (best parameter dict, list of measured candidates).
+
+    ``problem`` is a ``lib.Problem``; ``base`` extra parameters passed to
+    every plan (tolerance, precision...).
+    """
+    import torch
+
+    base = dict(base or {})
+    ref_plan = lib.Plan(problem, lib.default_params(**dict(base, op="direct",
+                                                           precision="fp64")), device)
+    ref_plan.setup()
+    rng = np.random.default_rng(seed)
+    x = torch.as_tensor(rng.normal(size=ref_plan.n_unknowns), dtype=torch.float64,
+                        device=device)
+    y_ref = ref_plan.matvec(x, lib.FP64)
+    scale = float(y_ref.abs().max())
+    del ref_plan
+    rows = []
+
+    def measure(theta, P, ncrit, db):
+        pl = lib.Plan(problem, lib.default_params(**dict(base, theta=theta, P=P, ncrit=ncrit,
+                                                         direct_below=db)), device)
+        pl.setup()
+        err64 = float((pl.matvec(x, lib.FP64) - y_ref).abs().max()) / scale
+        err32 = float((pl.matvec(x, lib.FP32) - y_ref).abs().max()) / scale
+        t32 = _time_matvec(pl, x, lib.FP32)
+        row = {"theta": theta, "P": P, "ncrit": ncrit, "direct_below": db, "err_fp64": err64,
+               "err_fp32": err32, "matvec_s_fp32": t32}
+        rows.append(row)
+        return row
+
+    # accuracy parameters at the default speed parameters
+    first = [measure(t, p, ncrits[len(ncrits) // 2], direct_belows[0])
+             for t, p in itertools.product(thetas, orders)]
+    ok = [r for r in first if r["err_fp32"] <= budget]
+    if not ok:
+        ok = [min(first, key=lambda r: r["err_fp32"])]
+    best = min(ok, key=lambda r: r["matvec_s_fp32"])
+    # speed parameters for the chosen (theta, P)
+    for nc, db in itertools.product(ncrits, direct_belows):
+        if nc == best["ncrit"] and db == best["direct_below"]:
+            continue
+        r = measure(best["theta"], best["P"], nc, db)
+        if r["err_fp32"] <= max(budget, best["err_fp32"]) and r["matvec_s_fp32"] < best["matvec_s_fp32"]:
+            best = r
+    params = {k: best[k] for k in ("theta", "P", "ncrit", "direct_below")}
+    return params, rows

@@ -527,16 +527,21 @@ __global__ __launch_bounds__(kT) void k_adj_m2p(AdjArgs a, const Src<real>* __re
   const Src<real> t = gpos[j0 + min(lane, nt - 1)];
   const real kap = (real)(kslot == 0 ? b.kappa0 : b.kappa1);
   const real* base = mom + (size_t)(b.slot0 + kslot) * cells_cap * 2 * N;
+  __shared__ real smom[kWaves][2 * N];
+  real* M = smom[uni(threadIdx.x >> 6)];
   real s = 0, f = 0;
   for (int e = e0; e < e1; ++e) {
     const int c = uni(a.cells_list[e]);
     const Cell& cl = a.cells[c];
+    const real* Mg = base + (size_t)c * 2 * N;
+    for (int k = lane; k < 2 * N; k += 64) M[k] = Mg[k];
+    wave_sync();
     const real dx = t.x - (real)cl.cx, dy = t.y - (real)cl.cy, dz = t.z - (real)cl.cz;
     const real r2 = dx * dx + dy * dy + dz * dz;
     const real rinv = rsqrt_(r2);
     const real ee = KIND ? exp_neg(kap * (r2 * rinv)) : real(1);
-    taylor_adj<P, real, KIND>(dx, dy, dz, rinv, ee, kap, t.px, t.py, t.pz,
-                              base + (size_t)c * 2 * N, s, f);
+    taylor_adj<P, real, KIND>(dx, dy, dz, rinv, ee, kap, t.px, t.py, t.pz, M, s, f);
+    wave_sync();
   }
   partial[((size_t)u * 4 + 0) * 64 + lane] = s;
   partial[((size_t)u * 4 + 1) * 64 + lane] = f;

@@ -36,4 +36,12 @@ __device__ __forceinline__ double exp_neg(double v) {
   return exp(-v);
 }
 
+// Orders LDS accesses of the lanes of one wavefront (no work-group barrier):
+// writes before the call are visible to every lane of the wave after it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 }  // namespace pbtc

@@ -180,19 +180,19 @@ __global__ void k_energy(const double* __restrict__ q, const double* __restrict_
 }
 
 
-// partial[chunk * ld + i] = <V_i, w> over the chunk (i < nv)
+// partial[chunk * ld + i] = <V_i, w> over the chunk; one block per (chunk, i)
 __global__ __launch_bounds__(kRedThreads) void k_dots_seg(const double* __restrict__ V, int nv,
                                                           int64_t n, const double* __restrict__ w,
                                                           const int4* __restrict__ chunks,
                                                           double* __restrict__ partial, int ld) {
   __shared__ double lds[kRedThreads / 64];
   const int4 ch = chunks[blockIdx.x];
-  for (int i = 0; i < nv; ++i) {
-    double s = 0.0;
-    for (int64_t j = ch.y + threadIdx.x; j < ch.z; j += kRedThreads) s += V[(size_t)i * n + j] * w[j];
-    s = block_sum(s, lds);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ld + i] = s;
-  }
+  const int i = blockIdx.y;
+  const double* v = V + (size_t)i * n;
+  double s = 0.0;
+  for (int64_t j = ch.y + threadIdx.x; j < ch.z; j += kRedThreads) s += v[j] * w[j];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ld + i] = s;
 }
 
 // out[c * ldo + i] = sum of the chunks of system c
@@ -378,16 +378,16 @@ struct Krylov {
 
   // out[c * ld + i] = <V_i, v> over system c, i < nv
   int dots(const double* Vb, int nv, const double* v, double* out) {
-    hipLaunchKernelGGL(k_dots_seg, dim3(nchunks), dim3(kRedThreads), 0, st, Vb, nv, n, v, chunks,
-                       red, ld);
+    hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, nv), dim3(kRedThreads), 0, st, Vb, nv, n, v,
+                       chunks, red, ld);
     hipLaunchKernelGGL(k_sum_seg, dim3(nc), dim3(kRedThreads), 0, st, red, ld, chunk0, nv, ld, out);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
   // out[c] = ||v|| over system c
   int norm(const double* v, double* out) {
-    hipLaunchKernelGGL(k_dots_seg, dim3(nchunks), dim3(kRedThreads), 0, st, v, 1, n, v, chunks, red,
-                       ld);
+    hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, 1), dim3(kRedThreads), 0, st, v, 1, n, v, chunks,
+                       red, ld);
     hipLaunchKernelGGL(k_sum_seg, dim3(nc), dim3(kRedThreads), 0, st, red, ld, chunk0, 1, 1, out);
     hipLaunchKernelGGL(k_sqrt_n, dim3(1), dim3(64), 0, st, out, nc);
     PBTC_LAUNCH_CHECK();

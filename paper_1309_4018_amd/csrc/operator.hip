@@ -289,18 +289,24 @@ __global__ __launch_bounds__(kItemThreads) void k_m2p(UnitArgs a, const real* __
   const long long ti = t0 + min(lane, nt - 1);
   const real x = tx[ti], y = ty[ti], z = tz[ti];
   const real kap = (real)(slot == 0 ? b.kappa0 : b.kappa1);
+  // the cell's moments go through a per-wavefront LDS slice (broadcast reads)
+  __shared__ real smom[kWaves][2 * N];
+  real* M = smom[uni(threadIdx.x >> 6)];
   real acc[4] = {0, 0, 0, 0};
   for (int e = e0; e < e1; ++e) {
     const int c = uni(a.cells_list[e]);
     const Cell& cl = a.cells[c];
+    const real* Mg = mom + (size_t)c * 2 * N;
+    for (int k = lane; k < 2 * N; k += 64) M[k] = Mg[k];
+    wave_sync();
     const real dx = x - (real)cl.cx, dy = y - (real)cl.cy, dz = z - (real)cl.cz;
     const real r2 = dx * dx + dy * dy + dz * dz;
     const real rinv = rsqrt_(r2);
-    const real* M = mom + (size_t)c * 2 * N;
     if (KIND == 0)
       taylor_laplace<P, real>(dx, dy, dz, rinv, M, acc[0], acc[1]);
     else
       taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(kap * (r2 * rinv)), kap, M, acc[0], acc[1]);
+    wave_sync();
   }
   unit_store<real, 2>(partial, u, acc);
 }

@@ -320,7 +320,7 @@ int build_plan(pbtc_plan& pl) {
       pl.comp_u1[c] = hi;
     }
     // Krylov reduction chunks never straddle two systems
-    constexpr int64_t kChunk = 16384;
+    constexpr int64_t kChunk = 4096;
     pl.dot_chunks.clear();
     pl.comp_chunk0.assign(pl.ncomp + 1, 0);
     for (int c = 0; c < pl.ncomp; ++c) {
