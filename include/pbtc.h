@@ -78,6 +78,14 @@ extern "C" {
 #define PBTC_OP_TREECODE 0 /* Taylor treecode: M2P where the MAC holds, P2P else */
 #define PBTC_OP_DIRECT 1   /* every pair by the K-point rule (dense, O(N^2)) */
 
+/* Right preconditioner of the GMRES solves.  The paper names none (sec. 2.3);
+ * the block-diagonal one leaves the solution and the residual test
+ * unchanged (GMRES on A M^-1, x = M^-1 y) and only reduces iterations. */
+#define PBTC_PREC_NONE 0
+#define PBTC_PREC_BLOCK_DIAG 1 /* per panel, the 2 x 2 block of A coupling its
+                                  two rows (inner / outer region) with its own
+                                  phi and psi: self terms only */
+
 typedef struct pbtc_problem pbtc_problem;
 typedef struct pbtc_plan pbtc_plan;
 
@@ -103,6 +111,8 @@ typedef struct {
   int validate_charges; /* 1: check every charge lies inside its region */
   int profile;      /* 1: time every P2P and M2P launch with HIP events on the
                        caller's stream (pbtc_result.t_p2p_s ...) */
+  int precond;      /* PBTC_PREC_NONE or PBTC_PREC_BLOCK_DIAG (forward and
+                       adjoint solves) */
 } pbtc_params;
 
 typedef struct {
@@ -149,7 +159,7 @@ int pbtc_set_charges(pbtc_problem* p, int region_id, const double* xyz, const do
 /* Defaults: K=4, K_fine=19, N_k=5, thres=2.0, theta=0.5, P=6, ncrit=0,
  * direct_below=-1, tol=1e-5, restart=100, max_iter=1000,
  * precision=PBTC_FP32_REFINED, op=PBTC_OP_TREECODE, inner_tol=1e-6,
- * max_refine=10, validate_charges=1, profile=0. */
+ * max_refine=10, validate_charges=1, profile=0, precond=PBTC_PREC_NONE. */
 int pbtc_params_default(pbtc_params* prm);
 
 /* Host-side checks only (no device work): parameter ranges; every region is
@@ -209,6 +219,19 @@ int pbtc_matvec(pbtc_plan* plan, void* d_workspace, void* hip_stream, const doub
  * pointers as for pbtc_matvec. */
 int pbtc_matvec_transpose(pbtc_plan* plan, void* d_workspace, void* hip_stream,
                           const double* d_x, double* d_y, int precision);
+/* y = M^-1 x (transpose = 0) or y = M^-T x (transpose = 1) for the
+ * block-diagonal preconditioner M of PBTC_PREC_BLOCK_DIAG, whatever
+ * params.precond says.  For panel p of surface t with unknowns phi_p, psi_p
+ * (Eq. matrix and its multi-surface form; the self integral of sec. 2.3):
+ *   M_p = [[1/2, -V_I(p,p)], [1/2, (eps_I / eps_O) V_O(p,p)]],
+ * rows (t, inner region I) and (t, outer region O), V_r(p,p) the singular
+ * integral of G_r over p at its centre (the double layer of a flat panel at
+ * its own centre is zero).  M^-1 maps a vector in row layout to the unknown
+ * layout (both are the pbtc_matvec layout).  x, y: distinct DEVICE buffers of
+ * n_unknowns FP64 values; requires pbtc_setup on the workspace; does not
+ * synchronise.  EINVAL for NULL or aliased buffers. */
+int pbtc_precond_apply(pbtc_plan* plan, void* d_workspace, void* hip_stream, const double* d_x,
+                       double* d_y, int transpose);
 /* The Coulomb right-hand side b (Eq. matel Q) into a device buffer of
  * n_unknowns FP64 values. */
 int pbtc_rhs(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* d_b);

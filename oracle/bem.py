@@ -47,7 +47,7 @@ import numpy as np
 
 from .geometry import panels
 from .gmres import gmres
-from .integrals import green, panel_integrals
+from .integrals import green, panel_integrals, self_integral
 
 KE = 1389.35458  # kJ * A / (mol * e^2)
 ENERGY_FACTOR = 0.5 * 4.0 * math.pi * KE
@@ -234,6 +234,43 @@ class Oracle:
                 S[np.ix_(rows, np.arange(self.uoff[s] + ns, self.uoff[s] + 2 * ns))] += aV * V
                 S[np.ix_(rows, np.arange(self.uoff[s], self.uoff[s] + ns))] += aK * K
         return S
+
+    # -- block-diagonal preconditioner (the paper names none) ----------------
+    def block_diagonal(self):
+        """(np_total, 2, 2) diagonal blocks of A, surfaces in order.
+
+        For panel p of surface t: rows (t, I(t)) and (t, O(t)) of its own
+        collocation point, columns phi_p and psi_p.  From the row formula:
+        entry (r, phi) = 1/2 + sigma_rt K_r(p, p) and (r, psi) =
+        -sigma_rt c_rt V_r(p, p), with K_r(p, p) = 0 (flat panel, centre in
+        its plane) and V_r(p, p) the semi-analytic self integral.
+        """
+        out = []
+        for t, nt in enumerate(self.ns):
+            M = np.zeros((nt, 2, 2))
+            for half, r in enumerate(self.row_regions(t)):
+                V = self_integral(self.pan[t], np.arange(nt), self.kappa[r], self.par.nk)
+                M[:, half, 0] = 0.5
+                M[:, half, 1] = -self.sigma(r, t) * self.ratio(r, t) * V
+            out.append(M)
+        return np.concatenate(out)
+
+    def precond_apply(self, v, transpose=False):
+        """M^-1 v (or M^-T v) for the block-diagonal M; v in the unknown layout."""
+        inv = np.linalg.inv(self.block_diagonal())
+        if transpose:
+            inv = np.transpose(inv, (0, 2, 1))
+        v = np.asarray(v, dtype=np.float64)
+        y = np.empty_like(v)
+        p0 = 0
+        for t, nt in enumerate(self.ns):
+            i0 = self.uoff[t] + np.arange(nt)
+            i1 = i0 + nt
+            blk = inv[p0:p0 + nt]
+            y[i0] = blk[:, 0, 0] * v[i0] + blk[:, 0, 1] * v[i1]
+            y[i1] = blk[:, 1, 0] * v[i0] + blk[:, 1, 1] * v[i1]
+            p0 += nt
+        return y
 
     # -- solve ----------------------------------------------------------------
     def solve(self, tol=None, restart=None, max_iter=None, use_lu=False):

@@ -22,6 +22,8 @@ int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, in
                    int phase);
 int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
                     int phase);
+int apply_precond(pbtc_plan& pl, hipStream_t st, const double* x, double* y, bool transpose,
+                  bool accumulate);
 double wall_seconds();
 }  // namespace pbtc
 
@@ -175,6 +177,7 @@ int pbtc_params_default(pbtc_params* prm) {
   prm->max_refine = 10;
   prm->validate_charges = 1;
   prm->profile = 0;
+  prm->precond = PBTC_PREC_NONE;
   return PBTC_OK;
 }
 
@@ -296,6 +299,15 @@ int pbtc_matvec_transpose(pbtc_plan* plan, void* d_workspace, void* hip_stream, 
   if (precision != PBTC_FP64 && precision != PBTC_FP32)
     return fail_plan(plan, PBTC_EINVAL, "precision must be PBTC_FP64 or PBTC_FP32");
   return apply_transpose(*plan, (hipStream_t)hip_stream, d_x, d_y, precision, 0);
+}
+
+int pbtc_precond_apply(pbtc_plan* plan, void* d_workspace, void* hip_stream, const double* d_x,
+                       double* d_y, int transpose) {
+  if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
+  if (!plan->setup_done || plan->ws != d_workspace)
+    return fail_plan(plan, PBTC_EINVAL, "workspace not set up (call pbtc_setup)");
+  if (!d_x || !d_y || d_x == d_y) return fail_plan(plan, PBTC_EINVAL, "x and y must be distinct device buffers");
+  return apply_precond(*plan, (hipStream_t)hip_stream, d_x, d_y, transpose != 0, false);
 }
 
 int pbtc_rhs(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* d_b) {

@@ -282,10 +282,11 @@ __global__ __launch_bounds__(128) void k_adj_p2m(const Cell* __restrict__ cells,
   const int c = blockIdx.x;
   const Cell cl = cells[c];
   if (cl.nchild != 0 || cl.surf != b.troot) return;
-  const int k = threadIdx.x;
-  const int k1 = k < N ? T.k1[k] : 0, k2 = k < N ? T.k2[k] : 0, k3 = k < N ? T.k3[k] : 0;
+  constexpr int KPT = (N + 127) / 128;  // coefficients per thread
   const real cx = (real)cl.cx, cy = (real)cl.cy, cz = (real)cl.cz;
-  real ms = 0, md = 0;
+  real ms[KPT], md[KPT];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) ms[q] = md[q] = 0;
   for (int base = cl.begin; base < cl.begin + cl.count; base += 128) {
     const int nj = min(128, cl.begin + cl.count - base);
     if (threadIdx.x < nj) {
@@ -304,18 +305,28 @@ __global__ __launch_bounds__(128) void k_adj_p2m(const Cell* __restrict__ cells,
       sq[threadIdx.x][1] = kid == 0 ? s.px : s.pz;
     }
     __syncthreads();
-    if (k < N)
-      for (int t = 0; t < nj; ++t) {
-        const real m = pw[t][0][k1] * pw[t][1][k2] * pw[t][2][k3];
-        ms += sq[t][0] * m;
-        md += sq[t][1] * m;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int k = threadIdx.x + 128 * q;
+      if (k < N) {
+        const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
+        for (int t = 0; t < nj; ++t) {
+          const real m = pw[t][0][k1] * pw[t][1][k2] * pw[t][2][k3];
+          ms[q] += sq[t][0] * m;
+          md[q] += sq[t][1] * m;
+        }
       }
+    }
     __syncthreads();
   }
-  if (k < N) {
-    real* M = mom + ((size_t)slot * cells_cap + c) * 2 * N;
-    M[k] = ms;
-    M[N + k] = md;
+  real* M = mom + ((size_t)slot * cells_cap + c) * 2 * N;
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = threadIdx.x + 128 * q;
+    if (k < N) {
+      M[k] = ms[q];
+      M[N + k] = md[q];
+    }
   }
 }
 
@@ -344,37 +355,37 @@ __global__ __launch_bounds__(128) void k_adj_m2m(const Cell* __restrict__ cells,
   const int c = c0 + blockIdx.x;
   const Cell cl = cells[c];
   if (cl.nchild == 0 || cl.surf != b.troot) return;
-  const int k = threadIdx.x;
-  if (k >= N) return;
-  const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
   real* base = mom + (size_t)slot * cells_cap * 2 * N;
-  real ms = 0, md = 0;
-  for (int ch = cl.child; ch < cl.child + cl.nchild; ++ch) {
-    const Cell cc = cells[ch];
-    const real d[3] = {(real)(cc.cx - cl.cx), (real)(cc.cy - cl.cy), (real)(cc.cz - cl.cz)};
-    real pw[3][P + 1];
+  for (int k = threadIdx.x; k < N; k += 128) {
+    const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
+    real ms = 0, md = 0;
+    for (int ch = cl.child; ch < cl.child + cl.nchild; ++ch) {
+      const Cell cc = cells[ch];
+      const real d[3] = {(real)(cc.cx - cl.cx), (real)(cc.cy - cl.cy), (real)(cc.cz - cl.cz)};
+      real pw[3][P + 1];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      real v = 1;
+      for (int a = 0; a < 3; ++a) {
+        real v = 1;
 #pragma unroll
-      for (int e = 0; e <= P; ++e) {
-        pw[a][e] = v;
-        v *= d[a];
-      }
-    }
-    const real* M = base + (size_t)ch * 2 * N;
-    for (int j1 = 0; j1 <= k1; ++j1)
-      for (int j2 = 0; j2 <= k2; ++j2)
-        for (int j3 = 0; j3 <= k3; ++j3) {
-          const real coef = real(B.c[k1][j1] * B.c[k2][j2] * B.c[k3][j3]) * pw[0][k1 - j1] *
-                            pw[1][k2 - j2] * pw[2][k3 - j3];
-          const int j = mindex(j1, j2, j3);
-          ms += coef * M[j];
-          md += coef * M[N + j];
+        for (int e = 0; e <= P; ++e) {
+          pw[a][e] = v;
+          v *= d[a];
         }
+      }
+      const real* M = base + (size_t)ch * 2 * N;
+      for (int j1 = 0; j1 <= k1; ++j1)
+        for (int j2 = 0; j2 <= k2; ++j2)
+          for (int j3 = 0; j3 <= k3; ++j3) {
+            const real coef = real(B.c[k1][j1] * B.c[k2][j2] * B.c[k3][j3]) * pw[0][k1 - j1] *
+                              pw[1][k2 - j2] * pw[2][k3 - j3];
+            const int j = mindex(j1, j2, j3);
+            ms += coef * M[j];
+            md += coef * M[N + j];
+          }
+    }
+    base[(size_t)c * 2 * N + k] = ms;
+    base[(size_t)c * 2 * N + N + k] = md;
   }
-  base[(size_t)c * 2 * N + k] = ms;
-  base[(size_t)c * 2 * N + N + k] = md;
 }
 
 struct AdjArgs {

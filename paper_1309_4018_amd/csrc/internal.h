@@ -200,6 +200,10 @@ struct pbtc_plan {
   size_t o_verts, o_tris, o_pan_surf, o_qxyz, o_q, o_qreg;
   size_t o_cx, o_cy, o_cz, o_nx, o_ny, o_nz, o_area, o_len;      // panels, FP64
   size_t o_pidx;                                                 // per panel: phi, psi index (int2)
+  size_t o_pinv = 0;   // per panel: inverse of the 2 x 2 diagonal block (row-major FP64)
+  size_t o_ptab = 0;   // per surface: kappa_inner, kappa_outer, eps_inner / eps_outer
+  size_t o_ptmp = 0;   // preconditioned Krylov vector (n FP64)
+  std::vector<double> ptab_host;  // host copy of the o_ptab table
   size_t o_tx, o_ty, o_tz, o_tidx;                               // sorted targets (FP64) + perm
   size_t o_txf, o_tyf, o_tzf;                                    // sorted targets FP32
   size_t o_grp;                                                  // group spheres (4 doubles)

@@ -36,6 +36,29 @@ __device__ __forceinline__ double exp_neg(double v) {
   return exp(-v);
 }
 
+// exp(a * r) with a = exp_arg(kappa) = -kappa (FP64) or -kappa log2(e) (FP32,
+// hardware exp2): one multiply per evaluation
+template <typename real>
+__host__ __device__ __forceinline__ real exp_arg(real kappa);
+template <>
+__host__ __device__ __forceinline__ float exp_arg(float kappa) {
+  return -1.4426950408889634f * kappa;
+}
+template <>
+__host__ __device__ __forceinline__ double exp_arg(double kappa) {
+  return -kappa;
+}
+template <typename real>
+__device__ __forceinline__ real exp_scaled(real a_times_r);
+template <>
+__device__ __forceinline__ float exp_scaled(float v) {
+  return __builtin_amdgcn_exp2f(v);
+}
+template <>
+__device__ __forceinline__ double exp_scaled(double v) {
+  return exp(v);
+}
+
 // Orders LDS accesses of the lanes of one wavefront (no work-group barrier):
 // writes before the call are visible to every lane of the wave after it.
 __device__ __forceinline__ void wave_sync() {

@@ -8,6 +8,9 @@
 // operator in FP64 iterative refinement: r = b - A_64 x, solve A_32 d = r,
 // x += d, until the FP64 residual meets the tolerance.  The energy is the
 // FP64 sum 1/2 * 4 pi k_e * sum_k q_k phi_reac(x_k) (Eq. solv).
+// Optional right preconditioning by the per-panel 2 x 2 diagonal blocks:
+// GMRES on A M^-1 (residuals are those of A, so the stopping test is
+// unchanged), x += M^-1 V y at the end of each cycle.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -113,6 +116,23 @@ __global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b
 __global__ void k_axpy(double alpha, const double* __restrict__ a, int64_t n, double* __restrict__ y) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) y[j] += alpha * a[j];
+}
+
+// y = M^-1 x or M^-T x for the per-panel 2 x 2 blocks inv (row-major);
+// pidx[2p], pidx[2p+1]: the phi and psi entries of panel p (equal to its
+// inner- and outer-region rows).  accumulate: y += instead of y =.
+__global__ void k_prec_apply(int64_t np, const int* __restrict__ pidx, const double* __restrict__ inv,
+                             const double* __restrict__ x, double* __restrict__ y, int transpose,
+                             int accumulate) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int i0 = pidx[2 * p], i1 = pidx[2 * p + 1];
+  const double a = x[i0], b = x[i1];
+  const double m00 = inv[4 * p], m01 = inv[4 * p + 1], m10 = inv[4 * p + 2], m11 = inv[4 * p + 3];
+  const double y0 = transpose ? m00 * a + m10 * b : m00 * a + m01 * b;
+  const double y1 = transpose ? m01 * a + m11 * b : m10 * a + m11 * b;
+  y[i0] = accumulate ? y[i0] + y0 : y0;
+  y[i1] = accumulate ? y[i1] + y1 : y1;
 }
 
 __global__ void k_fill(double* p, int64_t n, double v) {
@@ -403,11 +423,23 @@ struct Krylov {
   }
 };
 
+int apply_precond(pbtc_plan& pl, hipStream_t st, const double* x, double* y, bool transpose,
+                  bool accumulate) {
+  hipLaunchKernelGGL(k_prec_apply, dim3(nblocks(pl.np_tot, 256)), dim3(256), 0, st, pl.np_tot,
+                     wsp<int>(pl, pl.o_pidx), wsp<double>(pl, pl.o_pinv), x, y, transpose ? 1 : 0,
+                     accumulate ? 1 : 0);
+  PBTC_LAUNCH_CHECK();
+  return PBTC_OK;
+}
+
 // Restarted GMRES for A z = rhs on every system at once.  System c stops
 // when its implicit residual <= tol[c] * ref[c]; its Krylov vectors are zero
 // from then on, so further operator applications leave it untouched.
+// prec: 0 none, 1 right preconditioning by M^-1, 2 by M^-T (transposed
+// system).
 template <typename Op>
-static int gmres(pbtc_plan& pl, hipStream_t st, Op op, const double* rhs, double* z, bool zero_start,
+static int gmres(pbtc_plan& pl, hipStream_t st, Op op, int prec, const double* rhs, double* z,
+                 bool zero_start,
                  const std::vector<double>& tol, const std::vector<double>& ref, int max_iter,
                  int* iters, std::vector<double>* hist, std::vector<int>* conv,
                  std::vector<int>* conv_iter) {
@@ -416,6 +448,7 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, const double* rhs, double
   const int64_t n = K.n;
   const int m = K.m, nc = K.nc, ld = K.ld;
   double* r = wsp<double>(pl, pl.o_tmp);
+  double* pz = wsp<double>(pl, pl.o_ptmp);
   conv->assign(nc, 0);
   if (conv_iter) conv_iter->assign(nc, 0);
   std::vector<double> hbeta(nc), hscal(2 * nc), hact(nc), htol(nc), href(nc);
@@ -471,7 +504,12 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, const double* rhs, double
     for (; j < m && *iters < max_iter; ++j) {
       double* vj = K.V + (size_t)j * n;
       double* vn = K.V + (size_t)(j + 1) * n;
-      rc = op(vj, K.w);
+      if (prec) {
+        rc = apply_precond(pl, st, vj, pz, prec == 2, false);
+        if (!rc) rc = op(pz, K.w);
+      } else {
+        rc = op(vj, K.w);
+      }
       if (rc) return rc;
       // CGS2: two passes of classical Gram-Schmidt, per system
       rc = K.dots(K.V, j + 1, K.w, K.hbuf);
@@ -521,8 +559,18 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, const double* rhs, double
     }
     hipLaunchKernelGGL(k_finish_seg, dim3(1), dim3(64), 0, st, nc, std::min(j, m), ld, K.H, K.giv,
                        K.gstride, K.sc);
-    hipLaunchKernelGGL(k_add_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, n, K.giv,
-                       K.gstride, ld, K.scal(SC_KFIN), K.comp, z);
+    if (prec) {
+      // z += M^-1 (V y): the combination is formed in w (free at this point)
+      hipLaunchKernelGGL(k_fill, dim3(nblocks(n, T)), dim3(T), 0, st, K.w, n, 0.0);
+      hipLaunchKernelGGL(k_add_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, n, K.giv,
+                         K.gstride, ld, K.scal(SC_KFIN), K.comp, K.w);
+      PBTC_LAUNCH_CHECK();
+      rc = apply_precond(pl, st, K.w, z, prec == 2, true);
+      if (rc) return rc;
+    } else {
+      hipLaunchKernelGGL(k_add_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, n, K.giv,
+                         K.gstride, ld, K.scal(SC_KFIN), K.comp, z);
+    }
     PBTC_LAUNCH_CHECK();
     bool all = true;
     for (int c = 0; c < nc; ++c) all &= (*conv)[c] != 0;
@@ -566,6 +614,7 @@ int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* 
     return transpose ? apply_transpose(pl, st, in, out, PBTC_FP32, 0)
                      : apply_operator(pl, st, in, out, PBTC_FP32, 0);
   };
+  const int prec = pl.prm.precond == PBTC_PREC_BLOCK_DIAG ? (transpose ? 2 : 1) : 0;
   // systems with a zero right-hand side are solved by x = 0
   std::vector<double> ref(nc), tol(nc, pl.prm.tol);
   for (int c = 0; c < nc; ++c) ref[c] = bnorm[c] > 0.0 ? bnorm[c] : 1.0;
@@ -604,7 +653,8 @@ int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* 
         }
       }
       std::vector<int> cin;
-      rc = gmres(pl, st, op32, r, d, true, tin, rref, pl.prm.max_iter, &iters, hist, &cin, nullptr);
+      rc = gmres(pl, st, op32, prec, r, d, true, tin, rref, pl.prm.max_iter, &iters, hist, &cin,
+                 nullptr);
       if (rc) return rc;
       hipLaunchKernelGGL(k_axpy, dim3(nblocks(n, T)), dim3(T), 0, st, 1.0, d, n, x);
       rc = explicit_residual();
@@ -618,17 +668,19 @@ int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* 
     }
     for (int c = 0; c < nc; ++c) conv[c] = rel[c] <= pl.prm.tol;
   } else {
-    const int prec = pl.prm.precision == PBTC_FP64 ? PBTC_FP64 : PBTC_FP32;
-    if (prec == PBTC_FP64)
-      rc = gmres(pl, st, op64, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv, &cit);
+    const int opp = pl.prm.precision == PBTC_FP64 ? PBTC_FP64 : PBTC_FP32;
+    if (opp == PBTC_FP64)
+      rc = gmres(pl, st, op64, prec, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv,
+                 &cit);
     else
-      rc = gmres(pl, st, op32, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv, &cit);
+      rc = gmres(pl, st, op32, prec, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv,
+                 &cit);
     if (rc) return rc;
     rc = explicit_residual();
     if (rc) return rc;
     // FP64: implicit or explicit residual meets tol; FP32 without refinement:
     // the implicit residual of the FP32 operator meets tol (rel is reported)
-    for (int c = 0; c < nc; ++c) conv[c] = conv[c] || (prec == PBTC_FP64 && rel[c] <= pl.prm.tol);
+    for (int c = 0; c < nc; ++c) conv[c] = conv[c] || (opp == PBTC_FP64 && rel[c] <= pl.prm.tol);
   }
   all = true;
   double worst = 0.0;

@@ -68,22 +68,24 @@ struct Binom {
 };
 
 // Moments of a leaf: M_SL[k] = sum q (y - c)^k,
-// M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d).
+// M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d).  Thread i forms coefficients
+// i, i + kP2MThreads, ... (N_P exceeds the block size from P = 8 on).
 template <typename real, int P>
 __global__ __launch_bounds__(kP2MThreads) void k_p2m(const Cell* __restrict__ cells, int c0,
                                                      const Src<real>* __restrict__ src,
                                                      real* __restrict__ mom) {
   constexpr int N = ncoef(P);
+  constexpr int KPT = (N + kP2MThreads - 1) / kP2MThreads;
   constexpr MultiIndex<P> T{};
   __shared__ real pw[kP2MThreads][3][P + 1];
   __shared__ real sq[kP2MThreads][4];
   const int c = c0 + blockIdx.x;
   const Cell cl = cells[c];
   if (cl.nchild != 0) return;
-  const int k = threadIdx.x;
-  const int k1 = k < N ? T.k1[k] : 0, k2 = k < N ? T.k2[k] : 0, k3 = k < N ? T.k3[k] : 0;
   const real cx = (real)cl.cx, cy = (real)cl.cy, cz = (real)cl.cz;
-  real ms = 0, md = 0;
+  real ms[KPT], md[KPT];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) ms[q] = md[q] = 0;
   for (int base = cl.begin; base < cl.begin + cl.count; base += kP2MThreads) {
     const int j = base + threadIdx.x;
     const int nj = min(kP2MThreads, cl.begin + cl.count - base);
@@ -105,27 +107,37 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const Cell* __restrict__ ce
       sq[threadIdx.x][3] = s.pz;
     }
     __syncthreads();
-    if (k < N) {
-      for (int t = 0; t < nj; ++t) {
-        const real X = pw[t][0][k1], Y = pw[t][1][k2], Z = pw[t][2][k3];
-        ms += sq[t][0] * X * Y * Z;
-        real dl = 0;
-        if (k1) dl += sq[t][1] * real(k1) * pw[t][0][k1 - 1] * Y * Z;
-        if (k2) dl += sq[t][2] * real(k2) * X * pw[t][1][k2 - 1] * Z;
-        if (k3) dl += sq[t][3] * real(k3) * X * Y * pw[t][2][k3 - 1];
-        md += dl;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int k = threadIdx.x + q * kP2MThreads;
+      if (k < N) {
+        const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
+        for (int t = 0; t < nj; ++t) {
+          const real X = pw[t][0][k1], Y = pw[t][1][k2], Z = pw[t][2][k3];
+          ms[q] += sq[t][0] * X * Y * Z;
+          real dl = 0;
+          if (k1) dl += sq[t][1] * real(k1) * pw[t][0][k1 - 1] * Y * Z;
+          if (k2) dl += sq[t][2] * real(k2) * X * pw[t][1][k2 - 1] * Z;
+          if (k3) dl += sq[t][3] * real(k3) * X * Y * pw[t][2][k3 - 1];
+          md[q] += dl;
+        }
       }
     }
     __syncthreads();
   }
-  if (k < N) {
-    mom[(size_t)c * 2 * N + k] = ms;
-    mom[(size_t)c * 2 * N + N + k] = md;
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = threadIdx.x + q * kP2MThreads;
+    if (k < N) {
+      mom[(size_t)c * 2 * N + k] = ms[q];
+      mom[(size_t)c * 2 * N + N + k] = md[q];
+    }
   }
 }
 
 // Shift the children's moments to the parent's centre:
-// M_p[k] = sum_{j <= k} C(k, j) (c_child - c_parent)^(k - j) M_child[j].
+// M_p[k] = sum_{j <= k} C(k, j) (c_child - c_parent)^(k - j) M_child[j];
+// thread i forms coefficients i, i + kP2MThreads, ...
 template <typename real, int P>
 __global__ __launch_bounds__(kP2MThreads) void k_m2m(const Cell* __restrict__ cells, int c0,
                                                      real* __restrict__ mom) {
@@ -135,36 +147,36 @@ __global__ __launch_bounds__(kP2MThreads) void k_m2m(const Cell* __restrict__ ce
   const int c = c0 + blockIdx.x;
   const Cell cl = cells[c];
   if (cl.nchild == 0) return;
-  const int k = threadIdx.x;
-  if (k >= N) return;
-  const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
-  real ms = 0, md = 0;
-  for (int ch = cl.child; ch < cl.child + cl.nchild; ++ch) {
-    const Cell cc = cells[ch];
-    const real d[3] = {(real)(cc.cx - cl.cx), (real)(cc.cy - cl.cy), (real)(cc.cz - cl.cz)};
-    real pw[3][P + 1];
+  for (int k = threadIdx.x; k < N; k += kP2MThreads) {
+    const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
+    real ms = 0, md = 0;
+    for (int ch = cl.child; ch < cl.child + cl.nchild; ++ch) {
+      const Cell cc = cells[ch];
+      const real d[3] = {(real)(cc.cx - cl.cx), (real)(cc.cy - cl.cy), (real)(cc.cz - cl.cz)};
+      real pw[3][P + 1];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      real v = 1;
+      for (int a = 0; a < 3; ++a) {
+        real v = 1;
 #pragma unroll
-      for (int e = 0; e <= P; ++e) {
-        pw[a][e] = v;
-        v *= d[a];
-      }
-    }
-    const real* M = mom + (size_t)ch * 2 * N;
-    for (int j1 = 0; j1 <= k1; ++j1)
-      for (int j2 = 0; j2 <= k2; ++j2)
-        for (int j3 = 0; j3 <= k3; ++j3) {
-          const real coef = real(B.c[k1][j1] * B.c[k2][j2] * B.c[k3][j3]) * pw[0][k1 - j1] *
-                            pw[1][k2 - j2] * pw[2][k3 - j3];
-          const int j = mindex(j1, j2, j3);
-          ms += coef * M[j];
-          md += coef * M[N + j];
+        for (int e = 0; e <= P; ++e) {
+          pw[a][e] = v;
+          v *= d[a];
         }
+      }
+      const real* M = mom + (size_t)ch * 2 * N;
+      for (int j1 = 0; j1 <= k1; ++j1)
+        for (int j2 = 0; j2 <= k2; ++j2)
+          for (int j3 = 0; j3 <= k3; ++j3) {
+            const real coef = real(B.c[k1][j1] * B.c[k2][j2] * B.c[k3][j3]) * pw[0][k1 - j1] *
+                              pw[1][k2 - j2] * pw[2][k3 - j3];
+            const int j = mindex(j1, j2, j3);
+            ms += coef * M[j];
+            md += coef * M[N + j];
+          }
+    }
+    mom[(size_t)c * 2 * N + k] = ms;
+    mom[(size_t)c * 2 * N + N + k] = md;
   }
-  mom[(size_t)c * 2 * N + k] = ms;
-  mom[(size_t)c * 2 * N + N + k] = md;
 }
 
 // ------------------------------------------------------------------- p2p
@@ -188,9 +200,11 @@ struct UnitArgs {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// One (target, source) pair: single and double layer of the block's kernels.
+// k0, k1: kappa of kernel slots 0 / 1; a0, a1 = exp_arg(k0), exp_arg(k1).
 template <typename real, int KS>
 __device__ __forceinline__ void pair(real x, real y, real z, const Src<real>& s, real k0, real k1,
-                                     real (&acc)[4]) {
+                                     real a0, real a1, real (&acc)[4]) {
   const real dx = x - s.x, dy = y - s.y, dz = z - s.z;
   const real r2 = dx * dx + dy * dy + dz * dz;
   const real rinv = r2 > real(0) ? rsqrt_(r2) : real(0);
@@ -202,17 +216,19 @@ __device__ __forceinline__ void pair(real x, real y, real z, const Src<real>& s,
   }
   if (KS == KS_Y || KS == KS_LY || KS == KS_YY) {
     const real kap = KS == KS_LY ? k1 : k0;
+    const real ea = KS == KS_LY ? a1 : a0;
     const real r = r2 * rinv;
-    const real e = exp_neg(kap * r);
+    const real e = exp_scaled(ea * r);
     const int o = KS == KS_LY ? 2 : 0;
-    acc[o] += s.q * e * rinv;
-    acc[o + 1] += pd * r3 * e * (real(1) + kap * r);
+    const real er = e * rinv;
+    acc[o] += s.q * er;
+    acc[o + 1] += pd * (r3 * e) * (real(1) + kap * r);
   }
   if (KS == KS_YY) {
     const real r = r2 * rinv;
-    const real e = exp_neg(k1 * r);
+    const real e = exp_scaled(a1 * r);
     acc[2] += s.q * e * rinv;
-    acc[3] += pd * r3 * e * (real(1) + k1 * r);
+    acc[3] += pd * (r3 * e) * (real(1) + k1 * r);
   }
 }
 
@@ -247,20 +263,30 @@ __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __
   const long long ti = t0 + min(lane, nt - 1);
   const real x = tx[ti], y = ty[ti], z = tz[ti];
   const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
+  const real a0 = exp_arg(k0), a1 = exp_arg(k1);
   real acc[4] = {0, 0, 0, 0};
   for (int e = e0; e < e1; ++e) {
     const int c = uni(a.cells_list[e]);
     const int beg = uni(a.cells[c].begin), end = beg + uni(a.cells[c].count);
     int j = beg;
-    for (; j + 1 < end; j += 2) {
-      const Src<real> s0 = src[j];
-      const Src<real> s1 = src[j + 1];
-      pair<real, KS>(x, y, z, s0, k0, k1, acc);
-      pair<real, KS>(x, y, z, s1, k0, k1, acc);
+    if (j + 1 < end) {
+      // two sources per step; the next two are loaded before the current
+      // two are used, so scalar-load latency overlaps the arithmetic
+      Src<real> s0 = src[j], s1 = src[j + 1];
+      for (; j + 3 < end; j += 2) {
+        const Src<real> n0 = src[j + 2], n1 = src[j + 3];
+        pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
+        pair<real, KS>(x, y, z, s1, k0, k1, a0, a1, acc);
+        s0 = n0;
+        s1 = n1;
+      }
+      pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
+      pair<real, KS>(x, y, z, s1, k0, k1, a0, a1, acc);
+      j += 2;
     }
     if (j < end) {
       const Src<real> s0 = src[j];
-      pair<real, KS>(x, y, z, s0, k0, k1, acc);
+      pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
     }
   }
   unit_store<real, nacc<KS>()>(partial, u, acc);

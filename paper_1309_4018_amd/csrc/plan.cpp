@@ -478,6 +478,8 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_cy = L.add(8 * pl.np_tot);
   pl.o_cz = L.add(8 * pl.np_tot);
   pl.o_pidx = L.add(8 * pl.np_tot);
+  pl.o_pinv = L.add(8 * 4 * pl.np_tot);
+  pl.o_ptab = L.add(8 * 3 * pl.nsurf);
   pl.o_nx = L.add(8 * pl.np_tot);
   pl.o_ny = L.add(8 * pl.np_tot);
   pl.o_nz = L.add(8 * pl.np_tot);
@@ -535,6 +537,7 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_r = L.add(8 * n);
   pl.o_w = L.add(8 * n);
   pl.o_tmp = L.add(8 * n);
+  pl.o_ptmp = L.add(8 * n);
   pl.o_lam = L.add(8 * n);
   pl.o_adj_rhs = L.add(8 * n);
   pl.o_V = L.add(8 * (size_t)(m + 1) * n);

@@ -573,6 +573,34 @@ __global__ void k_near_values(NearArgs a, Tables T, int64_t nrows, const long lo
   }
 }
 
+// Inverse of the 2 x 2 diagonal block of panel p (rows (t, inner) and
+// (t, outer) of its surface t, columns phi_p and psi_p; Eq. matrix and its
+// multi-surface form): [[1/2, -V_I], [1/2, c V_O]] with c = eps_I / eps_O and
+// V_r the self integral of G_r (sec. 2.3); the double layer of a flat panel at
+// its own centre vanishes.  det = (c V_O + V_I) / 2 > 0.
+__global__ void k_prec_blocks(Tables T, int64_t np, const int* __restrict__ verts_tri,
+                              const double* __restrict__ verts, const long long* __restrict__ vbase,
+                              const int* __restrict__ pan_surf, const double* __restrict__ cx,
+                              const double* __restrict__ cy, const double* __restrict__ cz,
+                              const double* __restrict__ ptab, double* __restrict__ inv) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int s = pan_surf[p];
+  const long long vb = vbase[s];
+  const double* A = verts + 3 * (vb + verts_tri[3 * p + 0]);
+  const double* B = verts + 3 * (vb + verts_tri[3 * p + 1]);
+  const double* C = verts + 3 * (vb + verts_tri[3 * p + 2]);
+  const double kI = ptab[3 * s], kO = ptab[3 * s + 1], c = ptab[3 * s + 2];
+  const double vI = self_integral(T, A, B, C, cx[p], cy[p], cz[p], kI) * kInv4Pi;
+  const double vO = kO == kI ? vI : self_integral(T, A, B, C, cx[p], cy[p], cz[p], kO) * kInv4Pi;
+  const double det = 0.5 * (c * vO + vI);
+  const double id = 1.0 / det;
+  inv[4 * p + 0] = c * vO * id;
+  inv[4 * p + 1] = vI * id;
+  inv[4 * p + 2] = -0.5 * id;
+  inv[4 * p + 3] = 0.5 * id;
+}
+
 // ---------------------------------------------------------------------- rhs
 // b[row_off + i] = sum_k q_k / eps_r G_r(x_i, x_k) over the charges of r.
 __global__ void k_coulomb(int64_t n, long long row_off, long long pan_first,
@@ -640,6 +668,7 @@ static void near_args(pbtc_plan& pl, NearArgs* na) {
 
 int upload_descriptors(pbtc_plan& pl, hipStream_t st);
 int recompute_near_values(pbtc_plan& pl, hipStream_t st);
+int recompute_precond(pbtc_plan& pl, hipStream_t st);
 int recompute_rhs(pbtc_plan& pl, hipStream_t st);
 
 // Octree over Morton-sorted points, level by level from the given roots
@@ -936,6 +965,8 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   PBTC_LAUNCH_CHECK();
   rc = recompute_near_values(pl, st);
   if (rc) return rc;
+  rc = recompute_precond(pl, st);
+  if (rc) return rc;
 
   rc = recompute_rhs(pl, st);
   if (rc) return rc;
@@ -1055,6 +1086,36 @@ int recompute_near_values(pbtc_plan& pl, hipStream_t st) {
                      wsp<double>(pl, pl.o_nf_v64), wsp<float>(pl, pl.o_nf_v32));
   PBTC_LAUNCH_CHECK();
 
+  PBTC_HIP(hipStreamSynchronize(st));
+  return PBTC_OK;
+}
+
+// Diagonal blocks of the block-diagonal preconditioner (depend on kappa and
+// eps of the two regions of every surface).
+int recompute_precond(pbtc_plan& pl, hipStream_t st) {
+  Tables tb;
+  tb.K = pl.prm.K;
+  tb.Kf = pl.prm.K_fine;
+  tb.Nk = pl.prm.N_k;
+  for (int i = 0; i < tb.Nk; ++i) {
+    tb.glx[i] = pl.gl_x[i];
+    tb.glw[i] = pl.gl_w[i];
+  }
+  pl.ptab_host.assign(3 * pl.nsurf, 0.0);
+  for (int s = 0; s < pl.nsurf; ++s) {
+    const Surface& sf = pl.prob.surfaces[s];
+    pl.ptab_host[3 * s] = pl.prob.regions[sf.inner].kappa;
+    pl.ptab_host[3 * s + 1] = pl.prob.regions[sf.outer].kappa;
+    pl.ptab_host[3 * s + 2] = pl.prob.regions[sf.inner].eps / pl.prob.regions[sf.outer].eps;
+  }
+  double* ptab = wsp<double>(pl, pl.o_ptab);
+  PBTC_HIP(hipMemcpyAsync(ptab, pl.ptab_host.data(), 8 * pl.ptab_host.size(), hipMemcpyHostToDevice,
+                          st));
+  hipLaunchKernelGGL(k_prec_blocks, dim3(nblocks(pl.np_tot, 128)), dim3(128), 0, st, tb, pl.np_tot,
+                     wsp<int>(pl, pl.o_tris), wsp<double>(pl, pl.o_verts), near_vbase(pl),
+                     wsp<int>(pl, pl.o_pan_surf), wsp<double>(pl, pl.o_cx), wsp<double>(pl, pl.o_cy),
+                     wsp<double>(pl, pl.o_cz), ptab, wsp<double>(pl, pl.o_pinv));
+  PBTC_LAUNCH_CHECK();
   PBTC_HIP(hipStreamSynchronize(st));
   return PBTC_OK;
 }

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpbtc.so")
 OK, EINVAL, EMESH, ECHARGE, EWORKSPACE, EDEVICE, ENOCONV = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32_REFINED, FP32 = 0, 1, 2
 OP_TREECODE, OP_DIRECT = 0, 1
+PREC_NONE, PREC_BLOCK_DIAG = 0, 1
 
 _ERRNAMES = {EINVAL: "EINVAL", EMESH: "EMESH", ECHARGE: "ECHARGE", EWORKSPACE: "EWORKSPACE",
              EDEVICE: "EDEVICE", ENOCONV: "ENOCONV"}
@@ -31,6 +32,7 @@ class Params(C.Structure):
         ("tol", C.c_double), ("restart", C.c_int), ("max_iter", C.c_int),
         ("precision", C.c_int), ("op", C.c_int), ("inner_tol", C.c_double),
         ("max_refine", C.c_int), ("validate_charges", C.c_int), ("profile", C.c_int),
+        ("precond", C.c_int),
     ]
 
 
@@ -75,6 +77,8 @@ _EXPORTS = {
     "pbtc_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pbtc_matvec_transpose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_int]),
+    "pbtc_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int]),
     "pbtc_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pbtc_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_double,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Result)]),
@@ -144,6 +148,11 @@ def default_params(**kw):
         kw["op"] = {"treecode": OP_TREECODE, "direct": OP_DIRECT}[op]
     elif op is not None:
         kw["op"] = op
+    pc = kw.pop("precond", None)
+    if isinstance(pc, str):
+        kw["precond"] = {"none": PREC_NONE, "block_diag": PREC_BLOCK_DIAG}[pc]
+    elif pc is not None:
+        kw["precond"] = pc
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
@@ -312,6 +321,19 @@ class Plan:
         fn = self.lib.pbtc_matvec_transpose if transpose else self.lib.pbtc_matvec
         check(fn(self.h, C.c_void_p(self.ws.data_ptr()), self.stream, C.c_void_p(xd.data_ptr()),
                  C.c_void_p(yd.data_ptr()), int(precision)), self.h)
+        return yd
+
+    def precond_apply(self, x, transpose=False):
+        """M^-1 x (or M^-T x) of the block-diagonal preconditioner."""
+        torch = self.torch
+        xd = torch.as_tensor(np.asarray(x, dtype=np.float64) if not torch.is_tensor(x) else x,
+                             dtype=torch.float64).to(self.device).contiguous()
+        if xd.numel() != self.n_unknowns:
+            raise ValueError("x has the wrong length")
+        yd = torch.empty_like(xd)
+        check(self.lib.pbtc_precond_apply(self.h, C.c_void_p(self.ws.data_ptr()), self.stream,
+                                          C.c_void_p(xd.data_ptr()), C.c_void_p(yd.data_ptr()),
+                                          int(bool(transpose))), self.h)
         return yd
 
     def rhs(self):
