@@ -16,7 +16,13 @@ value = dense-equivalent interactions per second over the whole step:
 time.  The JSON line also reports the solve and set-up seconds, the plain FP64
 GPU treecode for comparison, matvec-only rates, the P2P/M2P roofline of the
 dominant kernel (HIP events on the launch stream, recorded by the library)
-and the CPU oracle timed on a bounded sample of rows.
+and the CPU oracle timed on a bounded sample of rows.  After the timed steps
+the adjoint gradient evaluation (dE/dq, dE/dkappa, dE/deps) is timed too.
+
+Other workloads (--workload): sphere (2,048 panels), multisurface (protein,
+Stern layer and two cavities, 167,936 panels) and batch (64 independent
+star-shaped molecules, 614,420 panels, solved together); --autotune picks
+theta, P and the tree parameters first.
 """
 
 from __future__ import annotations
@@ -38,6 +44,7 @@ PEAK_FP64_TFLOPS = 78.6
 
 
 def workload(name):
+    """(problem, description): a ``synth`` problem, or a list of them (batch)."""
     import synth
 
     if name == "star":
@@ -47,7 +54,17 @@ def workload(name):
     if name == "multisurface":
         return synth.config3_multisurface(), ("protein + Stern + 2 cavities, 167,936 panels, "
                                               "4,000 charges")
+    if name == "batch":
+        probs = synth.config4_batch(n_mol=64)
+        return probs, (f"64 star-shaped molecules, {sum(p.n_panels for p in probs):,} panels, "
+                       f"{sum(p.n_charges for p in probs):,} charges, one launch sequence")
     raise SystemExit(f"unknown workload {name}")
+
+
+def make_plan(lib, prob, **params):
+    if isinstance(prob, list):
+        return lib.Plan(lib.batch_problem(prob), lib.default_params(**params), "cuda:0")
+    return lib.plan_for(prob, "cuda:0", **params)
 
 
 def cpu_baseline(prob, seconds=15.0):
@@ -86,6 +103,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
                     help="also run one elementwise copy of this size (HBM counter calibration)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose theta, P, ncrit, direct_below with the autotuner first")
+    ap.add_argument("--adjoint", type=int, default=1,
+                    help="adjoint (gradient) evaluations timed after the solves")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU: the multi-GPU path (targets sharded across GPUs, "
@@ -109,8 +130,19 @@ def main():
         torch.cuda.synchronize(dev)
         del src, dst
     prob, desc = workload(a.workload)
-    pl = lib.plan_for(prob, "cuda:0", precision="fp32_refined", tol=1e-5, theta=0.5, P=6,
-                      profile=1)
+    probs = prob if isinstance(prob, list) else [prob]
+    n_panels = sum(p.n_panels for p in probs)
+    n_charges = sum(p.n_charges for p in probs)
+    tree = {"theta": 0.5, "P": 6}
+    tune = None
+    if a.autotune:
+        from paper_1309_4018_amd.autotune import autotune
+
+        t = time.perf_counter()
+        tree, rows = autotune(lib.batch_problem(probs), budget=1e-4,
+                              base={"precision": "fp32_refined", "tol": 1e-5})
+        tune = {"seconds": time.perf_counter() - t, "chosen": tree, "candidates": len(rows)}
+    pl = make_plan(lib, prob, precision="fp32_refined", tol=1e-5, profile=1, **tree)
     pl.setup()
     for _ in range(a.warmup):
         pl.solve(force_setup=True)
@@ -163,7 +195,20 @@ def main():
         mv[name] = s.elapsed_time(e) / 1e3 / reps
 
     # plain FP64 GPU treecode, same accuracy target
-    pl64 = lib.plan_for(prob, "cuda:0", precision="fp64", tol=1e-5, theta=0.5, P=6)
+    # adjoint: dE/dq, dE/dkappa, dE/deps after the last solve
+    adjoint = None
+    if a.adjoint > 0:
+        pl.backward()  # builds the transposed operator
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter()
+        for _ in range(a.adjoint):
+            pl.backward()
+        torch.cuda.synchronize(dev)
+        adjoint = {"seconds": (time.perf_counter() - t) / a.adjoint,
+                   "gmres_iterations": pl.last.n_iter,
+                   "matvecs_fp32": pl.last.n_matvec_fp32, "matvecs_fp64": pl.last.n_matvec_fp64}
+
+    pl64 = make_plan(lib, prob, precision="fp64", tol=1e-5, **tree)
     pl64.setup()
     r64 = [pl64.solve(force_setup=True) for _ in range(max(a.fp64_steps, 1))]
     solve64 = float(np.median([r["t_solve_s"] for r in r64]))
@@ -171,8 +216,7 @@ def main():
 
     # the same solve with the block-diagonal right preconditioner (not in the
     # paper; reported beside the headline, which follows the paper's solver)
-    plp = lib.plan_for(prob, "cuda:0", precision="fp32_refined", tol=1e-5, theta=0.5, P=6,
-                       precond="block_diag")
+    plp = make_plan(lib, prob, precision="fp32_refined", tol=1e-5, precond="block_diag", **tree)
     plp.setup()
     rp = [plp.solve(force_setup=True) for _ in range(max(a.fp64_steps, 1))]
     precond = {"solve_s": float(np.median([r["t_solve_s"] for r in rp])),
@@ -194,9 +238,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 operator, f64 krylov/refinement",
         "data": "synthetic",
-        "config": {"workload": desc, "panels": int(prob.n_panels),
-                   "gauss_points": int(prob.n_panels * 4), "charges": int(prob.n_charges),
-                   "K": 4, "theta": 0.5, "P": 6, "tol": 1e-5,
+        "config": {"workload": desc, "panels": int(n_panels),
+                   "gauss_points": int(n_panels * 4), "charges": int(n_charges),
+                   "K": 4, "theta": tree["theta"], "P": tree["P"], "tol": 1e-5,
                    "precision": "fp32 bulk, fp64 refinement"},
         "solve_s": solve32,
         "setup_s": float(np.median([r["t_setup_s"] for r in results])),
@@ -214,10 +258,12 @@ def main():
         "fp64_iterations": r64[-1]["n_iter"],
         "speedup_fp32_refined_vs_fp64": solve64 / solve32 if solve32 else None,
         "block_diag_precond": precond,
+        "adjoint": adjoint,
+        "autotune": tune,
         "roofline": roofline,
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(probs[0], a.cpu_seconds)
     print(json.dumps(out))
     return 0
 

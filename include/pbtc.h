@@ -232,6 +232,18 @@ int pbtc_matvec_transpose(pbtc_plan* plan, void* d_workspace, void* hip_stream,
  * synchronise.  EINVAL for NULL or aliased buffers. */
 int pbtc_precond_apply(pbtc_plan* plan, void* d_workspace, void* hip_stream, const double* d_x,
                        double* d_y, int transpose);
+/* Coulomb energy of the point charges (Eq. total_energy: the total energy
+ * of a species is its solvation energy plus this term; Eq. bind_energy
+ * combines three of them).  Pairs within each region, with that region's
+ * permittivity: E_C = k_e sum_r sum_{i<j in r} q_i q_j / (eps_r |x_i - x_j|)
+ * in kJ/mol (charges of different regions interact through the reaction
+ * potential only).  FP64 on the device; *total (host) receives the sum and
+ * per_system (host, n_systems values as in pbtc_get_systems, may be NULL)
+ * each independent system's share.  Requires pbtc_setup on the workspace;
+ * synchronises the stream.  EINVAL for NULL total or when two charges of one
+ * region coincide (non-finite energy). */
+int pbtc_coulomb_energy(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* total,
+                        double* per_system);
 /* The Coulomb right-hand side b (Eq. matel Q) into a device buffer of
  * n_unknowns FP64 values. */
 int pbtc_rhs(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* d_b);

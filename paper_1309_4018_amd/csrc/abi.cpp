@@ -25,6 +25,7 @@ int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, i
 int apply_precond(pbtc_plan& pl, hipStream_t st, const double* x, double* y, bool transpose,
                   bool accumulate);
 double wall_seconds();
+int device_coulomb(pbtc_plan& pl, hipStream_t st, double* total, double* per_system);
 }  // namespace pbtc
 
 using namespace pbtc;
@@ -308,6 +309,16 @@ int pbtc_precond_apply(pbtc_plan* plan, void* d_workspace, void* hip_stream, con
     return fail_plan(plan, PBTC_EINVAL, "workspace not set up (call pbtc_setup)");
   if (!d_x || !d_y || d_x == d_y) return fail_plan(plan, PBTC_EINVAL, "x and y must be distinct device buffers");
   return apply_precond(*plan, (hipStream_t)hip_stream, d_x, d_y, transpose != 0, false);
+}
+
+int pbtc_coulomb_energy(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* total,
+                        double* per_system) {
+  if (!plan || !total) return fail_global(PBTC_EINVAL, "NULL argument");
+  if (!plan->setup_done || plan->ws != d_workspace)
+    return fail_plan(plan, PBTC_EINVAL, "workspace not set up (call pbtc_setup)");
+  const int rc = device_coulomb(*plan, (hipStream_t)hip_stream, total, per_system);
+  if (rc) return fail_plan(plan, rc, plan->err.c_str());
+  return PBTC_OK;
 }
 
 int pbtc_rhs(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* d_b) {

@@ -34,6 +34,8 @@
 
 #include "device_util.h"
 #include "kernel_common.h"
+#include "moments.h"
+#include "traverse.h"
 #include "taylor.h"
 
 namespace pbtc {
@@ -123,55 +125,34 @@ __global__ void k_gp_groups(int64_t ngrp, int nsurf, const long long* __restrict
   grp[4 * G + 3] = sqrt(r2) * (1.0 + 1e-12);
 }
 
-constexpr int kStack = 8 * kMaxLevels + 16;
 
 // one thread per adjoint item (block, Gauss-point group); mode 0 count, 1 fill
-__global__ void k_adj_lists(int64_t nitems, const int* __restrict__ item_block,
-                            const DevBlock* __restrict__ blocks, const Cell* __restrict__ cells,
-                            const double* __restrict__ grp, double theta, int direct,
-                            int direct_below, int mode, long long* __restrict__ near_ptr,
-                            long long* __restrict__ far_ptr, int* __restrict__ near,
-                            int* __restrict__ far, long long cap_near, long long cap_far) {
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64 * kTravWaves) void k_adj_lists(
+    int64_t nitems, const int* __restrict__ item_block, const DevBlock* __restrict__ blocks,
+    const Cell* __restrict__ cells, const double* __restrict__ grp, double theta, int direct,
+    int direct_below, int mode, long long* __restrict__ near_ptr, long long* __restrict__ far_ptr,
+    int* __restrict__ near, int* __restrict__ far, long long cap_near, long long cap_far,
+    int* __restrict__ overflow) {
+  __shared__ int stk[kTravWaves][kTravStack];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * kTravWaves + w;
   if (it >= nitems) return;
-  const DevBlock b = blocks[item_block[it]];
+  const DevBlock& b = blocks[item_block[it]];
   const int64_t g = b.gpgrp_off + (it - b.aitem_off);
-  const double gxc = grp[4 * g], gyc = grp[4 * g + 1], gzc = grp[4 * g + 2], gr = grp[4 * g + 3];
-  long long nn = 0, nf = 0, pn = 0, pf = 0;
+  long long pn = 0, pf = 0, nn = 0, nf = 0;
   if (mode == 1) {
     pn = near_ptr[it];
     pf = far_ptr[it];
   }
   if (direct) {
-    if (mode == 1 && pn < cap_near) near[pn] = b.troot;
+    if (mode == 1 && lane == 0 && pn < cap_near) near[pn] = b.troot;
     nn = 1;
   } else {
-    int stack[kStack];
-    int sp = 0;
-    stack[sp++] = b.troot;
-    while (sp > 0) {
-      const int c = stack[--sp];
-      const Cell cl = cells[c];
-      if (cl.count == 0) continue;
-      const double dx = gxc - cl.cx, dy = gyc - cl.cy, dz = gzc - cl.cz;
-      const double rtb = sqrt(dx * dx + dy * dy + dz * dz) - gr;
-      if (theta * rtb > cl.rb) {
-        if (cl.count < direct_below) {
-          if (mode == 1 && pn + nn < cap_near) near[pn + nn] = c;
-          ++nn;
-        } else {
-          if (mode == 1 && pf + nf < cap_far) far[pf + nf] = c;
-          ++nf;
-        }
-      } else if (cl.nchild == 0) {
-        if (mode == 1 && pn + nn < cap_near) near[pn + nn] = c;
-        ++nn;
-      } else {
-        for (int k = cl.nchild - 1; k >= 0 && sp < kStack; --k) stack[sp++] = cl.child + k;
-      }
-    }
+    wave_lists(cells, b.troot, grp[4 * g], grp[4 * g + 1], grp[4 * g + 2], grp[4 * g + 3], theta,
+               direct_below, mode, pn, pf, near, far, cap_near, cap_far, stk[w], &nn, &nf,
+               overflow);
   }
-  if (mode == 0) {
+  if (mode == 0 && lane == 0) {
     near_ptr[it] = nn;
     far_ptr[it] = nf;
   }
@@ -268,20 +249,22 @@ template <typename real, int P>
 __global__ __launch_bounds__(128) void k_adj_p2m(const Cell* __restrict__ cells,
                                                  const int* __restrict__ slot_block,
                                                  const int* __restrict__ slot_kidx,
-                                                 const int* __restrict__ slot_ids,
+                                                 const int* __restrict__ tslot,
                                                  const DevBlock* __restrict__ blocks,
                                                  const Src<real>* __restrict__ asrc,
-                                                 real* __restrict__ mom, long long cells_cap) {
+                                                 real* __restrict__ mom, int nrec) {
   constexpr int N = ncoef(P);
   constexpr MultiIndex<P> T{};
   __shared__ real pw[128][3][P + 1];
   __shared__ real sq[128][2];
-  const int slot = slot_ids[blockIdx.y];
-  const DevBlock b = blocks[slot_block[slot]];
-  const int kid = slot_kidx[slot];
   const int c = blockIdx.x;
   const Cell cl = cells[c];
-  if (cl.nchild != 0 || cl.surf != b.troot) return;
+  if (cl.nchild != 0) return;
+  // blockIdx.y: local slot of the cell's tree
+  const int slot = tslot[(size_t)cl.surf * nrec + blockIdx.y];
+  if (slot < 0) return;
+  const DevBlock b = blocks[slot_block[slot]];
+  const int kid = slot_kidx[slot];
   constexpr int KPT = (N + 127) / 128;  // coefficients per thread
   const real cx = (real)cl.cx, cy = (real)cl.cy, cz = (real)cl.cz;
   real ms[KPT], md[KPT];
@@ -319,7 +302,7 @@ __global__ __launch_bounds__(128) void k_adj_p2m(const Cell* __restrict__ cells,
     }
     __syncthreads();
   }
-  real* M = mom + ((size_t)slot * cells_cap + c) * 2 * N;
+  real* M = mom + ((size_t)c * nrec + b.lslot0 + kid) * 2 * N;
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int k = threadIdx.x + 128 * q;
@@ -330,62 +313,22 @@ __global__ __launch_bounds__(128) void k_adj_p2m(const Cell* __restrict__ cells,
   }
 }
 
-template <int P>
-struct Binom2 {
-  int c[P + 1][P + 1];
-  constexpr Binom2() : c() {
-    for (int n = 0; n <= P; ++n) {
-      c[n][0] = 1;
-      for (int k = 1; k <= n; ++k) c[n][k] = c[n - 1][k - 1] + (k <= n - 1 ? c[n - 1][k] : 0);
-    }
-  }
-};
-
+// Upward pass of the transposed treecode (same binomial shift as forward).
 template <typename real, int P>
-__global__ __launch_bounds__(128) void k_adj_m2m(const Cell* __restrict__ cells, int c0,
-                                                 const int* __restrict__ slot_block,
-                                                 const int* __restrict__ slot_ids,
-                                                 const DevBlock* __restrict__ blocks,
-                                                 real* __restrict__ mom, long long cells_cap) {
+__global__ __launch_bounds__(kM2MThreads) void k_adj_m2m(const Cell* __restrict__ cells, int c0,
+                                                         const int* __restrict__ slot_block,
+                                                         const int* __restrict__ tslot,
+                                                         const DevBlock* __restrict__ blocks,
+                                                         real* __restrict__ mom, int ms) {
   constexpr int N = ncoef(P);
-  constexpr MultiIndex<P> T{};
-  constexpr Binom2<P> B{};
-  const int slot = slot_ids[blockIdx.y];
-  const DevBlock b = blocks[slot_block[slot]];
   const int c = c0 + blockIdx.x;
   const Cell cl = cells[c];
-  if (cl.nchild == 0 || cl.surf != b.troot) return;
-  real* base = mom + (size_t)slot * cells_cap * 2 * N;
-  for (int k = threadIdx.x; k < N; k += 128) {
-    const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
-    real ms = 0, md = 0;
-    for (int ch = cl.child; ch < cl.child + cl.nchild; ++ch) {
-      const Cell cc = cells[ch];
-      const real d[3] = {(real)(cc.cx - cl.cx), (real)(cc.cy - cl.cy), (real)(cc.cz - cl.cz)};
-      real pw[3][P + 1];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        real v = 1;
-#pragma unroll
-        for (int e = 0; e <= P; ++e) {
-          pw[a][e] = v;
-          v *= d[a];
-        }
-      }
-      const real* M = base + (size_t)ch * 2 * N;
-      for (int j1 = 0; j1 <= k1; ++j1)
-        for (int j2 = 0; j2 <= k2; ++j2)
-          for (int j3 = 0; j3 <= k3; ++j3) {
-            const real coef = real(B.c[k1][j1] * B.c[k2][j2] * B.c[k3][j3]) * pw[0][k1 - j1] *
-                              pw[1][k2 - j2] * pw[2][k3 - j3];
-            const int j = mindex(j1, j2, j3);
-            ms += coef * M[j];
-            md += coef * M[N + j];
-          }
-    }
-    base[(size_t)c * 2 * N + k] = ms;
-    base[(size_t)c * 2 * N + N + k] = md;
-  }
+  if (cl.nchild == 0) return;
+  const int slot = tslot[(size_t)cl.surf * ms + blockIdx.y];
+  if (slot < 0) return;
+  const DevBlock b = blocks[slot_block[slot]];
+  const int kid = slot - b.slot0;
+  m2m_cell<real, P>(cells, cl, c, mom + (size_t)(b.lslot0 + kid) * 2 * N, (size_t)ms * 2 * N);
 }
 
 struct AdjArgs {
@@ -523,7 +466,7 @@ __device__ __forceinline__ void taylor_adj(real dx, real dy, real dz, real rinv,
 
 template <typename real, int P, int KIND>
 __global__ __launch_bounds__(kT) void k_adj_m2p(AdjArgs a, const Src<real>* __restrict__ gpos,
-                                                const real* __restrict__ mom, long long cells_cap,
+                                                const real* __restrict__ mom, int ms,
                                                 int kslot, real* __restrict__ partial) {
   constexpr int N = ncoef(P);
   const int u = uni(blockIdx.x * kWaves + (threadIdx.x >> 6));
@@ -537,14 +480,14 @@ __global__ __launch_bounds__(kT) void k_adj_m2p(AdjArgs a, const Src<real>* __re
   const int lane = threadIdx.x & 63;
   const Src<real> t = gpos[j0 + min(lane, nt - 1)];
   const real kap = (real)(kslot == 0 ? b.kappa0 : b.kappa1);
-  const real* base = mom + (size_t)(b.slot0 + kslot) * cells_cap * 2 * N;
+  const real* base = mom + (size_t)(b.lslot0 + kslot) * 2 * N;
   __shared__ real smom[kWaves][2 * N];
   real* M = smom[uni(threadIdx.x >> 6)];
   real s = 0, f = 0;
   for (int e = e0; e < e1; ++e) {
     const int c = uni(a.cells_list[e]);
     const Cell& cl = a.cells[c];
-    const real* Mg = base + (size_t)c * 2 * N;
+    const real* Mg = base + (size_t)c * ms * 2 * N;
     for (int k = lane; k < 2 * N; k += 64) M[k] = Mg[k];
     wave_sync();
     const real dx = t.x - (real)cl.cx, dy = t.y - (real)cl.cy, dz = t.z - (real)cl.cz;
@@ -763,11 +706,13 @@ int adjoint_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   const int direct = pl.prm.op == PBTC_OP_DIRECT;
   long long* near_ptr = wsp<long long>(pl, pl.o_anear_ptr);
   long long* far_ptr = wsp<long long>(pl, pl.o_afar_ptr);
-  hipLaunchKernelGGL(k_adj_lists, dim3(nblocks(pl.nitems_adj, 64)), dim3(64), 0, st, pl.nitems_adj,
-                     wsp<int>(pl, pl.o_aitems), wsp<DevBlock>(pl, pl.o_blocks),
+  int* flags = wsp<int>(pl, pl.o_flags);
+  PBTC_HIP(hipMemsetAsync(flags, 0, 4 * 16, st));
+  hipLaunchKernelGGL(k_adj_lists, dim3(nblocks(pl.nitems_adj, kTravWaves)), dim3(64 * kTravWaves),
+                     0, st, pl.nitems_adj, wsp<int>(pl, pl.o_aitems), wsp<DevBlock>(pl, pl.o_blocks),
                      wsp<Cell>(pl, pl.o_tcells), wsp<double>(pl, pl.o_gpgrp), pl.prm.theta, direct,
                      pl.direct_below, 0, near_ptr, far_ptr, (int*)nullptr, (int*)nullptr,
-                     (long long)0, (long long)0);
+                     (long long)0, (long long)0, flags);
   PBTC_LAUNCH_CHECK();
   scan_exclusive<long long>(near_ptr, pl.nitems_adj, scan_scratch, st);
   scan_exclusive<long long>(far_ptr, pl.nitems_adj, scan_scratch, st);
@@ -784,12 +729,21 @@ int adjoint_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   }
   pl.n_anear = tot[0];
   pl.n_afar = tot[1];
-  hipLaunchKernelGGL(k_adj_lists, dim3(nblocks(pl.nitems_adj, 64)), dim3(64), 0, st, pl.nitems_adj,
-                     wsp<int>(pl, pl.o_aitems), wsp<DevBlock>(pl, pl.o_blocks),
+  hipLaunchKernelGGL(k_adj_lists, dim3(nblocks(pl.nitems_adj, kTravWaves)), dim3(64 * kTravWaves),
+                     0, st, pl.nitems_adj, wsp<int>(pl, pl.o_aitems), wsp<DevBlock>(pl, pl.o_blocks),
                      wsp<Cell>(pl, pl.o_tcells), wsp<double>(pl, pl.o_gpgrp), pl.prm.theta, direct,
                      pl.direct_below, 1, near_ptr, far_ptr, wsp<int>(pl, pl.o_anear),
-                     wsp<int>(pl, pl.o_afar), (long long)pl.cap_anear, (long long)pl.cap_afar);
+                     wsp<int>(pl, pl.o_afar), (long long)pl.cap_anear, (long long)pl.cap_afar, flags);
   PBTC_LAUNCH_CHECK();
+  {
+    int hflag = 0;
+    PBTC_HIP(hipMemcpyAsync(&hflag, flags, 4, hipMemcpyDeviceToHost, st));
+    PBTC_HIP(hipStreamSynchronize(st));
+    if (hflag) {
+      pl.err = "tree traversal stack exhausted (octree too deep)";
+      return PBTC_EDEVICE;
+    }
+  }
   // work units
   {
     std::vector<long long> np_(pl.nitems_adj + 1), fp_(pl.nitems_adj + 1);
@@ -905,6 +859,17 @@ static int adj_upload_small(pbtc_plan& pl, hipStream_t st) {
   PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_slot_block), sb.data(), 4 * sb.size(), hipMemcpyHostToDevice, st));
   PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_slot_kidx), sk.data(), 4 * sk.size(), hipMemcpyHostToDevice, st));
   for (int ph = 0; ph < 2; ++ph) {
+    // the slots of each target-set tree, by local slot number
+    std::vector<int>& ts = pl.adj_tslot_host[ph];
+    ts.assign(std::max<size_t>(pl.tsets.size() * pl.adj_ms, 1), -1);
+    for (size_t bi = 0; bi < pl.blocks.size(); ++bi) {
+      const Block& b = pl.blocks[bi];
+      if ((b.reaction ? 1 : 0) != ph) continue;
+      for (int k = 0; k < b.nk; ++k)
+        ts[(size_t)b.t * pl.adj_ms + pl.blk_lslot0[bi] + k] = (int)(pl.blk_slot0[bi] + k);
+    }
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_adj_tslot[ph]), ts.data(), 4 * ts.size(),
+                            hipMemcpyHostToDevice, st));
     if (!blk[ph].empty())
       PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_adj_blist[ph]), blk[ph].data(), 4 * blk[ph].size(),
                               hipMemcpyHostToDevice, st));
@@ -931,10 +896,10 @@ static void launch_adj_m2p(pbtc_plan& pl, hipStream_t st, const AdjArgs& a, int 
   case PP:                                                                                    \
     if (kind == 0)                                                                            \
       hipLaunchKernelGGL((k_adj_m2p<real, PP, 0>), dim3(grid), dim3(kT), 0, st, a, gpos, mom, \
-                         (long long)pl.cap_tcells, kslot, partial);                           \
+                         pl.adj_ms, kslot, partial);                                          \
     else                                                                                      \
       hipLaunchKernelGGL((k_adj_m2p<real, PP, 1>), dim3(grid), dim3(kT), 0, st, a, gpos, mom, \
-                         (long long)pl.cap_tcells, kslot, partial);                           \
+                         pl.adj_ms, kslot, partial);                                          \
     break;
   switch (pl.P) {
     PBTC_AM2P(2)
@@ -950,24 +915,23 @@ static void launch_adj_m2p(pbtc_plan& pl, hipStream_t st, const AdjArgs& a, int 
 
 template <typename real>
 static int adj_moments(pbtc_plan& pl, hipStream_t st, int phase, real* mom) {
-  const int ns = (int)pl.adj_sids[phase].size();
-  if (ns == 0) return PBTC_OK;
+  if (pl.adj_sids[phase].empty()) return PBTC_OK;
   const Cell* cells = wsp<Cell>(pl, pl.o_tcells);
-  const int* sids = wsp<int>(pl, pl.o_adj_sids[phase]);
+  const int* ts = wsp<int>(pl, pl.o_adj_tslot[phase]);
   const int* sb = wsp<int>(pl, pl.o_slot_block);
   const int* sk = wsp<int>(pl, pl.o_slot_kidx);
   const DevBlock* blocks = wsp<DevBlock>(pl, pl.o_blocks);
   const Src<real>* asrc = wsp<Src<real>>(pl, sizeof(real) == 4 ? pl.o_asrc32 : pl.o_asrc64);
-  const long long cap = pl.cap_tcells;
+  const int ms = pl.adj_ms;  // moment records per cell
 #define PBTC_AMOM(PP)                                                                          \
   case PP:                                                                                     \
-    hipLaunchKernelGGL((k_adj_p2m<real, PP>), dim3((unsigned)pl.n_tcells, ns), dim3(128), 0, st, \
-                       cells, sb, sk, sids, blocks, asrc, mom, cap);                           \
+    hipLaunchKernelGGL((k_adj_p2m<real, PP>), dim3((unsigned)pl.n_tcells, ms), dim3(128), 0, st, \
+                       cells, sb, sk, ts, blocks, asrc, mom, ms);                              \
     for (int l = pl.n_tlevels - 1; l >= 0; --l) {                                              \
       const int lb = pl.tlevel_begin[l], le = pl.tlevel_begin[l + 1];                          \
       if (le > lb)                                                                             \
-        hipLaunchKernelGGL((k_adj_m2m<real, PP>), dim3(le - lb, ns), dim3(128), 0, st, cells,  \
-                           lb, sb, sids, blocks, mom, cap);                                    \
+        hipLaunchKernelGGL((k_adj_m2m<real, PP>), dim3(le - lb, ms), dim3(kM2MThreads), 0, st, \
+                           cells, lb, sb, ts, blocks, mom, ms);                                \
     }                                                                                          \
     break;
   switch (pl.P) {

@@ -113,6 +113,8 @@ struct DevBlock {
   long long csc_off;         // first transposed near-field column of this block
   int slot0;                 // kernel slot of kernel 0 (slot0 + 1 for kernel 1)
   int troot;                 // root cell of the target-set tree
+  int lslot0;                // slot of kernel 0 among the slots of its target-set tree
+  int pad2;
 };
 
 // Weights of one (block, kernel) slot of the transposed operator:
@@ -203,7 +205,11 @@ struct pbtc_plan {
   size_t o_pinv = 0;   // per panel: inverse of the 2 x 2 diagonal block (row-major FP64)
   size_t o_ptab = 0;   // per surface: kappa_inner, kappa_outer, eps_inner / eps_outer
   size_t o_ptmp = 0;   // preconditioned Krylov vector (n FP64)
+  size_t o_flags = 0;  // device status flags (16 int)
+  size_t o_qtab = 0;   // per region: first charge (nreg + 1 long long), eps (nreg double)
+  size_t o_coul = 0;   // Coulomb energy per system (ncomp double)
   std::vector<double> ptab_host;  // host copy of the o_ptab table
+  std::vector<double> qtab_host;  // host copy of the o_qtab table
   size_t o_tx, o_ty, o_tz, o_tidx;                               // sorted targets (FP64) + perm
   size_t o_txf, o_tyf, o_tzf;                                    // sorted targets FP32
   size_t o_grp;                                                  // group spheres (4 doubles)
@@ -268,6 +274,8 @@ struct pbtc_plan {
   std::vector<int> tlevel_begin;
   int n_tlevels = 0;
   std::vector<int64_t> blk_slot0, blk_aout0, blk_aout1, blk_aitem_off, blk_csc_off;
+  std::vector<int> blk_lslot0;  // local slot of kernel 0 in its target-set tree
+  int adj_ms = 1;               // largest number of slots on one target-set tree
   size_t o_tkey_sorted = 0, o_gpos32 = 0, o_gpos64 = 0, o_gp_pos = 0, o_gpgrp = 0;
   size_t o_mu_s = 0, o_mu_d = 0, o_asrc32 = 0, o_asrc64 = 0, o_aout_s = 0, o_aout_d = 0;
   size_t o_aitems = 0, o_slots[2] = {0, 0}, o_gather[2] = {0, 0}, o_gather_slots[2] = {0, 0};
@@ -284,6 +292,8 @@ struct pbtc_plan {
   int64_t cap_aunits = 0, cap_auptr = 0;
   size_t o_aunits = 0, o_auptr = 0, o_slot_block = 0, o_slot_kidx = 0, o_adj_tab = 0;
   size_t o_adj_blist[2] = {0, 0}, o_adj_sids[2] = {0, 0}, o_csc_row = 0;
+  size_t o_adj_tslot[2] = {0, 0};  // per phase: [target-set tree][local slot] -> slot or -1
+  std::vector<int> adj_tslot_host[2];
   std::vector<int> adj_blist[2], adj_sids[2];
   std::vector<double> adj_history;
   size_t o_nf_rowblk = 0;                          // near-field row -> block (int)

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 
 #include "device_util.h"
 
@@ -215,18 +216,16 @@ __global__ __launch_bounds__(kRedThreads) void k_dots_seg(const double* __restri
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ld + i] = s;
 }
 
-// out[c * ldo + i] = sum of the chunks of system c
+// out[c * ldo + i] = sum of the chunks of system c, in chunk order: one
+// thread per (system c = blockIdx.x, i)
 __global__ void k_sum_seg(const double* __restrict__ partial, int pld, const int* __restrict__ chunk0,
                           int nv, int ldo, double* __restrict__ out) {
-  __shared__ double lds[kRedThreads / 64];
   const int c = blockIdx.x;
-  for (int i = 0; i < nv; ++i) {
-    double s = 0.0;
-    for (int b = chunk0[c] + threadIdx.x; b < chunk0[c + 1]; b += kRedThreads)
-      s += partial[(size_t)b * pld + i];
-    s = block_sum(s, lds);
-    if (threadIdx.x == 0) out[(size_t)c * ldo + i] = s;
-  }
+  const int i = blockIdx.y * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  double s = 0.0;
+  for (int b = chunk0[c]; b < chunk0[c + 1]; ++b) s += partial[(size_t)b * pld + i];
+  out[(size_t)c * ldo + i] = s;
 }
 
 __global__ void k_sqrt_n(double* p, int n) {
@@ -352,6 +351,24 @@ __global__ void k_energy_seg(const double* __restrict__ q, const double* __restr
   if (threadIdx.x == 0) out[c] = factor * s;
 }
 
+// phi_c[i] = sum over the other charges j of i's region of q_j / (eps_r |x_i - x_j|)
+__global__ void k_coulomb_pot(int64_t nq, const double* __restrict__ qxyz,
+                              const double* __restrict__ q, const int* __restrict__ qreg,
+                              const long long* __restrict__ qoff, const double* __restrict__ eps,
+                              double* __restrict__ phi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const int r = qreg[i];
+  const double x = qxyz[3 * i], y = qxyz[3 * i + 1], z = qxyz[3 * i + 2];
+  double s = 0.0;
+  for (long long j = qoff[r]; j < qoff[r + 1]; ++j) {
+    if (j == i) continue;
+    const double dx = x - qxyz[3 * j], dy = y - qxyz[3 * j + 1], dz = z - qxyz[3 * j + 2];
+    s += q[j] / sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  phi[i] = s / eps[r];
+}
+
 }  // namespace
 
 // Krylov state of every independent system (a connected component of the
@@ -400,7 +417,8 @@ struct Krylov {
   int dots(const double* Vb, int nv, const double* v, double* out) {
     hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, nv), dim3(kRedThreads), 0, st, Vb, nv, n, v,
                        chunks, red, ld);
-    hipLaunchKernelGGL(k_sum_seg, dim3(nc), dim3(kRedThreads), 0, st, red, ld, chunk0, nv, ld, out);
+    hipLaunchKernelGGL(k_sum_seg, dim3(nc, nblocks(nv, 64)), dim3(64), 0, st, red, ld, chunk0, nv, ld,
+                       out);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
@@ -408,7 +426,7 @@ struct Krylov {
   int norm(const double* v, double* out) {
     hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, 1), dim3(kRedThreads), 0, st, v, 1, n, v, chunks,
                        red, ld);
-    hipLaunchKernelGGL(k_sum_seg, dim3(nc), dim3(kRedThreads), 0, st, red, ld, chunk0, 1, 1, out);
+    hipLaunchKernelGGL(k_sum_seg, dim3(nc, 1), dim3(64), 0, st, red, ld, chunk0, 1, 1, out);
     hipLaunchKernelGGL(k_sqrt_n, dim3(1), dim3(64), 0, st, out, nc);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
@@ -760,6 +778,45 @@ int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res) {
     pl.err = "GMRES did not reach the tolerance within max_iter";
     return PBTC_ENOCONV;
   }
+  return PBTC_OK;
+}
+
+// Coulomb energy of every system: 1/2 k_e sum_i q_i phi_c[i].
+int device_coulomb(pbtc_plan& pl, hipStream_t st, double* total, double* per_system) {
+  // table: nreg + 1 first-charge offsets (int64), then nreg permittivities
+  std::vector<double>& tab = pl.qtab_host;
+  tab.assign(2 * pl.nreg + 1, 0.0);
+  for (int r = 0; r <= pl.nreg; ++r) {
+    const long long o = pl.q_off_region[r];
+    std::memcpy(&tab[r], &o, 8);
+  }
+  for (int r = 0; r < pl.nreg; ++r) tab[pl.nreg + 1 + r] = pl.prob.regions[r].eps;
+  double* dtab = wsp<double>(pl, pl.o_qtab);
+  PBTC_HIP(hipMemcpyAsync(dtab, tab.data(), 8 * tab.size(), hipMemcpyHostToDevice, st));
+  double* phi = wsp<double>(pl, pl.o_z2);
+  std::vector<double> e(pl.ncomp, 0.0);
+  if (pl.nq > 0) {
+    hipLaunchKernelGGL(k_coulomb_pot, dim3(nblocks(pl.nq, 256)), dim3(256), 0, st, pl.nq,
+                       wsp<double>(pl, pl.o_qxyz), wsp<double>(pl, pl.o_q), wsp<int>(pl, pl.o_qreg),
+                       reinterpret_cast<const long long*>(dtab), dtab + pl.nreg + 1, phi);
+    double* out = wsp<double>(pl, pl.o_coul);
+    hipLaunchKernelGGL(k_energy_seg, dim3(pl.ncomp), dim3(kRedThreads), 0, st,
+                       wsp<double>(pl, pl.o_q), phi, wsp<int>(pl, pl.o_comp_q), pl.nq, 0.5 * kCoulomb,
+                       out);
+    PBTC_LAUNCH_CHECK();
+    PBTC_HIP(hipMemcpyAsync(e.data(), out, 8 * pl.ncomp, hipMemcpyDeviceToHost, st));
+  }
+  PBTC_HIP(hipStreamSynchronize(st));
+  double t = 0.0;
+  for (int c = 0; c < pl.ncomp; ++c) {
+    if (!std::isfinite(e[c])) {
+      pl.err = "Coulomb energy is not finite (coincident charges in one region)";
+      return PBTC_EINVAL;
+    }
+    t += e[c];
+    if (per_system) per_system[c] = e[c];
+  }
+  *total = t;
   return PBTC_OK;
 }
 

@@ -22,6 +22,7 @@
 
 #include "device_util.h"
 #include "kernel_common.h"
+#include "moments.h"
 #include "taylor.h"
 
 namespace pbtc {
@@ -55,17 +56,6 @@ __global__ void k_prep(int64_t ngp, const double* __restrict__ gx, const double*
 
 // -------------------------------------------------------------- p2m / m2m
 constexpr int kP2MThreads = 128;
-
-template <int P>
-struct Binom {
-  int c[P + 1][P + 1];
-  constexpr Binom() : c() {
-    for (int n = 0; n <= P; ++n) {
-      c[n][0] = 1;
-      for (int k = 1; k <= n; ++k) c[n][k] = c[n - 1][k - 1] + (k <= n - 1 ? c[n - 1][k] : 0);
-    }
-  }
-};
 
 // Moments of a leaf: M_SL[k] = sum q (y - c)^k,
 // M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d).  Thread i forms coefficients
@@ -135,48 +125,14 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m(const Cell* __restrict__ ce
   }
 }
 
-// Shift the children's moments to the parent's centre:
-// M_p[k] = sum_{j <= k} C(k, j) (c_child - c_parent)^(k - j) M_child[j];
-// thread i forms coefficients i, i + kP2MThreads, ...
+// Upward pass: parent moments from the children's (binomial shift).
 template <typename real, int P>
-__global__ __launch_bounds__(kP2MThreads) void k_m2m(const Cell* __restrict__ cells, int c0,
+__global__ __launch_bounds__(kM2MThreads) void k_m2m(const Cell* __restrict__ cells, int c0,
                                                      real* __restrict__ mom) {
-  constexpr int N = ncoef(P);
-  constexpr MultiIndex<P> T{};
-  constexpr Binom<P> B{};
   const int c = c0 + blockIdx.x;
   const Cell cl = cells[c];
   if (cl.nchild == 0) return;
-  for (int k = threadIdx.x; k < N; k += kP2MThreads) {
-    const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
-    real ms = 0, md = 0;
-    for (int ch = cl.child; ch < cl.child + cl.nchild; ++ch) {
-      const Cell cc = cells[ch];
-      const real d[3] = {(real)(cc.cx - cl.cx), (real)(cc.cy - cl.cy), (real)(cc.cz - cl.cz)};
-      real pw[3][P + 1];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        real v = 1;
-#pragma unroll
-        for (int e = 0; e <= P; ++e) {
-          pw[a][e] = v;
-          v *= d[a];
-        }
-      }
-      const real* M = mom + (size_t)ch * 2 * N;
-      for (int j1 = 0; j1 <= k1; ++j1)
-        for (int j2 = 0; j2 <= k2; ++j2)
-          for (int j3 = 0; j3 <= k3; ++j3) {
-            const real coef = real(B.c[k1][j1] * B.c[k2][j2] * B.c[k3][j3]) * pw[0][k1 - j1] *
-                              pw[1][k2 - j2] * pw[2][k3 - j3];
-            const int j = mindex(j1, j2, j3);
-            ms += coef * M[j];
-            md += coef * M[N + j];
-          }
-    }
-    mom[(size_t)c * 2 * N + k] = ms;
-    mom[(size_t)c * 2 * N + N + k] = md;
-  }
+  m2m_cell<real, P>(cells, cl, c, mom);
 }
 
 // ------------------------------------------------------------------- p2p
@@ -269,22 +225,15 @@ __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __
     const int c = uni(a.cells_list[e]);
     const int beg = uni(a.cells[c].begin), end = beg + uni(a.cells[c].count);
     int j = beg;
-    if (j + 1 < end) {
-      // two sources per step; the next two are loaded before the current
-      // two are used, so scalar-load latency overlaps the arithmetic
-      Src<real> s0 = src[j], s1 = src[j + 1];
-      for (; j + 3 < end; j += 2) {
-        const Src<real> n0 = src[j + 2], n1 = src[j + 3];
-        pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
-        pair<real, KS>(x, y, z, s1, k0, k1, a0, a1, acc);
-        s0 = n0;
-        s1 = n1;
-      }
+    // four sources per step: their scalar loads are issued together
+    for (; j + 3 < end; j += 4) {
+      const Src<real> s0 = src[j], s1 = src[j + 1], s2 = src[j + 2], s3 = src[j + 3];
       pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
       pair<real, KS>(x, y, z, s1, k0, k1, a0, a1, acc);
-      j += 2;
+      pair<real, KS>(x, y, z, s2, k0, k1, a0, a1, acc);
+      pair<real, KS>(x, y, z, s3, k0, k1, a0, a1, acc);
     }
-    if (j < end) {
+    for (; j < end; ++j) {
       const Src<real> s0 = src[j];
       pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
     }
@@ -431,7 +380,7 @@ static int launch_moments(pbtc_plan& pl, hipStream_t st, real* mom, const Src<re
     for (int l = pl.n_levels - 1; l >= 0; --l) {                                             \
       const int lb = pl.level_begin[l], le = pl.level_begin[l + 1];                          \
       if (le > lb)                                                                           \
-        hipLaunchKernelGGL((k_m2m<real, PP>), dim3(le - lb), dim3(kP2MThreads), 0, st, cells, \
+        hipLaunchKernelGGL((k_m2m<real, PP>), dim3(le - lb), dim3(kM2MThreads), 0, st, cells, \
                            lb, mom);                                                         \
     }                                                                                        \
     break;
@@ -659,6 +608,7 @@ int upload_descriptors(pbtc_plan& pl, hipStream_t st) {
     d.aout1 = pl.blk_aout1[i];
     d.csc_off = pl.blk_csc_off[i];
     d.slot0 = (int)pl.blk_slot0[i];
+    d.lslot0 = pl.blk_lslot0.empty() ? 0 : pl.blk_lslot0[i];
     d.troot = b.t;  // the target-set trees have one root per target set, in order
   }
   PBTC_HIP(hipMemcpyAsync(wsp<DevBlock>(pl, pl.o_blocks), db.data(), sizeof(DevBlock) * db.size(),

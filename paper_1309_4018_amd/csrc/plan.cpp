@@ -346,6 +346,19 @@ int build_plan(pbtc_plan& pl) {
   for (int ph = 0; ph < 2; ++ph)
     for (int ks = 0; ks < KS_COUNT; ++ks) pl.aitem_list[ph][ks].clear();
   int64_t nslot = 0, aout = 0, aitems = 0, ncsc = 0;
+  // transposed moments live per cell of a target-set tree, one record per
+  // kernel slot of the blocks on that tree: local slot numbers per tree
+  pl.blk_lslot0.assign(nb, 0);
+  {
+    std::vector<int> per_tree(pl.tsets.size(), 0);
+    pl.adj_ms = 1;
+    for (size_t bi = 0; bi < nb; ++bi) {
+      const Block& b = pl.blocks[bi];
+      pl.blk_lslot0[bi] = per_tree[b.t];
+      per_tree[b.t] += b.nk;
+      pl.adj_ms = std::max(pl.adj_ms, per_tree[b.t]);
+    }
+  }
   for (size_t bi = 0; bi < nb; ++bi) {
     const Block& b = pl.blocks[bi];
     const int64_t ngs = pl.gp_off[b.s + 1] - pl.gp_off[b.s];
@@ -480,6 +493,8 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_pidx = L.add(8 * pl.np_tot);
   pl.o_pinv = L.add(8 * 4 * pl.np_tot);
   pl.o_ptab = L.add(8 * 3 * pl.nsurf);
+  pl.o_flags = L.add(4 * 16);
+  pl.o_qtab = L.add(8 * (2 * pl.nreg + 1));
   pl.o_nx = L.add(8 * pl.np_tot);
   pl.o_ny = L.add(8 * pl.np_tot);
   pl.o_nz = L.add(8 * pl.np_tot);
@@ -548,6 +563,7 @@ void compute_layout(pbtc_plan& pl) {
                          (size_t)(m + 2) * 1024));
   pl.o_phi_reac = L.add(8 * std::max<int64_t>(pl.nq, 1));
   pl.o_energy = L.add(8 * (pl.ncomp + 64));
+  pl.o_coul = L.add(8 * (pl.ncomp + 1));
   pl.o_z2 = L.add(8 * std::max<int64_t>(n, pl.nq));
   pl.o_comp_of_unk = L.add(4 * n);
   pl.o_chunks = L.add(16 * std::max<size_t>(pl.dot_chunks.size(), 1) + 4 * (pl.ncomp + 1));
@@ -584,6 +600,7 @@ void compute_layout(pbtc_plan& pl) {
     for (int ph = 0; ph < 2; ++ph) {
       pl.o_adj_blist[ph] = L.add(4 * std::max<size_t>(pl.blocks.size(), 1));
       pl.o_adj_sids[ph] = L.add(4 * std::max<int64_t>(ns, 1));
+      pl.o_adj_tslot[ph] = L.add(4 * std::max<int64_t>((int64_t)pl.tsets.size() * pl.adj_ms, 1));
     }
     pl.o_adj_tab = L.add(8 * 2 * (pl.nsurf + 1));
   }
@@ -616,8 +633,8 @@ void compute_layout(pbtc_plan& pl) {
   for (const Block& b : pl.blocks) nslot += b.nk;
   pl.o_tcells = L.add(sizeof(Cell) * pl.cap_tcells);
   pl.o_tcnt = L.add(8 * (pl.cap_tcells + 1));
-  pl.o_amom32 = L.add(4 * 2 * nP * pl.cap_tcells * nslot);
-  pl.o_amom64 = L.add(8 * 2 * nP * pl.cap_tcells * nslot);
+  pl.o_amom32 = L.add(4 * 2 * nP * pl.cap_tcells * pl.adj_ms);
+  pl.o_amom64 = L.add(8 * 2 * nP * pl.cap_tcells * pl.adj_ms);
   pl.o_anear = L.add(4 * pl.cap_anear);
   pl.o_units = L.add(16 * pl.cap_units);
   pl.o_uptr = L.add(4 * (2 * pl.nitems + 64));

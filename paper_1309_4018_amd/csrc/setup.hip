@@ -22,6 +22,7 @@
 #include <cmath>
 
 #include "device_util.h"
+#include "traverse.h"
 #include "taylor.h"
 
 namespace pbtc {
@@ -316,56 +317,33 @@ __global__ __launch_bounds__(256) void k_cell_radius(Cell* __restrict__ cells, i
 namespace {
 
 // -------------------------------------------------------------------- lists
-constexpr int kStack = 8 * kMaxLevels + 16;
-
-// One thread per (block, group) item.  mode 0: count, mode 1: fill.
-__global__ void k_lists(int64_t nitems, const int* __restrict__ item_block,
-                        const DevBlock* __restrict__ blocks, const Cell* __restrict__ cells,
-                        const double* __restrict__ grp, double theta, int direct, int direct_below,
-                        int mode, long long* __restrict__ near_ptr, long long* __restrict__ far_ptr,
-                        int* __restrict__ near, int* __restrict__ far, long long cap_near,
-                        long long cap_far) {
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per (block, group) item.  mode 0: count, mode 1: fill.
+__global__ __launch_bounds__(64 * kTravWaves) void k_lists(
+    int64_t nitems, const int* __restrict__ item_block, const DevBlock* __restrict__ blocks,
+    const Cell* __restrict__ cells, const double* __restrict__ grp, double theta, int direct,
+    int direct_below, int mode, long long* __restrict__ near_ptr, long long* __restrict__ far_ptr,
+    int* __restrict__ near, int* __restrict__ far, long long cap_near, long long cap_far,
+    int* __restrict__ overflow) {
+  __shared__ int stk[kTravWaves][kTravStack];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * kTravWaves + w;
   if (it >= nitems) return;
-  const DevBlock b = blocks[item_block[it]];
+  const DevBlock& b = blocks[item_block[it]];
   const int64_t g = b.grp_off + (it - b.item_off);
-  const double gxc = grp[4 * g], gyc = grp[4 * g + 1], gzc = grp[4 * g + 2], gr = grp[4 * g + 3];
-  long long nn = 0, nf = 0;
-  long long pn = 0, pf = 0;
+  long long pn = 0, pf = 0, nn = 0, nf = 0;
   if (mode == 1) {
     pn = near_ptr[it];
     pf = far_ptr[it];
   }
   if (direct) {
-    if (mode == 1 && pn < cap_near) near[pn] = b.root;
+    if (mode == 1 && lane == 0 && pn < cap_near) near[pn] = b.root;
     nn = 1;
   } else {
-    int stack[kStack];
-    int sp = 0;
-    stack[sp++] = b.root;
-    while (sp > 0) {
-      const int c = stack[--sp];
-      const Cell cl = cells[c];
-      if (cl.count == 0) continue;
-      const double dx = gxc - cl.cx, dy = gyc - cl.cy, dz = gzc - cl.cz;
-      const double rtb = sqrt(dx * dx + dy * dy + dz * dz) - gr;
-      if (theta * rtb > cl.rb) {
-        if (cl.count < direct_below) {
-          if (mode == 1 && pn + nn < cap_near) near[pn + nn] = c;
-          ++nn;
-        } else {
-          if (mode == 1 && pf + nf < cap_far) far[pf + nf] = c;
-          ++nf;
-        }
-      } else if (cl.nchild == 0) {
-        if (mode == 1 && pn + nn < cap_near) near[pn + nn] = c;
-        ++nn;
-      } else {
-        for (int k = cl.nchild - 1; k >= 0 && sp < kStack; --k) stack[sp++] = cl.child + k;
-      }
-    }
+    wave_lists(cells, b.root, grp[4 * g], grp[4 * g + 1], grp[4 * g + 2], grp[4 * g + 3], theta,
+               direct_below, mode, pn, pf, near, far, cap_near, cap_far, stk[w], &nn, &nf,
+               overflow);
   }
-  if (mode == 0) {
+  if (mode == 0 && lane == 0) {
     near_ptr[it] = nn;
     far_ptr[it] = nf;
   }
@@ -406,48 +384,54 @@ __device__ __forceinline__ void target_point(const NearArgs& a, const DevBlock& 
   }
 }
 
-// One thread per near-field row.  mode 0: count, mode 1: fill columns.
-__global__ void k_near_rows(NearArgs a, int64_t nrows, int mode, long long* __restrict__ ptr,
-                            int* __restrict__ col, long long cap) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= nrows) return;
-  const int bi = (int)a.nf_row_block[row];
-  const DevBlock b = a.blocks[bi];
-  const int64_t i = row - b.nf_row;
-  double x, y, z;
-  int64_t self_pan;
-  target_point(a, b, i, x, y, z, self_pan);
-  const double R = a.reach[b.s];
-  long long n = 0, base = mode == 1 ? ptr[row] : 0;
-  int stack[kStack];
-  int sp = 0;
-  stack[sp++] = b.root;
-  while (sp > 0) {
-    const Cell cl = a.cells[stack[--sp]];
-    if (cl.count == 0) continue;
-    const double dx = x - cl.cx, dy = y - cl.cy, dz = z - cl.cz;
-    const double d = sqrt(dx * dx + dy * dy + dz * dz);
-    if (d - cl.rb > R) continue;
-    if (cl.nchild > 0) {
-      for (int k = cl.nchild - 1; k >= 0 && sp < kStack; --k) stack[sp++] = cl.child + k;
-      continue;
-    }
-    for (int j = cl.begin; j < cl.begin + cl.count; ++j) {
+// Near-field columns of every row: the panels j with |x - centre_j| <
+// thres * L_j, plus the target's own panel.  One wavefront per (block, group)
+// item, a lane per target: the wave walks the leaves that may hold such a
+// panel for some target of the group and tests every panel of each leaf (its
+// first Gauss point stands for it) against all 64 targets at once.
+// mode 0: count per row, mode 1: fill columns.
+__global__ __launch_bounds__(64 * kTravWaves) void k_near_rows(
+    NearArgs a, int64_t nitems, const int* __restrict__ item_block, const double* __restrict__ grp,
+    const int* __restrict__ tidx, int mode, long long* __restrict__ ptr, int* __restrict__ col,
+    long long cap, int* __restrict__ overflow) {
+  __shared__ int stk[kTravWaves][kTravStack];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * kTravWaves + w;
+  if (it >= nitems) return;
+  const DevBlock& b = a.blocks[item_block[it]];
+  const int64_t g = it - b.item_off;
+  const int64_t gg = b.grp_off + g;
+  const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
+  const bool active = lane < nt;
+  int64_t i = 0;
+  double x = 0, y = 0, z = 0;
+  int64_t self_pan = -1;
+  if (active) {
+    i = tidx[b.tgt_off + g * kGroup + lane] - b.tgt_off;
+    target_point(a, b, i, x, y, z, self_pan);
+  }
+  const long long row = b.nf_row + i;
+  long long n = 0;
+  const long long base = (mode == 1 && active) ? ptr[row] : 0;
+  const long long gp0 = a.gp_first[b.s];
+  wave_leaves_within(a.cells, b.root, grp[4 * gg], grp[4 * gg + 1], grp[4 * gg + 2],
+                     grp[4 * gg + 3], a.reach[b.s], stk[w], overflow, [&](int leaf) {
+    const int beg = __builtin_amdgcn_readfirstlane(a.cells[leaf].begin);
+    const int end = beg + __builtin_amdgcn_readfirstlane(a.cells[leaf].count);
+    for (int j = beg; j < end; ++j) {
       const int og = a.gidx[j];
-      if ((og - a.gp_first[b.s]) % a.K != 0) continue;  // one test per panel
+      if ((og - gp0) % a.K != 0) continue;  // one test per panel
       const int p = a.gpid[j];
-      bool take = (p == self_pan);
-      if (!take) {
-        const double ex = x - a.cx[p], ey = y - a.cy[p], ez = z - a.cz[p];
-        take = ex * ex + ey * ey + ez * ez < (a.thres * a.len[p]) * (a.thres * a.len[p]);
-      }
+      const double ex = x - a.cx[p], ey = y - a.cy[p], ez = z - a.cz[p];
+      const double lim = a.thres * a.len[p];
+      const bool take = active && (p == self_pan || ex * ex + ey * ey + ez * ez < lim * lim);
       if (take) {
         if (mode == 1 && base + n < cap) col[base + n] = p;
         ++n;
       }
     }
-  }
-  if (mode == 0) ptr[row] = n;
+  });
+  if (mode == 0 && active) ptr[row] = n;
 }
 
 struct Tables {
@@ -915,10 +899,12 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   long long* near_ptr = wsp<long long>(pl, pl.o_near_ptr);
   long long* far_ptr = wsp<long long>(pl, pl.o_far_ptr);
   int* item_block = wsp<int>(pl, pl.o_items);
-  hipLaunchKernelGGL(k_lists, dim3(nblocks(pl.nitems, 64)), dim3(64), 0, st, pl.nitems, item_block,
-                     wsp<DevBlock>(pl, pl.o_blocks), cells, wsp<double>(pl, pl.o_grp),
-                     pl.prm.theta, direct, pl.direct_below, 0, near_ptr, far_ptr, (int*)nullptr,
-                     (int*)nullptr, (long long)0, (long long)0);
+  int* flags = wsp<int>(pl, pl.o_flags);
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, flags, (int64_t)16, 0);
+  hipLaunchKernelGGL(k_lists, dim3(nblocks(pl.nitems, kTravWaves)), dim3(64 * kTravWaves), 0, st,
+                     pl.nitems, item_block, wsp<DevBlock>(pl, pl.o_blocks), cells,
+                     wsp<double>(pl, pl.o_grp), pl.prm.theta, direct, pl.direct_below, 0, near_ptr,
+                     far_ptr, (int*)nullptr, (int*)nullptr, (long long)0, (long long)0, flags);
   PBTC_LAUNCH_CHECK();
   scan_exclusive<long long>(near_ptr, pl.nitems, scan_scratch, st);
   scan_exclusive<long long>(far_ptr, pl.nitems, scan_scratch, st);
@@ -935,19 +921,20 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   }
   pl.n_near = tot[0];
   pl.n_far = tot[1];
-  hipLaunchKernelGGL(k_lists, dim3(nblocks(pl.nitems, 64)), dim3(64), 0, st, pl.nitems, item_block,
-                     wsp<DevBlock>(pl, pl.o_blocks), cells, wsp<double>(pl, pl.o_grp),
-                     pl.prm.theta, direct, pl.direct_below, 1, near_ptr, far_ptr,
-                     wsp<int>(pl, pl.o_near), wsp<int>(pl, pl.o_far), (long long)pl.cap_near,
-                     (long long)pl.cap_far);
+  hipLaunchKernelGGL(k_lists, dim3(nblocks(pl.nitems, kTravWaves)), dim3(64 * kTravWaves), 0, st,
+                     pl.nitems, item_block, wsp<DevBlock>(pl, pl.o_blocks), cells,
+                     wsp<double>(pl, pl.o_grp), pl.prm.theta, direct, pl.direct_below, 1, near_ptr,
+                     far_ptr, wsp<int>(pl, pl.o_near), wsp<int>(pl, pl.o_far), (long long)pl.cap_near,
+                     (long long)pl.cap_far, flags);
   PBTC_LAUNCH_CHECK();
 
   // ---- near-field correction tables
   NearArgs na;
   near_args(pl, &na);
   long long* nf_ptr = wsp<long long>(pl, pl.o_nf_ptr);
-  hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nf_rows, 64)), dim3(64), 0, st, na, pl.nf_rows, 0,
-                     nf_ptr, (int*)nullptr, (long long)0);
+  hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nitems, kTravWaves)), dim3(64 * kTravWaves), 0,
+                     st, na, pl.nitems, item_block, wsp<double>(pl, pl.o_grp),
+                     wsp<int>(pl, pl.o_tidx), 0, nf_ptr, (int*)nullptr, (long long)0, flags);
   PBTC_LAUNCH_CHECK();
   scan_exclusive<long long>(nf_ptr, pl.nf_rows, scan_scratch, st);
   long long nnz = 0;
@@ -960,9 +947,20 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     return PBTC_EWORKSPACE;
   }
   pl.n_nf = nnz;
-  hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nf_rows, 64)), dim3(64), 0, st, na, pl.nf_rows, 1,
-                     nf_ptr, wsp<int>(pl, pl.o_nf_col), (long long)pl.cap_nf);
+  hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nitems, kTravWaves)), dim3(64 * kTravWaves), 0,
+                     st, na, pl.nitems, item_block, wsp<double>(pl, pl.o_grp),
+                     wsp<int>(pl, pl.o_tidx), 1, nf_ptr, wsp<int>(pl, pl.o_nf_col),
+                     (long long)pl.cap_nf, flags);
   PBTC_LAUNCH_CHECK();
+  {
+    int hflag = 0;
+    PBTC_HIP(hipMemcpyAsync(&hflag, flags, 4, hipMemcpyDeviceToHost, st));
+    PBTC_HIP(hipStreamSynchronize(st));
+    if (hflag) {
+      pl.err = "tree traversal stack exhausted (octree too deep)";
+      return PBTC_EDEVICE;
+    }
+  }
   rc = recompute_near_values(pl, st);
   if (rc) return rc;
   rc = recompute_precond(pl, st);

@@ -79,6 +79,8 @@ _EXPORTS = {
                                         C.c_void_p, C.c_int]),
     "pbtc_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_int]),
+    "pbtc_coulomb_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
     "pbtc_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pbtc_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_double,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Result)]),
@@ -335,6 +337,24 @@ class Plan:
                                           C.c_void_p(xd.data_ptr()), C.c_void_p(yd.data_ptr()),
                                           int(bool(transpose))), self.h)
         return yd
+
+    def coulomb_energy(self):
+        """(total, per system) Coulomb energy of the charges, kJ/mol."""
+        n = C.c_int()
+        check(self.lib.pbtc_get_systems(self.h, C.byref(n), None, None, None), self.h)
+        per = np.empty(max(n.value, 1))
+        tot = C.c_double()
+
+        def call():
+            return self.lib.pbtc_coulomb_energy(self.h, C.c_void_p(self.ws.data_ptr()),
+                                                self.stream, C.byref(tot), _ptr(per))
+
+        code = call()
+        if code == EINVAL:  # not set up on this workspace yet
+            self.setup()
+            code = call()
+        check(code, self.h)
+        return tot.value, per[:n.value]
 
     def rhs(self):
         torch = self.torch

@@ -27,6 +27,8 @@ from .configs import (
     config4_batch,
     config5_small,
     concentric_spheres,
+    born_pair,
+    star_pair,
 )
 
 __all__ = [
@@ -48,4 +50,6 @@ __all__ = [
     "config4_batch",
     "config5_small",
     "concentric_spheres",
+    "born_pair",
+    "star_pair",
 ]

@@ -192,3 +192,69 @@ def concentric_spheres(radii, eps, kappa, charges, charge_region, nu=16, base="o
         v, f = geodesic_sphere(base, nu, a)
         surfaces.append(Surface(v, f, i, i + 1, f"sphere{i}"))
     return Problem(regions, surfaces, {charge_region: charges}, name="concentric")
+
+
+def _translated(v, offset):
+    return np.asarray(v, dtype=np.float64) + np.asarray(offset, dtype=np.float64)[None, :]
+
+
+def _pair(rec, lig, name):
+    """Complex of two single-surface molecules sharing the outer region.
+
+    ``rec`` and ``lig`` are one-surface problems (region 0 inside, region 1
+    outside, charges in region 0) with the same solvent.  The complex has
+    regions [receptor interior, ligand interior, solvent].
+    """
+    sa, sb = rec.surfaces[0], lig.surfaces[0]
+    ra, rb, rs = rec.regions[0], lig.regions[0], rec.regions[1]
+    cplx = Problem(
+        regions=[Region(ra.eps, ra.kappa, "receptor"), Region(rb.eps, rb.kappa, "ligand"),
+                 Region(rs.eps, rs.kappa, "solvent")],
+        surfaces=[Surface(sa.verts, sa.tris, 0, 2, "receptor"),
+                  Surface(sb.verts, sb.tris, 1, 2, "ligand")],
+        charges={0: rec.charges[0], 1: lig.charges[0]},
+        name=name,
+    )
+    return cplx, rec, lig
+
+
+def born_pair(distance, radius=2.0, q=(1.0, -1.0), nu=8, base="oct", eps_in=4.0,
+              eps_out=80.0, kappa=0.0):
+    """Two Born ions (spheres of ``radius`` with a central charge each) whose
+    centres are ``distance`` apart along x: (complex, receptor, ligand)."""
+    rec = born_sphere(nu, base, radius, eps_in, eps_out, kappa,
+                      (np.zeros((1, 3)), np.array([q[0]], dtype=np.float64)))
+    v, f = geodesic_sphere(base, nu, radius, center=(distance, 0.0, 0.0))
+    lig = Problem(
+        regions=[Region(eps_in, 0.0, "molecule"), Region(eps_out, kappa, "solvent")],
+        surfaces=[Surface(v, f, 0, 1, "sphere")],
+        charges={0: (np.array([[distance, 0.0, 0.0]]), np.array([q[1]], dtype=np.float64))},
+        name="born-ligand",
+    )
+    return _pair(rec, lig, f"born-pair-{distance:g}")
+
+
+def star_pair(gap=4.0, r_rec=14.0, r_lig=9.0, nu_rec=24, nu_lig=16, n_rec=600, n_lig=200,
+              seed=6, kappa=0.125):
+    """Receptor and ligand star-shaped molecules (seeded as the star
+    workload) placed along x with at least ``gap`` angstrom between their
+    surfaces: (complex, receptor, ligand)."""
+    out = []
+    for r0, nu, nq, s in ((r_rec, nu_rec, n_rec, seed), (r_lig, nu_lig, n_lig, seed + 1)):
+        shape = StarShape(r0, s)
+        v, f = star_surface(shape, nu, "ico")
+        x, q = star_interior_charges(shape, nq, s, clearance=2.0)
+        out.append((v, f, x, q))
+    ra = float(np.max(np.linalg.norm(out[0][0], axis=1)))
+    rb = float(np.max(np.linalg.norm(out[1][0], axis=1)))
+    off = np.array([ra + rb + gap, 0.0, 0.0])
+    probs = []
+    for k, (v, f, x, q) in enumerate(out):
+        shift = off if k == 1 else np.zeros(3)
+        probs.append(Problem(
+            regions=[Region(4.0, 0.0, "protein"), Region(80.0, kappa, "solvent")],
+            surfaces=[Surface(_translated(v, shift), f, 0, 1, "SES")],
+            charges={0: (_translated(x, shift), q)},
+            name=("receptor", "ligand")[k],
+        ))
+    return _pair(probs[0], probs[1], "star-pair")

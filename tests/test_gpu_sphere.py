@@ -68,13 +68,15 @@ def test_treecode_matvec_truncation(c1, gpu_lib):
 
     prob, o, sol, x, y = c1
     errs = {}
-    for P in (2, 4, 6, 8):
+    for P in (2, 4, 6, 8, 10):
         pl = _plan(prob, op="treecode", theta=0.5, P=P, ncrit=64)
         errs[P] = _rel(pl.matvec(x, lib.FP64).cpu().numpy(), y)
         e32 = _rel(pl.matvec(x, lib.FP32).cpu().numpy(), y)
         assert e32 < errs[P] + 3e-5
-    assert errs[4] < 2e-3 and errs[6] < 2e-4
-    assert errs[8] < errs[6] < errs[4] < errs[2]
+    # P >= 8 has more Taylor coefficients (165, 286) than threads per moment
+    # block: every one of them must be formed
+    assert errs[4] < 2e-3 and errs[6] < 2e-4 and errs[8] < 0.6 * errs[6]
+    assert errs[10] < errs[8] < errs[6] < errs[4] < errs[2]
 
 
 def test_treecode_tiny_theta_equals_direct(c1, gpu_lib):
