@@ -411,57 +411,25 @@ template <int P, typename real, int KIND>
 __device__ __forceinline__ void taylor_adj(real dx, real dy, real dz, real rinv, real e,
                                            real kappa, real nx, real ny, real nz,
                                            const real* __restrict__ M, real& s, real& f) {
-  constexpr MultiIndex<P + 1> T{};
   constexpr int N1 = MultiIndex<P + 1>::N;
   constexpr int N = ncoef(P);
   const real r2inv = rinv * rinv;
   real a[N1], bb[KIND ? N1 : 1];
   a[0] = KIND ? e * rinv : rinv;
-  if (KIND) bb[0] = e;
+  if constexpr (KIND) bb[0] = e;
   s += a[0] * M[0];
-#pragma unroll
-  for (int k = 1; k < N1; ++k) {
-    const int n = T.n[k];
-    real s1 = real(0), s2 = real(0), t1 = real(0), t2 = real(0);
-    if (T.m1[k][0] >= 0) {
-      s1 += dx * a[T.m1[k][0]];
-      if (KIND) t1 += dx * bb[T.m1[k][0]];
-    }
-    if (T.m1[k][1] >= 0) {
-      s1 += dy * a[T.m1[k][1]];
-      if (KIND) t1 += dy * bb[T.m1[k][1]];
-    }
-    if (T.m1[k][2] >= 0) {
-      s1 += dz * a[T.m1[k][2]];
-      if (KIND) t1 += dz * bb[T.m1[k][2]];
-    }
-    if (T.m2[k][0] >= 0) {
-      s2 += a[T.m2[k][0]];
-      if (KIND) t2 += bb[T.m2[k][0]];
-    }
-    if (T.m2[k][1] >= 0) {
-      s2 += a[T.m2[k][1]];
-      if (KIND) t2 += bb[T.m2[k][1]];
-    }
-    if (T.m2[k][2] >= 0) {
-      s2 += a[T.m2[k][2]];
-      if (KIND) t2 += bb[T.m2[k][2]];
-    }
-    const real inv_n = real(1) / real(n);
-    const real c1 = real(2 * n - 1) / real(n), c2 = real(n - 1) / real(n);
-    if (KIND) {
-      bb[k] = kappa * inv_n * (s1 - s2);
-      a[k] = (c1 * s1 - c2 * s2 + kappa * inv_n * (t1 - t2)) * r2inv;
-    } else {
-      a[k] = (c1 * s1 - c2 * s2) * r2inv;
-    }
-    if (n <= P) s += a[k] * M[k];
+  static_for<N1 - 1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value + 1;
+    constexpr MultiIndex<P + 1> T{};
+    coef_step<P + 1, k, KIND != 0, real>(a, KIND ? bb : a, dx, dy, dz, r2inv, kappa);
+    if constexpr (T.n[k] <= P) s += a[k] * M[k];
+    constexpr int j0 = T.m1[k][0], j1 = T.m1[k][1], j2 = T.m1[k][2];
     real g = real(0);
-    if (T.m1[k][0] >= 0) g += nx * real(T.k1[k]) * M[N + T.m1[k][0]];
-    if (T.m1[k][1] >= 0) g += ny * real(T.k2[k]) * M[N + T.m1[k][1]];
-    if (T.m1[k][2] >= 0) g += nz * real(T.k3[k]) * M[N + T.m1[k][2]];
+    if constexpr (j0 >= 0) g += nx * real(T.k1[k]) * M[N + j0];
+    if constexpr (j1 >= 0) g += ny * real(T.k2[k]) * M[N + j1];
+    if constexpr (j2 >= 0) g += nz * real(T.k3[k]) * M[N + j2];
     f -= a[k] * g;
-  }
+  });
 }
 
 template <typename real, int P, int KIND>

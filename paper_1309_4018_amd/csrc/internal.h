@@ -20,6 +20,8 @@ constexpr int kMaxP = 10;
 constexpr int kGroup = 64;       // targets per target group (one wavefront)
 constexpr int kMaxLevels = 21;   // 63-bit Morton keys, 21 bits per axis
 constexpr int kMaxNk = 32;
+constexpr int kMomChunk = 128;   // sources staged at a time by the direct moment pass
+constexpr int kMomSpan = 1024;   // sources per block of the direct moment pass
 constexpr int kMaxRule = 19;
 
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
@@ -208,6 +210,8 @@ struct pbtc_plan {
   size_t o_flags = 0;  // device status flags (16 int)
   size_t o_qtab = 0;   // per region: first charge (nreg + 1 long long), eps (nreg double)
   size_t o_coul = 0;   // Coulomb energy per system (ncomp double)
+  size_t o_mchunks = 0, o_mcell = 0, o_mpart = 0;  // direct moment pass: chunks, per-cell chunk ranges, partial moments
+  int64_t cap_mchunks = 0, n_mchunks = 0;
   std::vector<double> ptab_host;  // host copy of the o_ptab table
   std::vector<double> qtab_host;  // host copy of the o_qtab table
   size_t o_tx, o_ty, o_tz, o_tidx;                               // sorted targets (FP64) + perm

@@ -11,33 +11,21 @@
 
 namespace pbtc {
 
-template <int P>
-struct Binomial {
-  int c[P + 1][P + 1];
-  constexpr Binomial() : c() {
-    for (int n = 0; n <= P; ++n) {
-      c[n][0] = 1;
-      for (int k = 1; k <= n; ++k) c[n][k] = c[n - 1][k - 1] + (k <= n - 1 ? c[n - 1][k] : 0);
-    }
-  }
-};
-
 constexpr int kM2MThreads = 256;
 
 // One work-group (kM2MThreads) per parent cell cl (index c) with 1..8
-// children in consecutive cells.  The children's moment records and the
-// powers of their shifts are staged in LDS; work items are (coefficient,
-// child) pairs, and the children are summed in a fixed order (deterministic).
+// children in consecutive cells.  The children's moment records and, per
+// child and axis, the factors C(k, j) d^(k - j) (k, j <= P) are staged in
+// LDS, so the inner loops read LDS only; work items are (coefficient, child)
+// pairs, and the children are summed in a fixed order (deterministic).
 // The record of cell i (2 N values) is at mom + i * stride.
 template <typename real, int P>
 __device__ __forceinline__ void m2m_cell(const Cell* __restrict__ cells, const Cell& cl, int c,
                                          real* __restrict__ mom, size_t stride = 2 * ncoef(P)) {
   constexpr int N = ncoef(P);
   constexpr int KPT = (8 * N + kM2MThreads - 1) / kM2MThreads;
-  constexpr MultiIndex<P> T{};
-  constexpr Binomial<P> B{};
   __shared__ real sm[8][2 * N];
-  __shared__ real pw[8][3][P + 1];
+  __shared__ real sh[8][3][P + 1][P + 1];
   const int nch = min(cl.nchild, 8);
   const int tid = threadIdx.x;
   for (int i = tid; i < nch * 2 * N; i += kM2MThreads)  // children are consecutive cells
@@ -47,10 +35,18 @@ __device__ __forceinline__ void m2m_cell(const Cell* __restrict__ cells, const C
     const Cell& cc = cells[cl.child + ch];
     const double dd = a == 0 ? cc.cx - cl.cx : (a == 1 ? cc.cy - cl.cy : cc.cz - cl.cz);
     const real d = (real)dd;
-    real v = 1;
-    for (int e = 0; e <= P; ++e) {
-      pw[ch][a][e] = v;
-      v *= d;
+    real pw[P + 1];
+    pw[0] = real(1);
+#pragma unroll
+    for (int e = 1; e <= P; ++e) pw[e] = pw[e - 1] * d;
+#pragma unroll
+    for (int k = 0; k <= P; ++k) {
+      real cb = real(1);  // C(k, j), exact: C(k, j + 1) = C(k, j) (k - j) / (j + 1)
+#pragma unroll
+      for (int j = 0; j <= k; ++j) {
+        sh[ch][a][k][j] = cb * pw[k - j];
+        cb = cb * real(k - j) / real(j + 1);
+      }
     }
   }
   __syncthreads();
@@ -61,17 +57,20 @@ __device__ __forceinline__ void m2m_cell(const Cell* __restrict__ cells, const C
     const int item = tid + q * kM2MThreads;
     const int ch = item / N, k = item - (item / N) * N;
     if (ch < nch) {
-      const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
-      for (int j1 = 0; j1 <= k1; ++j1)
+      int k1, k2, k3;
+      mindex_inv(k, k1, k2, k3);
+      for (int j1 = 0; j1 <= k1; ++j1) {
+        const real x1 = sh[ch][0][k1][j1];
         for (int j2 = 0; j2 <= k2; ++j2) {
-          const real c12 = real(B.c[k1][j1] * B.c[k2][j2]) * pw[ch][0][k1 - j1] * pw[ch][1][k2 - j2];
+          const real x12 = x1 * sh[ch][1][k2][j2];
           for (int j3 = 0; j3 <= k3; ++j3) {
-            const real coef = c12 * real(B.c[k3][j3]) * pw[ch][2][k3 - j3];
+            const real coef = x12 * sh[ch][2][k3][j3];
             const int j = mindex(j1, j2, j3);
             ps[q] += coef * sm[ch][j];
             pd[q] += coef * sm[ch][N + j];
           }
         }
+      }
     }
   }
   __syncthreads();

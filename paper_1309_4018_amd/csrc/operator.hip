@@ -22,7 +22,6 @@
 
 #include "device_util.h"
 #include "kernel_common.h"
-#include "moments.h"
 #include "taylor.h"
 
 namespace pbtc {
@@ -54,85 +53,122 @@ __global__ void k_prep(int64_t ngp, const double* __restrict__ gx, const double*
   src[j] = s;
 }
 
-// -------------------------------------------------------------- p2m / m2m
-constexpr int kP2MThreads = 128;
+// ------------------------------------------------------------- moments
+// Moments of every cell directly from its own sources (Eq. multexp), at
+// every level of the tree: M_SL[k] = sum q (y - c)^k and
+// M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d) about the cell centre c.  A
+// cell's sources are consecutive in Morton order; one block takes a span of
+// at most kMomSpan of them (all spans of all levels in one launch), staged
+// through LDS kMomChunk at a time with the next batch loaded ahead, and a
+// second launch sums each cell's spans in span order (deterministic).  This
+// replaces the level-by-level upward shift: the same moments with no
+// dependence between levels.
+constexpr int kMomThreads = 256;
 
-// Moments of a leaf: M_SL[k] = sum q (y - c)^k,
-// M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d).  Thread i forms coefficients
-// i, i + kP2MThreads, ... (N_P exceeds the block size from P = 8 on).
 template <typename real, int P>
-__global__ __launch_bounds__(kP2MThreads) void k_p2m(const Cell* __restrict__ cells, int c0,
-                                                     const Src<real>* __restrict__ src,
-                                                     real* __restrict__ mom) {
+__global__ __launch_bounds__(kMomThreads) void k_p2m_chunk(const int4* __restrict__ chunks,
+                                                           const Cell* __restrict__ cells,
+                                                           const Src<real>* __restrict__ src,
+                                                           real* __restrict__ part) {
   constexpr int N = ncoef(P);
-  constexpr int KPT = (N + kP2MThreads - 1) / kP2MThreads;
-  constexpr MultiIndex<P> T{};
-  __shared__ real pw[kP2MThreads][3][P + 1];
-  __shared__ real sq[kP2MThreads][4];
-  const int c = c0 + blockIdx.x;
-  const Cell cl = cells[c];
-  if (cl.nchild != 0) return;
+  constexpr int G = N <= kMomThreads ? kMomThreads / N : 1;  // groups of sources
+  constexpr int KPT = (N + kMomThreads - 1) / kMomThreads;   // coefficients per thread
+  static_assert(kMomChunk <= kMomThreads, "one source per thread while staging");
+  __shared__ real pw[kMomChunk][3][P + 1];
+  __shared__ real sq[kMomChunk][4];
+  __shared__ real red[G][2 * N];
+  const int4 ch = chunks[blockIdx.x];  // (cell, first source, count)
+  const Cell& cl = cells[ch.x];
   const real cx = (real)cl.cx, cy = (real)cl.cy, cz = (real)cl.cz;
+  const int tid = threadIdx.x;
+  const int g = N <= kMomThreads ? tid / N : 0;
+  int kk[KPT][3];
+  bool on[KPT];
   real ms[KPT], md[KPT];
 #pragma unroll
-  for (int q = 0; q < KPT; ++q) ms[q] = md[q] = 0;
-  for (int base = cl.begin; base < cl.begin + cl.count; base += kP2MThreads) {
-    const int j = base + threadIdx.x;
-    const int nj = min(kP2MThreads, cl.begin + cl.count - base);
-    if (threadIdx.x < nj) {
-      const Src<real> s = src[j];
+  for (int q = 0; q < KPT; ++q) {
+    const int k = N <= kMomThreads ? tid - g * N : tid + q * kMomThreads;
+    on[q] = N <= kMomThreads ? tid < G * N : k < N;
+    mindex_inv(on[q] ? k : 0, kk[q][0], kk[q][1], kk[q][2]);
+    ms[q] = md[q] = 0;
+  }
+  Src<real> nxt;
+  if (tid < min(kMomChunk, ch.z)) nxt = src[ch.y + tid];
+  for (int b0 = 0; b0 < ch.z; b0 += kMomChunk) {
+    const int nj = min(kMomChunk, ch.z - b0);
+    if (tid < nj) {
+      const Src<real> s = nxt;
       const real d[3] = {s.x - cx, s.y - cy, s.z - cz};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         real v = 1;
 #pragma unroll
         for (int e = 0; e <= P; ++e) {
-          pw[threadIdx.x][a][e] = v;
+          pw[tid][a][e] = v;
           v *= d[a];
         }
       }
-      sq[threadIdx.x][0] = s.q;
-      sq[threadIdx.x][1] = s.px;
-      sq[threadIdx.x][2] = s.py;
-      sq[threadIdx.x][3] = s.pz;
+      sq[tid][0] = s.q;
+      sq[tid][1] = s.px;
+      sq[tid][2] = s.py;
+      sq[tid][3] = s.pz;
     }
     __syncthreads();
+    // the next batch is loaded while this one is used
+    if (b0 + kMomChunk + tid < ch.z && tid < kMomChunk) nxt = src[ch.y + b0 + kMomChunk + tid];
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
-      const int k = threadIdx.x + q * kP2MThreads;
-      if (k < N) {
-        const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
-        for (int t = 0; t < nj; ++t) {
-          const real X = pw[t][0][k1], Y = pw[t][1][k2], Z = pw[t][2][k3];
-          ms[q] += sq[t][0] * X * Y * Z;
-          real dl = 0;
-          if (k1) dl += sq[t][1] * real(k1) * pw[t][0][k1 - 1] * Y * Z;
-          if (k2) dl += sq[t][2] * real(k2) * X * pw[t][1][k2 - 1] * Z;
-          if (k3) dl += sq[t][3] * real(k3) * X * Y * pw[t][2][k3 - 1];
-          md[q] += dl;
-        }
+      if (!on[q]) continue;
+      const int k1 = kk[q][0], k2 = kk[q][1], k3 = kk[q][2];
+      for (int t = g; t < nj; t += G) {
+        const real X = pw[t][0][k1], Y = pw[t][1][k2], Z = pw[t][2][k3];
+        ms[q] += sq[t][0] * X * Y * Z;
+        real dl = 0;
+        if (k1) dl += sq[t][1] * real(k1) * pw[t][0][k1 - 1] * Y * Z;
+        if (k2) dl += sq[t][2] * real(k2) * X * pw[t][1][k2 - 1] * Z;
+        if (k3) dl += sq[t][3] * real(k3) * X * Y * pw[t][2][k3 - 1];
+        md[q] += dl;
       }
     }
     __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
-    const int k = threadIdx.x + q * kP2MThreads;
-    if (k < N) {
-      mom[(size_t)c * 2 * N + k] = ms[q];
-      mom[(size_t)c * 2 * N + N + k] = md[q];
-    }
+    if (!on[q]) continue;
+    const int k = N <= kMomThreads ? tid - g * N : tid + q * kMomThreads;
+    red[g][k] = ms[q];
+    red[g][N + k] = md[q];
+  }
+  __syncthreads();
+  for (int k = tid; k < 2 * N; k += kMomThreads) {
+    real v = 0;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) v += red[gg][k];
+    part[(size_t)blockIdx.x * 2 * N + k] = v;
   }
 }
 
-// Upward pass: parent moments from the children's (binomial shift).
+// mom[c] = sum of the spans of cell c, eight loads in flight per step, in a
+// fixed order (zero for an empty cell)
 template <typename real, int P>
-__global__ __launch_bounds__(kM2MThreads) void k_m2m(const Cell* __restrict__ cells, int c0,
-                                                     real* __restrict__ mom) {
-  const int c = c0 + blockIdx.x;
-  const Cell cl = cells[c];
-  if (cl.nchild == 0) return;
-  m2m_cell<real, P>(cells, cl, c, mom);
+__global__ __launch_bounds__(256) void k_mom_sum(const int* __restrict__ cell_chunk,
+                                                 const real* __restrict__ part,
+                                                 real* __restrict__ mom) {
+  constexpr int N2 = 2 * ncoef(P);
+  const int c = blockIdx.x;
+  const int c0 = cell_chunk[c], c1 = cell_chunk[c + 1];
+  for (int k = threadIdx.x; k < N2; k += 256) {
+    real v = 0;
+    int j = c0;
+    for (; j + 8 <= c1; j += 8) {
+      real a[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a[i] = part[(size_t)(j + i) * N2 + k];
+      v += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+    for (; j < c1; ++j) v += part[(size_t)j * N2 + k];
+    mom[(size_t)c * N2 + k] = v;
+  }
 }
 
 // ------------------------------------------------------------------- p2p
@@ -372,17 +408,16 @@ __global__ void k_combine(const DevRowBlock* __restrict__ rows, const DevRowTerm
 template <typename real>
 static int launch_moments(pbtc_plan& pl, hipStream_t st, real* mom, const Src<real>* src) {
   const Cell* cells = wsp<Cell>(pl, pl.o_cells);
-  const int nc = (int)pl.n_cells;
-#define PBTC_MOM(PP)                                                                         \
-  case PP:                                                                                   \
-    hipLaunchKernelGGL((k_p2m<real, PP>), dim3(nc), dim3(kP2MThreads), 0, st, cells, 0, src, \
-                       mom);                                                                 \
-    for (int l = pl.n_levels - 1; l >= 0; --l) {                                             \
-      const int lb = pl.level_begin[l], le = pl.level_begin[l + 1];                          \
-      if (le > lb)                                                                           \
-        hipLaunchKernelGGL((k_m2m<real, PP>), dim3(le - lb), dim3(kM2MThreads), 0, st, cells, \
-                           lb, mom);                                                         \
-    }                                                                                        \
+  const int4* chunks = wsp<int4>(pl, pl.o_mchunks);
+  const int* cell_chunk = wsp<int>(pl, pl.o_mcell);
+  real* part = wsp<real>(pl, pl.o_mpart);
+  const unsigned nch = (unsigned)pl.n_mchunks, nc = (unsigned)pl.n_cells;
+#define PBTC_MOM(PP)                                                                           \
+  case PP:                                                                                     \
+    if (nch > 0)                                                                               \
+      hipLaunchKernelGGL((k_p2m_chunk<real, PP>), dim3(nch), dim3(kMomThreads), 0, st, chunks, \
+                         cells, src, part);                                                    \
+    hipLaunchKernelGGL((k_mom_sum<real, PP>), dim3(nc), dim3(256), 0, st, cell_chunk, part, mom); \
     break;
   switch (pl.P) {
     PBTC_MOM(2)

@@ -412,23 +412,51 @@ __global__ __launch_bounds__(64 * kTravWaves) void k_near_rows(
   }
   const long long row = b.nf_row + i;
   long long n = 0;
-  const long long base = (mode == 1 && active) ? ptr[row] : 0;
+  const long long out0 = (mode == 1 && active) ? ptr[row] : 0;
   const long long gp0 = a.gp_first[b.s];
+  const double reach = a.reach[b.s];
+  // a leaf's sources pass through LDS 64 at a time: each lane loads one, the
+  // panel's first Gauss point stands for the panel (one test per panel)
+  __shared__ double lx[kTravWaves][64], ly[kTravWaves][64], lz[kTravWaves][64];
+  __shared__ double ll[kTravWaves][64];
+  __shared__ int lp[kTravWaves][64];
   wave_leaves_within(a.cells, b.root, grp[4 * gg], grp[4 * gg + 1], grp[4 * gg + 2],
-                     grp[4 * gg + 3], a.reach[b.s], stk[w], overflow, [&](int leaf) {
+                     grp[4 * gg + 3], reach, stk[w], overflow,
+                     [&](int leaf, double lcx, double lcy, double lcz, double lrb) {
+    // skip the leaf unless some lane's own target is within reach of it
+    const double qx = x - lcx, qy = y - lcy, qz = z - lcz;
+    if (__ballot(active && sqrt(qx * qx + qy * qy + qz * qz) - lrb <= reach) == 0) return;
     const int beg = __builtin_amdgcn_readfirstlane(a.cells[leaf].begin);
     const int end = beg + __builtin_amdgcn_readfirstlane(a.cells[leaf].count);
-    for (int j = beg; j < end; ++j) {
-      const int og = a.gidx[j];
-      if ((og - gp0) % a.K != 0) continue;  // one test per panel
-      const int p = a.gpid[j];
-      const double ex = x - a.cx[p], ey = y - a.cy[p], ez = z - a.cz[p];
-      const double lim = a.thres * a.len[p];
-      const bool take = active && (p == self_pan || ex * ex + ey * ey + ez * ez < lim * lim);
-      if (take) {
-        if (mode == 1 && base + n < cap) col[base + n] = p;
-        ++n;
+    for (int c0 = beg; c0 < end; c0 += 64) {
+      const int j = c0 + lane;
+      bool rep = false;
+      if (j < end) {
+        rep = (a.gidx[j] - gp0) % a.K == 0;
+        if (rep) {
+          const int p = a.gpid[j];
+          const double lim = a.thres * a.len[p];
+          lx[w][lane] = a.cx[p];
+          ly[w][lane] = a.cy[p];
+          lz[w][lane] = a.cz[p];
+          ll[w][lane] = lim * lim;
+          lp[w][lane] = p;
+        }
       }
+      wave_sync();
+      uint64_t m = __ballot(rep);
+      while (m) {
+        const int t = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int p = lp[w][t];
+        const double ex = x - lx[w][t], ey = y - ly[w][t], ez = z - lz[w][t];
+        const bool take = active && (p == self_pan || ex * ex + ey * ey + ez * ez < ll[w][t]);
+        if (take) {
+          if (mode == 1 && out0 + n < cap) col[out0 + n] = p;
+          ++n;
+        }
+      }
+      wave_sync();  // the slots are rewritten by the next batch
     }
   });
   if (mode == 0 && active) ptr[row] = n;
@@ -1035,6 +1063,27 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
         }
     pl.n_units = (int64_t)units.size();
     pl.n_uptr = (int64_t)uptr.size();
+
+    // direct moment pass: the sources of every cell (all levels) in runs of
+    // at most kMomSpan, one block each, then one sum per cell
+    std::vector<int4> mch;
+    std::vector<int> mcell(pl.n_cells + 1);
+    for (int64_t c = 0; c < pl.n_cells; ++c) {
+      mcell[c] = (int)mch.size();
+      for (int b0 = 0; b0 < hc[c].count; b0 += kMomSpan)
+        mch.push_back(make_int4((int)c, hc[c].begin + b0, std::min(kMomSpan, hc[c].count - b0), 0));
+    }
+    mcell[pl.n_cells] = (int)mch.size();
+    pl.n_mchunks = (int64_t)mch.size();
+    if (pl.n_mchunks > pl.cap_mchunks) {
+      pl.cap_mchunks = pl.n_mchunks + pl.n_mchunks / 8 + 1024;
+      *need_retry = 1;
+      pl.err = "moment chunks exceed the workspace estimate";
+      return PBTC_EWORKSPACE;
+    }
+    if (!mch.empty())
+      PBTC_HIP(hipMemcpy(wsp<int4>(pl, pl.o_mchunks), mch.data(), 16 * mch.size(), hipMemcpyHostToDevice));
+    PBTC_HIP(hipMemcpy(wsp<int>(pl, pl.o_mcell), mcell.data(), 4 * mcell.size(), hipMemcpyHostToDevice));
     if (pl.n_units > pl.cap_units) {
       pl.cap_units = pl.n_units + pl.n_units / 8 + 1024;
       *need_retry = 1;

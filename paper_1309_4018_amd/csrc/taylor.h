@@ -25,6 +25,8 @@
 // then k1 descending, then k2 descending.
 #pragma once
 
+#include <utility>
+
 #include "internal.h"
 
 namespace pbtc {
@@ -32,6 +34,19 @@ namespace pbtc {
 __host__ __device__ constexpr int mindex(int a, int b, int c) {
   return (a + b + c) * (a + b + c + 1) * (a + b + c + 2) / 6 +
          (b + c) * (b + c + 1) / 2 + c;
+}
+
+// Inverse of mindex by arithmetic (no table): total degree n from the
+// tetrahedral numbers, then b + c from the triangular numbers.
+__host__ __device__ inline void mindex_inv(int k, int& a, int& b, int& c) {
+  int n = 0;
+  while ((n + 1) * (n + 2) * (n + 3) / 6 <= k) ++n;
+  const int r = k - n * (n + 1) * (n + 2) / 6;
+  int m = 0;
+  while ((m + 1) * (m + 2) / 2 <= r) ++m;
+  c = r - m * (m + 1) / 2;
+  b = m - c;
+  a = n - m;
 }
 
 template <int P>
@@ -61,31 +76,80 @@ struct MultiIndex {
 };
 
 // sum_k a_k M[k] and sum_k a_k M[N + k] for the Laplace kernel 1/R.
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1.
+// Every coefficient index below is then a constant, so the coefficient
+// arrays live in registers whatever the order (a run-time loop over 120+
+// terms is not fully unrolled and its arrays go to scratch memory).
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>()), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>());
+}
+
+// Coefficient K >= 1 of the table of order PP from those of lower degree
+// (the recurrences above): Laplace (YUK = false) fills a, Yukawa fills a
+// and b.
+template <int PP, int K, bool YUK, typename real>
+__device__ __forceinline__ void coef_step(real* a, real* b, real dx, real dy, real dz, real r2inv,
+                                          real kappa) {
+  constexpr MultiIndex<PP> T{};
+  constexpr int n = T.n[K];
+  constexpr int i10 = T.m1[K][0], i11 = T.m1[K][1], i12 = T.m1[K][2];
+  constexpr int i20 = T.m2[K][0], i21 = T.m2[K][1], i22 = T.m2[K][2];
+  real s1 = real(0), s2 = real(0), t1 = real(0), t2 = real(0);
+  if constexpr (i10 >= 0) {
+    s1 += dx * a[i10];
+    if constexpr (YUK) t1 += dx * b[i10];
+  }
+  if constexpr (i11 >= 0) {
+    s1 += dy * a[i11];
+    if constexpr (YUK) t1 += dy * b[i11];
+  }
+  if constexpr (i12 >= 0) {
+    s1 += dz * a[i12];
+    if constexpr (YUK) t1 += dz * b[i12];
+  }
+  if constexpr (i20 >= 0) {
+    s2 += a[i20];
+    if constexpr (YUK) t2 += b[i20];
+  }
+  if constexpr (i21 >= 0) {
+    s2 += a[i21];
+    if constexpr (YUK) t2 += b[i21];
+  }
+  if constexpr (i22 >= 0) {
+    s2 += a[i22];
+    if constexpr (YUK) t2 += b[i22];
+  }
+  constexpr real c1 = real(2 * n - 1) / real(n), c2 = real(n - 1) / real(n);
+  constexpr real inv_n = real(1) / real(n);
+  if constexpr (YUK) {
+    b[K] = kappa * inv_n * (s1 - s2);
+    a[K] = (c1 * s1 - c2 * s2 + kappa * inv_n * (t1 - t2)) * r2inv;
+  } else {
+    a[K] = (c1 * s1 - c2 * s2) * r2inv;
+  }
+}
+
+// sum_k a_k M[k] and sum_k a_k M[N + k] for the Laplace kernel 1/R.
 template <int P, typename real>
 __device__ __forceinline__ void taylor_laplace(real dx, real dy, real dz, real rinv,
                                                const real* __restrict__ M, real& s, real& d) {
-  constexpr MultiIndex<P> T{};
   constexpr int N = MultiIndex<P>::N;
   const real r2inv = rinv * rinv;
   real a[N];
   a[0] = rinv;
   s += a[0] * M[0];
   d += a[0] * M[N];
-#pragma unroll
-  for (int k = 1; k < N; ++k) {
-    const int n = T.n[k];
-    real s1 = real(0), s2 = real(0);
-    if (T.m1[k][0] >= 0) s1 += dx * a[T.m1[k][0]];
-    if (T.m1[k][1] >= 0) s1 += dy * a[T.m1[k][1]];
-    if (T.m1[k][2] >= 0) s1 += dz * a[T.m1[k][2]];
-    if (T.m2[k][0] >= 0) s2 += a[T.m2[k][0]];
-    if (T.m2[k][1] >= 0) s2 += a[T.m2[k][1]];
-    if (T.m2[k][2] >= 0) s2 += a[T.m2[k][2]];
-    const real c1 = real(2 * n - 1) / real(n), c2 = real(n - 1) / real(n);
-    a[k] = (c1 * s1 - c2 * s2) * r2inv;
+  static_for<N - 1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value + 1;
+    coef_step<P, k, false, real>(a, a, dx, dy, dz, r2inv, real(0));
     s += a[k] * M[k];
     d += a[k] * M[N + k];
-  }
+  });
 }
 
 // Same for the Yukawa kernel exp(-kappa R)/R; e = exp(-kappa R).
@@ -93,7 +157,6 @@ template <int P, typename real>
 __device__ __forceinline__ void taylor_yukawa(real dx, real dy, real dz, real rinv, real e,
                                               real kappa, const real* __restrict__ M, real& s,
                                               real& d) {
-  constexpr MultiIndex<P> T{};
   constexpr int N = MultiIndex<P>::N;
   const real r2inv = rinv * rinv;
   real a[N], b[N];
@@ -101,41 +164,12 @@ __device__ __forceinline__ void taylor_yukawa(real dx, real dy, real dz, real ri
   b[0] = e;
   s += a[0] * M[0];
   d += a[0] * M[N];
-#pragma unroll
-  for (int k = 1; k < N; ++k) {
-    const int n = T.n[k];
-    real s1 = real(0), s2 = real(0), t1 = real(0), t2 = real(0);
-    if (T.m1[k][0] >= 0) {
-      s1 += dx * a[T.m1[k][0]];
-      t1 += dx * b[T.m1[k][0]];
-    }
-    if (T.m1[k][1] >= 0) {
-      s1 += dy * a[T.m1[k][1]];
-      t1 += dy * b[T.m1[k][1]];
-    }
-    if (T.m1[k][2] >= 0) {
-      s1 += dz * a[T.m1[k][2]];
-      t1 += dz * b[T.m1[k][2]];
-    }
-    if (T.m2[k][0] >= 0) {
-      s2 += a[T.m2[k][0]];
-      t2 += b[T.m2[k][0]];
-    }
-    if (T.m2[k][1] >= 0) {
-      s2 += a[T.m2[k][1]];
-      t2 += b[T.m2[k][1]];
-    }
-    if (T.m2[k][2] >= 0) {
-      s2 += a[T.m2[k][2]];
-      t2 += b[T.m2[k][2]];
-    }
-    const real inv_n = real(1) / real(n);
-    const real c1 = real(2 * n - 1) / real(n), c2 = real(n - 1) / real(n);
-    b[k] = kappa * inv_n * (s1 - s2);
-    a[k] = (c1 * s1 - c2 * s2 + kappa * inv_n * (t1 - t2)) * r2inv;
+  static_for<N - 1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value + 1;
+    coef_step<P, k, true, real>(a, b, dx, dy, dz, r2inv, kappa);
     s += a[k] * M[k];
     d += a[k] * M[N + k];
-  }
+  });
 }
 
 // Floating-point operations of one P2P pair as written in the kernel

@@ -96,8 +96,8 @@ __device__ inline void wave_lists(const Cell* __restrict__ cells, int root, doub
 
 // Leaves of the tree under `root` that may hold a source within `reach` of
 // some point of the sphere (gx, gy, gz, gr): a cell is skipped when
-// |centre - g| - r_b - gr > reach.  leaf(c) is called by the whole wave, in a
-// fixed order, with a wave-uniform leaf index.
+// |centre - g| - r_b - gr > reach.  leaf(c, centre x, y, z, r_b) is called by
+// the whole wave, in a fixed order, with wave-uniform arguments.
 template <typename F>
 __device__ inline void wave_leaves_within(const Cell* __restrict__ cells, int root, double gx,
                                           double gy, double gz, double gr, double reach,
@@ -127,8 +127,13 @@ __device__ inline void wave_leaves_within(const Cell* __restrict__ cells, int ro
     }
     first = false;
     int kind = TV_NONE;
+    double ccx = 0.0, ccy = 0.0, ccz = 0.0, crb = 0.0;
     if (c >= 0) {
       const Cell cl = cells[c];
+      ccx = cl.cx;
+      ccy = cl.cy;
+      ccz = cl.cz;
+      crb = cl.rb;
       if (cl.count > 0) {
         const double dx = gx - cl.cx, dy = gy - cl.cy, dz = gz - cl.cz;
         if (sqrt(dx * dx + dy * dy + dz * dz) - cl.rb - gr <= reach)
@@ -144,7 +149,8 @@ __device__ inline void wave_leaves_within(const Cell* __restrict__ cells, int ro
     while (ml) {
       const int l = __ffsll((unsigned long long)ml) - 1;
       ml &= ml - 1;
-      leaf(__builtin_amdgcn_readfirstlane(__shfl(c, l, 64)));
+      leaf(__builtin_amdgcn_readfirstlane(__shfl(c, l, 64)), __shfl(ccx, l, 64),
+           __shfl(ccy, l, 64), __shfl(ccz, l, 64), __shfl(crb, l, 64));
     }
   }
 }
