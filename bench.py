@@ -28,6 +28,7 @@ theta, P and the tree parameters first.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,7 +40,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published (counts packed FP32)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # one FP32 FMA per lane per cycle: 256 CU x 64 x 2 x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
 
 
@@ -59,6 +61,31 @@ def workload(name):
         return probs, (f"64 star-shaped molecules, {sum(p.n_panels for p in probs):,} panels, "
                        f"{sum(p.n_charges for p in probs):,} charges, one launch sequence")
     raise SystemExit(f"unknown workload {name}")
+
+
+def counted_traffic(workload_name, kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE and WRITE_SIZE scaled by the copy
+    probe), or None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"hbm_counters_{workload_name}.txt")
+    if not os.path.exists(path):
+        return None
+    sha, sources, traffic = None, [], {}
+    for line in open(path):
+        if line.startswith("source_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("sources:"):
+            sources = line.split(":", 1)[1].split()
+        elif line.startswith("kernel "):
+            parts = line.split()
+            traffic[parts[1]] = float(parts[parts.index("traffic_bytes") + 1])
+    if not sha or not sources or kernel not in traffic:
+        return None
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return traffic[kernel] if h.hexdigest() == sha else None
 
 
 def make_plan(lib, prob, **params):
@@ -107,6 +134,8 @@ def main():
                     help="choose theta, P, ncrit, direct_below with the autotuner first")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="adjoint (gradient) evaluations timed after the solves")
+    ap.add_argument("--minimal", action="store_true",
+                    help="only the timed FP32-refined steps (for counter collection)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU: the multi-GPU path (targets sharded across GPUs, "
@@ -159,25 +188,39 @@ def main():
     nmv = sum(r["n_matvec_fp32"] + r["n_matvec_fp64"] for r in results)
     value = dense * nmv / el
 
-    # roofline of the dominant kernel over the timed steps
-    tp = sum(r["t_p2p_s"] for r in results)
-    tm = sum(r["t_m2p_s"] for r in results)
-    np_ = sum(r["n_p2p_launch"] for r in results)
-    nm = sum(r["n_m2p_launch"] for r in results)
-    fp = sum(r["p2p_flop"] for r in results)
-    fm = sum(r["m2p_flop"] for r in results)
-    if tm >= tp:
-        kern, t_k, n_k, f_k = "m2p", tm, nm, fm
-    else:
-        kern, t_k, n_k, f_k = "p2p", tp, np_, fp
+    # roofline of the dominant kernel over the timed steps: the library times
+    # each P2P, Laplace M2P and Yukawa M2P launch of the FP32 operator with
+    # HIP events on the launch stream
+    def tot(key):
+        return sum(r[key] for r in results)
+
+    kern = {
+        "p2p": (tot("t_p2p_s"), tot("n_p2p_launch"), tot("p2p_flop")),
+        "m2p_laplace": (tot("t_m2p_s") - tot("t_m2p_yuk_s"),
+                        tot("n_m2p_launch") - tot("n_m2p_yuk_launch"),
+                        tot("m2p_flop") - tot("m2p_yuk_flop")),
+        "m2p_yukawa": (tot("t_m2p_yuk_s"), tot("n_m2p_yuk_launch"), tot("m2p_yuk_flop")),
+    }
+    name = max(kern, key=lambda k: kern[k][0])
+    t_k, n_k, f_k = kern[name]
     achieved = f_k / t_k / 1e12 if t_k > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": kern, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+    roofline = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": counted_traffic(a.workload, name),
                 "avg_launch_ms": 1e3 * t_k / max(n_k, 1),
                 "flop_per_launch": f_k / max(n_k, 1),
-                "p2p_tflops": fp / tp / 1e12 if tp else 0.0,
-                "m2p_tflops": fm / tm / 1e12 if tm else 0.0,
-                "p2p_share_of_step": tp / el, "m2p_share_of_step": tm / el}
+                "peak_nonpacked_fp32": PEAK_FP32_NONPACKED_TFLOPS,
+                "kernels": {k: {"tflops": (v[2] / v[0] / 1e12) if v[0] else 0.0,
+                                "avg_launch_ms": 1e3 * v[0] / max(v[1], 1),
+                                "share_of_step": v[0] / el} for k, v in kern.items()}}
+
+    if a.minimal:
+        print(json.dumps({"metric": "BEM matvec interactions/s + GMRES solve s to 1e-5; "
+                                    "FP32-bulk vs FP64", "value": value,
+                          "unit": "interactions/s", "n_gpus": 1, "steps": a.steps,
+                          "warmup": a.warmup, "ms_per_step": ms, "roofline": roofline,
+                          "minimal": True}))
+        return 0
 
     # matvec-only rates (FP32 and FP64 operators) with events on the stream
     x = torch.randn(pl.n_unknowns, dtype=torch.float64, device=dev)

@@ -109,8 +109,9 @@ typedef struct {
   double inner_tol; /* FP32_REFINED: relative tolerance floor of inner solves */
   int max_refine;   /* FP32_REFINED: maximum outer refinement steps */
   int validate_charges; /* 1: check every charge lies inside its region */
-  int profile;      /* 1: time every P2P and M2P launch with HIP events on the
-                       caller's stream (pbtc_result.t_p2p_s ...) */
+  int profile;      /* 1: time every P2P and M2P kernel launch of the FP32
+                       operator (A x) with HIP events on the caller's stream
+                       (pbtc_result.t_p2p_s ...) */
   int precond;      /* PBTC_PREC_NONE or PBTC_PREC_BLOCK_DIAG (forward and
                        adjoint solves) */
 } pbtc_params;
@@ -132,10 +133,15 @@ typedef struct {
   double n_near_entries; /* near-field correction entries */
   size_t workspace_needed; /* bytes (set on PBTC_EWORKSPACE and on success) */
   /* with params.profile: summed HIP-event durations, launch counts and
-   * algorithmic FP operations of all P2P and M2P launches of the call */
+   * algorithmic FP operations of the P2P and M2P kernel launches of the
+   * FP32 operator (A x) during the call; M2P counts both kernels */
   double t_p2p_s, t_m2p_s;
   int n_p2p_launch, n_m2p_launch;
   double p2p_flop, m2p_flop;
+  /* the Yukawa M2P kernel's share of the M2P figures */
+  double t_m2p_yuk_s;
+  int n_m2p_yuk_launch;
+  double m2p_yuk_flop;
 } pbtc_result;
 
 /* Library version; never fails. */

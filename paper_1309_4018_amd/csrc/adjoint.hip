@@ -378,7 +378,7 @@ template <typename real, int KS>
 __global__ __launch_bounds__(kT) void k_adj_p2p(AdjArgs a, const Src<real>* __restrict__ gpos,
                                                 const Src<real>* __restrict__ asrc,
                                                 real* __restrict__ partial) {
-  const int u = uni(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  const int u = uni(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (u >= a.nunits) return;
   const int4 un = a.units[u];
   const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kT) void k_adj_m2p(AdjArgs a, const Src<real>* __re
                                                 const real* __restrict__ mom, int ms,
                                                 int kslot, real* __restrict__ partial) {
   constexpr int N = ncoef(P);
-  const int u = uni(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  const int u = uni(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (u >= a.nunits) return;
   const int4 un = a.units[u];
   const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);

@@ -250,8 +250,9 @@ struct pbtc_plan {
   // profiling (params.profile): events around P2P (kind 0) and M2P (kind 1)
   struct ProfEvent { int kind; double flop; hipEvent_t a, b; };
   std::vector<ProfEvent> prof, prof_pool;
-  double prof_t[2] = {0, 0}, prof_flop[2] = {0, 0};
-  int prof_n[2] = {0, 0};
+  // per kernel kind: 0 P2P, 1 Laplace M2P, 2 Yukawa M2P
+  double prof_t[3] = {0, 0, 0}, prof_flop[3] = {0, 0, 0};
+  int prof_n[3] = {0, 0, 0};
   std::vector<double> item_flop_p2p[2][pbtc::KS_COUNT], item_flop_m2p[2][pbtc::KS_COUNT];
   double launch_flop_p2p[2][pbtc::KS_COUNT] = {}, launch_flop_m2p[2][pbtc::KS_COUNT] = {};
   bool setup_done = false;

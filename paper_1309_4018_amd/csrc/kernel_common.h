@@ -59,6 +59,18 @@ __device__ __forceinline__ double exp_scaled(double v) {
   return exp(v);
 }
 
+// XCD-aware work-group order.  The dispatcher deals work-group b of a launch
+// to XCD b % 8, and each XCD has its own L2; consecutive work units (Morton-
+// ordered target groups) touch nearby sources, so each XCD is given one
+// contiguous run of logical blocks instead of every eighth one.  A bijection
+// of [0, nb).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = b % kXcds, i = b / kXcds;
+  return x * q + min(x, r) + i;
+}
+
 // Orders LDS accesses of the lanes of one wavefront (no work-group barrier):
 // writes before the call are visible to every lane of the wave after it.
 __device__ __forceinline__ void wave_sync() {

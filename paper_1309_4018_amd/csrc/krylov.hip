@@ -724,7 +724,7 @@ int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res) {
   Krylov K(pl, st);
   pl.history.clear();
   prof_collect(pl);
-  for (int i = 0; i < 2; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
+  for (int i = 0; i < 3; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
   int iters = 0, n32 = 0, n64 = 0, nref = 0;
   bool conv = false;
   double rel = 0.0;
@@ -768,11 +768,14 @@ int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res) {
     res->t_energy_s = t2 - t1;
     prof_collect(pl);
     res->t_p2p_s = pl.prof_t[0];
-    res->t_m2p_s = pl.prof_t[1];
+    res->t_m2p_s = pl.prof_t[1] + pl.prof_t[2];
     res->n_p2p_launch = pl.prof_n[0];
-    res->n_m2p_launch = pl.prof_n[1];
+    res->n_m2p_launch = pl.prof_n[1] + pl.prof_n[2];
     res->p2p_flop = pl.prof_flop[0];
-    res->m2p_flop = pl.prof_flop[1];
+    res->m2p_flop = pl.prof_flop[1] + pl.prof_flop[2];
+    res->t_m2p_yuk_s = pl.prof_t[2];
+    res->n_m2p_yuk_launch = pl.prof_n[2];
+    res->m2p_yuk_flop = pl.prof_flop[2];
   }
   if (!conv) {
     pl.err = "GMRES did not reach the tolerance within max_iter";

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __
                                                       const real* __restrict__ tz,
                                                       const Src<real>* __restrict__ src,
                                                       real* __restrict__ partial) {
-  const int u = uni(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  const int u = uni(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (u >= a.nunits) return;
   const int4 un = a.units[u];
   const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kItemThreads) void k_m2p(UnitArgs a, const real* __
                                                       const real* __restrict__ mom, int slot,
                                                       real* __restrict__ partial) {
   constexpr int N = ncoef(P);
-  const int u = uni(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  const int u = uni(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (u >= a.nunits) return;
   const int4 un = a.units[u];
   const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
@@ -454,9 +454,10 @@ static void launch_m2p(pbtc_plan& pl, hipStream_t st, const UnitArgs& a, int gri
 #undef PBTC_M2P
 }
 
-// Timing of P2P / M2P launches with events on the launch stream.
-static void prof_mark(pbtc_plan& pl, hipStream_t st, int kind, double flop, bool begin) {
-  if (!pl.prm.profile) return;
+// Timing of one kernel launch (kind 0 P2P, 1 Laplace M2P, 2 Yukawa M2P) with
+// events on the launch stream; only the FP32 operator (A x) is timed.
+static void prof_mark(pbtc_plan& pl, hipStream_t st, bool on, int kind, double flop, bool begin) {
+  if (!pl.prm.profile || !on) return;
   if (begin) {
     pbtc_plan::ProfEvent ev;
     if (!pl.prof_pool.empty()) {
@@ -491,6 +492,7 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
                      src);
   PBTC_LAUNCH_CHECK();
   const bool tree = pl.prm.op == PBTC_OP_TREECODE;
+  const bool timed = sizeof(real) == 4 && phase == 0;
   if (tree) {
     int rc = launch_moments<real>(pl, st, mom, src);
     if (rc) return rc;
@@ -514,7 +516,7 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
       a.nunits = (int)us.n;
       a.cells_list = wsp<int>(pl, pl.o_near);
       const int grid = nblocks(us.n, kWaves);
-      prof_mark(pl, st, 0, pl.launch_flop_p2p[phase][ks], true);
+      prof_mark(pl, st, timed, 0, pl.launch_flop_p2p[phase][ks], true);
       switch (ks) {
         case KS_L:
           hipLaunchKernelGGL((k_p2p<real, KS_L>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
@@ -529,7 +531,7 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
           hipLaunchKernelGGL((k_p2p<real, KS_YY>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
           break;
       }
-      prof_mark(pl, st, 0, 0.0, false);
+      prof_mark(pl, st, timed, 0, 0.0, false);
       const int* uptr = wsp<int>(pl, pl.o_uptr + 4 * us.ptr_off);
       if (ks == KS_L || ks == KS_Y)
         hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr, a.item_block,
@@ -550,17 +552,20 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
       // kernel of slot 0 and (for two-kernel blocks) slot 1
       const int kind0 = (ks == KS_L || ks == KS_LY) ? 0 : 1;
       const bool two = ks == KS_LY || ks == KS_YY;
-      prof_mark(pl, st, 1, pl.launch_flop_m2p[phase][ks], true);
       for (int slot = 0; slot < (two ? 2 : 1); ++slot) {
         const int kind = slot == 0 ? kind0 : 1;
+        // this kernel's share of the block's M2P operations
+        const double fl = pl.launch_flop_m2p[phase][ks] * m2p_flop_one(pl.P, kind) /
+                          m2p_flop_per_eval(pl.P, ks);
+        prof_mark(pl, st, timed, 1 + kind, fl, true);
         if (kind == 0)
           launch_m2p<real, 0>(pl, st, a, grid, tx, ty, tz, mom, slot, partial);
         else
           launch_m2p<real, 1>(pl, st, a, grid, tx, ty, tz, mom, slot, partial);
+        prof_mark(pl, st, timed, 1 + kind, 0.0, false);
         hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr,
                            a.item_block, a.blocks, tidx, partial, S, D, 1, slot);
       }
-      prof_mark(pl, st, 1, 0.0, false);
       PBTC_LAUNCH_CHECK();
     }
   }

@@ -47,6 +47,8 @@ class Result(C.Structure):
         ("t_p2p_s", C.c_double), ("t_m2p_s", C.c_double),
         ("n_p2p_launch", C.c_int), ("n_m2p_launch", C.c_int),
         ("p2p_flop", C.c_double), ("m2p_flop", C.c_double),
+        ("t_m2p_yuk_s", C.c_double), ("n_m2p_yuk_launch", C.c_int),
+        ("m2p_yuk_flop", C.c_double),
     ]
 
     def as_dict(self):
