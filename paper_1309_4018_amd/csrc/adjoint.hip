@@ -149,7 +149,7 @@ __global__ __launch_bounds__(64 * kTravWaves) void k_adj_lists(
     nn = 1;
   } else {
     wave_lists(cells, b.troot, grp[4 * g], grp[4 * g + 1], grp[4 * g + 2], grp[4 * g + 3], theta,
-               direct_below, mode, pn, pf, near, far, cap_near, cap_far, stk[w], &nn, &nf,
+               b.direct_below, mode, pn, pf, near, far, cap_near, cap_far, stk[w], &nn, &nf,
                overflow);
   }
   if (mode == 0 && lane == 0) {

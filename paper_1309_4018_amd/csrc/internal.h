@@ -116,7 +116,7 @@ struct DevBlock {
   int slot0;                 // kernel slot of kernel 0 (slot0 + 1 for kernel 1)
   int troot;                 // root cell of the target-set tree
   int lslot0;                // slot of kernel 0 among the slots of its target-set tree
-  int pad2;
+  int direct_below;          // MAC-accepted cells with fewer sources go to P2P
 };
 
 // Weights of one (block, kernel) slot of the transposed operator:

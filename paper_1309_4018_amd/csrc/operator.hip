@@ -19,6 +19,7 @@
 //   near      FP64-built corrections for the self and near-singular panels
 //   combine   1/2 phi_t - sum_s sigma_rs (c_rs S - D) per row block
 #include <algorithm>
+#include <cmath>
 
 #include "device_util.h"
 #include "kernel_common.h"
@@ -340,7 +341,20 @@ __global__ void k_reduce(const int* __restrict__ list, const int* __restrict__ u
   double v[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-  for (int u = uptr[l]; u < uptr[l + 1]; ++u)
+  // four units per step: their loads are in flight together (fixed order)
+  int u = uptr[l];
+  const int u1 = uptr[l + 1];
+  for (; u + 4 <= u1; u += 4) {
+    real p[4][NQ];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) p[w][q] = partial[((size_t)(u + w) * 4 + q) * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      v[q] += ((double)p[0][q] + (double)p[1][q]) + ((double)p[2][q] + (double)p[3][q]);
+  }
+  for (; u < u1; ++u)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * 64 + lane];
   const long long i = tidx[t0 + lane] - b.tgt_off;
@@ -649,6 +663,13 @@ int upload_descriptors(pbtc_plan& pl, hipStream_t st) {
     d.csc_off = pl.blk_csc_off[i];
     d.slot0 = (int)pl.blk_slot0[i];
     d.lslot0 = pl.blk_lslot0.empty() ? 0 : pl.blk_lslot0[i];
+    // automatic: a cell goes to P2P when its sources cost less there than
+    // one M2P evaluation (issue slots are about 0.7 of the flop ratio of
+    // the two kernels on gfx950)
+    d.direct_below = pl.prm.direct_below >= 0
+                         ? pl.prm.direct_below
+                         : (int)std::lround(0.7 * m2p_flop_per_eval(pl.P, b.ks) /
+                                            p2p_flop_per_pair(b.ks));
     d.troot = b.t;  // the target-set trees have one root per target set, in order
   }
   PBTC_HIP(hipMemcpyAsync(wsp<DevBlock>(pl, pl.o_blocks), db.data(), sizeof(DevBlock) * db.size(),

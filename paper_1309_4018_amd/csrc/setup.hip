@@ -340,7 +340,7 @@ __global__ __launch_bounds__(64 * kTravWaves) void k_lists(
     nn = 1;
   } else {
     wave_lists(cells, b.root, grp[4 * g], grp[4 * g + 1], grp[4 * g + 2], grp[4 * g + 3], theta,
-               direct_below, mode, pn, pf, near, far, cap_near, cap_far, stk[w], &nn, &nf,
+               b.direct_below, mode, pn, pf, near, far, cap_near, cap_far, stk[w], &nn, &nf,
                overflow);
   }
   if (mode == 0 && lane == 0) {
@@ -1028,9 +1028,10 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     pl.p2p_pairs = pairs;
     pl.m2p_evals = tree ? m2p : 0.0;
 
-    // wavefront work units: a P2P unit covers <= kUnitSources sources of one
+    // wavefront work units (enough of them to keep several waves per SIMD):
+    // a P2P unit covers <= kUnitSources sources of one
     // item's near list (whole cells), an M2P unit <= kUnitCells far cells
-    constexpr int kUnitSources = 1024, kUnitCells = 32;
+    constexpr int kUnitSources = 512, kUnitCells = 32;
     std::vector<int4> units;
     std::vector<int> uptr;
     for (int ph = 0; ph < 2; ++ph)
