@@ -111,9 +111,10 @@ typedef struct {
   double inner_tol; /* FP32_REFINED: relative tolerance floor of inner solves */
   int max_refine;   /* FP32_REFINED: maximum outer refinement steps */
   int validate_charges; /* 1: check every charge lies inside its region */
-  int profile;      /* 1: time every P2P and M2P kernel launch of the FP32
-                       operator (A x) with HIP events on the caller's stream
-                       (pbtc_result.t_p2p_s ...) */
+  int profile;      /* n > 0: time the P2P and M2P kernel launches of every
+                       n-th evaluation of the FP32 operator (A x) with HIP
+                       events on the caller's stream (pbtc_result.t_p2p_s
+                       ...); 0: off */
   int precond;      /* PBTC_PREC_NONE or PBTC_PREC_BLOCK_DIAG (forward and
                        adjoint solves) */
 } pbtc_params;
@@ -123,8 +124,10 @@ typedef struct {
   int n_iter;            /* GMRES iterations (all restarts / refinements) */
   int converged;         /* 1 if the explicit residual met tol */
   double final_rel_res;  /* explicit ||b - A x|| / ||b|| (FP64 operator) */
-  int n_matvec_fp32;     /* operator evaluations in FP32 */
-  int n_matvec_fp64;     /* operator evaluations in FP64 */
+  int n_matvec_fp32;     /* operator evaluations in FP32 whose results were used
+                            (the evaluation GMRES queues while it reads the
+                            previous residual is not counted when discarded) */
+  int n_matvec_fp64;     /* operator evaluations in FP64, likewise */
   int n_refine;          /* outer refinement steps (FP32_REFINED) */
   double t_setup_s;      /* device set-up: geometry, tree, lists, near field, RHS */
   double t_solve_s;      /* Krylov solve incl. refinement */

@@ -211,6 +211,17 @@ int pbtc_plan_create(const pbtc_problem* p, const pbtc_params* prm, pbtc_plan** 
   return PBTC_OK;
 }
 
+pbtc_plan::~pbtc_plan() {
+  for (auto* v : {&prof, &prof_pool})
+    for (auto& ev : *v) {
+      (void)hipEventDestroy(ev.a);
+      (void)hipEventDestroy(ev.b);
+    }
+  for (hipEvent_t e : res_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (res_pin) (void)hipHostFree(res_pin);
+}
+
 void pbtc_plan_destroy(pbtc_plan* plan) { delete plan; }
 
 int pbtc_plan_sizes(const pbtc_plan* plan, int64_t* n_unknowns, int64_t* n_charges,

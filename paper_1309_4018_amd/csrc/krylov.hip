@@ -435,6 +435,21 @@ struct Krylov {
     if (hipMemcpyAsync(h, d, 8 * cnt, hipMemcpyDeviceToHost, st) != hipSuccess) return false;
     return hipStreamSynchronize(st) == hipSuccess;
   }
+  // pinned host buffer of 2 slots x cnt values and two events for the
+  // residual readback (kept by the plan)
+  bool pinned(int cnt) {
+    if (pl.res_pin_n < 2 * cnt) {
+      if (pl.res_pin) (void)hipHostFree(pl.res_pin);
+      pl.res_pin = nullptr;
+      pl.res_pin_n = 0;
+      if (hipHostMalloc((void**)&pl.res_pin, 8 * 2 * (size_t)cnt) != hipSuccess) return false;
+      pl.res_pin_n = 2 * cnt;
+    }
+    for (int i = 0; i < 2; ++i)
+      if (!pl.res_ev[i] && hipEventCreateWithFlags(&pl.res_ev[i], hipEventDisableTiming) != hipSuccess)
+        return false;
+    return true;
+  }
   bool to_dev(double* d, const double* h, int cnt) {
     if (hipMemcpyAsync(d, h, 8 * cnt, hipMemcpyHostToDevice, st) != hipSuccess) return false;
     return hipStreamSynchronize(st) == hipSuccess;
@@ -460,7 +475,7 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, int prec, const double* r
                  bool zero_start,
                  const std::vector<double>& tol, const std::vector<double>& ref, int max_iter,
                  int* iters, std::vector<double>* hist, std::vector<int>* conv,
-                 std::vector<int>* conv_iter) {
+                 std::vector<int>* conv_iter, int* discarded) {
   Krylov K(pl, st);
   const int T = 256;
   const int64_t n = K.n;
@@ -469,7 +484,7 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, int prec, const double* r
   double* pz = wsp<double>(pl, pl.o_ptmp);
   conv->assign(nc, 0);
   if (conv_iter) conv_iter->assign(nc, 0);
-  std::vector<double> hbeta(nc), hscal(2 * nc), hact(nc), htol(nc), href(nc);
+  std::vector<double> hbeta(nc), hact(nc), htol(nc), href(nc);
   for (int c = 0; c < nc; ++c) {
     htol[c] = tol[c];
     href[c] = ref[c];
@@ -518,63 +533,88 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, int prec, const double* r
                        K.comp, K.scal(SC_ACTIVE), K.V);
     hipLaunchKernelGGL(k_init_seg, dim3(1), dim3(64), 0, st, nc, K.giv, K.gstride, ld,
                        K.scal(SC_BETA), K.scal(SC_KFIN));
-    int j = 0;
-    for (; j < m && *iters < max_iter; ++j) {
-      double* vj = K.V + (size_t)j * n;
-      double* vn = K.V + (size_t)(j + 1) * n;
-      if (prec) {
-        rc = apply_precond(pl, st, vj, pz, prec == 2, false);
-        if (!rc) rc = op(pz, K.w);
-      } else {
-        rc = op(vj, K.w);
-      }
-      if (rc) return rc;
-      // CGS2: two passes of classical Gram-Schmidt, per system
-      rc = K.dots(K.V, j + 1, K.w, K.hbuf);
-      if (rc) return rc;
-      hipLaunchKernelGGL(k_sub_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n,
-                         K.hbuf, ld, K.comp, K.w);
-      rc = K.dots(K.V, j + 1, K.w, K.h2buf);
-      if (rc) return rc;
-      hipLaunchKernelGGL(k_sub_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n,
-                         K.h2buf, ld, K.comp, K.w);
-      hipLaunchKernelGGL(k_axpy, dim3(nblocks((int64_t)nc * ld, T)), dim3(T), 0, st, 1.0, K.h2buf,
-                         (int64_t)nc * ld, K.hbuf);
-      rc = K.norm(K.w, K.scal(SC_HN));
-      if (rc) return rc;
-      hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.w, n, K.scal(SC_HN),
-                         K.comp, K.scal(SC_ACTIVE), vn);
-      hipLaunchKernelGGL(k_givens_seg, dim3(1), dim3(64), 0, st, nc, j, ld, K.hbuf, K.H, K.giv,
-                         K.gstride, K.sc);
-      PBTC_LAUNCH_CHECK();
-      // residual estimates and active flags of every system
-      if (!K.host(K.scal(SC_RES), hscal.data(), 2 * nc)) {
-        pl.err = "GMRES: copy failed";
-        return PBTC_EDEVICE;
-      }
+    // The residual estimates of iteration j are read on the host while
+    // iteration j + 1 already runs: each iteration's [residual, active]
+    // pair is copied to pinned memory behind its Givens step.  If iteration j
+    // turns out to be the last, the queued iteration j + 1 changes nothing
+    // that is used (every system is inactive: no Givens update, zero basis
+    // vector, kfin already fixed).
+    if (!K.pinned(2 * nc)) {
+      pl.err = "GMRES: pinned host buffer or event unavailable";
+      return PBTC_EDEVICE;
+    }
+    int j = 0, done = 0, still = nact;
+    auto process = [&](int slot) -> int {
+      const double* hs = pl.res_pin + (size_t)slot * 2 * nc;
       ++*iters;
       double worst = 0.0;
-      int still = 0;
+      int left = 0;
       for (int c = 0; c < nc; ++c) {
-        const double res = hscal[c];
+        const double res = hs[c];
         if (!std::isfinite(res)) {
           pl.err = "GMRES: residual estimate is not finite";
-          return PBTC_EDEVICE;
+          return -1;
         }
         if (hact[c] > 0.0) worst = std::max(worst, res);
-        if (hact[c] > 0.0 && hscal[nc + c] == 0.0) {
+        if (hact[c] > 0.0 && hs[nc + c] == 0.0) {
           (*conv)[c] = 1;
           if (conv_iter) (*conv_iter)[c] = *iters;
         }
-        hact[c] = hscal[nc + c];
-        still += hact[c] > 0.0;
+        hact[c] = hs[nc + c];
+        left += hact[c] > 0.0;
       }
       if (hist) hist->push_back(worst);
-      if (still == 0) {
+      return left;
+    };
+    while (true) {
+      const bool launch = j < m && *iters + (j - done) < max_iter && still > 0;
+      if (launch) {
+        double* vj = K.V + (size_t)j * n;
+        double* vn = K.V + (size_t)(j + 1) * n;
+        if (prec) {
+          rc = apply_precond(pl, st, vj, pz, prec == 2, false);
+          if (!rc) rc = op(pz, K.w);
+        } else {
+          rc = op(vj, K.w);
+        }
+        if (rc) return rc;
+        // CGS2: two passes of classical Gram-Schmidt, per system
+        rc = K.dots(K.V, j + 1, K.w, K.hbuf);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_sub_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n,
+                           K.hbuf, ld, K.comp, K.w);
+        rc = K.dots(K.V, j + 1, K.w, K.h2buf);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_sub_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n,
+                           K.h2buf, ld, K.comp, K.w);
+        hipLaunchKernelGGL(k_axpy, dim3(nblocks((int64_t)nc * ld, T)), dim3(T), 0, st, 1.0,
+                           K.h2buf, (int64_t)nc * ld, K.hbuf);
+        rc = K.norm(K.w, K.scal(SC_HN));
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.w, n,
+                           K.scal(SC_HN), K.comp, K.scal(SC_ACTIVE), vn);
+        hipLaunchKernelGGL(k_givens_seg, dim3(1), dim3(64), 0, st, nc, j, ld, K.hbuf, K.H, K.giv,
+                           K.gstride, K.sc);
+        PBTC_LAUNCH_CHECK();
+        // residual estimates and active flags of every system (SC_RES, SC_ACTIVE)
+        PBTC_HIP(hipMemcpyAsync(pl.res_pin + (size_t)(j & 1) * 2 * nc, K.scal(SC_RES), 16 * nc,
+                                hipMemcpyDeviceToHost, st));
+        PBTC_HIP(hipEventRecord(pl.res_ev[j & 1], st));
         ++j;
-        break;
       }
+      // process the older iteration once two are queued, or drain
+      if (done < j && (j - done > 1 || !launch)) {
+        PBTC_HIP(hipEventSynchronize(pl.res_ev[done & 1]));
+        still = process(done & 1);
+        ++done;
+        if (still < 0) return PBTC_EDEVICE;
+        if (still == 0) break;
+        continue;
+      }
+      if (!launch) break;
     }
+    *discarded += j - done;  // a queued iteration after the last one
+    j = done;                // columns formed for the systems still active
     hipLaunchKernelGGL(k_finish_seg, dim3(1), dim3(64), 0, st, nc, std::min(j, m), ld, K.H, K.giv,
                        K.gstride, K.sc);
     if (prec) {
@@ -671,8 +711,10 @@ int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* 
         }
       }
       std::vector<int> cin;
+      int disc = 0;
       rc = gmres(pl, st, op32, prec, r, d, true, tin, rref, pl.prm.max_iter, &iters, hist, &cin,
-                 nullptr);
+                 nullptr, &disc);
+      n32 -= disc;  // operator evaluations whose results were not used
       if (rc) return rc;
       hipLaunchKernelGGL(k_axpy, dim3(nblocks(n, T)), dim3(T), 0, st, 1.0, d, n, x);
       rc = explicit_residual();
@@ -687,12 +729,14 @@ int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* 
     for (int c = 0; c < nc; ++c) conv[c] = rel[c] <= pl.prm.tol;
   } else {
     const int opp = pl.prm.precision == PBTC_FP64 ? PBTC_FP64 : PBTC_FP32;
+    int disc = 0;
     if (opp == PBTC_FP64)
       rc = gmres(pl, st, op64, prec, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv,
-                 &cit);
+                 &cit, &disc);
     else
       rc = gmres(pl, st, op32, prec, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv,
-                 &cit);
+                 &cit, &disc);
+    (opp == PBTC_FP64 ? n64 : n32) -= disc;  // evaluations whose results were not used
     if (rc) return rc;
     rc = explicit_residual();
     if (rc) return rc;

@@ -506,7 +506,9 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
                      src);
   PBTC_LAUNCH_CHECK();
   const bool tree = pl.prm.op == PBTC_OP_TREECODE;
-  const bool timed = sizeof(real) == 4 && phase == 0;
+  bool timed = false;
+  if (sizeof(real) == 4 && phase == 0 && pl.prm.profile > 0)
+    timed = pl.prof_count++ % pl.prm.profile == 0;
   if (tree) {
     int rc = launch_moments<real>(pl, st, mom, src);
     if (rc) return rc;

@@ -147,6 +147,7 @@ std::string validate_problem(const pbtc_problem& p, const pbtc_params& prm, int*
   if (prm.op != PBTC_OP_TREECODE && prm.op != PBTC_OP_DIRECT) return fail(PBTC_EINVAL, "unknown op");
   if (!(prm.inner_tol > 0.0 && prm.inner_tol < 1.0)) return fail(PBTC_EINVAL, "inner_tol must be in (0, 1)");
   if (prm.max_refine < 1) return fail(PBTC_EINVAL, "max_refine must be >= 1");
+  if (prm.profile < 0) return fail(PBTC_EINVAL, "profile must be >= 0");
   if (prm.precond != PBTC_PREC_NONE && prm.precond != PBTC_PREC_BLOCK_DIAG)
     return fail(PBTC_EINVAL, "unknown precond");
   // regions
