@@ -34,7 +34,6 @@
 
 #include "device_util.h"
 #include "kernel_common.h"
-#include "moments.h"
 #include "traverse.h"
 #include "taylor.h"
 
@@ -243,92 +242,109 @@ __global__ void k_adj_src(const int* __restrict__ blist, const DevBlock* __restr
   asrc[b.nf_row + j] = s;
 }
 
-// Moments of mu about the centre of every leaf of the block's target tree:
-// mS[k] = sum muS (x - c)^k, mD[k] = sum muD (x - c)^k, for kernel slot ks.
+// Moments of mu about the centre of every cell of a block's target tree,
+// all levels at once: mS[k] = sum muS (x - c)^k and mD[k] = sum muD (x - c)^k
+// over the collocation points x of the cell, for one kernel slot.  One block
+// per chunk (cell, first source, count <= kMomSpan, slot), sources staged
+// through LDS kMomChunk at a time; a second launch sums each (cell, slot)
+// pair's chunks in chunk order into mom[(cell * nrec + local slot) * 2 N].
+constexpr int kAMomThreads = 256;
+
 template <typename real, int P>
-__global__ __launch_bounds__(128) void k_adj_p2m(const Cell* __restrict__ cells,
-                                                 const int* __restrict__ slot_block,
-                                                 const int* __restrict__ slot_kidx,
-                                                 const int* __restrict__ tslot,
-                                                 const DevBlock* __restrict__ blocks,
-                                                 const Src<real>* __restrict__ asrc,
-                                                 real* __restrict__ mom, int nrec) {
+__global__ __launch_bounds__(kAMomThreads) void k_adj_p2m_chunk(
+    const int4* __restrict__ chunks, const Cell* __restrict__ cells,
+    const int* __restrict__ slot_block, const int* __restrict__ slot_kidx,
+    const DevBlock* __restrict__ blocks, const Src<real>* __restrict__ asrc,
+    real* __restrict__ part) {
   constexpr int N = ncoef(P);
-  constexpr MultiIndex<P> T{};
-  __shared__ real pw[128][3][P + 1];
-  __shared__ real sq[128][2];
-  const int c = blockIdx.x;
-  const Cell cl = cells[c];
-  if (cl.nchild != 0) return;
-  // blockIdx.y: local slot of the cell's tree
-  const int slot = tslot[(size_t)cl.surf * nrec + blockIdx.y];
-  if (slot < 0) return;
-  const DevBlock b = blocks[slot_block[slot]];
-  const int kid = slot_kidx[slot];
-  constexpr int KPT = (N + 127) / 128;  // coefficients per thread
+  constexpr int G = N <= kAMomThreads ? kAMomThreads / N : 1;
+  constexpr int KPT = (N + kAMomThreads - 1) / kAMomThreads;
+  static_assert(kMomChunk <= kAMomThreads, "one source per thread while staging");
+  __shared__ real pw[kMomChunk][3][P + 1];
+  __shared__ real sw[kMomChunk][2];
+  __shared__ real red[G][2 * N];
+  const int4 ch = chunks[blockIdx.x];
+  const Cell& cl = cells[ch.x];
+  const DevBlock& b = blocks[slot_block[ch.w]];
+  const int kid = slot_kidx[ch.w];
   const real cx = (real)cl.cx, cy = (real)cl.cy, cz = (real)cl.cz;
+  const int tid = threadIdx.x;
+  const int g = N <= kAMomThreads ? tid / N : 0;
+  int kk[KPT][3];
+  bool on[KPT];
   real ms[KPT], md[KPT];
 #pragma unroll
-  for (int q = 0; q < KPT; ++q) ms[q] = md[q] = 0;
-  for (int base = cl.begin; base < cl.begin + cl.count; base += 128) {
-    const int nj = min(128, cl.begin + cl.count - base);
-    if (threadIdx.x < nj) {
-      const Src<real> s = asrc[b.nf_row + (base + threadIdx.x - b.tgt_off)];
+  for (int q = 0; q < KPT; ++q) {
+    const int k = N <= kAMomThreads ? tid - g * N : tid + q * kAMomThreads;
+    on[q] = N <= kAMomThreads ? tid < G * N : k < N;
+    mindex_inv(on[q] ? k : 0, kk[q][0], kk[q][1], kk[q][2]);
+    ms[q] = md[q] = 0;
+  }
+  for (int b0 = 0; b0 < ch.z; b0 += kMomChunk) {
+    const int nj = min(kMomChunk, ch.z - b0);
+    if (tid < nj) {
+      const Src<real> s = asrc[b.nf_row + (ch.y + b0 + tid - b.tgt_off)];
       const real d[3] = {s.x - cx, s.y - cy, s.z - cz};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         real v = 1;
 #pragma unroll
         for (int e = 0; e <= P; ++e) {
-          pw[threadIdx.x][a][e] = v;
+          pw[tid][a][e] = v;
           v *= d[a];
         }
       }
-      sq[threadIdx.x][0] = kid == 0 ? s.q : s.py;
-      sq[threadIdx.x][1] = kid == 0 ? s.px : s.pz;
+      sw[tid][0] = kid == 0 ? s.q : s.py;
+      sw[tid][1] = kid == 0 ? s.px : s.pz;
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
-      const int k = threadIdx.x + 128 * q;
-      if (k < N) {
-        const int k1 = T.k1[k], k2 = T.k2[k], k3 = T.k3[k];
-        for (int t = 0; t < nj; ++t) {
-          const real m = pw[t][0][k1] * pw[t][1][k2] * pw[t][2][k3];
-          ms[q] += sq[t][0] * m;
-          md[q] += sq[t][1] * m;
-        }
+      if (!on[q]) continue;
+      const int k1 = kk[q][0], k2 = kk[q][1], k3 = kk[q][2];
+      for (int t = g; t < nj; t += G) {
+        const real m = pw[t][0][k1] * pw[t][1][k2] * pw[t][2][k3];
+        ms[q] += sw[t][0] * m;
+        md[q] += sw[t][1] * m;
       }
     }
     __syncthreads();
   }
-  real* M = mom + ((size_t)c * nrec + b.lslot0 + kid) * 2 * N;
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
-    const int k = threadIdx.x + 128 * q;
-    if (k < N) {
-      M[k] = ms[q];
-      M[N + k] = md[q];
-    }
+    if (!on[q]) continue;
+    const int k = N <= kAMomThreads ? tid - g * N : tid + q * kAMomThreads;
+    red[g][k] = ms[q];
+    red[g][N + k] = md[q];
+  }
+  __syncthreads();
+  for (int k = tid; k < 2 * N; k += kAMomThreads) {
+    real v = 0;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) v += red[gg][k];
+    part[(size_t)blockIdx.x * 2 * N + k] = v;
   }
 }
 
-// Upward pass of the transposed treecode (same binomial shift as forward).
+// mom[pair.x] = sum of the pair's chunks [pair.y, pair.z), in order
 template <typename real, int P>
-__global__ __launch_bounds__(kM2MThreads) void k_adj_m2m(const Cell* __restrict__ cells, int c0,
-                                                         const int* __restrict__ slot_block,
-                                                         const int* __restrict__ tslot,
-                                                         const DevBlock* __restrict__ blocks,
-                                                         real* __restrict__ mom, int ms) {
-  constexpr int N = ncoef(P);
-  const int c = c0 + blockIdx.x;
-  const Cell cl = cells[c];
-  if (cl.nchild == 0) return;
-  const int slot = tslot[(size_t)cl.surf * ms + blockIdx.y];
-  if (slot < 0) return;
-  const DevBlock b = blocks[slot_block[slot]];
-  const int kid = slot - b.slot0;
-  m2m_cell<real, P>(cells, cl, c, mom + (size_t)(b.lslot0 + kid) * 2 * N, (size_t)ms * 2 * N);
+__global__ __launch_bounds__(256) void k_adj_mom_sum(const int4* __restrict__ pairs,
+                                                     const real* __restrict__ part,
+                                                     real* __restrict__ mom) {
+  constexpr int N2 = 2 * ncoef(P);
+  const int4 pr = pairs[blockIdx.x];
+  for (int k = threadIdx.x; k < N2; k += 256) {
+    real v = 0;
+    int j = pr.y;
+    for (; j + 4 <= pr.z; j += 4) {
+      real a[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = part[(size_t)(j + i) * N2 + k];
+      v += (a[0] + a[1]) + (a[2] + a[3]);
+    }
+    for (; j < pr.z; ++j) v += part[(size_t)j * N2 + k];
+    mom[(size_t)pr.x * N2 + k] = v;
+  }
 }
 
 struct AdjArgs {
@@ -723,7 +739,7 @@ int adjoint_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
       PBTC_HIP(hipMemcpy(nl.data(), wsp<int>(pl, pl.o_anear), 4 * pl.n_anear, hipMemcpyDeviceToHost));
     PBTC_HIP(hipMemcpy(hc.data(), wsp<Cell>(pl, pl.o_tcells), sizeof(Cell) * pl.n_tcells,
                        hipMemcpyDeviceToHost));
-    constexpr int kUnitSources = 1024, kUnitCells = 32;
+    constexpr int kUnitSources = 512, kUnitCells = 32;  // as the forward units
     std::vector<int4> units;
     std::vector<int> uptr;
     const bool tree = pl.prm.op == PBTC_OP_TREECODE;
@@ -765,6 +781,40 @@ int adjoint_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     }
     PBTC_HIP(hipMemcpy(wsp<int4>(pl, pl.o_aunits), units.data(), 16 * units.size(), hipMemcpyHostToDevice));
     PBTC_HIP(hipMemcpy(wsp<int>(pl, pl.o_auptr), uptr.data(), 4 * uptr.size(), hipMemcpyHostToDevice));
+
+    // direct moment pass: per phase, every (cell, slot of its tree) pair's
+    // sources in chunks of at most kMomSpan
+    std::vector<int4> amch, amp;
+    const int ms = pl.adj_ms;
+    for (int ph = 0; ph < 2; ++ph) {
+      pl.am_chunk_off[ph] = (int64_t)amch.size();
+      pl.am_pair_off[ph] = (int64_t)amp.size();
+      const std::vector<int>& ts = pl.adj_tslot_host[ph];
+      for (int64_t c = 0; c < pl.n_tcells; ++c) {
+        if (hc[c].count == 0) continue;
+        for (int l = 0; l < ms; ++l) {
+          const int slot = ts[(size_t)hc[c].surf * ms + l];
+          if (slot < 0) continue;
+          const int first = (int)amch.size();
+          for (int o = 0; o < hc[c].count; o += kMomSpan)
+            amch.push_back(make_int4((int)c, hc[c].begin + o, std::min(kMomSpan, hc[c].count - o), slot));
+          amp.push_back(make_int4((int)(c * ms + l), first, (int)amch.size(), 0));
+        }
+      }
+    }
+    pl.am_chunk_off[2] = (int64_t)amch.size();
+    pl.am_pair_off[2] = (int64_t)amp.size();
+    if ((int64_t)amch.size() > pl.cap_amchunks || (int64_t)amp.size() > pl.cap_ampairs) {
+      pl.cap_amchunks = std::max<int64_t>(pl.cap_amchunks, (int64_t)amch.size() + 1024);
+      pl.cap_ampairs = std::max<int64_t>(pl.cap_ampairs, (int64_t)amp.size() + 64);
+      *need_retry = 1;
+      pl.err = "adjoint moment chunks exceed the workspace estimate";
+      return PBTC_EWORKSPACE;
+    }
+    if (!amch.empty())
+      PBTC_HIP(hipMemcpy(wsp<int4>(pl, pl.o_amchunks), amch.data(), 16 * amch.size(), hipMemcpyHostToDevice));
+    if (!amp.empty())
+      PBTC_HIP(hipMemcpy(wsp<int4>(pl, pl.o_ampairs), amp.data(), 16 * amp.size(), hipMemcpyHostToDevice));
   }
   // transposed near-field table (CSC by (block, panel)), deterministic order
   {
@@ -883,24 +933,27 @@ static void launch_adj_m2p(pbtc_plan& pl, hipStream_t st, const AdjArgs& a, int 
 
 template <typename real>
 static int adj_moments(pbtc_plan& pl, hipStream_t st, int phase, real* mom) {
-  if (pl.adj_sids[phase].empty()) return PBTC_OK;
+  const int64_t c0 = pl.am_chunk_off[phase], c1 = pl.am_chunk_off[phase + 1];
+  const int64_t p0 = pl.am_pair_off[phase], p1 = pl.am_pair_off[phase + 1];
+  if (p1 == p0) return PBTC_OK;
   const Cell* cells = wsp<Cell>(pl, pl.o_tcells);
-  const int* ts = wsp<int>(pl, pl.o_adj_tslot[phase]);
+  const int4* chunks = wsp<int4>(pl, pl.o_amchunks) + c0;
+  const int4* pairs = wsp<int4>(pl, pl.o_ampairs) + p0;
   const int* sb = wsp<int>(pl, pl.o_slot_block);
   const int* sk = wsp<int>(pl, pl.o_slot_kidx);
   const DevBlock* blocks = wsp<DevBlock>(pl, pl.o_blocks);
   const Src<real>* asrc = wsp<Src<real>>(pl, sizeof(real) == 4 ? pl.o_asrc32 : pl.o_asrc64);
-  const int ms = pl.adj_ms;  // moment records per cell
-#define PBTC_AMOM(PP)                                                                          \
-  case PP:                                                                                     \
-    hipLaunchKernelGGL((k_adj_p2m<real, PP>), dim3((unsigned)pl.n_tcells, ms), dim3(128), 0, st, \
-                       cells, sb, sk, ts, blocks, asrc, mom, ms);                              \
-    for (int l = pl.n_tlevels - 1; l >= 0; --l) {                                              \
-      const int lb = pl.tlevel_begin[l], le = pl.tlevel_begin[l + 1];                          \
-      if (le > lb)                                                                             \
-        hipLaunchKernelGGL((k_adj_m2m<real, PP>), dim3(le - lb, ms), dim3(kM2MThreads), 0, st, \
-                           cells, lb, sb, ts, blocks, mom, ms);                                \
-    }                                                                                          \
+  // partial moments of this phase's chunks (chunk ids are global; the
+  // pairs' ranges index the same global table)
+  real* part = wsp<real>(pl, pl.o_ampart);
+#define PBTC_AMOM(PP)                                                                           \
+  case PP:                                                                                      \
+    if (c1 > c0)                                                                                \
+      hipLaunchKernelGGL((k_adj_p2m_chunk<real, PP>), dim3((unsigned)(c1 - c0)),                \
+                         dim3(kAMomThreads), 0, st, chunks, cells, sb, sk, blocks, asrc,        \
+                         part + (size_t)c0 * 2 * ncoef(PP));                                    \
+    hipLaunchKernelGGL((k_adj_mom_sum<real, PP>), dim3((unsigned)(p1 - p0)), dim3(256), 0, st,  \
+                       pairs, part, mom);                                                       \
     break;
   switch (pl.P) {
     PBTC_AMOM(2)
@@ -909,6 +962,7 @@ static int adj_moments(pbtc_plan& pl, hipStream_t st, int phase, real* mom) {
     PBTC_AMOM(8)
     PBTC_AMOM(10)
     default:
+      pl.err = "unsupported P";
       return PBTC_EINVAL;
   }
 #undef PBTC_AMOM

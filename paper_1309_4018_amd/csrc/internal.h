@@ -212,6 +212,12 @@ struct pbtc_plan {
   size_t o_coul = 0;   // Coulomb energy per system (ncomp double)
   size_t o_mchunks = 0, o_mcell = 0, o_mpart = 0;  // direct moment pass: chunks, per-cell chunk ranges, partial moments
   int64_t cap_mchunks = 0, n_mchunks = 0;
+  // direct moment pass of the transposed operator: chunks (cell, first
+  // source, count, slot) and (cell x local slot, first chunk, end chunk)
+  // pairs, per phase in [off[ph], off[ph + 1])
+  size_t o_amchunks = 0, o_ampairs = 0, o_ampart = 0;
+  int64_t cap_amchunks = 0, cap_ampairs = 0;
+  int64_t am_chunk_off[3] = {0, 0, 0}, am_pair_off[3] = {0, 0, 0};
   std::vector<double> ptab_host;  // host copy of the o_ptab table
   std::vector<double> qtab_host;  // host copy of the o_qtab table
   size_t o_tx, o_ty, o_tz, o_tidx;                               // sorted targets (FP64) + perm

@@ -465,6 +465,9 @@ int build_plan(pbtc_plan& pl) {
   if (pl.cap_auptr == 0) pl.cap_auptr = 2 * pl.nitems_adj + 64;
   if (pl.cap_tcells == 0) pl.cap_tcells = pl.ntgt / 16 + 64 * (int64_t)pl.tsets.size() + 1024;
   if (pl.cap_anear == 0) pl.cap_anear = 48 * pl.nitems_adj + 1024;
+  if (pl.cap_amchunks == 0)
+    pl.cap_amchunks = (pl.cap_tcells + 8 * pl.ntgt / kMomSpan + 1024) * pl.adj_ms;
+  if (pl.cap_ampairs == 0) pl.cap_ampairs = pl.cap_tcells * pl.adj_ms + 64;
   if (pl.cap_afar == 0) pl.cap_afar = (pl.prm.op == PBTC_OP_DIRECT ? 1 : 160) * pl.nitems_adj + 1024;
   if (pl.cap_nf == 0) {
     int64_t n = 0;
@@ -639,6 +642,9 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_tcnt = L.add(8 * (pl.cap_tcells + 1));
   pl.o_amom32 = L.add(4 * 2 * nP * pl.cap_tcells * pl.adj_ms);
   pl.o_amom64 = L.add(8 * 2 * nP * pl.cap_tcells * pl.adj_ms);
+  pl.o_amchunks = L.add(16 * pl.cap_amchunks);
+  pl.o_ampairs = L.add(16 * pl.cap_ampairs);
+  pl.o_ampart = L.add(8 * 2 * nP * pl.cap_amchunks);
   pl.o_anear = L.add(4 * pl.cap_anear);
   pl.o_units = L.add(16 * pl.cap_units);
   pl.o_uptr = L.add(4 * (2 * pl.nitems + 64));
