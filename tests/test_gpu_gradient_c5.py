@@ -1,0 +1,102 @@
+"""Gradients of the three-region system (protein, Stern layer, solvent,
+two cavities) at 5,120 + 5,120 + 2 x 512 panels and 4,000 charges.
+
+* The adjoint gradient of the direct FP64 operator (an exact transpose)
+  against central differences of the GPU energy with step 1e-4 on 20
+  charges picked by seed 5 (dE/dq), on kappa of the solvent and on eps_out,
+  the one permittivity shared by the Stern layer, the solvent and the
+  cavities (dE/deps_out = the sum of their per-region derivatives).
+  The energy is quadratic in q, so the charge differences are exact up to
+  rounding and the solve tolerance (1e-11): 1e-6 relative.
+* The FP32-refined treecode adjoint (theta 0.5, P 8) against the direct
+  FP64 gradients: 2e-3 relative (treecode truncation of two solves).
+"""
+
+import copy
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS_OUT = ("stern", "solvent", "cavity1", "cavity2")
+
+
+@pytest.fixture(scope="module")
+def c5():
+    return synth.config5_small()
+
+
+@pytest.fixture(scope="module")
+def direct(c5, gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    pl = lib.plan_for(c5, op="direct", precision="fp64", tol=1e-11, max_iter=5000,
+                      precond="block_diag")
+    e0 = pl.solve()["energy_kJmol"]
+    dq, dk, de = pl.backward()
+    return pl, e0, dq, dk, de
+
+
+def _energy(prob, **kw):
+    from paper_1309_4018_amd import lib
+
+    return lib.plan_for(prob, **kw).solve()["energy_kJmol"]
+
+
+def test_charge_gradient_fd(c5, direct):
+    pl, e0, dq, dk, de = direct
+    q0 = np.concatenate([c5.charges[r][1] for r in sorted(c5.charges)])
+    idx = np.random.default_rng(5).choice(len(q0), size=20, replace=False)
+    h = 1e-4
+    for k in idx:
+        ep = []
+        for sg in (1, -1):
+            q = q0.copy()
+            q[k] += sg * h
+            pl.set_charge_values(q)
+            ep.append(pl.solve()["energy_kJmol"])
+        fd = (ep[0] - ep[1]) / (2 * h)
+        assert abs(dq[k] - fd) < 1e-6 * np.max(np.abs(dq)), (k, dq[k], fd)
+    pl.set_charge_values(q0)
+    assert abs(pl.solve()["energy_kJmol"] - e0) < 1e-10 * abs(e0)
+
+
+def test_kappa_and_eps_out_fd(c5, direct):
+    pl, e0, dq, dk, de = direct
+    kw = dict(op="direct", precision="fp64", tol=1e-11, max_iter=5000, precond="block_diag")
+    names = [r.name for r in c5.regions]
+    h = 1e-4
+    ek = []
+    for sg in (1, -1):
+        p2 = copy.deepcopy(c5)
+        p2.regions[names.index("solvent")].kappa += sg * h
+        ek.append(_energy(p2, **kw))
+    fd = (ek[0] - ek[1]) / (2 * h)
+    assert abs(dk[names.index("solvent")] - fd) < 1e-5 * abs(fd)
+    ee = []
+    for sg in (1, -1):
+        p2 = copy.deepcopy(c5)
+        for nm in EPS_OUT:
+            p2.regions[names.index(nm)].eps += sg * h
+        ee.append(_energy(p2, **kw))
+    fd = (ee[0] - ee[1]) / (2 * h)
+    grad = sum(de[names.index(nm)] for nm in EPS_OUT)
+    assert abs(grad - fd) < 1e-5 * abs(fd)
+
+
+def test_treecode_adjoint_matches_direct(c5, direct):
+    from paper_1309_4018_amd import lib
+
+    _, _, dq, dk, de = direct
+    pl = lib.plan_for(c5, precision="fp32_refined", tol=1e-8, theta=0.5, P=8, max_iter=5000,
+                      precond="block_diag")
+    pl.solve()
+    tq, tk, te = pl.backward()
+    assert np.max(np.abs(tq - dq)) < 2e-3 * np.max(np.abs(dq))
+    s = [i for i, r in enumerate(c5.regions) if r.kappa > 0]
+    for i in s:
+        assert abs(tk[i] - dk[i]) < 2e-3 * abs(dk[i])
+    assert np.max(np.abs(te - de)) < 2e-3 * np.max(np.abs(de))
