@@ -29,6 +29,7 @@ from .configs import (
     concentric_spheres,
     born_pair,
     star_pair,
+    ion_cavity_protein,
 )
 
 __all__ = [
@@ -52,4 +53,5 @@ __all__ = [
     "concentric_spheres",
     "born_pair",
     "star_pair",
+    "ion_cavity_protein",
 ]

@@ -258,3 +258,40 @@ def star_pair(gap=4.0, r_rec=14.0, r_lig=9.0, nu_rec=24, nu_lig=16, n_rec=600, n
             name=("receptor", "ligand")[k],
         ))
     return _pair(probs[0], probs[1], "star-pair")
+
+
+def ion_cavity_protein(nu=16, cav_nu=8, seed=7, n_charges=400, r0=20.0, shape_seed=2,
+                       stern=2.0, eps_out=80.0, kappa=0.125, ion_radius=3.0, cav_stern=1.5):
+    """Protein with a Stern layer, one solvent-filled cavity and one cavity
+    large enough to hold ions, with its own interior Stern layer.
+
+    Protein and Stern: as the multi-surface workload (star of ``shape_seed``
+    at ico ``nu``, Stern moved out by 2 A).  Solvent cavity: radius 3 A at
+    (-7, 0, 0).  Ion cavity at (7, 0, 0): an outer sphere of radius
+    ion_radius + cav_stern bounds its Stern shell (solvent eps, no ions),
+    an inner sphere of radius ion_radius bounds the ionic interior (solvent
+    eps and kappa).  Charges in the protein region, >= 2 A from every
+    surface.
+    """
+    shape = StarShape(r0, shape_seed)
+    vp, fp = star_surface(shape, nu, "ico")
+    vs = radial_offset(vp, stern)
+    regions = [
+        Region(4.0, 0.0, "protein"),
+        Region(eps_out, 0.0, "stern"),
+        Region(eps_out, kappa, "solvent"),
+        Region(eps_out, 0.0, "cavity"),
+        Region(eps_out, 0.0, "cavity_stern"),
+        Region(eps_out, kappa, "cavity_ions"),
+    ]
+    c_sol, c_ion = (-7.0, 0.0, 0.0), (7.0, 0.0, 0.0)
+    surfaces = [Surface(vp, fp, 0, 1, "SES"), Surface(vs, fp.copy(), 1, 2, "stern")]
+    v, f = geodesic_sphere("oct", cav_nu, 3.0, c_sol)
+    surfaces.append(Surface(v, f, 3, 0, "cavity"))
+    v, f = geodesic_sphere("oct", cav_nu, ion_radius + cav_stern, c_ion)
+    surfaces.append(Surface(v, f, 4, 0, "cavity_stern"))
+    v, f = geodesic_sphere("oct", cav_nu, ion_radius, c_ion)
+    surfaces.append(Surface(v, f, 5, 4, "cavity_ions"))
+    excl = [(c_sol, 3.0), (c_ion, ion_radius + cav_stern)]
+    x, q = star_interior_charges(shape, n_charges, seed, clearance=2.0, exclude=excl)
+    return Problem(regions, surfaces, {0: (x, q)}, name=f"ion-cavity-ico{nu}")

@@ -74,7 +74,7 @@ def test_solves_match_oracle(small, gpu_lib):
     assert abs(r["energy_kJmol"] - sol.energy) < 1e-4 * abs(sol.energy)
 
 
-@pytest.mark.parametrize("case", ["stern", "cavity"])
+@pytest.mark.parametrize("case", ["stern", "cavity", "ioncavity"])
 def test_concentric_spheres(gpu_lib, case):
     from paper_1309_4018_amd import lib
 
@@ -82,10 +82,33 @@ def test_concentric_spheres(gpu_lib, case):
     qq = np.array([1.0, -0.5, 0.7])
     if case == "stern":
         radii, eps, kap, creg, xc = [4.0, 6.0], [4, 80, 80], [0, 0, 0.125], 0, xq
-    else:
+    elif case == "cavity":
         radii, eps, kap, creg, xc = [2.0, 6.0], [80, 4, 80], [0, 0, 0.125], 1, xq * 1.25
+    else:  # ions inside a cavity with its own Stern layer
+        radii, eps, kap = [2.5, 4.0, 9.0, 11.0], [80, 80, 4, 80, 80], [0.125, 0, 0, 0, 0.125]
+        creg, xc = 2, xq * 2.3
     p = synth.concentric_spheres(radii, eps, kap, (xc, qq), creg, nu=8)
     ref = Oracle(p).solve(tol=1e-12).energy
     pl = lib.plan_for(p, precision="fp32_refined", tol=1e-7, theta=0.5, P=8)
     r = pl.solve()
     assert abs(r["energy_kJmol"] - ref) < 1e-4 * abs(ref)
+
+
+def test_ion_holding_cavity_protein(gpu_lib):
+    """Star protein, Stern layer, a solvent cavity and an ion-holding cavity
+    with its own Stern shell (six regions, five surfaces): GPU direct FP64
+    and FP32-refined treecode against the dense oracle."""
+    from paper_1309_4018_amd import lib
+
+    prob = synth.ion_cavity_protein(nu=8, cav_nu=4, n_charges=100)
+    o = Oracle(prob)
+    sol = o.solve(tol=1e-12)
+    x = np.random.default_rng(9).normal(size=o.n)
+    pd = lib.plan_for(prob, op="direct", precision="fp64", tol=1e-12, max_iter=4000)
+    pd.setup()
+    assert _rel(pd.matvec(x, lib.FP64).cpu().numpy(), sol.A @ x) < 1e-12
+    rd = pd.solve()
+    assert abs(rd["energy_kJmol"] - sol.energy) < 1e-9 * abs(sol.energy)
+    pt = lib.plan_for(prob, precision="fp32_refined", tol=1e-7, theta=0.5, P=8, max_iter=4000)
+    rt = pt.solve()
+    assert abs(rt["energy_kJmol"] - sol.energy) < 1e-4 * abs(sol.energy)

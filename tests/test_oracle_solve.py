@@ -135,3 +135,23 @@ def test_multisurface_concentric(case):
         errs.append(abs(Oracle(p).solve(tol=1e-10).energy - exact))
     assert errs[1] < errs[0] / 3.0
     assert errs[1] < 0.025 * abs(exact)
+
+
+def test_ion_holding_cavity_concentric():
+    """A cavity holding ions inside its own Stern layer (linearized PB in the
+    cavity): ionic ball r < 2.5, Stern shell to 4, protein shell to 9 with
+    the charges, Stern to 11, solvent.  The Richardson estimate from oct
+    nu = 4 and 8 (first order in panel area, panel ratio 4) matches the
+    layered closed form, and is much closer to it than to the same system
+    without ions in the cavity."""
+    xq = np.array([[0.0, 0.0, 2.8], [0.8, 2.0, -1.6], [-2.4, 0.8, 0.8]]) * 2.3
+    qq = np.array([1.0, -0.5, 0.7])
+    radii, eps, kap = [2.5, 4.0, 9.0, 11.0], [80, 80, 4, 80, 80], [0.125, 0, 0, 0, 0.125]
+    exact = cf.concentric(radii, eps, kap, 2, xq, qq)
+    no_ions = cf.concentric(radii, eps, [0, 0, 0, 0, 0.125], 2, xq, qq)
+    e = {nu: Oracle(synth.concentric_spheres(radii, eps, kap, (xq, qq), 2, nu=nu))
+         .solve(tol=1e-10).energy for nu in (4, 8)}
+    ext = richardson(e[8], e[4], 4.0, 1.0)
+    assert abs(e[8] - exact) < abs(e[4] - exact) / 3.0
+    assert abs(ext - exact) < 3e-3 * abs(exact)
+    assert abs(ext - no_ions) > 3.0 * abs(ext - exact)
