@@ -300,6 +300,9 @@ def main():
                    "precision": "fp32 bulk, fp64 refinement"},
         "solve_s": solve32,
         "setup_s": float(np.median([r["t_setup_s"] for r in results])),
+        "setup_phase_s": dict(zip(
+            ["sort", "octree", "lists", "near_field", "precond_rhs", "tables"],
+            np.median([r["t_setup_phase_s"] for r in results], axis=0).tolist())),
         "energy_kJmol": last["energy_kJmol"],
         "final_rel_res": last["final_rel_res"],
         "gmres_iterations": last["n_iter"],

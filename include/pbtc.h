@@ -147,6 +147,11 @@ typedef struct {
   double t_m2p_yuk_s;
   int n_m2p_yuk_launch;
   double m2p_yuk_flop;
+  /* host wall-clock split of the last device set-up (seconds): [0] panels,
+   * Gauss points and targets in Morton order, [1] octrees, [2] interaction
+   * lists, [3] near-field tables and values, [4] preconditioner blocks and
+   * Coulomb right-hand side, [5] work units and moment tables */
+  double t_setup_phase_s[6];
 } pbtc_result;
 
 /* Library version; never fails. */

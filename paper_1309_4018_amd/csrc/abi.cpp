@@ -84,7 +84,10 @@ int setup_impl(pbtc_plan* pl, void* ws, size_t bytes, hipStream_t st, pbtc_resul
     if (rc) return rc;
     pl->setup_done = true;
     pl->charges_dirty = false;
-    if (res) res->t_setup_s = wall_seconds() - t0;
+    if (res) {
+      res->t_setup_s = wall_seconds() - t0;
+      for (int k = 0; k < 6; ++k) res->t_setup_phase_s[k] = pl->setup_phase[k];
+    }
     fill_sizes(pl, res);
     return PBTC_OK;
   }

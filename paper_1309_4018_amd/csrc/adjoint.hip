@@ -50,6 +50,7 @@ int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, in
                    int phase);
 int recompute_near_values(pbtc_plan& pl, hipStream_t st);
 int recompute_rhs(pbtc_plan& pl, hipStream_t st);
+int upload_coulomb_rows(pbtc_plan& pl, hipStream_t st);
 int upload_descriptors(pbtc_plan& pl, hipStream_t st);
 template <typename Op>
 int krylov_solve(pbtc_plan& pl, hipStream_t st, Op op32, Op op64, const double* b, double* x,
@@ -566,21 +567,34 @@ __global__ void k_adj_gather(int64_t np, int K, const int* __restrict__ pan_surf
 }
 
 // (B^T lam)_k = sum over rows of the charge's region lam_i G(x_i, x_k) / eps
-__global__ void k_coulomb_t(long long q0, long long nq, const double* __restrict__ qxyz,
-                            const double* __restrict__ cx, const double* __restrict__ cy,
-                            const double* __restrict__ cz, long long pan_first, long long n,
-                            const double* __restrict__ lam, long long row_off, double inv_eps,
-                            double kappa, double* __restrict__ out) {
-  const long long k = q0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= q0 + nq) return;
-  double s = 0.0;
+// Transposed Coulomb term: out[k] += sum over the row blocks of charge k's
+// region of sum_i lam_i G(c_i - x_k) / eps (one wavefront per charge; lanes
+// stride over the rows, a fixed butterfly combines them).
+__global__ void k_coulomb_t_rows(long long nq, const DevCoulRow* __restrict__ rows,
+                                 const int* __restrict__ reg_ptr, const int* __restrict__ reg_rows,
+                                 const int* __restrict__ qreg, const double* __restrict__ qxyz,
+                                 const double* __restrict__ cx, const double* __restrict__ cy,
+                                 const double* __restrict__ cz, const double* __restrict__ lam,
+                                 double* __restrict__ out) {
+  const long long k = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (k >= nq) return;
+  const int lane = threadIdx.x & 63;
+  const int r = qreg[k];
   const double x = qxyz[3 * k], y = qxyz[3 * k + 1], zq = qxyz[3 * k + 2];
-  for (long long i = 0; i < n; ++i) {
-    const double dx = cx[pan_first + i] - x, dy = cy[pan_first + i] - y, dz = cz[pan_first + i] - zq;
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    s += lam[row_off + i] * (kappa == 0.0 ? 1.0 : exp(-kappa * r)) / r;
+  double s = 0.0, inv_eps = 0.0;
+  for (int e = reg_ptr[r]; e < reg_ptr[r + 1]; ++e) {
+    const DevCoulRow rb = rows[reg_rows[e]];
+    inv_eps = rb.inv_eps;
+    for (long long i = lane; i < rb.n; i += 64) {
+      const long long p = rb.pan_first + i;
+      const double dx = cx[p] - x, dy = cy[p] - y, dz = cz[p] - zq;
+      const double d = sqrt(dx * dx + dy * dy + dz * dz);
+      s += lam[rb.row_off + i] * (rb.kappa == 0.0 ? 1.0 : exp(-rb.kappa * d)) / d;
+    }
   }
-  out[k] += s * inv_eps * kInv4Pi;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) out[k] += s * inv_eps * kInv4Pi;
 }
 
 // dots[t] = sum_i a[offa_t + i] b[offb_t + i]   (one block per pair)
@@ -1091,21 +1105,35 @@ int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, i
   return transpose_impl<float>(pl, st, x, y, phase);
 }
 
-// sum over the listed (a offset, b offset, n) triples of a . b (device dots -> host)
+// sum over the listed (a offset, b offset, n) triples of a . b (device dots ->
+// host).  Long triples are cut into pieces of at most kDotPiece elements, one
+// work-group each, whose dots the host adds in piece order.
 static int pair_dots(pbtc_plan& pl, hipStream_t st, const std::vector<long long>& tab,
                      const double* A, const double* B, std::vector<double>* out) {
+  constexpr long long kDotPiece = 16384;
   out->assign(tab.size() / 3, 0.0);
   if (tab.empty()) return PBTC_OK;
+  std::vector<long long> pieces;
+  std::vector<int> owner;
+  for (size_t t = 0; t < tab.size() / 3; ++t) {
+    const long long oa = tab[3 * t], ob = tab[3 * t + 1], n = tab[3 * t + 2];
+    for (long long o = 0; o < n; o += kDotPiece) {
+      pieces.insert(pieces.end(), {oa + o, ob + o, std::min(kDotPiece, n - o)});
+      owner.push_back((int)t);
+    }
+  }
   long long* dtab = wsp<long long>(pl, pl.o_dots);
   double* dres = reinterpret_cast<double*>(dtab + 3 * 1024);
-  for (size_t base = 0; base < tab.size() / 3; base += 1024) {
-    const size_t cnt = std::min<size_t>(1024, tab.size() / 3 - base);
-    PBTC_HIP(hipMemcpyAsync(dtab, tab.data() + 3 * base, 8 * 3 * cnt, hipMemcpyHostToDevice, st));
+  std::vector<double> part(owner.size());
+  for (size_t base = 0; base < owner.size(); base += 1024) {
+    const size_t cnt = std::min<size_t>(1024, owner.size() - base);
+    PBTC_HIP(hipMemcpyAsync(dtab, pieces.data() + 3 * base, 8 * 3 * cnt, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_pair_dots, dim3((unsigned)cnt), dim3(kT), 0, st, dtab, A, B, dres);
     PBTC_LAUNCH_CHECK();
-    PBTC_HIP(hipMemcpyAsync(out->data() + base, dres, 8 * cnt, hipMemcpyDeviceToHost, st));
+    PBTC_HIP(hipMemcpyAsync(part.data() + base, dres, 8 * cnt, hipMemcpyDeviceToHost, st));
     PBTC_HIP(hipStreamSynchronize(st));
   }
+  for (size_t i = 0; i < owner.size(); ++i) (*out)[owner[i]] += part[i];
   return PBTC_OK;
 }
 
@@ -1135,15 +1163,16 @@ int device_backward(pbtc_plan& pl, hipStream_t st, double gE, double* dq, double
   // dG/dq = 1/2 C (phi_reac + B^T lam)
   double* g = wsp<double>(pl, pl.o_z2);
   PBTC_HIP(hipMemcpyAsync(g, wsp<double>(pl, pl.o_phi_reac), 8 * pl.nq, hipMemcpyDeviceToDevice, st));
-  for (const RowBlock& rb : pl.rows) {
-    const int r = rb.r;
-    const int64_t nqr = pl.prob.charges[r].n();
-    if (nqr == 0) continue;
-    hipLaunchKernelGGL(k_coulomb_t, dim3(nblocks(nqr, T)), dim3(T), 0, st,
-                       (long long)pl.q_off_region[r], (long long)nqr, wsp<double>(pl, pl.o_qxyz),
+  rc = upload_coulomb_rows(pl, st);
+  if (rc) return rc;
+  if (pl.nq > 0) {
+    const char* ct = wsp<char>(pl, pl.o_crows);
+    const int* reg_ptr = reinterpret_cast<const int*>(ct + sizeof(DevCoulRow) * pl.rows.size());
+    hipLaunchKernelGGL(k_coulomb_t_rows, dim3(nblocks(pl.nq, T / 64)), dim3(T), 0, st,
+                       (long long)pl.nq, reinterpret_cast<const DevCoulRow*>(ct), reg_ptr,
+                       reg_ptr + pl.nreg + 1, wsp<int>(pl, pl.o_qreg), wsp<double>(pl, pl.o_qxyz),
                        wsp<double>(pl, pl.o_cx), wsp<double>(pl, pl.o_cy), wsp<double>(pl, pl.o_cz),
-                       (long long)pl.pan_off[rb.t], (long long)rb.n, lam, (long long)rb.row_off,
-                       1.0 / pl.prob.regions[r].eps, pl.prob.regions[r].kappa, g);
+                       lam, g);
   }
   PBTC_LAUNCH_CHECK();
   std::vector<double> gq(pl.nq);
@@ -1211,46 +1240,76 @@ int device_backward(pbtc_plan& pl, hipStream_t st, double gE, double* dq, double
       deps[p] = 0.5 * C * (vS - vA + vB);
     }
   }
-  // kappa: central difference of the FP64 operator in kappa_p
+  // kappa: central difference of the FP64 Lagrangian in kappa_p.  Only the
+  // rows of region p (forward rows, their Coulomb terms, the reaction rows of
+  // its charges) depend on kappa_p, so the difference quotient of each region
+  // reads those rows alone.  All regions that share one kappa value are then
+  // perturbed together (their kernels are shared between blocks), and one
+  // pair of operator evaluations serves all of them (every molecule of a
+  // batch at once).
   std::vector<double> dkap(pl.nreg, 0.0);
+  std::vector<double> kvals;
   for (int p = 0; p < pl.nreg; ++p) {
     const double k0 = pl.prob.regions[p].kappa;
-    if (k0 == 0.0) continue;  // a Laplace region: kappa is not a parameter of its kernel
+    if (k0 != 0.0 && std::find(kvals.begin(), kvals.end(), k0) == kvals.end())
+      kvals.push_back(k0);
+  }
+  for (const double k0 : kvals) {
+    std::vector<int> group;
+    for (int p = 0; p < pl.nreg; ++p)
+      if (pl.prob.regions[p].kappa == k0) group.push_back(p);
+    std::vector<std::pair<int, int>> kern;  // (block, kernel) pairs evaluated with k0
+    for (size_t bi = 0; bi < pl.blocks.size(); ++bi)
+      for (int k = 0; k < pl.blocks[bi].nk; ++k)
+        if (pl.blocks[bi].kappa[k] == k0) kern.emplace_back((int)bi, k);
+    // restricted dots: q . phi over region p's charges, lam . (A x) and
+    // lam . b over region p's forward rows; owner = index into group
+    std::vector<long long> tq, tr;
+    std::vector<int> oq, orow;
+    for (size_t gi = 0; gi < group.size(); ++gi) {
+      const int p = group[gi];
+      const int64_t nqp = pl.prob.charges[p].n();
+      if (nqp > 0) {
+        tq.insert(tq.end(), {(long long)pl.q_off_region[p], (long long)pl.q_off_region[p],
+                             (long long)nqp});
+        oq.push_back((int)gi);
+      }
+      for (const RowBlock& rb : pl.rows)
+        if (rb.r == p) {
+          tr.insert(tr.end(), {(long long)rb.row_off, (long long)rb.row_off, (long long)rb.n});
+          orow.push_back((int)gi);
+        }
+    }
     const double h = 1e-4 * k0;
-    double val[2] = {0.0, 0.0};
+    std::vector<double> val[2];
+    auto set_kappa = [&](double kv) -> int {
+      for (int p : group) pl.prob.regions[p].kappa = kv;
+      for (const auto& bk : kern) pl.blocks[bk.first].kappa[bk.second] = kv;
+      int r2 = upload_descriptors(pl, st);
+      if (!r2) r2 = recompute_near_values(pl, st);
+      if (!r2) r2 = recompute_rhs(pl, st);
+      return r2;
+    };
     for (int side = 0; side < 2; ++side) {
-      const double kp = side == 0 ? k0 + h : k0 - h;
-      pl.prob.regions[p].kappa = kp;
-      for (Block& b : pl.blocks)
-        for (int k = 0; k < b.nk; ++k)
-          if (b.kappa[k] == (side == 0 ? k0 : k0 + h)) b.kappa[k] = kp;
-      rc = upload_descriptors(pl, st);
-      if (!rc) rc = recompute_near_values(pl, st);
-      if (!rc) rc = recompute_rhs(pl, st);
+      rc = set_kappa(side == 0 ? k0 + h : k0 - h);
       if (rc) return rc;
       double* phi = wsp<double>(pl, pl.o_z2);
       rc = apply_operator(pl, st, x, phi, PBTC_FP64, 1);
       if (!rc) rc = apply_operator(pl, st, x, y, PBTC_FP64, 0);
       if (rc) return rc;
-      std::vector<long long> t1 = {0, 0, (long long)pl.nq};
-      std::vector<long long> t2 = {0, 0, (long long)n};
       std::vector<double> r1, r2, r3;
-      rc = pair_dots(pl, st, t1, q, phi, &r1);
-      if (!rc) rc = pair_dots(pl, st, t2, lam, y, &r2);
-      if (!rc) rc = pair_dots(pl, st, t2, lam, wsp<double>(pl, pl.o_b), &r3);
+      rc = pair_dots(pl, st, tq, q, phi, &r1);
+      if (!rc) rc = pair_dots(pl, st, tr, lam, y, &r2);
+      if (!rc) rc = pair_dots(pl, st, tr, lam, wsp<double>(pl, pl.o_b), &r3);
       if (rc) return rc;
-      val[side] = r1[0] - r2[0] + r3[0];
+      val[side].assign(group.size(), 0.0);
+      for (size_t i = 0; i < oq.size(); ++i) val[side][oq[i]] += r1[i];
+      for (size_t i = 0; i < orow.size(); ++i) val[side][orow[i]] += r3[i] - r2[i];
     }
-    // restore kappa
-    pl.prob.regions[p].kappa = k0;
-    for (Block& b : pl.blocks)
-      for (int k = 0; k < b.nk; ++k)
-        if (b.kappa[k] == k0 - h) b.kappa[k] = k0;
-    rc = upload_descriptors(pl, st);
-    if (!rc) rc = recompute_near_values(pl, st);
-    if (!rc) rc = recompute_rhs(pl, st);
+    rc = set_kappa(k0);
     if (rc) return rc;
-    dkap[p] = 0.5 * C * (val[0] - val[1]) / (2.0 * h);
+    for (size_t gi = 0; gi < group.size(); ++gi)
+      dkap[group[gi]] = 0.5 * C * (val[0][gi] - val[1][gi]) / (2.0 * h);
   }
   // restore the forward outputs of x (phi_reac on the device)
   rc = apply_operator(pl, st, x, wsp<double>(pl, pl.o_phi_reac), PBTC_FP64, 1);

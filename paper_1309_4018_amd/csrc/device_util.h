@@ -24,6 +24,14 @@ void scan_exclusive(T* data, int64_t n, T* scratch, hipStream_t st);
 void radix_sort64(uint64_t* keys, int* vals, uint64_t* tmpk, int* tmpv, int* hist, int64_t n,
                   hipStream_t st);
 
+// The same sort of several segments at once: vals[i] must hold the element's
+// position i before sorting, and seg_off (device, nseg + 1 ascending offsets
+// covering [0, n)) delimits the segments; each segment ends up sorted in
+// place, exactly as a separate stable sort of it would leave it.  Extra passes
+// over the segment index follow the 8 key passes.
+void radix_sort64_seg(uint64_t* keys, int* vals, uint64_t* tmpk, int* tmpv, int* hist, int64_t n,
+                      const long long* seg_off, int nseg, hipStream_t st);
+
 #define PBTC_HIP(call)                                                        \
   do {                                                                        \
     hipError_t e_ = (call);                                                   \

@@ -146,6 +146,15 @@ struct DevRowTerm {
   double sigma_c, sigma;
 };
 
+// A forward row block as the Coulomb right-hand side and its transpose see
+// it: rows [row_off, row_off + n) of surface panels pan_first.., the charges
+// [q0, q0 + nq) of the row block's region, its 1/eps and kappa.
+struct DevCoulRow {
+  long long row_off, n, pan_first, q0, nq;
+  double inv_eps, kappa;
+  long long pad;
+};
+
 struct Cell {
   double cx, cy, cz;  // box centre (expansion centre y_c)
   double h;           // half edge of the box
@@ -220,6 +229,11 @@ struct pbtc_plan {
   int64_t am_chunk_off[3] = {0, 0, 0}, am_pair_off[3] = {0, 0, 0};
   std::vector<double> ptab_host;  // host copy of the o_ptab table
   std::vector<double> qtab_host;  // host copy of the o_qtab table
+  std::vector<long long> tset_off_host;  // first target of every target set, then ntgt
+  // Coulomb row table: DevCoulRow per forward row block, then per region the
+  // CSR (nreg + 1 int offsets, row block indices) of its row blocks
+  size_t o_crows = 0;
+  std::vector<char> crow_host;
   size_t o_tx, o_ty, o_tz, o_tidx;                               // sorted targets (FP64) + perm
   size_t o_txf, o_tyf, o_tzf;                                    // sorted targets FP32
   size_t o_grp;                                                  // group spheres (4 doubles)
@@ -259,7 +273,8 @@ struct pbtc_plan {
   // per kernel kind: 0 P2P, 1 Laplace M2P, 2 Yukawa M2P
   double prof_t[3] = {0, 0, 0}, prof_flop[3] = {0, 0, 0};
   int prof_n[3] = {0, 0, 0};
-  int64_t prof_count = 0;  // FP32 operator evaluations seen by the sampler
+  int64_t prof_count = 0;
+  double setup_phase[6] = {0, 0, 0, 0, 0, 0};  // host seconds per set-up phase  // FP32 operator evaluations seen by the sampler
   // GMRES residual readback: pinned host slots and their events
   double* res_pin = nullptr;
   int res_pin_n = 0;

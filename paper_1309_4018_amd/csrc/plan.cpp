@@ -574,8 +574,9 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_comp_q = L.add(4 * std::max<int64_t>(pl.nq, 1));
   // per system: H ((m+1)^2), Givens (4 (m+2)), scalars (16)
   pl.o_kstate = L.add(8 * (size_t)pl.ncomp * ((size_t)(m + 1) * (m + 1) + 4 * (m + 2) + 16));
-  pl.o_surf_tab = L.add(8 * (9 * (pl.nsurf + 1) + 16));
+  pl.o_surf_tab = L.add(8 * (9 * (pl.nsurf + 1) + pl.tsets.size() + 1 + 16));
   pl.o_dots = L.add(8 * 4096);
+  pl.o_crows = L.add(sizeof(DevCoulRow) * pl.rows.size() + 4 * (pl.nreg + 1 + pl.rows.size()) + 16);
   // transposed operator
   pl.o_gpos32 = L.add(4 * 8 * pl.ngp);
   pl.o_gpos64 = L.add(8 * 8 * pl.ngp);

@@ -99,14 +99,31 @@ __global__ void k_put_total(T* d, int64_t n, const T* sums, int64_t nt) {
 // ---------------------------------------------------------------- radix sort
 constexpr int kSortThreads = 256;  // one element per thread per tile
 
+// Digit of one element for the pass at bit `shift`: a byte of the key for
+// shift < 64, above that a byte of the element's segment (the largest s with
+// seg_off[s] <= val; the value is the element's position before sorting).
+__device__ __forceinline__ int sort_digit(uint64_t key, int val, int shift,
+                                          const long long* __restrict__ seg_off, int nseg) {
+  if (shift < 64) return (int)((key >> shift) & 255);
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg_off[mid] <= val) lo = mid;
+    else hi = mid - 1;
+  }
+  return (lo >> (shift - 64)) & 255;
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint64_t* __restrict__ keys,
+                                                             const int* __restrict__ vals,
                                                              int64_t n, int shift, int ntiles,
-                                                             int* __restrict__ hist) {
+                                                             const long long* __restrict__ seg_off,
+                                                             int nseg, int* __restrict__ hist) {
   __shared__ int h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
-  if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+  if (i < n) atomicAdd(&h[sort_digit(keys[i], shift < 64 ? 0 : vals[i], shift, seg_off, nseg)], 1);
   __syncthreads();
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
@@ -116,7 +133,8 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint64_t* __r
 // digit counts.
 __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
     const uint64_t* __restrict__ keys, const int* __restrict__ vals, int64_t n, int shift,
-    int ntiles, const int* __restrict__ offs, uint64_t* __restrict__ okeys, int* __restrict__ ovals) {
+    int ntiles, const long long* __restrict__ seg_off, int nseg, const int* __restrict__ offs,
+    uint64_t* __restrict__ okeys, int* __restrict__ ovals) {
   __shared__ int wave_cnt[kSortThreads / 64][256];
   for (int k = threadIdx.x; k < (kSortThreads / 64) * 256; k += kSortThreads)
     (&wave_cnt[0][0])[k] = 0;
@@ -124,7 +142,8 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
   const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
   const bool valid = i < n;
   const uint64_t key = valid ? keys[i] : 0;
-  const int digit = valid ? (int)((key >> shift) & 255) : 0;
+  const int val = valid ? vals[i] : 0;
+  const int digit = valid ? sort_digit(key, val, shift, seg_off, nseg) : 0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -142,7 +161,7 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
   for (int w = 0; w < wid; ++w) before += wave_cnt[w][digit];
   const int dst = offs[(int64_t)digit * ntiles + blockIdx.x] + before + rank;
   okeys[dst] = key;
-  ovals[dst] = vals[i];
+  ovals[dst] = val;
 }
 
 }  // namespace
@@ -165,9 +184,12 @@ void scan_exclusive(T* data, int64_t n, T* scratch, hipStream_t st) {
 template void scan_exclusive<int>(int*, int64_t, int*, hipStream_t);
 template void scan_exclusive<long long>(long long*, int64_t, long long*, hipStream_t);
 
-void radix_sort64(uint64_t* keys, int* vals, uint64_t* tmpk, int* tmpv, int* hist, int64_t n,
-                  hipStream_t st) {
+void radix_sort64_seg(uint64_t* keys, int* vals, uint64_t* tmpk, int* tmpv, int* hist, int64_t n,
+                      const long long* seg_off, int nseg, hipStream_t st) {
   if (n <= 1) return;
+  int seg_bits = 0;
+  while (nseg > 1 && (1ll << seg_bits) < nseg) ++seg_bits;
+  const int passes = 8 + (seg_bits + 7) / 8;
   const int ntiles = nblocks(n, kSortThreads);
   const int64_t nh = 256ll * ntiles;
   int* scratch = hist + nh + 1;
@@ -175,17 +197,25 @@ void radix_sort64(uint64_t* keys, int* vals, uint64_t* tmpk, int* tmpv, int* his
   int* src_v = vals;
   uint64_t* dst_k = tmpk;
   int* dst_v = tmpv;
-  for (int pass = 0; pass < 8; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     const int shift = 8 * pass;
-    hipLaunchKernelGGL(k_digit_hist, dim3(ntiles), dim3(kSortThreads), 0, st, src_k, n, shift,
-                       ntiles, hist);
+    hipLaunchKernelGGL(k_digit_hist, dim3(ntiles), dim3(kSortThreads), 0, st, src_k, src_v, n,
+                       shift, ntiles, seg_off, nseg, hist);
     scan_exclusive<int>(hist, nh, scratch, st);
     hipLaunchKernelGGL(k_digit_scatter, dim3(ntiles), dim3(kSortThreads), 0, st, src_k, src_v, n,
-                       shift, ntiles, hist, dst_k, dst_v);
+                       shift, ntiles, seg_off, nseg, hist, dst_k, dst_v);
     std::swap(src_k, dst_k);
     std::swap(src_v, dst_v);
   }
-  // 8 passes: the sorted data is back in keys/vals
+  if (src_k != keys) {
+    (void)hipMemcpyAsync(keys, src_k, 8 * n, hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(vals, src_v, 4 * n, hipMemcpyDeviceToDevice, st);
+  }
+}
+
+void radix_sort64(uint64_t* keys, int* vals, uint64_t* tmpk, int* tmpv, int* hist, int64_t n,
+                  hipStream_t st) {
+  radix_sort64_seg(keys, vals, tmpk, tmpv, hist, n, nullptr, 1, st);
 }
 
 }  // namespace pbtc

@@ -19,6 +19,7 @@
 //               lysozyme parameter table of sec. 3
 //   rhs         Coulomb right-hand side (Eq. matel, Q)
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 
 #include "device_util.h"
@@ -165,8 +166,8 @@ __global__ void k_target_keys(int64_t off, int64_t n, const double* __restrict__
                               int* __restrict__ idx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  key[i] = morton(x[i * stride], y[i * stride], z[i * stride], cx, cy, cz, h);
-  idx[i] = (int)(off + i);
+  key[off + i] = morton(x[i * stride], y[i * stride], z[i * stride], cx, cy, cz, h);
+  idx[off + i] = (int)(off + i);
 }
 
 __global__ void k_target_gather(int64_t off, int64_t n, const int* __restrict__ idx,
@@ -615,21 +616,31 @@ __global__ void k_prec_blocks(Tables T, int64_t np, const int* __restrict__ vert
 
 // ---------------------------------------------------------------------- rhs
 // b[row_off + i] = sum_k q_k / eps_r G_r(x_i, x_k) over the charges of r.
-__global__ void k_coulomb(int64_t n, long long row_off, long long pan_first,
-                          const double* __restrict__ cx, const double* __restrict__ cy,
-                          const double* __restrict__ cz, const double* __restrict__ qxyz,
-                          const double* __restrict__ q, long long q0, long long nq, double inv_eps,
-                          double kappa, double* __restrict__ b) {
+// Coulomb right-hand side of every forward row (one thread per unknown): the
+// row's block is found by bisection over the row offsets; rows whose region
+// holds no charges get 0.
+__global__ void k_coulomb_rows(int64_t n_unk, const DevCoulRow* __restrict__ rows, int nrows,
+                               const double* __restrict__ cx, const double* __restrict__ cy,
+                               const double* __restrict__ cz, const double* __restrict__ qxyz,
+                               const double* __restrict__ q, double* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double x = cx[pan_first + i], y = cy[pan_first + i], z = cz[pan_first + i];
+  if (i >= n_unk) return;
+  int lo = 0, hi = nrows - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rows[mid].row_off <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  const DevCoulRow rb = rows[lo];
+  const int64_t l = i - rb.row_off;
+  const double x = cx[rb.pan_first + l], y = cy[rb.pan_first + l], z = cz[rb.pan_first + l];
   double s = 0.0;
-  for (long long k = q0; k < q0 + nq; ++k) {
+  for (long long k = rb.q0; k < rb.q0 + rb.nq; ++k) {
     const double dx = x - qxyz[3 * k], dy = y - qxyz[3 * k + 1], dz = z - qxyz[3 * k + 2];
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    s += q[k] * (kappa == 0.0 ? 1.0 : exp(-kappa * r)) / r;
+    s += q[k] * (rb.kappa == 0.0 ? 1.0 : exp(-rb.kappa * r)) / r;
   }
-  b[row_off + i] = s * inv_eps * kInv4Pi;
+  b[i] = s * rb.inv_eps * kInv4Pi;
 }
 
 __global__ void k_fill_int(int* p, int64_t n, int v) {
@@ -733,6 +744,15 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   *need_retry = 0;
   const pbtc_problem& P = pl.prob;
   const int T = 256;
+  auto t_last = std::chrono::steady_clock::now();
+  auto phase_done = [&](int k) -> int {
+    PBTC_HIP(hipStreamSynchronize(st));
+    const auto t = std::chrono::steady_clock::now();
+    pl.setup_phase[k] = std::chrono::duration<double>(t - t_last).count();
+    t_last = t;
+    return PBTC_OK;
+  };
+  for (double& v : pl.setup_phase) v = 0.0;
   // ---- inputs (copied once per workspace; later set-ups reuse them)
   if (pl.inputs_ws != pl.ws) {
     std::vector<double> verts(3 * pl.nv_tot);
@@ -780,6 +800,7 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   double* cube = reinterpret_cast<double*>(pan_off + pl.nsurf + 1);
   double* reach = cube + 4 * pl.nsurf;
   long long* gp_first = reinterpret_cast<long long*>(reach + pl.nsurf);
+  long long* tset_off = gp_first + pl.nsurf + 1;
   long long* scan_scratch = wsp<long long>(pl, pl.o_red);
   {
     std::vector<long long> tab(3 * (pl.nsurf + 1));
@@ -799,6 +820,11 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     PBTC_HIP(hipMemcpyAsync(cube, cr.data(), 8 * cr.size(), hipMemcpyHostToDevice, st));
     PBTC_HIP(hipMemcpyAsync(gp_first, tab.data() + pl.nsurf + 1, 8 * (pl.nsurf + 1),
                             hipMemcpyHostToDevice, st));
+    std::vector<long long>& toff = pl.tset_off_host;
+    toff.assign(pl.tsets.size() + 1, pl.ntgt);
+    for (size_t ti = 0; ti < pl.tsets.size(); ++ti) toff[ti] = pl.tsets[ti].off;
+    PBTC_HIP(hipMemcpyAsync(tset_off, toff.data(), 8 * toff.size(), hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
   }
   SetupArgs sa;
   sa.verts = wsp<double>(pl, pl.o_verts);
@@ -826,11 +852,9 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   hipLaunchKernelGGL(k_gauss, dim3(nblocks(pl.ngp, T)), dim3(T), 0, st, sa, rule, pl.np_tot, cube,
                      gp_off, pan_off, key, order);
   PBTC_LAUNCH_CHECK();
-  for (int s = 0; s < pl.nsurf; ++s) {
-    const int64_t o = pl.gp_off[s], n = pl.gp_off[s + 1] - o;
-    radix_sort64(key + o, order + o, wsp<uint64_t>(pl, pl.o_gtmpk), wsp<int>(pl, pl.o_gtmpv),
-                 wsp<int>(pl, pl.o_hist), n, st);
-  }
+  // one sort for all surfaces: Morton order within each surface's segment
+  radix_sort64_seg(key, order, wsp<uint64_t>(pl, pl.o_gtmpk), wsp<int>(pl, pl.o_gtmpv),
+                   wsp<int>(pl, pl.o_hist), pl.ngp, gp_off, pl.nsurf, st);
   int* gp2pan = wsp<int>(pl, pl.o_gtmpv);
   hipLaunchKernelGGL(k_gp2pan, dim3(nblocks(pl.ngp, T)), dim3(T), 0, st, pl.ngp, pl.prm.K, gp2pan);
   hipLaunchKernelGGL(k_gauss_gather, dim3(nblocks(pl.ngp, T)), dim3(T), 0, st, sa, rule, pl.ngp,
@@ -839,41 +863,51 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
                      wsp<int>(pl, pl.o_gidx));
   PBTC_LAUNCH_CHECK();
 
-  // ---- targets in Morton order per target set
+  // ---- targets in Morton order per target set (keys per set, one sort)
   uint64_t* tkey = wsp<uint64_t>(pl, pl.o_tkey);
   int* tord = wsp<int>(pl, pl.o_tval);
+  auto target_coords = [&](const TargetSet& ts, const double** X, const double** Y,
+                           const double** Z, int* stride) {
+    if (ts.kind == 0) {
+      *X = sa.cx + pl.pan_off[ts.id];
+      *Y = sa.cy + pl.pan_off[ts.id];
+      *Z = sa.cz + pl.pan_off[ts.id];
+      *stride = 1;
+    } else {
+      const double* qx = wsp<double>(pl, pl.o_qxyz) + 3 * pl.q_off_region[ts.id];
+      *X = qx;
+      *Y = qx + 1;
+      *Z = qx + 2;
+      *stride = 3;
+    }
+  };
   for (size_t ti = 0; ti < pl.tsets.size(); ++ti) {
     const TargetSet& ts = pl.tsets[ti];
+    if (ts.n == 0) continue;
     const double* c = &pl.tcube[4 * ti];
     const double *X, *Y, *Z;
     int stride;
-    int64_t src_off;
-    if (ts.kind == 0) {
-      X = sa.cx + pl.pan_off[ts.id];
-      Y = sa.cy + pl.pan_off[ts.id];
-      Z = sa.cz + pl.pan_off[ts.id];
-      stride = 1;
-      src_off = 0;
-    } else {
-      const double* qx = wsp<double>(pl, pl.o_qxyz) + 3 * pl.q_off_region[ts.id];
-      X = qx;
-      Y = qx + 1;
-      Z = qx + 2;
-      stride = 3;
-      src_off = 0;
-    }
+    target_coords(ts, &X, &Y, &Z, &stride);
     hipLaunchKernelGGL(k_target_keys, dim3(nblocks(ts.n, T)), dim3(T), 0, st, ts.off, ts.n, X, Y, Z,
                        stride, c[0], c[1], c[2], c[3], tkey, tord);
-    radix_sort64(tkey, tord, wsp<uint64_t>(pl, pl.o_tkey2), wsp<int>(pl, pl.o_tval2),
-                 wsp<int>(pl, pl.o_hist), ts.n, st);
-    PBTC_HIP(hipMemcpyAsync(wsp<uint64_t>(pl, pl.o_tkey_sorted) + ts.off, tkey, 8 * ts.n,
-                            hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_target_gather, dim3(nblocks(ts.n, T)), dim3(T), 0, st, ts.off, ts.n, tord,
-                       X, Y, Z, stride, src_off, wsp<double>(pl, pl.o_tx), wsp<double>(pl, pl.o_ty),
-                       wsp<double>(pl, pl.o_tz), wsp<float>(pl, pl.o_txf), wsp<float>(pl, pl.o_tyf),
-                       wsp<float>(pl, pl.o_tzf), wsp<int>(pl, pl.o_tidx));
-    PBTC_LAUNCH_CHECK();
   }
+  PBTC_LAUNCH_CHECK();
+  radix_sort64_seg(tkey, tord, wsp<uint64_t>(pl, pl.o_tkey2), wsp<int>(pl, pl.o_tval2),
+                   wsp<int>(pl, pl.o_hist), pl.ntgt, tset_off, (int)pl.tsets.size(), st);
+  PBTC_HIP(hipMemcpyAsync(wsp<uint64_t>(pl, pl.o_tkey_sorted), tkey, 8 * pl.ntgt,
+                          hipMemcpyDeviceToDevice, st));
+  for (size_t ti = 0; ti < pl.tsets.size(); ++ti) {
+    const TargetSet& ts = pl.tsets[ti];
+    if (ts.n == 0) continue;
+    const double *X, *Y, *Z;
+    int stride;
+    target_coords(ts, &X, &Y, &Z, &stride);
+    hipLaunchKernelGGL(k_target_gather, dim3(nblocks(ts.n, T)), dim3(T), 0, st, ts.off, ts.n,
+                       tord + ts.off, X, Y, Z, stride, (int64_t)0, wsp<double>(pl, pl.o_tx),
+                       wsp<double>(pl, pl.o_ty), wsp<double>(pl, pl.o_tz), wsp<float>(pl, pl.o_txf),
+                       wsp<float>(pl, pl.o_tyf), wsp<float>(pl, pl.o_tzf), wsp<int>(pl, pl.o_tidx));
+  }
+  PBTC_LAUNCH_CHECK();
   {
     std::vector<long long> go(pl.ngrp), gn(pl.ngrp);
     for (const TargetSet& ts : pl.tsets)
@@ -890,6 +924,8 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     PBTC_LAUNCH_CHECK();
     PBTC_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
   }
+  rc = phase_done(0);
+  if (rc) return rc;
 
   // ---- octree per surface, level by level
   Cell* cells = wsp<Cell>(pl, pl.o_cells);
@@ -921,6 +957,8 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     if (rc) return rc;
     pl.n_levels = (int)pl.level_begin.size() - 1;
   }
+  rc = phase_done(1);
+  if (rc) return rc;
 
   // ---- interaction lists
   const int direct = pl.prm.op == PBTC_OP_DIRECT;
@@ -955,6 +993,8 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
                      far_ptr, wsp<int>(pl, pl.o_near), wsp<int>(pl, pl.o_far), (long long)pl.cap_near,
                      (long long)pl.cap_far, flags);
   PBTC_LAUNCH_CHECK();
+  rc = phase_done(2);
+  if (rc) return rc;
 
   // ---- near-field correction tables
   NearArgs na;
@@ -991,10 +1031,14 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   }
   rc = recompute_near_values(pl, st);
   if (rc) return rc;
+  rc = phase_done(3);
+  if (rc) return rc;
   rc = recompute_precond(pl, st);
   if (rc) return rc;
 
   rc = recompute_rhs(pl, st);
+  if (rc) return rc;
+  rc = phase_done(4);
   if (rc) return rc;
 
   // ---- interaction counts and algorithmic operation counts per launch
@@ -1094,7 +1138,7 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     PBTC_HIP(hipMemcpy(wsp<int4>(pl, pl.o_units), units.data(), 16 * units.size(), hipMemcpyHostToDevice));
     PBTC_HIP(hipMemcpy(wsp<int>(pl, pl.o_uptr), uptr.data(), 4 * uptr.size(), hipMemcpyHostToDevice));
   }
-  return PBTC_OK;
+  return phase_done(5);
 }
 
 // New charge values (positions unchanged): upload and rebuild the RHS.
@@ -1168,26 +1212,49 @@ int recompute_precond(pbtc_plan& pl, hipStream_t st) {
   return PBTC_OK;
 }
 
-// Coulomb right-hand side (Eq. matel, Q; the charges of each row's region,
-// scaled by 1/eps of that region).
-int recompute_rhs(pbtc_plan& pl, hipStream_t st) {
+// Coulomb row table (o_crows) from the current permittivities and kappas.
+int upload_coulomb_rows(pbtc_plan& pl, hipStream_t st) {
   const pbtc_problem& P = pl.prob;
-  const int T = 256;
-  double* b = wsp<double>(pl, pl.o_b);
-  hipLaunchKernelGGL(k_fill_f64, dim3(nblocks(pl.nunk, T)), dim3(T), 0, st, b, pl.nunk, 0.0);
-  for (const RowBlock& rb : pl.rows) {
-    const int r = rb.r;
-    const int64_t nq = P.charges[r].n();
-    if (nq == 0) continue;
-    hipLaunchKernelGGL(k_coulomb, dim3(nblocks(rb.n, T)), dim3(T), 0, st, rb.n,
-                       (long long)rb.row_off, (long long)pl.pan_off[rb.t], wsp<double>(pl, pl.o_cx), wsp<double>(pl, pl.o_cy), wsp<double>(pl, pl.o_cz),
-                       wsp<double>(pl, pl.o_qxyz), wsp<double>(pl, pl.o_q),
-                       (long long)pl.q_off_region[r], (long long)nq, 1.0 / P.regions[r].eps,
-                       P.regions[r].kappa, b);
-    PBTC_LAUNCH_CHECK();
+  const size_t nr = pl.rows.size();
+  std::vector<char>& h = pl.crow_host;
+  h.assign(sizeof(DevCoulRow) * nr + 4 * (pl.nreg + 1 + nr), 0);
+  DevCoulRow* cr = reinterpret_cast<DevCoulRow*>(h.data());
+  int* reg_ptr = reinterpret_cast<int*>(h.data() + sizeof(DevCoulRow) * nr);
+  int* reg_rows = reg_ptr + pl.nreg + 1;
+  for (size_t i = 0; i < nr; ++i) {
+    const RowBlock& rb = pl.rows[i];
+    cr[i].row_off = rb.row_off;
+    cr[i].n = rb.n;
+    cr[i].pan_first = pl.pan_off[rb.t];
+    cr[i].q0 = pl.q_off_region[rb.r];
+    cr[i].nq = P.charges[rb.r].n();
+    cr[i].inv_eps = 1.0 / P.regions[rb.r].eps;
+    cr[i].kappa = P.regions[rb.r].kappa;
+    cr[i].pad = 0;
   }
-  PBTC_HIP(hipStreamSynchronize(st));
+  int k = 0;
+  for (int r = 0; r < pl.nreg; ++r) {
+    reg_ptr[r] = k;
+    for (size_t i = 0; i < nr; ++i)
+      if (pl.rows[i].r == r) reg_rows[k++] = (int)i;
+  }
+  reg_ptr[pl.nreg] = k;
+  PBTC_HIP(hipMemcpyAsync(wsp<char>(pl, pl.o_crows), h.data(), h.size(), hipMemcpyHostToDevice, st));
+  return PBTC_OK;
+}
 
+// Coulomb right-hand side (Eq. matel, Q; the charges of each row's region,
+// scaled by 1/eps of that region), all rows in one launch.
+int recompute_rhs(pbtc_plan& pl, hipStream_t st) {
+  int rc = upload_coulomb_rows(pl, st);
+  if (rc) return rc;
+  const int T = 64;
+  hipLaunchKernelGGL(k_coulomb_rows, dim3(nblocks(pl.nunk, T)), dim3(T), 0, st, (int64_t)pl.nunk,
+                     wsp<DevCoulRow>(pl, pl.o_crows), (int)pl.rows.size(), wsp<double>(pl, pl.o_cx),
+                     wsp<double>(pl, pl.o_cy), wsp<double>(pl, pl.o_cz), wsp<double>(pl, pl.o_qxyz),
+                     wsp<double>(pl, pl.o_q), wsp<double>(pl, pl.o_b));
+  PBTC_LAUNCH_CHECK();
+  PBTC_HIP(hipStreamSynchronize(st));
   return PBTC_OK;
 }
 

@@ -49,10 +49,15 @@ class Result(C.Structure):
         ("p2p_flop", C.c_double), ("m2p_flop", C.c_double),
         ("t_m2p_yuk_s", C.c_double), ("n_m2p_yuk_launch", C.c_int),
         ("m2p_yuk_flop", C.c_double),
+        ("t_setup_phase_s", C.c_double * 6),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if isinstance(v, C.Array) else v
+        return out
 
 
 _EXPORTS = {

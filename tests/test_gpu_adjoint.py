@@ -130,6 +130,26 @@ def test_multisurface_backward(gpu_lib):
     assert _rel(de, ref["dE_deps"]) < 1e-7
 
 
+def test_shared_kappa_regions_backward(gpu_lib):
+    """Two ionic regions with the same kappa (an ion-accessible layer and the
+    solvent): their kernels are shared between blocks, yet each region's
+    dE/dkappa is its own (oracle: exact discrete adjoint per region)."""
+    from paper_1309_4018_amd import lib
+
+    prob = synth.concentric_spheres([4.0, 5.5], [4, 80, 80], [0, 0.1, 0.1],
+                                    (np.array([[0.0, 0.0, 2.0], [1.0, -1.0, 0.5]]),
+                                     np.array([1.0, -0.6])), 0, nu=8)
+    ref = gradients(Oracle(prob))
+    pl = lib.plan_for(prob, op="direct", precision="fp64", tol=1e-12)
+    pl.solve()
+    dq, dk, de = pl.backward()
+    assert _rel(dq, ref["dE_dq"]) < 1e-8
+    assert _rel(de, ref["dE_deps"]) < 1e-8
+    for r in (1, 2):
+        assert abs(dk[r] - ref["dE_dkappa"][r]) < 1e-6 * abs(ref["dE_dkappa"][r]), r
+    assert dk[0] == 0.0
+
+
 def test_autograd_wrapper(sphere, gpu_lib):
     import torch
 

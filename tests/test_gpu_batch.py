@@ -62,3 +62,28 @@ def test_batch_treecode_fp32_refined(mols, gpu_lib):
     assert np.all(rel <= 1e-6)
     for i in range(len(mols)):
         assert abs(e[i] - refs[i]) < 1e-4 * abs(refs[i]), i
+
+
+def test_batch_backward_matches_individual(mols, gpu_lib):
+    """Gradients of a batch equal those of each molecule by itself; several
+    molecules share kappa = 0.125, so each region's dE/dkappa must read its
+    own rows only."""
+    from paper_1309_4018_amd import lib
+
+    prm = dict(op="direct", precision="fp64", tol=1e-12)
+    pl = lib.Plan(lib.batch_problem(mols), lib.default_params(**prm))
+    pl.solve()
+    dq, dk, de = pl.backward()
+    q0 = r0 = 0
+    for i, m in enumerate(mols):
+        single = lib.plan_for(m, **prm)
+        single.solve()
+        sq, sk, se = single.backward()
+        nq, nr = len(sq), len(sk)
+        assert np.max(np.abs(dq[q0:q0 + nq] - sq)) < 1e-8 * np.max(np.abs(sq)), i
+        for r in range(nr):
+            assert abs(dk[r0 + r] - sk[r]) <= 1e-6 * abs(sk[r]) + 1e-12, (i, r)
+            assert abs(de[r0 + r] - se[r]) <= 1e-8 * abs(se[r]) + 1e-12, (i, r)
+        q0 += nq
+        r0 += nr
+    assert q0 == len(dq) and r0 == len(dk)
