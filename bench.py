@@ -301,7 +301,7 @@ def main():
         "solve_s": solve32,
         "setup_s": float(np.median([r["t_setup_s"] for r in results])),
         "setup_phase_s": dict(zip(
-            ["sort", "octree", "lists", "near_field", "precond_rhs", "tables"],
+            ["sort", "octree", "lists", "near_columns", "host_tables", "near_values_precond_rhs"],
             np.median([r["t_setup_phase_s"] for r in results], axis=0).tolist())),
         "energy_kJmol": last["energy_kJmol"],
         "final_rel_res": last["final_rel_res"],
@@ -310,6 +310,7 @@ def main():
         "dense_interactions_per_matvec": dense,
         "p2p_pairs_per_matvec": last["n_p2p_pairs"],
         "m2p_evals_per_matvec": last["n_m2p_evals"],
+        "near_entries": last["n_near_entries"],
         "matvec_s": mv,
         "matvec_interactions_per_s": {k: dense / v for k, v in mv.items()},
         "fp64_solve_s": solve64,

@@ -149,8 +149,9 @@ typedef struct {
   double m2p_yuk_flop;
   /* host wall-clock split of the last device set-up (seconds): [0] panels,
    * Gauss points and targets in Morton order, [1] octrees, [2] interaction
-   * lists, [3] near-field tables and values, [4] preconditioner blocks and
-   * Coulomb right-hand side, [5] work units and moment tables */
+   * lists, [3] near-field columns, [4] work-unit and moment tables built on
+   * the host while the GPU computes the near-field values, preconditioner
+   * blocks and Coulomb right-hand side, [5] the rest of that GPU work */
   double t_setup_phase_s[6];
 } pbtc_result;
 

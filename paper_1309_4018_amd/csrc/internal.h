@@ -18,6 +18,8 @@ constexpr double kCoulomb = 1389.35458;
 
 constexpr int kMaxP = 10;
 constexpr int kGroup = 64;       // targets per target group (one wavefront)
+constexpr int kDotChunk = 4096;  // Krylov reduction chunk (entries of one system)
+constexpr int kNearSlots = 128; // near-field columns per row kept by the single traversal
 constexpr int kMaxLevels = 21;   // 63-bit Morton keys, 21 bits per axis
 constexpr int kMaxNk = 32;
 constexpr int kMomChunk = 128;   // sources staged at a time by the direct moment pass

@@ -52,61 +52,6 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return t;
 }
 
-// partial[b * nv + i] = sum over block b's slice of V[i] . w  (i < nv)
-__global__ __launch_bounds__(kRedThreads) void k_dots(const double* __restrict__ V, int nv,
-                                                      int64_t n, const double* __restrict__ w,
-                                                      double* __restrict__ partial) {
-  __shared__ double lds[kRedThreads / 64];
-  const int64_t stride = (int64_t)gridDim.x * kRedThreads;
-  for (int i = 0; i < nv; ++i) {
-    double s = 0.0;
-    for (int64_t j = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; j < n; j += stride)
-      s += V[(size_t)i * n + j] * w[j];
-    s = block_sum(s, lds);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nv + i] = s;
-  }
-}
-
-// out[i] (+)= sum_b partial[b * nv + i]
-__global__ void k_sum_partials(const double* __restrict__ partial, int nb, int nv,
-                               double* __restrict__ out, int accumulate) {
-  __shared__ double lds[kRedThreads / 64];
-  for (int i = 0; i < nv; ++i) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kRedThreads) s += partial[(size_t)b * nv + i];
-    s = block_sum(s, lds);
-    if (threadIdx.x == 0) out[i] = accumulate ? out[i] + s : s;
-  }
-}
-
-// w -= sum_i h[i] V[i]
-__global__ void k_sub_combo(const double* __restrict__ V, int nv, int64_t n,
-                            const double* __restrict__ h, double* __restrict__ w) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double s = w[j];
-  for (int i = 0; i < nv; ++i) s -= h[i] * V[(size_t)i * n + j];
-  w[j] = s;
-}
-
-// x += sum_i y[i] V[i]
-__global__ void k_add_combo(const double* __restrict__ V, int nv, int64_t n,
-                            const double* __restrict__ y, double* __restrict__ x) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double s = x[j];
-  for (int i = 0; i < nv; ++i) s += y[i] * V[(size_t)i * n + j];
-  x[j] = s;
-}
-
-__global__ void k_scale(const double* __restrict__ w, int64_t n, const double* __restrict__ s,
-                        int invert, double* __restrict__ out) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const double f = invert ? (s[0] > 0.0 ? 1.0 / s[0] : 0.0) : s[0];
-  out[j] = w[j] * f;
-}
-
 // out = a - b
 __global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
                       double* __restrict__ out) {
@@ -141,66 +86,6 @@ __global__ void k_fill(double* p, int64_t n, double v) {
   if (j < n) p[j] = v;
 }
 
-__global__ void k_sqrt(double* p) { p[0] = sqrt(fmax(p[0], 0.0)); }
-
-// Givens step for column j: H(:, j) = h (CGS2 sum), H(j+1, j) = hnorm; apply
-// the stored rotations, form the new one, update g and the residual estimate.
-// H column-major with leading dimension ld.  giv = [cs (m+1), sn (m+1), g (m+2)].
-__global__ void k_givens(int j, int ld, const double* __restrict__ h, const double* __restrict__ hn,
-                         double* __restrict__ H, double* __restrict__ giv, double bnorm,
-                         double* __restrict__ res) {
-  double* cs = giv;
-  double* sn = giv + ld;
-  double* g = giv + 2 * ld;
-  double* col = H + (size_t)j * ld;
-  for (int i = 0; i <= j; ++i) col[i] = h[i];
-  col[j + 1] = hn[0];
-  for (int i = 0; i < j; ++i) {
-    const double a = col[i], b = col[i + 1];
-    col[i] = cs[i] * a + sn[i] * b;
-    col[i + 1] = -sn[i] * a + cs[i] * b;
-  }
-  const double a = col[j], b = col[j + 1];
-  const double den = hypot(a, b);
-  const double c = den > 0.0 ? a / den : 1.0, s = den > 0.0 ? b / den : 0.0;
-  cs[j] = c;
-  sn[j] = s;
-  col[j] = den;
-  col[j + 1] = 0.0;
-  g[j + 1] = -s * g[j];
-  g[j] = c * g[j];
-  res[0] = fabs(g[j + 1]) / bnorm;
-}
-
-// y = R^{-1} g (upper triangular, k columns)
-__global__ void k_backsolve(int k, int ld, const double* __restrict__ H, const double* __restrict__ giv,
-                            double* __restrict__ y) {
-  const double* g = giv + 2 * ld;
-  for (int i = k - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * ld + i] * y[c];
-    const double d = H[(size_t)i * ld + i];
-    y[i] = d != 0.0 ? s / d : 0.0;
-  }
-}
-
-__global__ void k_init_g(double* giv, int ld, const double* beta) {
-  double* g = giv + 2 * ld;
-  for (int i = 0; i < ld + 1; ++i) g[i] = 0.0;
-  g[0] = beta[0];
-}
-
-// 1/2 * C * sum_k q_k phi_k  (single block)
-__global__ void k_energy(const double* __restrict__ q, const double* __restrict__ phi, int64_t n,
-                         double factor, double* __restrict__ out) {
-  __shared__ double lds[kRedThreads / 64];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kRedThreads) s += q[i] * phi[i];
-  s = block_sum(s, lds);
-  if (threadIdx.x == 0) out[0] = factor * s;
-}
-
-
 // partial[chunk * ld + i] = <V_i, w> over the chunk; one block per (chunk, i)
 __global__ __launch_bounds__(kRedThreads) void k_dots_seg(const double* __restrict__ V, int nv,
                                                           int64_t n, const double* __restrict__ w,
@@ -216,20 +101,16 @@ __global__ __launch_bounds__(kRedThreads) void k_dots_seg(const double* __restri
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ld + i] = s;
 }
 
-// out[c * ldo + i] = sum of the chunks of system c, in chunk order: one
-// thread per (system c = blockIdx.x, i)
+// out[c * ldo + i] = sum of the chunk partials of system c, in chunk order:
+// one thread per (system c = blockIdx.x, i); with root set, the square root.
 __global__ void k_sum_seg(const double* __restrict__ partial, int pld, const int* __restrict__ chunk0,
-                          int nv, int ldo, double* __restrict__ out) {
+                          int nv, int ldo, int root, double* __restrict__ out) {
   const int c = blockIdx.x;
   const int i = blockIdx.y * blockDim.x + threadIdx.x;
   if (i >= nv) return;
   double s = 0.0;
   for (int b = chunk0[c]; b < chunk0[c + 1]; ++b) s += partial[(size_t)b * pld + i];
-  out[(size_t)c * ldo + i] = s;
-}
-
-__global__ void k_sqrt_n(double* p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = sqrt(fmax(p[i], 0.0));
+  out[(size_t)c * ldo + i] = root ? sqrt(fmax(s, 0.0)) : s;
 }
 
 // w -= sum_i h[c, i] V_i on the entries of system c
@@ -242,6 +123,42 @@ __global__ void k_sub_combo_seg(const double* __restrict__ V, int nv, int64_t n,
   double s = w[j];
   for (int i = 0; i < nv; ++i) s -= hc[i] * V[(size_t)i * n + j];
   w[j] = s;
+}
+
+// out[c] = sqrt of the sum of partial[b] over b in [chunk0[c] * per,
+// chunk0[c + 1] * per): one wavefront per system, lanes strided, then a fixed
+// butterfly.
+__global__ void k_norm_seg(const double* __restrict__ partial, const int* __restrict__ chunk0,
+                           int per, double* __restrict__ out) {
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int b = chunk0[c] * per + (int)threadIdx.x; b < chunk0[c + 1] * per; b += 64) s += partial[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[c] = sqrt(fmax(s, 0.0));
+}
+
+// Second Gram-Schmidt pass fused with the norm: w -= sum_i h[c, i] V_i, and
+// partial[b] = sum of w^2 over block b's part of its chunk (kChunkBlocks
+// blocks of kRedThreads entries per chunk; a chunk lies in one system c).
+constexpr int kChunkBlocks = kDotChunk / kRedThreads;
+static_assert(kChunkBlocks * kRedThreads == kDotChunk, "chunks split into whole blocks");
+
+__global__ __launch_bounds__(kRedThreads) void k_sub_combo_norm_seg(
+    const double* __restrict__ V, int nv, int64_t n, const double* __restrict__ h, int ld,
+    const int4* __restrict__ chunks, double* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double lds[kRedThreads / 64];
+  const int4 ch = chunks[blockIdx.x / kChunkBlocks];
+  const int64_t j = ch.y + (int64_t)(blockIdx.x % kChunkBlocks) * kRedThreads + threadIdx.x;
+  double sq = 0.0;
+  if (j < ch.z) {
+    const double* hc = h + (size_t)ch.x * ld;
+    double s = w[j];
+    for (int i = 0; i < nv; ++i) s -= hc[i] * V[(size_t)i * n + j];
+    w[j] = s;
+    sq = s * s;
+  }
+  sq = block_sum(sq, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sq;
 }
 
 // out = w / s[c] for active systems, 0 for the others
@@ -269,8 +186,8 @@ __global__ void k_init_seg(int nc, double* giv, int gstride, int ld, const doubl
 // hn; apply the stored rotations, form the new one, update g, and deactivate
 // the system once |g_{j+1}| <= tol * ref (kfin = j + 1).
 __global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h,
-                             double* __restrict__ H, double* __restrict__ giv, int gstride,
-                             double* __restrict__ sc) {
+                             const double* __restrict__ h2, double* __restrict__ H,
+                             double* __restrict__ giv, int gstride, double* __restrict__ sc) {
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
     double* act = sc + (size_t)SC_ACTIVE * nc;
     if (act[c] <= 0.0) continue;
@@ -279,7 +196,8 @@ __global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h
     double* g = cs + 2 * ld;
     double* col = H + ((size_t)c * ld + j) * ld;
     const double* hc = h + (size_t)c * ld;
-    for (int i = 0; i <= j; ++i) col[i] = hc[i];
+    const double* h2c = h2 + (size_t)c * ld;
+    for (int i = 0; i <= j; ++i) col[i] = hc[i] + h2c[i];
     col[j + 1] = sc[(size_t)SC_HN * nc + c];
     for (int i = 0; i < j; ++i) {
       const double a = col[i], b = col[i + 1];
@@ -387,6 +305,7 @@ struct Krylov {
   double* red;    // partials: nchunks x ld
   double* hbuf;   // nc x ld
   double* h2buf;  // nc x ld
+  double* nrm;    // norm partials of the fused second pass: nchunks x kChunkBlocks
   double* w;
   const int4* chunks;
   const int* chunk0;
@@ -406,6 +325,7 @@ struct Krylov {
     red = wsp<double>(pl, pl.o_red);
     hbuf = red + (size_t)nchunks * ld;
     h2buf = hbuf + (size_t)nc * ld;
+    nrm = h2buf + (size_t)nc * ld;
     w = wsp<double>(pl, pl.o_w);
     chunks = wsp<int4>(pl, pl.o_chunks);
     chunk0 = reinterpret_cast<const int*>(chunks + nchunks);
@@ -417,8 +337,8 @@ struct Krylov {
   int dots(const double* Vb, int nv, const double* v, double* out) {
     hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, nv), dim3(kRedThreads), 0, st, Vb, nv, n, v,
                        chunks, red, ld);
-    hipLaunchKernelGGL(k_sum_seg, dim3(nc, nblocks(nv, 64)), dim3(64), 0, st, red, ld, chunk0, nv, ld,
-                       out);
+    hipLaunchKernelGGL(k_sum_seg, dim3(nc, nblocks(nv, 64)), dim3(64), 0, st, red, ld, chunk0, nv,
+                       ld, 0, out);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
@@ -426,8 +346,15 @@ struct Krylov {
   int norm(const double* v, double* out) {
     hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, 1), dim3(kRedThreads), 0, st, v, 1, n, v, chunks,
                        red, ld);
-    hipLaunchKernelGGL(k_sum_seg, dim3(nc, 1), dim3(64), 0, st, red, ld, chunk0, 1, 1, out);
-    hipLaunchKernelGGL(k_sqrt_n, dim3(1), dim3(64), 0, st, out, nc);
+    hipLaunchKernelGGL(k_sum_seg, dim3(nc, 1), dim3(64), 0, st, red, ld, chunk0, 1, 1, 1, out);
+    PBTC_LAUNCH_CHECK();
+    return PBTC_OK;
+  }
+  // w -= V h (second pass) and out[c] = ||w|| over system c
+  int sub_combo_norm(int nv, const double* h, double* out) {
+    hipLaunchKernelGGL(k_sub_combo_norm_seg, dim3(nchunks * kChunkBlocks), dim3(kRedThreads), 0, st,
+                       V, nv, n, h, ld, chunks, w, nrm);
+    hipLaunchKernelGGL(k_norm_seg, dim3(nc), dim3(64), 0, st, nrm, chunk0, kChunkBlocks, out);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
@@ -585,16 +512,13 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, int prec, const double* r
                            K.hbuf, ld, K.comp, K.w);
         rc = K.dots(K.V, j + 1, K.w, K.h2buf);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_sub_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n,
-                           K.h2buf, ld, K.comp, K.w);
-        hipLaunchKernelGGL(k_axpy, dim3(nblocks((int64_t)nc * ld, T)), dim3(T), 0, st, 1.0,
-                           K.h2buf, (int64_t)nc * ld, K.hbuf);
-        rc = K.norm(K.w, K.scal(SC_HN));
+        rc = K.sub_combo_norm(j + 1, K.h2buf, K.scal(SC_HN));
         if (rc) return rc;
         hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.w, n,
                            K.scal(SC_HN), K.comp, K.scal(SC_ACTIVE), vn);
-        hipLaunchKernelGGL(k_givens_seg, dim3(1), dim3(64), 0, st, nc, j, ld, K.hbuf, K.H, K.giv,
-                           K.gstride, K.sc);
+        // Hessenberg column = first-pass + second-pass coefficients
+        hipLaunchKernelGGL(k_givens_seg, dim3(1), dim3(64), 0, st, nc, j, ld, K.hbuf, K.h2buf, K.H,
+                           K.giv, K.gstride, K.sc);
         PBTC_LAUNCH_CHECK();
         // residual estimates and active flags of every system (SC_RES, SC_ACTIVE)
         PBTC_HIP(hipMemcpyAsync(pl.res_pin + (size_t)(j & 1) * 2 * nc, K.scal(SC_RES), 16 * nc,

@@ -372,30 +372,75 @@ __global__ void k_reduce(const int* __restrict__ list, const int* __restrict__ u
 
 // ----------------------------------------------------------- near field
 // S[out_k + i] += sum_e dV_k(e) psi(col), D[out_k + i] += sum_e dK_k(e) phi(col)
+// kNearLanes consecutive lanes share a row and stride over its entries, so a
+// wavefront's loads of the entry values are contiguous; a fixed butterfly adds
+// the lanes' sums.
+constexpr int kNearLanes = 4;
+
+template <typename real>
+__device__ __forceinline__ void load_near4(const real* __restrict__ v, real& a, real& b, real& c,
+                                           real& d);
+template <>
+__device__ __forceinline__ void load_near4<float>(const float* __restrict__ v, float& a, float& b,
+                                                  float& c, float& d) {
+  const float4 q = *reinterpret_cast<const float4*>(v);
+  a = q.x;
+  b = q.y;
+  c = q.z;
+  d = q.w;
+}
+template <>
+__device__ __forceinline__ void load_near4<double>(const double* __restrict__ v, double& a,
+                                                   double& b, double& c, double& d) {
+  const double2 q0 = *reinterpret_cast<const double2*>(v);
+  const double2 q1 = *reinterpret_cast<const double2*>(v + 2);
+  a = q0.x;
+  b = q0.y;
+  c = q1.x;
+  d = q1.y;
+}
+
 template <typename real>
 __global__ void k_near_apply(long long r0, long long r1, const int* __restrict__ row_block,
                              const DevBlock* __restrict__ blocks, const long long* __restrict__ ptr,
                              const int* __restrict__ col, const real* __restrict__ val,
                              const int* __restrict__ pidx, const double* __restrict__ x,
                              double* __restrict__ S, double* __restrict__ D) {
-  const long long row = r0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= r1) return;
-  const DevBlock b = blocks[row_block[row]];
-  const long long i = row - b.nf_row;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long row = r0 + gid / kNearLanes;
+  const int sub = (int)(gid % kNearLanes);
+  const bool live = row < r1;
   real s0 = 0, d0 = 0, s1 = 0, d1 = 0;
-  for (long long e = ptr[row]; e < ptr[row + 1]; ++e) {
-    const int p = col[e];
-    const real phi = (real)x[pidx[2 * p]], psi = (real)x[pidx[2 * p + 1]];
-    s0 += val[4 * e] * psi;
-    d0 += val[4 * e + 1] * phi;
-    if (b.nk == 2) {
-      s1 += val[4 * e + 2] * psi;
-      d1 += val[4 * e + 3] * phi;
+  int nk = 1;
+  if (live) {
+    nk = blocks[row_block[row]].nk;
+    const long long e1 = ptr[row + 1];
+    for (long long e = ptr[row] + sub; e < e1; e += kNearLanes) {
+      const int p = col[e];
+      const real phi = (real)x[pidx[2 * p]], psi = (real)x[pidx[2 * p + 1]];
+      real v0, v1, v2, v3;
+      load_near4<real>(val + 4 * e, v0, v1, v2, v3);
+      s0 += v0 * psi;
+      d0 += v1 * phi;
+      if (nk == 2) {
+        s1 += v2 * psi;
+        d1 += v3 * phi;
+      }
     }
   }
+#pragma unroll
+  for (int o = 1; o < kNearLanes; o <<= 1) {
+    s0 += __shfl_xor(s0, o, 64);
+    d0 += __shfl_xor(d0, o, 64);
+    s1 += __shfl_xor(s1, o, 64);
+    d1 += __shfl_xor(d1, o, 64);
+  }
+  if (!live || sub != 0) return;
+  const DevBlock& b = blocks[row_block[row]];
+  const long long i = row - b.nf_row;
   S[b.out0 + i] += (double)s0;
   D[b.out0 + i] += (double)d0;
-  if (b.nk == 2) {
+  if (nk == 2) {
     S[b.out1 + i] += (double)s1;
     D[b.out1 + i] += (double)d1;
   }
@@ -589,7 +634,8 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
   const long long r0 = phase == 0 ? 0 : pl.nf_fwd_rows;
   const long long r1 = phase == 0 ? pl.nf_fwd_rows : pl.nf_rows;
   if (r1 > r0) {
-    hipLaunchKernelGGL(k_near_apply<real>, dim3(nblocks(r1 - r0, T)), dim3(T), 0, st, r0, r1,
+    hipLaunchKernelGGL(k_near_apply<real>, dim3(nblocks((r1 - r0) * kNearLanes, T)), dim3(T), 0, st,
+                       r0, r1,
                        wsp<int>(pl, pl.o_nf_rowblk), wsp<DevBlock>(pl, pl.o_blocks),
                        wsp<long long>(pl, pl.o_nf_ptr), wsp<int>(pl, pl.o_nf_col),
                        wsp<real>(pl, sizeof(real) == 4 ? pl.o_nf_v32 : pl.o_nf_v64),

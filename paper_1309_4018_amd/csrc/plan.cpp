@@ -320,7 +320,7 @@ int build_plan(pbtc_plan& pl) {
       pl.comp_u1[c] = hi;
     }
     // Krylov reduction chunks never straddle two systems
-    constexpr int64_t kChunk = 4096;
+    constexpr int64_t kChunk = kDotChunk;
     pl.dot_chunks.clear();
     pl.comp_chunk0.assign(pl.ncomp + 1, 0);
     for (int c = 0; c < pl.ncomp; ++c) {
@@ -563,8 +563,10 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_H = L.add(8 * (size_t)(m + 1) * (m + 1));
   pl.o_givens = L.add(8 * 4 * (size_t)(m + 2));
   pl.o_scal = L.add(8 * 64);
+  // chunk partials (m + 1 per chunk), two coefficient sets per system, the
+  // norm partials of the fused second pass (16 per chunk), reduction scratch
   pl.o_red = L.add(8 * ((size_t)(m + 1) * (pl.dot_chunks.size() + 2 * (size_t)pl.ncomp) +
-                         (size_t)(m + 2) * 1024));
+                         16 * pl.dot_chunks.size() + (size_t)(m + 2) * 1024));
   pl.o_phi_reac = L.add(8 * std::max<int64_t>(pl.nq, 1));
   pl.o_energy = L.add(8 * (pl.ncomp + 64));
   pl.o_coul = L.add(8 * (pl.ncomp + 1));

@@ -390,11 +390,13 @@ __device__ __forceinline__ void target_point(const NearArgs& a, const DevBlock& 
 // item, a lane per target: the wave walks the leaves that may hold such a
 // panel for some target of the group and tests every panel of each leaf (its
 // first Gauss point stands for it) against all 64 targets at once.
-// mode 0: count per row, mode 1: fill columns.
+// mode 0: count per row; mode 1: fill columns at the row offsets in ptr;
+// mode 2: count per row and keep the first `slot_cap` columns of every row in
+// slots[row * slot_cap ..] (flags[1] set when a row has more).
 __global__ __launch_bounds__(64 * kTravWaves) void k_near_rows(
     NearArgs a, int64_t nitems, const int* __restrict__ item_block, const double* __restrict__ grp,
     const int* __restrict__ tidx, int mode, long long* __restrict__ ptr, int* __restrict__ col,
-    long long cap, int* __restrict__ overflow) {
+    long long cap, int* __restrict__ slots, int slot_cap, int* __restrict__ overflow) {
   __shared__ int stk[kTravWaves][kTravStack];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * kTravWaves + w;
@@ -454,13 +456,29 @@ __global__ __launch_bounds__(64 * kTravWaves) void k_near_rows(
         const bool take = active && (p == self_pan || ex * ex + ey * ey + ez * ez < ll[w][t]);
         if (take) {
           if (mode == 1 && out0 + n < cap) col[out0 + n] = p;
+          if (mode == 2 && n < slot_cap) slots[row * slot_cap + n] = p;
           ++n;
         }
       }
       wave_sync();  // the slots are rewritten by the next batch
     }
   });
-  if (mode == 0 && active) ptr[row] = n;
+  if (mode != 1 && active) ptr[row] = n;
+  if (mode == 2 && active && n > slot_cap) overflow[1] = 1;
+}
+
+// Row slots to CSR: one thread per entry (its row by bisection over ptr).
+__global__ void k_near_compact(int64_t nrows, int64_t nnz, const long long* __restrict__ ptr,
+                               const int* __restrict__ slots, int slot_cap, int* __restrict__ col) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  int64_t lo = 0, hi = nrows - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  col[e] = slots[lo * slot_cap + (e - ptr[lo])];
 }
 
 struct Tables {
@@ -518,21 +536,29 @@ __device__ double self_integral(const Tables& T, const double* A, const double* 
 }
 
 // One thread per near-field entry: correction = rule value - K-point sum,
-// for each kernel of the block (FP64), times 1/(4 pi).
-__global__ void k_near_values(NearArgs a, Tables T, int64_t nrows, const long long* __restrict__ ptr,
-                              const int* __restrict__ col, const int* __restrict__ verts_tri,
-                              const double* __restrict__ verts, const long long* __restrict__ vbase,
-                              const int* __restrict__ pan_surf, double* __restrict__ v64,
-                              float* __restrict__ v32) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= nrows) return;
+// for each kernel of the block (FP64), times 1/(4 pi).  The entry's row is
+// the last row whose first entry is <= e (empty rows are skipped over).
+__global__ void k_near_values(NearArgs a, Tables T, int64_t nrows, int64_t nnz,
+                              const long long* __restrict__ ptr, const int* __restrict__ col,
+                              const int* __restrict__ verts_tri, const double* __restrict__ verts,
+                              const long long* __restrict__ vbase, const int* __restrict__ pan_surf,
+                              double* __restrict__ v64, float* __restrict__ v32) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  int64_t lo = 0, hi = nrows - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t row = lo;
   const int bi = (int)a.nf_row_block[row];
-  const DevBlock b = a.blocks[bi];
+  const DevBlock& b = a.blocks[bi];
   const int64_t i = row - b.nf_row;
   double x, y, z;
   int64_t self_pan;
   target_point(a, b, i, x, y, z, self_pan);
-  for (long long e = ptr[row]; e < ptr[row + 1]; ++e) {
+  {
     const int p = col[e];
     const long long vb = vbase[pan_surf[p]];
     const double* A = verts + 3 * (vb + verts_tri[3 * p + 0]);
@@ -693,6 +719,9 @@ int upload_descriptors(pbtc_plan& pl, hipStream_t st);
 int recompute_near_values(pbtc_plan& pl, hipStream_t st);
 int recompute_precond(pbtc_plan& pl, hipStream_t st);
 int recompute_rhs(pbtc_plan& pl, hipStream_t st);
+int launch_near_values(pbtc_plan& pl, hipStream_t st);
+int launch_precond(pbtc_plan& pl, hipStream_t st);
+int launch_rhs(pbtc_plan& pl, hipStream_t st);
 
 // Octree over Morton-sorted points, level by level from the given roots
 // (one per point set): a box holding >= ncrit points is split into its
@@ -747,6 +776,12 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   auto t_last = std::chrono::steady_clock::now();
   auto phase_done = [&](int k) -> int {
     PBTC_HIP(hipStreamSynchronize(st));
+    const auto t = std::chrono::steady_clock::now();
+    pl.setup_phase[k] = std::chrono::duration<double>(t - t_last).count();
+    t_last = t;
+    return PBTC_OK;
+  };
+  auto phase_done_host = [&](int k) -> int {
     const auto t = std::chrono::steady_clock::now();
     pl.setup_phase[k] = std::chrono::duration<double>(t - t_last).count();
     t_last = t;
@@ -1000,13 +1035,22 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   NearArgs na;
   near_args(pl, &na);
   long long* nf_ptr = wsp<long long>(pl, pl.o_nf_ptr);
+  // one traversal keeps up to slot_cap columns per row in the Krylov basis
+  // (unused during set-up); rows with more take a second, filling traversal
+  const int64_t slot_cap = std::min<int64_t>(
+      kNearSlots, (int64_t)(8 * (size_t)(pl.prm.restart + 1) * pl.nunk / 4) /
+                      std::max<int64_t>(pl.nf_rows, 1));
+  int* slots = wsp<int>(pl, pl.o_V);
   hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nitems, kTravWaves)), dim3(64 * kTravWaves), 0,
                      st, na, pl.nitems, item_block, wsp<double>(pl, pl.o_grp),
-                     wsp<int>(pl, pl.o_tidx), 0, nf_ptr, (int*)nullptr, (long long)0, flags);
+                     wsp<int>(pl, pl.o_tidx), slot_cap > 0 ? 2 : 0, nf_ptr, (int*)nullptr,
+                     (long long)0, slots, (int)slot_cap, flags);
   PBTC_LAUNCH_CHECK();
   scan_exclusive<long long>(nf_ptr, pl.nf_rows, scan_scratch, st);
   long long nnz = 0;
+  int sflag[2] = {0, 0};
   PBTC_HIP(hipMemcpyAsync(&nnz, nf_ptr + pl.nf_rows, 8, hipMemcpyDeviceToHost, st));
+  PBTC_HIP(hipMemcpyAsync(sflag, flags, 8, hipMemcpyDeviceToHost, st));
   PBTC_HIP(hipStreamSynchronize(st));
   if (nnz > pl.cap_nf) {
     pl.cap_nf = nnz + nnz / 8 + 1024;
@@ -1015,10 +1059,16 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
     return PBTC_EWORKSPACE;
   }
   pl.n_nf = nnz;
-  hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nitems, kTravWaves)), dim3(64 * kTravWaves), 0,
-                     st, na, pl.nitems, item_block, wsp<double>(pl, pl.o_grp),
-                     wsp<int>(pl, pl.o_tidx), 1, nf_ptr, wsp<int>(pl, pl.o_nf_col),
-                     (long long)pl.cap_nf, flags);
+  if (slot_cap > 0 && !sflag[1]) {
+    if (nnz > 0)
+      hipLaunchKernelGGL(k_near_compact, dim3(nblocks(nnz, T)), dim3(T), 0, st, (int64_t)pl.nf_rows,
+                         (int64_t)nnz, nf_ptr, slots, (int)slot_cap, wsp<int>(pl, pl.o_nf_col));
+  } else {
+    hipLaunchKernelGGL(k_near_rows, dim3(nblocks(pl.nitems, kTravWaves)), dim3(64 * kTravWaves), 0,
+                       st, na, pl.nitems, item_block, wsp<double>(pl, pl.o_grp),
+                       wsp<int>(pl, pl.o_tidx), 1, nf_ptr, wsp<int>(pl, pl.o_nf_col),
+                       (long long)pl.cap_nf, (int*)nullptr, 0, flags);
+  }
   PBTC_LAUNCH_CHECK();
   {
     int hflag = 0;
@@ -1029,27 +1079,27 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
       return PBTC_EDEVICE;
     }
   }
-  rc = recompute_near_values(pl, st);
-  if (rc) return rc;
   rc = phase_done(3);
   if (rc) return rc;
-  rc = recompute_precond(pl, st);
-  if (rc) return rc;
 
-  rc = recompute_rhs(pl, st);
-  if (rc) return rc;
-  rc = phase_done(4);
-  if (rc) return rc;
-
-  // ---- interaction counts and algorithmic operation counts per launch
+  // ---- interaction counts and algorithmic operation counts per launch,
+  // work units and moment tables: built on the host from the lists while
+  // the GPU computes the near-field values, preconditioner blocks and RHS
   {
     std::vector<long long> np_(pl.nitems + 1), fp_(pl.nitems + 1);
     std::vector<int> nl(std::max<int64_t>(pl.n_near, 1));
     std::vector<Cell> hc(pl.n_cells);
-    PBTC_HIP(hipMemcpy(np_.data(), near_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost));
-    PBTC_HIP(hipMemcpy(fp_.data(), far_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost));
-    if (pl.n_near) PBTC_HIP(hipMemcpy(nl.data(), wsp<int>(pl, pl.o_near), 4 * pl.n_near, hipMemcpyDeviceToHost));
-    PBTC_HIP(hipMemcpy(hc.data(), cells, sizeof(Cell) * pl.n_cells, hipMemcpyDeviceToHost));
+    PBTC_HIP(hipMemcpyAsync(np_.data(), near_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost, st));
+    PBTC_HIP(hipMemcpyAsync(fp_.data(), far_ptr, 8 * (pl.nitems + 1), hipMemcpyDeviceToHost, st));
+    if (pl.n_near)
+      PBTC_HIP(hipMemcpyAsync(nl.data(), wsp<int>(pl, pl.o_near), 4 * pl.n_near,
+                              hipMemcpyDeviceToHost, st));
+    PBTC_HIP(hipMemcpyAsync(hc.data(), cells, sizeof(Cell) * pl.n_cells, hipMemcpyDeviceToHost, st));
+    PBTC_HIP(hipStreamSynchronize(st));
+    rc = launch_near_values(pl, st);
+    if (!rc) rc = launch_precond(pl, st);
+    if (!rc) rc = launch_rhs(pl, st);
+    if (rc) return rc;
     double pairs = 0.0, m2p = 0.0;
     for (int ph = 0; ph < 2; ++ph)
       for (int ks = 0; ks < KS_COUNT; ++ks) pl.launch_flop_p2p[ph][ks] = pl.launch_flop_m2p[ph][ks] = 0.0;
@@ -1124,21 +1174,32 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
       pl.cap_mchunks = pl.n_mchunks + pl.n_mchunks / 8 + 1024;
       *need_retry = 1;
       pl.err = "moment chunks exceed the workspace estimate";
+      PBTC_HIP(hipStreamSynchronize(st));
       return PBTC_EWORKSPACE;
     }
-    if (!mch.empty())
-      PBTC_HIP(hipMemcpy(wsp<int4>(pl, pl.o_mchunks), mch.data(), 16 * mch.size(), hipMemcpyHostToDevice));
-    PBTC_HIP(hipMemcpy(wsp<int>(pl, pl.o_mcell), mcell.data(), 4 * mcell.size(), hipMemcpyHostToDevice));
     if (pl.n_units > pl.cap_units) {
       pl.cap_units = pl.n_units + pl.n_units / 8 + 1024;
       *need_retry = 1;
       pl.err = "work units exceed the workspace estimate";
+      PBTC_HIP(hipStreamSynchronize(st));
       return PBTC_EWORKSPACE;
     }
-    PBTC_HIP(hipMemcpy(wsp<int4>(pl, pl.o_units), units.data(), 16 * units.size(), hipMemcpyHostToDevice));
-    PBTC_HIP(hipMemcpy(wsp<int>(pl, pl.o_uptr), uptr.data(), 4 * uptr.size(), hipMemcpyHostToDevice));
+    rc = phase_done_host(4);
+    if (rc) return rc;
+    if (!mch.empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mchunks), mch.data(), 16 * mch.size(),
+                              hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_mcell), mcell.data(), 4 * mcell.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_units), units.data(), 16 * units.size(),
+                            hipMemcpyHostToDevice, st));
+    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_uptr), uptr.data(), 4 * uptr.size(),
+                            hipMemcpyHostToDevice, st));
+    // the host vectors go out of scope: wait for the copies (and the GPU work)
+    rc = phase_done(5);
+    if (rc) return rc;
   }
-  return phase_done(5);
+  return PBTC_OK;
 }
 
 // New charge values (positions unchanged): upload and rebuild the RHS.
@@ -1158,6 +1219,14 @@ int update_charges(pbtc_plan& pl, hipStream_t st) {
 
 // FP64 near-field corrections for every row of every block (depends on kappa).
 int recompute_near_values(pbtc_plan& pl, hipStream_t st) {
+  const int rc = launch_near_values(pl, st);
+  if (rc) return rc;
+  PBTC_HIP(hipStreamSynchronize(st));
+  return PBTC_OK;
+}
+
+// The same, queued on the stream only.
+int launch_near_values(pbtc_plan& pl, hipStream_t st) {
   NearArgs na;
   near_args(pl, &na);
   Tables tb;
@@ -1172,19 +1241,27 @@ int recompute_near_values(pbtc_plan& pl, hipStream_t st) {
     tb.glx[i] = pl.gl_x[i];
     tb.glw[i] = pl.gl_w[i];
   }
-  hipLaunchKernelGGL(k_near_values, dim3(nblocks(pl.nf_rows, 64)), dim3(64), 0, st, na, tb,
-                     pl.nf_rows, wsp<long long>(pl, pl.o_nf_ptr), wsp<int>(pl, pl.o_nf_col), wsp<int>(pl, pl.o_tris),
+  if (pl.n_nf == 0) return PBTC_OK;
+  hipLaunchKernelGGL(k_near_values, dim3(nblocks(pl.n_nf, 128)), dim3(128), 0, st, na, tb,
+                     pl.nf_rows, (int64_t)pl.n_nf, wsp<long long>(pl, pl.o_nf_ptr),
+                     wsp<int>(pl, pl.o_nf_col), wsp<int>(pl, pl.o_tris),
                      wsp<double>(pl, pl.o_verts), near_vbase(pl), wsp<int>(pl, pl.o_pan_surf),
                      wsp<double>(pl, pl.o_nf_v64), wsp<float>(pl, pl.o_nf_v32));
   PBTC_LAUNCH_CHECK();
-
-  PBTC_HIP(hipStreamSynchronize(st));
   return PBTC_OK;
 }
 
 // Diagonal blocks of the block-diagonal preconditioner (depend on kappa and
 // eps of the two regions of every surface).
 int recompute_precond(pbtc_plan& pl, hipStream_t st) {
+  const int rc = launch_precond(pl, st);
+  if (rc) return rc;
+  PBTC_HIP(hipStreamSynchronize(st));
+  return PBTC_OK;
+}
+
+// The same, queued on the stream only.
+int launch_precond(pbtc_plan& pl, hipStream_t st) {
   Tables tb;
   tb.K = pl.prm.K;
   tb.Kf = pl.prm.K_fine;
@@ -1208,7 +1285,6 @@ int recompute_precond(pbtc_plan& pl, hipStream_t st) {
                      wsp<int>(pl, pl.o_pan_surf), wsp<double>(pl, pl.o_cx), wsp<double>(pl, pl.o_cy),
                      wsp<double>(pl, pl.o_cz), ptab, wsp<double>(pl, pl.o_pinv));
   PBTC_LAUNCH_CHECK();
-  PBTC_HIP(hipStreamSynchronize(st));
   return PBTC_OK;
 }
 
@@ -1246,6 +1322,14 @@ int upload_coulomb_rows(pbtc_plan& pl, hipStream_t st) {
 // Coulomb right-hand side (Eq. matel, Q; the charges of each row's region,
 // scaled by 1/eps of that region), all rows in one launch.
 int recompute_rhs(pbtc_plan& pl, hipStream_t st) {
+  const int rc = launch_rhs(pl, st);
+  if (rc) return rc;
+  PBTC_HIP(hipStreamSynchronize(st));
+  return PBTC_OK;
+}
+
+// The same, queued on the stream only.
+int launch_rhs(pbtc_plan& pl, hipStream_t st) {
   int rc = upload_coulomb_rows(pl, st);
   if (rc) return rc;
   const int T = 64;
@@ -1254,7 +1338,6 @@ int recompute_rhs(pbtc_plan& pl, hipStream_t st) {
                      wsp<double>(pl, pl.o_cy), wsp<double>(pl, pl.o_cz), wsp<double>(pl, pl.o_qxyz),
                      wsp<double>(pl, pl.o_q), wsp<double>(pl, pl.o_b));
   PBTC_LAUNCH_CHECK();
-  PBTC_HIP(hipStreamSynchronize(st));
   return PBTC_OK;
 }
 
