@@ -121,15 +121,26 @@ __global__ __launch_bounds__(kMomThreads) void k_p2m_chunk(const int4* __restric
     for (int q = 0; q < KPT; ++q) {
       if (!on[q]) continue;
       const int k1 = kk[q][0], k2 = kk[q][1], k3 = kk[q][2];
-      for (int t = g; t < nj; t += G) {
+      auto term = [&](int t, real& s_acc, real& d_acc) {
         const real X = pw[t][0][k1], Y = pw[t][1][k2], Z = pw[t][2][k3];
-        ms[q] += sq[t][0] * X * Y * Z;
+        s_acc += sq[t][0] * X * Y * Z;
         real dl = 0;
         if (k1) dl += sq[t][1] * real(k1) * pw[t][0][k1 - 1] * Y * Z;
         if (k2) dl += sq[t][2] * real(k2) * X * pw[t][1][k2 - 1] * Z;
         if (k3) dl += sq[t][3] * real(k3) * X * Y * pw[t][2][k3 - 1];
-        md[q] += dl;
+        d_acc += dl;
+      };
+      // four sources per step into independent sums, so that their LDS
+      // reads are in flight together
+      real s4[4] = {0, 0, 0, 0}, d4[4] = {0, 0, 0, 0};
+      int t = g;
+      for (; t + 3 * G < nj; t += 4 * G) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) term(t + u * G, s4[u], d4[u]);
       }
+      for (; t < nj; t += G) term(t, s4[0], d4[0]);
+      ms[q] += (s4[0] + s4[1]) + (s4[2] + s4[3]);
+      md[q] += (d4[0] + d4[1]) + (d4[2] + d4[3]);
     }
     __syncthreads();
   }

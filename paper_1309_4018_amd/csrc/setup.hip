@@ -293,16 +293,24 @@ __global__ void k_split_write(Cell* __restrict__ cells, int lb, int le,
   }
 }
 
-__global__ __launch_bounds__(256) void k_cell_radius(Cell* __restrict__ cells, int ncell,
+// Radius of every cell about its centre: the largest distance to one of its
+// sources.  Cells [c0, c0 + gridDim.x) with gridDim.y blocks each: block y
+// takes the y-th of gridDim.y equal spans of the cell's sources.  With one
+// block per cell the radius is stored directly; otherwise the blocks combine
+// the squared maximum through an integer atomic max on its bits (non-negative
+// doubles order like their bit patterns) and k_cell_radius_fin finishes.
+__global__ __launch_bounds__(256) void k_cell_radius(Cell* __restrict__ cells, int c0,
                                                      const double* __restrict__ gx,
                                                      const double* __restrict__ gy,
                                                      const double* __restrict__ gz) {
   __shared__ double red[256];
-  const int c = blockIdx.x;
-  if (c >= ncell) return;
+  const int c = c0 + blockIdx.x;
   const Cell cl = cells[c];
+  const int span = (cl.count + gridDim.y - 1) / gridDim.y;
+  const int i0 = cl.begin + (int)blockIdx.y * span;
+  const int i1 = min(cl.begin + cl.count, i0 + span);
   double m = 0.0;
-  for (int i = cl.begin + threadIdx.x; i < cl.begin + cl.count; i += 256) {
+  for (int i = i0 + threadIdx.x; i < i1; i += 256) {
     const double dx = gx[i] - cl.cx, dy = gy[i] - cl.cy, dz = gz[i] - cl.cz;
     m = fmax(m, dx * dx + dy * dy + dz * dz);
   }
@@ -312,7 +320,17 @@ __global__ __launch_bounds__(256) void k_cell_radius(Cell* __restrict__ cells, i
     if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) cells[c].rb = sqrt(red[0]) * (1.0 + 1e-12);
+  if (threadIdx.x != 0) return;
+  if (gridDim.y == 1)
+    cells[c].rb = sqrt(red[0]) * (1.0 + 1e-12);
+  else
+    atomicMax(reinterpret_cast<unsigned long long*>(&cells[c].rb),
+              (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__global__ void k_cell_radius_fin(Cell* __restrict__ cells, int n) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) cells[c].rb = sqrt(cells[c].rb) * (1.0 + 1e-12);
 }
 
 namespace {
@@ -642,31 +660,42 @@ __global__ void k_prec_blocks(Tables T, int64_t np, const int* __restrict__ vert
 
 // ---------------------------------------------------------------------- rhs
 // b[row_off + i] = sum_k q_k / eps_r G_r(x_i, x_k) over the charges of r.
-// Coulomb right-hand side of every forward row (one thread per unknown): the
-// row's block is found by bisection over the row offsets; rows whose region
-// holds no charges get 0.
+// Coulomb right-hand side of every forward row: kCoulLanes consecutive lanes
+// per unknown stride over the charges and a fixed butterfly adds their sums;
+// the row's block is found by bisection over the row offsets; rows whose
+// region holds no charges get 0.
+constexpr int kCoulLanes = 8;
+
 __global__ void k_coulomb_rows(int64_t n_unk, const DevCoulRow* __restrict__ rows, int nrows,
                                const double* __restrict__ cx, const double* __restrict__ cy,
                                const double* __restrict__ cz, const double* __restrict__ qxyz,
                                const double* __restrict__ q, double* __restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_unk) return;
-  int lo = 0, hi = nrows - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (rows[mid].row_off <= i) lo = mid;
-    else hi = mid - 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gid / kCoulLanes;
+  const int sub = (int)(gid % kCoulLanes);
+  const bool live = i < n_unk;
+  double s = 0.0, scale = 0.0;
+  if (live) {
+    int lo = 0, hi = nrows - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rows[mid].row_off <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    const DevCoulRow& rb = rows[lo];
+    const int64_t l = i - rb.row_off;
+    const double x = cx[rb.pan_first + l], y = cy[rb.pan_first + l], z = cz[rb.pan_first + l];
+    const double kap = rb.kappa;
+    for (long long k = rb.q0 + sub; k < rb.q0 + rb.nq; k += kCoulLanes) {
+      const double dx = x - qxyz[3 * k], dy = y - qxyz[3 * k + 1], dz = z - qxyz[3 * k + 2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      s += q[k] * (kap == 0.0 ? 1.0 : exp(-kap * r)) / r;
+    }
+    scale = rb.inv_eps * kInv4Pi;
   }
-  const DevCoulRow rb = rows[lo];
-  const int64_t l = i - rb.row_off;
-  const double x = cx[rb.pan_first + l], y = cy[rb.pan_first + l], z = cz[rb.pan_first + l];
-  double s = 0.0;
-  for (long long k = rb.q0; k < rb.q0 + rb.nq; ++k) {
-    const double dx = x - qxyz[3 * k], dy = y - qxyz[3 * k + 1], dz = z - qxyz[3 * k + 2];
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    s += q[k] * (rb.kappa == 0.0 ? 1.0 : exp(-rb.kappa * r)) / r;
-  }
-  b[i] = s * rb.inv_eps * kInv4Pi;
+#pragma unroll
+  for (int o = 1; o < kCoulLanes; o <<= 1) s += __shfl_xor(s, o, 64);
+  if (live && sub == 0) b[i] = s * scale;
 }
 
 __global__ void k_fill_int(int* p, int64_t n, int v) {
@@ -761,7 +790,17 @@ int build_octree(pbtc_plan& pl, hipStream_t st, Cell* cells, int64_t cap,
     le = le + (int)total;
   }
   *n_cells = le;
-  hipLaunchKernelGGL(k_cell_radius, dim3((unsigned)le), dim3(256), 0, st, cells, le, px, py, pz);
+  // the two top levels (largest cells) split over kRadiusSpans blocks each
+  constexpr int kRadiusSpans = 32;
+  const int nbig = (*level_begin)[std::min<size_t>(2, level_begin->size() - 1)];
+  if (nbig > 0) {
+    hipLaunchKernelGGL(k_cell_radius, dim3((unsigned)nbig, kRadiusSpans), dim3(256), 0, st, cells,
+                       0, px, py, pz);
+    hipLaunchKernelGGL(k_cell_radius_fin, dim3(nblocks(nbig, 256)), dim3(256), 0, st, cells, nbig);
+  }
+  if (le > nbig)
+    hipLaunchKernelGGL(k_cell_radius, dim3((unsigned)(le - nbig), 1), dim3(256), 0, st, cells, nbig,
+                       px, py, pz);
   PBTC_LAUNCH_CHECK();
   return PBTC_OK;
 }
@@ -1332,8 +1371,9 @@ int recompute_rhs(pbtc_plan& pl, hipStream_t st) {
 int launch_rhs(pbtc_plan& pl, hipStream_t st) {
   int rc = upload_coulomb_rows(pl, st);
   if (rc) return rc;
-  const int T = 64;
-  hipLaunchKernelGGL(k_coulomb_rows, dim3(nblocks(pl.nunk, T)), dim3(T), 0, st, (int64_t)pl.nunk,
+  const int T = 256;
+  hipLaunchKernelGGL(k_coulomb_rows, dim3(nblocks(pl.nunk * kCoulLanes, T)), dim3(T), 0, st,
+                     (int64_t)pl.nunk,
                      wsp<DevCoulRow>(pl, pl.o_crows), (int)pl.rows.size(), wsp<double>(pl, pl.o_cx),
                      wsp<double>(pl, pl.o_cy), wsp<double>(pl, pl.o_cz), wsp<double>(pl, pl.o_qxyz),
                      wsp<double>(pl, pl.o_q), wsp<double>(pl, pl.o_b));
