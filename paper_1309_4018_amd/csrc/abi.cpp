@@ -222,6 +222,9 @@ pbtc_plan::~pbtc_plan() {
     }
   for (hipEvent_t e : res_ev)
     if (e) (void)hipEventDestroy(e);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (side) (void)hipStreamDestroy(side);
   if (res_pin) (void)hipHostFree(res_pin);
 }
 

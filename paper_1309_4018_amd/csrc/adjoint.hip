@@ -488,23 +488,35 @@ __global__ __launch_bounds__(kT) void k_adj_m2p(AdjArgs a, const Src<real>* __re
 
 // per Gauss point of the item's group: aout[slot] (+)= sum over units / (4 pi)
 template <typename real, int NQ>
-__global__ void k_adj_reduce(const int* __restrict__ list, const int* __restrict__ uptr,
-                             const int* __restrict__ item_block, const DevBlock* __restrict__ blocks,
-                             const real* __restrict__ partial, double* __restrict__ aS,
-                             double* __restrict__ aD, int mode, int first_slot) {
+__global__ __launch_bounds__(256) void k_adj_reduce(
+    const int* __restrict__ list, const int* __restrict__ uptr, const int* __restrict__ item_block,
+    const DevBlock* __restrict__ blocks, const real* __restrict__ partial, double* __restrict__ aS,
+    double* __restrict__ aD, int mode, int first_slot) {
+  // four waves take the item's units round-robin; their sums are added in
+  // wave order (deterministic)
+  __shared__ double lds[3][NQ][64];
   const int l = blockIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  for (int u = uptr[l] + w; u < uptr[l + 1]; u += 4)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * 64 + lane];
+  if (w > 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[w - 1][q][lane] = v[q];
+  __syncthreads();
+  if (w > 0) return;
   const int item = list[l];
   const DevBlock& b = blocks[item_block[item]];
   const long long g = item - b.aitem_off;
   const int nt = (int)min((long long)kGroup, b.gp_n - g * kGroup);
-  const int lane = threadIdx.x;
   if (lane >= nt) return;
-  double v[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-  for (int u = uptr[l]; u < uptr[l + 1]; ++u)
+  for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * 64 + lane];
+    for (int q = 0; q < NQ; ++q) v[q] += lds[k][q][lane];
   const long long i = g * kGroup + lane;  // sorted position within the surface
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -1049,10 +1061,10 @@ static int transpose_impl(pbtc_plan& pl, hipStream_t st, const double* lam, doub
       }
       const int* uptr = wsp<int>(pl, pl.o_auptr + 4 * us.ptr_off);
       if (two)
-        hipLaunchKernelGGL((k_adj_reduce<real, 4>), dim3(n), dim3(64), 0, st, list, uptr, a.item_block,
+        hipLaunchKernelGGL((k_adj_reduce<real, 4>), dim3(n), dim3(256), 0, st, list, uptr, a.item_block,
                            a.blocks, partial, aS, aD, 0, 0);
       else
-        hipLaunchKernelGGL((k_adj_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr, a.item_block,
+        hipLaunchKernelGGL((k_adj_reduce<real, 2>), dim3(n), dim3(256), 0, st, list, uptr, a.item_block,
                            a.blocks, partial, aS, aD, 0, 0);
       PBTC_LAUNCH_CHECK();
     }
@@ -1067,7 +1079,7 @@ static int transpose_impl(pbtc_plan& pl, hipStream_t st, const double* lam, doub
       const int kind0 = (ks == KS_L || ks == KS_LY) ? 0 : 1;
       for (int slot = 0; slot < (two ? 2 : 1); ++slot) {
         launch_adj_m2p<real>(pl, st, a, grid, gpos, mom, slot == 0 ? kind0 : 1, slot, partial);
-        hipLaunchKernelGGL((k_adj_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr,
+        hipLaunchKernelGGL((k_adj_reduce<real, 2>), dim3(n), dim3(256), 0, st, list, uptr,
                            a.item_block, a.blocks, partial, aS, aD, 1, slot);
       }
       PBTC_LAUNCH_CHECK();

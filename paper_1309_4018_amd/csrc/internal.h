@@ -275,12 +275,16 @@ struct pbtc_plan {
   // per kernel kind: 0 P2P, 1 Laplace M2P, 2 Yukawa M2P
   double prof_t[3] = {0, 0, 0}, prof_flop[3] = {0, 0, 0};
   int prof_n[3] = {0, 0, 0};
-  int64_t prof_count = 0;
-  double setup_phase[6] = {0, 0, 0, 0, 0, 0};  // host seconds per set-up phase  // FP32 operator evaluations seen by the sampler
+  int64_t prof_count = 0;  // FP32 operator evaluations seen by the sampler
+  double setup_phase[6] = {0, 0, 0, 0, 0, 0};  // host seconds per set-up phase
   // GMRES residual readback: pinned host slots and their events
   double* res_pin = nullptr;
   int res_pin_n = 0;
   hipEvent_t res_ev[2] = {nullptr, nullptr};
+  // second stream of the operator (the moment pass runs beside P2P) and the
+  // events that fork and join it (created on first use)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~pbtc_plan();
   std::vector<double> item_flop_p2p[2][pbtc::KS_COUNT], item_flop_m2p[2][pbtc::KS_COUNT];
   double launch_flop_p2p[2][pbtc::KS_COUNT] = {}, launch_flop_m2p[2][pbtc::KS_COUNT] = {};

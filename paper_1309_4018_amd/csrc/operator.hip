@@ -334,40 +334,56 @@ __global__ __launch_bounds__(kItemThreads) void k_m2p(UnitArgs a, const real* __
   unit_store<real, 2>(partial, u, acc);
 }
 
-// Sum of the units of every listed item in unit order, times 1/(4 pi), into
-// S and D of kernel slots first_slot.. (mode 0 store, mode 1 add).
+// Sum of the units of every listed item, times 1/(4 pi), into S and D of
+// kernel slots first_slot.. (mode 0 store, mode 1 add).  The four waves of
+// the work-group take the item's units round-robin (wave w: units w, w + 4,
+// ...), so that four times as many loads are in flight; their sums are then
+// added in wave order (fixed order: deterministic).
+constexpr int kReduceWaves = 4;
+
 template <typename real, int NQ>
-__global__ void k_reduce(const int* __restrict__ list, const int* __restrict__ uptr,
-                         const int* __restrict__ item_block, const DevBlock* __restrict__ blocks,
-                         const int* __restrict__ tidx, const real* __restrict__ partial,
-                         double* __restrict__ S, double* __restrict__ D, int mode, int first_slot) {
+__global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
+    const int* __restrict__ list, const int* __restrict__ uptr, const int* __restrict__ item_block,
+    const DevBlock* __restrict__ blocks, const int* __restrict__ tidx,
+    const real* __restrict__ partial, double* __restrict__ S, double* __restrict__ D, int mode,
+    int first_slot) {
+  __shared__ double lds[kReduceWaves - 1][NQ][64];
   const int l = blockIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  const int u0 = uptr[l], u1 = uptr[l + 1];
+  int u = u0 + w;
+  // two units per step per wave
+  for (; u + kReduceWaves < u1; u += 2 * kReduceWaves) {
+    real p[2][NQ];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        p[k][q] = partial[((size_t)(u + k * kReduceWaves) * 4 + q) * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] += (double)p[0][q] + (double)p[1][q];
+  }
+  if (u < u1)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * 64 + lane];
+  if (w > 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[w - 1][q][lane] = v[q];
+  __syncthreads();
+  if (w > 0) return;
   const int item = list[l];
   const DevBlock& b = blocks[item_block[item]];
   const long long g = item - b.item_off;
   const long long t0 = b.tgt_off + g * kGroup;
   const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
-  const int lane = threadIdx.x;
   if (lane >= nt) return;
-  double v[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-  // four units per step: their loads are in flight together (fixed order)
-  int u = uptr[l];
-  const int u1 = uptr[l + 1];
-  for (; u + 4 <= u1; u += 4) {
-    real p[4][NQ];
+  for (int k = 0; k < kReduceWaves - 1; ++k)
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) p[w][q] = partial[((size_t)(u + w) * 4 + q) * 64 + lane];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      v[q] += ((double)p[0][q] + (double)p[1][q]) + ((double)p[2][q] + (double)p[3][q]);
-  }
-  for (; u < u1; ++u)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * 64 + lane];
+    for (int q = 0; q < NQ; ++q) v[q] += lds[k][q][lane];
   const long long i = tidx[t0 + lane] - b.tgt_off;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -565,10 +581,25 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
   bool timed = false;
   if (sizeof(real) == 4 && phase == 0 && pl.prm.profile > 0)
     timed = pl.prof_count++ % pl.prm.profile == 0;
-  if (tree) {
+  // the moment pass (latency-bound) runs on a second stream beside the
+  // P2P launches (ALU-bound); M2P waits for it
+  const bool fork = tree && pl.n_far > 0;
+  if (fork) {
+    if (!pl.side) {
+      PBTC_HIP(hipStreamCreateWithFlags(&pl.side, hipStreamNonBlocking));
+      PBTC_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
+      PBTC_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
+    }
+    PBTC_HIP(hipEventRecord(pl.ev_fork, st));
+    PBTC_HIP(hipStreamWaitEvent(pl.side, pl.ev_fork, 0));
+    int rc = launch_moments<real>(pl, pl.side, mom, src);
+    if (rc) return rc;
+    PBTC_HIP(hipEventRecord(pl.ev_join, pl.side));
+  } else if (tree) {
     int rc = launch_moments<real>(pl, st, mom, src);
     if (rc) return rc;
   }
+  bool joined = !fork;
   UnitArgs a;
   a.item_block = wsp<int>(pl, pl.o_items);
   a.blocks = wsp<DevBlock>(pl, pl.o_blocks);
@@ -606,16 +637,20 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
       prof_mark(pl, st, timed, 0, 0.0, false);
       const int* uptr = wsp<int>(pl, pl.o_uptr + 4 * us.ptr_off);
       if (ks == KS_L || ks == KS_Y)
-        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr, a.item_block,
-                           a.blocks, tidx, partial, S, D, 0, 0);
+        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64 * kReduceWaves), 0, st, list,
+                           uptr, a.item_block, a.blocks, tidx, partial, S, D, 0, 0);
       else
-        hipLaunchKernelGGL((k_reduce<real, 4>), dim3(n), dim3(64), 0, st, list, uptr, a.item_block,
-                           a.blocks, tidx, partial, S, D, 0, 0);
+        hipLaunchKernelGGL((k_reduce<real, 4>), dim3(n), dim3(64 * kReduceWaves), 0, st, list,
+                           uptr, a.item_block, a.blocks, tidx, partial, S, D, 0, 0);
       PBTC_LAUNCH_CHECK();
     }
     if (tree && pl.n_far > 0) {
       const UnitSet& us = pl.units[phase][ks][1];
       if (us.n == 0) continue;
+      if (!joined) {
+        PBTC_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));
+        joined = true;
+      }
       a.units = wsp<int4>(pl, pl.o_units + 16 * us.off);
       a.nunits = (int)us.n;
       a.cells_list = wsp<int>(pl, pl.o_far);
@@ -635,12 +670,13 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
         else
           launch_m2p<real, 1>(pl, st, a, grid, tx, ty, tz, mom, slot, partial);
         prof_mark(pl, st, timed, 1 + kind, 0.0, false);
-        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64), 0, st, list, uptr,
-                           a.item_block, a.blocks, tidx, partial, S, D, 1, slot);
+        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64 * kReduceWaves), 0, st, list,
+                           uptr, a.item_block, a.blocks, tidx, partial, S, D, 1, slot);
       }
       PBTC_LAUNCH_CHECK();
     }
   }
+  if (!joined) PBTC_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));  // no far field in this phase
   // near-field corrections of this phase's blocks
   const long long r0 = phase == 0 ? 0 : pl.nf_fwd_rows;
   const long long r1 = phase == 0 ? pl.nf_fwd_rows : pl.nf_rows;
