@@ -101,16 +101,17 @@ __global__ __launch_bounds__(kRedThreads) void k_dots_seg(const double* __restri
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ld + i] = s;
 }
 
-// out[c * ldo + i] = sum of the chunk partials of system c, in chunk order:
-// one thread per (system c = blockIdx.x, i); with root set, the square root.
+// out[c * ldo + i] = sum of the chunk partials of system c: one wavefront
+// per (system c = blockIdx.x, i = blockIdx.y), lanes strided over the chunks,
+// then a fixed butterfly; with root set, the square root.
 __global__ void k_sum_seg(const double* __restrict__ partial, int pld, const int* __restrict__ chunk0,
-                          int nv, int ldo, int root, double* __restrict__ out) {
-  const int c = blockIdx.x;
-  const int i = blockIdx.y * blockDim.x + threadIdx.x;
-  if (i >= nv) return;
+                          int ldo, int root, double* __restrict__ out) {
+  const int c = blockIdx.x, i = blockIdx.y;
   double s = 0.0;
-  for (int b = chunk0[c]; b < chunk0[c + 1]; ++b) s += partial[(size_t)b * pld + i];
-  out[(size_t)c * ldo + i] = root ? sqrt(fmax(s, 0.0)) : s;
+  for (int b = chunk0[c] + (int)threadIdx.x; b < chunk0[c + 1]; b += 64)
+    s += partial[(size_t)b * pld + i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[(size_t)c * ldo + i] = root ? sqrt(fmax(s, 0.0)) : s;
 }
 
 // w -= sum_i h[c, i] V_i on the entries of system c
@@ -182,45 +183,61 @@ __global__ void k_init_seg(int nc, double* giv, int gstride, int ld, const doubl
   }
 }
 
-// Givens step for column j of every active system: H(:, j) = h, H(j+1, j) =
-// hn; apply the stored rotations, form the new one, update g, and deactivate
-// the system once |g_{j+1}| <= tol * ref (kfin = j + 1).
+// Givens step for column j of every active system (one work-group of 64 per
+// system): H(:, j) = h + h2 (the two Gram-Schmidt passes), H(j+1, j) = hn;
+// apply the stored rotations, form the new one, update g, and deactivate the
+// system once |g_{j+1}| <= tol * ref (kfin = j + 1).  The column and the
+// rotations pass through LDS; the rotations themselves are sequential.
 __global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h,
                              const double* __restrict__ h2, double* __restrict__ H,
                              double* __restrict__ giv, int gstride, double* __restrict__ sc) {
-  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-    double* act = sc + (size_t)SC_ACTIVE * nc;
-    if (act[c] <= 0.0) continue;
-    double* cs = giv + (size_t)c * gstride;
-    double* sn = cs + ld;
-    double* g = cs + 2 * ld;
-    double* col = H + ((size_t)c * ld + j) * ld;
-    const double* hc = h + (size_t)c * ld;
-    const double* h2c = h2 + (size_t)c * ld;
-    for (int i = 0; i <= j; ++i) col[i] = hc[i] + h2c[i];
-    col[j + 1] = sc[(size_t)SC_HN * nc + c];
-    for (int i = 0; i < j; ++i) {
-      const double a = col[i], b = col[i + 1];
-      col[i] = cs[i] * a + sn[i] * b;
-      col[i + 1] = -sn[i] * a + cs[i] * b;
+  extern __shared__ double lds[];  // col (ld + 1), cs (ld), sn (ld)
+  const int c = blockIdx.x;
+  double* act = sc + (size_t)SC_ACTIVE * nc;
+  if (act[c] <= 0.0) return;
+  double* cs = giv + (size_t)c * gstride;
+  double* sn = cs + ld;
+  double* g = cs + 2 * ld;
+  double* col = H + ((size_t)c * ld + j) * ld;
+  const double* hc = h + (size_t)c * ld;
+  const double* h2c = h2 + (size_t)c * ld;
+  double* lc = lds;
+  double* lcs = lds + ld + 1;
+  double* lsn = lcs + ld;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    lc[i] = hc[i] + h2c[i];
+    if (i < j) {
+      lcs[i] = cs[i];
+      lsn[i] = sn[i];
     }
-    const double a = col[j], b = col[j + 1];
+  }
+  if (threadIdx.x == 0) lc[j + 1] = sc[(size_t)SC_HN * nc + c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < j; ++i) {
+      const double a = lc[i], b = lc[i + 1];
+      lc[i] = lcs[i] * a + lsn[i] * b;
+      lc[i + 1] = -lsn[i] * a + lcs[i] * b;
+    }
+    const double a = lc[j], b = lc[j + 1];
     const double den = hypot(a, b);
     const double cc = den > 0.0 ? a / den : 1.0, ss = den > 0.0 ? b / den : 0.0;
     cs[j] = cc;
     sn[j] = ss;
-    col[j] = den;
-    col[j + 1] = 0.0;
+    lc[j] = den;
+    lc[j + 1] = 0.0;
     g[j + 1] = -ss * g[j];
     g[j] = cc * g[j];
     const double ref = sc[(size_t)SC_REF * nc + c];
     const double res = fabs(g[j + 1]) / ref;
     sc[(size_t)SC_RES * nc + c] = res;
-    if (res <= sc[(size_t)SC_TOL * nc + c] || col[j] == 0.0) {
+    if (res <= sc[(size_t)SC_TOL * nc + c] || den == 0.0) {
       act[c] = 0.0;
       sc[(size_t)SC_KFIN * nc + c] = j + 1;
     }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) col[i] = lc[i];
 }
 
 // end of a cycle: kfin of still-active systems = columns built; y = R^-1 g
@@ -337,8 +354,7 @@ struct Krylov {
   int dots(const double* Vb, int nv, const double* v, double* out) {
     hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, nv), dim3(kRedThreads), 0, st, Vb, nv, n, v,
                        chunks, red, ld);
-    hipLaunchKernelGGL(k_sum_seg, dim3(nc, nblocks(nv, 64)), dim3(64), 0, st, red, ld, chunk0, nv,
-                       ld, 0, out);
+    hipLaunchKernelGGL(k_sum_seg, dim3(nc, nv), dim3(64), 0, st, red, ld, chunk0, ld, 0, out);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
@@ -346,7 +362,7 @@ struct Krylov {
   int norm(const double* v, double* out) {
     hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, 1), dim3(kRedThreads), 0, st, v, 1, n, v, chunks,
                        red, ld);
-    hipLaunchKernelGGL(k_sum_seg, dim3(nc, 1), dim3(64), 0, st, red, ld, chunk0, 1, 1, 1, out);
+    hipLaunchKernelGGL(k_sum_seg, dim3(nc, 1), dim3(64), 0, st, red, ld, chunk0, 1, 1, out);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
@@ -517,8 +533,8 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, int prec, const double* r
         hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.w, n,
                            K.scal(SC_HN), K.comp, K.scal(SC_ACTIVE), vn);
         // Hessenberg column = first-pass + second-pass coefficients
-        hipLaunchKernelGGL(k_givens_seg, dim3(1), dim3(64), 0, st, nc, j, ld, K.hbuf, K.h2buf, K.H,
-                           K.giv, K.gstride, K.sc);
+        hipLaunchKernelGGL(k_givens_seg, dim3(nc), dim3(64), 8 * (3 * ld + 1), st, nc, j, ld,
+                           K.hbuf, K.h2buf, K.H, K.giv, K.gstride, K.sc);
         PBTC_LAUNCH_CHECK();
         // residual estimates and active flags of every system (SC_RES, SC_ACTIVE)
         PBTC_HIP(hipMemcpyAsync(pl.res_pin + (size_t)(j & 1) * 2 * nc, K.scal(SC_RES), 16 * nc,
