@@ -162,6 +162,75 @@ __global__ __launch_bounds__(kRedThreads) void k_sub_combo_norm_seg(
   if (threadIdx.x == 0) partial[blockIdx.x] = sq;
 }
 
+// One Gram-Schmidt pass with its coefficient sums folded in: every block
+// (kChunkBlocks per chunk, a chunk lies in one system c) first forms
+// h[c, i] = sum of the chunk partials of system c (lanes strided over the
+// chunks, a fixed butterfly: the same value in every block, equal to
+// k_sum_seg's), the system's first block stores it in hout, then
+// w -= sum_i h[c, i] V_i on the block's entries.  With NORM, partial norms of
+// the new w per block go to nrm.
+template <bool NORM>
+__global__ __launch_bounds__(kRedThreads) void k_gs_pass_seg(
+    const double* __restrict__ V, int nv, int64_t n, const double* __restrict__ partial, int pld,
+    const int4* __restrict__ chunks, const int* __restrict__ chunk0, double* __restrict__ hout,
+    int ld, double* __restrict__ w, double* __restrict__ nrm) {
+  extern __shared__ double hl[];  // nv coefficients
+  __shared__ double lds[kRedThreads / 64];
+  const int4 ch = chunks[blockIdx.x / kChunkBlocks];
+  const int c = ch.x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b0 = chunk0[c], b1 = chunk0[c + 1];
+  const bool first = (int)blockIdx.x == b0 * kChunkBlocks;
+  for (int i = wv; i < nv; i += kRedThreads / 64) {
+    double s = 0.0;
+    for (int b = b0 + lane; b < b1; b += 64) s += partial[(size_t)b * pld + i];
+    s = wave_sum(s);
+    if (lane == 0) {
+      hl[i] = s;
+      if (first) hout[(size_t)c * ld + i] = s;
+    }
+  }
+  __syncthreads();
+  const int64_t j = ch.y + (int64_t)(blockIdx.x % kChunkBlocks) * kRedThreads + threadIdx.x;
+  double sq = 0.0;
+  if (j < ch.z) {
+    double s = w[j];
+    for (int i = 0; i < nv; ++i) s -= hl[i] * V[(size_t)i * n + j];
+    w[j] = s;
+    sq = s * s;
+  }
+  if (NORM) {
+    sq = block_sum(sq, lds);
+    if (threadIdx.x == 0) nrm[blockIdx.x] = sq;
+  }
+}
+
+// The norm of system c from the partials of k_gs_pass_seg (lanes strided,
+// fixed butterfly, as k_norm_seg), then out = w / norm for active systems
+// and 0 for the others; the system's first block stores the norm in hn.
+__global__ __launch_bounds__(kRedThreads) void k_norm_scale_seg(
+    const double* __restrict__ w, const double* __restrict__ nrm, const int4* __restrict__ chunks,
+    const int* __restrict__ chunk0, const double* __restrict__ active, double* __restrict__ hn,
+    double* __restrict__ out) {
+  __shared__ double norm;
+  const int4 ch = chunks[blockIdx.x / kChunkBlocks];
+  const int c = ch.x;
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int b = chunk0[c] * kChunkBlocks + (int)threadIdx.x; b < chunk0[c + 1] * kChunkBlocks;
+         b += 64)
+      s += nrm[b];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+      norm = sqrt(fmax(s, 0.0));
+      if ((int)blockIdx.x == chunk0[c] * kChunkBlocks) hn[c] = norm;
+    }
+  }
+  __syncthreads();
+  const int64_t j = ch.y + (int64_t)(blockIdx.x % kChunkBlocks) * kRedThreads + threadIdx.x;
+  if (j < ch.z) out[j] = (active[c] > 0.0 && norm > 0.0) ? w[j] / norm : 0.0;
+}
+
 // out = w / s[c] for active systems, 0 for the others
 __global__ void k_scale_seg(const double* __restrict__ w, int64_t n, const double* __restrict__ s,
                             const int* __restrict__ comp, const double* __restrict__ active,
@@ -324,6 +393,7 @@ struct Krylov {
   double* h2buf;  // nc x ld
   double* nrm;    // norm partials of the fused second pass: nchunks x kChunkBlocks
   double* w;
+  bool fuse;      // coefficient sums folded into the Gram-Schmidt passes
   const int4* chunks;
   const int* chunk0;
   const int* comp;
@@ -343,6 +413,12 @@ struct Krylov {
     hbuf = red + (size_t)nchunks * ld;
     h2buf = hbuf + (size_t)nc * ld;
     nrm = h2buf + (size_t)nc * ld;
+    // every block of a fused pass re-reads its system's chunk partials:
+    // worth it while systems span few chunks
+    int maxch = 0;
+    for (int c = 0; c < nc; ++c)
+      maxch = std::max(maxch, pl.comp_chunk0[c + 1] - pl.comp_chunk0[c]);
+    fuse = maxch <= 256;
     w = wsp<double>(pl, pl.o_w);
     chunks = wsp<int4>(pl, pl.o_chunks);
     chunk0 = reinterpret_cast<const int*>(chunks + nchunks);
@@ -371,6 +447,39 @@ struct Krylov {
     hipLaunchKernelGGL(k_sub_combo_norm_seg, dim3(nchunks * kChunkBlocks), dim3(kRedThreads), 0, st,
                        V, nv, n, h, ld, chunks, w, nrm);
     hipLaunchKernelGGL(k_norm_seg, dim3(nc), dim3(64), 0, st, nrm, chunk0, kChunkBlocks, out);
+    PBTC_LAUNCH_CHECK();
+    return PBTC_OK;
+  }
+  // one Arnoldi orthogonalisation of w against V_0..V_{nv-1} (CGS2) with
+  // coefficients in h1 and h2 (per system), then vn = w / ||w|| and
+  // hn = ||w|| for active systems
+  int arnoldi(int nv, double* h1, double* h2, double* hn, const double* active, double* vn) {
+    const int T = 256;
+    if (!fuse) {
+      int rc = dots(V, nv, w, h1);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_sub_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, V, nv, n, h1, ld,
+                         comp, w);
+      rc = dots(V, nv, w, h2);
+      if (rc) return rc;
+      rc = sub_combo_norm(nv, h2, hn);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, w, n, hn, comp, active,
+                         vn);
+      PBTC_LAUNCH_CHECK();
+      return PBTC_OK;
+    }
+    const dim3 grid(nchunks * kChunkBlocks);
+    hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, nv), dim3(kRedThreads), 0, st, V, nv, n, w, chunks,
+                       red, ld);
+    hipLaunchKernelGGL(k_gs_pass_seg<false>, grid, dim3(kRedThreads), 8 * nv, st, V, nv, n, red, ld,
+                       chunks, chunk0, h1, ld, w, nrm);
+    hipLaunchKernelGGL(k_dots_seg, dim3(nchunks, nv), dim3(kRedThreads), 0, st, V, nv, n, w, chunks,
+                       red, ld);
+    hipLaunchKernelGGL(k_gs_pass_seg<true>, grid, dim3(kRedThreads), 8 * nv, st, V, nv, n, red, ld,
+                       chunks, chunk0, h2, ld, w, nrm);
+    hipLaunchKernelGGL(k_norm_scale_seg, grid, dim3(kRedThreads), 0, st, w, nrm, chunks, chunk0,
+                       active, hn, vn);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
@@ -522,16 +631,8 @@ static int gmres(pbtc_plan& pl, hipStream_t st, Op op, int prec, const double* r
         }
         if (rc) return rc;
         // CGS2: two passes of classical Gram-Schmidt, per system
-        rc = K.dots(K.V, j + 1, K.w, K.hbuf);
+        rc = K.arnoldi(j + 1, K.hbuf, K.h2buf, K.scal(SC_HN), K.scal(SC_ACTIVE), vn);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_sub_combo_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.V, j + 1, n,
-                           K.hbuf, ld, K.comp, K.w);
-        rc = K.dots(K.V, j + 1, K.w, K.h2buf);
-        if (rc) return rc;
-        rc = K.sub_combo_norm(j + 1, K.h2buf, K.scal(SC_HN));
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, K.w, n,
-                           K.scal(SC_HN), K.comp, K.scal(SC_ACTIVE), vn);
         // Hessenberg column = first-pass + second-pass coefficients
         hipLaunchKernelGGL(k_givens_seg, dim3(nc), dim3(64), 8 * (3 * ld + 1), st, nc, j, ld,
                            K.hbuf, K.h2buf, K.H, K.giv, K.gstride, K.sc);
