@@ -114,7 +114,9 @@ typedef struct {
   int profile;      /* n > 0: time the P2P and M2P kernel launches of every
                        n-th evaluation of the FP32 operator (A x) with HIP
                        events on the caller's stream (pbtc_result.t_p2p_s
-                       ...); 0: off */
+                       ...); 0: off.  Other evaluations run the moment pass
+                       on a second stream beside P2P; a timed one runs it
+                       first, so that each timed launch has the GPU alone */
   int precond;      /* PBTC_PREC_NONE or PBTC_PREC_BLOCK_DIAG (forward and
                        adjoint solves) */
 } pbtc_params;

@@ -222,8 +222,8 @@ pbtc_plan::~pbtc_plan() {
     }
   for (hipEvent_t e : res_ev)
     if (e) (void)hipEventDestroy(e);
-  if (ev_fork) (void)hipEventDestroy(ev_fork);
-  if (ev_join) (void)hipEventDestroy(ev_join);
+  for (hipEvent_t e : {ev_fork, ev_join})
+    if (e) (void)hipEventDestroy(e);
   if (side) (void)hipStreamDestroy(side);
   if (res_pin) (void)hipHostFree(res_pin);
 }

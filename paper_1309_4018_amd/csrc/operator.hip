@@ -213,26 +213,26 @@ __device__ __forceinline__ void pair(real x, real y, real z, const Src<real>& s,
   const real r2 = dx * dx + dy * dy + dz * dz;
   const real rinv = r2 > real(0) ? rsqrt_(r2) : real(0);
   const real pd = s.px * dx + s.py * dy + s.pz * dz;
-  const real r3 = rinv * rinv * rinv;
+  const real t = rinv * rinv;
   if (KS == KS_L || KS == KS_LY) {
     acc[0] += s.q * rinv;
-    acc[1] += pd * r3;
+    acc[1] += pd * (t * rinv);
   }
+  // Yukawa double layer: pd e (1 + kappa r) / r^3 = pd (e / r) (1/r^2 + kappa / r)
   if (KS == KS_Y || KS == KS_LY || KS == KS_YY) {
     const real kap = KS == KS_LY ? k1 : k0;
     const real ea = KS == KS_LY ? a1 : a0;
     const real r = r2 * rinv;
-    const real e = exp_scaled(ea * r);
+    const real er = exp_scaled(ea * r) * rinv;
     const int o = KS == KS_LY ? 2 : 0;
-    const real er = e * rinv;
     acc[o] += s.q * er;
-    acc[o + 1] += pd * (r3 * e) * (real(1) + kap * r);
+    acc[o + 1] += pd * (er * (kap * rinv + t));
   }
   if (KS == KS_YY) {
     const real r = r2 * rinv;
-    const real e = exp_scaled(a1 * r);
-    acc[2] += s.q * e * rinv;
-    acc[3] += pd * (r3 * e) * (real(1) + k1 * r);
+    const real er = exp_scaled(a1 * r) * rinv;
+    acc[2] += s.q * er;
+    acc[3] += pd * (er * (k1 * rinv + t));
   }
 }
 
@@ -582,8 +582,10 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
   if (sizeof(real) == 4 && phase == 0 && pl.prm.profile > 0)
     timed = pl.prof_count++ % pl.prm.profile == 0;
   // the moment pass (latency-bound) runs on a second stream beside the
-  // P2P launches (ALU-bound); M2P waits for it
-  const bool fork = tree && pl.n_far > 0;
+  // P2P launches (ALU-bound); M2P waits for it.  A sampled (timed)
+  // evaluation runs it first instead, so that each timed launch has the GPU
+  // to itself.
+  const bool fork = tree && pl.n_far > 0 && !timed;
   if (fork) {
     if (!pl.side) {
       PBTC_HIP(hipStreamCreateWithFlags(&pl.side, hipStreamNonBlocking));
