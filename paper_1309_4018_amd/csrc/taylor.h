@@ -134,42 +134,174 @@ __device__ __forceinline__ void coef_step(real* a, real* b, real dx, real dy, re
   }
 }
 
-// sum_k a_k M[k] and sum_k a_k M[N + k] for the Laplace kernel 1/R.
+// sum_k a_k M[k] and sum_k a_k M[N + k] for the Laplace kernel 1/R, with
+// the coefficients scaled per degree: a_k = rho_n beta_k for |k| = n, where
+// rho_0 = 1/R and rho_n = c1(n) rho_{n-1} / R^2, c1(n) = (2n - 1)/n.  The
+// recurrence above then reads
+//   beta_k = sum_i d_i beta_{k-e_i} - w_n R^2 sum_i beta_{k-2e_i},
+//   w_n = (n - 1)^2 / ((2n - 1)(2n - 3)),   beta_0 = 1,
+// one fused multiply-add per coefficient instead of three operations; the
+// contraction is summed per degree and the rho_n enter by Horner's rule.
 template <int P, typename real>
 __device__ __forceinline__ void taylor_laplace(real dx, real dy, real dz, real rinv,
                                                const real* __restrict__ M, real& s, real& d) {
   constexpr int N = MultiIndex<P>::N;
+  constexpr MultiIndex<P> T{};
   const real r2inv = rinv * rinv;
-  real a[N];
-  a[0] = rinv;
-  s += a[0] * M[0];
-  d += a[0] * M[N];
+  const real r2 = dx * dx + dy * dy + dz * dz;
+  real wr[P + 1];
+  static_for<P + 1>([&](auto nc) {
+    constexpr int n = decltype(nc)::value;
+    if constexpr (n >= 2) {
+      constexpr real w = real((n - 1) * (n - 1)) / real((2 * n - 1) * (2 * n - 3));
+      wr[n] = w * r2;
+    } else {
+      wr[n] = real(0);
+    }
+  });
+  real beta[N];
+  real S[P + 1], D[P + 1];
+  static_for<P + 1>([&](auto nc) {
+    S[decltype(nc)::value] = real(0);
+    D[decltype(nc)::value] = real(0);
+  });
+  beta[0] = real(1);
+  S[0] = M[0];
+  D[0] = M[N];
   static_for<N - 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value + 1;
-    coef_step<P, k, false, real>(a, a, dx, dy, dz, r2inv, real(0));
-    s += a[k] * M[k];
-    d += a[k] * M[N + k];
+    constexpr int n = T.n[k];
+    constexpr int i10 = T.m1[k][0], i11 = T.m1[k][1], i12 = T.m1[k][2];
+    constexpr int i20 = T.m2[k][0], i21 = T.m2[k][1], i22 = T.m2[k][2];
+    real s1 = real(0), s2 = real(0);
+    if constexpr (i10 >= 0) s1 += dx * beta[i10];
+    if constexpr (i11 >= 0) s1 += dy * beta[i11];
+    if constexpr (i12 >= 0) s1 += dz * beta[i12];
+    if constexpr (i20 >= 0) s2 += beta[i20];
+    if constexpr (i21 >= 0) s2 += beta[i21];
+    if constexpr (i22 >= 0) s2 += beta[i22];
+    if constexpr (i20 >= 0 || i21 >= 0 || i22 >= 0)
+      beta[k] = s1 - wr[n] * s2;
+    else
+      beta[k] = s1;
+    S[n] += beta[k] * M[k];
+    D[n] += beta[k] * M[N + k];
   });
+  // sum_n rho_n S_n = (1/R) (S_0 + g_1 (S_1 + g_2 (S_2 + ...))), g_n = c1(n) / R^2
+  real hs = S[P], hd = D[P];
+  static_for<P>([&](auto nc) {
+    constexpr int n = P - decltype(nc)::value;  // P .. 1
+    constexpr real c1 = real(2 * n - 1) / real(n);
+    const real g = c1 * r2inv;
+    hs = S[n - 1] + g * hs;
+    hd = D[n - 1] + g * hd;
+  });
+  s += rinv * hs;
+  d += rinv * hd;
 }
 
-// Same for the Yukawa kernel exp(-kappa R)/R; e = exp(-kappa R).
+// Same for the Yukawa kernel exp(-kappa R)/R; e = exp(-kappa R).  Scaled
+// per degree like the Laplace form: a_k = rho_n alpha_k and b_k = sigma_n
+// beta_k with rho_n as above, sigma_0 = e, sigma_n = kappa rho_{n-1} / n.
+// The two-sequence recurrence then reads, for |k| = n >= 1,
+//   alpha_k = s1(alpha) - A_n s2(alpha) + B_n s1(beta) - C_n s2(beta),
+//   beta_k  = s1(alpha) - V_n s2(alpha),
+// with s1(x) = sum_i d_i x_{k-e_i}, s2(x) = sum_i x_{k-2e_i},
+// alpha_0 = e, beta_0 = 1, and per-degree factors
+//   A_n = (n-1) R^2 / ((2n-1) c1(n-1)),  V_n = R^2 / c1(n-1),
+//   B_1 = kappa e R,  B_n = kappa^2 R^2 / ((n-1)(2n-1) c1(n-1))  (n >= 2),
+//   C_2 = kappa e R^3 / 3,
+//   C_n = kappa^2 R^4 / ((n-2)(2n-1) c1(n-1) c1(n-2))  (n >= 3).
 template <int P, typename real>
 __device__ __forceinline__ void taylor_yukawa(real dx, real dy, real dz, real rinv, real e,
                                               real kappa, const real* __restrict__ M, real& s,
                                               real& d) {
   constexpr int N = MultiIndex<P>::N;
+  constexpr MultiIndex<P> T{};
   const real r2inv = rinv * rinv;
-  real a[N], b[N];
-  a[0] = e * rinv;
-  b[0] = e;
-  s += a[0] * M[0];
-  d += a[0] * M[N];
+  const real r2 = dx * dx + dy * dy + dz * dz;
+  const real R = r2 * rinv;
+  const real k2r2 = kappa * kappa * r2;
+  const real k2r4 = k2r2 * r2;
+  real A[P + 1], B[P + 1], C[P + 1], V[P + 1];
+  static_for<P + 1>([&](auto nc) {
+    constexpr int n = decltype(nc)::value;
+    A[n] = B[n] = C[n] = V[n] = real(0);
+    if constexpr (n == 1) B[1] = kappa * e * R;
+    if constexpr (n >= 2) {
+      constexpr real c1m = real(2 * n - 3) / real(n - 1);  // c1(n - 1)
+      A[n] = (real(n - 1) / (real(2 * n - 1) * c1m)) * r2;
+      V[n] = (real(1) / c1m) * r2;
+      B[n] = (real(1) / (real((n - 1) * (2 * n - 1)) * c1m)) * k2r2;
+    }
+    if constexpr (n == 2) C[2] = kappa * e * R * r2 * (real(1) / real(3));
+    if constexpr (n >= 3) {
+      constexpr real c1m = real(2 * n - 3) / real(n - 1);   // c1(n - 1)
+      constexpr real c1mm = real(2 * n - 5) / real(n - 2);  // c1(n - 2)
+      C[n] = (real(1) / (real((n - 2) * (2 * n - 1)) * c1m * c1mm)) * k2r4;
+    }
+  });
+  real alpha[N], beta[N];
+  real S[P + 1], D[P + 1];
+  static_for<P + 1>([&](auto nc) {
+    S[decltype(nc)::value] = real(0);
+    D[decltype(nc)::value] = real(0);
+  });
+  alpha[0] = e;
+  beta[0] = real(1);
+  S[0] = e * M[0];
+  D[0] = e * M[N];
   static_for<N - 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value + 1;
-    coef_step<P, k, true, real>(a, b, dx, dy, dz, r2inv, kappa);
-    s += a[k] * M[k];
-    d += a[k] * M[N + k];
+    constexpr int n = T.n[k];
+    constexpr int i10 = T.m1[k][0], i11 = T.m1[k][1], i12 = T.m1[k][2];
+    constexpr int i20 = T.m2[k][0], i21 = T.m2[k][1], i22 = T.m2[k][2];
+    constexpr bool has2 = i20 >= 0 || i21 >= 0 || i22 >= 0;
+    real s1a = real(0), s2a = real(0), s1b = real(0), s2b = real(0);
+    if constexpr (i10 >= 0) {
+      s1a += dx * alpha[i10];
+      s1b += dx * beta[i10];
+    }
+    if constexpr (i11 >= 0) {
+      s1a += dy * alpha[i11];
+      s1b += dy * beta[i11];
+    }
+    if constexpr (i12 >= 0) {
+      s1a += dz * alpha[i12];
+      s1b += dz * beta[i12];
+    }
+    if constexpr (i20 >= 0) {
+      s2a += alpha[i20];
+      s2b += beta[i20];
+    }
+    if constexpr (i21 >= 0) {
+      s2a += alpha[i21];
+      s2b += beta[i21];
+    }
+    if constexpr (i22 >= 0) {
+      s2a += alpha[i22];
+      s2b += beta[i22];
+    }
+    if constexpr (has2) {
+      alpha[k] = s1a - A[n] * s2a + B[n] * s1b - C[n] * s2b;
+      if constexpr (n < P) beta[k] = s1a - V[n] * s2a;
+    } else {
+      alpha[k] = s1a + B[n] * s1b;
+      if constexpr (n < P) beta[k] = s1a;
+    }
+    S[n] += alpha[k] * M[k];
+    D[n] += alpha[k] * M[N + k];
   });
+  real hs = S[P], hd = D[P];
+  static_for<P>([&](auto nc) {
+    constexpr int n = P - decltype(nc)::value;  // P .. 1
+    constexpr real c1 = real(2 * n - 1) / real(n);
+    const real g = c1 * r2inv;
+    hs = S[n - 1] + g * hs;
+    hd = D[n - 1] + g * hd;
+  });
+  s += rinv * hs;
+  d += rinv * hd;
 }
 
 // Floating-point operations of one P2P pair as written in the kernel
@@ -186,23 +318,27 @@ inline double p2p_flop_per_pair(int ks) {
 
 // Floating-point operations of one (target, cell) Taylor evaluation, counted
 // from the recurrences above term by term (FMA = 2).
+// Both kernels in the degree-scaled form: set-up (d, r^2, rsqrt, 1/r^2 [, r,
+// exp], R^2 again, the per-degree factors), per coefficient the index sums,
+// the combination and the two contractions, then Horner over the degrees.
 inline double m2p_flop_one(int P, int kind) {
-  double f = kind == 0 ? 11.0 : 16.0;  // d, r^2, rsqrt, 1/r^2 [, r, exp]
+  double f = kind == 0 ? 11.0 + 5.0 + (P - 1) + 5.0 * P + 4.0
+                       : 16.0 + 5.0 + 6.0 + 4.0 * P + 5.0 * P + 4.0;
   for (int deg = 0; deg <= P; ++deg)
     for (int a = deg; a >= 0; --a)
       for (int b = deg - a; b >= 0; --b) {
         const int c = deg - a - b;
         if (deg == 0) {
-          f += 4.0 + (kind ? 1.0 : 0.0);
+          f += kind ? 2.0 : 0.0;
           continue;
         }
         const int nz1 = (a >= 1) + (b >= 1) + (c >= 1);
         const int nz2 = (a >= 2) + (b >= 2) + (c >= 2);
         const double s1 = 2.0 * nz1 - 1.0, s2 = nz2 > 0 ? nz2 - 1.0 : 0.0;
         if (kind == 0)
-          f += s1 + s2 + (nz2 ? 4.0 : 2.0) + 4.0;
+          f += s1 + s2 + (nz2 ? 2.0 : 0.0) + 4.0;
         else
-          f += 2.0 * (s1 + s2) + (nz2 ? 3.0 : 2.0) + (nz2 ? 7.0 : 5.0) + 4.0;
+          f += 2.0 * (s1 + s2) + (nz2 ? 6.0 : 2.0) + (deg < P ? (nz2 ? 2.0 : 0.0) : 0.0) + 4.0;
       }
   return f;
 }
