@@ -622,7 +622,9 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
       a.cells_list = wsp<int>(pl, pl.o_near);
       const int grid = nblocks(us.n, kWaves);
       prof_mark(pl, st, timed, 0, pl.launch_flop_p2p[phase][ks], true);
-      switch (ks) {
+      // no units (every cell seen through its expansion): the reduction
+      // below still stores the zero P2P sums
+      if (grid > 0) switch (ks) {
         case KS_L:
           hipLaunchKernelGGL((k_p2p<real, KS_L>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
           break;
