@@ -312,24 +312,47 @@ __global__ __launch_bounds__(kItemThreads) void k_m2p(UnitArgs a, const real* __
   const long long ti = t0 + min(lane, nt - 1);
   const real x = tx[ti], y = ty[ti], z = tz[ti];
   const real kap = (real)(slot == 0 ? b.kappa0 : b.kappa1);
-  // the cell's moments go through a per-wavefront LDS slice (broadcast reads)
-  __shared__ real smom[kWaves][2 * N];
-  real* M = smom[uni(threadIdx.x >> 6)];
-  real acc[4] = {0, 0, 0, 0};
-  for (int e = e0; e < e1; ++e) {
+  // The cell's moments go through a per-wavefront LDS slice (broadcast
+  // reads), double-buffered: the next cell's moments and centre are loaded
+  // into registers while the current cell is evaluated.
+  constexpr int PER = (2 * N + 63) / 64;
+  __shared__ real smom[kWaves][2][2 * N];
+  const int wv = uni(threadIdx.x >> 6);
+  real pre[PER];
+  double pcx = 0, pcy = 0, pcz = 0;
+  auto fetch = [&](int e) {
     const int c = uni(a.cells_list[e]);
     const Cell& cl = a.cells[c];
+    pcx = cl.cx;
+    pcy = cl.cy;
+    pcz = cl.cz;
     const real* Mg = mom + (size_t)c * 2 * N;
-    for (int k = lane; k < 2 * N; k += 64) M[k] = Mg[k];
-    wave_sync();
-    const real dx = x - (real)cl.cx, dy = y - (real)cl.cy, dz = z - (real)cl.cz;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = lane + 64 * q;
+      pre[q] = k < 2 * N ? Mg[k] : real(0);
+    }
+  };
+  real acc[4] = {0, 0, 0, 0};
+  if (e0 < e1) fetch(e0);
+  int buf = 0;
+  for (int e = e0; e < e1; ++e) {
+    real* M = smom[wv][buf];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = lane + 64 * q;
+      if (k < 2 * N) M[k] = pre[q];
+    }
+    const real dx = x - (real)pcx, dy = y - (real)pcy, dz = z - (real)pcz;
+    wave_sync();  // this buffer is written; the other one was last read a cell ago
+    if (e + 1 < e1) fetch(e + 1);
     const real r2 = dx * dx + dy * dy + dz * dz;
     const real rinv = rsqrt_(r2);
     if (KIND == 0)
       taylor_laplace<P, real>(dx, dy, dz, rinv, M, acc[0], acc[1]);
     else
       taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(kap * (r2 * rinv)), kap, M, acc[0], acc[1]);
-    wave_sync();
+    buf ^= 1;
   }
   unit_store<real, 2>(partial, u, acc);
 }
