@@ -201,6 +201,16 @@ __global__ void k_zero_ll(long long* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+__global__ void k_zero_i32(int* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_zero_f64(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 // --------------------------------------------------------------- per apply
 // mu weights of every kernel slot from the row weights lambda
 __global__ void k_adj_mu(const DevSlot* __restrict__ slots, const double* __restrict__ lam,
@@ -627,12 +637,6 @@ __global__ void k_pair_dots(const long long* __restrict__ tab, const double* __r
   }
 }
 
-__global__ void k_axpby(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
-                        int64_t n, double* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = a * x[i] + b * y[i];
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------- host side
@@ -641,8 +645,6 @@ namespace {
 struct AdjTables {
   std::vector<int> slot_block, slot_kidx, slot_ids[2], blist[2];
 };
-
-size_t adj_off(pbtc_plan& pl, size_t add) { return add; }
 
 }  // namespace
 
@@ -717,7 +719,7 @@ int adjoint_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
   long long* near_ptr = wsp<long long>(pl, pl.o_anear_ptr);
   long long* far_ptr = wsp<long long>(pl, pl.o_afar_ptr);
   int* flags = wsp<int>(pl, pl.o_flags);
-  PBTC_HIP(hipMemsetAsync(flags, 0, 4 * 16, st));
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, flags, (int64_t)16);
   hipLaunchKernelGGL(k_adj_lists, dim3(nblocks(pl.nitems_adj, kTravWaves)), dim3(64 * kTravWaves),
                      0, st, pl.nitems_adj, wsp<int>(pl, pl.o_aitems), wsp<DevBlock>(pl, pl.o_blocks),
                      wsp<Cell>(pl, pl.o_tcells), wsp<double>(pl, pl.o_gpgrp), pl.prm.theta, direct,
@@ -1005,7 +1007,9 @@ static int transpose_impl(pbtc_plan& pl, hipStream_t st, const double* lam, doub
   double* muD = wsp<double>(pl, pl.o_mu_d);
   const auto& slots = pl.slots[phase];
   if (slots.empty()) {
-    hipMemsetAsync(z, 0, 8 * pl.nunk, st);
+    hipLaunchKernelGGL(k_zero_f64, dim3(nblocks(pl.nunk, 256)), dim3(256), 0, st, z,
+                       (int64_t)pl.nunk);
+    PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
   {
@@ -1157,7 +1161,6 @@ int device_backward(pbtc_plan& pl, hipStream_t st, double gE, double* dq, double
     return rc;
   }
   const int T = 256;
-  const int64_t n = pl.nunk;
   const double C = 4.0 * kPi * kCoulomb;
   double* x = wsp<double>(pl, pl.o_x);
   double* lam = wsp<double>(pl, pl.o_lam);

@@ -270,7 +270,12 @@ struct pbtc_plan {
   void* ws = nullptr;
   void* inputs_ws = nullptr;  // workspace that already holds the uploaded inputs
   // profiling (params.profile): events around P2P (kind 0) and M2P (kind 1)
-  struct ProfEvent { int kind; double flop; hipEvent_t a, b; };
+  struct ProfEvent {
+    int kind = 0;
+    double flop = 0.0;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool recorded = false;  // both events recorded on the stream
+  };
   std::vector<ProfEvent> prof, prof_pool;
   // per kernel kind: 0 P2P, 1 Laplace M2P, 2 Yukawa M2P
   double prof_t[3] = {0, 0, 0}, prof_flop[3] = {0, 0, 0};

@@ -32,7 +32,6 @@ enum { SC_BNORM = 0, SC_RES, SC_ACTIVE, SC_BETA, SC_HN, SC_TOL, SC_KFIN, SC_REF,
 namespace {
 
 constexpr int kRedThreads = 256;
-constexpr int kRedBlocks = 512;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -572,16 +572,19 @@ static void prof_mark(pbtc_plan& pl, hipStream_t st, bool on, int kind, double f
     if (!pl.prof_pool.empty()) {
       ev = pl.prof_pool.back();
       pl.prof_pool.pop_back();
-    } else {
-      hipEventCreate(&ev.a);
-      hipEventCreate(&ev.b);
+    } else if (hipEventCreate(&ev.a) != hipSuccess) {
+      return;  // profiling is best effort: no event, no sample
+    } else if (hipEventCreate(&ev.b) != hipSuccess) {
+      (void)hipEventDestroy(ev.a);
+      return;
     }
     ev.kind = kind;
     ev.flop = flop;
-    hipEventRecord(ev.a, st);
+    ev.recorded = hipEventRecord(ev.a, st) == hipSuccess;
     pl.prof.push_back(ev);
-  } else {
-    hipEventRecord(pl.prof.back().b, st);
+  } else if (!pl.prof.empty()) {
+    pbtc_plan::ProfEvent& ev = pl.prof.back();
+    ev.recorded = ev.recorded && hipEventRecord(ev.b, st) == hipSuccess;
   }
 }
 
@@ -735,7 +738,7 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
 void prof_collect(pbtc_plan& pl) {
   for (auto& ev : pl.prof) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
+    if (ev.recorded && hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
       pl.prof_t[ev.kind] += 1e-3 * ms;
       pl.prof_n[ev.kind] += 1;
       pl.prof_flop[ev.kind] += ev.flop;

@@ -639,8 +639,6 @@ void compute_layout(pbtc_plan& pl) {
   pl.o_csc_ent = L.add(4 * pl.cap_nf);
   pl.o_csc_row = L.add(4 * pl.cap_nf);
   // transposed-operator trees and lists
-  int64_t nslot = 0;
-  for (const Block& b : pl.blocks) nslot += b.nk;
   pl.o_tcells = L.add(sizeof(Cell) * pl.cap_tcells);
   pl.o_tcnt = L.add(8 * (pl.cap_tcells + 1));
   pl.o_amom32 = L.add(4 * 2 * nP * pl.cap_tcells * pl.adj_ms);

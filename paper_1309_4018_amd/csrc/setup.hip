@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void k_cell_radius(Cell* __restrict__ cells, i
   red[threadIdx.x] = m;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
@@ -699,11 +699,6 @@ __global__ void k_coulomb_rows(int64_t n_unk, const DevCoulRow* __restrict__ row
 }
 
 __global__ void k_fill_int(int* p, int64_t n, int v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-__global__ void k_fill_f64(double* p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
