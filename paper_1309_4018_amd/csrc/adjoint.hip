@@ -476,21 +476,44 @@ __global__ __launch_bounds__(kT) void k_adj_m2p(AdjArgs a, const Src<real>* __re
   const Src<real> t = gpos[j0 + min(lane, nt - 1)];
   const real kap = (real)(kslot == 0 ? b.kappa0 : b.kappa1);
   const real* base = mom + (size_t)(b.lslot0 + kslot) * 2 * N;
-  __shared__ real smom[kWaves][2 * N];
-  real* M = smom[uni(threadIdx.x >> 6)];
-  real s = 0, f = 0;
-  for (int e = e0; e < e1; ++e) {
+  // double-buffered moment staging: the next cell's moments and centre are
+  // loaded into registers while the current cell is evaluated
+  constexpr int PER = (2 * N + 63) / 64;
+  __shared__ real smom[kWaves][2][2 * N];
+  const int wv = uni(threadIdx.x >> 6);
+  real pre[PER];
+  double pcx = 0, pcy = 0, pcz = 0;
+  auto fetch = [&](int e) {
     const int c = uni(a.cells_list[e]);
     const Cell& cl = a.cells[c];
+    pcx = cl.cx;
+    pcy = cl.cy;
+    pcz = cl.cz;
     const real* Mg = base + (size_t)c * ms * 2 * N;
-    for (int k = lane; k < 2 * N; k += 64) M[k] = Mg[k];
-    wave_sync();
-    const real dx = t.x - (real)cl.cx, dy = t.y - (real)cl.cy, dz = t.z - (real)cl.cz;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = lane + 64 * q;
+      pre[q] = k < 2 * N ? Mg[k] : real(0);
+    }
+  };
+  real s = 0, f = 0;
+  if (e0 < e1) fetch(e0);
+  int buf = 0;
+  for (int e = e0; e < e1; ++e) {
+    real* M = smom[wv][buf];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = lane + 64 * q;
+      if (k < 2 * N) M[k] = pre[q];
+    }
+    const real dx = t.x - (real)pcx, dy = t.y - (real)pcy, dz = t.z - (real)pcz;
+    wave_sync();  // this buffer is written; the other one was last read a cell ago
+    if (e + 1 < e1) fetch(e + 1);
     const real r2 = dx * dx + dy * dy + dz * dz;
     const real rinv = rsqrt_(r2);
     const real ee = KIND ? exp_neg(kap * (r2 * rinv)) : real(1);
     taylor_adj<P, real, KIND>(dx, dy, dz, rinv, ee, kap, t.px, t.py, t.pz, M, s, f);
-    wave_sync();
+    buf ^= 1;
   }
   partial[((size_t)u * 4 + 0) * 64 + lane] = s;
   partial[((size_t)u * 4 + 1) * 64 + lane] = f;
