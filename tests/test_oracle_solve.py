@@ -155,3 +155,26 @@ def test_ion_holding_cavity_concentric():
     assert abs(e[8] - exact) < abs(e[4] - exact) / 3.0
     assert abs(ext - exact) < 3e-3 * abs(exact)
     assert abs(ext - no_ions) > 3.0 * abs(ext - exact)
+
+
+@pytest.mark.parametrize("which", ["sphere", "three_region"])
+def test_apply_rows_equals_assembled_rows(which):
+    """Oracle.apply_rows (the matrix-free rows used at sizes too large to
+    assemble) against the same rows of the assembled matrix (Eq. matrix and
+    its multi-surface form): every surface, both row halves, random rows."""
+    if which == "sphere":
+        prob = synth.config1_kirkwood_sphere(nu=8)
+    else:
+        prob = synth.config3_multisurface(nu=4, cav_nu=2, n_charges=40)
+    o = Oracle(prob)
+    A = o.matrix()
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=o.n)
+    y = A @ x
+    for t, nt in enumerate(o.ns):
+        rows = rng.choice(nt, size=min(nt, 17), replace=False)
+        halves = o.apply_rows(x, t, rows)
+        assert len(halves) == 2
+        for half, yr in enumerate(halves):
+            ref = y[o.uoff[t] + half * nt + rows]
+            assert np.max(np.abs(yr - ref)) < 1e-13 * np.max(np.abs(y)), (t, half)
