@@ -31,11 +31,15 @@
  *   Host input arrays belong to the caller and are copied during the call.
  *   Output buffers are caller-allocated.  All device memory is ONE workspace
  *   that the caller allocates (any device allocation >= the size that
- *   pbtc_plan_create reports) and passes to every device call together with
- *   a hipStream_t (NULL = the default stream).  The library never calls
- *   hipMalloc/hipFree.  A workspace holds the plan's device state between
- *   calls (tree, lists, near-field tables, solution); passing a different
- *   workspace pointer makes the next call rebuild that state.
+ *   pbtc_plan reports) and passes to every device call together with a
+ *   hipStream_t (NULL = the default stream).  The library never calls
+ *   hipMalloc/hipFree.  A workspace holds the device state of ONE plan (or
+ *   of one batch, pbtc_solve_batch) between calls: tree, lists, near-field
+ *   tables, solution.  The library remembers which plan last set a workspace
+ *   up: a solve on a workspace that another plan (or batch) has used since,
+ *   or on a different workspace pointer, rebuilds the state first, and the
+ *   calls that need the state (pbtc_matvec, pbtc_backward, ...) return
+ *   PBTC_EINVAL instead of reading another plan's data.
  *
  * Errors
  *   Every int-returning function returns PBTC_OK (0) or a negative code.
@@ -68,6 +72,8 @@ extern "C" {
 #define PBTC_EWORKSPACE -4 /* workspace too small; pbtc_result.workspace_needed */
 #define PBTC_EDEVICE -5    /* HIP runtime error */
 #define PBTC_ENOCONV -6    /* GMRES hit max_iter; outputs hold the last iterate */
+#define PBTC_EHOST -7      /* host-side failure: out of host memory or another
+                              internal error (no exception leaves the library) */
 
 /* Arithmetic of the operator kernels (tree passes, P2P, M2P, near field). */
 #define PBTC_FP64 0         /* everything in FP64 */
@@ -87,7 +93,7 @@ extern "C" {
                                   phi and psi: self terms only */
 
 typedef struct pbtc_problem pbtc_problem;
-typedef struct pbtc_plan pbtc_plan;
+typedef struct pbtc_plan_s pbtc_plan_t;
 
 typedef struct {
   /* discretisation (sec. 3, parameter tables) */
@@ -193,13 +199,14 @@ int pbtc_validate(const pbtc_problem* p, const pbtc_params* prm);
 /* Validates, fixes the block structure (which surface pairs interact in
  * which region) and returns the workspace size for pbtc_setup/pbtc_solve.
  * The size includes an estimate for the interaction lists; pbtc_setup
- * returns EWORKSPACE with the exact need if the estimate was low. */
-int pbtc_plan_create(const pbtc_problem* p, const pbtc_params* prm, pbtc_plan** out,
-                     size_t* workspace_bytes);
-void pbtc_plan_destroy(pbtc_plan* plan);
+ * returns EWORKSPACE with the exact need if the estimate was low.  The
+ * problem is copied: later changes to it do not reach the plan. */
+int pbtc_plan(const pbtc_problem* p, const pbtc_params* prm, pbtc_plan_t** out,
+              size_t* workspace_bytes);
+void pbtc_plan_destroy(pbtc_plan_t* plan);
 
 /* Unknowns (2 * total panels), charges, surfaces and regions of a plan. */
-int pbtc_plan_sizes(const pbtc_plan* plan, int64_t* n_unknowns, int64_t* n_charges,
+int pbtc_plan_sizes(const pbtc_plan_t* plan, int64_t* n_unknowns, int64_t* n_charges,
                     int* n_surfaces, int* n_regions);
 
 /* Device set-up on the caller's workspace and stream, once per geometry
@@ -208,7 +215,7 @@ int pbtc_plan_sizes(const pbtc_plan* plan, int64_t* n_unknowns, int64_t* n_charg
  * and Gauss points, sorts them in Morton order, builds one octree per
  * surface, the interaction lists, the near-singular correction tables and
  * the Coulomb right-hand side.  Synchronises the stream.  res may be NULL. */
-int pbtc_setup(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream,
+int pbtc_setup(pbtc_plan_t* plan, void* d_workspace, size_t bytes, void* hip_stream,
                pbtc_result* res);
 
 /* Solves the BEM system by GMRES and evaluates the solvation energy.  Runs
@@ -216,27 +223,27 @@ int pbtc_setup(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_strea
  * rebuilds every device structure (geometry, Gauss points, tree, lists,
  * near field, right-hand side) from the inputs already in the workspace.
  * Returns ENOCONV (outputs valid) when max_iter is reached. */
-int pbtc_solve(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream,
+int pbtc_solve(pbtc_plan_t* plan, void* d_workspace, size_t bytes, void* hip_stream,
                int force_setup, pbtc_result* res);
 
 /* After pbtc_solve: phi (n_s) and d phi/dn on the inner side (n_s) of one
  * surface in its triangle order (host buffers). */
-int pbtc_get_surface(const pbtc_plan* plan, int surface_id, double* phi, double* dphidn_inner);
+int pbtc_get_surface(const pbtc_plan_t* plan, int surface_id, double* phi, double* dphidn_inner);
 /* Reaction potential at every charge (regions in id order, charges in the
  * order given), host buffer of n_charges. */
-int pbtc_get_phi_reac(const pbtc_plan* plan, double* phi_reac);
+int pbtc_get_phi_reac(const pbtc_plan_t* plan, double* phi_reac);
 /* GMRES implicit relative residual per iteration (host buffer). */
-int pbtc_get_history(const pbtc_plan* plan, double* rel_res, int cap, int* n_iter);
+int pbtc_get_history(const pbtc_plan_t* plan, double* rel_res, int cap, int* n_iter);
 
 /* y = A x with the plan's operator (sec. 2.2 Eq. matrix and its
  * multi-surface form), x and y DEVICE pointers to n_unknowns FP64 values,
  * evaluated in `precision` (PBTC_FP64 or PBTC_FP32) with the plan's op.
  * Requires pbtc_setup on the same workspace.  Does not synchronise. */
-int pbtc_matvec(pbtc_plan* plan, void* d_workspace, void* hip_stream, const double* d_x,
+int pbtc_matvec(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, const double* d_x,
                 double* d_y, int precision);
 /* y = A^T x (exact transpose of the same discrete operator).  Device
  * pointers as for pbtc_matvec. */
-int pbtc_matvec_transpose(pbtc_plan* plan, void* d_workspace, void* hip_stream,
+int pbtc_matvec_transpose(pbtc_plan_t* plan, void* d_workspace, void* hip_stream,
                           const double* d_x, double* d_y, int precision);
 /* y = M^-1 x (transpose = 0) or y = M^-T x (transpose = 1) for the
  * block-diagonal preconditioner M of PBTC_PREC_BLOCK_DIAG, whatever
@@ -249,7 +256,7 @@ int pbtc_matvec_transpose(pbtc_plan* plan, void* d_workspace, void* hip_stream,
  * layout (both are the pbtc_matvec layout).  x, y: distinct DEVICE buffers of
  * n_unknowns FP64 values; requires pbtc_setup on the workspace; does not
  * synchronise.  EINVAL for NULL or aliased buffers. */
-int pbtc_precond_apply(pbtc_plan* plan, void* d_workspace, void* hip_stream, const double* d_x,
+int pbtc_precond_apply(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, const double* d_x,
                        double* d_y, int transpose);
 /* Coulomb energy of the point charges (Eq. total_energy: the total energy
  * of a species is its solvation energy plus this term; Eq. bind_energy
@@ -261,11 +268,11 @@ int pbtc_precond_apply(pbtc_plan* plan, void* d_workspace, void* hip_stream, con
  * each independent system's share.  Requires pbtc_setup on the workspace;
  * synchronises the stream.  EINVAL for NULL total or when two charges of one
  * region coincide (non-finite energy). */
-int pbtc_coulomb_energy(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* total,
+int pbtc_coulomb_energy(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, double* total,
                         double* per_system);
 /* The Coulomb right-hand side b (Eq. matel Q) into a device buffer of
  * n_unknowns FP64 values. */
-int pbtc_rhs(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* d_b);
+int pbtc_rhs(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, double* d_b);
 
 /* Gradients of the solvation energy by the adjoint method: solves
  * A^T lambda = S^T q (S: unknowns -> reaction potential at the charges)
@@ -276,7 +283,7 @@ int pbtc_rhs(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* d_b);
  * C = 4 pi k_e.  Requires a converged pbtc_solve on the same workspace.
  * Host outputs: dE_dq (n_charges), dE_dkappa and dE_deps (n_regions); any
  * may be NULL.  The energy is scaled by gE (dL/dE of a caller's loss). */
-int pbtc_backward(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream,
+int pbtc_backward(pbtc_plan_t* plan, void* d_workspace, size_t bytes, void* hip_stream,
                   double gE, double* dE_dq, double* dE_dkappa, double* dE_deps,
                   pbtc_result* res);
 
@@ -289,13 +296,38 @@ int pbtc_backward(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_st
  * is solved as one system).  After pbtc_solve: n_systems, and per system
  * (host buffers of n_systems, any may be NULL) the solvation energy, the
  * explicit FP64 relative residual, and the first unknown / charge index. */
-int pbtc_get_systems(const pbtc_plan* plan, int* n_systems, double* energy_kJmol,
+int pbtc_get_systems(const pbtc_plan_t* plan, int* n_systems, double* energy_kJmol,
                      double* rel_res, int64_t* first_unknown);
+
+/* Solves n plans (sec. 2.1-2.2 problem statement, one per molecule) as one
+ * batch on one workspace: every GMRES iteration of all their systems shares
+ * each kernel launch (an uneven batch of molecules), while every system keeps
+ * its own Krylov space, Givens rotations and convergence test, so the
+ * results equal those of n separate pbtc_solve calls up to rounding.
+ *   plans: n >= 1 distinct plans made with identical pbtc_params (EINVAL
+ *     otherwise); the library merges their problems (regions, surfaces and
+ *     charges in plan order) into one internal plan that it keeps with
+ *     plans[0] and reuses while the same plans are passed in the same order
+ *     (charge values set with pbtc_set_charge_values are carried over).
+ *   d_workspace, bytes: one device workspace for the whole batch.  When it is
+ *     smaller than the batch needs (bytes = 0 asks), the call returns
+ *     EWORKSPACE with the size in res[0].workspace_needed and does no work.
+ *   res: host array of n results: energy_kJmol, converged and final_rel_res
+ *     are per plan; n_iter, matvec counts, timings and interaction counts
+ *     are the batch's.
+ * Afterwards pbtc_get_surface, pbtc_get_phi_reac, pbtc_get_history (the
+ * batch's history: per iteration the largest implicit residual over its
+ * systems) and pbtc_get_systems answer per plan.  The batch state lives in
+ * the batch workspace, so pbtc_backward on a member needs pbtc_solve on
+ * the member's own workspace first.  Returns ENOCONV if any system missed
+ * the tolerance (every plan's outputs are still filled). */
+int pbtc_solve_batch(pbtc_plan_t** plans, int n, void* d_workspace, size_t bytes,
+                     void* hip_stream, pbtc_result* res);
 
 /* Replaces the values (not the positions) of every charge of a plan, in the
  * order of pbtc_get_phi_reac (nq values, host).  The next pbtc_solve reuses
  * the device set-up and only rebuilds the right-hand side. */
-int pbtc_set_charge_values(pbtc_plan* plan, const double* q);
+int pbtc_set_charge_values(pbtc_plan_t* plan, const double* q);
 
 /* Host-side tables used by the library (no device work), for checking:
  * barycentric points (K x 3) and weights (K) of the K-point triangle rule;
@@ -305,7 +337,7 @@ int pbtc_gauss_legendre(int n, double* nodes, double* weights);
 
 /* Message of the last error of `plan` (or of the calling thread when plan
  * is NULL).  The pointer stays valid until the next call on that plan. */
-const char* pbtc_last_error(const pbtc_plan* plan);
+const char* pbtc_last_error(const pbtc_plan_t* plan);
 
 #ifdef __cplusplus
 }

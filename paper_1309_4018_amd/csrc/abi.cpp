@@ -1,9 +1,14 @@
 // C interface of libpbtc (see include/pbtc.h for the contract).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <memory>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 
 #include "internal.h"
 
@@ -11,21 +16,32 @@ namespace pbtc {
 bool triangle_rule(int k, double* bary, double* w);
 bool gauss_legendre(int n, double* x, double* w);
 std::string validate_problem(const pbtc_problem& p, const pbtc_params& prm, int* code);
-int build_plan(pbtc_plan& pl);
-void compute_layout(pbtc_plan& pl);
-int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry);
-int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res);
-int update_charges(pbtc_plan& pl, hipStream_t st);
-int device_backward(pbtc_plan& pl, hipStream_t st, double gE, double* dq, double* dk, double* de,
+int build_plan(pbtc_plan_t& pl);
+void compute_layout(pbtc_plan_t& pl);
+int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry);
+int device_solve(pbtc_plan_t& pl, hipStream_t st, pbtc_result* res);
+int update_charges(pbtc_plan_t& pl, hipStream_t st);
+int device_backward(pbtc_plan_t& pl, hipStream_t st, double gE, double* dq, double* dk, double* de,
                     pbtc_result* res);
-int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+int apply_operator(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int precision,
                    int phase);
-int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+int apply_transpose(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int precision,
                     int phase);
-int apply_precond(pbtc_plan& pl, hipStream_t st, const double* x, double* y, bool transpose,
+int apply_precond(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, bool transpose,
                   bool accumulate);
 double wall_seconds();
-int device_coulomb(pbtc_plan& pl, hipStream_t st, double* total, double* per_system);
+int device_coulomb(pbtc_plan_t& pl, hipStream_t st, double* total, double* per_system);
+
+// The merged problem of a pbtc_solve_batch call and where each member's
+// regions, systems, unknowns and charges sit in it.
+struct BatchCache {
+  std::vector<uint64_t> serials;  // members, in call order
+  std::vector<uint64_t> charge_versions;
+  pbtc_plan_t* merged = nullptr;
+  std::vector<int> reg0, comp0;   // first region / system of every member (+ end)
+  std::vector<int64_t> unk0, q0;  // first unknown / charge of every member (+ end)
+  ~BatchCache() { delete merged; }
+};
 }  // namespace pbtc
 
 using namespace pbtc;
@@ -33,15 +49,70 @@ using namespace pbtc;
 namespace {
 
 thread_local std::string g_err;
+std::atomic<uint64_t> g_serial{1};
+
+// Which plan last set up each workspace (a workspace holds the device state
+// of one plan at a time).
+std::mutex g_ws_mu;
+std::unordered_map<const void*, uint64_t> g_ws_owner;
+
+void claim_ws(const void* ws, const pbtc_plan_t* pl) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  g_ws_owner[ws] = pl->serial;
+}
+
+bool owns_ws(const void* ws, const pbtc_plan_t* pl) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  const auto it = g_ws_owner.find(ws);
+  return it != g_ws_owner.end() && it->second == pl->serial;
+}
+
+void release_ws(const pbtc_plan_t* pl) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (auto it = g_ws_owner.begin(); it != g_ws_owner.end();)
+    it = it->second == pl->serial ? g_ws_owner.erase(it) : std::next(it);
+}
+
+// True when `ws` holds this plan's set-up device state.
+bool ready(const pbtc_plan_t* pl, const void* ws) {
+  return pl->setup_done && pl->ws == ws && owns_ws(ws, pl);
+}
 
 int fail_global(int code, const char* msg) {
-  g_err = msg;
+  try {
+    g_err = msg;
+  } catch (...) {
+  }
   return code;
 }
 
-int fail_plan(pbtc_plan* pl, int code, const std::string& msg) {
-  pl->err = msg;
+int fail_plan(pbtc_plan_t* pl, int code, const std::string& msg) {
+  try {
+    pl->err = msg;
+  } catch (...) {
+  }
   return code;
+}
+
+// Runs the body of an entry point: a C++ exception (std::bad_alloc from a
+// host table, ...) becomes PBTC_EHOST with a message instead of crossing the
+// C interface.  `pl` receives the message (NULL: the thread's last error).
+template <typename F>
+int guarded(pbtc_plan_t* pl, F&& body) noexcept {
+  const char* msg = "internal error";
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    msg = "out of host memory";
+  } catch (const std::exception& e) {
+    try {
+      const std::string m = std::string("internal error: ") + e.what();
+      return pl ? fail_plan(pl, PBTC_EHOST, m) : fail_global(PBTC_EHOST, m.c_str());
+    } catch (...) {
+    }
+  } catch (...) {
+  }
+  return pl ? fail_plan(pl, PBTC_EHOST, msg) : fail_global(PBTC_EHOST, msg);
 }
 
 bool finite_all(const double* p, int64_t n) {
@@ -50,7 +121,7 @@ bool finite_all(const double* p, int64_t n) {
   return true;
 }
 
-void fill_sizes(const pbtc_plan* pl, pbtc_result* res) {
+void fill_sizes(const pbtc_plan_t* pl, pbtc_result* res) {
   if (!res) return;
   res->n_p2p_pairs = pl->p2p_pairs;
   res->n_m2p_evals = pl->m2p_evals;
@@ -60,11 +131,15 @@ void fill_sizes(const pbtc_plan* pl, pbtc_result* res) {
 }
 
 // Set-up on a workspace, growing capacity estimates as needed.
-int setup_impl(pbtc_plan* pl, void* ws, size_t bytes, hipStream_t st, pbtc_result* res,
+int setup_impl(pbtc_plan_t* pl, void* ws, size_t bytes, hipStream_t st, pbtc_result* res,
                bool reuse_inputs = false) {
+  const bool same = pl->ws == ws && owns_ws(ws, pl);
   pl->setup_done = false;
   pl->solved = false;
-  if (!reuse_inputs || pl->inputs_ws != ws) pl->inputs_ws = nullptr;
+  pl->dev_solved = false;
+  // another plan (or another workspace) held this memory: nothing in it is ours
+  if (!reuse_inputs || pl->inputs_ws != ws || !same) pl->inputs_ws = nullptr;
+  if (!same) pl->adj_done = false;
   for (int attempt = 0; attempt < 4; ++attempt) {
     if (bytes < pl->ws_bytes) {
       if (res) res->workspace_needed = pl->ws_bytes;
@@ -73,12 +148,14 @@ int setup_impl(pbtc_plan* pl, void* ws, size_t bytes, hipStream_t st, pbtc_resul
                            std::to_string(pl->ws_bytes) + " bytes this plan needs");
     }
     pl->ws = ws;
+    claim_ws(ws, pl);
     const double t0 = wall_seconds();
     int retry = 0;
     const int rc = device_setup(*pl, st, &retry);
     if (rc == PBTC_EWORKSPACE && retry) {
       compute_layout(*pl);
       pl->inputs_ws = nullptr;
+      pl->adj_done = false;
       continue;
     }
     if (rc) return rc;
@@ -94,6 +171,111 @@ int setup_impl(pbtc_plan* pl, void* ws, size_t bytes, hipStream_t st, pbtc_resul
   return fail_plan(pl, PBTC_EWORKSPACE, "workspace estimate did not converge");
 }
 
+// Plan of a problem: validation, block structure, layout.
+int make_plan(const pbtc_problem& p, const pbtc_params& prm, pbtc_plan_t** out) {
+  *out = nullptr;
+  int code = PBTC_OK;
+  std::string msg = validate_problem(p, prm, &code);
+  if (code) return fail_global(code, msg.c_str());
+  std::unique_ptr<pbtc_plan_t> pl(new pbtc_plan_t());
+  pl->serial = g_serial.fetch_add(1);
+  pl->prob = p;
+  pl->prm = prm;
+  const int rc = build_plan(*pl);
+  if (rc) return fail_global(rc, "problem too large for 32-bit indices");
+  *out = pl.release();
+  return PBTC_OK;
+}
+
+// Solve on a workspace: set-up when needed, charges, GMRES, energy.
+int solve_impl(pbtc_plan_t* plan, void* ws, size_t bytes, hipStream_t st, bool force_setup,
+               pbtc_result* res) {
+  if (force_setup || !ready(plan, ws)) {
+    const int rc = setup_impl(plan, ws, bytes, st, res, force_setup);
+    if (rc) return rc;
+  } else if (bytes < plan->ws_bytes) {
+    res->workspace_needed = plan->ws_bytes;
+    return fail_plan(plan, PBTC_EWORKSPACE, "workspace smaller than the plan needs");
+  }
+  fill_sizes(plan, res);
+  if (plan->charges_dirty) {
+    const int rc = update_charges(*plan, st);
+    if (rc) return rc;
+  }
+  return device_solve(*plan, st, res);
+}
+
+bool same_params(const pbtc_params& a, const pbtc_params& b) {
+  return a.K == b.K && a.K_fine == b.K_fine && a.N_k == b.N_k && a.thres == b.thres &&
+         a.theta == b.theta && a.P == b.P && a.ncrit == b.ncrit &&
+         a.direct_below == b.direct_below && a.tol == b.tol && a.restart == b.restart &&
+         a.max_iter == b.max_iter && a.precision == b.precision && a.op == b.op &&
+         a.inner_tol == b.inner_tol && a.max_refine == b.max_refine &&
+         a.validate_charges == b.validate_charges && a.profile == b.profile &&
+         a.precond == b.precond;
+}
+
+// The merged plan of a batch (kept with plans[0] while the members stay the
+// same), with the members' current charge values.
+int batch_plan(pbtc_plan_t** plans, int n, BatchCache** out) {
+  pbtc_plan_t* head = plans[0];
+  BatchCache* bc = head->batch;
+  bool hit = bc && (int)bc->serials.size() == n;
+  for (int i = 0; hit && i < n; ++i) hit = bc->serials[i] == plans[i]->serial;
+  if (!hit) {
+    delete bc;
+    head->batch = nullptr;
+    std::unique_ptr<BatchCache> fresh(new BatchCache());
+    pbtc_problem merged;
+    fresh->reg0.push_back(0);
+    fresh->comp0.push_back(0);
+    fresh->unk0.push_back(0);
+    fresh->q0.push_back(0);
+    int ncomp = 0;
+    for (int i = 0; i < n; ++i) {
+      const pbtc_problem& P = plans[i]->prob;
+      const int r0 = (int)merged.regions.size();
+      for (size_t r = 0; r < P.regions.size(); ++r) {
+        merged.regions.push_back(P.regions[r]);
+        merged.charges.push_back(P.charges[r]);
+      }
+      for (const Surface& s : P.surfaces) {
+        Surface c = s;
+        c.inner += r0;
+        c.outer += r0;
+        merged.surfaces.push_back(std::move(c));
+      }
+      ncomp += plans[i]->ncomp;
+      fresh->serials.push_back(plans[i]->serial);
+      fresh->charge_versions.push_back(plans[i]->charge_version);
+      fresh->reg0.push_back((int)merged.regions.size());
+      fresh->comp0.push_back(ncomp);
+      fresh->unk0.push_back(fresh->unk0.back() + plans[i]->nunk);
+      fresh->q0.push_back(fresh->q0.back() + plans[i]->nq);
+    }
+    const int rc = make_plan(merged, head->prm, &fresh->merged);
+    if (rc) return fail_plan(head, rc, std::string("batch: ") + g_err);
+    if (fresh->merged->ncomp != ncomp)
+      return fail_plan(head, PBTC_EINVAL,
+                       "batch: a plan's systems are not contiguous in its surface order");
+    bc = fresh.release();
+    head->batch = bc;
+  }
+  // charge values changed since the merged plan copied them
+  for (int i = 0; i < n; ++i) {
+    if (bc->charge_versions[i] == plans[i]->charge_version) continue;
+    const pbtc_problem& P = plans[i]->prob;
+    for (size_t r = 0; r < P.regions.size(); ++r)
+      bc->merged->prob.charges[bc->reg0[i] + r].q = P.charges[r].q;
+    bc->merged->charges_dirty = true;
+    bc->merged->solved = false;
+    bc->merged->dev_solved = false;
+    bc->charge_versions[i] = plans[i]->charge_version;
+  }
+  *out = bc;
+  return PBTC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -105,61 +287,71 @@ int pbtc_version(int* major, int* minor) {
 }
 
 int pbtc_problem_create(pbtc_problem** out) {
-  if (!out) return fail_global(PBTC_EINVAL, "out is NULL");
-  *out = new (std::nothrow) pbtc_problem();
-  if (!*out) return fail_global(PBTC_EINVAL, "out of host memory");
-  return PBTC_OK;
+  return guarded(nullptr, [&] {
+    if (!out) return fail_global(PBTC_EINVAL, "out is NULL");
+    *out = new pbtc_problem();
+    return PBTC_OK;
+  });
 }
 
 void pbtc_problem_destroy(pbtc_problem* p) { delete p; }
 
 int pbtc_add_region(pbtc_problem* p, double eps, double kappa, int* region_id) {
-  if (!p) return fail_global(PBTC_EINVAL, "problem is NULL");
-  if (!(eps > 0.0) || !std::isfinite(eps) || !(kappa >= 0.0) || !std::isfinite(kappa))
-    return fail_global(PBTC_EINVAL, "eps must be > 0 and kappa >= 0, both finite");
-  Region r;
-  r.eps = eps;
-  r.kappa = kappa;
-  p->regions.push_back(r);
-  p->charges.emplace_back();
-  if (region_id) *region_id = (int)p->regions.size() - 1;
-  return PBTC_OK;
+  return guarded(nullptr, [&] {
+    if (!p) return fail_global(PBTC_EINVAL, "problem is NULL");
+    if (!(eps > 0.0) || !std::isfinite(eps) || !(kappa >= 0.0) || !std::isfinite(kappa))
+      return fail_global(PBTC_EINVAL, "eps must be > 0 and kappa >= 0, both finite");
+    Region r;
+    r.eps = eps;
+    r.kappa = kappa;
+    p->regions.push_back(r);
+    p->charges.emplace_back();
+    if (region_id) *region_id = (int)p->regions.size() - 1;
+    return PBTC_OK;
+  });
 }
 
 int pbtc_add_surface(pbtc_problem* p, const double* verts, int64_t nv, const int32_t* tris,
                      int64_t np, int inner_region, int outer_region, int* surface_id) {
-  if (!p) return fail_global(PBTC_EINVAL, "problem is NULL");
-  const int nreg = (int)p->regions.size();
-  if (inner_region < 0 || inner_region >= nreg || outer_region < 0 || outer_region >= nreg)
-    return fail_global(PBTC_EINVAL, "unknown region id");
-  if (inner_region == outer_region) return fail_global(PBTC_EINVAL, "inner and outer region are equal");
-  if (nv < 3 || np < 4 || !verts || !tris)
-    return fail_global(PBTC_EINVAL, "a closed surface needs >= 3 vertices and >= 4 triangles");
-  if (np >= (int64_t(1) << 30) || nv >= (int64_t(1) << 31)) return fail_global(PBTC_EINVAL, "surface too large");
-  for (int64_t i = 0; i < 3 * np; ++i)
-    if (tris[i] < 0 || tris[i] >= nv) return fail_global(PBTC_EINVAL, "triangle index out of range");
-  if (!finite_all(verts, 3 * nv)) return fail_global(PBTC_EINVAL, "vertex coordinate not finite");
-  Surface s;
-  s.v.assign(verts, verts + 3 * nv);
-  s.t.assign(tris, tris + 3 * np);
-  s.inner = inner_region;
-  s.outer = outer_region;
-  p->surfaces.push_back(std::move(s));
-  if (surface_id) *surface_id = (int)p->surfaces.size() - 1;
-  return PBTC_OK;
+  return guarded(nullptr, [&] {
+    if (!p) return fail_global(PBTC_EINVAL, "problem is NULL");
+    const int nreg = (int)p->regions.size();
+    if (inner_region < 0 || inner_region >= nreg || outer_region < 0 || outer_region >= nreg)
+      return fail_global(PBTC_EINVAL, "unknown region id");
+    if (inner_region == outer_region)
+      return fail_global(PBTC_EINVAL, "inner and outer region are equal");
+    if (nv < 3 || np < 4 || !verts || !tris)
+      return fail_global(PBTC_EINVAL, "a closed surface needs >= 3 vertices and >= 4 triangles");
+    if (np >= (int64_t(1) << 30) || nv >= (int64_t(1) << 31))
+      return fail_global(PBTC_EINVAL, "surface too large");
+    for (int64_t i = 0; i < 3 * np; ++i)
+      if (tris[i] < 0 || tris[i] >= nv)
+        return fail_global(PBTC_EINVAL, "triangle index out of range");
+    if (!finite_all(verts, 3 * nv)) return fail_global(PBTC_EINVAL, "vertex coordinate not finite");
+    Surface s;
+    s.v.assign(verts, verts + 3 * nv);
+    s.t.assign(tris, tris + 3 * np);
+    s.inner = inner_region;
+    s.outer = outer_region;
+    p->surfaces.push_back(std::move(s));
+    if (surface_id) *surface_id = (int)p->surfaces.size() - 1;
+    return PBTC_OK;
+  });
 }
 
 int pbtc_set_charges(pbtc_problem* p, int region_id, const double* xyz, const double* q, int64_t nq) {
-  if (!p) return fail_global(PBTC_EINVAL, "problem is NULL");
-  if (region_id < 0 || region_id >= (int)p->regions.size())
-    return fail_global(PBTC_EINVAL, "unknown region id");
-  if (nq < 0 || (nq > 0 && (!xyz || !q))) return fail_global(PBTC_EINVAL, "bad charge arrays");
-  if (!finite_all(xyz, 3 * nq) || !finite_all(q, nq))
-    return fail_global(PBTC_EINVAL, "charge position or value not finite");
-  ChargeSet& c = p->charges[region_id];
-  c.xyz.assign(xyz, xyz + 3 * nq);
-  c.q.assign(q, q + nq);
-  return PBTC_OK;
+  return guarded(nullptr, [&] {
+    if (!p) return fail_global(PBTC_EINVAL, "problem is NULL");
+    if (region_id < 0 || region_id >= (int)p->regions.size())
+      return fail_global(PBTC_EINVAL, "unknown region id");
+    if (nq < 0 || (nq > 0 && (!xyz || !q))) return fail_global(PBTC_EINVAL, "bad charge arrays");
+    if (!finite_all(xyz, 3 * nq) || !finite_all(q, nq))
+      return fail_global(PBTC_EINVAL, "charge position or value not finite");
+    ChargeSet& c = p->charges[region_id];
+    c.xyz.assign(xyz, xyz + 3 * nq);
+    c.q.assign(q, q + nq);
+    return PBTC_OK;
+  });
 }
 
 int pbtc_params_default(pbtc_params* prm) {
@@ -186,35 +378,27 @@ int pbtc_params_default(pbtc_params* prm) {
 }
 
 int pbtc_validate(const pbtc_problem* p, const pbtc_params* prm) {
-  if (!p || !prm) return fail_global(PBTC_EINVAL, "problem or params is NULL");
-  int code = PBTC_OK;
-  std::string msg = validate_problem(*p, *prm, &code);
-  if (code) return fail_global(code, msg.c_str());
-  return PBTC_OK;
+  return guarded(nullptr, [&] {
+    if (!p || !prm) return fail_global(PBTC_EINVAL, "problem or params is NULL");
+    int code = PBTC_OK;
+    std::string msg = validate_problem(*p, *prm, &code);
+    if (code) return fail_global(code, msg.c_str());
+    return PBTC_OK;
+  });
 }
 
-int pbtc_plan_create(const pbtc_problem* p, const pbtc_params* prm, pbtc_plan** out,
-                     size_t* workspace_bytes) {
-  if (!p || !prm || !out) return fail_global(PBTC_EINVAL, "NULL argument");
-  *out = nullptr;
-  int code = PBTC_OK;
-  std::string msg = validate_problem(*p, *prm, &code);
-  if (code) return fail_global(code, msg.c_str());
-  pbtc_plan* pl = new (std::nothrow) pbtc_plan();
-  if (!pl) return fail_global(PBTC_EINVAL, "out of host memory");
-  pl->prob = *p;
-  pl->prm = *prm;
-  const int rc = build_plan(*pl);
-  if (rc) {
-    delete pl;
-    return fail_global(rc, "problem too large for 32-bit indices");
-  }
-  *out = pl;
-  if (workspace_bytes) *workspace_bytes = pl->ws_bytes;
-  return PBTC_OK;
+int pbtc_plan(const pbtc_problem* p, const pbtc_params* prm, pbtc_plan_t** out,
+              size_t* workspace_bytes) {
+  return guarded(nullptr, [&] {
+    if (!p || !prm || !out) return fail_global(PBTC_EINVAL, "NULL argument");
+    const int rc = make_plan(*p, *prm, out);
+    if (rc) return rc;
+    if (workspace_bytes) *workspace_bytes = (*out)->ws_bytes;
+    return PBTC_OK;
+  });
 }
 
-pbtc_plan::~pbtc_plan() {
+pbtc_plan_s::~pbtc_plan_s() {
   for (auto* v : {&prof, &prof_pool})
     for (auto& ev : *v) {
       (void)hipEventDestroy(ev.a);
@@ -226,11 +410,17 @@ pbtc_plan::~pbtc_plan() {
     if (e) (void)hipEventDestroy(e);
   if (side) (void)hipStreamDestroy(side);
   if (res_pin) (void)hipHostFree(res_pin);
+  delete batch;
 }
 
-void pbtc_plan_destroy(pbtc_plan* plan) { delete plan; }
+void pbtc_plan_destroy(pbtc_plan_t* plan) {
+  if (!plan) return;
+  release_ws(plan);
+  if (plan->batch && plan->batch->merged) release_ws(plan->batch->merged);
+  delete plan;
+}
 
-int pbtc_plan_sizes(const pbtc_plan* plan, int64_t* n_unknowns, int64_t* n_charges,
+int pbtc_plan_sizes(const pbtc_plan_t* plan, int64_t* n_unknowns, int64_t* n_charges,
                     int* n_surfaces, int* n_regions) {
   if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
   if (n_unknowns) *n_unknowns = plan->nunk;
@@ -240,37 +430,95 @@ int pbtc_plan_sizes(const pbtc_plan* plan, int64_t* n_unknowns, int64_t* n_charg
   return PBTC_OK;
 }
 
-int pbtc_setup(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream, pbtc_result* res) {
-  if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
-  if (!d_workspace) return fail_plan(plan, PBTC_EINVAL, "workspace is NULL");
-  if (res) std::memset(res, 0, sizeof(*res));
-  return setup_impl(plan, d_workspace, bytes, (hipStream_t)hip_stream, res);
-}
-
-int pbtc_solve(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream, int force_setup,
+int pbtc_setup(pbtc_plan_t* plan, void* d_workspace, size_t bytes, void* hip_stream,
                pbtc_result* res) {
   if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
-  if (!d_workspace) return fail_plan(plan, PBTC_EINVAL, "workspace is NULL");
-  pbtc_result local;
-  if (!res) res = &local;
-  std::memset(res, 0, sizeof(*res));
-  hipStream_t st = (hipStream_t)hip_stream;
-  if (force_setup || !plan->setup_done || plan->ws != d_workspace) {
-    const int rc = setup_impl(plan, d_workspace, bytes, st, res, force_setup != 0);
-    if (rc) return rc;
-  } else if (bytes < plan->ws_bytes) {
-    res->workspace_needed = plan->ws_bytes;
-    return fail_plan(plan, PBTC_EWORKSPACE, "workspace smaller than the plan needs");
-  }
-  fill_sizes(plan, res);
-  if (plan->charges_dirty) {
-    const int rc = update_charges(*plan, st);
-    if (rc) return rc;
-  }
-  return device_solve(*plan, st, res);
+  return guarded(plan, [&] {
+    if (!d_workspace) return fail_plan(plan, PBTC_EINVAL, "workspace is NULL");
+    if (res) std::memset(res, 0, sizeof(*res));
+    return setup_impl(plan, d_workspace, bytes, (hipStream_t)hip_stream, res);
+  });
 }
 
-int pbtc_get_surface(const pbtc_plan* plan, int surface_id, double* phi, double* dphidn_inner) {
+int pbtc_solve(pbtc_plan_t* plan, void* d_workspace, size_t bytes, void* hip_stream,
+               int force_setup, pbtc_result* res) {
+  if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
+  return guarded(plan, [&] {
+    if (!d_workspace) return fail_plan(plan, PBTC_EINVAL, "workspace is NULL");
+    pbtc_result local;
+    pbtc_result* r = res ? res : &local;
+    std::memset(r, 0, sizeof(*r));
+    return solve_impl(plan, d_workspace, bytes, (hipStream_t)hip_stream, force_setup != 0, r);
+  });
+}
+
+int pbtc_solve_batch(pbtc_plan_t** plans, int n, void* d_workspace, size_t bytes,
+                     void* hip_stream, pbtc_result* res) {
+  if (!plans || n < 1) return fail_global(PBTC_EINVAL, "plans is NULL or n < 1");
+  for (int i = 0; i < n; ++i)
+    if (!plans[i]) return fail_global(PBTC_EINVAL, "a plan is NULL");
+  pbtc_plan_t* head = plans[0];
+  return guarded(head, [&] {
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < i; ++j)
+        if (plans[j] == plans[i]) return fail_plan(head, PBTC_EINVAL, "batch: a plan appears twice");
+      if (!same_params(plans[i]->prm, head->prm))
+        return fail_plan(head, PBTC_EINVAL, "batch: the plans' parameters differ");
+    }
+    if (res) std::memset(res, 0, sizeof(pbtc_result) * (size_t)n);
+    BatchCache* bc = nullptr;
+    int rc = batch_plan(plans, n, &bc);
+    if (rc) return rc;
+    pbtc_plan_t* m = bc->merged;
+    if (bytes < m->ws_bytes) {
+      if (res)
+        for (int i = 0; i < n; ++i) res[i].workspace_needed = m->ws_bytes;
+      return fail_plan(head, PBTC_EWORKSPACE,
+                       "batch workspace of " + std::to_string(bytes) + " bytes; the batch needs " +
+                           std::to_string(m->ws_bytes));
+    }
+    if (!d_workspace) return fail_plan(head, PBTC_EINVAL, "workspace is NULL");
+    pbtc_result all;
+    std::memset(&all, 0, sizeof(all));
+    rc = solve_impl(m, d_workspace, bytes, (hipStream_t)hip_stream, false, &all);
+    if (rc == PBTC_EWORKSPACE && res)
+      for (int i = 0; i < n; ++i) res[i].workspace_needed = all.workspace_needed;
+    if (rc && rc != PBTC_ENOCONV) return fail_plan(head, rc, "batch: " + m->err);
+    // scatter the merged solution to the members
+    for (int i = 0; i < n; ++i) {
+      pbtc_plan_t* p = plans[i];
+      const int64_t u0 = bc->unk0[i], u1 = bc->unk0[i + 1], q0 = bc->q0[i], q1 = bc->q0[i + 1];
+      p->x_host.assign(m->x_host.begin() + u0, m->x_host.begin() + u1);
+      p->phi_reac_host.assign(m->phi_reac_host.begin() + q0, m->phi_reac_host.begin() + q1);
+      p->history = m->history;
+      const int c0 = bc->comp0[i], c1 = bc->comp0[i + 1];
+      p->comp_energy.assign(m->comp_energy.begin() + c0, m->comp_energy.begin() + c1);
+      p->comp_rel.assign(m->comp_rel.begin() + c0, m->comp_rel.begin() + c1);
+      p->comp_conv.assign(m->comp_conv.begin() + c0, m->comp_conv.begin() + c1);
+      double e = 0.0, worst = 0.0;
+      bool conv = true;
+      for (int c = 0; c < c1 - c0; ++c) {
+        e += p->comp_energy[c];
+        worst = std::max(worst, p->comp_rel[c]);
+        conv = conv && p->comp_conv[c] != 0;
+      }
+      p->energy = e;
+      p->solved = true;
+      p->dev_solved = false;  // the solution lives in the batch workspace only
+      if (res) {
+        res[i] = all;
+        res[i].energy_kJmol = e;
+        res[i].converged = conv ? 1 : 0;
+        res[i].final_rel_res = worst;
+      }
+    }
+    if (rc == PBTC_ENOCONV)
+      return fail_plan(head, PBTC_ENOCONV, "batch: GMRES did not reach the tolerance within max_iter");
+    return PBTC_OK;
+  });
+}
+
+int pbtc_get_surface(const pbtc_plan_t* plan, int surface_id, double* phi, double* dphidn_inner) {
   if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
   if (!plan->solved) return fail_global(PBTC_EINVAL, "no solution yet (call pbtc_solve)");
   if (surface_id < 0 || surface_id >= plan->nsurf) return fail_global(PBTC_EINVAL, "unknown surface");
@@ -281,14 +529,14 @@ int pbtc_get_surface(const pbtc_plan* plan, int surface_id, double* phi, double*
   return PBTC_OK;
 }
 
-int pbtc_get_phi_reac(const pbtc_plan* plan, double* phi_reac) {
+int pbtc_get_phi_reac(const pbtc_plan_t* plan, double* phi_reac) {
   if (!plan || !phi_reac) return fail_global(PBTC_EINVAL, "NULL argument");
   if (!plan->solved) return fail_global(PBTC_EINVAL, "no solution yet (call pbtc_solve)");
   std::memcpy(phi_reac, plan->phi_reac_host.data(), 8 * plan->nq);
   return PBTC_OK;
 }
 
-int pbtc_get_history(const pbtc_plan* plan, double* rel_res, int cap, int* n_iter) {
+int pbtc_get_history(const pbtc_plan_t* plan, double* rel_res, int cap, int* n_iter) {
   if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
   const int n = (int)plan->history.size();
   if (n_iter) *n_iter = n;
@@ -297,71 +545,88 @@ int pbtc_get_history(const pbtc_plan* plan, double* rel_res, int cap, int* n_ite
   return PBTC_OK;
 }
 
-int pbtc_matvec(pbtc_plan* plan, void* d_workspace, void* hip_stream, const double* d_x, double* d_y,
-                int precision) {
+int pbtc_matvec(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, const double* d_x,
+                double* d_y, int precision) {
   if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
-  if (!plan->setup_done || plan->ws != d_workspace)
-    return fail_plan(plan, PBTC_EINVAL, "workspace not set up (call pbtc_setup)");
-  if (!d_x || !d_y || d_x == d_y) return fail_plan(plan, PBTC_EINVAL, "x and y must be distinct device buffers");
-  if (precision != PBTC_FP64 && precision != PBTC_FP32)
-    return fail_plan(plan, PBTC_EINVAL, "precision must be PBTC_FP64 or PBTC_FP32");
-  return apply_operator(*plan, (hipStream_t)hip_stream, d_x, d_y, precision, 0);
+  return guarded(plan, [&] {
+    if (!ready(plan, d_workspace))
+      return fail_plan(plan, PBTC_EINVAL, "workspace not set up for this plan (call pbtc_setup)");
+    if (!d_x || !d_y || d_x == d_y)
+      return fail_plan(plan, PBTC_EINVAL, "x and y must be distinct device buffers");
+    if (precision != PBTC_FP64 && precision != PBTC_FP32)
+      return fail_plan(plan, PBTC_EINVAL, "precision must be PBTC_FP64 or PBTC_FP32");
+    return apply_operator(*plan, (hipStream_t)hip_stream, d_x, d_y, precision, 0);
+  });
 }
 
-int pbtc_matvec_transpose(pbtc_plan* plan, void* d_workspace, void* hip_stream, const double* d_x,
+int pbtc_matvec_transpose(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, const double* d_x,
                           double* d_y, int precision) {
   if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
-  if (!plan->setup_done || plan->ws != d_workspace)
-    return fail_plan(plan, PBTC_EINVAL, "workspace not set up (call pbtc_setup)");
-  if (!d_x || !d_y || d_x == d_y) return fail_plan(plan, PBTC_EINVAL, "x and y must be distinct device buffers");
-  if (precision != PBTC_FP64 && precision != PBTC_FP32)
-    return fail_plan(plan, PBTC_EINVAL, "precision must be PBTC_FP64 or PBTC_FP32");
-  return apply_transpose(*plan, (hipStream_t)hip_stream, d_x, d_y, precision, 0);
+  return guarded(plan, [&] {
+    if (!ready(plan, d_workspace))
+      return fail_plan(plan, PBTC_EINVAL, "workspace not set up for this plan (call pbtc_setup)");
+    if (!d_x || !d_y || d_x == d_y)
+      return fail_plan(plan, PBTC_EINVAL, "x and y must be distinct device buffers");
+    if (precision != PBTC_FP64 && precision != PBTC_FP32)
+      return fail_plan(plan, PBTC_EINVAL, "precision must be PBTC_FP64 or PBTC_FP32");
+    return apply_transpose(*plan, (hipStream_t)hip_stream, d_x, d_y, precision, 0);
+  });
 }
 
-int pbtc_precond_apply(pbtc_plan* plan, void* d_workspace, void* hip_stream, const double* d_x,
+int pbtc_precond_apply(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, const double* d_x,
                        double* d_y, int transpose) {
   if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
-  if (!plan->setup_done || plan->ws != d_workspace)
-    return fail_plan(plan, PBTC_EINVAL, "workspace not set up (call pbtc_setup)");
-  if (!d_x || !d_y || d_x == d_y) return fail_plan(plan, PBTC_EINVAL, "x and y must be distinct device buffers");
-  return apply_precond(*plan, (hipStream_t)hip_stream, d_x, d_y, transpose != 0, false);
+  return guarded(plan, [&] {
+    if (!ready(plan, d_workspace))
+      return fail_plan(plan, PBTC_EINVAL, "workspace not set up for this plan (call pbtc_setup)");
+    if (!d_x || !d_y || d_x == d_y)
+      return fail_plan(plan, PBTC_EINVAL, "x and y must be distinct device buffers");
+    return apply_precond(*plan, (hipStream_t)hip_stream, d_x, d_y, transpose != 0, false);
+  });
 }
 
-int pbtc_coulomb_energy(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* total,
+int pbtc_coulomb_energy(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, double* total,
                         double* per_system) {
   if (!plan || !total) return fail_global(PBTC_EINVAL, "NULL argument");
-  if (!plan->setup_done || plan->ws != d_workspace)
-    return fail_plan(plan, PBTC_EINVAL, "workspace not set up (call pbtc_setup)");
-  const int rc = device_coulomb(*plan, (hipStream_t)hip_stream, total, per_system);
-  if (rc) return fail_plan(plan, rc, plan->err.c_str());
-  return PBTC_OK;
+  return guarded(plan, [&] {
+    if (!ready(plan, d_workspace))
+      return fail_plan(plan, PBTC_EINVAL, "workspace not set up for this plan (call pbtc_setup)");
+    return device_coulomb(*plan, (hipStream_t)hip_stream, total, per_system);
+  });
 }
 
-int pbtc_rhs(pbtc_plan* plan, void* d_workspace, void* hip_stream, double* d_b) {
+int pbtc_rhs(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, double* d_b) {
   if (!plan || !d_b) return fail_global(PBTC_EINVAL, "NULL argument");
-  if (!plan->setup_done || plan->ws != d_workspace)
-    return fail_plan(plan, PBTC_EINVAL, "workspace not set up (call pbtc_setup)");
-  const hipError_t e = hipMemcpyAsync(d_b, static_cast<char*>(plan->ws) + plan->o_b,
-                                      8 * plan->nunk, hipMemcpyDeviceToDevice,
-                                      (hipStream_t)hip_stream);
-  if (e != hipSuccess) return fail_plan(plan, PBTC_EDEVICE, hipGetErrorString(e));
-  return PBTC_OK;
+  return guarded(plan, [&] {
+    if (!ready(plan, d_workspace))
+      return fail_plan(plan, PBTC_EINVAL, "workspace not set up for this plan (call pbtc_setup)");
+    if (plan->charges_dirty) {
+      const int rc = update_charges(*plan, (hipStream_t)hip_stream);
+      if (rc) return rc;
+    }
+    const hipError_t e = hipMemcpyAsync(d_b, static_cast<char*>(plan->ws) + plan->o_b,
+                                        8 * plan->nunk, hipMemcpyDeviceToDevice,
+                                        (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail_plan(plan, PBTC_EDEVICE, hipGetErrorString(e));
+    return PBTC_OK;
+  });
 }
 
-int pbtc_backward(pbtc_plan* plan, void* d_workspace, size_t bytes, void* hip_stream, double gE,
+int pbtc_backward(pbtc_plan_t* plan, void* d_workspace, size_t bytes, void* hip_stream, double gE,
                   double* dE_dq, double* dE_dkappa, double* dE_deps, pbtc_result* res) {
   if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
-  if (!plan->solved || plan->ws != d_workspace || bytes < plan->ws_bytes)
-    return fail_plan(plan, PBTC_EINVAL, "call pbtc_solve on this workspace first");
-  pbtc_result local;
-  if (!res) res = &local;
-  std::memset(res, 0, sizeof(*res));
-  fill_sizes(plan, res);
-  return device_backward(*plan, (hipStream_t)hip_stream, gE, dE_dq, dE_dkappa, dE_deps, res);
+  return guarded(plan, [&] {
+    if (!plan->dev_solved || !ready(plan, d_workspace) || bytes < plan->ws_bytes)
+      return fail_plan(plan, PBTC_EINVAL, "call pbtc_solve on this workspace first");
+    pbtc_result local;
+    pbtc_result* r = res ? res : &local;
+    std::memset(r, 0, sizeof(*r));
+    fill_sizes(plan, r);
+    return device_backward(*plan, (hipStream_t)hip_stream, gE, dE_dq, dE_dkappa, dE_deps, r);
+  });
 }
 
-int pbtc_get_systems(const pbtc_plan* plan, int* n_systems, double* energy_kJmol,
+int pbtc_get_systems(const pbtc_plan_t* plan, int* n_systems, double* energy_kJmol,
                      double* rel_res, int64_t* first_unknown) {
   if (!plan) return fail_global(PBTC_EINVAL, "plan is NULL");
   if (n_systems) *n_systems = plan->ncomp;
@@ -375,7 +640,7 @@ int pbtc_get_systems(const pbtc_plan* plan, int* n_systems, double* energy_kJmol
   return PBTC_OK;
 }
 
-int pbtc_set_charge_values(pbtc_plan* plan, const double* q) {
+int pbtc_set_charge_values(pbtc_plan_t* plan, const double* q) {
   if (!plan || !q) return fail_global(PBTC_EINVAL, "NULL argument");
   if (!finite_all(q, plan->nq)) return fail_plan(plan, PBTC_EINVAL, "charge value not finite");
   for (int r = 0; r < plan->nreg; ++r) {
@@ -384,6 +649,8 @@ int pbtc_set_charge_values(pbtc_plan* plan, const double* q) {
   }
   plan->charges_dirty = true;
   plan->solved = false;
+  plan->dev_solved = false;
+  ++plan->charge_version;
   return PBTC_OK;
 }
 
@@ -399,7 +666,7 @@ int pbtc_gauss_legendre(int n, double* nodes, double* weights) {
   return PBTC_OK;
 }
 
-const char* pbtc_last_error(const pbtc_plan* plan) {
+const char* pbtc_last_error(const pbtc_plan_t* plan) {
   if (plan) return plan->err.c_str();
   return g_err.c_str();
 }

@@ -41,22 +41,22 @@ namespace pbtc {
 
 __global__ void k_split_count(Cell* __restrict__ cells, int lb, int le, int ncrit,
                               const uint64_t* __restrict__ key, long long* __restrict__ cnt);
-int build_octree(pbtc_plan& pl, hipStream_t st, Cell* cells, int64_t cap,
+int build_octree(pbtc_plan_t& pl, hipStream_t st, Cell* cells, int64_t cap,
                  const std::vector<Cell>& roots, const uint64_t* key, const double* px,
                  const double* py, const double* pz, int ncrit, long long* cnt,
                  long long* scan_scratch, int64_t* n_cells, std::vector<int>* level_begin,
                  int64_t* need);
-int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+int apply_operator(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int precision,
                    int phase);
-int recompute_near_values(pbtc_plan& pl, hipStream_t st);
-int recompute_rhs(pbtc_plan& pl, hipStream_t st);
-int upload_coulomb_rows(pbtc_plan& pl, hipStream_t st);
-int upload_descriptors(pbtc_plan& pl, hipStream_t st);
+int recompute_near_values(pbtc_plan_t& pl, hipStream_t st);
+int recompute_rhs(pbtc_plan_t& pl, hipStream_t st);
+int upload_coulomb_rows(pbtc_plan_t& pl, hipStream_t st);
+int upload_descriptors(pbtc_plan_t& pl, hipStream_t st);
 template <typename Op>
-int krylov_solve(pbtc_plan& pl, hipStream_t st, Op op32, Op op64, const double* b, double* x,
+int krylov_solve(pbtc_plan_t& pl, hipStream_t st, Op op32, Op op64, const double* b, double* x,
                  int precision, double tol, int* iters, int* n32, int* n64, int* nref,
                  double* rel, bool* conv, std::vector<double>* hist);
-int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* b, double* x,
+int solve_with_ops(pbtc_plan_t& pl, hipStream_t st, bool transpose, const double* b, double* x,
                    int* iters, int* n32, int* n64, int* nref, double* rel, bool* conv,
                    std::vector<double>* hist);
 
@@ -671,10 +671,10 @@ struct AdjTables {
 
 }  // namespace
 
-static int adj_upload_small(pbtc_plan& pl, hipStream_t st);
+static int adj_upload_small(pbtc_plan_t& pl, hipStream_t st);
 
 // One-off set-up of the transposed operator on the plan's workspace.
-int adjoint_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
+int adjoint_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
   *need_retry = 0;
   const int T = 256;
   // Gauss points as targets, and the inverse of their Morton permutation
@@ -893,7 +893,7 @@ int adjoint_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
 }
 
 // slot tables, item lists and gather tables of the transposed operator
-static int adj_upload_small(pbtc_plan& pl, hipStream_t st) {
+static int adj_upload_small(pbtc_plan_t& pl, hipStream_t st) {
   PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_aitems), pl.aitem_block.data(),
                           4 * pl.aitem_block.size(), hipMemcpyHostToDevice, st));
   for (int ph = 0; ph < 2; ++ph) {
@@ -958,7 +958,7 @@ static int adj_upload_small(pbtc_plan& pl, hipStream_t st) {
 }
 
 template <typename real>
-static void launch_adj_m2p(pbtc_plan& pl, hipStream_t st, const AdjArgs& a, int grid,
+static void launch_adj_m2p(pbtc_plan_t& pl, hipStream_t st, const AdjArgs& a, int grid,
                            const Src<real>* gpos, const real* mom, int kind, int kslot,
                            real* partial) {
 #define PBTC_AM2P(PP)                                                                         \
@@ -983,7 +983,7 @@ static void launch_adj_m2p(pbtc_plan& pl, hipStream_t st, const AdjArgs& a, int 
 }
 
 template <typename real>
-static int adj_moments(pbtc_plan& pl, hipStream_t st, int phase, real* mom) {
+static int adj_moments(pbtc_plan_t& pl, hipStream_t st, int phase, real* mom) {
   const int64_t c0 = pl.am_chunk_off[phase], c1 = pl.am_chunk_off[phase + 1];
   const int64_t p0 = pl.am_pair_off[phase], p1 = pl.am_pair_off[phase + 1];
   if (p1 == p0) return PBTC_OK;
@@ -1023,7 +1023,7 @@ static int adj_moments(pbtc_plan& pl, hipStream_t st, int phase, real* mom) {
 
 // z = A^T lam (phase 0) or z = S^T lam (phase 1, lam = charge weights)
 template <typename real>
-static int transpose_impl(pbtc_plan& pl, hipStream_t st, const double* lam, double* z, int phase) {
+static int transpose_impl(pbtc_plan_t& pl, hipStream_t st, const double* lam, double* z, int phase) {
   const int T = 256;
   const bool tree = pl.prm.op == PBTC_OP_TREECODE;
   double* muS = wsp<double>(pl, pl.o_mu_s);
@@ -1126,7 +1126,7 @@ static int transpose_impl(pbtc_plan& pl, hipStream_t st, const double* lam, doub
   return PBTC_OK;
 }
 
-static int ensure_adjoint(pbtc_plan& pl, hipStream_t st) {
+static int ensure_adjoint(pbtc_plan_t& pl, hipStream_t st) {
   if (pl.adj_done) return PBTC_OK;
   int retry = 0;
   const int rc = adjoint_setup(pl, st, &retry);
@@ -1136,7 +1136,7 @@ static int ensure_adjoint(pbtc_plan& pl, hipStream_t st) {
   return rc;
 }
 
-int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+int apply_transpose(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int precision,
                     int phase) {
   const int rc = ensure_adjoint(pl, st);
   if (rc) return rc;
@@ -1147,7 +1147,7 @@ int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, i
 // sum over the listed (a offset, b offset, n) triples of a . b (device dots ->
 // host).  Long triples are cut into pieces of at most kDotPiece elements, one
 // work-group each, whose dots the host adds in piece order.
-static int pair_dots(pbtc_plan& pl, hipStream_t st, const std::vector<long long>& tab,
+static int pair_dots(pbtc_plan_t& pl, hipStream_t st, const std::vector<long long>& tab,
                      const double* A, const double* B, std::vector<double>* out) {
   constexpr long long kDotPiece = 16384;
   out->assign(tab.size() / 3, 0.0);
@@ -1176,7 +1176,7 @@ static int pair_dots(pbtc_plan& pl, hipStream_t st, const std::vector<long long>
   return PBTC_OK;
 }
 
-int device_backward(pbtc_plan& pl, hipStream_t st, double gE, double* dq, double* dk, double* de,
+int device_backward(pbtc_plan_t& pl, hipStream_t st, double gE, double* dq, double* dk, double* de,
                     pbtc_result* res) {
   int rc = ensure_adjoint(pl, st);
   if (rc) {

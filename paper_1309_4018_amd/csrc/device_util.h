@@ -8,7 +8,7 @@
 namespace pbtc {
 
 template <typename T>
-inline T* wsp(const pbtc_plan& pl, size_t off) {
+inline T* wsp(const pbtc_plan_t& pl, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(pl.ws) + off);
 }
 

@@ -177,6 +177,7 @@ struct Layout {
 };
 
 struct Timer;
+struct BatchCache;  // merged plan of pbtc_solve_batch, kept by the batch's first plan
 
 // A run of work units (one wavefront each) over the lists of one kernel set.
 struct UnitSet {
@@ -187,7 +188,7 @@ struct UnitSet {
 }  // namespace pbtc
 
 // Plan: everything the host knows about a problem plus the device layout.
-struct pbtc_plan {
+struct pbtc_plan_s {
   pbtc_problem prob;
   pbtc_params prm;
   std::string err;
@@ -290,7 +291,7 @@ struct pbtc_plan {
   // events that fork and join it (created on first use)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  ~pbtc_plan();
+  ~pbtc_plan_s();
   std::vector<double> item_flop_p2p[2][pbtc::KS_COUNT], item_flop_m2p[2][pbtc::KS_COUNT];
   double launch_flop_p2p[2][pbtc::KS_COUNT] = {}, launch_flop_m2p[2][pbtc::KS_COUNT] = {};
   bool setup_done = false;
@@ -343,8 +344,13 @@ struct pbtc_plan {
   size_t o_grp_tab = 0;                            // group target offsets and counts
   size_t o_tkey = 0, o_tkey2 = 0, o_tval = 0, o_tval2 = 0;  // target sort buffers
   double p2p_pairs = 0, m2p_evals = 0, dense_equiv = 0;
-  bool solved = false;
+  bool solved = false;        // host results (x_host, phi_reac_host, energy) are current
+  bool dev_solved = false;    // the plan's own workspace holds the solution of its charges
   bool charges_dirty = false;
+  uint64_t serial = 0;        // unique per plan (batch cache identity)
+  uint64_t charge_version = 0;  // bumped by pbtc_set_charge_values
+  std::vector<int> comp_conv;   // per system: converged in the last solve
+  pbtc::BatchCache* batch = nullptr;  // owned; see abi.cpp
 
   // host results
   std::vector<double> x_host, phi_reac_host, history;

@@ -20,11 +20,11 @@
 
 namespace pbtc {
 
-int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+int apply_operator(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int precision,
                    int phase);
-int apply_transpose(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+int apply_transpose(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int precision,
                     int phase);
-void prof_collect(pbtc_plan& pl);
+void prof_collect(pbtc_plan_t& pl);
 
 // per-system scalar arrays of the Krylov state
 enum { SC_BNORM = 0, SC_RES, SC_ACTIVE, SC_BETA, SC_HN, SC_TOL, SC_KFIN, SC_REF, SC_NORM, SC_N };
@@ -378,7 +378,7 @@ __global__ void k_coulomb_pot(int64_t nq, const double* __restrict__ qxyz,
 // region graph): H, Givens data and scalars live per system in o_kstate;
 // vector operations run over the whole unknown vector, reductions per system.
 struct Krylov {
-  pbtc_plan& pl;
+  pbtc_plan_t& pl;
   hipStream_t st;
   int64_t n;
   int m, ld, nc, nchunks;
@@ -397,7 +397,7 @@ struct Krylov {
   const int* chunk0;
   const int* comp;
 
-  Krylov(pbtc_plan& p, hipStream_t s) : pl(p), st(s) {
+  Krylov(pbtc_plan_t& p, hipStream_t s) : pl(p), st(s) {
     n = pl.nunk;
     m = pl.prm.restart;
     ld = m + 1;
@@ -507,7 +507,7 @@ struct Krylov {
   }
 };
 
-int apply_precond(pbtc_plan& pl, hipStream_t st, const double* x, double* y, bool transpose,
+int apply_precond(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, bool transpose,
                   bool accumulate) {
   hipLaunchKernelGGL(k_prec_apply, dim3(nblocks(pl.np_tot, 256)), dim3(256), 0, st, pl.np_tot,
                      wsp<int>(pl, pl.o_pidx), wsp<double>(pl, pl.o_pinv), x, y, transpose ? 1 : 0,
@@ -522,7 +522,7 @@ int apply_precond(pbtc_plan& pl, hipStream_t st, const double* x, double* y, boo
 // prec: 0 none, 1 right preconditioning by M^-1, 2 by M^-T (transposed
 // system).
 template <typename Op>
-static int gmres(pbtc_plan& pl, hipStream_t st, Op op, int prec, const double* rhs, double* z,
+static int gmres(pbtc_plan_t& pl, hipStream_t st, Op op, int prec, const double* rhs, double* z,
                  bool zero_start,
                  const std::vector<double>& tol, const std::vector<double>& ref, int max_iter,
                  int* iters, std::vector<double>* hist, std::vector<int>* conv,
@@ -685,7 +685,7 @@ static double now_s() {
 // tolerance in the plan's precision: FP64 GMRES, FP32 GMRES, or FP32 GMRES
 // inside FP64 iterative refinement.  rel = the largest explicit
 // ||b_c - (A x)_c|| / ||b_c|| over systems, with the FP64 operator.
-int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* b, double* x,
+int solve_with_ops(pbtc_plan_t& pl, hipStream_t st, bool transpose, const double* b, double* x,
                    int* iters_out, int* n32_out, int* n64_out, int* nref_out, double* rel_out,
                    bool* conv_out, std::vector<double>* hist) {
   const int T = 256;
@@ -790,7 +790,10 @@ int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* 
     all &= conv[c] != 0;
     worst = std::max(worst, rel[c]);
   }
-  pl.comp_rel = rel;
+  if (!transpose) {  // per-system results of the forward solve
+    pl.comp_rel = rel;
+    pl.comp_conv = conv;
+  }
   *iters_out = iters;
   *n32_out = n32;
   *n64_out = n64;
@@ -801,7 +804,7 @@ int solve_with_ops(pbtc_plan& pl, hipStream_t st, bool transpose, const double* 
 }
 
 // Solve on a set-up workspace; fills res (timings from t_setup on).
-int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res) {
+int device_solve(pbtc_plan_t& pl, hipStream_t st, pbtc_result* res) {
   const int64_t n = pl.nunk;
   double* b = wsp<double>(pl, pl.o_b);
   double* x = wsp<double>(pl, pl.o_x);
@@ -840,6 +843,7 @@ int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res) {
   PBTC_HIP(hipMemcpyAsync(pl.phi_reac_host.data(), phi, 8 * pl.nq, hipMemcpyDeviceToHost, st));
   PBTC_HIP(hipStreamSynchronize(st));
   pl.solved = true;
+  pl.dev_solved = true;
   if (res) {
     res->energy_kJmol = pl.energy;
     res->n_iter = iters;
@@ -869,7 +873,7 @@ int device_solve(pbtc_plan& pl, hipStream_t st, pbtc_result* res) {
 }
 
 // Coulomb energy of every system: 1/2 k_e sum_i q_i phi_c[i].
-int device_coulomb(pbtc_plan& pl, hipStream_t st, double* total, double* per_system) {
+int device_coulomb(pbtc_plan_t& pl, hipStream_t st, double* total, double* per_system) {
   // table: nreg + 1 first-charge offsets (int64), then nreg permittivities
   std::vector<double>& tab = pl.qtab_host;
   tab.assign(2 * pl.nreg + 1, 0.0);

@@ -515,7 +515,7 @@ __global__ void k_combine(const DevRowBlock* __restrict__ rows, const DevRowTerm
 
 // ------------------------------------------------------------ host side
 template <typename real>
-static int launch_moments(pbtc_plan& pl, hipStream_t st, real* mom, const Src<real>* src) {
+static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<real>* src) {
   const Cell* cells = wsp<Cell>(pl, pl.o_cells);
   const int4* chunks = wsp<int4>(pl, pl.o_mchunks);
   const int* cell_chunk = wsp<int>(pl, pl.o_mcell);
@@ -544,7 +544,7 @@ static int launch_moments(pbtc_plan& pl, hipStream_t st, real* mom, const Src<re
 }
 
 template <typename real, int KIND>
-static void launch_m2p(pbtc_plan& pl, hipStream_t st, const UnitArgs& a, int grid, const real* tx,
+static void launch_m2p(pbtc_plan_t& pl, hipStream_t st, const UnitArgs& a, int grid, const real* tx,
                        const real* ty, const real* tz, const real* mom, int slot, real* partial) {
 #define PBTC_M2P(PP)                                                                           \
   case PP:                                                                                     \
@@ -565,10 +565,10 @@ static void launch_m2p(pbtc_plan& pl, hipStream_t st, const UnitArgs& a, int gri
 
 // Timing of one kernel launch (kind 0 P2P, 1 Laplace M2P, 2 Yukawa M2P) with
 // events on the launch stream; only the FP32 operator (A x) is timed.
-static void prof_mark(pbtc_plan& pl, hipStream_t st, bool on, int kind, double flop, bool begin) {
+static void prof_mark(pbtc_plan_t& pl, hipStream_t st, bool on, int kind, double flop, bool begin) {
   if (!pl.prm.profile || !on) return;
   if (begin) {
-    pbtc_plan::ProfEvent ev;
+    pbtc_plan_t::ProfEvent ev;
     if (!pl.prof_pool.empty()) {
       ev = pl.prof_pool.back();
       pl.prof_pool.pop_back();
@@ -583,14 +583,14 @@ static void prof_mark(pbtc_plan& pl, hipStream_t st, bool on, int kind, double f
     ev.recorded = hipEventRecord(ev.a, st) == hipSuccess;
     pl.prof.push_back(ev);
   } else if (!pl.prof.empty()) {
-    pbtc_plan::ProfEvent& ev = pl.prof.back();
+    pbtc_plan_t::ProfEvent& ev = pl.prof.back();
     ev.recorded = ev.recorded && hipEventRecord(ev.b, st) == hipSuccess;
   }
 }
 
 // y = A x (phase 0) or phi_reac = S x (phase 1) in precision `prec`.
 template <typename real>
-static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int phase) {
+static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int phase) {
   const int T = 256;
   Src<real>* src = wsp<Src<real>>(pl, sizeof(real) == 4 ? pl.o_src32 : pl.o_src64);
   real* mom = wsp<real>(pl, sizeof(real) == 4 ? pl.o_mom32 : pl.o_mom64);
@@ -735,7 +735,7 @@ static int apply_impl(pbtc_plan& pl, hipStream_t st, const double* x, double* y,
 }
 
 // Folds finished profiling events into the plan's totals (stream synchronised).
-void prof_collect(pbtc_plan& pl) {
+void prof_collect(pbtc_plan_t& pl) {
   for (auto& ev : pl.prof) {
     float ms = 0.0f;
     if (ev.recorded && hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
@@ -748,14 +748,14 @@ void prof_collect(pbtc_plan& pl) {
   pl.prof.clear();
 }
 
-int apply_operator(pbtc_plan& pl, hipStream_t st, const double* x, double* y, int precision,
+int apply_operator(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int precision,
                    int phase) {
   if (precision == PBTC_FP64) return apply_impl<double>(pl, st, x, y, phase);
   return apply_impl<float>(pl, st, x, y, phase);
 }
 
 // Descriptor tables (blocks, rows, item lists) to the device.
-int upload_descriptors(pbtc_plan& pl, hipStream_t st) {
+int upload_descriptors(pbtc_plan_t& pl, hipStream_t st) {
   std::vector<DevBlock> db(pl.blocks.size());
   for (size_t i = 0; i < pl.blocks.size(); ++i) {
     const Block& b = pl.blocks[i];

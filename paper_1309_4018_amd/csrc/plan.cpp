@@ -41,9 +41,9 @@ int kernel_set(int nk, const double* kap) {
 
 }  // namespace
 
-void compute_layout(pbtc_plan& pl);
+void compute_layout(pbtc_plan_t& pl);
 
-int build_plan(pbtc_plan& pl) {
+int build_plan(pbtc_plan_t& pl) {
   const pbtc_problem& P = pl.prob;
   pl.nsurf = (int)P.surfaces.size();
   pl.nreg = (int)P.regions.size();
@@ -478,7 +478,7 @@ int build_plan(pbtc_plan& pl) {
   return PBTC_OK;
 }
 
-void compute_layout(pbtc_plan& pl) {
+void compute_layout(pbtc_plan_t& pl) {
   Layout L;
   const int64_t nP = ncoef(pl.P);
   const int m = pl.prm.restart;

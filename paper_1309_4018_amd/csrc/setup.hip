@@ -707,9 +707,9 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 
 // Per-surface tables (persistent): vertex base, Gauss-point and panel
 // offsets, cube, near-field query radius, first original Gauss point.
-static long long* near_vbase(pbtc_plan& pl) { return wsp<long long>(pl, pl.o_surf_tab); }
+static long long* near_vbase(pbtc_plan_t& pl) { return wsp<long long>(pl, pl.o_surf_tab); }
 
-static void near_args(pbtc_plan& pl, NearArgs* na) {
+static void near_args(pbtc_plan_t& pl, NearArgs* na) {
   long long* vbase = near_vbase(pl);
   long long* pan_off = vbase + 2 * (pl.nsurf + 1);
   double* cube = reinterpret_cast<double*>(pan_off + pl.nsurf + 1);
@@ -739,18 +739,18 @@ static void near_args(pbtc_plan& pl, NearArgs* na) {
   na->np_tot = pl.np_tot;
 }
 
-int upload_descriptors(pbtc_plan& pl, hipStream_t st);
-int recompute_near_values(pbtc_plan& pl, hipStream_t st);
-int recompute_precond(pbtc_plan& pl, hipStream_t st);
-int recompute_rhs(pbtc_plan& pl, hipStream_t st);
-int launch_near_values(pbtc_plan& pl, hipStream_t st);
-int launch_precond(pbtc_plan& pl, hipStream_t st);
-int launch_rhs(pbtc_plan& pl, hipStream_t st);
+int upload_descriptors(pbtc_plan_t& pl, hipStream_t st);
+int recompute_near_values(pbtc_plan_t& pl, hipStream_t st);
+int recompute_precond(pbtc_plan_t& pl, hipStream_t st);
+int recompute_rhs(pbtc_plan_t& pl, hipStream_t st);
+int launch_near_values(pbtc_plan_t& pl, hipStream_t st);
+int launch_precond(pbtc_plan_t& pl, hipStream_t st);
+int launch_rhs(pbtc_plan_t& pl, hipStream_t st);
 
 // Octree over Morton-sorted points, level by level from the given roots
 // (one per point set): a box holding >= ncrit points is split into its
 // non-empty octants.  Fills cells, their radii, *n_cells and level_begin.
-int build_octree(pbtc_plan& pl, hipStream_t st, Cell* cells, int64_t cap,
+int build_octree(pbtc_plan_t& pl, hipStream_t st, Cell* cells, int64_t cap,
                  const std::vector<Cell>& roots, const uint64_t* key, const double* px,
                  const double* py, const double* pz, int ncrit, long long* cnt,
                  long long* scan_scratch, int64_t* n_cells, std::vector<int>* level_begin,
@@ -800,10 +800,10 @@ int build_octree(pbtc_plan& pl, hipStream_t st, Cell* cells, int64_t cap,
   return PBTC_OK;
 }
 
-int upload_descriptors(pbtc_plan& pl, hipStream_t st);
+int upload_descriptors(pbtc_plan_t& pl, hipStream_t st);
 
 // Builds every once-per-geometry structure on the plan's workspace.
-int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
+int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
   *need_retry = 0;
   const pbtc_problem& P = pl.prob;
   const int T = 256;
@@ -1237,7 +1237,7 @@ int device_setup(pbtc_plan& pl, hipStream_t st, int* need_retry) {
 }
 
 // New charge values (positions unchanged): upload and rebuild the RHS.
-int update_charges(pbtc_plan& pl, hipStream_t st) {
+int update_charges(pbtc_plan_t& pl, hipStream_t st) {
   std::vector<double> q(std::max<int64_t>(pl.nq, 1));
   for (int r = 0; r < pl.nreg; ++r) {
     const ChargeSet& c = pl.prob.charges[r];
@@ -1252,7 +1252,7 @@ int update_charges(pbtc_plan& pl, hipStream_t st) {
 }
 
 // FP64 near-field corrections for every row of every block (depends on kappa).
-int recompute_near_values(pbtc_plan& pl, hipStream_t st) {
+int recompute_near_values(pbtc_plan_t& pl, hipStream_t st) {
   const int rc = launch_near_values(pl, st);
   if (rc) return rc;
   PBTC_HIP(hipStreamSynchronize(st));
@@ -1260,7 +1260,7 @@ int recompute_near_values(pbtc_plan& pl, hipStream_t st) {
 }
 
 // The same, queued on the stream only.
-int launch_near_values(pbtc_plan& pl, hipStream_t st) {
+int launch_near_values(pbtc_plan_t& pl, hipStream_t st) {
   NearArgs na;
   near_args(pl, &na);
   Tables tb;
@@ -1287,7 +1287,7 @@ int launch_near_values(pbtc_plan& pl, hipStream_t st) {
 
 // Diagonal blocks of the block-diagonal preconditioner (depend on kappa and
 // eps of the two regions of every surface).
-int recompute_precond(pbtc_plan& pl, hipStream_t st) {
+int recompute_precond(pbtc_plan_t& pl, hipStream_t st) {
   const int rc = launch_precond(pl, st);
   if (rc) return rc;
   PBTC_HIP(hipStreamSynchronize(st));
@@ -1295,7 +1295,7 @@ int recompute_precond(pbtc_plan& pl, hipStream_t st) {
 }
 
 // The same, queued on the stream only.
-int launch_precond(pbtc_plan& pl, hipStream_t st) {
+int launch_precond(pbtc_plan_t& pl, hipStream_t st) {
   Tables tb;
   tb.K = pl.prm.K;
   tb.Kf = pl.prm.K_fine;
@@ -1323,7 +1323,7 @@ int launch_precond(pbtc_plan& pl, hipStream_t st) {
 }
 
 // Coulomb row table (o_crows) from the current permittivities and kappas.
-int upload_coulomb_rows(pbtc_plan& pl, hipStream_t st) {
+int upload_coulomb_rows(pbtc_plan_t& pl, hipStream_t st) {
   const pbtc_problem& P = pl.prob;
   const size_t nr = pl.rows.size();
   std::vector<char>& h = pl.crow_host;
@@ -1355,7 +1355,7 @@ int upload_coulomb_rows(pbtc_plan& pl, hipStream_t st) {
 
 // Coulomb right-hand side (Eq. matel, Q; the charges of each row's region,
 // scaled by 1/eps of that region), all rows in one launch.
-int recompute_rhs(pbtc_plan& pl, hipStream_t st) {
+int recompute_rhs(pbtc_plan_t& pl, hipStream_t st) {
   const int rc = launch_rhs(pl, st);
   if (rc) return rc;
   PBTC_HIP(hipStreamSynchronize(st));
@@ -1363,7 +1363,7 @@ int recompute_rhs(pbtc_plan& pl, hipStream_t st) {
 }
 
 // The same, queued on the stream only.
-int launch_rhs(pbtc_plan& pl, hipStream_t st) {
+int launch_rhs(pbtc_plan_t& pl, hipStream_t st) {
   int rc = upload_coulomb_rows(pl, st);
   if (rc) return rc;
   const int T = 256;

@@ -16,13 +16,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpbtc.so")
 
-OK, EINVAL, EMESH, ECHARGE, EWORKSPACE, EDEVICE, ENOCONV = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EMESH, ECHARGE, EWORKSPACE, EDEVICE, ENOCONV, EHOST = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_REFINED, FP32 = 0, 1, 2
 OP_TREECODE, OP_DIRECT = 0, 1
 PREC_NONE, PREC_BLOCK_DIAG = 0, 1
 
 _ERRNAMES = {EINVAL: "EINVAL", EMESH: "EMESH", ECHARGE: "ECHARGE", EWORKSPACE: "EWORKSPACE",
-             EDEVICE: "EDEVICE", ENOCONV: "ENOCONV"}
+             EDEVICE: "EDEVICE", ENOCONV: "ENOCONV", EHOST: "EHOST"}
 
 
 class Params(C.Structure):
@@ -70,14 +70,16 @@ _EXPORTS = {
     "pbtc_set_charges": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int64]),
     "pbtc_params_default": (C.c_int, [C.POINTER(Params)]),
     "pbtc_validate": (C.c_int, [C.c_void_p, C.POINTER(Params)]),
-    "pbtc_plan_create": (C.c_int, [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_void_p),
-                                   C.POINTER(C.c_size_t)]),
+    "pbtc_plan": (C.c_int, [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_void_p),
+                            C.POINTER(C.c_size_t)]),
     "pbtc_plan_destroy": (None, [C.c_void_p]),
     "pbtc_plan_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                   C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "pbtc_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(Result)]),
     "pbtc_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int,
                              C.POINTER(Result)]),
+    "pbtc_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_size_t,
+                                   C.c_void_p, C.POINTER(Result)]),
     "pbtc_get_surface": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "pbtc_get_phi_reac": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pbtc_get_history": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
@@ -237,7 +239,7 @@ class Plan:
         self.device = torch.device(device)
         h = C.c_void_p()
         nbytes = C.c_size_t()
-        check(self.lib.pbtc_plan_create(problem.h, C.byref(self.params), C.byref(h), C.byref(nbytes)))
+        check(self.lib.pbtc_plan(problem.h, C.byref(self.params), C.byref(h), C.byref(nbytes)))
         self.h = h
         self.ws = None
         self._alloc(nbytes.value)
@@ -430,6 +432,42 @@ def systems(plan):
     u = np.empty(n.value, dtype=np.int64)
     check(plan.lib.pbtc_get_systems(plan.h, C.byref(n), _ptr(e), _ptr(r), _ptr(u)), plan.h)
     return e, r, u
+
+
+class Batch:
+    """Several plans solved together by ``pbtc_solve_batch`` on one workspace
+    (every kernel launch shared, every system with its own Krylov space)."""
+
+    def __init__(self, plans):
+        import torch
+
+        self.torch = torch
+        self.plans = list(plans)
+        if not self.plans:
+            raise ValueError("empty batch")
+        self.lib = load()
+        self.device = self.plans[0].device
+        self._arr = (C.c_void_p * len(self.plans))(*[p.h for p in self.plans])
+        self.ws = torch.empty(0, dtype=torch.uint8, device=self.device)
+
+    def solve(self, allow_noconv=False):
+        """Results (one dict per plan); the workspace grows on demand."""
+        n = len(self.plans)
+        for _ in range(4):
+            res = (Result * n)()
+            code = self.lib.pbtc_solve_batch(
+                self._arr, n, C.c_void_p(self.ws.data_ptr() if self.ws.numel() else 0),
+                self.ws.numel(), _stream_handle(self.torch, self.device), res)
+            if code == EWORKSPACE and res[0].workspace_needed > self.ws.numel():
+                self.ws = self.torch.empty(int(res[0].workspace_needed), dtype=self.torch.uint8,
+                                           device=self.device)
+                continue
+            break
+        if not (allow_noconv and code == ENOCONV):
+            check(code, self.plans[0].h)
+        for p, r in zip(self.plans, res):
+            p.last = r
+        return [r.as_dict() for r in res]
 
 
 def triangle_rule(k):

@@ -138,7 +138,7 @@ def test_plan_sizes_without_device(lib):
     h = C.c_void_p()
     nb = C.c_size_t()
     prm = lib.default_params()
-    lib.check(lib.load().pbtc_plan_create(p.h, C.byref(prm), C.byref(h), C.byref(nb)))
+    lib.check(lib.load().pbtc_plan(p.h, C.byref(prm), C.byref(h), C.byref(nb)))
     n_unk, n_q, n_s, n_r = C.c_int64(), C.c_int64(), C.c_int(), C.c_int()
     lib.check(lib.load().pbtc_plan_sizes(h, C.byref(n_unk), C.byref(n_q), C.byref(n_s), C.byref(n_r)))
     assert n_unk.value == 2 * prob.n_panels == 22528
