@@ -211,6 +211,11 @@ __global__ void k_zero_f64(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+__global__ void k_ones_f64(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 1.0;
+}
+
 // --------------------------------------------------------------- per apply
 // mu weights of every kernel slot from the row weights lambda
 __global__ void k_adj_mu(const DevSlot* __restrict__ slots, const double* __restrict__ lam,
@@ -1176,6 +1181,8 @@ static int pair_dots(pbtc_plan_t& pl, hipStream_t st, const std::vector<long lon
   return PBTC_OK;
 }
 
+int launch_dk0_diag(pbtc_plan_t& pl, hipStream_t st, const double* x, double* e);
+
 int device_backward(pbtc_plan_t& pl, hipStream_t st, double gE, double* dq, double* dk, double* de,
                     pbtc_result* res) {
   int rc = ensure_adjoint(pl, st);
@@ -1348,6 +1355,59 @@ int device_backward(pbtc_plan_t& pl, hipStream_t st, double gE, double* dq, doub
     if (rc) return rc;
     for (size_t gi = 0; gi < group.size(); ++gi)
       dkap[group[gi]] = 0.5 * C * (val[0][gi] - val[1][gi]) / (2.0 * h);
+  }
+  // kappa = 0 (Laplace regions): the derivative kernels are d G / d kappa =
+  // -1/(4 pi) and d (n . grad G) / d kappa = 0 there, so with
+  // Psi_s = sum_j A_j psi_j over surface s, Lambda_rb = sum of lam over a row
+  // block, E_rb = sum_i lam_i e_i (e from k_dk0_diag: the self-term remainder)
+  // and Q_p the charge of region p:
+  //   q^T S' x    = Q_p sum_{reaction terms of p} sigma c (-Psi_s / (4 pi))
+  //   lam^T A' x  = sum_{rows of p} sum_terms -sigma c (-Psi_s / (4 pi) Lambda_rb
+  //                                                    + [s = t] E_rb)
+  //   lam^T B' q  = sum_{rows of p} Lambda_rb (-Q_p / (4 pi eps_p))
+  bool any0 = false;
+  for (int p = 0; p < pl.nreg; ++p) any0 = any0 || pl.prob.regions[p].kappa == 0.0;
+  if (any0) {
+    double* e = wsp<double>(pl, pl.o_z2);         // np_tot values
+    double* ones = e + pl.np_tot;                  // np_tot values (o_z2 holds 2 np_tot)
+    rc = launch_dk0_diag(pl, st, x, e);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_ones_f64, dim3(nblocks(pl.np_tot, T)), dim3(T), 0, st, ones, pl.np_tot);
+    PBTC_LAUNCH_CHECK();
+    std::vector<long long> tP, tL, tE;
+    for (int s = 0; s < pl.nsurf; ++s) {
+      const int64_t ns = pl.pan_off[s + 1] - pl.pan_off[s];
+      tP.insert(tP.end(), {(long long)pl.pan_off[s], (long long)(pl.unk_off[s] + ns), (long long)ns});
+    }
+    for (const RowBlock& rb : pl.rows) {
+      tL.insert(tL.end(), {(long long)rb.row_off, 0LL, (long long)rb.n});
+      tE.insert(tE.end(), {(long long)rb.row_off, (long long)pl.pan_off[rb.t], (long long)rb.n});
+    }
+    std::vector<double> Psi, Lam, Ed;
+    rc = pair_dots(pl, st, tP, wsp<double>(pl, pl.o_area), x, &Psi);
+    if (!rc) rc = pair_dots(pl, st, tL, lam, ones, &Lam);
+    if (!rc) rc = pair_dots(pl, st, tE, lam, e, &Ed);
+    if (rc) return rc;
+    for (int p = 0; p < pl.nreg; ++p) {
+      const Region& R = pl.prob.regions[p];
+      if (R.kappa != 0.0) continue;
+      double Qp = 0.0;
+      for (double v : pl.prob.charges[p].q) Qp += v;
+      double qSx = 0.0, lAx = 0.0, lBq = 0.0;
+      for (const RowBlock& rb : pl.reac_rows)
+        if (rb.r == p)
+          for (const RowTerm& t : rb.terms) qSx += Qp * t.sigma_c * (-Psi[pl.blocks[t.block].s] * kInv4Pi);
+      for (size_t i = 0; i < pl.rows.size(); ++i) {
+        const RowBlock& rb = pl.rows[i];
+        if (rb.r != p) continue;
+        for (const RowTerm& t : rb.terms) {
+          const int s = pl.blocks[t.block].s;
+          lAx += -t.sigma_c * (-Psi[s] * kInv4Pi * Lam[i] + (s == rb.t ? Ed[i] : 0.0));
+        }
+        lBq += Lam[i] * (-Qp * kInv4Pi / R.eps);
+      }
+      dkap[p] = 0.5 * C * (qSx - lAx + lBq);
+    }
   }
   // restore the forward outputs of x (phi_reac on the device)
   rc = apply_operator(pl, st, x, wsp<double>(pl, pl.o_phi_reac), PBTC_FP64, 1);

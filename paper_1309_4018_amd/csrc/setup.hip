@@ -524,8 +524,10 @@ __device__ __forceinline__ void kern64(double kappa, double dx, double dy, doubl
 // semi-analytic self integral of G over panel p at its centroid (sec. 2.3,
 // singular integrals after Zhu et al.): three sub-triangles at the centroid,
 // closed-form radial integral, N_k-point Gauss-Legendre in the angle
+// (dk0: instead the derivative in kappa at kappa = 0 of the same rule, whose
+// radial part is d/dkappa (1 - exp(-kappa rho)) / kappa = -rho^2 / 2 there)
 __device__ double self_integral(const Tables& T, const double* A, const double* B, const double* C,
-                                double cx, double cy, double cz, double kappa) {
+                                double cx, double cy, double cz, double kappa, bool dk0 = false) {
   const double* v[3] = {A, B, C};
   double total = 0.0;
   for (int e = 0; e < 3; ++e) {
@@ -545,7 +547,7 @@ __device__ double self_integral(const Tables& T, const double* A, const double* 
     for (int k = 0; k < T.Nk; ++k) {
       const double th = mid + half * T.glx[k];
       const double rho = h / cos(th);
-      const double rad = kappa == 0.0 ? rho : -expm1(-kappa * rho) / kappa;
+      const double rad = dk0 ? -0.5 * rho * rho : kappa == 0.0 ? rho : -expm1(-kappa * rho) / kappa;
       s += T.glw[k] * rad;
     }
     total += half * s;
@@ -656,6 +658,27 @@ __global__ void k_prec_blocks(Tables T, int64_t np, const int* __restrict__ vert
   inv[4 * p + 1] = vI * id;
   inv[4 * p + 2] = -0.5 * id;
   inv[4 * p + 3] = 0.5 * id;
+}
+
+// Per panel p, for the kappa derivative at kappa = 0 (where d G / d kappa is
+// the constant -1/(4 pi) and the double-layer derivative vanishes):
+// e_p = (V'_pp + A_p / (4 pi)) psi_p, V'_pp the kappa derivative of the self
+// integral (times 1/(4 pi)); with the far and near entries -A_j / (4 pi) of
+// every other panel this is the diagonal remainder of V' psi.
+__global__ void k_dk0_diag(Tables T, int64_t np, const int* __restrict__ verts_tri,
+                           const double* __restrict__ verts, const long long* __restrict__ vbase,
+                           const int* __restrict__ pan_surf, const double* __restrict__ cx,
+                           const double* __restrict__ cy, const double* __restrict__ cz,
+                           const double* __restrict__ area, const int* __restrict__ pidx,
+                           const double* __restrict__ x, double* __restrict__ e) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const long long vb = vbase[pan_surf[p]];
+  const double* A = verts + 3 * (vb + verts_tri[3 * p + 0]);
+  const double* B = verts + 3 * (vb + verts_tri[3 * p + 1]);
+  const double* C = verts + 3 * (vb + verts_tri[3 * p + 2]);
+  const double vd = self_integral(T, A, B, C, cx[p], cy[p], cz[p], 0.0, true) * kInv4Pi;
+  e[p] = (vd + area[p] * kInv4Pi) * x[pidx[2 * p + 1]];
 }
 
 // ---------------------------------------------------------------------- rhs
@@ -1318,6 +1341,25 @@ int launch_precond(pbtc_plan_t& pl, hipStream_t st) {
                      wsp<int>(pl, pl.o_tris), wsp<double>(pl, pl.o_verts), near_vbase(pl),
                      wsp<int>(pl, pl.o_pan_surf), wsp<double>(pl, pl.o_cx), wsp<double>(pl, pl.o_cy),
                      wsp<double>(pl, pl.o_cz), ptab, wsp<double>(pl, pl.o_pinv));
+  PBTC_LAUNCH_CHECK();
+  return PBTC_OK;
+}
+
+// e (np_tot values) of k_dk0_diag for the unknown vector x (device).
+int launch_dk0_diag(pbtc_plan_t& pl, hipStream_t st, const double* x, double* e) {
+  Tables tb;
+  tb.K = pl.prm.K;
+  tb.Kf = pl.prm.K_fine;
+  tb.Nk = pl.prm.N_k;
+  for (int i = 0; i < tb.Nk; ++i) {
+    tb.glx[i] = pl.gl_x[i];
+    tb.glw[i] = pl.gl_w[i];
+  }
+  hipLaunchKernelGGL(k_dk0_diag, dim3(nblocks(pl.np_tot, 128)), dim3(128), 0, st, tb, pl.np_tot,
+                     wsp<int>(pl, pl.o_tris), wsp<double>(pl, pl.o_verts), near_vbase(pl),
+                     wsp<int>(pl, pl.o_pan_surf), wsp<double>(pl, pl.o_cx), wsp<double>(pl, pl.o_cy),
+                     wsp<double>(pl, pl.o_cz), wsp<double>(pl, pl.o_area), wsp<int>(pl, pl.o_pidx),
+                     x, e);
   PBTC_LAUNCH_CHECK();
   return PBTC_OK;
 }

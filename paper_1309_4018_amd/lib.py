@@ -250,6 +250,7 @@ class Plan:
         self.n_surfaces, self.n_regions = n_s.value, n_r.value
         self.problem_sizes = list(getattr(problem, "surface_sizes", []))
         self.last = Result()
+        self.solve_count = 0  # completed solves (the autograd wrapper checks it)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -288,6 +289,8 @@ class Plan:
         code, res = self._call_growing(
             lambda p, n, r: self.lib.pbtc_solve(self.h, p, n, self.stream, int(force_setup),
                                                 C.byref(r)))
+        if code in (OK, ENOCONV):
+            self.solve_count += 1
         if not (allow_noconv and code == ENOCONV):
             check(code, self.h)
         return res.as_dict()
@@ -392,6 +395,9 @@ class Plan:
                                           self.stream, float(gE), _ptr(dq), _ptr(dk), _ptr(de),
                                           C.byref(res))
             if code == EWORKSPACE and res.workspace_needed > self.ws.numel():
+                # the transposed operator needs more room: the forward solve of
+                # the same charges (pbtc_backward accepts no others) is redone
+                # on the larger workspace
                 self._alloc(res.workspace_needed)
                 self.solve()
                 continue

@@ -60,7 +60,8 @@ def test_backward_direct_matches_oracle(sphere, gpu_lib):
     assert _rel(dq, g["dE_dq"]) < 1e-8
     assert abs(dk[1] - g["dE_dkappa"][1]) < 1e-6 * abs(g["dE_dkappa"][1])
     assert _rel(de, g["dE_deps"]) < 1e-8
-    assert dk[0] == 0.0  # Laplace region
+    # Laplace region: dG/dkappa = -1/(4 pi) at kappa = 0 (nonzero derivative)
+    assert abs(dk[0] - g["dE_dkappa"][0]) < 1e-8 * abs(g["dE_dkappa"][0])
 
 
 def test_backward_treecode_fp32_refined(sphere, gpu_lib):
@@ -72,6 +73,7 @@ def test_backward_treecode_fp32_refined(sphere, gpu_lib):
     dq, dk, de = pl.backward()
     assert _rel(dq, g["dE_dq"]) < 1e-4
     assert abs(dk[1] - g["dE_dkappa"][1]) < 1e-3 * abs(g["dE_dkappa"][1])
+    assert abs(dk[0] - g["dE_dkappa"][0]) < 1e-4 * abs(g["dE_dkappa"][0])
     assert _rel(de, g["dE_deps"]) < 1e-4
 
 
@@ -107,6 +109,16 @@ def test_backward_vs_gpu_finite_differences(gpu_lib):
         ek.append(lib.plan_for(p2, **kw).solve()["energy_kJmol"])
     fd = (ek[0] - ek[1]) / (2 * h)
     assert abs(dk[2] - fd) < 1e-6 * abs(fd)
+    assert _rel(dk, ref["dE_dkappa"]) < 1e-7  # kappa = 0 regions included
+    # kappa of a Laplace region: one-sided difference from kappa = 0 (the
+    # library takes kappa >= 0), error O(h)
+    ek0 = []
+    for hh in (h, 2 * h):
+        p2 = copy.deepcopy(prob)
+        p2.regions[1].kappa = hh
+        ek0.append(lib.plan_for(p2, **kw).solve()["energy_kJmol"])
+    fd1 = (4 * ek0[0] - ek0[1] - 3 * e0) / (2 * h)  # second-order one-sided
+    assert abs(dk[1] - fd1) < 1e-4 * abs(dk[1])
     for r in range(3):
         ee = []
         for sg in (1, -1):
@@ -126,7 +138,8 @@ def test_multisurface_backward(gpu_lib):
     pl.solve()
     dq, dk, de = pl.backward()
     assert _rel(dq, ref["dE_dq"]) < 1e-7
-    assert abs(dk[2] - ref["dE_dkappa"][2]) < 1e-5 * abs(ref["dE_dkappa"][2])
+    for r in range(len(prob.regions)):  # kappa = 0 regions included
+        assert abs(dk[r] - ref["dE_dkappa"][r]) < 1e-5 * abs(ref["dE_dkappa"][r]), r
     assert _rel(de, ref["dE_deps"]) < 1e-7
 
 
@@ -145,9 +158,8 @@ def test_shared_kappa_regions_backward(gpu_lib):
     dq, dk, de = pl.backward()
     assert _rel(dq, ref["dE_dq"]) < 1e-8
     assert _rel(de, ref["dE_deps"]) < 1e-8
-    for r in (1, 2):
+    for r in (0, 1, 2):
         assert abs(dk[r] - ref["dE_dkappa"][r]) < 1e-6 * abs(ref["dE_dkappa"][r]), r
-    assert dk[0] == 0.0
 
 
 def test_autograd_wrapper(sphere, gpu_lib):
@@ -164,3 +176,24 @@ def test_autograd_wrapper(sphere, gpu_lib):
     assert abs(e.item() - g["energy"]) < 1e-9 * abs(g["energy"])
     assert _rel(q.grad.numpy(), 2.0 * g["dE_dq"]) < 1e-8
     assert "dE_dkappa" in pl.last_param_grads
+
+
+def test_autograd_two_forwards_one_plan(sphere, gpu_lib):
+    """Two energies of one plan in one graph: each term's gradient belongs to
+    its own charges (backward re-solves for the charges its forward used)."""
+    import torch
+
+    from paper_1309_4018_amd import lib
+    from paper_1309_4018_amd.autograd import solvation_energy
+
+    prob, o, g = sphere
+    pl = lib.plan_for(prob, op="direct", precision="fp64", tol=1e-12)
+    q1 = torch.tensor(prob.charges[0][1], dtype=torch.float64, requires_grad=True)
+    q2 = torch.tensor(0.5 * prob.charges[0][1] + 0.1, dtype=torch.float64, requires_grad=True)
+    (solvation_energy(q1, pl) + solvation_energy(q2, pl)).backward()
+    # the energy is quadratic in q: dE/dq is linear, dE/dq(q) = G q
+    assert _rel(q1.grad.numpy(), g["dE_dq"]) < 1e-8
+    p2 = copy.deepcopy(prob)
+    p2.charges[0] = (prob.charges[0][0], q2.detach().numpy())
+    g2 = gradients(Oracle(p2))
+    assert _rel(q2.grad.numpy(), g2["dE_dq"]) < 1e-8

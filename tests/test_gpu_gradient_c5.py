@@ -10,9 +10,16 @@ two cavities) at 5,120 + 5,120 + 2 x 512 panels and 4,000 charges.
   rounding and the solve tolerance (1e-11): 1e-6 relative.
 * The FP32-refined treecode adjoint (theta 0.5, P 8) against the direct
   FP64 gradients: 2e-3 relative (treecode truncation of two solves).
+* Both against the dense FP64 oracle's exact discrete gradient of the same
+  system (22,528 unknowns; stored by tests/golden/make_c5_gradient.py):
+  dE/dq of all 4,000 charges, dE/dkappa and dE/deps of every region (the
+  Laplace regions' kappa derivatives included), 1e-6 for the direct FP64
+  operator and 2e-3 for the treecode.
 """
 
 import copy
+import json
+import os
 
 import numpy as np
 import pytest
@@ -22,6 +29,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 EPS_OUT = ("stern", "solvent", "cavity1", "cavity2")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "c5_gradient.json")
 
 
 @pytest.fixture(scope="module")
@@ -87,16 +95,49 @@ def test_kappa_and_eps_out_fd(c5, direct):
     assert abs(grad - fd) < 1e-5 * abs(fd)
 
 
-def test_treecode_adjoint_matches_direct(c5, direct):
+@pytest.fixture(scope="module")
+def tree(c5, gpu_lib):
     from paper_1309_4018_amd import lib
 
-    _, _, dq, dk, de = direct
     pl = lib.plan_for(c5, precision="fp32_refined", tol=1e-8, theta=0.5, P=8, max_iter=5000,
                       precond="block_diag")
     pl.solve()
-    tq, tk, te = pl.backward()
+    return pl.backward()
+
+
+def test_treecode_adjoint_matches_direct(c5, direct, tree):
+    _, _, dq, dk, de = direct
+    tq, tk, te = tree
     assert np.max(np.abs(tq - dq)) < 2e-3 * np.max(np.abs(dq))
-    s = [i for i, r in enumerate(c5.regions) if r.kappa > 0]
-    for i in s:
-        assert abs(tk[i] - dk[i]) < 2e-3 * abs(dk[i])
+    for i in range(len(c5.regions)):
+        assert abs(tk[i] - dk[i]) < 2e-3 * abs(dk[i]), i
     assert np.max(np.abs(te - de)) < 2e-3 * np.max(np.abs(de))
+
+
+def _gold(c5):
+    g = json.load(open(GOLD))
+    assert g["regions"] == [r.name for r in c5.regions]
+    assert g["n_charges"] == 4000 and g["n_unknowns"] == 22528
+    return g
+
+
+def test_direct_gradient_matches_dense_oracle(c5, direct):
+    g = _gold(c5)
+    pl, e0, dq, dk, de = direct
+    assert abs(e0 - g["energy_kJmol"]) < 1e-9 * abs(g["energy_kJmol"])
+    ref_q = np.array(g["dE_dq"])
+    assert np.max(np.abs(dq - ref_q)) < 1e-6 * np.max(np.abs(ref_q))
+    for i in range(len(c5.regions)):
+        assert abs(dk[i] - g["dE_dkappa"][i]) < 1e-6 * abs(g["dE_dkappa"][i]), i
+        assert abs(de[i] - g["dE_deps"][i]) < 1e-6 * abs(g["dE_deps"][i]), i
+
+
+def test_treecode_gradient_matches_dense_oracle(c5, tree):
+    g = _gold(c5)
+    tq, tk, te = tree
+    ref_q = np.array(g["dE_dq"])
+    assert np.max(np.abs(tq - ref_q)) < 2e-3 * np.max(np.abs(ref_q))
+    for i in range(len(c5.regions)):
+        assert abs(tk[i] - g["dE_dkappa"][i]) < 2e-3 * abs(g["dE_dkappa"][i]), i
+    ref_e = np.array(g["dE_deps"])
+    assert np.max(np.abs(te - ref_e)) < 2e-3 * np.max(np.abs(ref_e))

@@ -1,0 +1,169 @@
+"""GPU parity of the less common paths, through the C interface.
+
+* Quadrature options of the parameter tables (sec. 3): K = 1, 3, 7 Gauss
+  points per panel, K_fine = 7 and thres = 1.25 (the lysozyme table), each
+  against the oracle's dense matrix with the same options (direct FP64
+  operator, 1e-12).
+* Near-field columns found by the second (filling) traversal: a restart
+  length of 1 leaves too little Krylov-basis room for the one-traversal
+  slots, so the set-up takes the other path; the matrix must not change.
+* GMRES stopped by max_iter: PBTC_ENOCONV with the iterations' history and
+  finite outputs.  Zero charges: x = 0 after no iteration, energy 0.
+* pbtc_solve_batch: n plans on one workspace equal n separate solves; a
+  member's charge change reaches the next batch call; members keep working
+  on their own workspaces.
+* Two plans sharing one workspace: each solve rebuilds what the other
+  overwrote; device calls on a workspace another plan set up are refused.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Oracle, Params
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    return synth.config1_kirkwood_sphere(nu=8)
+
+
+@pytest.mark.parametrize("K,K_fine,thres", [(1, 19, 2.0), (3, 19, 2.0), (7, 19, 2.0),
+                                             (4, 7, 2.0), (4, 19, 1.25), (7, 7, 1.25)])
+def test_quadrature_options_match_oracle(sphere, gpu_lib, K, K_fine, thres):
+    from paper_1309_4018_amd import lib
+
+    o = Oracle(sphere, Params(k=K, k_fine=K_fine, thres=thres))
+    A = o.matrix()
+    x = np.random.default_rng(K * 100 + K_fine).normal(size=o.n)
+    pl = lib.plan_for(sphere, op="direct", precision="fp64", K=K, K_fine=K_fine, thres=thres)
+    pl.setup()
+    assert _rel(pl.matvec(x, lib.FP64).cpu().numpy(), A @ x) < 1e-12
+    assert _rel(pl.matvec(x, lib.FP64, transpose=True).cpu().numpy(), A.T @ x) < 1e-12
+    assert _rel(pl.rhs().cpu().numpy(), o.rhs()) < 1e-13
+    # the treecode with the same options agrees to its truncation level
+    pt = lib.plan_for(sphere, K=K, K_fine=K_fine, thres=thres, theta=0.5, P=8)
+    pt.setup()
+    assert _rel(pt.matvec(x, lib.FP64).cpu().numpy(), A @ x) < 1e-4
+
+
+def test_near_field_filling_traversal(gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    prob = synth.config3_multisurface(nu=4, cav_nu=2, n_charges=20)
+    o = Oracle(prob)
+    A = o.matrix()
+    x = np.random.default_rng(2).normal(size=o.n)
+    ref = lib.plan_for(prob, op="direct", precision="fp64")
+    r_ref = ref.setup()
+    small = lib.plan_for(prob, op="direct", precision="fp64", restart=1)
+    r_small = small.setup()
+    assert r_small["n_near_entries"] == r_ref["n_near_entries"] > 0
+    assert _rel(small.matvec(x, lib.FP64).cpu().numpy(), A @ x) < 1e-12
+    assert _rel(small.matvec(x, lib.FP64, transpose=True).cpu().numpy(), A.T @ x) < 1e-12
+
+
+def test_max_iter_gives_enoconv(sphere, gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    pl = lib.plan_for(sphere, precision="fp64", tol=1e-12, max_iter=3)
+    with pytest.raises(lib.PbtcError) as ei:
+        pl.solve()
+    assert ei.value.code == lib.ENOCONV
+    res = pl.solve(allow_noconv=True)
+    assert res["converged"] == 0 and res["n_iter"] == 3
+    h = pl.history()
+    assert len(h) == 3 and np.all(np.isfinite(h)) and h[-1] < 1.0
+    x = pl.solution()
+    assert np.all(np.isfinite(x)) and np.max(np.abs(x)) > 0
+    assert np.isfinite(res["energy_kJmol"]) and np.all(np.isfinite(pl.phi_reac()))
+    assert res["final_rel_res"] > 1e-12
+
+
+def test_zero_charges(sphere, gpu_lib):
+    from paper_1309_4018_amd import lib
+
+    prob = synth.config1_kirkwood_sphere(nu=8)
+    x, q = prob.charges[0]
+    prob.charges[0] = (x, np.zeros_like(q))
+    for prec in ("fp64", "fp32_refined"):
+        pl = lib.plan_for(prob, precision=prec)
+        res = pl.solve()
+        assert res["converged"] == 1 and res["n_iter"] == 0
+        assert res["energy_kJmol"] == 0.0
+        assert np.all(pl.solution() == 0.0)
+        assert np.all(pl.phi_reac() == 0.0)
+
+
+def _members():
+    return [synth.config1_kirkwood_sphere(nu=4), synth.config1_kirkwood_sphere(nu=8, seed=7),
+            synth.config3_multisurface(nu=4, cav_nu=2, n_charges=20)] + \
+        synth.config4_batch(n_mol=2, nu_cap=8)
+
+
+@pytest.mark.parametrize("mode", ["direct_fp64", "treecode_fp32_refined"])
+def test_solve_batch_equals_single_solves(gpu_lib, mode):
+    from paper_1309_4018_amd import lib
+
+    prm = dict(op="direct", precision="fp64", tol=1e-11) if mode == "direct_fp64" else \
+        dict(precision="fp32_refined", tol=1e-7, theta=0.5, P=8)
+    mols = _members()
+    plans = [lib.plan_for(m, **prm) for m in mols]
+    batch = lib.Batch(plans)
+    res = batch.solve()
+    singles = [lib.plan_for(m, **prm) for m in mols]
+    tol_e, tol_x = (1e-10, 1e-9) if mode == "direct_fp64" else (2e-6, 2e-5)
+    for p, s, r in zip(plans, singles, res):
+        rs = s.solve()
+        assert r["converged"] == 1
+        assert abs(r["energy_kJmol"] - rs["energy_kJmol"]) < tol_e * abs(rs["energy_kJmol"])
+        assert _rel(p.solution(), s.solution()) < tol_x
+        assert _rel(p.phi_reac(), s.phi_reac()) < tol_x
+    if mode != "direct_fp64":
+        return
+    # a member's new charges reach the next batch call (the merged plan is reused)
+    q1 = 2.0 * mols[1].charges[0][1]
+    plans[1].set_charge_values(q1)
+    res2 = batch.solve()
+    assert abs(res2[1]["energy_kJmol"] - 4.0 * res[1]["energy_kJmol"]) < 1e-9 * abs(res[1]["energy_kJmol"])
+    assert abs(res2[0]["energy_kJmol"] - res[0]["energy_kJmol"]) < 1e-10 * abs(res[0]["energy_kJmol"])
+    # the gradient needs the member's own solve
+    with pytest.raises(lib.PbtcError) as ei:
+        plans[0].backward()
+    assert ei.value.code == lib.EINVAL
+    plans[0].solve()
+    dq, _, _ = plans[0].backward()
+    sdq, _, _ = singles[0].backward()
+    assert _rel(dq, sdq) < 1e-9
+
+
+def test_shared_workspace_between_plans(sphere, gpu_lib):
+    import ctypes as C
+
+    import torch
+
+    from paper_1309_4018_amd import lib
+
+    other = synth.config1_kirkwood_sphere(nu=4, seed=9)
+    pa = lib.plan_for(sphere, op="direct", precision="fp64", tol=1e-11)
+    pb = lib.plan_for(other, op="direct", precision="fp64", tol=1e-11)
+    ea = pa.solve()["energy_kJmol"]
+    eb = pb.solve()["energy_kJmol"]
+    ws = torch.empty(max(pa.ws.numel(), pb.ws.numel()), dtype=torch.uint8, device="cuda:0")
+    pa.ws = ws
+    pb.ws = ws
+    assert abs(pa.solve()["energy_kJmol"] - ea) < 1e-12 * abs(ea)
+    assert abs(pb.solve()["energy_kJmol"] - eb) < 1e-12 * abs(eb)
+    # pa's state was overwritten by pb: device calls are refused, a solve rebuilds
+    x = torch.zeros(pa.n_unknowns, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    code = pa.lib.pbtc_matvec(pa.h, C.c_void_p(ws.data_ptr()), pa.stream,
+                              C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), lib.FP64)
+    assert code == lib.EINVAL
+    assert abs(pa.solve()["energy_kJmol"] - ea) < 1e-12 * abs(ea)
