@@ -118,13 +118,20 @@ typedef struct {
   int max_refine;   /* FP32_REFINED: maximum outer refinement steps */
   int validate_charges; /* 1: check every charge lies inside its region */
   int profile;      /* n > 0: time the P2P and M2P kernel launches of every
-                       n-th evaluation of the FP32 operator (A x) with HIP
-                       events on the caller's stream (pbtc_result.t_p2p_s
-                       ...); 0: off.  Other evaluations run the moment pass
-                       on a second stream beside P2P; a timed one runs it
-                       first, so that each timed launch has the GPU alone */
+                       n-th evaluation of the FP32 operator (A x, and A^T x
+                       in pbtc_backward) with HIP events on the caller's
+                       stream (pbtc_result.t_kernel_s ...); 0: off.  Other
+                       evaluations run the moment pass on a second stream
+                       beside P2P (and replay the launch graph); a timed one
+                       launches kernel by kernel with the moment pass first,
+                       so that each timed launch has the GPU alone */
   int precond;      /* PBTC_PREC_NONE or PBTC_PREC_BLOCK_DIAG (forward and
                        adjoint solves) */
+  int op_graph;     /* 1: every evaluation of A x (all surface-pair blocks of
+                       all regions and systems) is replayed as ONE captured
+                       HIP launch graph of its kernels, captured once per
+                       set-up and precision; 0: the kernels are launched one
+                       by one (same kernels, same results bit for bit) */
 } pbtc_params;
 
 typedef struct {
@@ -161,6 +168,18 @@ typedef struct {
    * the host while the GPU computes the near-field values, preconditioner
    * blocks and Coulomb right-hand side, [5] the rest of that GPU work */
   double t_setup_phase_s[6];
+  /* kernels of one evaluation of the FP32 operator A x (the nodes of its
+   * launch graph) and how many evaluations replayed the graph in the call */
+  int op_kernels;
+  int op_graph_launches;
+  /* with params.profile, per kernel kind -- [0] P2P, [1] Laplace M2P,
+   * [2] Yukawa M2P of the FP32 A x (pbtc_solve), [3] P2P, [4] Laplace M2P,
+   * [5] Yukawa M2P of the FP32 A^T x (pbtc_backward) -- the summed HIP-event
+   * seconds, the timed launches and their algorithmic floating-point
+   * operations (FMA = 2, a transcendental = 1) */
+  double t_kernel_s[6];
+  int n_kernel_launch[6];
+  double kernel_flop[6];
 } pbtc_result;
 
 /* Library version; never fails. */
@@ -184,7 +203,8 @@ int pbtc_set_charges(pbtc_problem* p, int region_id, const double* xyz, const do
 /* Defaults: K=4, K_fine=19, N_k=5, thres=2.0, theta=0.5, P=6, ncrit=0,
  * direct_below=-1, tol=1e-5, restart=100, max_iter=1000,
  * precision=PBTC_FP32_REFINED, op=PBTC_OP_TREECODE, inner_tol=1e-6,
- * max_refine=10, validate_charges=1, profile=0, precond=PBTC_PREC_NONE. */
+ * max_refine=10, validate_charges=1, profile=0, precond=PBTC_PREC_NONE,
+ * op_graph=1. */
 int pbtc_params_default(pbtc_params* prm);
 
 /* Host-side checks only (no device work): parameter ranges; every region is

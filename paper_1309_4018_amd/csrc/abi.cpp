@@ -31,6 +31,7 @@ int apply_precond(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, b
                   bool accumulate);
 double wall_seconds();
 int device_coulomb(pbtc_plan_t& pl, hipStream_t st, double* total, double* per_system);
+void release_op_graphs(pbtc_plan_t& pl);
 
 // The merged problem of a pbtc_solve_batch call and where each member's
 // regions, systems, unknowns and charges sit in it.
@@ -212,7 +213,7 @@ bool same_params(const pbtc_params& a, const pbtc_params& b) {
          a.max_iter == b.max_iter && a.precision == b.precision && a.op == b.op &&
          a.inner_tol == b.inner_tol && a.max_refine == b.max_refine &&
          a.validate_charges == b.validate_charges && a.profile == b.profile &&
-         a.precond == b.precond;
+         a.precond == b.precond && a.op_graph == b.op_graph;
 }
 
 // The merged plan of a batch (kept with plans[0] while the members stay the
@@ -374,6 +375,7 @@ int pbtc_params_default(pbtc_params* prm) {
   prm->validate_charges = 1;
   prm->profile = 0;
   prm->precond = PBTC_PREC_NONE;
+  prm->op_graph = 1;
   return PBTC_OK;
 }
 
@@ -408,7 +410,9 @@ pbtc_plan_s::~pbtc_plan_s() {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : {ev_fork, ev_join})
     if (e) (void)hipEventDestroy(e);
+  release_op_graphs(*this);
   if (side) (void)hipStreamDestroy(side);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (res_pin) (void)hipHostFree(res_pin);
   delete batch;
 }

@@ -342,12 +342,15 @@ __global__ __launch_bounds__(kAMomThreads) void k_adj_p2m_chunk(
   }
 }
 
-// mom[pair.x] = sum of the pair's chunks [pair.y, pair.z), in order
+// mom[pair.x] = sum of the pair's chunks [pair.y, pair.z), in order, in the
+// layout the transposed M2P reads: [mS_k (|k| <= P) | G_1,k | G_2,k | G_3,k
+// (|k| <= P + 1)] with G_j,k = k_j mD_{k - e_j} (0 where k_j = 0)
 template <typename real, int P>
 __global__ __launch_bounds__(256) void k_adj_mom_sum(const int4* __restrict__ pairs,
                                                      const real* __restrict__ part,
                                                      real* __restrict__ mom) {
-  constexpr int N2 = 2 * ncoef(P);
+  constexpr int N = ncoef(P), N2 = 2 * N, N1 = ncoef(P + 1), MS = adj_mom_len(P);
+  __shared__ real sm[N2];
   const int4 pr = pairs[blockIdx.x];
   for (int k = threadIdx.x; k < N2; k += 256) {
     real v = 0;
@@ -359,169 +362,22 @@ __global__ __launch_bounds__(256) void k_adj_mom_sum(const int4* __restrict__ pa
       v += (a[0] + a[1]) + (a[2] + a[3]);
     }
     for (; j < pr.z; ++j) v += part[(size_t)j * N2 + k];
-    mom[(size_t)pr.x * N2 + k] = v;
+    sm[k] = v;
   }
-}
-
-struct AdjArgs {
-  const int4* units;
-  int nunits;
-  const int* item_block;
-  const DevBlock* blocks;
-  const int* cells_list;
-  const Cell* cells;
-};
-
-// target Gauss point (x, y, z, normal) against sources (mu weights):
-// acc[0/2] += muS G, acc[1/3] += muD (n . grad_y G), grad_y G with d = x_src - y
-template <typename real, int KS>
-__device__ __forceinline__ void adj_pair(const Src<real>& t, const Src<real>& s, real k0, real k1,
-                                         real (&acc)[4]) {
-  const real dx = s.x - t.x, dy = s.y - t.y, dz = s.z - t.z;
-  const real r2 = dx * dx + dy * dy + dz * dz;
-  const real rinv = r2 > real(0) ? rsqrt_(r2) : real(0);
-  const real dn = t.px * dx + t.py * dy + t.pz * dz;
-  const real r3 = rinv * rinv * rinv;
-  if (KS == KS_L || KS == KS_LY) {
-    acc[0] += s.q * rinv;
-    acc[1] += s.px * dn * r3;
-  }
-  if (KS == KS_Y || KS == KS_YY) {
-    const real r = r2 * rinv;
-    const real e = exp_neg(k0 * r);
-    acc[0] += s.q * e * rinv;
-    acc[1] += s.px * dn * r3 * e * (real(1) + k0 * r);
-  }
-  if (KS == KS_LY || KS == KS_YY) {
-    const real kap = k1;
-    const real r = r2 * rinv;
-    const real e = exp_neg(kap * r);
-    acc[2] += s.py * e * rinv;
-    acc[3] += s.pz * dn * r3 * e * (real(1) + kap * r);
-  }
-}
-
-template <int KS>
-constexpr int nacc2() {
-  return KS == KS_L || KS == KS_Y ? 2 : 4;
-}
-
-template <typename real, int KS>
-__global__ __launch_bounds__(kT) void k_adj_p2p(AdjArgs a, const Src<real>* __restrict__ gpos,
-                                                const Src<real>* __restrict__ asrc,
-                                                real* __restrict__ partial) {
-  const int u = uni(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
-  if (u >= a.nunits) return;
-  const int4 un = a.units[u];
-  const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
-  const DevBlock& b = a.blocks[uni(a.item_block[item])];
-  const long long g = item - b.aitem_off;
-  const long long j0 = b.gp_off + g * kGroup;
-  const int nt = (int)min((long long)kGroup, b.gp_n - g * kGroup);
-  const int lane = threadIdx.x & 63;
-  const Src<real> t = gpos[j0 + min(lane, nt - 1)];
-  const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
-  const long long soff = b.nf_row - b.tgt_off;
-  real acc[4] = {0, 0, 0, 0};
-  for (int e = e0; e < e1; ++e) {
-    const int c = uni(a.cells_list[e]);
-    const int beg = uni(a.cells[c].begin), end = beg + uni(a.cells[c].count);
-    for (int j = beg; j < end; ++j) {
-      const Src<real> s = asrc[soff + j];
-      adj_pair<real, KS>(t, s, k0, k1, acc);
+  __syncthreads();
+  real* out = mom + (size_t)pr.x * MS;
+  for (int k = threadIdx.x; k < N; k += 256) out[k] = sm[k];
+  for (int i = threadIdx.x; i < 3 * N1; i += 256) {
+    const int d = i / N1, k = i - d * N1;
+    int c[3];
+    mindex_inv(k, c[0], c[1], c[2]);
+    real v = 0;
+    if (c[d] > 0) {
+      c[d] -= 1;
+      v = real(c[d] + 1) * sm[N + mindex(c[0], c[1], c[2])];
     }
+    out[N + i] = v;
   }
-  const int lane_ = threadIdx.x & 63;
-#pragma unroll
-  for (int q = 0; q < nacc2<KS>(); ++q) partial[((size_t)u * 4 + q) * 64 + lane_] = acc[q];
-}
-
-// Coefficients to order P + 1 about the cell centre x_c of the sources,
-// target y: potential sum_{|k|<=P} a_k mS_k and
-// n . gradient = -sum_k sum_d n_d k_d a_k mD_{k - e_d}.
-template <int P, typename real, int KIND>
-__device__ __forceinline__ void taylor_adj(real dx, real dy, real dz, real rinv, real e,
-                                           real kappa, real nx, real ny, real nz,
-                                           const real* __restrict__ M, real& s, real& f) {
-  constexpr int N1 = MultiIndex<P + 1>::N;
-  constexpr int N = ncoef(P);
-  const real r2inv = rinv * rinv;
-  real a[N1], bb[KIND ? N1 : 1];
-  a[0] = KIND ? e * rinv : rinv;
-  if constexpr (KIND) bb[0] = e;
-  s += a[0] * M[0];
-  static_for<N1 - 1>([&](auto kc) {
-    constexpr int k = decltype(kc)::value + 1;
-    constexpr MultiIndex<P + 1> T{};
-    coef_step<P + 1, k, KIND != 0, real>(a, KIND ? bb : a, dx, dy, dz, r2inv, kappa);
-    if constexpr (T.n[k] <= P) s += a[k] * M[k];
-    constexpr int j0 = T.m1[k][0], j1 = T.m1[k][1], j2 = T.m1[k][2];
-    real g = real(0);
-    if constexpr (j0 >= 0) g += nx * real(T.k1[k]) * M[N + j0];
-    if constexpr (j1 >= 0) g += ny * real(T.k2[k]) * M[N + j1];
-    if constexpr (j2 >= 0) g += nz * real(T.k3[k]) * M[N + j2];
-    f -= a[k] * g;
-  });
-}
-
-template <typename real, int P, int KIND>
-__global__ __launch_bounds__(kT) void k_adj_m2p(AdjArgs a, const Src<real>* __restrict__ gpos,
-                                                const real* __restrict__ mom, int ms,
-                                                int kslot, real* __restrict__ partial) {
-  constexpr int N = ncoef(P);
-  const int u = uni(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
-  if (u >= a.nunits) return;
-  const int4 un = a.units[u];
-  const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
-  const DevBlock& b = a.blocks[uni(a.item_block[item])];
-  const long long g = item - b.aitem_off;
-  const long long j0 = b.gp_off + g * kGroup;
-  const int nt = (int)min((long long)kGroup, b.gp_n - g * kGroup);
-  const int lane = threadIdx.x & 63;
-  const Src<real> t = gpos[j0 + min(lane, nt - 1)];
-  const real kap = (real)(kslot == 0 ? b.kappa0 : b.kappa1);
-  const real* base = mom + (size_t)(b.lslot0 + kslot) * 2 * N;
-  // double-buffered moment staging: the next cell's moments and centre are
-  // loaded into registers while the current cell is evaluated
-  constexpr int PER = (2 * N + 63) / 64;
-  __shared__ real smom[kWaves][2][2 * N];
-  const int wv = uni(threadIdx.x >> 6);
-  real pre[PER];
-  double pcx = 0, pcy = 0, pcz = 0;
-  auto fetch = [&](int e) {
-    const int c = uni(a.cells_list[e]);
-    const Cell& cl = a.cells[c];
-    pcx = cl.cx;
-    pcy = cl.cy;
-    pcz = cl.cz;
-    const real* Mg = base + (size_t)c * ms * 2 * N;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int k = lane + 64 * q;
-      pre[q] = k < 2 * N ? Mg[k] : real(0);
-    }
-  };
-  real s = 0, f = 0;
-  if (e0 < e1) fetch(e0);
-  int buf = 0;
-  for (int e = e0; e < e1; ++e) {
-    real* M = smom[wv][buf];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int k = lane + 64 * q;
-      if (k < 2 * N) M[k] = pre[q];
-    }
-    const real dx = t.x - (real)pcx, dy = t.y - (real)pcy, dz = t.z - (real)pcz;
-    wave_sync();  // this buffer is written; the other one was last read a cell ago
-    if (e + 1 < e1) fetch(e + 1);
-    const real r2 = dx * dx + dy * dy + dz * dz;
-    const real rinv = rsqrt_(r2);
-    const real ee = KIND ? exp_neg(kap * (r2 * rinv)) : real(1);
-    taylor_adj<P, real, KIND>(dx, dy, dz, rinv, ee, kap, t.px, t.py, t.pz, M, s, f);
-    buf ^= 1;
-  }
-  partial[((size_t)u * 4 + 0) * 64 + lane] = s;
-  partial[((size_t)u * 4 + 1) * 64 + lane] = f;
 }
 
 // per Gauss point of the item's group: aout[slot] (+)= sum over units / (4 pi)
@@ -799,6 +655,24 @@ int adjoint_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     std::vector<int4> units;
     std::vector<int> uptr;
     const bool tree = pl.prm.op == PBTC_OP_TREECODE;
+    // algorithmic operations of each launch (kernel timing)
+    for (int ph = 0; ph < 2; ++ph)
+      for (int ks = 0; ks < KS_COUNT; ++ks) {
+        double fp = 0.0, fm = 0.0;
+        for (int item : pl.aitem_list[ph][ks]) {
+          const int bi = pl.aitem_block[item];
+          const int s_ = pl.blocks[bi].s;
+          const int64_t g = item - pl.blk_aitem_off[bi];
+          const int64_t ngs = pl.gp_off[s_ + 1] - pl.gp_off[s_];
+          const double ntg = (double)std::min<int64_t>(kGroup, ngs - g * kGroup);
+          double src = 0.0;
+          for (long long e = np_[item]; e < np_[item + 1]; ++e) src += hc[nl[e]].count;
+          fp += ntg * src * adj_p2p_flop_per_pair(ks);
+          if (tree) fm += ntg * (double)(fp_[item + 1] - fp_[item]) * adj_m2p_flop_per_eval(pl.P, ks);
+        }
+        pl.alaunch_flop_p2p[ph][ks] = fp;
+        pl.alaunch_flop_m2p[ph][ks] = fm;
+      }
     for (int ph = 0; ph < 2; ++ph)
       for (int ks = 0; ks < KS_COUNT; ++ks)
         for (int kind = 0; kind < 2; ++kind) {
@@ -962,30 +836,15 @@ static int adj_upload_small(pbtc_plan_t& pl, hipStream_t st) {
   return PBTC_OK;
 }
 
+void prof_mark(pbtc_plan_t& pl, hipStream_t st, bool on, int kind, double flop, bool begin);
+void prof_collect(pbtc_plan_t& pl);
+
 template <typename real>
-static void launch_adj_m2p(pbtc_plan_t& pl, hipStream_t st, const AdjArgs& a, int grid,
-                           const Src<real>* gpos, const real* mom, int kind, int kslot,
-                           real* partial) {
-#define PBTC_AM2P(PP)                                                                         \
-  case PP:                                                                                    \
-    if (kind == 0)                                                                            \
-      hipLaunchKernelGGL((k_adj_m2p<real, PP, 0>), dim3(grid), dim3(kT), 0, st, a, gpos, mom, \
-                         pl.adj_ms, kslot, partial);                                          \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_adj_m2p<real, PP, 1>), dim3(grid), dim3(kT), 0, st, a, gpos, mom, \
-                         pl.adj_ms, kslot, partial);                                          \
-    break;
-  switch (pl.P) {
-    PBTC_AM2P(2)
-    PBTC_AM2P(4)
-    PBTC_AM2P(6)
-    PBTC_AM2P(8)
-    PBTC_AM2P(10)
-    default:
-      break;
-  }
-#undef PBTC_AM2P
-}
+void launch_adj_p2p(hipStream_t st, int ks, const UnitArgs& a, int grid, const Src<real>* gpos,
+                    const Src<real>* asrc, real* partial);
+template <typename real>
+void launch_adj_m2p(hipStream_t st, int P, const UnitArgs& a, int grid, const Src<real>* gpos,
+                    const real* mom, int ms, int kind, int kslot, real* partial);
 
 template <typename real>
 static int adj_moments(pbtc_plan_t& pl, hipStream_t st, int phase, real* mom) {
@@ -1031,6 +890,9 @@ template <typename real>
 static int transpose_impl(pbtc_plan_t& pl, hipStream_t st, const double* lam, double* z, int phase) {
   const int T = 256;
   const bool tree = pl.prm.op == PBTC_OP_TREECODE;
+  // every profile-th FP32 evaluation of A^T x times its P2P and M2P launches
+  const bool timed = sizeof(real) == 4 && phase == 0 && pl.prm.profile > 0 &&
+                     pl.aprof_count++ % pl.prm.profile == 0;
   double* muS = wsp<double>(pl, pl.o_mu_s);
   double* muD = wsp<double>(pl, pl.o_mu_d);
   const auto& slots = pl.slots[phase];
@@ -1068,7 +930,7 @@ static int transpose_impl(pbtc_plan_t& pl, hipStream_t st, const double* lam, do
   real* partial = wsp<real>(pl, pl.o_partial);
   double* aS = wsp<double>(pl, pl.o_aout_s);
   double* aD = wsp<double>(pl, pl.o_aout_d);
-  AdjArgs a;
+  UnitArgs a;
   a.item_block = wsp<int>(pl, pl.o_aitems);
   a.blocks = wsp<DevBlock>(pl, pl.o_blocks);
   a.cells = wsp<Cell>(pl, pl.o_tcells);
@@ -1084,12 +946,9 @@ static int transpose_impl(pbtc_plan_t& pl, hipStream_t st, const double* lam, do
       a.cells_list = wsp<int>(pl, pl.o_anear);
       const int grid = nblocks(us.n, kWaves);
       if (us.n > 0) {
-        switch (ks) {
-          case KS_L: hipLaunchKernelGGL((k_adj_p2p<real, KS_L>), dim3(grid), dim3(kT), 0, st, a, gpos, asrc, partial); break;
-          case KS_Y: hipLaunchKernelGGL((k_adj_p2p<real, KS_Y>), dim3(grid), dim3(kT), 0, st, a, gpos, asrc, partial); break;
-          case KS_LY: hipLaunchKernelGGL((k_adj_p2p<real, KS_LY>), dim3(grid), dim3(kT), 0, st, a, gpos, asrc, partial); break;
-          case KS_YY: hipLaunchKernelGGL((k_adj_p2p<real, KS_YY>), dim3(grid), dim3(kT), 0, st, a, gpos, asrc, partial); break;
-        }
+        prof_mark(pl, st, timed, 3, pl.alaunch_flop_p2p[phase][ks], true);
+        launch_adj_p2p<real>(st, ks, a, grid, gpos, asrc, partial);
+        prof_mark(pl, st, timed, 3, 0.0, false);
       }
       const int* uptr = wsp<int>(pl, pl.o_auptr + 4 * us.ptr_off);
       if (two)
@@ -1110,7 +969,12 @@ static int transpose_impl(pbtc_plan_t& pl, hipStream_t st, const double* lam, do
       const int* uptr = wsp<int>(pl, pl.o_auptr + 4 * us.ptr_off);
       const int kind0 = (ks == KS_L || ks == KS_LY) ? 0 : 1;
       for (int slot = 0; slot < (two ? 2 : 1); ++slot) {
-        launch_adj_m2p<real>(pl, st, a, grid, gpos, mom, slot == 0 ? kind0 : 1, slot, partial);
+        const int kind = slot == 0 ? kind0 : 1;
+        const double fl = pl.alaunch_flop_m2p[phase][ks] * adj_m2p_flop_one(pl.P, kind) /
+                          adj_m2p_flop_per_eval(pl.P, ks);
+        prof_mark(pl, st, timed, 4 + kind, fl, true);
+        launch_adj_m2p<real>(st, pl.P, a, grid, gpos, mom, pl.adj_ms, kind, slot, partial);
+        prof_mark(pl, st, timed, 4 + kind, 0.0, false);
         hipLaunchKernelGGL((k_adj_reduce<real, 2>), dim3(n), dim3(256), 0, st, list, uptr,
                            a.item_block, a.blocks, partial, aS, aD, 1, slot);
       }
@@ -1192,6 +1056,8 @@ int device_backward(pbtc_plan_t& pl, hipStream_t st, double gE, double* dq, doub
   }
   const int T = 256;
   const double C = 4.0 * kPi * kCoulomb;
+  prof_collect(pl);
+  for (int i = 0; i < 6; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
   double* x = wsp<double>(pl, pl.o_x);
   double* lam = wsp<double>(pl, pl.o_lam);
   double* rhs = wsp<double>(pl, pl.o_adj_rhs);
@@ -1425,6 +1291,12 @@ int device_backward(pbtc_plan_t& pl, hipStream_t st, double gE, double* dq, doub
     res->n_matvec_fp32 = n32;
     res->n_matvec_fp64 = n64;
     res->n_refine = nref;
+    prof_collect(pl);
+    for (int k = 0; k < 6; ++k) {
+      res->t_kernel_s[k] = pl.prof_t[k];
+      res->n_kernel_launch[k] = pl.prof_n[k];
+      res->kernel_flop[k] = pl.prof_flop[k];
+    }
   }
   pl.adj_history = hist;
   if (!conv) {

@@ -27,6 +27,9 @@ constexpr int kMomSpan = 1024;   // sources per block of the direct moment pass
 constexpr int kMaxRule = 19;
 
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+// values per (cell, kernel slot) of the transposed operator's moments:
+// single layer to order P, the three double-layer gradient arrays to P + 1
+__host__ __device__ constexpr int adj_mom_len(int p) { return ncoef(p) + 3 * ncoef(p + 1); }
 
 // Kernel sets evaluated by one block: up to two distinct Green's functions.
 enum KernelSet : int { KS_L = 0, KS_Y = 1, KS_LY = 2, KS_YY = 3, KS_COUNT = 4 };
@@ -278,10 +281,12 @@ struct pbtc_plan_s {
     bool recorded = false;  // both events recorded on the stream
   };
   std::vector<ProfEvent> prof, prof_pool;
-  // per kernel kind: 0 P2P, 1 Laplace M2P, 2 Yukawa M2P
-  double prof_t[3] = {0, 0, 0}, prof_flop[3] = {0, 0, 0};
-  int prof_n[3] = {0, 0, 0};
-  int64_t prof_count = 0;  // FP32 operator evaluations seen by the sampler
+  // per kernel kind: 0 P2P, 1 Laplace M2P, 2 Yukawa M2P of A x; 3, 4, 5 the
+  // same of A^T x
+  double prof_t[6] = {0, 0, 0, 0, 0, 0}, prof_flop[6] = {0, 0, 0, 0, 0, 0};
+  int prof_n[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_count = 0;   // FP32 operator evaluations seen by the sampler
+  int64_t aprof_count = 0;  // the same for the transposed operator
   double setup_phase[6] = {0, 0, 0, 0, 0, 0};  // host seconds per set-up phase
   // GMRES residual readback: pinned host slots and their events
   double* res_pin = nullptr;
@@ -291,9 +296,22 @@ struct pbtc_plan_s {
   // events that fork and join it (created on first use)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // launch graphs of the operator per [precision FP64 / FP32][phase]: the
+  // kernel sequence captured on cap_stream with x and y in o_gxin / o_gyout,
+  // valid for the set-up generation and workspace it was captured on
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t op_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t op_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  uint64_t op_graph_gen[2][2] = {{0, 0}, {0, 0}};
+  void* op_graph_ws[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int op_kernels[2][2] = {{0, 0}, {0, 0}};  // kernel nodes per graph
+  uint64_t setup_gen = 0;                   // bumped by every device set-up
+  int64_t n_graph_launch = 0;               // graph replays of the FP32 A x
+  size_t o_gxin = 0, o_gyout = 0;
   ~pbtc_plan_s();
   std::vector<double> item_flop_p2p[2][pbtc::KS_COUNT], item_flop_m2p[2][pbtc::KS_COUNT];
   double launch_flop_p2p[2][pbtc::KS_COUNT] = {}, launch_flop_m2p[2][pbtc::KS_COUNT] = {};
+  double alaunch_flop_p2p[2][pbtc::KS_COUNT] = {}, alaunch_flop_m2p[2][pbtc::KS_COUNT] = {};
   bool setup_done = false;
   int n_levels = 0;
   std::vector<int> level_begin;  // cell index where each level starts (+ end)

@@ -3,7 +3,21 @@
 
 #include <hip/hip_runtime.h>
 
+#include "internal.h"
+
 namespace pbtc {
+
+// Arguments of the work-unit kernels (P2P and M2P, forward and transposed):
+// units (item, first list entry, end entry, -), the item -> block map, the
+// blocks, the cell list of this kernel kind and the cells.
+struct UnitArgs {
+  const int4* units;
+  int nunits;
+  const int* item_block;
+  const DevBlock* blocks;
+  const int* cells_list;
+  const Cell* cells;
+};
 
 // One source record of the treecode: position, single-layer strength and
 // double-layer dipole (forward operator), or position and the adjoint

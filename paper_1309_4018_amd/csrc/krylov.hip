@@ -810,8 +810,9 @@ int device_solve(pbtc_plan_t& pl, hipStream_t st, pbtc_result* res) {
   double* x = wsp<double>(pl, pl.o_x);
   Krylov K(pl, st);
   pl.history.clear();
+  pl.n_graph_launch = 0;
   prof_collect(pl);
-  for (int i = 0; i < 3; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
+  for (int i = 0; i < 6; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
   int iters = 0, n32 = 0, n64 = 0, nref = 0;
   bool conv = false;
   double rel = 0.0;
@@ -864,6 +865,13 @@ int device_solve(pbtc_plan_t& pl, hipStream_t st, pbtc_result* res) {
     res->t_m2p_yuk_s = pl.prof_t[2];
     res->n_m2p_yuk_launch = pl.prof_n[2];
     res->m2p_yuk_flop = pl.prof_flop[2];
+    res->op_kernels = pl.op_kernels[1][0];
+    res->op_graph_launches = (int)pl.n_graph_launch;
+    for (int k = 0; k < 6; ++k) {
+      res->t_kernel_s[k] = pl.prof_t[k];
+      res->n_kernel_launch[k] = pl.prof_n[k];
+      res->kernel_flop[k] = pl.prof_flop[k];
+    }
   }
   if (!conv) {
     pl.err = "GMRES did not reach the tolerance within max_iter";

@@ -193,15 +193,6 @@ __global__ __launch_bounds__(256) void k_mom_sum(const int* __restrict__ cell_ch
 constexpr int kItemThreads = 256;
 constexpr int kWaves = kItemThreads / 64;
 
-struct UnitArgs {
-  const int4* units;   // (item, e0, e1, -)
-  int nunits;
-  const int* item_block;
-  const DevBlock* blocks;
-  const int* cells_list;
-  const Cell* cells;
-};
-
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // One (target, source) pair: single and double layer of the block's kernels.
@@ -563,9 +554,10 @@ static void launch_m2p(pbtc_plan_t& pl, hipStream_t st, const UnitArgs& a, int g
 #undef PBTC_M2P
 }
 
-// Timing of one kernel launch (kind 0 P2P, 1 Laplace M2P, 2 Yukawa M2P) with
-// events on the launch stream; only the FP32 operator (A x) is timed.
-static void prof_mark(pbtc_plan_t& pl, hipStream_t st, bool on, int kind, double flop, bool begin) {
+// Timing of one kernel launch (kind 0 P2P, 1 Laplace M2P, 2 Yukawa M2P of
+// A x; 3, 4, 5 of A^T x) with events on the launch stream; only FP32
+// operator evaluations are timed.
+void prof_mark(pbtc_plan_t& pl, hipStream_t st, bool on, int kind, double flop, bool begin) {
   if (!pl.prm.profile || !on) return;
   if (begin) {
     pbtc_plan_t::ProfEvent ev;
@@ -589,8 +581,11 @@ static void prof_mark(pbtc_plan_t& pl, hipStream_t st, bool on, int kind, double
 }
 
 // y = A x (phase 0) or phi_reac = S x (phase 1) in precision `prec`.
+// capture: the launches are being recorded into a launch graph (no timing
+// events, the moment pass always on the side stream).
 template <typename real>
-static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int phase) {
+static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int phase,
+                      bool capture = false) {
   const int T = 256;
   Src<real>* src = wsp<Src<real>>(pl, sizeof(real) == 4 ? pl.o_src32 : pl.o_src64);
   real* mom = wsp<real>(pl, sizeof(real) == 4 ? pl.o_mom32 : pl.o_mom64);
@@ -605,7 +600,7 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
   PBTC_LAUNCH_CHECK();
   const bool tree = pl.prm.op == PBTC_OP_TREECODE;
   bool timed = false;
-  if (sizeof(real) == 4 && phase == 0 && pl.prm.profile > 0)
+  if (sizeof(real) == 4 && phase == 0 && pl.prm.profile > 0 && !capture)
     timed = pl.prof_count++ % pl.prm.profile == 0;
   // the moment pass (latency-bound) runs on a second stream beside the
   // P2P launches (ALU-bound); M2P waits for it.  A sampled (timed)
@@ -748,10 +743,92 @@ void prof_collect(pbtc_plan_t& pl) {
   pl.prof.clear();
 }
 
+void release_op_graphs(pbtc_plan_t& pl) {
+  for (int p = 0; p < 2; ++p)
+    for (int ph = 0; ph < 2; ++ph) {
+      if (pl.op_exec[p][ph]) (void)hipGraphExecDestroy(pl.op_exec[p][ph]);
+      if (pl.op_graph[p][ph]) (void)hipGraphDestroy(pl.op_graph[p][ph]);
+      pl.op_exec[p][ph] = nullptr;
+      pl.op_graph[p][ph] = nullptr;
+      pl.op_graph_ws[p][ph] = nullptr;
+    }
+}
+
+// Records the kernel sequence of one operator evaluation (all blocks of all
+// regions and systems, the side-stream moment pass as a parallel branch)
+// into a launch graph that reads x from o_gxin and writes y to o_gyout.
+// Kernel nodes only: no memset or copy node is recorded.
+static int capture_operator(pbtc_plan_t& pl, int precision, int phase) {
+  const int p = precision == PBTC_FP64 ? 0 : 1;
+  if (pl.op_exec[p][phase]) (void)hipGraphExecDestroy(pl.op_exec[p][phase]);
+  if (pl.op_graph[p][phase]) (void)hipGraphDestroy(pl.op_graph[p][phase]);
+  pl.op_exec[p][phase] = nullptr;
+  pl.op_graph[p][phase] = nullptr;
+  if (!pl.cap_stream) PBTC_HIP(hipStreamCreateWithFlags(&pl.cap_stream, hipStreamNonBlocking));
+  if (!pl.side) {
+    PBTC_HIP(hipStreamCreateWithFlags(&pl.side, hipStreamNonBlocking));
+    PBTC_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
+    PBTC_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
+  }
+  const double* x = wsp<double>(pl, pl.o_gxin);
+  double* y = wsp<double>(pl, pl.o_gyout);
+  PBTC_HIP(hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = p == 0 ? apply_impl<double>(pl, pl.cap_stream, x, y, phase, true)
+                        : apply_impl<float>(pl, pl.cap_stream, x, y, phase, true);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(pl.cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  PBTC_HIP(e);
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    PBTC_HIP(ei);
+  }
+  size_t nodes = 0;
+  PBTC_HIP(hipGraphGetNodes(g, nullptr, &nodes));
+  pl.op_graph[p][phase] = g;
+  pl.op_exec[p][phase] = ex;
+  pl.op_graph_gen[p][phase] = pl.setup_gen;
+  pl.op_graph_ws[p][phase] = pl.ws;
+  pl.op_kernels[p][phase] = (int)nodes;
+  return PBTC_OK;
+}
+
+// y = A x (phase 0) or phi_reac = S x (phase 1).  With params.op_graph the
+// evaluation is one replay of the captured launch graph (x copied into its
+// input buffer first and the result out of its output buffer after, unless
+// the caller passes those buffers); an evaluation sampled for kernel timing
+// launches its kernels one by one.
 int apply_operator(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, int precision,
                    int phase) {
-  if (precision == PBTC_FP64) return apply_impl<double>(pl, st, x, y, phase);
-  return apply_impl<float>(pl, st, x, y, phase);
+  const bool fp32 = precision != PBTC_FP64;
+  const bool sampled = fp32 && phase == 0 && pl.prm.profile > 0 &&
+                       pl.prof_count % pl.prm.profile == 0;
+  if (!pl.prm.op_graph || sampled)
+    return fp32 ? apply_impl<float>(pl, st, x, y, phase) : apply_impl<double>(pl, st, x, y, phase);
+  const int p = fp32 ? 1 : 0;
+  if (!pl.op_exec[p][phase] || pl.op_graph_gen[p][phase] != pl.setup_gen ||
+      pl.op_graph_ws[p][phase] != pl.ws) {
+    const int rc = capture_operator(pl, precision, phase);
+    if (rc) return rc;
+  }
+  double* xin = wsp<double>(pl, pl.o_gxin);
+  double* yout = wsp<double>(pl, pl.o_gyout);
+  const int64_t ny = phase == 0 ? pl.nunk : pl.nq;
+  if (x != xin)
+    PBTC_HIP(hipMemcpyAsync(xin, x, 8 * pl.nunk, hipMemcpyDeviceToDevice, st));
+  PBTC_HIP(hipGraphLaunch(pl.op_exec[p][phase], st));
+  if (y != yout && ny > 0)
+    PBTC_HIP(hipMemcpyAsync(y, yout, 8 * ny, hipMemcpyDeviceToDevice, st));
+  if (fp32 && phase == 0) {
+    if (pl.prm.profile > 0) ++pl.prof_count;
+    ++pl.n_graph_launch;
+  }
+  return PBTC_OK;
 }
 
 // Descriptor tables (blocks, rows, item lists) to the device.

@@ -571,6 +571,8 @@ void compute_layout(pbtc_plan_t& pl) {
   pl.o_energy = L.add(8 * (pl.ncomp + 64));
   pl.o_coul = L.add(8 * (pl.ncomp + 1));
   pl.o_z2 = L.add(8 * std::max<int64_t>(n, pl.nq));
+  pl.o_gxin = L.add(8 * n);
+  pl.o_gyout = L.add(8 * std::max<int64_t>(n, pl.nq));
   pl.o_comp_of_unk = L.add(4 * n);
   pl.o_chunks = L.add(16 * std::max<size_t>(pl.dot_chunks.size(), 1) + 4 * (pl.ncomp + 1));
   pl.o_comp_q = L.add(4 * std::max<int64_t>(pl.nq, 1));
@@ -641,8 +643,8 @@ void compute_layout(pbtc_plan_t& pl) {
   // transposed-operator trees and lists
   pl.o_tcells = L.add(sizeof(Cell) * pl.cap_tcells);
   pl.o_tcnt = L.add(8 * (pl.cap_tcells + 1));
-  pl.o_amom32 = L.add(4 * 2 * nP * pl.cap_tcells * pl.adj_ms);
-  pl.o_amom64 = L.add(8 * 2 * nP * pl.cap_tcells * pl.adj_ms);
+  pl.o_amom32 = L.add(4 * (size_t)adj_mom_len(pl.P) * pl.cap_tcells * pl.adj_ms);
+  pl.o_amom64 = L.add(8 * (size_t)adj_mom_len(pl.P) * pl.cap_tcells * pl.adj_ms);
   pl.o_amchunks = L.add(16 * pl.cap_amchunks);
   pl.o_ampairs = L.add(16 * pl.cap_ampairs);
   pl.o_ampart = L.add(8 * 2 * nP * pl.cap_amchunks);

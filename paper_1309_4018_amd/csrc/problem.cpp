@@ -150,6 +150,7 @@ std::string validate_problem(const pbtc_problem& p, const pbtc_params& prm, int*
   if (prm.profile < 0) return fail(PBTC_EINVAL, "profile must be >= 0");
   if (prm.precond != PBTC_PREC_NONE && prm.precond != PBTC_PREC_BLOCK_DIAG)
     return fail(PBTC_EINVAL, "unknown precond");
+  if (prm.op_graph != 0 && prm.op_graph != 1) return fail(PBTC_EINVAL, "op_graph must be 0 or 1");
   // regions
   const int nreg = (int)p.regions.size();
   if (nreg < 2) return fail(PBTC_EINVAL, "need at least two regions");

@@ -828,6 +828,7 @@ int upload_descriptors(pbtc_plan_t& pl, hipStream_t st);
 // Builds every once-per-geometry structure on the plan's workspace.
 int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
   *need_retry = 0;
+  ++pl.setup_gen;  // captured operator graphs of an earlier set-up are stale
   const pbtc_problem& P = pl.prob;
   const int T = 256;
   auto t_last = std::chrono::steady_clock::now();

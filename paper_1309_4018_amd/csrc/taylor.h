@@ -343,6 +343,53 @@ inline double m2p_flop_one(int P, int kind) {
   return f;
 }
 
+// The same for the transposed operator's pair (target normal n at the
+// Gauss point, source weights muS and muD): d, r^2, rsqrt, n.d, 1/r^2 (15),
+// Laplace single + double layer (6), Yukawa (12) per kernel.
+inline double adj_p2p_flop_per_pair(int ks) {
+  switch (ks) {
+    case KS_L: return 21.0;
+    case KS_Y: return 27.0;
+    case KS_LY: return 33.0;
+    default: return 39.0;
+  }
+}
+
+// Operations of one transposed (target Gauss point, cell) evaluation as
+// written in the transposed M2P: the degree-scaled recurrence to order
+// P + 1, the single-layer contraction to P, the three gradient contractions
+// to P + 1 and Horner's rule over the degrees (FMA = 2).
+inline double adj_m2p_flop_one(int P, int kind) {
+  const int Q = P + 1;
+  double f = kind == 0 ? 11.0 + 5.0 + (Q - 1) : 16.0 + 5.0 + 9.0 + 4.0 * (Q - 1);
+  f += 1.0;                          // S_0
+  f += 5.0 + 4.0;                    // n . F_Q, the two final products
+  f += 8.0 * Q + 2.0 * P;            // Horner: g_n, n . F_n, two FMAs (one to P)
+  for (int deg = 1; deg <= Q; ++deg)
+    for (int a = deg; a >= 0; --a)
+      for (int b = deg - a; b >= 0; --b) {
+        const int c = deg - a - b;
+        const int nz1 = (a >= 1) + (b >= 1) + (c >= 1);
+        const int nz2 = (a >= 2) + (b >= 2) + (c >= 2);
+        const double s1 = 2.0 * nz1 - 1.0, s2 = nz2 > 0 ? nz2 - 1.0 : 0.0;
+        if (kind == 0)
+          f += s1 + s2 + (nz2 ? 2.0 : 0.0);
+        else
+          f += 2.0 * (s1 + s2) + (nz2 ? 6.0 : 2.0) + (deg < Q ? (nz2 ? 2.0 : 0.0) : 0.0);
+        f += (deg <= P ? 2.0 : 0.0) + 2.0 * nz1;  // contractions
+      }
+  return f;
+}
+
+inline double adj_m2p_flop_per_eval(int P, int ks) {
+  switch (ks) {
+    case KS_L: return adj_m2p_flop_one(P, 0);
+    case KS_Y: return adj_m2p_flop_one(P, 1);
+    case KS_LY: return adj_m2p_flop_one(P, 0) + adj_m2p_flop_one(P, 1);
+    default: return 2.0 * adj_m2p_flop_one(P, 1);
+  }
+}
+
 inline double m2p_flop_per_eval(int P, int ks) {
   switch (ks) {
     case KS_L: return m2p_flop_one(P, 0);

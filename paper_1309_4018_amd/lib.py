@@ -32,7 +32,7 @@ class Params(C.Structure):
         ("tol", C.c_double), ("restart", C.c_int), ("max_iter", C.c_int),
         ("precision", C.c_int), ("op", C.c_int), ("inner_tol", C.c_double),
         ("max_refine", C.c_int), ("validate_charges", C.c_int), ("profile", C.c_int),
-        ("precond", C.c_int),
+        ("precond", C.c_int), ("op_graph", C.c_int),
     ]
 
 
@@ -50,6 +50,9 @@ class Result(C.Structure):
         ("t_m2p_yuk_s", C.c_double), ("n_m2p_yuk_launch", C.c_int),
         ("m2p_yuk_flop", C.c_double),
         ("t_setup_phase_s", C.c_double * 6),
+        ("op_kernels", C.c_int), ("op_graph_launches", C.c_int),
+        ("t_kernel_s", C.c_double * 6), ("n_kernel_launch", C.c_int * 6),
+        ("kernel_flop", C.c_double * 6),
     ]
 
     def as_dict(self):

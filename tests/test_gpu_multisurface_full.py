@@ -12,7 +12,7 @@ The oracle cannot assemble this system; it evaluates sampled rows one by one
 * the reaction potential (Eq. reac_integral) at 24 sampled charges.
 Tolerance 3e-4 of each row block's scale (Taylor truncation at P = 6,
 theta = 0.5).  The FP32-refined energy agrees with the plain FP64 treecode's
-to 1e-5.
+to 1e-4 at the benchmark's tolerance and to 1e-6 when both solve to 1e-8.
 """
 
 import numpy as np
@@ -100,9 +100,15 @@ def test_solution_residual_and_reaction_potential(c3, plan):
 
 
 def test_energy_fp32_refined_vs_fp64(c3, plan):
+    """At the benchmark's tolerance (1e-5) the FP32-refined energy is within
+    1e-4 of the plain FP64 treecode's; with both solved to 1e-8 the two differ
+    only by the FP32 rounding that refinement removes (1e-6)."""
     from paper_1309_4018_amd import lib
 
     e32 = plan.solve()["energy_kJmol"]
-    p64 = lib.plan_for(c3[0], precision="fp64", tol=1e-7, theta=0.5, P=6)
+    p64 = lib.plan_for(c3[0], precision="fp64", tol=1e-8, theta=0.5, P=6, max_iter=3000)
     e64 = p64.solve()["energy_kJmol"]
-    assert abs(e32 - e64) < 1e-5 * abs(e64)
+    assert abs(e32 - e64) < 1e-4 * abs(e64)
+    p32 = lib.plan_for(c3[0], precision="fp32_refined", tol=1e-8, theta=0.5, P=6, max_iter=3000)
+    e32t = p32.solve()["energy_kJmol"]
+    assert abs(e32t - e64) < 1e-6 * abs(e64)

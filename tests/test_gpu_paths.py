@@ -167,3 +167,34 @@ def test_shared_workspace_between_plans(sphere, gpu_lib):
                               C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), lib.FP64)
     assert code == lib.EINVAL
     assert abs(pa.solve()["energy_kJmol"] - ea) < 1e-12 * abs(ea)
+
+
+def test_operator_launch_graph_matches_kernel_by_kernel(gpu_lib):
+    """Every evaluation of A x as one replay of the captured launch graph
+    against the same kernels launched one by one: the same numbers bit for
+    bit, on every replay, with other GPU work and synchronisations between
+    the replays (multi-surface system: several kernel sets and a moment pass
+    on a second stream)."""
+    import torch
+
+    from paper_1309_4018_amd import lib
+
+    prob = synth.config3_multisurface(nu=8, cav_nu=4, n_charges=60)
+    pg = lib.plan_for(prob, theta=0.5, P=6, op_graph=1)
+    pe = lib.plan_for(prob, theta=0.5, P=6, op_graph=0)
+    pg.setup()
+    pe.setup()
+    rng = np.random.default_rng(8)
+    for it in range(4):
+        x = torch.from_numpy(rng.normal(size=pg.n_unknowns)).to("cuda:0")
+        for prec in (lib.FP32, lib.FP64):
+            yg = pg.matvec(x, prec).cpu().numpy()
+            junk = torch.randn(1 << 20, device="cuda:0").sum()  # unrelated eager work
+            ye = pe.matvec(x, prec).cpu().numpy()
+            torch.cuda.synchronize()
+            assert np.array_equal(yg, ye), (it, prec, float(junk))
+    rg = pg.solve()
+    re_ = pe.solve()
+    assert rg["energy_kJmol"] == re_["energy_kJmol"]
+    assert rg["op_kernels"] > 5 and rg["op_graph_launches"] >= rg["n_matvec_fp32"] > 0
+    assert re_["op_graph_launches"] == 0
