@@ -290,6 +290,19 @@ int pbtc_precond_apply(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, c
  * region coincide (non-finite energy). */
 int pbtc_coulomb_energy(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, double* total,
                         double* per_system);
+/* pbtc_coulomb_energy for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid allocation):
+ * the same arguments, kernels and results, with the scratch the kernels need
+ * (the Coulomb potential at every charge, the region table, the per-system
+ * sums) in a fixed device array inside the library instead of the plan's
+ * workspace; the plan's charges are read from d_workspace as before.
+ * Limits: at most 1,048,576 charges and 2 n_regions + 1 + n_systems <= 65,536
+ * (EINVAL beyond).  The array (9 MiB) is held by each GPU the library runs on
+ * until the process ends and is shared by every call on that GPU: calls that
+ * overlap on one GPU (different streams or threads) race.  No device or host
+ * memory is allocated during the call. */
+int pbtc_coulomb_energy_noalloc(pbtc_plan_t* plan, void* d_workspace, void* hip_stream,
+                                double* total, double* per_system);
 /* The Coulomb right-hand side b (Eq. matel Q) into a device buffer of
  * n_unknowns FP64 values. */
 int pbtc_rhs(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, double* d_b);

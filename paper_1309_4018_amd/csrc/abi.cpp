@@ -31,6 +31,7 @@ int apply_precond(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, b
                   bool accumulate);
 double wall_seconds();
 int device_coulomb(pbtc_plan_t& pl, hipStream_t st, double* total, double* per_system);
+int device_coulomb_noalloc(pbtc_plan_t& pl, hipStream_t st, double* total, double* per_system);
 void release_op_graphs(pbtc_plan_t& pl);
 
 // The merged problem of a pbtc_solve_batch call and where each member's
@@ -596,6 +597,16 @@ int pbtc_coulomb_energy(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, 
     if (!ready(plan, d_workspace))
       return fail_plan(plan, PBTC_EINVAL, "workspace not set up for this plan (call pbtc_setup)");
     return device_coulomb(*plan, (hipStream_t)hip_stream, total, per_system);
+  });
+}
+
+int pbtc_coulomb_energy_noalloc(pbtc_plan_t* plan, void* d_workspace, void* hip_stream,
+                                double* total, double* per_system) {
+  if (!plan || !total) return fail_global(PBTC_EINVAL, "NULL argument");
+  return guarded(plan, [&] {
+    if (!ready(plan, d_workspace))
+      return fail_plan(plan, PBTC_EINVAL, "workspace not set up for this plan (call pbtc_setup)");
+    return device_coulomb_noalloc(*plan, (hipStream_t)hip_stream, total, per_system);
   });
 }
 

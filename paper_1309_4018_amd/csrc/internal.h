@@ -369,6 +369,9 @@ struct pbtc_plan_s {
   uint64_t charge_version = 0;  // bumped by pbtc_set_charge_values
   std::vector<int> comp_conv;   // per system: converged in the last solve
   pbtc::BatchCache* batch = nullptr;  // owned; see abi.cpp
+  // host table of the allocation-free Coulomb energy (region offsets, eps,
+  // per-system sums), sized when the plan is made
+  std::vector<double> coul_host;
 
   // host results
   std::vector<double> x_host, phi_reac_host, history;

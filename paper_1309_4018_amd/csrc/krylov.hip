@@ -15,6 +15,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "device_util.h"
 
@@ -920,5 +922,92 @@ int device_coulomb(pbtc_plan_t& pl, hipStream_t st, double* total, double* per_s
 }
 
 double wall_seconds() { return now_s(); }
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of the Coulomb energy for callers that cannot
+// allocate device memory (code under HIP graph capture, tight serving loops):
+// its scratch -- the Coulomb potential at every charge, the per-system sums and
+// the region table -- lives in this file-scope device array instead of the
+// plan's workspace.  Each GPU holds its own copy until the process ends; its
+// device address is taken once per device with hipGetSymbolAddress (the
+// array's name in host code is not a device address).  Calls that overlap on
+// one GPU share the array and race; every value a call reads is written by
+// that call first, so nothing needs clearing.
+constexpr int64_t kScratchCharges = int64_t(1) << 20;  // phi: one double per charge
+constexpr int64_t kScratchTable = int64_t(1) << 16;    // region table + per-system sums
+constexpr size_t kScratchBytes = 8 * (size_t)(kScratchCharges + kScratchTable);
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device (looked up once per device).
+static int scratch_address(pbtc_plan_t& pl, char** out) {
+  int dev = 0;
+  PBTC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    pl.err = "device index beyond the scratch table";
+    return PBTC_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    PBTC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return PBTC_OK;
+}
+
+int device_coulomb_noalloc(pbtc_plan_t& pl, hipStream_t st, double* total, double* per_system) {
+  const int64_t ntab = 2 * (int64_t)pl.nreg + 1, nout = pl.ncomp;
+  if (pl.nq > kScratchCharges || ntab + nout > kScratchTable) {
+    pl.err = "allocation-free Coulomb energy: at most " + std::to_string(kScratchCharges) +
+             " charges and " + std::to_string(kScratchTable) +
+             " values of region table plus systems (2 regions + 1 + systems)";
+    return PBTC_EINVAL;
+  }
+  char* base = nullptr;
+  int rc = scratch_address(pl, &base);
+  if (rc) return rc;
+  double* phi = reinterpret_cast<double*>(base);
+  double* dtab = phi + kScratchCharges;
+  double* out = dtab + ntab;
+  // host tables sized when the plan was made: no allocation here
+  double* tab = pl.coul_host.data();
+  for (int r = 0; r <= pl.nreg; ++r) {
+    const long long o = pl.q_off_region[r];
+    std::memcpy(&tab[r], &o, 8);
+  }
+  for (int r = 0; r < pl.nreg; ++r) tab[pl.nreg + 1 + r] = pl.prob.regions[r].eps;
+  double* e = tab + ntab;
+  for (int64_t c = 0; c < nout; ++c) e[c] = 0.0;
+  PBTC_HIP(hipMemcpyAsync(dtab, tab, 8 * ntab, hipMemcpyHostToDevice, st));
+  if (pl.nq > 0) {
+    hipLaunchKernelGGL(k_coulomb_pot, dim3(nblocks(pl.nq, 256)), dim3(256), 0, st, pl.nq,
+                       wsp<double>(pl, pl.o_qxyz), wsp<double>(pl, pl.o_q), wsp<int>(pl, pl.o_qreg),
+                       reinterpret_cast<const long long*>(dtab), dtab + pl.nreg + 1, phi);
+    hipLaunchKernelGGL(k_energy_seg, dim3(pl.ncomp), dim3(kRedThreads), 0, st,
+                       wsp<double>(pl, pl.o_q), phi, wsp<int>(pl, pl.o_comp_q), pl.nq, 0.5 * kCoulomb,
+                       out);
+    PBTC_LAUNCH_CHECK();
+    PBTC_HIP(hipMemcpyAsync(e, out, 8 * nout, hipMemcpyDeviceToHost, st));
+  }
+  PBTC_HIP(hipStreamSynchronize(st));
+  double t = 0.0;
+  for (int64_t c = 0; c < nout; ++c) {
+    if (!std::isfinite(e[c])) {
+      pl.err = "Coulomb energy is not finite (coincident charges in one region)";
+      return PBTC_EINVAL;
+    }
+    t += e[c];
+    if (per_system) per_system[c] = e[c];
+  }
+  *total = t;
+  return PBTC_OK;
+}
 
 }  // namespace pbtc

@@ -329,6 +329,7 @@ int build_plan(pbtc_plan_t& pl) {
         pl.dot_chunks.push_back(make_int4(c, (int)a, (int)std::min(a + kChunk, pl.comp_u1[c]), 0));
     }
     pl.comp_chunk0[pl.ncomp] = (int)pl.dot_chunks.size();
+    pl.coul_host.assign(2 * (size_t)pl.nreg + 1 + (size_t)pl.ncomp, 0.0);
   }
 
   // transposed operator: Gauss-point groups, items, kernel slots, CSC columns
