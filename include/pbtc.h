@@ -104,7 +104,7 @@ typedef struct {
   /* treecode (sec. 2.3) */
   double theta;  /* MAC: accept a cell when theta * r_tb > r_b */
   int P;         /* Taylor order: 2, 4, 6, 8 or 10 */
-  int ncrit;     /* split a cell holding >= ncrit sources; 0 = automatic */
+  int ncrit;     /* split a cell holding >= ncrit sources (2..1024); 0 = automatic */
   int direct_below; /* a MAC-accepted cell with fewer sources goes to P2P; -1 =
                        auto: per block, where P2P costs less than one M2P
                        evaluation of the block's kernels */

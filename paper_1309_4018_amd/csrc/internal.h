@@ -225,8 +225,10 @@ struct pbtc_plan_s {
   size_t o_flags = 0;  // device status flags (16 int)
   size_t o_qtab = 0;   // per region: first charge (nreg + 1 long long), eps (nreg double)
   size_t o_coul = 0;   // Coulomb energy per system (ncomp double)
-  size_t o_mchunks = 0, o_mcell = 0, o_mpart = 0;  // direct moment pass: chunks, per-cell chunk ranges, partial moments
-  int64_t cap_mchunks = 0, n_mchunks = 0;
+  // moment pass: span cells (cell, first source, count), span roots in
+  // source order, upper cells (cell, first span root, end)
+  size_t o_mchunks = 0, o_mcell = 0, o_mpart = 0;
+  int64_t n_mchunks = 0, n_mup = 0;
   // direct moment pass of the transposed operator: chunks (cell, first
   // source, count, slot) and (cell x local slot, first chunk, end chunk)
   // pairs, per phase in [off[ph], off[ph + 1])

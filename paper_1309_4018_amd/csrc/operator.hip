@@ -55,22 +55,27 @@ __global__ void k_prep(int64_t ngp, const double* __restrict__ gx, const double*
 }
 
 // ------------------------------------------------------------- moments
-// Moments of every cell directly from its own sources (Eq. multexp), at
-// every level of the tree: M_SL[k] = sum q (y - c)^k and
-// M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d) about the cell centre c.  A
-// cell's sources are consecutive in Morton order; one block takes a span of
-// at most kMomSpan of them (all spans of all levels in one launch), staged
-// through LDS kMomChunk at a time with the next batch loaded ahead, and a
-// second launch sums each cell's spans in span order (deterministic).  This
-// replaces the level-by-level upward shift: the same moments with no
-// dependence between levels.
+// Moments of every cell about its centre c (Eq. multexp):
+//   M_SL[k] = sum q (y - c)^k,   M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d).
+// A span root is a cell of at most kMomSpan sources whose parent has more
+// (or a tree root that small); every cell of a span root's subtree takes one
+// work-group that computes its moments directly from its own (Morton-
+// contiguous) sources, staged through LDS kMomChunk at a time.  The work-
+// groups of one span are consecutive in a list that is dealt to the XCDs in
+// contiguous runs, so that a span's sources come from HBM once and from that
+// XCD's L2 for the deeper cells.  A larger (upper) cell sums the moments of
+// the span roots inside it shifted to its own centre by the multi-index
+// binomial theorem (sec. 2.3: moments shifted to the parents):
+//   (y - c_u)^k = sum_{j <= k} C(k, j) h^(k - j) (y - c_s)^j,   h = c_s - c_u,
+// which holds for both moment kinds (the double layer is a linear map of the
+// same monomials), so upper cells never re-read the sources.
 constexpr int kMomThreads = 256;
 
 template <typename real, int P>
-__global__ __launch_bounds__(kMomThreads) void k_p2m_chunk(const int4* __restrict__ chunks,
-                                                           const Cell* __restrict__ cells,
-                                                           const Src<real>* __restrict__ src,
-                                                           real* __restrict__ part) {
+__global__ __launch_bounds__(kMomThreads) void k_p2m_cell(const int4* __restrict__ chunks,
+                                                          const Cell* __restrict__ cells,
+                                                          const Src<real>* __restrict__ src,
+                                                          real* __restrict__ mom) {
   constexpr int N = ncoef(P);
   constexpr int G = N <= kMomThreads ? kMomThreads / N : 1;  // groups of sources
   constexpr int KPT = (N + kMomThreads - 1) / kMomThreads;   // coefficients per thread
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(kMomThreads) void k_p2m_chunk(const int4* __restric
   __shared__ real pw[kMomChunk][3][P + 1];
   __shared__ real sq[kMomChunk][4];
   __shared__ real red[G][2 * N];
-  const int4 ch = chunks[blockIdx.x];  // (cell, first source, count)
+  const int4 ch = chunks[xcd_block(blockIdx.x, gridDim.x)];  // (cell, first source, count)
   const Cell& cl = cells[ch.x];
   const real cx = (real)cl.cx, cy = (real)cl.cy, cz = (real)cl.cz;
   const int tid = threadIdx.x;
@@ -156,30 +161,72 @@ __global__ __launch_bounds__(kMomThreads) void k_p2m_chunk(const int4* __restric
     real v = 0;
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) v += red[gg][k];
-    part[(size_t)blockIdx.x * 2 * N + k] = v;
+    mom[(size_t)ch.x * 2 * N + k] = v;
   }
 }
 
-// mom[c] = sum of the spans of cell c, eight loads in flight per step, in a
-// fixed order (zero for an empty cell)
+// binomial coefficient C(n, k) for n <= kMaxP
+__host__ __device__ constexpr int binom(int n, int k) {
+  int r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Moments of an upper cell u: the span roots sroot[up.y .. up.z) shifted to
+// its centre and added in order (deterministic).
 template <typename real, int P>
-__global__ __launch_bounds__(256) void k_mom_sum(const int* __restrict__ cell_chunk,
-                                                 const real* __restrict__ part,
-                                                 real* __restrict__ mom) {
-  constexpr int N2 = 2 * ncoef(P);
-  const int c = blockIdx.x;
-  const int c0 = cell_chunk[c], c1 = cell_chunk[c + 1];
-  for (int k = threadIdx.x; k < N2; k += 256) {
-    real v = 0;
-    int j = c0;
-    for (; j + 8 <= c1; j += 8) {
-      real a[8];
+__global__ __launch_bounds__(256) void k_mom_up(const int4* __restrict__ up,
+                                                const int* __restrict__ sroot,
+                                                const Cell* __restrict__ cells,
+                                                real* __restrict__ mom) {
+  constexpr int N = ncoef(P);
+  constexpr int KPT = (2 * N + 255) / 256;
+  __shared__ real hp[3][P + 1];
+  const int4 u = up[blockIdx.x];
+  const Cell& cu = cells[u.x];
+  const int tid = threadIdx.x;
+  int kk[KPT][3];
+  real acc[KPT];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) a[i] = part[(size_t)(j + i) * N2 + k];
-      v += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  for (int q = 0; q < KPT; ++q) {
+    const int k = tid + 256 * q;
+    mindex_inv(k < 2 * N ? (k < N ? k : k - N) : 0, kk[q][0], kk[q][1], kk[q][2]);
+    acc[q] = 0;
+  }
+  for (int i = u.y; i < u.z; ++i) {
+    const int cs = sroot[i];
+    const Cell& c = cells[cs];
+    __syncthreads();  // the previous root's powers are no longer read
+    if (tid < 3) {
+      const double h = tid == 0 ? c.cx - cu.cx : tid == 1 ? c.cy - cu.cy : c.cz - cu.cz;
+      real v = 1;
+      for (int e = 0; e <= P; ++e) {
+        hp[tid][e] = v;
+        v *= (real)h;
+      }
     }
-    for (; j < c1; ++j) v += part[(size_t)j * N2 + k];
-    mom[(size_t)c * N2 + k] = v;
+    __syncthreads();
+    const real* Ms = mom + (size_t)cs * 2 * N;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int k = tid + 256 * q;
+      if (k >= 2 * N) continue;
+      const int a = kk[q][0], b = kk[q][1], cc = kk[q][2];
+      const real* M = k < N ? Ms : Ms + N;
+      real s = 0;
+      for (int j1 = 0; j1 <= a; ++j1)
+        for (int j2 = 0; j2 <= b; ++j2) {
+          const real f12 = real(binom(a, j1) * binom(b, j2)) * hp[0][a - j1] * hp[1][b - j2];
+          for (int j3 = 0; j3 <= cc; ++j3)
+            s += f12 * real(binom(cc, j3)) * hp[2][cc - j3] * M[mindex(j1, j2, j3)];
+        }
+      acc[q] += s;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = tid + 256 * q;
+    if (k < 2 * N) mom[(size_t)u.x * 2 * N + k] = acc[q];
   }
 }
 
@@ -509,15 +556,17 @@ template <typename real>
 static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<real>* src) {
   const Cell* cells = wsp<Cell>(pl, pl.o_cells);
   const int4* chunks = wsp<int4>(pl, pl.o_mchunks);
-  const int* cell_chunk = wsp<int>(pl, pl.o_mcell);
-  real* part = wsp<real>(pl, pl.o_mpart);
-  const unsigned nch = (unsigned)pl.n_mchunks, nc = (unsigned)pl.n_cells;
-#define PBTC_MOM(PP)                                                                           \
-  case PP:                                                                                     \
-    if (nch > 0)                                                                               \
-      hipLaunchKernelGGL((k_p2m_chunk<real, PP>), dim3(nch), dim3(kMomThreads), 0, st, chunks, \
-                         cells, src, part);                                                    \
-    hipLaunchKernelGGL((k_mom_sum<real, PP>), dim3(nc), dim3(256), 0, st, cell_chunk, part, mom); \
+  const int* sroot = wsp<int>(pl, pl.o_mcell);
+  const int4* up = wsp<int4>(pl, pl.o_mpart);
+  const unsigned nch = (unsigned)pl.n_mchunks, nup = (unsigned)pl.n_mup;
+#define PBTC_MOM(PP)                                                                          \
+  case PP:                                                                                    \
+    if (nch > 0)                                                                              \
+      hipLaunchKernelGGL((k_p2m_cell<real, PP>), dim3(nch), dim3(kMomThreads), 0, st, chunks, \
+                         cells, src, mom);                                                    \
+    if (nup > 0)                                                                              \
+      hipLaunchKernelGGL((k_mom_up<real, PP>), dim3(nup), dim3(256), 0, st, up, sroot, cells, \
+                         mom);                                                                \
     break;
   switch (pl.P) {
     PBTC_MOM(2)

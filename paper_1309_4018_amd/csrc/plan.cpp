@@ -461,7 +461,6 @@ int build_plan(pbtc_plan_t& pl) {
   if (pl.cap_far == 0)
     pl.cap_far = (pl.prm.op == PBTC_OP_DIRECT ? 1 : 160) * pl.nitems + 1024;
   if (pl.cap_units == 0) pl.cap_units = 8 * pl.nitems + 1024;
-  if (pl.cap_mchunks == 0) pl.cap_mchunks = pl.cap_cells + 8 * pl.ngp / kMomSpan + 1024;
   if (pl.cap_aunits == 0) pl.cap_aunits = 8 * pl.nitems_adj + 1024;
   if (pl.cap_auptr == 0) pl.cap_auptr = 2 * pl.nitems_adj + 64;
   if (pl.cap_tcells == 0) pl.cap_tcells = pl.ntgt / 16 + 64 * (int64_t)pl.tsets.size() + 1024;
@@ -624,9 +623,9 @@ void compute_layout(pbtc_plan_t& pl) {
   pl.o_scan = L.add(8 * (std::max<int64_t>(pl.cap_cells, pl.nitems) + 2));
   pl.o_mom64 = L.add(8 * 2 * nP * pl.cap_cells);
   pl.o_mom32 = L.add(4 * 2 * nP * pl.cap_cells);
-  pl.o_mchunks = L.add(16 * pl.cap_mchunks);
-  pl.o_mcell = L.add(4 * (pl.cap_cells + 1));
-  pl.o_mpart = L.add(8 * 2 * nP * pl.cap_mchunks);
+  pl.o_mchunks = L.add(16 * pl.cap_cells);
+  pl.o_mcell = L.add(4 * pl.cap_cells);
+  pl.o_mpart = L.add(16 * pl.cap_cells);
   // lists
   pl.o_near_ptr = L.add(8 * (pl.nitems + 1));
   pl.o_far_ptr = L.add(8 * (pl.nitems + 1));

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <functional>
 
 #include "device_util.h"
 #include "traverse.h"
@@ -1217,24 +1218,40 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     pl.n_units = (int64_t)units.size();
     pl.n_uptr = (int64_t)uptr.size();
 
-    // direct moment pass: the sources of every cell (all levels) in runs of
-    // at most kMomSpan, one block each, then one sum per cell
-    std::vector<int4> mch;
-    std::vector<int> mcell(pl.n_cells + 1);
-    for (int64_t c = 0; c < pl.n_cells; ++c) {
-      mcell[c] = (int)mch.size();
-      for (int b0 = 0; b0 < hc[c].count; b0 += kMomSpan)
-        mch.push_back(make_int4((int)c, hc[c].begin + b0, std::min(kMomSpan, hc[c].count - b0), 0));
-    }
-    mcell[pl.n_cells] = (int)mch.size();
-    pl.n_mchunks = (int64_t)mch.size();
-    if (pl.n_mchunks > pl.cap_mchunks) {
-      pl.cap_mchunks = pl.n_mchunks + pl.n_mchunks / 8 + 1024;
-      *need_retry = 1;
-      pl.err = "moment chunks exceed the workspace estimate";
+    // moment pass: span roots (at most kMomSpan sources, parent larger), the
+    // cells of their subtrees span by span, and the upper cells with the run
+    // of span roots inside them (children visited in source order)
+    std::vector<int4> mch, mup;
+    std::vector<int> sroot;
+    bool too_big = false;
+    std::function<void(int)> visit = [&](int c) {
+      if (hc[c].count <= kMomSpan) {
+        sroot.push_back(c);
+        const size_t first = mch.size();
+        mch.push_back(make_int4(c, hc[c].begin, hc[c].count, 0));
+        for (size_t i = first; i < mch.size(); ++i) {
+          const Cell& cc = hc[mch[i].x];
+          for (int k = 0; k < cc.nchild; ++k)
+            mch.push_back(make_int4(cc.child + k, hc[cc.child + k].begin, hc[cc.child + k].count, 0));
+        }
+        return;
+      }
+      if (hc[c].nchild == 0) {  // a leaf larger than a span: coincident points
+        too_big = true;
+        return;
+      }
+      const int first = (int)sroot.size();
+      for (int k = 0; k < hc[c].nchild; ++k) visit(hc[c].child + k);
+      mup.push_back(make_int4(c, first, (int)sroot.size(), 0));
+    };
+    for (int r = 0; r < pl.nsurf; ++r) visit(r);
+    if (too_big) {
+      pl.err = "a tree leaf holds more than 1024 Gauss points (coincident points)";
       PBTC_HIP(hipStreamSynchronize(st));
-      return PBTC_EWORKSPACE;
+      return PBTC_EMESH;
     }
+    pl.n_mchunks = (int64_t)mch.size();
+    pl.n_mup = (int64_t)mup.size();
     if (pl.n_units > pl.cap_units) {
       pl.cap_units = pl.n_units + pl.n_units / 8 + 1024;
       *need_retry = 1;
@@ -1247,8 +1264,12 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     if (!mch.empty())
       PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mchunks), mch.data(), 16 * mch.size(),
                               hipMemcpyHostToDevice, st));
-    PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_mcell), mcell.data(), 4 * mcell.size(),
-                            hipMemcpyHostToDevice, st));
+    if (!sroot.empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_mcell), sroot.data(), 4 * sroot.size(),
+                              hipMemcpyHostToDevice, st));
+    if (!mup.empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mpart), mup.data(), 16 * mup.size(),
+                              hipMemcpyHostToDevice, st));
     PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_units), units.data(), 16 * units.size(),
                             hipMemcpyHostToDevice, st));
     PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_uptr), uptr.data(), 4 * uptr.size(),
