@@ -140,10 +140,10 @@ def time_matvecs(torch, lib, pl, reps=10):
 
 
 def run_config(torch, lib, prob, tree, steps, warmup, fp64_steps, adjoint, precond=True,
-               eager_compare=True):
+               eager_compare=True, profile=8):
     """Timed figures of one workload (see the module docstring)."""
     dev = torch.device("cuda:0")
-    pl = make_plan(lib, prob, precision="fp32_refined", tol=1e-5, profile=8, **tree)
+    pl = make_plan(lib, prob, precision="fp32_refined", tol=1e-5, profile=profile, **tree)
     pl.setup()
     for _ in range(warmup):
         pl.solve(force_setup=True)
@@ -188,7 +188,6 @@ def run_config(torch, lib, prob, tree, steps, warmup, fp64_steps, adjoint, preco
         pe.setup()
         out["matvec_s_kernel_by_kernel"] = time_matvecs(torch, lib, pe)
         pe.solve()
-        t = time.perf_counter()
         re_ = pe.solve()
         out["solve_s_kernel_by_kernel"] = re_["t_solve_s"]
         del pe
@@ -365,6 +364,9 @@ def main():
                     help="adjoint (gradient) evaluations timed after the solves")
     ap.add_argument("--minimal", action="store_true",
                     help="only the timed FP32-refined steps (for counter collection)")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="kernel timing on every n-th FP32 operator evaluation (1: every "
+                         "evaluation launches kernel by kernel with the moment pass first)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU: the multi-GPU path (targets sharded across GPUs, "
@@ -402,7 +404,8 @@ def main():
         tune = {"seconds": time.perf_counter() - t, "chosen": tree, "candidates": len(rows)}
 
     if a.minimal:
-        pl = make_plan(lib, prob, precision="fp32_refined", tol=1e-5, profile=8, **tree)
+        pl = make_plan(lib, prob, precision="fp32_refined", tol=1e-5, profile=a.profile_every,
+                       **tree)
         pl.setup()
         for _ in range(a.warmup):
             pl.solve(force_setup=True)
@@ -419,7 +422,7 @@ def main():
         return 0
 
     head, results, pl = run_config(torch, lib, prob, tree, a.steps, a.warmup, a.fp64_steps,
-                                   a.adjoint)
+                                   a.adjoint, profile=a.profile_every)
     del pl
     rl = head["rooflines"]
     fwd = {k: v for k, v in rl.items() if not k.startswith("adj")}
@@ -446,11 +449,13 @@ def main():
         t = time.perf_counter()
         tree4, rows4 = autotune(lib.batch_problem(p4), budget=1e-4,
                                 base={"precision": "fp32_refined", "tol": 1e-5},
-                                ncrits=(128, 256), direct_belows=(-1,))
+                                ncrits=(64, 128, 256), direct_belows=(-1,))
         tune4 = {"seconds": time.perf_counter() - t, "chosen": tree4, "budget": 1e-4,
-                 "grid": "theta {0.4, 0.5, 0.6} x P {4, 6, 8}, then ncrit {128, 256}",
-                 "candidates": [{k: r[k] for k in ("theta", "P", "ncrit", "err_fp32",
-                                                   "matvec_s_fp32")} for r in rows4]}
+                 "grid": ("theta {0.4, 0.5, 0.6} x P {4, 6, 8}, then ncrit {64, 128, 256}, "
+                          "then P2P tile {256, 512, 1024} sources x M2P tile {16, 32, 64} cells"),
+                 "candidates": [{k: r[k] for k in ("theta", "P", "ncrit", "unit_sources",
+                                                   "unit_cells", "err_fp32", "matvec_s_fp32")}
+                                for r in rows4]}
         c4, _, _ = run_config(torch, lib, p4, tree4, 3, 1, 1, 1)
         c4["workload"] = d4
         c4["autotune"] = tune4

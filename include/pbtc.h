@@ -127,6 +127,11 @@ typedef struct {
                        so that each timed launch has the GPU alone */
   int precond;      /* PBTC_PREC_NONE or PBTC_PREC_BLOCK_DIAG (forward and
                        adjoint solves) */
+  int unit_sources; /* work tile of P2P: one wavefront takes a target group and
+                       a run of its near-list cells of at most this many
+                       sources (whole cells; 64..8192, 0 = 512) */
+  int unit_cells;   /* work tile of M2P: a target group and at most this many
+                       of its far cells (1..1024, 0 = 32) */
   int op_graph;     /* 1: every evaluation of A x (all surface-pair blocks of
                        all regions and systems) is replayed as ONE captured
                        HIP launch graph of its kernels, captured once per
@@ -204,7 +209,7 @@ int pbtc_set_charges(pbtc_problem* p, int region_id, const double* xyz, const do
  * direct_below=-1, tol=1e-5, restart=100, max_iter=1000,
  * precision=PBTC_FP32_REFINED, op=PBTC_OP_TREECODE, inner_tol=1e-6,
  * max_refine=10, validate_charges=1, profile=0, precond=PBTC_PREC_NONE,
- * op_graph=1. */
+ * unit_sources=0, unit_cells=0, op_graph=1. */
 int pbtc_params_default(pbtc_params* prm);
 
 /* Host-side checks only (no device work): parameter ranges; every region is

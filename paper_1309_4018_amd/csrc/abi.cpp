@@ -214,7 +214,8 @@ bool same_params(const pbtc_params& a, const pbtc_params& b) {
          a.max_iter == b.max_iter && a.precision == b.precision && a.op == b.op &&
          a.inner_tol == b.inner_tol && a.max_refine == b.max_refine &&
          a.validate_charges == b.validate_charges && a.profile == b.profile &&
-         a.precond == b.precond && a.op_graph == b.op_graph;
+         a.precond == b.precond && a.op_graph == b.op_graph &&
+         a.unit_sources == b.unit_sources && a.unit_cells == b.unit_cells;
 }
 
 // The merged plan of a batch (kept with plans[0] while the members stay the
@@ -376,6 +377,8 @@ int pbtc_params_default(pbtc_params* prm) {
   prm->validate_charges = 1;
   prm->profile = 0;
   prm->precond = PBTC_PREC_NONE;
+  prm->unit_sources = 0;
+  prm->unit_cells = 0;
   prm->op_graph = 1;
   return PBTC_OK;
 }

@@ -651,7 +651,7 @@ int adjoint_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       PBTC_HIP(hipMemcpy(nl.data(), wsp<int>(pl, pl.o_anear), 4 * pl.n_anear, hipMemcpyDeviceToHost));
     PBTC_HIP(hipMemcpy(hc.data(), wsp<Cell>(pl, pl.o_tcells), sizeof(Cell) * pl.n_tcells,
                        hipMemcpyDeviceToHost));
-    constexpr int kUnitSources = 512, kUnitCells = 32;  // as the forward units
+    const int kUnitSources = unit_sources(pl.prm), kUnitCells = unit_cells(pl.prm);
     std::vector<int4> units;
     std::vector<int> uptr;
     const bool tree = pl.prm.op == PBTC_OP_TREECODE;

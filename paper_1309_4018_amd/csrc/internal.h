@@ -27,6 +27,10 @@ constexpr int kMomSpan = 1024;   // sources per block of the direct moment pass
 constexpr int kMaxRule = 19;
 
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// work tiles of P2P (sources per unit) and M2P (cells per unit)
+inline int unit_sources(const pbtc_params& p) { return p.unit_sources > 0 ? p.unit_sources : 512; }
+inline int unit_cells(const pbtc_params& p) { return p.unit_cells > 0 ? p.unit_cells : 32; }
 // values per (cell, kernel slot) of the transposed operator's moments:
 // single layer to order P, the three double-layer gradient arrays to P + 1
 __host__ __device__ constexpr int adj_mom_len(int p) { return ncoef(p) + 3 * ncoef(p + 1); }
@@ -226,9 +230,11 @@ struct pbtc_plan_s {
   size_t o_qtab = 0;   // per region: first charge (nreg + 1 long long), eps (nreg double)
   size_t o_coul = 0;   // Coulomb energy per system (ncomp double)
   // moment pass: span cells (cell, first source, count), span roots in
-  // source order, upper cells (cell, first span root, end)
-  size_t o_mchunks = 0, o_mcell = 0, o_mpart = 0;
-  int64_t n_mchunks = 0, n_mup = 0;
+  // source order, upper cells (cell, first span root, end, first partial
+  // block) followed by the partial blocks (upper index, first span root,
+  // end), the partial moments of those blocks
+  size_t o_mchunks = 0, o_mcell = 0, o_mpart = 0, o_mupart = 0;
+  int64_t n_mchunks = 0, n_mup = 0, n_mupb = 0, cap_mup = 0;
   // direct moment pass of the transposed operator: chunks (cell, first
   // source, count, slot) and (cell x local slot, first chunk, end chunk)
   // pairs, per phase in [off[ph], off[ph + 1])

@@ -165,68 +165,73 @@ __global__ __launch_bounds__(kMomThreads) void k_p2m_cell(const int4* __restrict
   }
 }
 
-// binomial coefficient C(n, k) for n <= kMaxP
-__host__ __device__ constexpr int binom(int n, int k) {
-  int r = 1;
-  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
-  return r;
+// binomial coefficients C(n, k), n, k <= kMaxP
+struct Binom {
+  int c[kMaxP + 1][kMaxP + 1];
+  constexpr Binom() : c() {
+    for (int n = 0; n <= kMaxP; ++n) {
+      c[n][0] = 1;
+      for (int k = 1; k <= n; ++k) c[n][k] = c[n - 1][k - 1] + (k <= n - 1 ? c[n - 1][k] : 0);
+    }
+  }
+};
+__constant__ Binom kBinom = Binom();
+
+constexpr int kUpSpans = 8;  // span roots per work-group of the upper-cell pass
+
+// Partial moments of an upper cell from a run of at most kUpSpans of the span
+// roots inside it: upb = (upper index, first span root, end span root); one
+// thread per output coefficient (single- then double-layer half); the powers
+// of h and the binomial factors are formed term by term (no per-thread arrays).
+template <typename real, int P>
+__global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ upb,
+                                                     const int4* __restrict__ up,
+                                                     const int* __restrict__ sroot,
+                                                     const Cell* __restrict__ cells,
+                                                     const real* __restrict__ mom,
+                                                     real* __restrict__ part) {
+  constexpr int N = ncoef(P);
+  const int4 ub = upb[blockIdx.x];
+  const Cell& cu = cells[up[ub.x].x];
+  for (int k = threadIdx.x; k < 2 * N; k += 256) {
+    int a, b, c;
+    mindex_inv(k < N ? k : k - N, a, b, c);
+    const int half = k < N ? 0 : N;
+    real acc = 0;
+    for (int i = ub.y; i < ub.z; ++i) {
+      const int cs = sroot[i];
+      const Cell& cl = cells[cs];
+      const real hx = (real)(cl.cx - cu.cx), hy = (real)(cl.cy - cu.cy), hz = (real)(cl.cz - cu.cz);
+      const real* M = mom + (size_t)cs * 2 * N + half;
+      real s = 0, p1 = 1;
+      for (int j1 = a; j1 >= 0; --j1, p1 *= hx) {
+        real p2 = p1 * real(kBinom.c[a][j1]);
+        for (int j2 = b; j2 >= 0; --j2, p2 *= hy) {
+          const real f12 = p2 * real(kBinom.c[b][j2]);
+          real p3 = 1;
+          for (int j3 = c; j3 >= 0; --j3, p3 *= hz)
+            s += f12 * p3 * real(kBinom.c[c][j3]) * M[mindex(j1, j2, j3)];
+        }
+      }
+      acc += s;
+    }
+    part[(size_t)blockIdx.x * 2 * N + k] = acc;
+  }
 }
 
-// Moments of an upper cell u: the span roots sroot[up.y .. up.z) shifted to
-// its centre and added in order (deterministic).
+// mom[u] = sum of the upper cell's partials, in block order (deterministic);
+// up = (cell, first span root, end span root, first partial block)
 template <typename real, int P>
-__global__ __launch_bounds__(256) void k_mom_up(const int4* __restrict__ up,
-                                                const int* __restrict__ sroot,
-                                                const Cell* __restrict__ cells,
-                                                real* __restrict__ mom) {
-  constexpr int N = ncoef(P);
-  constexpr int KPT = (2 * N + 255) / 256;
-  __shared__ real hp[3][P + 1];
+__global__ __launch_bounds__(256) void k_mom_up_sum(const int4* __restrict__ up,
+                                                    const real* __restrict__ part,
+                                                    real* __restrict__ mom) {
+  constexpr int N2 = 2 * ncoef(P);
   const int4 u = up[blockIdx.x];
-  const Cell& cu = cells[u.x];
-  const int tid = threadIdx.x;
-  int kk[KPT][3];
-  real acc[KPT];
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = tid + 256 * q;
-    mindex_inv(k < 2 * N ? (k < N ? k : k - N) : 0, kk[q][0], kk[q][1], kk[q][2]);
-    acc[q] = 0;
-  }
-  for (int i = u.y; i < u.z; ++i) {
-    const int cs = sroot[i];
-    const Cell& c = cells[cs];
-    __syncthreads();  // the previous root's powers are no longer read
-    if (tid < 3) {
-      const double h = tid == 0 ? c.cx - cu.cx : tid == 1 ? c.cy - cu.cy : c.cz - cu.cz;
-      real v = 1;
-      for (int e = 0; e <= P; ++e) {
-        hp[tid][e] = v;
-        v *= (real)h;
-      }
-    }
-    __syncthreads();
-    const real* Ms = mom + (size_t)cs * 2 * N;
-#pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-      const int k = tid + 256 * q;
-      if (k >= 2 * N) continue;
-      const int a = kk[q][0], b = kk[q][1], cc = kk[q][2];
-      const real* M = k < N ? Ms : Ms + N;
-      real s = 0;
-      for (int j1 = 0; j1 <= a; ++j1)
-        for (int j2 = 0; j2 <= b; ++j2) {
-          const real f12 = real(binom(a, j1) * binom(b, j2)) * hp[0][a - j1] * hp[1][b - j2];
-          for (int j3 = 0; j3 <= cc; ++j3)
-            s += f12 * real(binom(cc, j3)) * hp[2][cc - j3] * M[mindex(j1, j2, j3)];
-        }
-      acc[q] += s;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = tid + 256 * q;
-    if (k < 2 * N) mom[(size_t)u.x * 2 * N + k] = acc[q];
+  const int nb = (u.z - u.y + kUpSpans - 1) / kUpSpans;
+  for (int k = threadIdx.x; k < N2; k += 256) {
+    real v = 0;
+    for (int j = 0; j < nb; ++j) v += part[(size_t)(u.w + j) * N2 + k];
+    mom[(size_t)u.x * N2 + k] = v;
   }
 }
 
@@ -558,15 +563,19 @@ static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<
   const int4* chunks = wsp<int4>(pl, pl.o_mchunks);
   const int* sroot = wsp<int>(pl, pl.o_mcell);
   const int4* up = wsp<int4>(pl, pl.o_mpart);
-  const unsigned nch = (unsigned)pl.n_mchunks, nup = (unsigned)pl.n_mup;
-#define PBTC_MOM(PP)                                                                          \
-  case PP:                                                                                    \
-    if (nch > 0)                                                                              \
-      hipLaunchKernelGGL((k_p2m_cell<real, PP>), dim3(nch), dim3(kMomThreads), 0, st, chunks, \
-                         cells, src, mom);                                                    \
-    if (nup > 0)                                                                              \
-      hipLaunchKernelGGL((k_mom_up<real, PP>), dim3(nup), dim3(256), 0, st, up, sroot, cells, \
-                         mom);                                                                \
+  const int4* upb = up + pl.n_mup;
+  real* part = wsp<real>(pl, pl.o_mupart);
+  const unsigned nch = (unsigned)pl.n_mchunks, nup = (unsigned)pl.n_mup, nupb = (unsigned)pl.n_mupb;
+#define PBTC_MOM(PP)                                                                             \
+  case PP:                                                                                       \
+    if (nch > 0)                                                                                 \
+      hipLaunchKernelGGL((k_p2m_cell<real, PP>), dim3(nch), dim3(kMomThreads), 0, st, chunks,    \
+                         cells, src, mom);                                                       \
+    if (nup > 0) {                                                                               \
+      hipLaunchKernelGGL((k_mom_up_part<real, PP>), dim3(nupb), dim3(256), 0, st, upb, up, sroot, \
+                         cells, mom, part);                                                      \
+      hipLaunchKernelGGL((k_mom_up_sum<real, PP>), dim3(nup), dim3(256), 0, st, up, part, mom);  \
+    }                                                                                            \
     break;
   switch (pl.P) {
     PBTC_MOM(2)

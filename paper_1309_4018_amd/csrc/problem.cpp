@@ -151,6 +151,10 @@ std::string validate_problem(const pbtc_problem& p, const pbtc_params& prm, int*
   if (prm.precond != PBTC_PREC_NONE && prm.precond != PBTC_PREC_BLOCK_DIAG)
     return fail(PBTC_EINVAL, "unknown precond");
   if (prm.op_graph != 0 && prm.op_graph != 1) return fail(PBTC_EINVAL, "op_graph must be 0 or 1");
+  if (prm.unit_sources != 0 && (prm.unit_sources < 64 || prm.unit_sources > 8192))
+    return fail(PBTC_EINVAL, "unit_sources must be 0 (auto) or in 64..8192");
+  if (prm.unit_cells != 0 && (prm.unit_cells < 1 || prm.unit_cells > 1024))
+    return fail(PBTC_EINVAL, "unit_cells must be 0 (auto) or in 1..1024");
   // regions
   const int nreg = (int)p.regions.size();
   if (nreg < 2) return fail(PBTC_EINVAL, "need at least two regions");

@@ -1184,7 +1184,7 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     // wavefront work units (enough of them to keep several waves per SIMD):
     // a P2P unit covers <= kUnitSources sources of one
     // item's near list (whole cells), an M2P unit <= kUnitCells far cells
-    constexpr int kUnitSources = 512, kUnitCells = 32;
+    const int kUnitSources = unit_sources(pl.prm), kUnitCells = unit_cells(pl.prm);
     std::vector<int4> units;
     std::vector<int> uptr;
     for (int ph = 0; ph < 2; ++ph)
@@ -1244,14 +1244,31 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       for (int k = 0; k < hc[c].nchild; ++k) visit(hc[c].child + k);
       mup.push_back(make_int4(c, first, (int)sroot.size(), 0));
     };
+    constexpr int kUpSpans = 8;  // span roots per partial block (operator.hip)
     for (int r = 0; r < pl.nsurf; ++r) visit(r);
     if (too_big) {
       pl.err = "a tree leaf holds more than 1024 Gauss points (coincident points)";
       PBTC_HIP(hipStreamSynchronize(st));
       return PBTC_EMESH;
     }
+    // partial blocks of every upper cell, consecutive (first in mup[].w)
+    std::vector<int4> mupb;
+    for (size_t i = 0; i < mup.size(); ++i) {
+      mup[i].w = (int)mupb.size();
+      for (int s0 = mup[i].y; s0 < mup[i].z; s0 += kUpSpans)
+        mupb.push_back(make_int4((int)i, s0, std::min(s0 + kUpSpans, mup[i].z), 0));
+    }
     pl.n_mchunks = (int64_t)mch.size();
     pl.n_mup = (int64_t)mup.size();
+    pl.n_mupb = (int64_t)mupb.size();
+    mup.insert(mup.end(), mupb.begin(), mupb.end());  // one table: upper cells, then blocks
+    if ((int64_t)mup.size() > pl.cap_mup) {
+      pl.cap_mup = (int64_t)mup.size() + (int64_t)mup.size() / 8 + 1024;
+      *need_retry = 1;
+      pl.err = "upper-cell moment blocks exceed the workspace estimate";
+      PBTC_HIP(hipStreamSynchronize(st));
+      return PBTC_EWORKSPACE;
+    }
     if (pl.n_units > pl.cap_units) {
       pl.cap_units = pl.n_units + pl.n_units / 8 + 1024;
       *need_retry = 1;

@@ -32,7 +32,8 @@ class Params(C.Structure):
         ("tol", C.c_double), ("restart", C.c_int), ("max_iter", C.c_int),
         ("precision", C.c_int), ("op", C.c_int), ("inner_tol", C.c_double),
         ("max_refine", C.c_int), ("validate_charges", C.c_int), ("profile", C.c_int),
-        ("precond", C.c_int), ("op_graph", C.c_int),
+        ("precond", C.c_int), ("unit_sources", C.c_int), ("unit_cells", C.c_int),
+        ("op_graph", C.c_int),
     ]
 
 
