@@ -180,9 +180,10 @@ __constant__ Binom kBinom = Binom();
 constexpr int kUpSpans = 8;  // span roots per work-group of the upper-cell pass
 
 // Partial moments of an upper cell from a run of at most kUpSpans of the span
-// roots inside it: upb = (upper index, first span root, end span root); one
-// thread per output coefficient (single- then double-layer half); the powers
-// of h and the binomial factors are formed term by term (no per-thread arrays).
+// roots inside it: upb = (upper index, first span root, end span root).  The
+// roots' moments are staged in LDS first (one coalesced load); then one thread
+// per output coefficient (single- then double-layer half) sums its terms, the
+// powers of h and the binomial factors formed term by term.
 template <typename real, int P>
 __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ upb,
                                                      const int4* __restrict__ up,
@@ -190,19 +191,31 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ up
                                                      const Cell* __restrict__ cells,
                                                      const real* __restrict__ mom,
                                                      real* __restrict__ part) {
-  constexpr int N = ncoef(P);
+  constexpr int N = ncoef(P), N2 = 2 * N;
+  __shared__ real sm[kUpSpans][N2];
+  __shared__ real sh[kUpSpans][3];
   const int4 ub = upb[blockIdx.x];
   const Cell& cu = cells[up[ub.x].x];
-  for (int k = threadIdx.x; k < 2 * N; k += 256) {
+  const int ns = ub.z - ub.y;
+  for (int i = threadIdx.x; i < ns * N2; i += 256) {
+    const int r = i / N2, k = i - r * N2;
+    sm[r][k] = mom[(size_t)sroot[ub.y + r] * N2 + k];
+  }
+  if (threadIdx.x < ns) {
+    const Cell& cl = cells[sroot[ub.y + threadIdx.x]];
+    sh[threadIdx.x][0] = (real)(cl.cx - cu.cx);
+    sh[threadIdx.x][1] = (real)(cl.cy - cu.cy);
+    sh[threadIdx.x][2] = (real)(cl.cz - cu.cz);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < N2; k += 256) {
     int a, b, c;
     mindex_inv(k < N ? k : k - N, a, b, c);
     const int half = k < N ? 0 : N;
     real acc = 0;
-    for (int i = ub.y; i < ub.z; ++i) {
-      const int cs = sroot[i];
-      const Cell& cl = cells[cs];
-      const real hx = (real)(cl.cx - cu.cx), hy = (real)(cl.cy - cu.cy), hz = (real)(cl.cz - cu.cz);
-      const real* M = mom + (size_t)cs * 2 * N + half;
+    for (int r = 0; r < ns; ++r) {
+      const real hx = sh[r][0], hy = sh[r][1], hz = sh[r][2];
+      const real* M = sm[r] + half;
       real s = 0, p1 = 1;
       for (int j1 = a; j1 >= 0; --j1, p1 *= hx) {
         real p2 = p1 * real(kBinom.c[a][j1]);
@@ -215,7 +228,7 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ up
       }
       acc += s;
     }
-    part[(size_t)blockIdx.x * 2 * N + k] = acc;
+    part[(size_t)blockIdx.x * N2 + k] = acc;
   }
 }
 
