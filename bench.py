@@ -173,6 +173,7 @@ def run_config(torch, lib, prob, tree, steps, warmup, fp64_steps, adjoint, preco
         "m2p_evals_per_matvec": last["n_m2p_evals"],
         "near_entries": last["n_near_entries"],
         "kernels_per_matvec": last["op_kernels"],
+        "work_tiles": {"p2p_sources": last["tile_sources"], "m2p_cells": last["tile_cells"]},
         "graph_launches_per_solve": last["op_graph_launches"],
         "setup_phase_s": dict(zip(
             ["sort", "octree", "lists", "near_columns", "host_tables", "near_values_precond_rhs"],
@@ -452,7 +453,8 @@ def main():
                                 ncrits=(64, 128, 256), direct_belows=(-1,))
         tune4 = {"seconds": time.perf_counter() - t, "chosen": tree4, "budget": 1e-4,
                  "grid": ("theta {0.4, 0.5, 0.6} x P {4, 6, 8}, then ncrit {64, 128, 256}, "
-                          "then P2P tile {256, 512, 1024} sources x M2P tile {16, 32, 64} cells"),
+                          "then P2P tile {128, 256, 512} sources x M2P tile {8, 16, 32} cells "
+                          "(from the automatic tiles)"),
                  "candidates": [{k: r[k] for k in ("theta", "P", "ncrit", "unit_sources",
                                                    "unit_cells", "err_fp32", "matvec_s_fp32")}
                                 for r in rows4]}

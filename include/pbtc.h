@@ -104,7 +104,7 @@ typedef struct {
   /* treecode (sec. 2.3) */
   double theta;  /* MAC: accept a cell when theta * r_tb > r_b */
   int P;         /* Taylor order: 2, 4, 6, 8 or 10 */
-  int ncrit;     /* split a cell holding >= ncrit sources (2..1024); 0 = automatic */
+  int ncrit;     /* split a cell holding >= ncrit sources (2..256); 0 = automatic */
   int direct_below; /* a MAC-accepted cell with fewer sources goes to P2P; -1 =
                        auto: per block, where P2P costs less than one M2P
                        evaluation of the block's kernels */
@@ -129,9 +129,12 @@ typedef struct {
                        adjoint solves) */
   int unit_sources; /* work tile of P2P: one wavefront takes a target group and
                        a run of its near-list cells of at most this many
-                       sources (whole cells; 64..8192, 0 = 512) */
+                       sources (whole cells; 64..8192); 0 = automatic: the
+                       largest of 512, 256, 128 that gives the launch ~1.5
+                       rounds of waves on the GPU (a short tail) */
   int unit_cells;   /* work tile of M2P: a target group and at most this many
-                       of its far cells (1..1024, 0 = 32) */
+                       of its far cells (1..1024); 0 = automatic: the largest
+                       of 32, 16, 8 by the same rule */
   int op_graph;     /* 1: every evaluation of A x (all surface-pair blocks of
                        all regions and systems) is replayed as ONE captured
                        HIP launch graph of its kernels, captured once per
@@ -185,6 +188,9 @@ typedef struct {
   double t_kernel_s[6];
   int n_kernel_launch[6];
   double kernel_flop[6];
+  /* the P2P and M2P work tiles the set-up used (params.unit_sources and
+   * unit_cells, or the automatic choice) */
+  int tile_sources, tile_cells;
 } pbtc_result;
 
 /* Library version; never fails. */

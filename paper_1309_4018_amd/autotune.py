@@ -8,7 +8,7 @@ Three kinds of parameters are chosen, in this order:
   marginally);
 * the work tiles of the P2P and M2P kernels: sources per P2P work unit and
   far cells per M2P work unit (speed only: the same sums in another order of
-  units).  The target-group size is not tuned: it is the wavefront width
+  units), starting from the library's automatic choice.  The target-group size is not tuned: it is the wavefront width
   (64), which keeps every list a wave walks wave-uniform (scalar loads of
   sources and moments); a smaller group would leave lanes idle.
 
@@ -52,8 +52,8 @@ SPEED_KEYS = ("ncrit", "direct_below", "unit_sources", "unit_cells")
 
 
 def autotune(problem, budget=1e-4, thetas=(0.4, 0.5, 0.6), orders=(4, 6, 8),
-             ncrits=(64, 128, 256), direct_belows=(-1,), unit_sources=(256, 512, 1024),
-             unit_cells=(16, 32, 64), device="cuda:0", seed=0, base=None):
+             ncrits=(64, 128, 256), direct_belows=(-1,), unit_sources=(128, 256, 512),
+             unit_cells=(8, 16, 32), device="cuda:0", seed=0, base=None):
     """Returns (best parameter dict, list of measured candidates).
 
     ``problem`` is a ``lib.Problem``; ``base`` extra parameters passed to
@@ -84,8 +84,9 @@ def autotune(problem, budget=1e-4, thetas=(0.4, 0.5, 0.6), orders=(4, 6, 8),
         rows.append(row)
         return row
 
+    # tiles start automatic (0: chosen by the library from the lists' sizes)
     speed = {"ncrit": ncrits[len(ncrits) // 2], "direct_below": direct_belows[0],
-             "unit_sources": 512, "unit_cells": 32}
+             "unit_sources": 0, "unit_cells": 0}
     first = [measure(t, p, speed) for t, p in itertools.product(thetas, orders)]
     ok = [r for r in first if r["err_fp32"] <= budget]
     if not ok:

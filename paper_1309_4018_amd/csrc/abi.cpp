@@ -130,6 +130,8 @@ void fill_sizes(const pbtc_plan_t* pl, pbtc_result* res) {
   res->n_dense_equiv = pl->dense_equiv;
   res->n_near_entries = (double)pl->n_nf;
   res->workspace_needed = pl->ws_bytes;
+  res->tile_sources = pl->tile_sources;
+  res->tile_cells = pl->tile_cells;
 }
 
 // Set-up on a workspace, growing capacity estimates as needed.

@@ -651,7 +651,8 @@ int adjoint_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       PBTC_HIP(hipMemcpy(nl.data(), wsp<int>(pl, pl.o_anear), 4 * pl.n_anear, hipMemcpyDeviceToHost));
     PBTC_HIP(hipMemcpy(hc.data(), wsp<Cell>(pl, pl.o_tcells), sizeof(Cell) * pl.n_tcells,
                        hipMemcpyDeviceToHost));
-    const int kUnitSources = unit_sources(pl.prm), kUnitCells = unit_cells(pl.prm);
+    // the forward operator's tiles (chosen at set-up for the same lists' sizes)
+    const int kUnitSources = pl.tile_sources, kUnitCells = pl.tile_cells;
     std::vector<int4> units;
     std::vector<int> uptr;
     const bool tree = pl.prm.op == PBTC_OP_TREECODE;

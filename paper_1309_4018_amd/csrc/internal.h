@@ -23,14 +23,26 @@ constexpr int kNearSlots = 128; // near-field columns per row kept by the single
 constexpr int kMaxLevels = 21;   // 63-bit Morton keys, 21 bits per axis
 constexpr int kMaxNk = 32;
 constexpr int kMomChunk = 128;   // sources staged at a time by the direct moment pass
-constexpr int kMomSpan = 1024;   // sources per block of the direct moment pass
+constexpr int kMomSpan = 1024;   // sources per block of the transposed operator's moment pass
+constexpr int kSpanSources = 256;  // largest cell whose moments one work-group forms from its sources
 constexpr int kMaxRule = 19;
 
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
-// work tiles of P2P (sources per unit) and M2P (cells per unit)
-inline int unit_sources(const pbtc_params& p) { return p.unit_sources > 0 ? p.unit_sources : 512; }
-inline int unit_cells(const pbtc_params& p) { return p.unit_cells > 0 ? p.unit_cells : 32; }
+// Work tiles of P2P (sources per unit) and M2P (far cells per unit).  Left
+// automatic (0), a tile is the largest of (512, 256, 128) sources or (32, 16,
+// 8) cells whose units still fill every SIMD with waves for ~1.5 rounds
+// (kUnitRounds x the waves the GPU holds at once), so that the launch's tail
+// -- waves finishing at different times -- is short; `work(t)` returns the
+// number of units a tile t gives.
+constexpr double kUnitRounds = 1.5;
+template <typename F>
+int auto_tile(int fixed, const int (&choices)[3], double waves_resident, F work) {
+  if (fixed > 0) return fixed;
+  for (int t : choices)
+    if (work(t) >= kUnitRounds * waves_resident) return t;
+  return choices[2];
+}
 // values per (cell, kernel slot) of the transposed operator's moments:
 // single layer to order P, the three double-layer gradient arrays to P + 1
 __host__ __device__ constexpr int adj_mom_len(int p) { return ncoef(p) + 3 * ncoef(p + 1); }
@@ -356,6 +368,7 @@ struct pbtc_plan_s {
   // wavefront work units: [phase][kernel set][0 = P2P, 1 = M2P]
   pbtc::UnitSet units[2][pbtc::KS_COUNT][2];
   int64_t cap_units = 0, n_units = 0, n_uptr = 0;
+  int tile_sources = 512, tile_cells = 32;  // work tiles of the last set-up
   size_t o_units = 0, o_uptr = 0, o_partial = 0;
   // transposed operator: units, slot and block tables
   pbtc::UnitSet aunits[2][pbtc::KS_COUNT][2];

@@ -57,7 +57,7 @@ __global__ void k_prep(int64_t ngp, const double* __restrict__ gx, const double*
 // ------------------------------------------------------------- moments
 // Moments of every cell about its centre c (Eq. multexp):
 //   M_SL[k] = sum q (y - c)^k,   M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d).
-// A span root is a cell of at most kMomSpan sources whose parent has more
+// A span root is a cell of at most kSpanSources sources whose parent has more
 // (or a tree root that small); every cell of a span root's subtree takes one
 // work-group that computes its moments directly from its own (Morton-
 // contiguous) sources, staged through LDS kMomChunk at a time.  The work-
@@ -194,6 +194,7 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ up
   constexpr int N = ncoef(P), N2 = 2 * N;
   __shared__ real sm[kUpSpans][N2];
   __shared__ real sh[kUpSpans][3];
+  __shared__ real bin[P + 1][P + 1];  // binomials (LDS: per-lane indices)
   const int4 ub = upb[blockIdx.x];
   const Cell& cu = cells[up[ub.x].x];
   const int ns = ub.z - ub.y;
@@ -207,6 +208,8 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ up
     sh[threadIdx.x][1] = (real)(cl.cy - cu.cy);
     sh[threadIdx.x][2] = (real)(cl.cz - cu.cz);
   }
+  for (int i = threadIdx.x; i < (P + 1) * (P + 1); i += 256)
+    bin[i / (P + 1)][i % (P + 1)] = real(kBinom.c[i / (P + 1)][i % (P + 1)]);
   __syncthreads();
   for (int k = threadIdx.x; k < N2; k += 256) {
     int a, b, c;
@@ -218,12 +221,12 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ up
       const real* M = sm[r] + half;
       real s = 0, p1 = 1;
       for (int j1 = a; j1 >= 0; --j1, p1 *= hx) {
-        real p2 = p1 * real(kBinom.c[a][j1]);
+        real p2 = p1 * bin[a][j1];
         for (int j2 = b; j2 >= 0; --j2, p2 *= hy) {
-          const real f12 = p2 * real(kBinom.c[b][j2]);
+          const real f12 = p2 * bin[b][j2];
           real p3 = 1;
           for (int j3 = c; j3 >= 0; --j3, p3 *= hz)
-            s += f12 * p3 * real(kBinom.c[c][j3]) * M[mindex(j1, j2, j3)];
+            s += f12 * p3 * bin[c][j3] * M[mindex(j1, j2, j3)];
         }
       }
       acc += s;

@@ -137,8 +137,8 @@ std::string validate_problem(const pbtc_problem& p, const pbtc_params& prm, int*
   if (!(prm.theta > 0.0 && prm.theta < 1.0)) return fail(PBTC_EINVAL, "theta must be in (0, 1)");
   if (prm.P != 2 && prm.P != 4 && prm.P != 6 && prm.P != 8 && prm.P != 10)
     return fail(PBTC_EINVAL, "P must be 2, 4, 6, 8 or 10");
-  if (prm.ncrit < 0 || prm.ncrit == 1 || prm.ncrit > kMomSpan)
-    return fail(PBTC_EINVAL, "ncrit must be 0 (auto) or in 2..1024");
+  if (prm.ncrit < 0 || prm.ncrit == 1 || prm.ncrit > kSpanSources)
+    return fail(PBTC_EINVAL, "ncrit must be 0 (auto) or in 2..256");
   if (!(prm.tol > 0.0 && prm.tol < 1.0)) return fail(PBTC_EINVAL, "tol must be in (0, 1)");
   if (prm.restart < 1 || prm.restart > 256) return fail(PBTC_EINVAL, "restart must be in 1..256");
   if (prm.max_iter < 1) return fail(PBTC_EINVAL, "max_iter must be >= 1");

@@ -1184,7 +1184,34 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     // wavefront work units (enough of them to keep several waves per SIMD):
     // a P2P unit covers <= kUnitSources sources of one
     // item's near list (whole cells), an M2P unit <= kUnitCells far cells
-    const int kUnitSources = unit_sources(pl.prm), kUnitCells = unit_cells(pl.prm);
+    int n_cu = 256;
+    {
+      int dev = 0;
+      if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    const double resident = 32.0 * std::max(n_cu, 1);  // 4 SIMDs x 8 waves per CU
+    auto p2p_units = [&](int t) {
+      double u = 0.0;
+      for (int64_t it = 0; it < pl.nitems; ++it) {
+        if (pl.blocks[pl.item_block[it]].reaction) continue;
+        double src = 0.0;
+        for (long long e = np_[it]; e < np_[it + 1]; ++e) src += hc[nl[e]].count;
+        u += std::ceil(src / t);
+      }
+      return u;
+    };
+    auto m2p_units = [&](int t) {
+      double u = 0.0;
+      for (int64_t it = 0; it < pl.nitems; ++it)
+        if (!pl.blocks[pl.item_block[it]].reaction)
+          u += std::ceil((double)(fp_[it + 1] - fp_[it]) / t);
+      return u;
+    };
+    const int kUnitSources = auto_tile(pl.prm.unit_sources, {512, 256, 128}, resident, p2p_units);
+    const int kUnitCells = auto_tile(pl.prm.unit_cells, {32, 16, 8}, resident, m2p_units);
+    pl.tile_sources = kUnitSources;
+    pl.tile_cells = kUnitCells;
     std::vector<int4> units;
     std::vector<int> uptr;
     for (int ph = 0; ph < 2; ++ph)
@@ -1218,14 +1245,14 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     pl.n_units = (int64_t)units.size();
     pl.n_uptr = (int64_t)uptr.size();
 
-    // moment pass: span roots (at most kMomSpan sources, parent larger), the
+    // moment pass: span roots (at most kSpanSources sources, parent larger), the
     // cells of their subtrees span by span, and the upper cells with the run
     // of span roots inside them (children visited in source order)
     std::vector<int4> mch, mup;
     std::vector<int> sroot;
     bool too_big = false;
     std::function<void(int)> visit = [&](int c) {
-      if (hc[c].count <= kMomSpan) {
+      if (hc[c].count <= kSpanSources) {
         sroot.push_back(c);
         const size_t first = mch.size();
         mch.push_back(make_int4(c, hc[c].begin, hc[c].count, 0));
@@ -1247,7 +1274,7 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     constexpr int kUpSpans = 8;  // span roots per partial block (operator.hip)
     for (int r = 0; r < pl.nsurf; ++r) visit(r);
     if (too_big) {
-      pl.err = "a tree leaf holds more than 1024 Gauss points (coincident points)";
+      pl.err = "a tree leaf holds more than 256 Gauss points (coincident points)";
       PBTC_HIP(hipStreamSynchronize(st));
       return PBTC_EMESH;
     }

@@ -54,6 +54,7 @@ class Result(C.Structure):
         ("op_kernels", C.c_int), ("op_graph_launches", C.c_int),
         ("t_kernel_s", C.c_double * 6), ("n_kernel_launch", C.c_int * 6),
         ("kernel_flop", C.c_double * 6),
+        ("tile_sources", C.c_int), ("tile_cells", C.c_int),
     ]
 
     def as_dict(self):
