@@ -379,6 +379,38 @@ int pbtc_set_charge_values(pbtc_plan_t* plan, const double* q);
 int pbtc_triangle_rule(int K, double* bary, double* weights);
 int pbtc_gauss_legendre(int n, double* nodes, double* weights);
 
+/* Sizes of the source octrees and forward interaction lists (pbtc_get_tree). */
+typedef struct {
+  int64_t n_cells, n_gauss_points, n_targets, n_groups, n_items, n_near, n_far;
+  int n_surfaces, ncrit;
+} pbtc_tree_sizes;
+
+/* The octrees over the Gauss points and the forward interaction lists of the
+ * set-up on d_workspace (sec. 2.3: cells split while they hold ncrit or more
+ * points; Eq. MAC), copied to host buffers for checking; synchronises the
+ * stream.  sizes is required; every buffer may be NULL (then skipped):
+ *   cells        n_cells x 9 FP64: centre x, y, z, half edge, r_b (largest
+ *                centre-point distance), first Gauss point, count, first
+ *                child, number of children (0: a leaf); cells of all
+ *                surfaces, surface s's root is cell s
+ *   gauss_points n_gauss_points x 3: the Gauss points in tree order
+ *   surface_gp   n_surfaces x 2 int64: each surface's range of them
+ *   targets      n_targets x 3: targets (collocation points, then charges)
+ *                in group order
+ *   groups       n_groups x 6 FP64: bounding sphere (x, y, z, radius), first
+ *                target, number of targets of every target group
+ *   items        n_items x 4 int64 (one per block and target group): the
+ *                source surface's root cell, the group, the block's P2P
+ *                threshold (MAC-accepted cells with fewer points are P2P),
+ *                the block
+ *   near_ptr, far_ptr  n_items + 1 int64 offsets into near / far (int32
+ *                cell ids)
+ * EINVAL without a set-up of this plan on d_workspace. */
+int pbtc_get_tree(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, pbtc_tree_sizes* sizes,
+                  double* cells, double* gauss_points, int64_t* surface_gp, double* targets,
+                  double* groups, int64_t* items, int64_t* near_ptr, int32_t* near_cells,
+                  int64_t* far_ptr, int32_t* far_cells);
+
 /* Message of the last error of `plan` (or of the calling thread when plan
  * is NULL).  The pointer stays valid until the next call on that plan. */
 const char* pbtc_last_error(const pbtc_plan_t* plan);

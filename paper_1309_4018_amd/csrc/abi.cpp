@@ -10,7 +10,9 @@
 #include <new>
 #include <unordered_map>
 
+#include "device_util.h"
 #include "internal.h"
+#include "taylor.h"
 
 namespace pbtc {
 bool triangle_rule(int k, double* bary, double* w);
@@ -643,6 +645,110 @@ int pbtc_backward(pbtc_plan_t* plan, void* d_workspace, size_t bytes, void* hip_
     std::memset(r, 0, sizeof(*r));
     fill_sizes(plan, r);
     return device_backward(*plan, (hipStream_t)hip_stream, gE, dE_dq, dE_dkappa, dE_deps, r);
+  });
+}
+
+int pbtc_get_tree(pbtc_plan_t* plan, void* d_workspace, void* hip_stream, pbtc_tree_sizes* sizes,
+                  double* cells, double* gauss_points, int64_t* surface_gp, double* targets,
+                  double* groups, int64_t* items, int64_t* near_ptr, int32_t* near_cells,
+                  int64_t* far_ptr, int32_t* far_cells) {
+  if (!plan || !sizes) return fail_global(PBTC_EINVAL, "NULL argument");
+  return guarded(plan, [&] {
+    if (!ready(plan, d_workspace))
+      return fail_plan(plan, PBTC_EINVAL, "workspace not set up for this plan (call pbtc_setup)");
+    pbtc_plan_t& pl = *plan;
+    hipStream_t st = (hipStream_t)hip_stream;
+    sizes->n_cells = pl.n_cells;
+    sizes->n_gauss_points = pl.ngp;
+    sizes->n_targets = pl.ntgt;
+    sizes->n_groups = pl.ngrp;
+    sizes->n_items = pl.nitems;
+    sizes->n_near = pl.n_near;
+    sizes->n_far = pl.n_far;
+    sizes->n_surfaces = pl.nsurf;
+    sizes->ncrit = pl.ncrit;
+    auto dev = [&](size_t off) { return static_cast<const char*>(pl.ws) + off; };
+    auto get = [&](void* dst, size_t off, size_t bytes) -> int {
+      if (bytes == 0) return PBTC_OK;
+      PBTC_HIP(hipMemcpyAsync(dst, dev(off), bytes, hipMemcpyDeviceToHost, st));
+      return PBTC_OK;
+    };
+    int rc = PBTC_OK;
+    std::vector<Cell> hc;
+    if (cells) {
+      hc.resize(pl.n_cells);
+      rc = get(hc.data(), pl.o_cells, sizeof(Cell) * pl.n_cells);
+    }
+    std::vector<double> x, y, z;
+    if (!rc && gauss_points) {
+      x.resize(pl.ngp), y.resize(pl.ngp), z.resize(pl.ngp);
+      rc = get(x.data(), pl.o_gx, 8 * pl.ngp);
+      if (!rc) rc = get(y.data(), pl.o_gy, 8 * pl.ngp);
+      if (!rc) rc = get(z.data(), pl.o_gz, 8 * pl.ngp);
+    }
+    std::vector<double> tx, ty, tz;
+    if (!rc && targets) {
+      tx.resize(pl.ntgt), ty.resize(pl.ntgt), tz.resize(pl.ntgt);
+      rc = get(tx.data(), pl.o_tx, 8 * pl.ntgt);
+      if (!rc) rc = get(ty.data(), pl.o_ty, 8 * pl.ntgt);
+      if (!rc) rc = get(tz.data(), pl.o_tz, 8 * pl.ntgt);
+    }
+    std::vector<double> gs;
+    if (!rc && groups) {
+      gs.resize(4 * pl.ngrp);
+      rc = get(gs.data(), pl.o_grp, 32 * pl.ngrp);
+    }
+    std::vector<long long> np_, fp_;
+    if (!rc && near_ptr) {
+      np_.resize(pl.nitems + 1);
+      rc = get(np_.data(), pl.o_near_ptr, 8 * (pl.nitems + 1));
+    }
+    if (!rc && far_ptr) {
+      fp_.resize(pl.nitems + 1);
+      rc = get(fp_.data(), pl.o_far_ptr, 8 * (pl.nitems + 1));
+    }
+    if (!rc && near_cells) rc = get(near_cells, pl.o_near, 4 * pl.n_near);
+    if (!rc && far_cells) rc = get(far_cells, pl.o_far, 4 * pl.n_far);
+    if (rc) return rc;
+    PBTC_HIP(hipStreamSynchronize(st));
+    for (int64_t c = 0; c < (int64_t)hc.size(); ++c) {
+      const Cell& q = hc[c];
+      double* o = cells + 9 * c;
+      o[0] = q.cx, o[1] = q.cy, o[2] = q.cz, o[3] = q.h, o[4] = q.rb;
+      o[5] = q.begin, o[6] = q.count, o[7] = q.nchild > 0 ? q.child : -1, o[8] = q.nchild;
+    }
+    for (int64_t i = 0; i < (int64_t)x.size(); ++i)
+      gauss_points[3 * i] = x[i], gauss_points[3 * i + 1] = y[i], gauss_points[3 * i + 2] = z[i];
+    if (surface_gp)
+      for (int sf = 0; sf < pl.nsurf; ++sf)
+        surface_gp[2 * sf] = pl.gp_off[sf], surface_gp[2 * sf + 1] = pl.gp_off[sf + 1];
+    for (int64_t i = 0; i < (int64_t)tx.size(); ++i)
+      targets[3 * i] = tx[i], targets[3 * i + 1] = ty[i], targets[3 * i + 2] = tz[i];
+    if (groups)
+      for (const TargetSet& ts : pl.tsets)
+        for (int64_t g = 0; g < ts.ngrp; ++g) {
+          double* o = groups + 6 * (ts.grp_off + g);
+          const double* gsp = gs.data() + 4 * (ts.grp_off + g);
+          o[0] = gsp[0], o[1] = gsp[1], o[2] = gsp[2], o[3] = gsp[3];
+          o[4] = (double)(ts.off + g * kGroup);
+          o[5] = (double)std::min<int64_t>(kGroup, ts.n - g * kGroup);
+        }
+    if (items)
+      for (int64_t it = 0; it < pl.nitems; ++it) {
+        const int bi = pl.item_block[it];
+        const Block& b = pl.blocks[bi];
+        const TargetSet& ts = pl.tsets[b.t];
+        const int db = pl.prm.direct_below >= 0
+                           ? pl.prm.direct_below
+                           : (int)std::lround(0.7 * m2p_flop_per_eval(pl.P, b.ks) / p2p_flop_per_pair(b.ks));
+        items[4 * it] = b.s;
+        items[4 * it + 1] = ts.grp_off + (it - b.item_off);
+        items[4 * it + 2] = db;
+        items[4 * it + 3] = bi;
+      }
+    for (size_t i = 0; i < np_.size(); ++i) near_ptr[i] = np_[i];
+    for (size_t i = 0; i < fp_.size(); ++i) far_ptr[i] = fp_[i];
+    return PBTC_OK;
   });
 }
 

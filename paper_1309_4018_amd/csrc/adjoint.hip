@@ -996,13 +996,21 @@ static int transpose_impl(pbtc_plan_t& pl, hipStream_t st, const double* lam, do
   return PBTC_OK;
 }
 
+void compute_layout(pbtc_plan_t& pl);
+
 static int ensure_adjoint(pbtc_plan_t& pl, hipStream_t st) {
   if (pl.adj_done) return PBTC_OK;
   int retry = 0;
   const int rc = adjoint_setup(pl, st, &retry);
-  if (rc == PBTC_EWORKSPACE && retry)
+  if (rc == PBTC_EWORKSPACE && retry) {
+    // the grown capacities move every array: the workspace must be set up
+    // (and the forward system solved) again at the new size
+    compute_layout(pl);
+    pl.setup_done = false;
+    pl.dev_solved = false;
     pl.err = "workspace too small for the transposed operator: " + pl.err +
-             " (grow it to pbtc_result.workspace_needed and call again)";
+             " (grow it to pbtc_result.workspace_needed, solve again and call again)";
+  }
   return rc;
 }
 

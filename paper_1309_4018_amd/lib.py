@@ -25,6 +25,12 @@ _ERRNAMES = {EINVAL: "EINVAL", EMESH: "EMESH", ECHARGE: "ECHARGE", EWORKSPACE: "
              EDEVICE: "EDEVICE", ENOCONV: "ENOCONV", EHOST: "EHOST"}
 
 
+class TreeSizes(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_gauss_points", C.c_int64), ("n_targets", C.c_int64),
+                ("n_groups", C.c_int64), ("n_items", C.c_int64), ("n_near", C.c_int64),
+                ("n_far", C.c_int64), ("n_surfaces", C.c_int), ("ncrit", C.c_int)]
+
+
 class Params(C.Structure):
     _fields_ = [
         ("K", C.c_int), ("K_fine", C.c_int), ("N_k", C.c_int), ("thres", C.c_double),
@@ -100,6 +106,8 @@ _EXPORTS = {
     "pbtc_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pbtc_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_double,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Result)]),
+    "pbtc_get_tree": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(TreeSizes)]
+                      + [C.c_void_p] * 10),
     "pbtc_get_systems": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p,
                                    C.c_void_p]),
     "pbtc_set_charge_values": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -340,8 +348,16 @@ class Plan:
             raise ValueError("x has the wrong length")
         yd = torch.empty_like(xd)
         fn = self.lib.pbtc_matvec_transpose if transpose else self.lib.pbtc_matvec
-        check(fn(self.h, C.c_void_p(self.ws.data_ptr()), self.stream, C.c_void_p(xd.data_ptr()),
-                 C.c_void_p(yd.data_ptr()), int(precision)), self.h)
+        for _ in range(3):
+            code = fn(self.h, C.c_void_p(self.ws.data_ptr()), self.stream,
+                      C.c_void_p(xd.data_ptr()), C.c_void_p(yd.data_ptr()), int(precision))
+            if code == EWORKSPACE and transpose:
+                # the transposed operator needs more room: set up again at the
+                # grown layout (the workspace grows on demand)
+                self.setup()
+                continue
+            break
+        check(code, self.h)
         return yd
 
     def precond_apply(self, x, transpose=False):
@@ -374,6 +390,31 @@ class Plan:
             code = call()
         check(code, self.h)
         return tot.value, per[:n.value]
+
+    def tree(self):
+        """Octrees and forward interaction lists of the set-up (host copies)."""
+        sz = TreeSizes()
+        ws = C.c_void_p(self.ws.data_ptr())
+        nulls = [None] * 10
+        check(self.lib.pbtc_get_tree(self.h, ws, self.stream, C.byref(sz), *nulls), self.h)
+        out = {
+            "cells": np.empty((sz.n_cells, 9)),
+            "gauss_points": np.empty((sz.n_gauss_points, 3)),
+            "surface_gp": np.empty((sz.n_surfaces, 2), dtype=np.int64),
+            "targets": np.empty((sz.n_targets, 3)),
+            "groups": np.empty((sz.n_groups, 6)),
+            "items": np.empty((sz.n_items, 4), dtype=np.int64),
+            "near_ptr": np.empty(sz.n_items + 1, dtype=np.int64),
+            "near": np.empty(max(sz.n_near, 1), dtype=np.int32),
+            "far_ptr": np.empty(sz.n_items + 1, dtype=np.int64),
+            "far": np.empty(max(sz.n_far, 1), dtype=np.int32),
+        }
+        keys = ["cells", "gauss_points", "surface_gp", "targets", "groups", "items", "near_ptr",
+                "near", "far_ptr", "far"]
+        check(self.lib.pbtc_get_tree(self.h, ws, self.stream, C.byref(sz),
+                                     *[_ptr(out[k]) for k in keys]), self.h)
+        out["ncrit"] = sz.ncrit
+        return out
 
     def rhs(self):
         torch = self.torch
