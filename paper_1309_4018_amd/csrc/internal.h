@@ -241,12 +241,11 @@ struct pbtc_plan_s {
   size_t o_flags = 0;  // device status flags (16 int)
   size_t o_qtab = 0;   // per region: first charge (nreg + 1 long long), eps (nreg double)
   size_t o_coul = 0;   // Coulomb energy per system (ncomp double)
-  // moment pass: span cells (cell, first source, count), span roots in
-  // source order, upper cells (cell, first span root, end, first partial
-  // block) followed by the partial blocks (upper index, first span root,
-  // end), the partial moments of those blocks
-  size_t o_mchunks = 0, o_mcell = 0, o_mpart = 0, o_mupart = 0;
-  int64_t n_mchunks = 0, n_mup = 0, n_mupb = 0, cap_mup = 0;
+  // moment pass: span cells (cell, first source, count), the upper cells by
+  // level, deepest first, and where each level starts (+ end)
+  size_t o_mchunks = 0, o_mcell = 0;
+  int64_t n_mchunks = 0;
+  std::vector<int> up_level;
   // direct moment pass of the transposed operator: chunks (cell, first
   // source, count, slot) and (cell x local slot, first chunk, end chunk)
   // pairs, per phase in [off[ph], off[ph + 1])

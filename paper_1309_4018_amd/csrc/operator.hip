@@ -63,9 +63,10 @@ __global__ void k_prep(int64_t ngp, const double* __restrict__ gx, const double*
 // contiguous) sources, staged through LDS kMomChunk at a time.  The work-
 // groups of one span are consecutive in a list that is dealt to the XCDs in
 // contiguous runs, so that a span's sources come from HBM once and from that
-// XCD's L2 for the deeper cells.  A larger (upper) cell sums the moments of
-// the span roots inside it shifted to its own centre by the multi-index
-// binomial theorem (sec. 2.3: moments shifted to the parents):
+// XCD's L2 for the deeper cells.  The larger (upper) cells follow level by
+// level, bottom-up: each adds its children's moments shifted to its own
+// centre by the multi-index binomial theorem (sec. 2.3: moments shifted to
+// the parents and added),
 //   (y - c_u)^k = sum_{j <= k} C(k, j) h^(k - j) (y - c_s)^j,   h = c_s - c_u,
 // which holds for both moment kinds (the double layer is a linear map of the
 // same monomials), so upper cells never re-read the sources.
@@ -177,77 +178,64 @@ struct Binom {
 };
 __constant__ Binom kBinom = Binom();
 
-constexpr int kUpSpans = 8;  // span roots per work-group of the upper-cell pass
-
-// Partial moments of an upper cell from a run of at most kUpSpans of the span
-// roots inside it: upb = (upper index, first span root, end span root).  The
-// roots' moments are staged in LDS first (one coalesced load); then one thread
-// per output coefficient (single- then double-layer half) sums its terms, the
-// powers of h and the binomial factors formed term by term.
+// Moments of the upper cells of one tree level (bottom-up, one launch per
+// level): a cell's moments are the sum of its children's (span cells or upper
+// cells of the level below, both final), each shifted to the cell's centre.
+// The children's moments, the powers of their offsets h and the binomials are
+// staged in LDS; one thread per output coefficient walks its terms
+// j <= k in one flat loop (the lanes of a wave differ in k, so nested loops
+// over (j1, j2, j3) would run the union of their bounds).
 template <typename real, int P>
-__global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ upb,
-                                                     const int4* __restrict__ up,
-                                                     const int* __restrict__ sroot,
-                                                     const Cell* __restrict__ cells,
-                                                     const real* __restrict__ mom,
-                                                     real* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_m2m_up(const int* __restrict__ ucells,
+                                                const Cell* __restrict__ cells,
+                                                real* __restrict__ mom) {
   constexpr int N = ncoef(P), N2 = 2 * N;
-  __shared__ real sm[kUpSpans][N2];
-  __shared__ real sh[kUpSpans][3];
-  __shared__ real bin[P + 1][P + 1];  // binomials (LDS: per-lane indices)
-  const int4 ub = upb[blockIdx.x];
-  const Cell& cu = cells[up[ub.x].x];
-  const int ns = ub.z - ub.y;
-  for (int i = threadIdx.x; i < ns * N2; i += 256) {
+  __shared__ real sm[8][N2];
+  __shared__ real hp[8][3][P + 1];
+  __shared__ real bin[P + 1][P + 1];
+  const int u = ucells[blockIdx.x];
+  const Cell& cu = cells[u];
+  const int nch = cu.nchild, c0 = cu.child;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < nch * N2; i += 256) {
     const int r = i / N2, k = i - r * N2;
-    sm[r][k] = mom[(size_t)sroot[ub.y + r] * N2 + k];
+    sm[r][k] = mom[(size_t)(c0 + r) * N2 + k];
   }
-  if (threadIdx.x < ns) {
-    const Cell& cl = cells[sroot[ub.y + threadIdx.x]];
-    sh[threadIdx.x][0] = (real)(cl.cx - cu.cx);
-    sh[threadIdx.x][1] = (real)(cl.cy - cu.cy);
-    sh[threadIdx.x][2] = (real)(cl.cz - cu.cz);
+  if (tid < 3 * nch) {
+    const int r = tid / 3, d = tid - 3 * r;
+    const Cell& ch = cells[c0 + r];
+    const double h = d == 0 ? ch.cx - cu.cx : d == 1 ? ch.cy - cu.cy : ch.cz - cu.cz;
+    real v = 1;
+    for (int e = 0; e <= P; ++e) {
+      hp[r][d][e] = v;
+      v *= (real)h;
+    }
   }
-  for (int i = threadIdx.x; i < (P + 1) * (P + 1); i += 256)
+  for (int i = tid; i < (P + 1) * (P + 1); i += 256)
     bin[i / (P + 1)][i % (P + 1)] = real(kBinom.c[i / (P + 1)][i % (P + 1)]);
   __syncthreads();
-  for (int k = threadIdx.x; k < N2; k += 256) {
+  for (int k = tid; k < N2; k += 256) {
     int a, b, c;
     mindex_inv(k < N ? k : k - N, a, b, c);
     const int half = k < N ? 0 : N;
+    const int nt = (a + 1) * (b + 1) * (c + 1);
     real acc = 0;
-    for (int r = 0; r < ns; ++r) {
-      const real hx = sh[r][0], hy = sh[r][1], hz = sh[r][2];
+    for (int r = 0; r < nch; ++r) {
       const real* M = sm[r] + half;
-      real s = 0, p1 = 1;
-      for (int j1 = a; j1 >= 0; --j1, p1 *= hx) {
-        real p2 = p1 * bin[a][j1];
-        for (int j2 = b; j2 >= 0; --j2, p2 *= hy) {
-          const real f12 = p2 * bin[b][j2];
-          real p3 = 1;
-          for (int j3 = c; j3 >= 0; --j3, p3 *= hz)
-            s += f12 * p3 * bin[c][j3] * M[mindex(j1, j2, j3)];
-        }
+      real s = 0;
+      int j1 = 0, j2 = 0, j3 = 0;
+      for (int t = 0; t < nt; ++t) {
+        s += (bin[a][j1] * hp[r][0][a - j1]) * (bin[b][j2] * hp[r][1][b - j2]) *
+             (bin[c][j3] * hp[r][2][c - j3]) * M[mindex(j1, j2, j3)];
+        // next (j1, j2, j3), j3 fastest
+        const bool w3 = j3 == c, w2 = w3 && j2 == b;
+        j3 = w3 ? 0 : j3 + 1;
+        j2 = w2 ? 0 : (w3 ? j2 + 1 : j2);
+        j1 = w2 ? j1 + 1 : j1;
       }
       acc += s;
     }
-    part[(size_t)blockIdx.x * N2 + k] = acc;
-  }
-}
-
-// mom[u] = sum of the upper cell's partials, in block order (deterministic);
-// up = (cell, first span root, end span root, first partial block)
-template <typename real, int P>
-__global__ __launch_bounds__(256) void k_mom_up_sum(const int4* __restrict__ up,
-                                                    const real* __restrict__ part,
-                                                    real* __restrict__ mom) {
-  constexpr int N2 = 2 * ncoef(P);
-  const int4 u = up[blockIdx.x];
-  const int nb = (u.z - u.y + kUpSpans - 1) / kUpSpans;
-  for (int k = threadIdx.x; k < N2; k += 256) {
-    real v = 0;
-    for (int j = 0; j < nb; ++j) v += part[(size_t)(u.w + j) * N2 + k];
-    mom[(size_t)u.x * N2 + k] = v;
+    mom[(size_t)u * N2 + k] = acc;
   }
 }
 
@@ -577,21 +565,17 @@ template <typename real>
 static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<real>* src) {
   const Cell* cells = wsp<Cell>(pl, pl.o_cells);
   const int4* chunks = wsp<int4>(pl, pl.o_mchunks);
-  const int* sroot = wsp<int>(pl, pl.o_mcell);
-  const int4* up = wsp<int4>(pl, pl.o_mpart);
-  const int4* upb = up + pl.n_mup;
-  real* part = wsp<real>(pl, pl.o_mupart);
-  const unsigned nch = (unsigned)pl.n_mchunks, nup = (unsigned)pl.n_mup, nupb = (unsigned)pl.n_mupb;
-#define PBTC_MOM(PP)                                                                             \
-  case PP:                                                                                       \
-    if (nch > 0)                                                                                 \
-      hipLaunchKernelGGL((k_p2m_cell<real, PP>), dim3(nch), dim3(kMomThreads), 0, st, chunks,    \
-                         cells, src, mom);                                                       \
-    if (nup > 0) {                                                                               \
-      hipLaunchKernelGGL((k_mom_up_part<real, PP>), dim3(nupb), dim3(256), 0, st, upb, up, sroot, \
-                         cells, mom, part);                                                      \
-      hipLaunchKernelGGL((k_mom_up_sum<real, PP>), dim3(nup), dim3(256), 0, st, up, part, mom);  \
-    }                                                                                            \
+  const int* ucells = wsp<int>(pl, pl.o_mcell);
+  const unsigned nch = (unsigned)pl.n_mchunks;
+#define PBTC_MOM(PP)                                                                          \
+  case PP:                                                                                    \
+    if (nch > 0)                                                                              \
+      hipLaunchKernelGGL((k_p2m_cell<real, PP>), dim3(nch), dim3(kMomThreads), 0, st, chunks, \
+                         cells, src, mom);                                                    \
+    for (size_t l = 0; l + 1 < pl.up_level.size(); ++l)                                       \
+      if (pl.up_level[l + 1] > pl.up_level[l])                                                \
+        hipLaunchKernelGGL((k_m2m_up<real, PP>), dim3(pl.up_level[l + 1] - pl.up_level[l]),   \
+                           dim3(256), 0, st, ucells + pl.up_level[l], cells, mom);            \
     break;
   switch (pl.P) {
     PBTC_MOM(2)

@@ -623,12 +623,8 @@ void compute_layout(pbtc_plan_t& pl) {
   pl.o_scan = L.add(8 * (std::max<int64_t>(pl.cap_cells, pl.nitems) + 2));
   pl.o_mom64 = L.add(8 * 2 * nP * pl.cap_cells);
   pl.o_mom32 = L.add(4 * 2 * nP * pl.cap_cells);
-  // upper cells and partial blocks of the upper-cell pass (grown on demand)
   pl.o_mchunks = L.add(16 * pl.cap_cells);
   pl.o_mcell = L.add(4 * pl.cap_cells);
-  if (pl.cap_mup == 0) pl.cap_mup = pl.cap_cells / 2 + 1024;
-  pl.o_mpart = L.add(16 * pl.cap_mup);
-  pl.o_mupart = L.add(8 * 2 * (size_t)nP * pl.cap_mup);
   // lists
   pl.o_near_ptr = L.add(8 * (pl.nitems + 1));
   pl.o_far_ptr = L.add(8 * (pl.nitems + 1));

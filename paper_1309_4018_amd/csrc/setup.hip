@@ -1245,15 +1245,14 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     pl.n_units = (int64_t)units.size();
     pl.n_uptr = (int64_t)uptr.size();
 
-    // moment pass: span roots (at most kSpanSources sources, parent larger), the
-    // cells of their subtrees span by span, and the upper cells with the run
-    // of span roots inside them (children visited in source order)
-    std::vector<int4> mch, mup;
-    std::vector<int> sroot;
+    // moment pass: span roots (at most kSpanSources sources, parent larger),
+    // the cells of their subtrees span by span, and the upper (larger) cells
+    // grouped by tree level, deepest first (children visited in source order)
+    std::vector<int4> mch;
+    std::vector<int> ucell;
     bool too_big = false;
     std::function<void(int)> visit = [&](int c) {
       if (hc[c].count <= kSpanSources) {
-        sroot.push_back(c);
         const size_t first = mch.size();
         mch.push_back(make_int4(c, hc[c].begin, hc[c].count, 0));
         for (size_t i = first; i < mch.size(); ++i) {
@@ -1267,35 +1266,22 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
         too_big = true;
         return;
       }
-      const int first = (int)sroot.size();
       for (int k = 0; k < hc[c].nchild; ++k) visit(hc[c].child + k);
-      mup.push_back(make_int4(c, first, (int)sroot.size(), 0));
+      ucell.push_back(c);
     };
-    constexpr int kUpSpans = 8;  // span roots per partial block (operator.hip)
     for (int r = 0; r < pl.nsurf; ++r) visit(r);
     if (too_big) {
       pl.err = "a tree leaf holds more than 256 Gauss points (coincident points)";
       PBTC_HIP(hipStreamSynchronize(st));
       return PBTC_EMESH;
     }
-    // partial blocks of every upper cell, consecutive (first in mup[].w)
-    std::vector<int4> mupb;
-    for (size_t i = 0; i < mup.size(); ++i) {
-      mup[i].w = (int)mupb.size();
-      for (int s0 = mup[i].y; s0 < mup[i].z; s0 += kUpSpans)
-        mupb.push_back(make_int4((int)i, s0, std::min(s0 + kUpSpans, mup[i].z), 0));
-    }
+    std::stable_sort(ucell.begin(), ucell.end(),
+                     [&](int x, int y) { return hc[x].level > hc[y].level; });
+    pl.up_level.assign(1, 0);
+    for (size_t i = 1; i <= ucell.size(); ++i)
+      if (i == ucell.size() || hc[ucell[i]].level != hc[ucell[i - 1]].level)
+        pl.up_level.push_back((int)i);
     pl.n_mchunks = (int64_t)mch.size();
-    pl.n_mup = (int64_t)mup.size();
-    pl.n_mupb = (int64_t)mupb.size();
-    mup.insert(mup.end(), mupb.begin(), mupb.end());  // one table: upper cells, then blocks
-    if ((int64_t)mup.size() > pl.cap_mup) {
-      pl.cap_mup = (int64_t)mup.size() + (int64_t)mup.size() / 8 + 1024;
-      *need_retry = 1;
-      pl.err = "upper-cell moment blocks exceed the workspace estimate";
-      PBTC_HIP(hipStreamSynchronize(st));
-      return PBTC_EWORKSPACE;
-    }
     if (pl.n_units > pl.cap_units) {
       pl.cap_units = pl.n_units + pl.n_units / 8 + 1024;
       *need_retry = 1;
@@ -1308,11 +1294,8 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     if (!mch.empty())
       PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mchunks), mch.data(), 16 * mch.size(),
                               hipMemcpyHostToDevice, st));
-    if (!sroot.empty())
-      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_mcell), sroot.data(), 4 * sroot.size(),
-                              hipMemcpyHostToDevice, st));
-    if (!mup.empty())
-      PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mpart), mup.data(), 16 * mup.size(),
+    if (!ucell.empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_mcell), ucell.data(), 4 * ucell.size(),
                               hipMemcpyHostToDevice, st));
     PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_units), units.data(), 16 * units.size(),
                             hipMemcpyHostToDevice, st));
