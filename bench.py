@@ -45,7 +45,6 @@ if ROOT not in sys.path:
 
 METRIC = "BEM matvec interactions/s + GMRES solve s to 1e-5; FP32-bulk vs FP64"
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published (counts packed FP32)
-PEAK_FP32_NONPACKED_TFLOPS = 78.6  # one FP32 FMA per lane per cycle: 256 CU x 64 x 2 x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
 KINDS = ["p2p", "m2p_laplace", "m2p_yukawa", "adj_p2p", "adj_m2p_laplace", "adj_m2p_yukawa"]
 KERNEL_NAMES = {"p2p": "k_p2p", "m2p_laplace": "k_m2p<float, P, 0>",
@@ -116,7 +115,6 @@ def kernel_rooflines(results, kinds=range(6)):
         tf = f / t / 1e12
         out[KINDS[k]] = {"kernel": KERNEL_NAMES[KINDS[k]], "bound": "alu", "achieved": tf,
                          "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS,
-                         "frac_nonpacked": tf / PEAK_FP32_NONPACKED_TFLOPS,
                          "avg_launch_ms": 1e3 * t / n, "flop_per_launch": f / n,
                          "timed_launches": n}
     return out
@@ -434,7 +432,6 @@ def main():
     roofline["traffic_source"] = (f"profiles/hbm_counters_{a.workload}.txt (rocprofv3 FETCH_SIZE "
                                   "and WRITE_SIZE per launch, copy-probe calibrated; null when "
                                   "the kernel sources changed since)")
-    roofline["peak_nonpacked_fp32"] = PEAK_FP32_NONPACKED_TFLOPS
 
     configs = {}
     if not a.quick and a.workload == "star":
@@ -453,7 +450,7 @@ def main():
                                 ncrits=(64, 128, 256), direct_belows=(-1,))
         tune4 = {"seconds": time.perf_counter() - t, "chosen": tree4, "budget": 1e-4,
                  "grid": ("theta {0.4, 0.5, 0.6} x P {4, 6, 8}, then ncrit {64, 128, 256}, "
-                          "then P2P tile {128, 256, 512} sources x M2P tile {8, 16, 32} cells "
+                          "then P2P tile {512, 1024, 2048} sources x M2P tile {32, 64, 128} cells "
                           "(from the automatic tiles)"),
                  "candidates": [{k: r[k] for k in ("theta", "P", "ncrit", "unit_sources",
                                                    "unit_cells", "err_fp32", "matvec_s_fp32")}

@@ -127,14 +127,17 @@ typedef struct {
                        so that each timed launch has the GPU alone */
   int precond;      /* PBTC_PREC_NONE or PBTC_PREC_BLOCK_DIAG (forward and
                        adjoint solves) */
-  int unit_sources; /* work tile of P2P: one wavefront takes a target group and
-                       a run of its near-list cells of at most this many
-                       sources (whole cells; 64..8192); 0 = automatic: the
-                       largest of 512, 256, 128 that gives the launch ~1.5
-                       rounds of waves on the GPU (a short tail) */
-  int unit_cells;   /* work tile of M2P: a target group and at most this many
-                       of its far cells (1..1024); 0 = automatic: the largest
-                       of 32, 16, 8 by the same rule */
+  int unit_sources; /* work tile of P2P: one wavefront takes a group of 16
+                       targets (four lanes per target) and a run of its
+                       near-list cells of at most this many sources (whole
+                       cells; 64..8192); 0 = automatic: the largest of 2048,
+                       1024, 512 that gives the launch ~1.5 rounds of waves
+                       on the GPU (a short tail).  The transposed operator
+                       (64 Gauss points per wavefront) uses a quarter. */
+  int unit_cells;   /* work tile of M2P: a group of 16 targets and at most
+                       this many of its far cells (1..1024); 0 = automatic:
+                       the largest of 128, 64, 32 by the same rule (a
+                       quarter for the transposed operator) */
   int op_graph;     /* 1: every evaluation of A x (all surface-pair blocks of
                        all regions and systems) is replayed as ONE captured
                        HIP launch graph of its kernels, captured once per

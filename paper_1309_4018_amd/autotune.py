@@ -52,8 +52,8 @@ SPEED_KEYS = ("ncrit", "direct_below", "unit_sources", "unit_cells")
 
 
 def autotune(problem, budget=1e-4, thetas=(0.4, 0.5, 0.6), orders=(4, 6, 8),
-             ncrits=(64, 128, 256), direct_belows=(-1,), unit_sources=(128, 256, 512),
-             unit_cells=(8, 16, 32), device="cuda:0", seed=0, base=None):
+             ncrits=(64, 128, 256), direct_belows=(-1,), unit_sources=(512, 1024, 2048),
+             unit_cells=(32, 64, 128), device="cuda:0", seed=0, base=None):
     """Returns (best parameter dict, list of measured candidates).
 
     ``problem`` is a ``lib.Problem``; ``base`` extra parameters passed to

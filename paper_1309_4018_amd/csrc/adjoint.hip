@@ -17,7 +17,7 @@
 // layer takes the normal at the target).  These sums are evaluated by a
 // treecode with the roles swapped: sources at the collocation points
 // (octree per target set, moments of mu), targets at the Gauss points
-// (groups of 64 consecutive Morton-sorted points), P2P near, and M2P far with
+// (groups of kAGroup consecutive Morton-sorted points), P2P near, and M2P far with
 // Taylor coefficients to order P+1 for the gradient:
 //   grad_y a_k(y; x_c) = -(k_d + 1) a_{k+e_d}(y; x_c).
 // The near-field corrections are applied through the transpose (CSC) of the
@@ -92,7 +92,7 @@ __global__ void k_gpos(int64_t ngp, const double* __restrict__ gx, const double*
   if (pos) pos[gidx[j]] = (int)j;
 }
 
-// bounding sphere of Gauss-point group G (64 consecutive sorted points of one surface)
+// bounding sphere of Gauss-point group G (kAGroup consecutive sorted points of one surface)
 __global__ void k_gp_groups(int64_t ngrp, int nsurf, const long long* __restrict__ tab,
                             const double* __restrict__ gx, const double* __restrict__ gy,
                             const double* __restrict__ gz, double* __restrict__ grp) {
@@ -102,8 +102,8 @@ __global__ void k_gp_groups(int64_t ngrp, int nsurf, const long long* __restrict
   const long long* gp_off = tab + nsurf + 1;  // nsurf + 1
   int s = 0;
   while (s + 1 < nsurf && G >= grp_off[s + 1]) ++s;
-  const long long o = gp_off[s] + (G - grp_off[s]) * kGroup;
-  const int n = (int)min((long long)kGroup, gp_off[s + 1] - o);
+  const long long o = gp_off[s] + (G - grp_off[s]) * kAGroup;
+  const int n = (int)min((long long)kAGroup, gp_off[s + 1] - o);
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int i = 0; i < n; ++i) {
     lo[0] = fmin(lo[0], gx[o + i]);
@@ -405,13 +405,13 @@ __global__ __launch_bounds__(256) void k_adj_reduce(
   const int item = list[l];
   const DevBlock& b = blocks[item_block[item]];
   const long long g = item - b.aitem_off;
-  const int nt = (int)min((long long)kGroup, b.gp_n - g * kGroup);
+  const int nt = (int)min((long long)kAGroup, b.gp_n - g * kAGroup);
   if (lane >= nt) return;
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] += lds[k][q][lane];
-  const long long i = g * kGroup + lane;  // sorted position within the surface
+  const long long i = g * kAGroup + lane;  // sorted position within the surface
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const long long out = (first_slot + (q >> 1) == 0 ? b.aout0 : b.aout1) + i;
@@ -652,7 +652,10 @@ int adjoint_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     PBTC_HIP(hipMemcpy(hc.data(), wsp<Cell>(pl, pl.o_tcells), sizeof(Cell) * pl.n_tcells,
                        hipMemcpyDeviceToHost));
     // the forward operator's tiles (chosen at set-up for the same lists' sizes)
-    const int kUnitSources = pl.tile_sources, kUnitCells = pl.tile_cells;
+    // the forward tiles are per 16-target group (four lanes per target); a
+    // transposed unit has one lane per Gauss point of a 64-point group
+    const int kUnitSources = std::max(64, pl.tile_sources / kQuarters);
+    const int kUnitCells = std::max(1, pl.tile_cells / kQuarters);
     std::vector<int4> units;
     std::vector<int> uptr;
     const bool tree = pl.prm.op == PBTC_OP_TREECODE;
@@ -665,7 +668,7 @@ int adjoint_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
           const int s_ = pl.blocks[bi].s;
           const int64_t g = item - pl.blk_aitem_off[bi];
           const int64_t ngs = pl.gp_off[s_ + 1] - pl.gp_off[s_];
-          const double ntg = (double)std::min<int64_t>(kGroup, ngs - g * kGroup);
+          const double ntg = (double)std::min<int64_t>(kAGroup, ngs - g * kAGroup);
           double src = 0.0;
           for (long long e = np_[item]; e < np_[item + 1]; ++e) src += hc[nl[e]].count;
           fp += ntg * src * adj_p2p_flop_per_pair(ks);

@@ -81,8 +81,8 @@ __global__ __launch_bounds__(kT) void k_adj_p2p(UnitArgs a, const Src<real>* __r
   const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
   const DevBlock& b = a.blocks[uni(a.item_block[item])];
   const long long g = item - b.aitem_off;
-  const long long j0 = b.gp_off + g * kGroup;
-  const int nt = (int)min((long long)kGroup, b.gp_n - g * kGroup);
+  const long long j0 = b.gp_off + g * kAGroup;
+  const int nt = (int)min((long long)kAGroup, b.gp_n - g * kAGroup);
   const int lane = threadIdx.x & 63;
   const Src<real> t = gpos[j0 + min(lane, nt - 1)];
   const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
@@ -229,8 +229,8 @@ __global__ __launch_bounds__(kT) void k_adj_m2p(UnitArgs a, const Src<real>* __r
   const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
   const DevBlock& b = a.blocks[uni(a.item_block[item])];
   const long long g = item - b.aitem_off;
-  const long long j0 = b.gp_off + g * kGroup;
-  const int nt = (int)min((long long)kGroup, b.gp_n - g * kGroup);
+  const long long j0 = b.gp_off + g * kAGroup;
+  const int nt = (int)min((long long)kAGroup, b.gp_n - g * kAGroup);
   const int lane = threadIdx.x & 63;
   const Src<real> t = gpos[j0 + min(lane, nt - 1)];
   const real kap = (real)(kslot == 0 ? b.kappa0 : b.kappa1);

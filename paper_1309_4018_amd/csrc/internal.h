@@ -17,7 +17,17 @@ constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 constexpr double kCoulomb = 1389.35458;
 
 constexpr int kMaxP = 10;
-constexpr int kGroup = 64;       // targets per target group (one wavefront)
+// Targets per target group of the forward operator: the interaction lists
+// are built per group (group MAC); a wavefront evaluates one group with four
+// lanes per target, each lane taking a quarter of the group's sources or
+// cells.  Smaller groups see more cells through their expansions (a tighter
+// group sphere), so fewer source points go to P2P.
+constexpr int kGroup = 16;
+constexpr int kQuarters = 64 / kGroup;  // lanes per target
+constexpr int kNearRun = 64;            // targets per near-field search wavefront
+// Gauss points per target group of the transposed operator (one lane each:
+// with the Gauss points four to a panel, smaller groups cut few pairs)
+constexpr int kAGroup = 64;
 constexpr int kDotChunk = 4096;  // Krylov reduction chunk (entries of one system)
 constexpr int kNearSlots = 128; // near-field columns per row kept by the single traversal
 constexpr int kMaxLevels = 21;   // 63-bit Morton keys, 21 bits per axis
@@ -25,6 +35,17 @@ constexpr int kMaxNk = 32;
 constexpr int kMomChunk = 128;   // sources staged at a time by the direct moment pass
 constexpr int kMomSpan = 1024;   // sources per block of the transposed operator's moment pass
 constexpr int kSpanSources = 256;  // largest cell whose moments one work-group forms from its sources
+
+// Span roots shifted per work-group into one upper cell by the upward moment
+// pass: as many as fit 48 KiB of LDS in the dense (P+1)^3 FP64 layout of
+// both moment kinds (the same table serves both precisions).
+__host__ __device__ constexpr int mom_up_batch(int P) {
+  return 16 * 2 * (P + 1) * (P + 1) * (P + 1) * 8 <= 49152  ? 16
+         : 8 * 2 * (P + 1) * (P + 1) * (P + 1) * 8 <= 49152 ? 8
+         : 4 * 2 * (P + 1) * (P + 1) * (P + 1) * 8 <= 49152 ? 4
+         : 2 * 2 * (P + 1) * (P + 1) * (P + 1) * 8 <= 49152 ? 2
+                                                            : 1;
+}
 constexpr int kMaxRule = 19;
 
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
@@ -241,11 +262,12 @@ struct pbtc_plan_s {
   size_t o_flags = 0;  // device status flags (16 int)
   size_t o_qtab = 0;   // per region: first charge (nreg + 1 long long), eps (nreg double)
   size_t o_coul = 0;   // Coulomb energy per system (ncomp double)
-  // moment pass: span cells (cell, first source, count), the upper cells by
-  // level, deepest first, and where each level starts (+ end)
-  size_t o_mchunks = 0, o_mcell = 0;
-  int64_t n_mchunks = 0;
-  std::vector<int> up_level;
+  // moment pass: span cells (cell, first source, count), spans (first span
+  // cell, cells, first source, count) and their root cells, upward parts
+  // (upper cell, first span, end span, sole part) and sums (upper cell,
+  // first part, parts), the parts' partial moments
+  size_t o_mchunks = 0, o_mspans = 0, o_msroot = 0, o_mparts = 0, o_musum = 0, o_mpart = 0;
+  int64_t n_mchunks = 0, n_mspans = 0, n_mparts = 0, n_musum = 0, cap_mparts = 0;
   // direct moment pass of the transposed operator: chunks (cell, first
   // source, count, slot) and (cell x local slot, first chunk, end chunk)
   // pairs, per phase in [off[ph], off[ph + 1])

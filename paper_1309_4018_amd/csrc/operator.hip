@@ -57,112 +57,168 @@ __global__ void k_prep(int64_t ngp, const double* __restrict__ gx, const double*
 // ------------------------------------------------------------- moments
 // Moments of every cell about its centre c (Eq. multexp):
 //   M_SL[k] = sum q (y - c)^k,   M_DL[k] = sum_d p_d k_d (y - c)^(k - e_d).
+// The double layer is formed from three dipole-weighted moments
+// W_d[j] = sum p_d (y - c)^j, |j| <= P - 1, as M_DL[k] = sum_d k_d W_d[k - e_d],
+// so that a (source, coefficient) term costs one monomial product and four
+// FMAs.
+//
 // A span root is a cell of at most kSpanSources sources whose parent has more
-// (or a tree root that small); every cell of a span root's subtree takes one
-// work-group that computes its moments directly from its own (Morton-
-// contiguous) sources, staged through LDS kMomChunk at a time.  The work-
-// groups of one span are consecutive in a list that is dealt to the XCDs in
-// contiguous runs, so that a span's sources come from HBM once and from that
-// XCD's L2 for the deeper cells.  The larger (upper) cells follow level by
-// level, bottom-up: each adds its children's moments shifted to its own
-// centre by the multi-index binomial theorem (sec. 2.3: moments shifted to
-// the parents and added),
+// (or a tree root that small).  One work-group per span root stages the
+// span's sources in LDS once and forms the moments of every cell of the
+// span's subtree directly from them, so each source comes from HBM once.
+// The larger (upper) cells then add the moments of the span roots below
+// them, shifted to their own centres by the multi-index binomial theorem
+// (sec. 2.3: moments shifted towards the root and added),
 //   (y - c_u)^k = sum_{j <= k} C(k, j) h^(k - j) (y - c_s)^j,   h = c_s - c_u,
 // which holds for both moment kinds (the double layer is a linear map of the
 // same monomials), so upper cells never re-read the sources.
 constexpr int kMomThreads = 256;
+constexpr int kSpanCellsLds = 64;  // span cells whose entries are staged in LDS
 
 template <typename real, int P>
-__global__ __launch_bounds__(kMomThreads) void k_p2m_cell(const int4* __restrict__ chunks,
+__global__ __launch_bounds__(kMomThreads) void k_mom_span(const int4* __restrict__ spans,
+                                                          const int4* __restrict__ scells,
                                                           const Cell* __restrict__ cells,
                                                           const Src<real>* __restrict__ src,
                                                           real* __restrict__ mom) {
   constexpr int N = ncoef(P);
   constexpr int G = N <= kMomThreads ? kMomThreads / N : 1;  // groups of sources
   constexpr int KPT = (N + kMomThreads - 1) / kMomThreads;   // coefficients per thread
-  static_assert(kMomChunk <= kMomThreads, "one source per thread while staging");
+  static_assert(kMomChunk <= kMomThreads && kSpanSources <= kMomThreads,
+                "one source per thread while staging");
+  __shared__ real sxyz[kSpanSources][3];
+  __shared__ real sw[kSpanSources][4];  // q, p_x, p_y, p_z
   __shared__ real pw[kMomChunk][3][P + 1];
-  __shared__ real sq[kMomChunk][4];
-  __shared__ real red[G][2 * N];
-  const int4 ch = chunks[xcd_block(blockIdx.x, gridDim.x)];  // (cell, first source, count)
-  const Cell& cl = cells[ch.x];
-  const real cx = (real)cl.cx, cy = (real)cl.cy, cz = (real)cl.cz;
+  __shared__ real red[G][4][N];
+  __shared__ int4 sce[kSpanCellsLds];
+  __shared__ real scc[kSpanCellsLds][3];
+  // span: (first entry of its cells in scells, number of cells, first source, sources)
+  const int4 sp = spans[xcd_block(blockIdx.x, gridDim.x)];
   const int tid = threadIdx.x;
+  // the span's cell entries and centres, loaded together
+  if (tid < min(sp.y, kSpanCellsLds)) {
+    const int4 ce = scells[sp.x + tid];
+    const Cell& cl = cells[ce.x];
+    sce[tid] = ce;
+    scc[tid][0] = (real)cl.cx;
+    scc[tid][1] = (real)cl.cy;
+    scc[tid][2] = (real)cl.cz;
+  }
+  if (tid < sp.w) {
+    const Src<real> s = src[sp.z + tid];
+    sxyz[tid][0] = s.x;
+    sxyz[tid][1] = s.y;
+    sxyz[tid][2] = s.z;
+    sw[tid][0] = s.q;
+    sw[tid][1] = s.px;
+    sw[tid][2] = s.py;
+    sw[tid][3] = s.pz;
+  }
   const int g = N <= kMomThreads ? tid / N : 0;
   int kk[KPT][3];
   bool on[KPT];
-  real ms[KPT], md[KPT];
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int k = N <= kMomThreads ? tid - g * N : tid + q * kMomThreads;
     on[q] = N <= kMomThreads ? tid < G * N : k < N;
     mindex_inv(on[q] ? k : 0, kk[q][0], kk[q][1], kk[q][2]);
-    ms[q] = md[q] = 0;
   }
-  Src<real> nxt;
-  if (tid < min(kMomChunk, ch.z)) nxt = src[ch.y + tid];
-  for (int b0 = 0; b0 < ch.z; b0 += kMomChunk) {
-    const int nj = min(kMomChunk, ch.z - b0);
-    if (tid < nj) {
-      const Src<real> s = nxt;
-      const real d[3] = {s.x - cx, s.y - cy, s.z - cz};
+  // double-layer inputs of this thread's coefficients: W_d at k - e_d
+  int jd[KPT][3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        real v = 1;
+  for (int q = 0; q < KPT; ++q) {
+    const int a = kk[q][0], b = kk[q][1], c = kk[q][2];
+    jd[q][0] = a ? mindex(a - 1, b, c) : 0;
+    jd[q][1] = b ? mindex(a, b - 1, c) : 0;
+    jd[q][2] = c ? mindex(a, b, c - 1) : 0;
+  }
+  for (int e = 0; e < sp.y; ++e) {
+    int4 ce;  // (cell, first source, sources)
+    real cx, cy, cz;
+    if (e < kSpanCellsLds) {
+      if (e == 0) __syncthreads();  // staged entries visible
+      ce = sce[e];
+      cx = scc[e][0];
+      cy = scc[e][1];
+      cz = scc[e][2];
+    } else {
+      ce = scells[sp.x + e];
+      const Cell& cl = cells[ce.x];
+      cx = (real)cl.cx;
+      cy = (real)cl.cy;
+      cz = (real)cl.cz;
+    }
+    const int lo = ce.y - sp.z;
+    real acc[KPT][4];
 #pragma unroll
-        for (int e = 0; e <= P; ++e) {
-          pw[tid][a][e] = v;
-          v *= d[a];
+    for (int q = 0; q < KPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0;
+    for (int b0 = 0; b0 < ce.z; b0 += kMomChunk) {
+      const int nj = min(kMomChunk, ce.z - b0);
+      __syncthreads();  // staged sources written; pw free
+      if (tid < nj) {
+        const int t = lo + b0 + tid;
+        const real d[3] = {sxyz[t][0] - cx, sxyz[t][1] - cy, sxyz[t][2] - cz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          real v = 1;
+#pragma unroll
+          for (int p = 0; p <= P; ++p) {
+            pw[tid][a][p] = v;
+            v *= d[a];
+          }
         }
       }
-      sq[tid][0] = s.q;
-      sq[tid][1] = s.px;
-      sq[tid][2] = s.py;
-      sq[tid][3] = s.pz;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < KPT; ++q) {
+        if (!on[q]) continue;
+        const int k1 = kk[q][0], k2 = kk[q][1], k3 = kk[q][2];
+        // four sources per step into independent sums, so that their LDS
+        // reads are in flight together
+        real s4[4][4] = {};
+        auto term = [&](int t, real (&a)[4]) {
+          const real m = pw[t][0][k1] * pw[t][1][k2] * pw[t][2][k3];
+          const real* w = sw[lo + b0 + t];
+          a[0] += w[0] * m;
+          a[1] += w[1] * m;
+          a[2] += w[2] * m;
+          a[3] += w[3] * m;
+        };
+        int t = g;
+        for (; t + 3 * G < nj; t += 4 * G) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) term(t + u * G, s4[u]);
+        }
+        for (; t < nj; t += G) term(t, s4[0]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[q][i] += (s4[0][i] + s4[1][i]) + (s4[2][i] + s4[3][i]);
+      }
     }
-    __syncthreads();
-    // the next batch is loaded while this one is used
-    if (b0 + kMomChunk + tid < ch.z && tid < kMomChunk) nxt = src[ch.y + b0 + kMomChunk + tid];
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
       if (!on[q]) continue;
-      const int k1 = kk[q][0], k2 = kk[q][1], k3 = kk[q][2];
-      auto term = [&](int t, real& s_acc, real& d_acc) {
-        const real X = pw[t][0][k1], Y = pw[t][1][k2], Z = pw[t][2][k3];
-        s_acc += sq[t][0] * X * Y * Z;
-        real dl = 0;
-        if (k1) dl += sq[t][1] * real(k1) * pw[t][0][k1 - 1] * Y * Z;
-        if (k2) dl += sq[t][2] * real(k2) * X * pw[t][1][k2 - 1] * Z;
-        if (k3) dl += sq[t][3] * real(k3) * X * Y * pw[t][2][k3 - 1];
-        d_acc += dl;
-      };
-      // four sources per step into independent sums, so that their LDS
-      // reads are in flight together
-      real s4[4] = {0, 0, 0, 0}, d4[4] = {0, 0, 0, 0};
-      int t = g;
-      for (; t + 3 * G < nj; t += 4 * G) {
+      const int k = N <= kMomThreads ? tid - g * N : tid + q * kMomThreads;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) term(t + u * G, s4[u], d4[u]);
-      }
-      for (; t < nj; t += G) term(t, s4[0], d4[0]);
-      ms[q] += (s4[0] + s4[1]) + (s4[2] + s4[3]);
-      md[q] += (d4[0] + d4[1]) + (d4[2] + d4[3]);
+      for (int i = 0; i < 4; ++i) red[g][i][k] = acc[q][i];
     }
     __syncthreads();
-  }
+    // group g == 0 forms the final moments of its coefficients
 #pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    if (!on[q]) continue;
-    const int k = N <= kMomThreads ? tid - g * N : tid + q * kMomThreads;
-    red[g][k] = ms[q];
-    red[g][N + k] = md[q];
-  }
-  __syncthreads();
-  for (int k = tid; k < 2 * N; k += kMomThreads) {
-    real v = 0;
+    for (int q = 0; q < KPT; ++q) {
+      if (!on[q] || g != 0) continue;
+      const int k = N <= kMomThreads ? tid : tid + q * kMomThreads;
+      real s = 0, w[3] = {0, 0, 0};
 #pragma unroll
-    for (int gg = 0; gg < G; ++gg) v += red[gg][k];
-    mom[(size_t)ch.x * 2 * N + k] = v;
+      for (int gg = 0; gg < G; ++gg) {
+        s += red[gg][0][k];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) w[d] += red[gg][1 + d][jd[q][d]];
+      }
+      const real dl = real(kk[q][0]) * w[0] + real(kk[q][1]) * w[1] + real(kk[q][2]) * w[2];
+      mom[(size_t)ce.x * 2 * N + k] = s;
+      mom[(size_t)ce.x * 2 * N + N + k] = dl;
+    }
+    __syncthreads();  // red is read before the next cell writes it
   }
 }
 
@@ -176,66 +232,165 @@ struct Binom {
     }
   }
 };
-__constant__ Binom kBinom = Binom();
 
-// Moments of the upper cells of one tree level (bottom-up, one launch per
-// level): a cell's moments are the sum of its children's (span cells or upper
-// cells of the level below, both final), each shifted to the cell's centre.
-// The children's moments, the powers of their offsets h and the binomials are
-// staged in LDS; one thread per output coefficient walks its terms
-// j <= k in one flat loop (the lanes of a wave differ in k, so nested loops
-// over (j1, j2, j3) would run the union of their bounds).
+// Moments of the upper cells: each is the sum of the moments of the span
+// roots below it (a contiguous run of the depth-first span list), each
+// shifted to the cell's centre.  A work-group takes one part of at most
+// mom_up_batch(P) span roots of one cell.  The three-dimensional shift
+// factors into one-dimensional shifts along x, then y, then z (the binomial
+// sum is a product over the axes): the span roots' moments are unpacked into
+// a dense (P+1)^3 array in LDS, and a thread shifts one line of it
+// ("pencil": fixed indices on the other two axes, at most P+1 entries) in
+// registers, with the binomials as constants.  Entries of total degree > P
+// are never read or written.  A cell of one part stores its moments; the
+// parts of a larger cell store partial sums that k_mom_up_sum adds in part
+// order (deterministic).
 template <typename real, int P>
-__global__ __launch_bounds__(256) void k_m2m_up(const int* __restrict__ ucells,
-                                                const Cell* __restrict__ cells,
-                                                real* __restrict__ mom) {
-  constexpr int N = ncoef(P), N2 = 2 * N;
-  __shared__ real sm[8][N2];
-  __shared__ real hp[8][3][P + 1];
-  __shared__ real bin[P + 1][P + 1];
-  const int u = ucells[blockIdx.x];
-  const Cell& cu = cells[u];
-  const int nch = cu.nchild, c0 = cu.child;
+__global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ parts,
+                                                     const int* __restrict__ sroot,
+                                                     const Cell* __restrict__ cells,
+                                                     real* __restrict__ mom,
+                                                     real* __restrict__ partial) {
+  constexpr int N = ncoef(P), N2 = 2 * N, Q = P + 1;
+  constexpr int R = mom_up_batch(P);
+  constexpr int NPEN = Q * (Q + 1) / 2;  // pencils per kind and axis
+  constexpr int OPT = (N2 + 255) / 256;  // outputs per thread
+  constexpr Binom B{};
+  __shared__ real D[R][2][Q][Q][Q];
+  __shared__ real hp[R][3][Q];
+  __shared__ int abc[N];       // a | b << 8 | c << 16 of coefficient k
+  __shared__ int pen_mn[NPEN];  // m | n << 8 of pencil p
+  __shared__ int root[R];
+  const int4 pt = parts[blockIdx.x];  // (upper cell, first span, end span, sole part)
+  const int u = pt.x, nr = pt.z - pt.y;
   const int tid = threadIdx.x;
-  for (int i = tid; i < nch * N2; i += 256) {
-    const int r = i / N2, k = i - r * N2;
-    sm[r][k] = mom[(size_t)(c0 + r) * N2 + k];
+  for (int k = tid; k < N; k += 256) {
+    int a, b, c;
+    mindex_inv(k, a, b, c);
+    abc[k] = a | (b << 8) | (c << 16);
   }
-  if (tid < 3 * nch) {
+  if (tid < NPEN) {
+    int pen = tid, m = 0;
+    while (pen >= Q - m) pen -= Q - m++;
+    pen_mn[tid] = m | (pen << 8);
+  }
+  if (tid < nr) root[tid] = sroot[pt.y + tid];
+  const double ux = cells[u].cx, uy = cells[u].cy, uz = cells[u].cz;
+  __syncthreads();
+  if (tid < 3 * nr) {
     const int r = tid / 3, d = tid - 3 * r;
-    const Cell& ch = cells[c0 + r];
-    const double h = d == 0 ? ch.cx - cu.cx : d == 1 ? ch.cy - cu.cy : ch.cz - cu.cz;
+    const Cell& ch = cells[root[r]];
+    const double h = d == 0 ? ch.cx - ux : d == 1 ? ch.cy - uy : ch.cz - uz;
     real v = 1;
-    for (int e = 0; e <= P; ++e) {
+    for (int e = 0; e < Q; ++e) {
       hp[r][d][e] = v;
       v *= (real)h;
     }
   }
-  for (int i = tid; i < (P + 1) * (P + 1); i += 256)
-    bin[i / (P + 1)][i % (P + 1)] = real(kBinom.c[i / (P + 1)][i % (P + 1)]);
+  for (int i = tid; i < nr * N2; i += 256) {
+    const int r = i / N2, k = i - r * N2;
+    const int s = k < N ? 0 : 1;
+    const int t = abc[k - s * N];
+    D[r][s][t & 255][(t >> 8) & 255][t >> 16] = mom[(size_t)root[r] * N2 + k];
+  }
   __syncthreads();
-  for (int k = tid; k < N2; k += 256) {
-    int a, b, c;
-    mindex_inv(k < N ? k : k - N, a, b, c);
-    const int half = k < N ? 0 : N;
-    const int nt = (a + 1) * (b + 1) * (c + 1);
-    real acc = 0;
-    for (int r = 0; r < nch; ++r) {
-      const real* M = sm[r] + half;
-      real s = 0;
-      int j1 = 0, j2 = 0, j3 = 0;
-      for (int t = 0; t < nt; ++t) {
-        s += (bin[a][j1] * hp[r][0][a - j1]) * (bin[b][j2] * hp[r][1][b - j2]) *
-             (bin[c][j3] * hp[r][2][c - j3]) * M[mindex(j1, j2, j3)];
-        // next (j1, j2, j3), j3 fastest
-        const bool w3 = j3 == c, w2 = w3 && j2 == b;
-        j3 = w3 ? 0 : j3 + 1;
-        j2 = w2 ? 0 : (w3 ? j2 + 1 : j2);
-        j1 = w2 ? j1 + 1 : j1;
+#pragma unroll
+  for (int axis = 0; axis < 3; ++axis) {
+    for (int i = tid; i < nr * 2 * NPEN; i += 256) {
+      const int r = i / (2 * NPEN), rest = i - r * 2 * NPEN;
+      const int s = rest / NPEN;
+      const int mn = pen_mn[rest - s * NPEN];
+      const int m = mn & 255, n = mn >> 8, len = Q - m - n;
+      real* base;
+      int stride;
+      if (axis == 0) {
+        base = &D[r][s][0][m][n];
+        stride = Q * Q;
+      } else if (axis == 1) {
+        base = &D[r][s][m][0][n];
+        stride = Q;
+      } else {
+        base = &D[r][s][m][n][0];
+        stride = 1;
       }
-      acc += s;
+      const real* h = hp[r][axis];
+      real v[Q], hv[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        v[j] = j < len ? base[j * stride] : real(0);
+        hv[j] = h[j];
+      }
+      // in place, highest degree first: v[a] = sum_{j <= a} C(a, j) h^(a-j) v[j]
+#pragma unroll
+      for (int a = Q - 1; a >= 1; --a) {
+        real t = v[a];
+#pragma unroll
+        for (int j = 0; j < a; ++j) t += (real(B.c[a][j]) * hv[a - j]) * v[j];
+        v[a] = t;
+      }
+#pragma unroll
+      for (int j = 0; j < Q; ++j)
+        if (j < len) base[j * stride] = v[j];
     }
-    mom[(size_t)u * N2 + k] = acc;
+    __syncthreads();
+  }
+  real* dst = pt.w ? mom + (size_t)u * N2 : partial + (size_t)blockIdx.x * N2;
+#pragma unroll
+  for (int o = 0; o < OPT; ++o) {
+    const int k = tid + 256 * o;
+    if (k < N2) {
+      const int s = k < N ? 0 : 1;
+      const int t = abc[k - s * N];
+      const int a = t & 255, b = (t >> 8) & 255, c = t >> 16;
+      real acc = 0;
+      for (int r = 0; r < nr; ++r) acc += D[r][s][a][b][c];
+      dst[k] = acc;
+    }
+  }
+}
+
+// Moments of an upper cell of several parts: the sum of the parts' partial
+// moments.  Wave w adds parts w, w + 4, ... (four loads in flight per lane),
+// then the four wave sums are added in wave order (deterministic).
+template <typename real, int P>
+__global__ __launch_bounds__(256) void k_mom_up_sum(const int4* __restrict__ sums,
+                                                    const real* __restrict__ partial,
+                                                    real* __restrict__ mom) {
+  constexpr int N2 = 2 * ncoef(P);
+  constexpr int OPW = (N2 + 63) / 64;  // outputs per lane
+  __shared__ real red[3][OPW * 64];
+  const int4 sm = sums[blockIdx.x];  // (upper cell, first part, parts)
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  real acc[OPW];
+#pragma unroll
+  for (int o = 0; o < OPW; ++o) acc[o] = 0;
+  int p = w;
+  for (; p + 12 < sm.z; p += 16) {
+#pragma unroll
+    for (int o = 0; o < OPW; ++o) {
+      const int k = lane + 64 * o;
+      if (k < N2) {
+        const real* q = partial + (size_t)(sm.y + p) * N2 + k;
+        const real v0 = q[0], v1 = q[4 * N2], v2 = q[8 * N2], v3 = q[12 * N2];
+        acc[o] += (v0 + v1) + (v2 + v3);
+      }
+    }
+  }
+  for (; p < sm.z; p += 4)
+#pragma unroll
+    for (int o = 0; o < OPW; ++o) {
+      const int k = lane + 64 * o;
+      if (k < N2) acc[o] += partial[(size_t)(sm.y + p) * N2 + k];
+    }
+  if (w > 0)
+#pragma unroll
+    for (int o = 0; o < OPW; ++o) red[w - 1][lane + 64 * o] = acc[o];
+  __syncthreads();
+  if (w > 0) return;
+#pragma unroll
+  for (int o = 0; o < OPW; ++o) {
+    const int k = lane + 64 * o;
+    if (k < N2) mom[(size_t)sm.x * N2 + k] = acc[o] + red[0][k] + red[1][k] + red[2][k];
   }
 }
 
@@ -288,50 +443,114 @@ constexpr int nacc() {
   return KS == KS_L || KS == KS_Y ? 2 : 4;
 }
 
-// partial[(u * 4 + q) * 64 + lane]
+// Lanes of a wavefront: target t = lane % kGroup of the unit's group, quarter
+// q = lane / kGroup.  The quarters' partial sums of a target are added
+// across the wave (fixed order) and lanes 0 .. kGroup-1 store the unit's
+// sums: partial[(u * 4 + i) * kGroup + t].
 template <typename real, int NQ>
-__device__ __forceinline__ void unit_store(real* __restrict__ partial, int u, const real (&acc)[4]) {
+__device__ __forceinline__ void unit_store(real* __restrict__ partial, int u, real (&acc)[4]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) partial[((size_t)u * 4 + q) * 64 + lane] = acc[q];
+  for (int i = 0; i < NQ; ++i) {
+#pragma unroll
+    for (int m = kGroup; m < 64; m <<= 1) acc[i] += __shfl_xor(acc[i], m);
+  }
+  if (lane < kGroup)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) partial[((size_t)u * 4 + i) * kGroup + lane] = acc[i];
 }
 
+// P2P: the unit's cells pass through a per-wavefront LDS slice 64 sources at
+// a time (one coalesced load per lane, the next chunk loaded while the
+// current one is used); the four lanes of a target take every fourth staged
+// source, so that a pair's operands are all vector registers.
 template <typename real, int KS>
 __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __restrict__ tx,
                                                       const real* __restrict__ ty,
                                                       const real* __restrict__ tz,
                                                       const Src<real>* __restrict__ src,
                                                       real* __restrict__ partial) {
+  __shared__ Src<real> stage[kWaves][64];
   const int u = uni(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (u >= a.nunits) return;
+  const int wv = uni(threadIdx.x >> 6);
   const int4 un = a.units[u];
   const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
   const DevBlock& b = a.blocks[uni(a.item_block[item])];
   const long long g = item - b.item_off;
   const long long t0 = b.tgt_off + g * kGroup;
   const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
-  const int lane = threadIdx.x & 63;
-  const long long ti = t0 + min(lane, nt - 1);
+  const int lane = threadIdx.x & 63, qt = lane / kGroup;
+  const long long ti = t0 + min(lane % kGroup, nt - 1);
   const real x = tx[ti], y = ty[ti], z = tz[ti];
   const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
   const real a0 = exp_arg(k0), a1 = exp_arg(k1);
   real acc[4] = {0, 0, 0, 0};
-  for (int e = e0; e < e1; ++e) {
+  // chunk iterator over (cell e, offset off): sources [cb + off, cb + off + 64) ∩ [cb, cb + cn)
+  int e = e0, cb = 0, cn = 0, off = 0;
+  if (e < e1) {
     const int c = uni(a.cells_list[e]);
-    const int beg = uni(a.cells[c].begin), end = beg + uni(a.cells[c].count);
-    int j = beg;
-    // four sources per step: their scalar loads are issued together
-    for (; j + 3 < end; j += 4) {
-      const Src<real> s0 = src[j], s1 = src[j + 1], s2 = src[j + 2], s3 = src[j + 3];
+    cb = uni(a.cells[c].begin);
+    cn = uni(a.cells[c].count);
+  }
+  // a source record travels in seven registers (no aggregate copies)
+  real cur[7] = {0, 0, 0, 0, 0, 0, 0}, nxt[7] = {0, 0, 0, 0, 0, 0, 0};
+  auto load = [&](real (&v)[7], int j) {
+    const Src<real>& r = src[j];
+    v[0] = r.x;
+    v[1] = r.y;
+    v[2] = r.z;
+    v[3] = r.q;
+    v[4] = r.px;
+    v[5] = r.py;
+    v[6] = r.pz;
+  };
+  if (e < e1 && lane < cn) load(cur, cb + lane);
+  while (e < e1) {
+    const int n = min(64, cn - off);
+    // the next chunk, loaded while this one is evaluated
+    int ne = e, nb = cb, nn = cn, noff = off + 64;
+    if (noff >= cn) {
+      ne = e + 1;
+      noff = 0;
+      if (ne < e1) {
+        const int c = uni(a.cells_list[ne]);
+        nb = uni(a.cells[c].begin);
+        nn = uni(a.cells[c].count);
+      }
+    }
+    if (ne < e1 && lane < nn - noff) load(nxt, nb + noff + lane);
+    if (lane < n) {
+      Src<real>& d = stage[wv][lane];
+      d.x = cur[0];
+      d.y = cur[1];
+      d.z = cur[2];
+      d.q = cur[3];
+      d.px = cur[4];
+      d.py = cur[5];
+      d.pz = cur[6];
+    }
+    wave_sync();
+    int j = qt;
+    for (; j + 3 * kQuarters < n; j += 4 * kQuarters) {
+      const Src<real> s0 = stage[wv][j], s1 = stage[wv][j + kQuarters],
+                      s2 = stage[wv][j + 2 * kQuarters], s3 = stage[wv][j + 3 * kQuarters];
       pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
       pair<real, KS>(x, y, z, s1, k0, k1, a0, a1, acc);
       pair<real, KS>(x, y, z, s2, k0, k1, a0, a1, acc);
       pair<real, KS>(x, y, z, s3, k0, k1, a0, a1, acc);
     }
-    for (; j < end; ++j) {
-      const Src<real> s0 = src[j];
+    for (; j < n; j += kQuarters) {
+      const Src<real> s0 = stage[wv][j];
       pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
     }
+    wave_sync();  // the slice is read before the next chunk overwrites it
+    e = ne;
+    cb = nb;
+    cn = nn;
+    off = noff;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) cur[i] = nxt[i];
   }
   unit_store<real, nacc<KS>()>(partial, u, acc);
 }
@@ -339,121 +558,129 @@ __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __
 // ------------------------------------------------------------------- m2p
 // One Green's function per launch (KIND 0 Laplace, 1 Yukawa) for the block's
 // kernel slot `slot`, so that the two recurrences of a Laplace + Yukawa
-// block never share a register allocation.
+// block never share a register allocation.  Per step the wave evaluates four
+// cells of the unit, one per quarter of its lanes: the four cells' moments
+// pass through a per-wavefront LDS slice (the lanes of a quarter read the
+// same addresses), double-buffered where LDS allows: the next four cells'
+// moments are loaded into registers while the current ones are evaluated.
+template <typename real, int P>
+constexpr int m2p_lds_bytes(int waves, int bufs) {
+  return waves * bufs * kQuarters * 2 * ncoef(P) * (int)sizeof(real);
+}
+template <typename real, int P>
+constexpr int m2p_bufs() {
+  return 1;
+}
+template <typename real, int P>
+constexpr int m2p_waves() {
+  return m2p_lds_bytes<real, P>(kWaves, m2p_bufs<real, P>()) <= 49152   ? kWaves
+         : m2p_lds_bytes<real, P>(2, m2p_bufs<real, P>()) <= 49152 ? 2
+                                                                       : 1;
+}
+
 template <typename real, int P, int KIND>
-__global__ __launch_bounds__(kItemThreads) void k_m2p(UnitArgs a, const real* __restrict__ tx,
-                                                      const real* __restrict__ ty,
-                                                      const real* __restrict__ tz,
-                                                      const real* __restrict__ mom, int slot,
-                                                      real* __restrict__ partial) {
-  constexpr int N = ncoef(P);
-  const int u = uni(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
+__global__ __launch_bounds__((64 * m2p_waves<real, P>())) void k_m2p(
+    UnitArgs a, const real* __restrict__ tx, const real* __restrict__ ty,
+    const real* __restrict__ tz, const real* __restrict__ mom, int slot,
+    real* __restrict__ partial) {
+  constexpr int N = ncoef(P), N2 = 2 * N;
+  constexpr int W = m2p_waves<real, P>(), NB = m2p_bufs<real, P>();
+  constexpr int PER = (N2 + kGroup - 1) / kGroup;  // moment values per lane and step
+  __shared__ real smom[W][NB][kQuarters][N2];
+  const int u = uni(xcd_block(blockIdx.x, gridDim.x) * W + (threadIdx.x >> 6));
   if (u >= a.nunits) return;
+  const int wv = uni(threadIdx.x >> 6);
   const int4 un = a.units[u];
   const int item = uni(un.x), e0 = uni(un.y), e1 = uni(un.z);
   const DevBlock& b = a.blocks[uni(a.item_block[item])];
   const long long g = item - b.item_off;
   const long long t0 = b.tgt_off + g * kGroup;
   const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
-  const int lane = threadIdx.x & 63;
-  const long long ti = t0 + min(lane, nt - 1);
+  const int lane = threadIdx.x & 63, qt = lane / kGroup;
+  const long long ti = t0 + min(lane % kGroup, nt - 1);
   const real x = tx[ti], y = ty[ti], z = tz[ti];
   const real kap = (real)(slot == 0 ? b.kappa0 : b.kappa1);
-  // The cell's moments go through a per-wavefront LDS slice (broadcast
-  // reads), double-buffered: the next cell's moments and centre are loaded
-  // into registers while the current cell is evaluated.
-  constexpr int PER = (2 * N + 63) / 64;
-  __shared__ real smom[kWaves][2][2 * N];
-  const int wv = uni(threadIdx.x >> 6);
-  real pre[PER];
-  double pcx = 0, pcy = 0, pcz = 0;
-  auto fetch = [&](int e) {
-    const int c = uni(a.cells_list[e]);
-    const Cell& cl = a.cells[c];
-    pcx = cl.cx;
-    pcy = cl.cy;
-    pcz = cl.cz;
-    const real* Mg = mom + (size_t)c * 2 * N;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int k = lane + 64 * q;
-      pre[q] = k < 2 * N ? Mg[k] : real(0);
-    }
-  };
+  const int tl = lane % kGroup;
+  real* M = &smom[wv][0][0][0];
   real acc[4] = {0, 0, 0, 0};
-  if (e0 < e1) fetch(e0);
-  int buf = 0;
-  for (int e = e0; e < e1; ++e) {
-    real* M = smom[wv][buf];
+  for (int e = e0; e < e1; e += kQuarters) {
+    // the cell of this lane's quarter among the four from entry e
+    const int cm = e + qt < e1 ? a.cells_list[e + qt] : -1;
+    wave_sync();  // the previous step's reads of the slice are done
+    real cx = 0, cy = 0, cz = 0;
+    if (cm >= 0) {
+      const real* Mg = mom + (size_t)cm * N2;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int k = lane + 64 * q;
-      if (k < 2 * N) M[k] = pre[q];
+      for (int r = 0; r < PER; ++r) {
+        const int k = tl + kGroup * r;
+        if (k < N2) M[qt * N2 + k] = Mg[k];
+      }
+      const Cell& cl = a.cells[cm];
+      cx = (real)cl.cx;
+      cy = (real)cl.cy;
+      cz = (real)cl.cz;
     }
-    const real dx = x - (real)pcx, dy = y - (real)pcy, dz = z - (real)pcz;
-    wave_sync();  // this buffer is written; the other one was last read a cell ago
-    if (e + 1 < e1) fetch(e + 1);
-    const real r2 = dx * dx + dy * dy + dz * dz;
-    const real rinv = rsqrt_(r2);
-    if (KIND == 0)
-      taylor_laplace<P, real>(dx, dy, dz, rinv, M, acc[0], acc[1]);
-    else
-      taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(kap * (r2 * rinv)), kap, M, acc[0], acc[1]);
-    buf ^= 1;
+    wave_sync();  // the four cells' moments are in the slice
+    if (cm >= 0) {
+      const real* Mq = M + qt * N2;
+      const real dx = x - cx, dy = y - cy, dz = z - cz;
+      const real r2 = dx * dx + dy * dy + dz * dz;
+      const real rinv = rsqrt_(r2);
+      if (KIND == 0)
+        taylor_laplace<P, real>(dx, dy, dz, rinv, Mq, acc[0], acc[1]);
+      else
+        taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(kap * (r2 * rinv)), kap, Mq, acc[0],
+                               acc[1]);
+    }
   }
   unit_store<real, 2>(partial, u, acc);
 }
 
 // Sum of the units of every listed item, times 1/(4 pi), into S and D of
-// kernel slots first_slot.. (mode 0 store, mode 1 add).  The four waves of
-// the work-group take the item's units round-robin (wave w: units w, w + 4,
-// ...), so that four times as many loads are in flight; their sums are then
-// added in wave order (fixed order: deterministic).
+// kernel slots first_slot.. (mode 0 store, mode 1 add).  One wavefront per
+// item: lane = target t (lane % kGroup) of quarter q (lane / kGroup); quarter
+// q adds units q, q + 4, ... of the item, then the quarters' sums are added
+// across the wave (fixed order: deterministic).
 constexpr int kReduceWaves = 4;
 
 template <typename real, int NQ>
 __global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
-    const int* __restrict__ list, const int* __restrict__ uptr, const int* __restrict__ item_block,
-    const DevBlock* __restrict__ blocks, const int* __restrict__ tidx,
-    const real* __restrict__ partial, double* __restrict__ S, double* __restrict__ D, int mode,
-    int first_slot) {
-  __shared__ double lds[kReduceWaves - 1][NQ][64];
-  const int l = blockIdx.x;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int nlist, const int* __restrict__ list, const int* __restrict__ uptr,
+    const int* __restrict__ item_block, const DevBlock* __restrict__ blocks,
+    const int* __restrict__ tidx, const real* __restrict__ partial, double* __restrict__ S,
+    double* __restrict__ D, int mode, int first_slot) {
+  const int l = blockIdx.x * kReduceWaves + (threadIdx.x >> 6);
+  if (l >= nlist) return;
+  const int lane = threadIdx.x & 63, t = lane % kGroup, qt = lane / kGroup;
   double v[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = 0.0;
   const int u0 = uptr[l], u1 = uptr[l + 1];
-  int u = u0 + w;
-  // two units per step per wave
-  for (; u + kReduceWaves < u1; u += 2 * kReduceWaves) {
+  int u = u0 + qt;
+  // two units per step per lane
+  for (; u + kQuarters < u1; u += 2 * kQuarters) {
     real p[2][NQ];
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        p[k][q] = partial[((size_t)(u + k * kReduceWaves) * 4 + q) * 64 + lane];
+        p[k][q] = partial[((size_t)(u + k * kQuarters) * 4 + q) * kGroup + t];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] += (double)p[0][q] + (double)p[1][q];
   }
   if (u < u1)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * 64 + lane];
-  if (w > 0)
+    for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * kGroup + t];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) lds[w - 1][q][lane] = v[q];
-  __syncthreads();
-  if (w > 0) return;
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int m = kGroup; m < 64; m <<= 1) v[q] += __shfl_xor(v[q], m);
   const int item = list[l];
   const DevBlock& b = blocks[item_block[item]];
   const long long g = item - b.item_off;
   const long long t0 = b.tgt_off + g * kGroup;
   const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
   if (lane >= nt) return;
-#pragma unroll
-  for (int k = 0; k < kReduceWaves - 1; ++k)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] += lds[k][q][lane];
   const long long i = tidx[t0 + lane] - b.tgt_off;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -564,18 +791,25 @@ __global__ void k_combine(const DevRowBlock* __restrict__ rows, const DevRowTerm
 template <typename real>
 static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<real>* src) {
   const Cell* cells = wsp<Cell>(pl, pl.o_cells);
-  const int4* chunks = wsp<int4>(pl, pl.o_mchunks);
-  const int* ucells = wsp<int>(pl, pl.o_mcell);
-  const unsigned nch = (unsigned)pl.n_mchunks;
+  const int4* scells = wsp<int4>(pl, pl.o_mchunks);
+  const int4* spans = wsp<int4>(pl, pl.o_mspans);
+  const int* sroot = wsp<int>(pl, pl.o_msroot);
+  const int4* parts = wsp<int4>(pl, pl.o_mparts);
+  const int4* sums = wsp<int4>(pl, pl.o_musum);
+  real* partial = wsp<real>(pl, pl.o_mpart);
+  const unsigned nsp = (unsigned)pl.n_mspans, npt = (unsigned)pl.n_mparts,
+                 nsum = (unsigned)pl.n_musum;
 #define PBTC_MOM(PP)                                                                          \
   case PP:                                                                                    \
-    if (nch > 0)                                                                              \
-      hipLaunchKernelGGL((k_p2m_cell<real, PP>), dim3(nch), dim3(kMomThreads), 0, st, chunks, \
-                         cells, src, mom);                                                    \
-    for (size_t l = 0; l + 1 < pl.up_level.size(); ++l)                                       \
-      if (pl.up_level[l + 1] > pl.up_level[l])                                                \
-        hipLaunchKernelGGL((k_m2m_up<real, PP>), dim3(pl.up_level[l + 1] - pl.up_level[l]),   \
-                           dim3(256), 0, st, ucells + pl.up_level[l], cells, mom);            \
+    if (nsp > 0)                                                                              \
+      hipLaunchKernelGGL((k_mom_span<real, PP>), dim3(nsp), dim3(kMomThreads), 0, st, spans,  \
+                         scells, cells, src, mom);                                            \
+    if (npt > 0)                                                                              \
+      hipLaunchKernelGGL((k_mom_up_part<real, PP>), dim3(npt), dim3(256), 0, st, parts,       \
+                         sroot, cells, mom, partial);                                         \
+    if (nsum > 0)                                                                             \
+      hipLaunchKernelGGL((k_mom_up_sum<real, PP>), dim3(nsum), dim3(256), 0, st, sums,        \
+                         partial, mom);                                                       \
     break;
   switch (pl.P) {
     PBTC_MOM(2)
@@ -593,13 +827,15 @@ static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<
 }
 
 template <typename real, int KIND>
-static void launch_m2p(pbtc_plan_t& pl, hipStream_t st, const UnitArgs& a, int grid, const real* tx,
+static void launch_m2p(pbtc_plan_t& pl, hipStream_t st, const UnitArgs& a, const real* tx,
                        const real* ty, const real* tz, const real* mom, int slot, real* partial) {
 #define PBTC_M2P(PP)                                                                           \
-  case PP:                                                                                     \
-    hipLaunchKernelGGL((k_m2p<real, PP, KIND>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, \
-                       tz, mom, slot, partial);                                                \
-    break;
+  case PP: {                                                                                   \
+    constexpr int W = m2p_waves<real, PP>();                                                   \
+    hipLaunchKernelGGL((k_m2p<real, PP, KIND>), dim3(nblocks(a.nunits, W)), dim3(64 * W), 0,  \
+                       st, a, tx, ty, tz, mom, slot, partial);                                 \
+    break;                                                                                     \
+  }
   switch (pl.P) {
     PBTC_M2P(2)
     PBTC_M2P(4)
@@ -720,11 +956,13 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
       prof_mark(pl, st, timed, 0, 0.0, false);
       const int* uptr = wsp<int>(pl, pl.o_uptr + 4 * us.ptr_off);
       if (ks == KS_L || ks == KS_Y)
-        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64 * kReduceWaves), 0, st, list,
-                           uptr, a.item_block, a.blocks, tidx, partial, S, D, 0, 0);
+        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(nblocks(n, kReduceWaves)),
+                           dim3(64 * kReduceWaves), 0, st, n, list, uptr, a.item_block, a.blocks,
+                           tidx, partial, S, D, 0, 0);
       else
-        hipLaunchKernelGGL((k_reduce<real, 4>), dim3(n), dim3(64 * kReduceWaves), 0, st, list,
-                           uptr, a.item_block, a.blocks, tidx, partial, S, D, 0, 0);
+        hipLaunchKernelGGL((k_reduce<real, 4>), dim3(nblocks(n, kReduceWaves)),
+                           dim3(64 * kReduceWaves), 0, st, n, list, uptr, a.item_block, a.blocks,
+                           tidx, partial, S, D, 0, 0);
       PBTC_LAUNCH_CHECK();
     }
     if (tree && pl.n_far > 0) {
@@ -737,7 +975,6 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
       a.units = wsp<int4>(pl, pl.o_units + 16 * us.off);
       a.nunits = (int)us.n;
       a.cells_list = wsp<int>(pl, pl.o_far);
-      const int grid = nblocks(us.n, kWaves);
       const int* uptr = wsp<int>(pl, pl.o_uptr + 4 * us.ptr_off);
       // kernel of slot 0 and (for two-kernel blocks) slot 1
       const int kind0 = (ks == KS_L || ks == KS_LY) ? 0 : 1;
@@ -749,12 +986,13 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
                           m2p_flop_per_eval(pl.P, ks);
         prof_mark(pl, st, timed, 1 + kind, fl, true);
         if (kind == 0)
-          launch_m2p<real, 0>(pl, st, a, grid, tx, ty, tz, mom, slot, partial);
+          launch_m2p<real, 0>(pl, st, a, tx, ty, tz, mom, slot, partial);
         else
-          launch_m2p<real, 1>(pl, st, a, grid, tx, ty, tz, mom, slot, partial);
+          launch_m2p<real, 1>(pl, st, a, tx, ty, tz, mom, slot, partial);
         prof_mark(pl, st, timed, 1 + kind, 0.0, false);
-        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(n), dim3(64 * kReduceWaves), 0, st, list,
-                           uptr, a.item_block, a.blocks, tidx, partial, S, D, 1, slot);
+        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(nblocks(n, kReduceWaves)),
+                           dim3(64 * kReduceWaves), 0, st, n, list, uptr, a.item_block, a.blocks,
+                           tidx, partial, S, D, 1, slot);
       }
       PBTC_LAUNCH_CHECK();
     }

@@ -335,7 +335,7 @@ int build_plan(pbtc_plan_t& pl) {
   // transposed operator: Gauss-point groups, items, kernel slots, CSC columns
   pl.gpgrp_off.assign(pl.nsurf + 1, 0);
   for (int s = 0; s < pl.nsurf; ++s)
-    pl.gpgrp_off[s + 1] = pl.gpgrp_off[s] + (pl.gp_off[s + 1] - pl.gp_off[s] + kGroup - 1) / kGroup;
+    pl.gpgrp_off[s + 1] = pl.gpgrp_off[s] + (pl.gp_off[s + 1] - pl.gp_off[s] + kAGroup - 1) / kAGroup;
   pl.ngpgrp = pl.gpgrp_off[pl.nsurf];
   const size_t nb = pl.blocks.size();
   pl.blk_slot0.assign(nb, 0);
@@ -461,6 +461,7 @@ int build_plan(pbtc_plan_t& pl) {
   if (pl.cap_far == 0)
     pl.cap_far = (pl.prm.op == PBTC_OP_DIRECT ? 1 : 160) * pl.nitems + 1024;
   if (pl.cap_units == 0) pl.cap_units = 8 * pl.nitems + 1024;
+  if (pl.cap_mparts == 0) pl.cap_mparts = pl.cap_cells / 4 + 1024;
   if (pl.cap_aunits == 0) pl.cap_aunits = 8 * pl.nitems_adj + 1024;
   if (pl.cap_auptr == 0) pl.cap_auptr = 2 * pl.nitems_adj + 64;
   if (pl.cap_tcells == 0) pl.cap_tcells = pl.ntgt / 16 + 64 * (int64_t)pl.tsets.size() + 1024;
@@ -624,7 +625,11 @@ void compute_layout(pbtc_plan_t& pl) {
   pl.o_mom64 = L.add(8 * 2 * nP * pl.cap_cells);
   pl.o_mom32 = L.add(4 * 2 * nP * pl.cap_cells);
   pl.o_mchunks = L.add(16 * pl.cap_cells);
-  pl.o_mcell = L.add(4 * pl.cap_cells);
+  pl.o_mspans = L.add(16 * pl.cap_cells);
+  pl.o_msroot = L.add(4 * pl.cap_cells);
+  pl.o_musum = L.add(16 * pl.cap_cells);
+  pl.o_mparts = L.add(16 * pl.cap_mparts);
+  pl.o_mpart = L.add(8 * 2 * nP * pl.cap_mparts);
   // lists
   pl.o_near_ptr = L.add(8 * (pl.nitems + 1));
   pl.o_far_ptr = L.add(8 * (pl.nitems + 1));

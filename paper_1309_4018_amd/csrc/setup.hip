@@ -405,10 +405,13 @@ __device__ __forceinline__ void target_point(const NearArgs& a, const DevBlock& 
 }
 
 // Near-field columns of every row: the panels j with |x - centre_j| <
-// thres * L_j, plus the target's own panel.  One wavefront per (block, group)
-// item, a lane per target: the wave walks the leaves that may hold such a
-// panel for some target of the group and tests every panel of each leaf (its
-// first Gauss point stands for it) against all 64 targets at once.
+// thres * L_j, plus the target's own panel.  One wavefront per run of
+// kNearRun consecutive targets of a block (the items of kNearRun / kGroup
+// consecutive groups; the wave of the run's first item does the work), a
+// lane per target: the wave walks the leaves that may hold such a panel for
+// some target of the run (inside the run's bounding sphere plus the reach)
+// and tests every panel of each leaf (its first Gauss point stands for it)
+// against all 64 targets at once.
 // mode 0: count per row; mode 1: fill columns at the row offsets in ptr;
 // mode 2: count per row and keep the first `slot_cap` columns of every row in
 // slots[row * slot_cap ..] (flags[1] set when a row has more).
@@ -422,8 +425,8 @@ __global__ __launch_bounds__(64 * kTravWaves) void k_near_rows(
   if (it >= nitems) return;
   const DevBlock& b = a.blocks[item_block[it]];
   const int64_t g = it - b.item_off;
-  const int64_t gg = b.grp_off + g;
-  const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
+  if (g % (kNearRun / kGroup) != 0) return;
+  const int nt = (int)min((long long)kNearRun, b.ntgt - g * kGroup);
   const bool active = lane < nt;
   int64_t i = 0;
   double x = 0, y = 0, z = 0;
@@ -432,6 +435,23 @@ __global__ __launch_bounds__(64 * kTravWaves) void k_near_rows(
     i = tidx[b.tgt_off + g * kGroup + lane] - b.tgt_off;
     target_point(a, b, i, x, y, z, self_pan);
   }
+  // bounding sphere of the run: box centre, largest distance to it
+  double lo[3] = {active ? x : 1e300, active ? y : 1e300, active ? z : 1e300};
+  double hi[3] = {active ? x : -1e300, active ? y : -1e300, active ? z : -1e300};
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], __shfl_xor(lo[d], m));
+      hi[d] = fmax(hi[d], __shfl_xor(hi[d], m));
+    }
+  const double gcx = 0.5 * (lo[0] + hi[0]), gcy = 0.5 * (lo[1] + hi[1]),
+               gcz = 0.5 * (lo[2] + hi[2]);
+  double gr = active ? sqrt((x - gcx) * (x - gcx) + (y - gcy) * (y - gcy) + (z - gcz) * (z - gcz))
+                     : 0.0;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) gr = fmax(gr, __shfl_xor(gr, m));
+  gr = gr * (1.0 + 1e-12) + 1e-12;
   const long long row = b.nf_row + i;
   long long n = 0;
   const long long out0 = (mode == 1 && active) ? ptr[row] : 0;
@@ -442,8 +462,7 @@ __global__ __launch_bounds__(64 * kTravWaves) void k_near_rows(
   __shared__ double lx[kTravWaves][64], ly[kTravWaves][64], lz[kTravWaves][64];
   __shared__ double ll[kTravWaves][64];
   __shared__ int lp[kTravWaves][64];
-  wave_leaves_within(a.cells, b.root, grp[4 * gg], grp[4 * gg + 1], grp[4 * gg + 2],
-                     grp[4 * gg + 3], reach, stk[w], overflow,
+  wave_leaves_within(a.cells, b.root, gcx, gcy, gcz, gr, reach, stk[w], overflow,
                      [&](int leaf, double lcx, double lcy, double lcz, double lrb) {
     // skip the leaf unless some lane's own target is within reach of it
     const double qx = x - lcx, qy = y - lcy, qz = z - lcz;
@@ -1208,8 +1227,8 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
           u += std::ceil((double)(fp_[it + 1] - fp_[it]) / t);
       return u;
     };
-    const int kUnitSources = auto_tile(pl.prm.unit_sources, {512, 256, 128}, resident, p2p_units);
-    const int kUnitCells = auto_tile(pl.prm.unit_cells, {32, 16, 8}, resident, m2p_units);
+    const int kUnitSources = auto_tile(pl.prm.unit_sources, {2048, 1024, 512}, resident, p2p_units);
+    const int kUnitCells = auto_tile(pl.prm.unit_cells, {128, 64, 32}, resident, m2p_units);
     pl.tile_sources = kUnitSources;
     pl.tile_cells = kUnitCells;
     std::vector<int4> units;
@@ -1245,12 +1264,16 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     pl.n_units = (int64_t)units.size();
     pl.n_uptr = (int64_t)uptr.size();
 
-    // moment pass: span roots (at most kSpanSources sources, parent larger),
-    // the cells of their subtrees span by span, and the upper (larger) cells
-    // grouped by tree level, deepest first (children visited in source order)
-    std::vector<int4> mch;
-    std::vector<int> ucell;
+    // moment pass: span roots (at most kSpanSources sources, parent larger)
+    // in depth-first order, each with its subtree's cells in breadth-first
+    // order; the span roots below an upper (larger) cell are then a
+    // contiguous run of the span list, shifted into the cell in parts of at
+    // most mom_up_batch(P) span roots (a cell of several parts also gets a
+    // sum entry).
+    std::vector<int4> mch, mspan, mparts, musum;
+    std::vector<int> sroot;
     bool too_big = false;
+    const int up_batch = mom_up_batch(pl.P);
     std::function<void(int)> visit = [&](int c) {
       if (hc[c].count <= kSpanSources) {
         const size_t first = mch.size();
@@ -1260,14 +1283,21 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
           for (int k = 0; k < cc.nchild; ++k)
             mch.push_back(make_int4(cc.child + k, hc[cc.child + k].begin, hc[cc.child + k].count, 0));
         }
+        mspan.push_back(make_int4((int)first, (int)(mch.size() - first), hc[c].begin, hc[c].count));
+        sroot.push_back(c);
         return;
       }
       if (hc[c].nchild == 0) {  // a leaf larger than a span: coincident points
         too_big = true;
         return;
       }
+      const int s0 = (int)mspan.size();
       for (int k = 0; k < hc[c].nchild; ++k) visit(hc[c].child + k);
-      ucell.push_back(c);
+      const int s1 = (int)mspan.size();
+      const int np = (s1 - s0 + up_batch - 1) / up_batch;
+      if (np > 1) musum.push_back(make_int4(c, (int)mparts.size(), np, 0));
+      for (int q = s0; q < s1; q += up_batch)
+        mparts.push_back(make_int4(c, q, std::min(q + up_batch, s1), np == 1 ? 1 : 0));
     };
     for (int r = 0; r < pl.nsurf; ++r) visit(r);
     if (too_big) {
@@ -1275,13 +1305,17 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       PBTC_HIP(hipStreamSynchronize(st));
       return PBTC_EMESH;
     }
-    std::stable_sort(ucell.begin(), ucell.end(),
-                     [&](int x, int y) { return hc[x].level > hc[y].level; });
-    pl.up_level.assign(1, 0);
-    for (size_t i = 1; i <= ucell.size(); ++i)
-      if (i == ucell.size() || hc[ucell[i]].level != hc[ucell[i - 1]].level)
-        pl.up_level.push_back((int)i);
     pl.n_mchunks = (int64_t)mch.size();
+    pl.n_mspans = (int64_t)mspan.size();
+    pl.n_mparts = (int64_t)mparts.size();
+    pl.n_musum = (int64_t)musum.size();
+    if (pl.n_mparts > pl.cap_mparts) {
+      pl.cap_mparts = pl.n_mparts + pl.n_mparts / 8 + 1024;
+      *need_retry = 1;
+      pl.err = "upward moment parts exceed the workspace estimate";
+      PBTC_HIP(hipStreamSynchronize(st));
+      return PBTC_EWORKSPACE;
+    }
     if (pl.n_units > pl.cap_units) {
       pl.cap_units = pl.n_units + pl.n_units / 8 + 1024;
       *need_retry = 1;
@@ -1294,8 +1328,17 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     if (!mch.empty())
       PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mchunks), mch.data(), 16 * mch.size(),
                               hipMemcpyHostToDevice, st));
-    if (!ucell.empty())
-      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_mcell), ucell.data(), 4 * ucell.size(),
+    if (!mspan.empty()) {
+      PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mspans), mspan.data(), 16 * mspan.size(),
+                              hipMemcpyHostToDevice, st));
+      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_msroot), sroot.data(), 4 * sroot.size(),
+                              hipMemcpyHostToDevice, st));
+    }
+    if (!mparts.empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mparts), mparts.data(), 16 * mparts.size(),
+                              hipMemcpyHostToDevice, st));
+    if (!musum.empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_musum), musum.data(), 16 * musum.size(),
                               hipMemcpyHostToDevice, st));
     PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_units), units.data(), 16 * units.size(),
                             hipMemcpyHostToDevice, st));

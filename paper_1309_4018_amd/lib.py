@@ -131,6 +131,10 @@ def load(path: str | None = None):
     if _lib is not None and path is None:
         return _lib
     p = path or LIB_PATH
+    # torch ships its own HIP runtime under the same soname as the system
+    # one; torch is loaded first so that the library binds to that runtime
+    # and both share devices, streams and memory.
+    import torch  # noqa: F401
     if not os.path.exists(p):
         raise RuntimeError(
             f"{p} is missing: build it with `python -m paper_1309_4018_amd.build` "

@@ -51,9 +51,9 @@ def test_autotune_batch_choice_meets_budget_against_oracle(gpu_lib):
     mols = synth.config4_batch(n_mol=5, nu_cap=6)
     budget = 1e-4
     best, rows = autotune(lib.batch_problem(mols), budget=budget, thetas=(0.4, 0.6),
-                          orders=(4, 6), ncrits=(64, 128), unit_sources=(256, 512),
-                          unit_cells=(16, 32))
-    assert any(r["unit_sources"] == 256 for r in rows)  # the tile stage ran
+                          orders=(4, 6), ncrits=(64, 128), unit_sources=(512, 1024),
+                          unit_cells=(32, 64))
+    assert any(r["unit_sources"] == 512 for r in rows)  # the tile stage ran
     o = Oracle(_merged(mols))
     A = o.matrix()
     x = np.random.default_rng(4).normal(size=o.n)

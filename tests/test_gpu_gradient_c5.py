@@ -108,9 +108,12 @@ def tree(c5, gpu_lib):
 def test_treecode_adjoint_matches_direct(c5, direct, tree):
     _, _, dq, dk, de = direct
     tq, tk, te = tree
+    # the treecode's truncation error (Eq. MAC, theta = 0.5, P = 8) is an
+    # error of the operator relative to its size, so every gradient is
+    # compared in the max norm of its vector (a component that is small by
+    # cancellation carries the same absolute error as the others)
     assert np.max(np.abs(tq - dq)) < 2e-3 * np.max(np.abs(dq))
-    for i in range(len(c5.regions)):
-        assert abs(tk[i] - dk[i]) < 2e-3 * abs(dk[i]), i
+    assert np.max(np.abs(tk - dk)) < 2e-3 * np.max(np.abs(dk))
     assert np.max(np.abs(te - de)) < 2e-3 * np.max(np.abs(de))
 
 
@@ -137,7 +140,7 @@ def test_treecode_gradient_matches_dense_oracle(c5, tree):
     tq, tk, te = tree
     ref_q = np.array(g["dE_dq"])
     assert np.max(np.abs(tq - ref_q)) < 2e-3 * np.max(np.abs(ref_q))
-    for i in range(len(c5.regions)):
-        assert abs(tk[i] - g["dE_dkappa"][i]) < 2e-3 * abs(g["dE_dkappa"][i]), i
+    ref_k = np.array(g["dE_dkappa"])
+    assert np.max(np.abs(tk - ref_k)) < 2e-3 * np.max(np.abs(ref_k))
     ref_e = np.array(g["dE_deps"])
     assert np.max(np.abs(te - ref_e)) < 2e-3 * np.max(np.abs(ref_e))
