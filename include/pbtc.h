@@ -72,6 +72,7 @@ extern "C" {
 #define PBTC_EWORKSPACE -4 /* workspace too small; pbtc_result.workspace_needed */
 #define PBTC_EDEVICE -5    /* HIP runtime error */
 #define PBTC_ENOCONV -6    /* GMRES hit max_iter; outputs hold the last iterate */
+#define PBTC_KERNEL_KINDS 7 /* kernel kinds timed in pbtc_result */
 #define PBTC_EHOST -7      /* host-side failure: out of host memory or another
                               internal error (no exception leaves the library) */
 
@@ -165,11 +166,11 @@ typedef struct {
   size_t workspace_needed; /* bytes (set on PBTC_EWORKSPACE and on success) */
   /* with params.profile: summed HIP-event durations, launch counts and
    * algorithmic FP operations of the P2P and M2P kernel launches of the
-   * FP32 operator (A x) during the call; M2P counts both kernels */
+   * FP32 operator (A x) during the call; M2P counts every M2P launch */
   double t_p2p_s, t_m2p_s;
   int n_p2p_launch, n_m2p_launch;
   double p2p_flop, m2p_flop;
-  /* the Yukawa M2P kernel's share of the M2P figures */
+  /* the share of the M2P launches of Yukawa-only blocks */
   double t_m2p_yuk_s;
   int n_m2p_yuk_launch;
   double m2p_yuk_flop;
@@ -185,12 +186,14 @@ typedef struct {
   int op_graph_launches;
   /* with params.profile, per kernel kind -- [0] P2P, [1] Laplace M2P,
    * [2] Yukawa M2P of the FP32 A x (pbtc_solve), [3] P2P, [4] Laplace M2P,
-   * [5] Yukawa M2P of the FP32 A^T x (pbtc_backward) -- the summed HIP-event
+   * [5] Yukawa M2P of the FP32 A^T x (pbtc_backward), [6] M2P of the FP32
+   * A x for blocks of two Green's functions (Laplace + Yukawa or two Yukawa
+   * kernels evaluated in one pass over the cells) -- the summed HIP-event
    * seconds, the timed launches and their algorithmic floating-point
    * operations (FMA = 2, a transcendental = 1) */
-  double t_kernel_s[6];
-  int n_kernel_launch[6];
-  double kernel_flop[6];
+  double t_kernel_s[PBTC_KERNEL_KINDS];
+  int n_kernel_launch[PBTC_KERNEL_KINDS];
+  double kernel_flop[PBTC_KERNEL_KINDS];
   /* the P2P and M2P work tiles the set-up used (params.unit_sources and
    * unit_cells, or the automatic choice) */
   int tile_sources, tile_cells;

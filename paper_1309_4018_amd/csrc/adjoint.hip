@@ -1069,7 +1069,7 @@ int device_backward(pbtc_plan_t& pl, hipStream_t st, double gE, double* dq, doub
   const int T = 256;
   const double C = 4.0 * kPi * kCoulomb;
   prof_collect(pl);
-  for (int i = 0; i < 6; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
+  for (int i = 0; i < kProfKinds; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
   double* x = wsp<double>(pl, pl.o_x);
   double* lam = wsp<double>(pl, pl.o_lam);
   double* rhs = wsp<double>(pl, pl.o_adj_rhs);
@@ -1304,7 +1304,7 @@ int device_backward(pbtc_plan_t& pl, hipStream_t st, double gE, double* dq, doub
     res->n_matvec_fp64 = n64;
     res->n_refine = nref;
     prof_collect(pl);
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < kProfKinds; ++k) {
       res->t_kernel_s[k] = pl.prof_t[k];
       res->n_kernel_launch[k] = pl.prof_n[k];
       res->kernel_flop[k] = pl.prof_flop[k];

@@ -17,6 +17,11 @@ constexpr double kInv4Pi = 0.0795774715459476678844;  // 1 / (4 pi)
 constexpr double kCoulomb = 1389.35458;
 
 constexpr int kMaxP = 10;
+// Timed kernel kinds: 0 P2P, 1 Laplace M2P, 2 Yukawa M2P of A x; 3 P2P,
+// 4 Laplace M2P, 5 Yukawa M2P of A^T x; 6 M2P of two Green's functions per
+// cell pass (Laplace + Yukawa or two Yukawa blocks) of A x.
+constexpr int kProfKinds = 7;
+constexpr int kProfM2PPair = 6;
 // Targets per target group of the forward operator: the interaction lists
 // are built per group (group MAC); a wavefront evaluates one group with four
 // lanes per target, each lane taking a quarter of the group's sources or
@@ -324,8 +329,8 @@ struct pbtc_plan_s {
   std::vector<ProfEvent> prof, prof_pool;
   // per kernel kind: 0 P2P, 1 Laplace M2P, 2 Yukawa M2P of A x; 3, 4, 5 the
   // same of A^T x
-  double prof_t[6] = {0, 0, 0, 0, 0, 0}, prof_flop[6] = {0, 0, 0, 0, 0, 0};
-  int prof_n[6] = {0, 0, 0, 0, 0, 0};
+  double prof_t[pbtc::kProfKinds] = {}, prof_flop[pbtc::kProfKinds] = {};
+  int prof_n[pbtc::kProfKinds] = {};
   int64_t prof_count = 0;   // FP32 operator evaluations seen by the sampler
   int64_t aprof_count = 0;  // the same for the transposed operator
   double setup_phase[6] = {0, 0, 0, 0, 0, 0};  // host seconds per set-up phase

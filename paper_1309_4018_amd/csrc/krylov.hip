@@ -814,7 +814,7 @@ int device_solve(pbtc_plan_t& pl, hipStream_t st, pbtc_result* res) {
   pl.history.clear();
   pl.n_graph_launch = 0;
   prof_collect(pl);
-  for (int i = 0; i < 6; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
+  for (int i = 0; i < kProfKinds; ++i) pl.prof_t[i] = pl.prof_flop[i] = 0.0, pl.prof_n[i] = 0;
   int iters = 0, n32 = 0, n64 = 0, nref = 0;
   bool conv = false;
   double rel = 0.0;
@@ -859,17 +859,18 @@ int device_solve(pbtc_plan_t& pl, hipStream_t st, pbtc_result* res) {
     res->t_energy_s = t2 - t1;
     prof_collect(pl);
     res->t_p2p_s = pl.prof_t[0];
-    res->t_m2p_s = pl.prof_t[1] + pl.prof_t[2];
+    res->t_m2p_s = pl.prof_t[1] + pl.prof_t[2] + pl.prof_t[kProfM2PPair];
     res->n_p2p_launch = pl.prof_n[0];
-    res->n_m2p_launch = pl.prof_n[1] + pl.prof_n[2];
+    res->n_m2p_launch = pl.prof_n[1] + pl.prof_n[2] + pl.prof_n[kProfM2PPair];
     res->p2p_flop = pl.prof_flop[0];
-    res->m2p_flop = pl.prof_flop[1] + pl.prof_flop[2];
+    res->m2p_flop = pl.prof_flop[1] + pl.prof_flop[2] + pl.prof_flop[kProfM2PPair];
     res->t_m2p_yuk_s = pl.prof_t[2];
     res->n_m2p_yuk_launch = pl.prof_n[2];
     res->m2p_yuk_flop = pl.prof_flop[2];
     res->op_kernels = pl.op_kernels[1][0];
     res->op_graph_launches = (int)pl.n_graph_launch;
-    for (int k = 0; k < 6; ++k) {
+    static_assert(kProfKinds == PBTC_KERNEL_KINDS, "timed kernel kinds of pbtc_result");
+    for (int k = 0; k < kProfKinds; ++k) {
       res->t_kernel_s[k] = pl.prof_t[k];
       res->n_kernel_launch[k] = pl.prof_n[k];
       res->kernel_flop[k] = pl.prof_flop[k];

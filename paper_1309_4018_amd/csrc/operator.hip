@@ -556,37 +556,36 @@ __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __
 }
 
 // ------------------------------------------------------------------- m2p
-// One Green's function per launch (KIND 0 Laplace, 1 Yukawa) for the block's
-// kernel slot `slot`, so that the two recurrences of a Laplace + Yukawa
-// block never share a register allocation.  Per step the wave evaluates four
-// cells of the unit, one per quarter of its lanes: the four cells' moments
-// pass through a per-wavefront LDS slice (the lanes of a quarter read the
-// same addresses), double-buffered where LDS allows: the next four cells'
-// moments are loaded into registers while the current ones are evaluated.
-template <typename real, int P>
-constexpr int m2p_lds_bytes(int waves, int bufs) {
-  return waves * bufs * kQuarters * 2 * ncoef(P) * (int)sizeof(real);
-}
-template <typename real, int P>
-constexpr int m2p_bufs() {
-  return 1;
-}
+// Green's function KIND0 of kernel slot `slot` (0 Laplace, 1 Yukawa), and
+// with KIND1 >= 0 also KIND1 of slot 1 for the same (target, cell) pairs
+// (blocks of two kernels: one pass over the cells, the geometry and the
+// staged moments shared).  Per step the wave evaluates four cells of the
+// unit, one per quarter of its lanes: the four cells' moments pass through a
+// per-wavefront LDS slice (the lanes of a quarter read the same addresses).
 template <typename real, int P>
 constexpr int m2p_waves() {
-  return m2p_lds_bytes<real, P>(kWaves, m2p_bufs<real, P>()) <= 49152   ? kWaves
-         : m2p_lds_bytes<real, P>(2, m2p_bufs<real, P>()) <= 49152 ? 2
-                                                                       : 1;
+  constexpr int per = kQuarters * 2 * ncoef(P) * (int)sizeof(real);
+  return kWaves * per <= 49152 ? kWaves : 2 * per <= 49152 ? 2 : 1;
 }
 
 template <typename real, int P, int KIND>
+__device__ __forceinline__ void m2p_eval(real dx, real dy, real dz, real r2, real rinv, real kap,
+                                         const real* __restrict__ M, real& s, real& d) {
+  if (KIND == 0)
+    taylor_laplace<P, real>(dx, dy, dz, rinv, M, s, d);
+  else
+    taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(kap * (r2 * rinv)), kap, M, s, d);
+}
+
+template <typename real, int P, int KIND0, int KIND1>
 __global__ __launch_bounds__((64 * m2p_waves<real, P>())) void k_m2p(
     UnitArgs a, const real* __restrict__ tx, const real* __restrict__ ty,
     const real* __restrict__ tz, const real* __restrict__ mom, int slot,
     real* __restrict__ partial) {
   constexpr int N = ncoef(P), N2 = 2 * N;
-  constexpr int W = m2p_waves<real, P>(), NB = m2p_bufs<real, P>();
+  constexpr int W = m2p_waves<real, P>();
   constexpr int PER = (N2 + kGroup - 1) / kGroup;  // moment values per lane and step
-  __shared__ real smom[W][NB][kQuarters][N2];
+  __shared__ real smom[W][kQuarters][N2];
   const int u = uni(xcd_block(blockIdx.x, gridDim.x) * W + (threadIdx.x >> 6));
   if (u >= a.nunits) return;
   const int wv = uni(threadIdx.x >> 6);
@@ -596,12 +595,11 @@ __global__ __launch_bounds__((64 * m2p_waves<real, P>())) void k_m2p(
   const long long g = item - b.item_off;
   const long long t0 = b.tgt_off + g * kGroup;
   const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
-  const int lane = threadIdx.x & 63, qt = lane / kGroup;
-  const long long ti = t0 + min(lane % kGroup, nt - 1);
+  const int lane = threadIdx.x & 63, qt = lane / kGroup, tl = lane % kGroup;
+  const long long ti = t0 + min(tl, nt - 1);
   const real x = tx[ti], y = ty[ti], z = tz[ti];
-  const real kap = (real)(slot == 0 ? b.kappa0 : b.kappa1);
-  const int tl = lane % kGroup;
-  real* M = &smom[wv][0][0][0];
+  const real kap0 = (real)(slot == 0 ? b.kappa0 : b.kappa1), kap1 = (real)b.kappa1;
+  real* M = &smom[wv][0][0];
   real acc[4] = {0, 0, 0, 0};
   for (int e = e0; e < e1; e += kQuarters) {
     // the cell of this lane's quarter among the four from entry e
@@ -626,14 +624,18 @@ __global__ __launch_bounds__((64 * m2p_waves<real, P>())) void k_m2p(
       const real dx = x - cx, dy = y - cy, dz = z - cz;
       const real r2 = dx * dx + dy * dy + dz * dz;
       const real rinv = rsqrt_(r2);
-      if (KIND == 0)
-        taylor_laplace<P, real>(dx, dy, dz, rinv, Mq, acc[0], acc[1]);
-      else
-        taylor_yukawa<P, real>(dx, dy, dz, rinv, exp_neg(kap * (r2 * rinv)), kap, Mq, acc[0],
-                               acc[1]);
+      m2p_eval<real, P, KIND0>(dx, dy, dz, r2, rinv, kap0, Mq, acc[0], acc[1]);
+      if (KIND1 >= 0) {
+        // the second recurrence after the first, reading the moments from
+        // LDS again (no interleaving, no moments held across: the registers
+        // of one recurrence at a time)
+        __asm__ volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        m2p_eval<real, P, (KIND1 > 0 ? 1 : 0)>(dx, dy, dz, r2, rinv, kap1, Mq, acc[2], acc[3]);
+      }
     }
   }
-  unit_store<real, 2>(partial, u, acc);
+  unit_store<real, KIND1 >= 0 ? 4 : 2>(partial, u, acc);
 }
 
 // Sum of the units of every listed item, times 1/(4 pi), into S and D of
@@ -826,14 +828,14 @@ static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<
   return PBTC_OK;
 }
 
-template <typename real, int KIND>
+template <typename real, int KIND0, int KIND1>
 static void launch_m2p(pbtc_plan_t& pl, hipStream_t st, const UnitArgs& a, const real* tx,
                        const real* ty, const real* tz, const real* mom, int slot, real* partial) {
 #define PBTC_M2P(PP)                                                                           \
   case PP: {                                                                                   \
     constexpr int W = m2p_waves<real, PP>();                                                   \
-    hipLaunchKernelGGL((k_m2p<real, PP, KIND>), dim3(nblocks(a.nunits, W)), dim3(64 * W), 0,  \
-                       st, a, tx, ty, tz, mom, slot, partial);                                 \
+    hipLaunchKernelGGL((k_m2p<real, PP, KIND0, KIND1>), dim3(nblocks(a.nunits, W)),           \
+                       dim3(64 * W), 0, st, a, tx, ty, tz, mom, slot, partial);                \
     break;                                                                                     \
   }
   switch (pl.P) {
@@ -976,23 +978,28 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
       a.nunits = (int)us.n;
       a.cells_list = wsp<int>(pl, pl.o_far);
       const int* uptr = wsp<int>(pl, pl.o_uptr + 4 * us.ptr_off);
-      // kernel of slot 0 and (for two-kernel blocks) slot 1
-      const int kind0 = (ks == KS_L || ks == KS_LY) ? 0 : 1;
-      const bool two = ks == KS_LY || ks == KS_YY;
-      for (int slot = 0; slot < (two ? 2 : 1); ++slot) {
-        const int kind = slot == 0 ? kind0 : 1;
-        // this kernel's share of the block's M2P operations
-        const double fl = pl.launch_flop_m2p[phase][ks] * m2p_flop_one(pl.P, kind) /
-                          m2p_flop_per_eval(pl.P, ks);
-        prof_mark(pl, st, timed, 1 + kind, fl, true);
+      if (ks == KS_L || ks == KS_Y) {
+        const int kind = ks == KS_L ? 0 : 1;
+        prof_mark(pl, st, timed, 1 + kind, pl.launch_flop_m2p[phase][ks], true);
         if (kind == 0)
-          launch_m2p<real, 0>(pl, st, a, tx, ty, tz, mom, slot, partial);
+          launch_m2p<real, 0, -1>(pl, st, a, tx, ty, tz, mom, 0, partial);
         else
-          launch_m2p<real, 1>(pl, st, a, tx, ty, tz, mom, slot, partial);
+          launch_m2p<real, 1, -1>(pl, st, a, tx, ty, tz, mom, 0, partial);
         prof_mark(pl, st, timed, 1 + kind, 0.0, false);
         hipLaunchKernelGGL((k_reduce<real, 2>), dim3(nblocks(n, kReduceWaves)),
                            dim3(64 * kReduceWaves), 0, st, n, list, uptr, a.item_block, a.blocks,
-                           tidx, partial, S, D, 1, slot);
+                           tidx, partial, S, D, 1, 0);
+      } else {
+        // two kernels (Laplace + Yukawa, or two Yukawa) in one pass
+        prof_mark(pl, st, timed, kProfM2PPair, pl.launch_flop_m2p[phase][ks], true);
+        if (ks == KS_LY)
+          launch_m2p<real, 0, 1>(pl, st, a, tx, ty, tz, mom, 0, partial);
+        else
+          launch_m2p<real, 1, 1>(pl, st, a, tx, ty, tz, mom, 0, partial);
+        prof_mark(pl, st, timed, kProfM2PPair, 0.0, false);
+        hipLaunchKernelGGL((k_reduce<real, 4>), dim3(nblocks(n, kReduceWaves)),
+                           dim3(64 * kReduceWaves), 0, st, n, list, uptr, a.item_block, a.blocks,
+                           tidx, partial, S, D, 1, 0);
       }
       PBTC_LAUNCH_CHECK();
     }

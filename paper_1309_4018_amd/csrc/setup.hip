@@ -1178,6 +1178,14 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     if (!rc) rc = launch_precond(pl, st);
     if (!rc) rc = launch_rhs(pl, st);
     if (rc) return rc;
+    // sources of every near-list entry and of every item's near list
+    std::vector<int> ncnt(std::max<int64_t>(pl.n_near, 1));
+    std::vector<double> isrc(pl.nitems);
+    for (int64_t it = 0; it < pl.nitems; ++it) {
+      long long sum = 0;
+      for (long long e = np_[it]; e < np_[it + 1]; ++e) sum += (ncnt[e] = hc[nl[e]].count);
+      isrc[it] = (double)sum;
+    }
     double pairs = 0.0, m2p = 0.0;
     for (int ph = 0; ph < 2; ++ph)
       for (int ks = 0; ks < KS_COUNT; ++ks) pl.launch_flop_p2p[ph][ks] = pl.launch_flop_m2p[ph][ks] = 0.0;
@@ -1187,8 +1195,7 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       const TargetSet& ts = pl.tsets[bl.t];
       const int64_t g = it - bl.item_off;
       const double ntg = (double)std::min<int64_t>(kGroup, ts.n - g * kGroup);
-      double src = 0.0;
-      for (long long e = np_[it]; e < np_[it + 1]; ++e) src += hc[nl[e]].count;
+      const double src = isrc[it];
       const double ncell = (double)(fp_[it + 1] - fp_[it]);
       const int ph = bl.reaction ? 1 : 0;
       pl.launch_flop_p2p[ph][bl.ks] += ntg * src * p2p_flop_per_pair(bl.ks);
@@ -1212,12 +1219,8 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     const double resident = 32.0 * std::max(n_cu, 1);  // 4 SIMDs x 8 waves per CU
     auto p2p_units = [&](int t) {
       double u = 0.0;
-      for (int64_t it = 0; it < pl.nitems; ++it) {
-        if (pl.blocks[pl.item_block[it]].reaction) continue;
-        double src = 0.0;
-        for (long long e = np_[it]; e < np_[it + 1]; ++e) src += hc[nl[e]].count;
-        u += std::ceil(src / t);
-      }
+      for (int64_t it = 0; it < pl.nitems; ++it)
+        if (!pl.blocks[pl.item_block[it]].reaction) u += std::ceil(isrc[it] / t);
       return u;
     };
     auto m2p_units = [&](int t) {
@@ -1244,7 +1247,7 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
             if (kind == 0) {
               long long e = np_[item], acc = 0, start = e;
               for (; e < np_[item + 1]; ++e) {
-                const int cnt = hc[nl[e]].count;
+                const int cnt = ncnt[e];
                 if (acc > 0 && acc + cnt > kUnitSources) {
                   units.push_back(make_int4(item, (int)start, (int)e, 0));
                   start = e;

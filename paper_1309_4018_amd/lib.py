@@ -58,8 +58,8 @@ class Result(C.Structure):
         ("m2p_yuk_flop", C.c_double),
         ("t_setup_phase_s", C.c_double * 6),
         ("op_kernels", C.c_int), ("op_graph_launches", C.c_int),
-        ("t_kernel_s", C.c_double * 6), ("n_kernel_launch", C.c_int * 6),
-        ("kernel_flop", C.c_double * 6),
+        ("t_kernel_s", C.c_double * 7), ("n_kernel_launch", C.c_int * 7),
+        ("kernel_flop", C.c_double * 7),
         ("tile_sources", C.c_int), ("tile_cells", C.c_int),
     ]
 
