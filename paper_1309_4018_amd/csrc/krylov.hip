@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kRedThreads) void k_gs_pass_seg(
 __global__ __launch_bounds__(kRedThreads) void k_norm_scale_seg(
     const double* __restrict__ w, const double* __restrict__ nrm, const int4* __restrict__ chunks,
     const int* __restrict__ chunk0, const double* __restrict__ active, double* __restrict__ hn,
-    double* __restrict__ out) {
+    double* __restrict__ out, double* __restrict__ out2) {
   __shared__ double norm;
   const int4 ch = chunks[blockIdx.x / kChunkBlocks];
   const int c = ch.x;
@@ -229,17 +229,23 @@ __global__ __launch_bounds__(kRedThreads) void k_norm_scale_seg(
   }
   __syncthreads();
   const int64_t j = ch.y + (int64_t)(blockIdx.x % kChunkBlocks) * kRedThreads + threadIdx.x;
-  if (j < ch.z) out[j] = (active[c] > 0.0 && norm > 0.0) ? w[j] / norm : 0.0;
+  if (j < ch.z) {
+    const double v = (active[c] > 0.0 && norm > 0.0) ? w[j] / norm : 0.0;
+    out[j] = v;
+    if (out2) out2[j] = v;
+  }
 }
 
-// out = w / s[c] for active systems, 0 for the others
+// out = w / s[c] for active systems, 0 for the others (also into out2 if given)
 __global__ void k_scale_seg(const double* __restrict__ w, int64_t n, const double* __restrict__ s,
                             const int* __restrict__ comp, const double* __restrict__ active,
-                            double* __restrict__ out) {
+                            double* __restrict__ out, double* __restrict__ out2) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int c = comp[j];
-  out[j] = (active[c] > 0.0 && s[c] > 0.0) ? w[j] / s[c] : 0.0;
+  const double v = (active[c] > 0.0 && s[c] > 0.0) ? w[j] / s[c] : 0.0;
+  out[j] = v;
+  if (out2) out2[j] = v;
 }
 
 // start of a restart cycle: g = (beta, 0, ...), kfin = 0
@@ -454,7 +460,8 @@ struct Krylov {
   // one Arnoldi orthogonalisation of w against V_0..V_{nv-1} (CGS2) with
   // coefficients in h1 and h2 (per system), then vn = w / ||w|| and
   // hn = ||w|| for active systems
-  int arnoldi(int nv, double* h1, double* h2, double* hn, const double* active, double* vn) {
+  int arnoldi(int nv, double* h1, double* h2, double* hn, const double* active, double* vn,
+              double* vn2) {
     const int T = 256;
     if (!fuse) {
       int rc = dots(V, nv, w, h1);
@@ -466,7 +473,7 @@ struct Krylov {
       rc = sub_combo_norm(nv, h2, hn);
       if (rc) return rc;
       hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, w, n, hn, comp, active,
-                         vn);
+                         vn, vn2);
       PBTC_LAUNCH_CHECK();
       return PBTC_OK;
     }
@@ -480,7 +487,7 @@ struct Krylov {
     hipLaunchKernelGGL(k_gs_pass_seg<true>, grid, dim3(kRedThreads), 8 * nv, st, V, nv, n, red, ld,
                        chunks, chunk0, h2, ld, w, nrm);
     hipLaunchKernelGGL(k_norm_scale_seg, grid, dim3(kRedThreads), 0, st, w, nrm, chunks, chunk0,
-                       active, hn, vn);
+                       active, hn, vn, vn2);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
@@ -523,13 +530,20 @@ int apply_precond(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, b
 // from then on, so further operator applications leave it untouched.
 // prec: 0 none, 1 right preconditioning by M^-1, 2 by M^-T (transposed
 // system).
+// gin, gout (or null): the input and output buffers of the operator's launch
+// graph.  The Arnoldi step then writes each new basis vector (or its
+// preconditioned image) into gin as well and orthogonalises in gout, so that
+// the graph reads and writes them in place (no copies around a replay).
 template <typename Op>
 static int gmres(pbtc_plan_t& pl, hipStream_t st, Op op, int prec, const double* rhs, double* z,
                  bool zero_start,
                  const std::vector<double>& tol, const std::vector<double>& ref, int max_iter,
                  int* iters, std::vector<double>* hist, std::vector<int>* conv,
-                 std::vector<int>* conv_iter, int* discarded) {
+                 std::vector<int>* conv_iter, int* discarded, double* gin = nullptr,
+                 double* gout = nullptr) {
   Krylov K(pl, st);
+  if (gout) K.w = gout;
+  double* vin2 = (gin && !prec) ? gin : nullptr;  // second copy of each new basis vector
   const int T = 256;
   const int64_t n = K.n;
   const int m = K.m, nc = K.nc, ld = K.ld;
@@ -583,7 +597,7 @@ static int gmres(pbtc_plan_t& pl, hipStream_t st, Op op, int prec, const double*
       return PBTC_EDEVICE;
     }
     hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, r, n, K.scal(SC_BETA),
-                       K.comp, K.scal(SC_ACTIVE), K.V);
+                       K.comp, K.scal(SC_ACTIVE), K.V, vin2);
     hipLaunchKernelGGL(k_init_seg, dim3(1), dim3(64), 0, st, nc, K.giv, K.gstride, ld,
                        K.scal(SC_BETA), K.scal(SC_KFIN));
     // The residual estimates of iteration j are read on the host while
@@ -625,14 +639,15 @@ static int gmres(pbtc_plan_t& pl, hipStream_t st, Op op, int prec, const double*
         double* vj = K.V + (size_t)j * n;
         double* vn = K.V + (size_t)(j + 1) * n;
         if (prec) {
-          rc = apply_precond(pl, st, vj, pz, prec == 2, false);
-          if (!rc) rc = op(pz, K.w);
+          double* pin = gin ? gin : pz;
+          rc = apply_precond(pl, st, vj, pin, prec == 2, false);
+          if (!rc) rc = op(pin, K.w);
         } else {
-          rc = op(vj, K.w);
+          rc = op(gin ? gin : vj, K.w);
         }
         if (rc) return rc;
         // CGS2: two passes of classical Gram-Schmidt, per system
-        rc = K.arnoldi(j + 1, K.hbuf, K.h2buf, K.scal(SC_HN), K.scal(SC_ACTIVE), vn);
+        rc = K.arnoldi(j + 1, K.hbuf, K.h2buf, K.scal(SC_HN), K.scal(SC_ACTIVE), vn, vin2);
         if (rc) return rc;
         // Hessenberg column = first-pass + second-pass coefficients
         hipLaunchKernelGGL(k_givens_seg, dim3(nc), dim3(64), 8 * (3 * ld + 1), st, nc, j, ld,
@@ -715,6 +730,10 @@ int solve_with_ops(pbtc_plan_t& pl, hipStream_t st, bool transpose, const double
                      : apply_operator(pl, st, in, out, PBTC_FP32, 0);
   };
   const int prec = pl.prm.precond == PBTC_PREC_BLOCK_DIAG ? (transpose ? 2 : 1) : 0;
+  // A x through its launch graph: GMRES keeps its operator input and output
+  // in the graph's own buffers
+  double* gin = (!transpose && pl.prm.op_graph) ? wsp<double>(pl, pl.o_gxin) : nullptr;
+  double* gout = (!transpose && pl.prm.op_graph) ? wsp<double>(pl, pl.o_gyout) : nullptr;
   // systems with a zero right-hand side are solved by x = 0
   std::vector<double> ref(nc), tol(nc, pl.prm.tol);
   for (int c = 0; c < nc; ++c) ref[c] = bnorm[c] > 0.0 ? bnorm[c] : 1.0;
@@ -755,7 +774,7 @@ int solve_with_ops(pbtc_plan_t& pl, hipStream_t st, bool transpose, const double
       std::vector<int> cin;
       int disc = 0;
       rc = gmres(pl, st, op32, prec, r, d, true, tin, rref, pl.prm.max_iter, &iters, hist, &cin,
-                 nullptr, &disc);
+                 nullptr, &disc, gin, gout);
       n32 -= disc;  // operator evaluations whose results were not used
       if (rc) return rc;
       hipLaunchKernelGGL(k_axpy, dim3(nblocks(n, T)), dim3(T), 0, st, 1.0, d, n, x);
@@ -774,10 +793,10 @@ int solve_with_ops(pbtc_plan_t& pl, hipStream_t st, bool transpose, const double
     int disc = 0;
     if (opp == PBTC_FP64)
       rc = gmres(pl, st, op64, prec, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv,
-                 &cit, &disc);
+                 &cit, &disc, gin, gout);
     else
       rc = gmres(pl, st, op32, prec, b, x, true, tol, ref, pl.prm.max_iter, &iters, hist, &conv,
-                 &cit, &disc);
+                 &cit, &disc, gin, gout);
     (opp == PBTC_FP64 ? n64 : n32) -= disc;  // evaluations whose results were not used
     if (rc) return rc;
     rc = explicit_residual();
