@@ -29,7 +29,7 @@ constexpr int kProfM2PPair = 6;
 // group sphere), so fewer source points go to P2P.
 constexpr int kGroup = 16;
 constexpr int kQuarters = 64 / kGroup;  // lanes per target
-constexpr int kNearRun = 64;            // targets per near-field search wavefront
+constexpr int kNearRun = 16;            // targets per near-field search wavefront
 // Gauss points per target group of the transposed operator (one lane each:
 // with the Gauss points four to a panel, smaller groups cut few pairs)
 constexpr int kAGroup = 64;
@@ -40,6 +40,9 @@ constexpr int kMaxNk = 32;
 constexpr int kMomChunk = 128;   // sources staged at a time by the direct moment pass
 constexpr int kMomSpan = 1024;   // sources per block of the transposed operator's moment pass
 constexpr int kSpanSources = 256;  // largest cell whose moments one work-group forms from its sources
+// non-leaf cells of at most this many sources form their moments with their
+// subtree in one work-group; larger ones (and all cells above) by upward shifts
+constexpr int kSpanCell = 256;
 
 // Span roots shifted per work-group into one upper cell by the upward moment
 // pass: as many as fit 48 KiB of LDS in the dense (P+1)^3 FP64 layout of

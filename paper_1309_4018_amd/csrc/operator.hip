@@ -350,47 +350,52 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ pa
 }
 
 // Moments of an upper cell of several parts: the sum of the parts' partial
-// moments.  Wave w adds parts w, w + 4, ... (four loads in flight per lane),
-// then the four wave sums are added in wave order (deterministic).
+// moments.  Wave w of W adds parts w, w + W, ..., then the W wave sums are
+// added in wave order (deterministic).
 template <typename real, int P>
-__global__ __launch_bounds__(256) void k_mom_up_sum(const int4* __restrict__ sums,
-                                                    const real* __restrict__ partial,
-                                                    real* __restrict__ mom) {
+constexpr int sum_waves() {
+  constexpr int per = ((2 * ncoef(P) + 63) / 64) * 64 * (int)sizeof(real);
+  return 16 * per <= 49152 ? 16 : 8 * per <= 49152 ? 8 : 4;
+}
+
+template <typename real, int P>
+__global__ __launch_bounds__((64 * sum_waves<real, P>())) void k_mom_up_sum(
+    const int4* __restrict__ sums, const real* __restrict__ partial, real* __restrict__ mom) {
   constexpr int N2 = 2 * ncoef(P);
   constexpr int OPW = (N2 + 63) / 64;  // outputs per lane
-  __shared__ real red[3][OPW * 64];
+  constexpr int kSumWaves = sum_waves<real, P>();
+  __shared__ real red[kSumWaves][OPW * 64];
   const int4 sm = sums[blockIdx.x];  // (upper cell, first part, parts)
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   real acc[OPW];
 #pragma unroll
   for (int o = 0; o < OPW; ++o) acc[o] = 0;
   int p = w;
-  for (; p + 12 < sm.z; p += 16) {
+  for (; p + 3 * kSumWaves < sm.z; p += 4 * kSumWaves)  // four loads in flight per output
 #pragma unroll
     for (int o = 0; o < OPW; ++o) {
       const int k = lane + 64 * o;
       if (k < N2) {
         const real* q = partial + (size_t)(sm.y + p) * N2 + k;
-        const real v0 = q[0], v1 = q[4 * N2], v2 = q[8 * N2], v3 = q[12 * N2];
+        const real v0 = q[0], v1 = q[(size_t)kSumWaves * N2], v2 = q[(size_t)2 * kSumWaves * N2],
+                   v3 = q[(size_t)3 * kSumWaves * N2];
         acc[o] += (v0 + v1) + (v2 + v3);
       }
     }
-  }
-  for (; p < sm.z; p += 4)
+  for (; p < sm.z; p += kSumWaves)
 #pragma unroll
     for (int o = 0; o < OPW; ++o) {
       const int k = lane + 64 * o;
       if (k < N2) acc[o] += partial[(size_t)(sm.y + p) * N2 + k];
     }
-  if (w > 0)
 #pragma unroll
-    for (int o = 0; o < OPW; ++o) red[w - 1][lane + 64 * o] = acc[o];
+  for (int o = 0; o < OPW; ++o) red[w][lane + 64 * o] = acc[o];
   __syncthreads();
-  if (w > 0) return;
+  for (int k = threadIdx.x; k < N2; k += 64 * kSumWaves) {
+    real v = 0;
 #pragma unroll
-  for (int o = 0; o < OPW; ++o) {
-    const int k = lane + 64 * o;
-    if (k < N2) mom[(size_t)sm.x * N2 + k] = acc[o] + red[0][k] + red[1][k] + red[2][k];
+    for (int ww = 0; ww < kSumWaves; ++ww) v += red[ww][k];
+    mom[(size_t)sm.x * N2 + k] = v;
   }
 }
 
@@ -460,10 +465,12 @@ __device__ __forceinline__ void unit_store(real* __restrict__ partial, int u, re
     for (int i = 0; i < NQ; ++i) partial[((size_t)u * 4 + i) * kGroup + lane] = acc[i];
 }
 
-// P2P: the unit's cells pass through a per-wavefront LDS slice 64 sources at
-// a time (one coalesced load per lane, the next chunk loaded while the
-// current one is used); the four lanes of a target take every fourth staged
-// source, so that a pair's operands are all vector registers.
+// P2P: the sources of the unit's cells form one stream (cells in list order)
+// that passes through a per-wavefront LDS slice 64 sources at a time: one
+// load per lane, whatever cell the source lies in (a lane finds it by binary
+// search over the prefix of the cells' counts), the next chunk loaded while
+// the current one is used.  The four lanes of a target take every fourth
+// staged source, so that a pair's operands are all vector registers.
 template <typename real, int KS>
 __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __restrict__ tx,
                                                       const real* __restrict__ ty,
@@ -471,6 +478,7 @@ __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __
                                                       const Src<real>* __restrict__ src,
                                                       real* __restrict__ partial) {
   __shared__ Src<real> stage[kWaves][64];
+  __shared__ int cbeg[kWaves][64], cpre[kWaves][64];
   const int u = uni(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (u >= a.nunits) return;
   const int wv = uni(threadIdx.x >> 6);
@@ -486,13 +494,6 @@ __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __
   const real k0 = (real)b.kappa0, k1 = (real)b.kappa1;
   const real a0 = exp_arg(k0), a1 = exp_arg(k1);
   real acc[4] = {0, 0, 0, 0};
-  // chunk iterator over (cell e, offset off): sources [cb + off, cb + off + 64) ∩ [cb, cb + cn)
-  int e = e0, cb = 0, cn = 0, off = 0;
-  if (e < e1) {
-    const int c = uni(a.cells_list[e]);
-    cb = uni(a.cells[c].begin);
-    cn = uni(a.cells[c].count);
-  }
   // a source record travels in seven registers (no aggregate copies)
   real cur[7] = {0, 0, 0, 0, 0, 0, 0}, nxt[7] = {0, 0, 0, 0, 0, 0, 0};
   auto load = [&](real (&v)[7], int j) {
@@ -505,52 +506,68 @@ __global__ __launch_bounds__(kItemThreads) void k_p2p(UnitArgs a, const real* __
     v[5] = r.py;
     v[6] = r.pz;
   };
-  if (e < e1 && lane < cn) load(cur, cb + lane);
-  while (e < e1) {
-    const int n = min(64, cn - off);
-    // the next chunk, loaded while this one is evaluated
-    int ne = e, nb = cb, nn = cn, noff = off + 64;
-    if (noff >= cn) {
-      ne = e + 1;
-      noff = 0;
-      if (ne < e1) {
-        const int c = uni(a.cells_list[ne]);
-        nb = uni(a.cells[c].begin);
-        nn = uni(a.cells[c].count);
-      }
-    }
-    if (ne < e1 && lane < nn - noff) load(nxt, nb + noff + lane);
-    if (lane < n) {
-      Src<real>& d = stage[wv][lane];
-      d.x = cur[0];
-      d.y = cur[1];
-      d.z = cur[2];
-      d.q = cur[3];
-      d.px = cur[4];
-      d.py = cur[5];
-      d.pz = cur[6];
-    }
-    wave_sync();
-    int j = qt;
-    for (; j + 3 * kQuarters < n; j += 4 * kQuarters) {
-      const Src<real> s0 = stage[wv][j], s1 = stage[wv][j + kQuarters],
-                      s2 = stage[wv][j + 2 * kQuarters], s3 = stage[wv][j + 3 * kQuarters];
-      pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
-      pair<real, KS>(x, y, z, s1, k0, k1, a0, a1, acc);
-      pair<real, KS>(x, y, z, s2, k0, k1, a0, a1, acc);
-      pair<real, KS>(x, y, z, s3, k0, k1, a0, a1, acc);
-    }
-    for (; j < n; j += kQuarters) {
-      const Src<real> s0 = stage[wv][j];
-      pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
-    }
-    wave_sync();  // the slice is read before the next chunk overwrites it
-    e = ne;
-    cb = nb;
-    cn = nn;
-    off = noff;
+  // source of stream position p of the current batch of cells
+  int ncb = 0;
+  auto source_of = [&](int p) {
+    int lo = 0;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) cur[i] = nxt[i];
+    for (int step = 32; step > 0; step >>= 1)
+      if (lo + step < ncb && cpre[wv][lo + step] <= p) lo += step;
+    return cbeg[wv][lo] + (p - cpre[wv][lo]);
+  };
+  for (int eb = e0; eb < e1; eb += 64) {
+    // a batch of up to 64 cells: first sources and the exclusive prefix of
+    // their counts
+    ncb = min(64, e1 - eb);
+    int beg = 0, cnt = 0;
+    if (lane < ncb) {
+      const int c = a.cells_list[eb + lane];
+      beg = a.cells[c].begin;
+      cnt = a.cells[c].count;
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    const int total = __shfl(incl, 63);
+    wave_sync();  // the previous batch's table is no longer read
+    cbeg[wv][lane] = beg;
+    cpre[wv][lane] = incl - cnt;
+    wave_sync();
+    if (lane < total) load(cur, source_of(lane));
+    for (int p0 = 0; p0 < total; p0 += 64) {
+      const int n = min(64, total - p0);
+      if (p0 + 64 + lane < total) load(nxt, source_of(p0 + 64 + lane));
+      if (lane < n) {
+        Src<real>& d = stage[wv][lane];
+        d.x = cur[0];
+        d.y = cur[1];
+        d.z = cur[2];
+        d.q = cur[3];
+        d.px = cur[4];
+        d.py = cur[5];
+        d.pz = cur[6];
+      }
+      wave_sync();
+      int j = qt;
+      for (; j + 3 * kQuarters < n; j += 4 * kQuarters) {
+        const Src<real> s0 = stage[wv][j], s1 = stage[wv][j + kQuarters],
+                        s2 = stage[wv][j + 2 * kQuarters], s3 = stage[wv][j + 3 * kQuarters];
+        pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
+        pair<real, KS>(x, y, z, s1, k0, k1, a0, a1, acc);
+        pair<real, KS>(x, y, z, s2, k0, k1, a0, a1, acc);
+        pair<real, KS>(x, y, z, s3, k0, k1, a0, a1, acc);
+      }
+      for (; j < n; j += kQuarters) {
+        const Src<real> s0 = stage[wv][j];
+        pair<real, KS>(x, y, z, s0, k0, k1, a0, a1, acc);
+      }
+      wave_sync();  // the slice is read before the next chunk overwrites it
+#pragma unroll
+      for (int i = 0; i < 7; ++i) cur[i] = nxt[i];
+    }
   }
   unit_store<real, nacc<KS>()>(partial, u, acc);
 }
@@ -810,8 +827,8 @@ static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<
       hipLaunchKernelGGL((k_mom_up_part<real, PP>), dim3(npt), dim3(256), 0, st, parts,       \
                          sroot, cells, mom, partial);                                         \
     if (nsum > 0)                                                                             \
-      hipLaunchKernelGGL((k_mom_up_sum<real, PP>), dim3(nsum), dim3(256), 0, st, sums,        \
-                         partial, mom);                                                       \
+      hipLaunchKernelGGL((k_mom_up_sum<real, PP>), dim3(nsum), dim3(64 * sum_waves<real, PP>()), \
+                         0, st, sums, partial, mom);                                          \
     break;
   switch (pl.P) {
     PBTC_MOM(2)

@@ -411,7 +411,8 @@ __device__ __forceinline__ void target_point(const NearArgs& a, const DevBlock& 
 // lane per target: the wave walks the leaves that may hold such a panel for
 // some target of the run (inside the run's bounding sphere plus the reach)
 // and tests every panel of each leaf (its first Gauss point stands for it)
-// against all 64 targets at once.
+// against the run's targets at once.  Small runs keep the sphere tight and
+// give many short walks.
 // mode 0: count per row; mode 1: fill columns at the row offsets in ptr;
 // mode 2: count per row and keep the first `slot_cap` columns of every row in
 // slots[row * slot_cap ..] (flags[1] set when a row has more).
@@ -1278,7 +1279,7 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     bool too_big = false;
     const int up_batch = mom_up_batch(pl.P);
     std::function<void(int)> visit = [&](int c) {
-      if (hc[c].count <= kSpanSources) {
+      if (hc[c].nchild == 0 ? hc[c].count <= kSpanSources : hc[c].count <= kSpanCell) {
         const size_t first = mch.size();
         mch.push_back(make_int4(c, hc[c].begin, hc[c].count, 0));
         for (size_t i = first; i < mch.size(); ++i) {
