@@ -264,13 +264,23 @@ __global__ void k_init_seg(int nc, double* giv, int gstride, int ld, const doubl
 // apply the stored rotations, form the new one, update g, and deactivate the
 // system once |g_{j+1}| <= tol * ref (kfin = j + 1).  The column and the
 // rotations pass through LDS; the rotations themselves are sequential.
+// hout (or null): pinned host memory that receives [residual estimate,
+// active flag] of every system (2 nc values), read by the host behind the
+// event recorded after this kernel.
 __global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h,
                              const double* __restrict__ h2, double* __restrict__ H,
-                             double* __restrict__ giv, int gstride, double* __restrict__ sc) {
+                             double* __restrict__ giv, int gstride, double* __restrict__ sc,
+                             double* __restrict__ hout) {
   extern __shared__ double lds[];  // col (ld + 1), cs (ld), sn (ld)
   const int c = blockIdx.x;
   double* act = sc + (size_t)SC_ACTIVE * nc;
-  if (act[c] <= 0.0) return;
+  if (act[c] <= 0.0) {
+    if (hout && threadIdx.x == 0) {
+      hout[c] = sc[(size_t)SC_RES * nc + c];
+      hout[nc + c] = 0.0;
+    }
+    return;
+  }
   double* cs = giv + (size_t)c * gstride;
   double* sn = cs + ld;
   double* g = cs + 2 * ld;
@@ -310,6 +320,10 @@ __global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h
     if (res <= sc[(size_t)SC_TOL * nc + c] || den == 0.0) {
       act[c] = 0.0;
       sc[(size_t)SC_KFIN * nc + c] = j + 1;
+    }
+    if (hout) {
+      hout[c] = res;
+      hout[nc + c] = act[c];
     }
   }
   __syncthreads();
@@ -650,12 +664,12 @@ static int gmres(pbtc_plan_t& pl, hipStream_t st, Op op, int prec, const double*
         rc = K.arnoldi(j + 1, K.hbuf, K.h2buf, K.scal(SC_HN), K.scal(SC_ACTIVE), vn, vin2);
         if (rc) return rc;
         // Hessenberg column = first-pass + second-pass coefficients
+        // the residual estimates and active flags of every system go straight
+        // to pinned host memory (no copy operation)
         hipLaunchKernelGGL(k_givens_seg, dim3(nc), dim3(64), 8 * (3 * ld + 1), st, nc, j, ld,
-                           K.hbuf, K.h2buf, K.H, K.giv, K.gstride, K.sc);
+                           K.hbuf, K.h2buf, K.H, K.giv, K.gstride, K.sc,
+                           pl.res_pin + (size_t)(j & 1) * 2 * nc);
         PBTC_LAUNCH_CHECK();
-        // residual estimates and active flags of every system (SC_RES, SC_ACTIVE)
-        PBTC_HIP(hipMemcpyAsync(pl.res_pin + (size_t)(j & 1) * 2 * nc, K.scal(SC_RES), 16 * nc,
-                                hipMemcpyDeviceToHost, st));
         PBTC_HIP(hipEventRecord(pl.res_ev[j & 1], st));
         ++j;
       }

@@ -655,26 +655,17 @@ __global__ __launch_bounds__((64 * m2p_waves<real, P>())) void k_m2p(
   unit_store<real, KIND1 >= 0 ? 4 : 2>(partial, u, acc);
 }
 
-// Sum of the units of every listed item, times 1/(4 pi), into S and D of
-// kernel slots first_slot.. (mode 0 store, mode 1 add).  One wavefront per
-// item: lane = target t (lane % kGroup) of quarter q (lane / kGroup); quarter
-// q adds units q, q + 4, ... of the item, then the quarters' sums are added
-// across the wave (fixed order: deterministic).
+// Sum of the P2P units and the M2P units of every listed item, times
+// 1/(4 pi), stored into S and D of the block's kernel slots.  One wavefront
+// per item: lane = target t (lane % kGroup) of quarter q (lane / kGroup);
+// quarter q adds units q, q + 4, ... of each set, then the quarters' sums are
+// added across the wave (fixed order: deterministic).  uptr_f = null: no
+// far-field units.
 constexpr int kReduceWaves = 4;
 
 template <typename real, int NQ>
-__global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
-    int nlist, const int* __restrict__ list, const int* __restrict__ uptr,
-    const int* __restrict__ item_block, const DevBlock* __restrict__ blocks,
-    const int* __restrict__ tidx, const real* __restrict__ partial, double* __restrict__ S,
-    double* __restrict__ D, int mode, int first_slot) {
-  const int l = blockIdx.x * kReduceWaves + (threadIdx.x >> 6);
-  if (l >= nlist) return;
-  const int lane = threadIdx.x & 63, t = lane % kGroup, qt = lane / kGroup;
-  double v[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-  const int u0 = uptr[l], u1 = uptr[l + 1];
+__device__ __forceinline__ void add_units(double (&v)[NQ], const real* __restrict__ partial,
+                                          int u0, int u1, int t, int qt) {
   int u = u0 + qt;
   // two units per step per lane
   for (; u + kQuarters < u1; u += 2 * kQuarters) {
@@ -690,6 +681,23 @@ __global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
   if (u < u1)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] += (double)partial[((size_t)u * 4 + q) * kGroup + t];
+}
+
+template <typename real, int NQ>
+__global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
+    int nlist, const int* __restrict__ list, const int* __restrict__ uptr_n,
+    const real* __restrict__ partial_n, const int* __restrict__ uptr_f,
+    const real* __restrict__ partial_f, const int* __restrict__ item_block,
+    const DevBlock* __restrict__ blocks, const int* __restrict__ tidx, double* __restrict__ S,
+    double* __restrict__ D) {
+  const int l = blockIdx.x * kReduceWaves + (threadIdx.x >> 6);
+  if (l >= nlist) return;
+  const int lane = threadIdx.x & 63, t = lane % kGroup, qt = lane / kGroup;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  add_units<real, NQ>(v, partial_n, uptr_n[l], uptr_n[l + 1], t, qt);
+  if (uptr_f) add_units<real, NQ>(v, partial_f, uptr_f[l], uptr_f[l + 1], t, qt);
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -703,13 +711,8 @@ __global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
   const long long i = tidx[t0 + lane] - b.tgt_off;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const long long out = (first_slot + (q >> 1) == 0 ? b.out0 : b.out1) + i;
-    double* dst = (q & 1) ? D : S;
-    const double val = v[q] * kInv4Pi;
-    if (mode == 0)
-      dst[out] = val;
-    else
-      dst[out] += val;
+    const long long out = ((q >> 1) == 0 ? b.out0 : b.out1) + i;
+    ((q & 1) ? D : S)[out] = v[q] * kInv4Pi;
   }
 }
 
@@ -948,78 +951,77 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
     const int n = (int)pl.item_list[phase][ks].size();
     if (n == 0) continue;
     const int* list = wsp<int>(pl, pl.o_item_list[phase][ks]);
-    // P2P over the near lists
+    // P2P over the near lists; each unit set writes its own region of the
+    // partial sums (by the set's first unit), so that one reduction adds both
+    const UnitSet& un = pl.units[phase][ks][0];
+    real* part_n = partial + (size_t)un.off * 4 * kGroup;
     {
-      const UnitSet& us = pl.units[phase][ks][0];
-      a.units = wsp<int4>(pl, pl.o_units + 16 * us.off);
-      a.nunits = (int)us.n;
+      a.units = wsp<int4>(pl, pl.o_units + 16 * un.off);
+      a.nunits = (int)un.n;
       a.cells_list = wsp<int>(pl, pl.o_near);
-      const int grid = nblocks(us.n, kWaves);
+      const int grid = nblocks(un.n, kWaves);
       prof_mark(pl, st, timed, 0, pl.launch_flop_p2p[phase][ks], true);
       // no units (every cell seen through its expansion): the reduction
-      // below still stores the zero P2P sums
+      // below still stores the (M2P or zero) sums
       if (grid > 0) switch (ks) {
         case KS_L:
-          hipLaunchKernelGGL((k_p2p<real, KS_L>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
+          hipLaunchKernelGGL((k_p2p<real, KS_L>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, part_n);
           break;
         case KS_Y:
-          hipLaunchKernelGGL((k_p2p<real, KS_Y>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
+          hipLaunchKernelGGL((k_p2p<real, KS_Y>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, part_n);
           break;
         case KS_LY:
-          hipLaunchKernelGGL((k_p2p<real, KS_LY>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
+          hipLaunchKernelGGL((k_p2p<real, KS_LY>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, part_n);
           break;
         case KS_YY:
-          hipLaunchKernelGGL((k_p2p<real, KS_YY>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, partial);
+          hipLaunchKernelGGL((k_p2p<real, KS_YY>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, part_n);
           break;
       }
       prof_mark(pl, st, timed, 0, 0.0, false);
-      const int* uptr = wsp<int>(pl, pl.o_uptr + 4 * us.ptr_off);
-      if (ks == KS_L || ks == KS_Y)
-        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(nblocks(n, kReduceWaves)),
-                           dim3(64 * kReduceWaves), 0, st, n, list, uptr, a.item_block, a.blocks,
-                           tidx, partial, S, D, 0, 0);
-      else
-        hipLaunchKernelGGL((k_reduce<real, 4>), dim3(nblocks(n, kReduceWaves)),
-                           dim3(64 * kReduceWaves), 0, st, n, list, uptr, a.item_block, a.blocks,
-                           tidx, partial, S, D, 0, 0);
       PBTC_LAUNCH_CHECK();
     }
-    if (tree && pl.n_far > 0) {
-      const UnitSet& us = pl.units[phase][ks][1];
-      if (us.n == 0) continue;
+    const int* uptr_n = wsp<int>(pl, pl.o_uptr + 4 * un.ptr_off);
+    const int* uptr_f = nullptr;
+    real* part_f = nullptr;
+    const UnitSet& uf = pl.units[phase][ks][1];
+    if (tree && pl.n_far > 0 && uf.n > 0) {
       if (!joined) {
         PBTC_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));
         joined = true;
       }
-      a.units = wsp<int4>(pl, pl.o_units + 16 * us.off);
-      a.nunits = (int)us.n;
+      a.units = wsp<int4>(pl, pl.o_units + 16 * uf.off);
+      a.nunits = (int)uf.n;
       a.cells_list = wsp<int>(pl, pl.o_far);
-      const int* uptr = wsp<int>(pl, pl.o_uptr + 4 * us.ptr_off);
+      part_f = partial + (size_t)uf.off * 4 * kGroup;
+      uptr_f = wsp<int>(pl, pl.o_uptr + 4 * uf.ptr_off);
       if (ks == KS_L || ks == KS_Y) {
         const int kind = ks == KS_L ? 0 : 1;
         prof_mark(pl, st, timed, 1 + kind, pl.launch_flop_m2p[phase][ks], true);
         if (kind == 0)
-          launch_m2p<real, 0, -1>(pl, st, a, tx, ty, tz, mom, 0, partial);
+          launch_m2p<real, 0, -1>(pl, st, a, tx, ty, tz, mom, 0, part_f);
         else
-          launch_m2p<real, 1, -1>(pl, st, a, tx, ty, tz, mom, 0, partial);
+          launch_m2p<real, 1, -1>(pl, st, a, tx, ty, tz, mom, 0, part_f);
         prof_mark(pl, st, timed, 1 + kind, 0.0, false);
-        hipLaunchKernelGGL((k_reduce<real, 2>), dim3(nblocks(n, kReduceWaves)),
-                           dim3(64 * kReduceWaves), 0, st, n, list, uptr, a.item_block, a.blocks,
-                           tidx, partial, S, D, 1, 0);
       } else {
         // two kernels (Laplace + Yukawa, or two Yukawa) in one pass
         prof_mark(pl, st, timed, kProfM2PPair, pl.launch_flop_m2p[phase][ks], true);
         if (ks == KS_LY)
-          launch_m2p<real, 0, 1>(pl, st, a, tx, ty, tz, mom, 0, partial);
+          launch_m2p<real, 0, 1>(pl, st, a, tx, ty, tz, mom, 0, part_f);
         else
-          launch_m2p<real, 1, 1>(pl, st, a, tx, ty, tz, mom, 0, partial);
+          launch_m2p<real, 1, 1>(pl, st, a, tx, ty, tz, mom, 0, part_f);
         prof_mark(pl, st, timed, kProfM2PPair, 0.0, false);
-        hipLaunchKernelGGL((k_reduce<real, 4>), dim3(nblocks(n, kReduceWaves)),
-                           dim3(64 * kReduceWaves), 0, st, n, list, uptr, a.item_block, a.blocks,
-                           tidx, partial, S, D, 1, 0);
       }
       PBTC_LAUNCH_CHECK();
     }
+    if (ks == KS_L || ks == KS_Y)
+      hipLaunchKernelGGL((k_reduce<real, 2>), dim3(nblocks(n, kReduceWaves)),
+                         dim3(64 * kReduceWaves), 0, st, n, list, uptr_n, part_n, uptr_f, part_f,
+                         a.item_block, a.blocks, tidx, S, D);
+    else
+      hipLaunchKernelGGL((k_reduce<real, 4>), dim3(nblocks(n, kReduceWaves)),
+                         dim3(64 * kReduceWaves), 0, st, n, list, uptr_n, part_n, uptr_f, part_f,
+                         a.item_block, a.blocks, tidx, S, D);
+    PBTC_LAUNCH_CHECK();
   }
   if (!joined) PBTC_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));  // no far field in this phase
   // near-field corrections of this phase's blocks
