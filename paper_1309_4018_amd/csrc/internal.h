@@ -43,6 +43,13 @@ constexpr int kSpanSources = 256;  // largest cell whose moments one work-group 
 // non-leaf cells of at most this many sources form their moments with their
 // subtree in one work-group; larger ones (and all cells above) by upward shifts
 constexpr int kSpanCell = 256;
+// a span cell of more sources than this (or the only cell of its span, when
+// it has more than kMomSharedLone) is summed by all waves of the span's
+// work-group; smaller cells by one wave each
+constexpr int kMomShared = 64;
+constexpr int kMomSharedLone = 16;
+// sources (summed over cells) of one work-group of the span moment pass
+constexpr int kMomJob = 128;
 
 // Span roots shifted per work-group into one upper cell by the upward moment
 // pass: as many as fit 48 KiB of LDS in the dense (P+1)^3 FP64 layout of
@@ -274,7 +281,8 @@ struct pbtc_plan_s {
   // cell, cells, first source, count) and their root cells, upward parts
   // (upper cell, first span, end span, sole part) and sums (upper cell,
   // first part, parts), the parts' partial moments
-  size_t o_mchunks = 0, o_mspans = 0, o_msroot = 0, o_mparts = 0, o_musum = 0, o_mpart = 0;
+  size_t o_mchunks = 0, o_mcent = 0, o_mspans = 0, o_mproot = 0, o_mph = 0, o_mparts = 0,
+         o_musum = 0, o_mpart = 0;
   int64_t n_mchunks = 0, n_mspans = 0, n_mparts = 0, n_musum = 0, cap_mparts = 0;
   // direct moment pass of the transposed operator: chunks (cell, first
   // source, count, slot) and (cell x local slot, first chunk, end chunk)

@@ -63,162 +63,264 @@ __global__ void k_prep(int64_t ngp, const double* __restrict__ gx, const double*
 // FMAs.
 //
 // A span root is a cell of at most kSpanSources sources whose parent has more
-// (or a tree root that small).  One work-group per span root stages the
-// span's sources in LDS once and forms the moments of every cell of the
-// span's subtree directly from them, so each source comes from HBM once.
+// (or a tree root that small).  The cells of a span root's subtree are
+// formed directly from the sources, in jobs: breadth-first runs of the
+// span's cells of at most kMomJob sources in all, one work-group each, which
+// stages the sources of its cells in LDS once (the jobs of one span are
+// neighbours in the launch, so a second read of the span's sources is
+// served by L2).
 // The larger (upper) cells then add the moments of the span roots below
 // them, shifted to their own centres by the multi-index binomial theorem
 // (sec. 2.3: moments shifted towards the root and added),
 //   (y - c_u)^k = sum_{j <= k} C(k, j) h^(k - j) (y - c_s)^j,   h = c_s - c_u,
 // which holds for both moment kinds (the double layer is a linear map of the
 // same monomials), so upper cells never re-read the sources.
-constexpr int kMomThreads = 256;
+//
+// Inside a job the work is split so that waves rarely wait for each other:
+// cells the host marks as shared (more than kMomShared sources, or the only
+// cell of its job) are summed by all four waves, a quarter of the sources
+// each, and combined after one barrier; every other cell belongs to one wave
+// (round robin over the job's cells, largest first), which sums all of its
+// sources and assembles the double layer with wave-level synchronisation only.
+// A lane owns coefficients lane, lane + 64, ...; for a run of kMomRows staged
+// sources the lanes first write each source's power table into the wave's
+// LDS slice -- (y-c)_x^a (y-c)_y^b for a + b <= P, then (y-c)_z^c -- so that a
+// (source, coefficient) term is two LDS reads, one product and four FMAs.
+constexpr int kMomWaves = 4;
+constexpr int kMomThreads = 64 * kMomWaves;
+constexpr int kMomRows = 32;       // sources per fill of a wave's power table
 constexpr int kSpanCellsLds = 64;  // span cells whose entries are staged in LDS
+
+__host__ __device__ constexpr int mom_xy_terms(int P) { return (P + 1) * (P + 2) / 2; }
+__host__ __device__ constexpr int mom_row(int P) { return mom_xy_terms(P) + P + 1; }
+
+// Per-coefficient constants of the moment pass, indexed by k (lane + 64 p):
+// e[k][0] = power-table offsets (x-y entry | z entry << 8) | a << 16 |
+// b << 20 | c << 24 for k = (a, b, c); e[k][1] = the entries k - e_d of the
+// dipole moments (10 bits each, 0 where k_d = 0).  Indices past the last
+// coefficient repeat k = 0.
+template <int P>
+struct MomLaneTable {
+  static constexpr int KP = (ncoef(P) + 63) / 64;
+  int e[KP * 64][2];
+  constexpr MomLaneTable() : e() {
+    for (int deg = 0; deg <= P; ++deg)
+      for (int a = deg; a >= 0; --a)
+        for (int b = deg - a; b >= 0; --b) {
+          const int c = deg - a - b;
+          const int k = mindex(a, b, c);
+          const int ixy = a * (P + 1) - a * (a - 1) / 2 + b, iz = mom_xy_terms(P) + c;
+          e[k][0] = ixy | (iz << 8) | (a << 16) | (b << 20) | (c << 24);
+          e[k][1] = (a ? mindex(a - 1, b, c) : 0) | ((b ? mindex(a, b - 1, c) : 0) << 10) |
+                    ((c ? mindex(a, b, c - 1) : 0) << 20);
+        }
+    for (int k = ncoef(P); k < KP * 64; ++k) {
+      e[k][0] = e[0][0];
+      e[k][1] = e[0][1];
+    }
+  }
+};
+template <int P>
+__constant__ MomLaneTable<P> kMomLanes = MomLaneTable<P>();
+
+template <typename real>
+struct alignas(4 * sizeof(real)) Wt4 {
+  real v[4];  // q, p_x, p_y, p_z of a source
+};
+
+// Sums sources [lo, lo + n) of the staged span into acc (coefficient k =
+// lane + 64 p, weights q, p_x, p_y, p_z) about centre c; slice is the wave's
+// power-table scratch.
+template <typename real, int P, int KP>
+__device__ __forceinline__ void mom_accumulate(const real (*sxyz)[3], const Wt4<real>* sw, real* slice,
+                                               int lo, int n, real cx, real cy, real cz,
+                                               const int (&ixy)[KP], const int (&iz)[KP],
+                                               real (&acc)[KP][4]) {
+  constexpr int ROW = mom_row(P), TXY = mom_xy_terms(P);
+  const int lane = threadIdx.x & 63;
+  for (int r0 = 0; r0 < n; r0 += kMomRows) {
+    const int nr = min(kMomRows, n - r0);
+    if (lane < nr) {
+      const int t = lo + r0 + lane;
+      const real dx = sxyz[t][0] - cx, dy = sxyz[t][1] - cy, dz = sxyz[t][2] - cz;
+      real px[P + 1], py[P + 1];
+      px[0] = py[0] = 1;
+#pragma unroll
+      for (int a = 1; a <= P; ++a) {
+        px[a] = px[a - 1] * dx;
+        py[a] = py[a - 1] * dy;
+      }
+      real* row = slice + lane * ROW;
+#pragma unroll
+      for (int a = 0; a <= P; ++a)
+#pragma unroll
+        for (int b = 0; a + b <= P; ++b) row[a * (P + 1) - a * (a - 1) / 2 + b] = px[a] * py[b];
+      real v = 1;
+#pragma unroll
+      for (int c = 0; c <= P; ++c) {
+        row[TXY + c] = v;
+        v *= dz;
+      }
+    }
+    wave_sync();  // the power tables are written
+#pragma unroll 4
+    for (int t = 0; t < nr; ++t) {
+      const Wt4<real> wt = sw[lo + r0 + t];
+      const real* row = slice + t * ROW;
+#pragma unroll
+      for (int p = 0; p < KP; ++p) {
+        const real m = row[ixy[p]] * row[iz[p]];
+        // the dipole moments are needed below degree P only: a pass of
+        // degree-P coefficients sums the charge term alone
+        constexpr int kLow = ncoef(P - 1);
+        const int nw = 64 * p >= kLow ? 1 : 4;
+#pragma unroll
+        for (int i = 0; i < nw; ++i) acc[p][i] += wt.v[i] * m;
+      }
+    }
+    wave_sync();  // the rows are read before the next fill
+  }
+}
 
 template <typename real, int P>
 __global__ __launch_bounds__(kMomThreads) void k_mom_span(const int4* __restrict__ spans,
                                                           const int4* __restrict__ scells,
-                                                          const Cell* __restrict__ cells,
+                                                          const double4* __restrict__ cent,
                                                           const Src<real>* __restrict__ src,
                                                           real* __restrict__ mom) {
   constexpr int N = ncoef(P);
-  constexpr int G = N <= kMomThreads ? kMomThreads / N : 1;  // groups of sources
-  constexpr int KPT = (N + kMomThreads - 1) / kMomThreads;   // coefficients per thread
-  static_assert(kMomChunk <= kMomThreads && kSpanSources <= kMomThreads,
-                "one source per thread while staging");
+  constexpr int KP = (N + 63) / 64;  // coefficients per lane
+  constexpr int TXY = mom_xy_terms(P);
+  constexpr int SLICE = kMomRows * mom_row(P);
+  static_assert(4 * N <= SLICE, "a wave's partial moments fit its slice");
+  static_assert(kSpanCell <= kSpanSources && kSpanCellsLds <= kMomThreads,
+                "a span's sources and cell entries fit the staging arrays");
   __shared__ real sxyz[kSpanSources][3];
-  __shared__ real sw[kSpanSources][4];  // q, p_x, p_y, p_z
-  __shared__ real pw[kMomChunk][3][P + 1];
-  __shared__ real red[G][4][N];
+  __shared__ Wt4<real> sw[kSpanSources];
+  __shared__ real slice[kMomWaves][SLICE];
   __shared__ int4 sce[kSpanCellsLds];
   __shared__ real scc[kSpanCellsLds][3];
-  // span: (first entry of its cells in scells, number of cells, first source, sources)
+  // job: (first entry of its cells in scells, number of cells, first source, sources)
   const int4 sp = spans[xcd_block(blockIdx.x, gridDim.x)];
-  const int tid = threadIdx.x;
-  // the span's cell entries and centres, loaded together
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid < min(sp.y, kSpanCellsLds)) {
-    const int4 ce = scells[sp.x + tid];
-    const Cell& cl = cells[ce.x];
-    sce[tid] = ce;
-    scc[tid][0] = (real)cl.cx;
-    scc[tid][1] = (real)cl.cy;
-    scc[tid][2] = (real)cl.cz;
+    const double4 cc = cent[sp.x + tid];
+    sce[tid] = scells[sp.x + tid];
+    scc[tid][0] = (real)cc.x;
+    scc[tid][1] = (real)cc.y;
+    scc[tid][2] = (real)cc.z;
   }
-  if (tid < sp.w) {
-    const Src<real> s = src[sp.z + tid];
-    sxyz[tid][0] = s.x;
-    sxyz[tid][1] = s.y;
-    sxyz[tid][2] = s.z;
-    sw[tid][0] = s.q;
-    sw[tid][1] = s.px;
-    sw[tid][2] = s.py;
-    sw[tid][3] = s.pz;
+  for (int t = tid; t < sp.w; t += kMomThreads) {
+    const Src<real> s = src[sp.z + t];
+    sxyz[t][0] = s.x;
+    sxyz[t][1] = s.y;
+    sxyz[t][2] = s.z;
+    Wt4<real> wt;
+    wt.v[0] = s.q;
+    wt.v[1] = s.px;
+    wt.v[2] = s.py;
+    wt.v[3] = s.pz;
+    sw[t] = wt;
   }
-  const int g = N <= kMomThreads ? tid / N : 0;
-  int kk[KPT][3];
-  bool on[KPT];
+  // this lane's coefficients: power-table offsets, and the entries
+  // k - e_d of the dipole moments that form the double layer
+  int ixy[KP], iz[KP], jd[KP][3], kd[KP][3];
 #pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = N <= kMomThreads ? tid - g * N : tid + q * kMomThreads;
-    on[q] = N <= kMomThreads ? tid < G * N : k < N;
-    mindex_inv(on[q] ? k : 0, kk[q][0], kk[q][1], kk[q][2]);
+  for (int p = 0; p < KP; ++p) {
+    const int e0 = kMomLanes<P>.e[lane + 64 * p][0], e1 = kMomLanes<P>.e[lane + 64 * p][1];
+    ixy[p] = e0 & 255;
+    iz[p] = (e0 >> 8) & 255;
+    kd[p][0] = (e0 >> 16) & 15;
+    kd[p][1] = (e0 >> 20) & 15;
+    kd[p][2] = e0 >> 24;
+    jd[p][0] = e1 & 1023;
+    jd[p][1] = (e1 >> 10) & 1023;
+    jd[p][2] = e1 >> 20;
   }
-  // double-layer inputs of this thread's coefficients: W_d at k - e_d
-  int jd[KPT][3];
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int a = kk[q][0], b = kk[q][1], c = kk[q][2];
-    jd[q][0] = a ? mindex(a - 1, b, c) : 0;
-    jd[q][1] = b ? mindex(a, b - 1, c) : 0;
-    jd[q][2] = c ? mindex(a, b, c - 1) : 0;
-  }
-  for (int e = 0; e < sp.y; ++e) {
-    int4 ce;  // (cell, first source, sources)
-    real cx, cy, cz;
+  __syncthreads();
+  // entry e: (cell, first source, sources, shared flag) and its centre
+  auto entry = [&](int e, int4& ce, real& cx, real& cy, real& cz) {
     if (e < kSpanCellsLds) {
-      if (e == 0) __syncthreads();  // staged entries visible
       ce = sce[e];
       cx = scc[e][0];
       cy = scc[e][1];
       cz = scc[e][2];
     } else {
       ce = scells[sp.x + e];
-      const Cell& cl = cells[ce.x];
-      cx = (real)cl.cx;
-      cy = (real)cl.cy;
-      cz = (real)cl.cz;
+      const double4 cc = cent[sp.x + e];
+      cx = (real)cc.x;
+      cy = (real)cc.y;
+      cz = (real)cc.z;
     }
-    const int lo = ce.y - sp.z;
-    real acc[KPT][4];
+    ce.x = __builtin_amdgcn_readfirstlane(ce.x);  // wave-uniform loop bounds
+    ce.y = __builtin_amdgcn_readfirstlane(ce.y);
+    ce.z = __builtin_amdgcn_readfirstlane(ce.z);
+    ce.w = __builtin_amdgcn_readfirstlane(ce.w);
+  };
+  real* my = slice[w];
+  // shared cells (listed first): a quarter of the sources per wave
+  int e = 0;
+  for (; e < sp.y; ++e) {
+    int4 ce;
+    real cx, cy, cz;
+    entry(e, ce, cx, cy, cz);
+    if (!ce.w) break;
+    const int q = (ce.z + kMomWaves - 1) / kMomWaves;
+    const int n = max(0, min(q, ce.z - w * q));
+    real acc[KP][4] = {};
+    mom_accumulate<real, P, KP>(sxyz, sw, my, ce.y - sp.z + w * q, n, cx, cy, cz, ixy, iz, acc);
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0;
-    for (int b0 = 0; b0 < ce.z; b0 += kMomChunk) {
-      const int nj = min(kMomChunk, ce.z - b0);
-      __syncthreads();  // staged sources written; pw free
-      if (tid < nj) {
-        const int t = lo + b0 + tid;
-        const real d[3] = {sxyz[t][0] - cx, sxyz[t][1] - cy, sxyz[t][2] - cz};
+    for (int p = 0; p < KP; ++p) {
+      const int k = lane + 64 * p;
+      if (k < N)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          real v = 1;
-#pragma unroll
-          for (int p = 0; p <= P; ++p) {
-            pw[tid][a][p] = v;
-            v *= d[a];
-          }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < KPT; ++q) {
-        if (!on[q]) continue;
-        const int k1 = kk[q][0], k2 = kk[q][1], k3 = kk[q][2];
-        // four sources per step into independent sums, so that their LDS
-        // reads are in flight together
-        real s4[4][4] = {};
-        auto term = [&](int t, real (&a)[4]) {
-          const real m = pw[t][0][k1] * pw[t][1][k2] * pw[t][2][k3];
-          const real* w = sw[lo + b0 + t];
-          a[0] += w[0] * m;
-          a[1] += w[1] * m;
-          a[2] += w[2] * m;
-          a[3] += w[3] * m;
-        };
-        int t = g;
-        for (; t + 3 * G < nj; t += 4 * G) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) term(t + u * G, s4[u]);
-        }
-        for (; t < nj; t += G) term(t, s4[0]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[q][i] += (s4[0][i] + s4[1][i]) + (s4[2][i] + s4[3][i]);
-      }
+        for (int i = 0; i < 4; ++i) my[i * N + k] = acc[p][i];
     }
+    __syncthreads();  // the four partial sums are in the slices
+    for (int k = tid; k < N; k += kMomThreads) {
+      const int e0 = kMomLanes<P>.e[k][0], e1 = kMomLanes<P>.e[k][1];
+      const int a = (e0 >> 16) & 15, b = (e0 >> 20) & 15, c = e0 >> 24;
+      const int j0 = e1 & 1023, j1 = (e1 >> 10) & 1023, j2 = e1 >> 20;
+      real s = 0, w0 = 0, w1 = 0, w2 = 0;
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-      if (!on[q]) continue;
-      const int k = N <= kMomThreads ? tid - g * N : tid + q * kMomThreads;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) red[g][i][k] = acc[q][i];
-    }
-    __syncthreads();
-    // group g == 0 forms the final moments of its coefficients
-#pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-      if (!on[q] || g != 0) continue;
-      const int k = N <= kMomThreads ? tid : tid + q * kMomThreads;
-      real s = 0, w[3] = {0, 0, 0};
-#pragma unroll
-      for (int gg = 0; gg < G; ++gg) {
-        s += red[gg][0][k];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) w[d] += red[gg][1 + d][jd[q][d]];
+      for (int v = 0; v < kMomWaves; ++v) {
+        s += slice[v][k];
+        w0 += slice[v][N + j0];
+        w1 += slice[v][2 * N + j1];
+        w2 += slice[v][3 * N + j2];
       }
-      const real dl = real(kk[q][0]) * w[0] + real(kk[q][1]) * w[1] + real(kk[q][2]) * w[2];
       mom[(size_t)ce.x * 2 * N + k] = s;
-      mom[(size_t)ce.x * 2 * N + N + k] = dl;
+      mom[(size_t)ce.x * 2 * N + N + k] = real(a) * w0 + real(b) * w1 + real(c) * w2;
     }
-    __syncthreads();  // red is read before the next cell writes it
+    __syncthreads();  // the slices are read before they are refilled
+  }
+  // the other cells, one wave each
+  for (e += w; e < sp.y; e += kMomWaves) {
+    int4 ce;
+    real cx, cy, cz;
+    entry(e, ce, cx, cy, cz);
+    real acc[KP][4] = {};
+    mom_accumulate<real, P, KP>(sxyz, sw, my, ce.y - sp.z, ce.z, cx, cy, cz, ixy, iz, acc);
+#pragma unroll
+    for (int p = 0; p < KP; ++p) {
+      const int k = lane + 64 * p;
+      if (k < N)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) my[d * N + k] = acc[p][1 + d];
+    }
+    wave_sync();  // the dipole moments are in the slice
+#pragma unroll
+    for (int p = 0; p < KP; ++p) {
+      const int k = lane + 64 * p;
+      if (k < N) {
+        const real dl = real(kd[p][0]) * my[jd[p][0]] + real(kd[p][1]) * my[N + jd[p][1]] +
+                        real(kd[p][2]) * my[2 * N + jd[p][2]];
+        mom[(size_t)ce.x * 2 * N + k] = acc[p][0];
+        mom[(size_t)ce.x * 2 * N + N + k] = dl;
+      }
+    }
+    wave_sync();  // the slice is read before the next cell's power tables
   }
 }
 
@@ -247,8 +349,8 @@ struct Binom {
 // order (deterministic).
 template <typename real, int P>
 __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ parts,
-                                                     const int* __restrict__ sroot,
-                                                     const Cell* __restrict__ cells,
+                                                     const int* __restrict__ proot,
+                                                     const double* __restrict__ ph,
                                                      real* __restrict__ mom,
                                                      real* __restrict__ partial) {
   constexpr int N = ncoef(P), N2 = 2 * N, Q = P + 1;
@@ -274,19 +376,19 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ pa
     while (pen >= Q - m) pen -= Q - m++;
     pen_mn[tid] = m | (pen << 8);
   }
-  if (tid < nr) root[tid] = sroot[pt.y + tid];
-  const double ux = cells[u].cx, uy = cells[u].cy, uz = cells[u].cz;
-  __syncthreads();
-  if (tid < 3 * nr) {
+  // the part's span roots and their offsets from the cell's centre (R
+  // slots per part, unused ones zero), read without waiting for pt
+  if (tid < R) root[tid] = proot[(size_t)blockIdx.x * R + tid];
+  if (tid < 3 * R) {
     const int r = tid / 3, d = tid - 3 * r;
-    const Cell& ch = cells[root[r]];
-    const double h = d == 0 ? ch.cx - ux : d == 1 ? ch.cy - uy : ch.cz - uz;
+    const double h = ph[((size_t)blockIdx.x * R + r) * 3 + d];
     real v = 1;
     for (int e = 0; e < Q; ++e) {
       hp[r][d][e] = v;
       v *= (real)h;
     }
   }
+  __syncthreads();
   for (int i = tid; i < nr * N2; i += 256) {
     const int r = i / N2, k = i - r * N2;
     const int s = k < N ? 0 : 1;
@@ -812,10 +914,11 @@ __global__ void k_combine(const DevRowBlock* __restrict__ rows, const DevRowTerm
 // ------------------------------------------------------------ host side
 template <typename real>
 static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<real>* src) {
-  const Cell* cells = wsp<Cell>(pl, pl.o_cells);
   const int4* scells = wsp<int4>(pl, pl.o_mchunks);
+  const double4* cent = wsp<double4>(pl, pl.o_mcent);
   const int4* spans = wsp<int4>(pl, pl.o_mspans);
-  const int* sroot = wsp<int>(pl, pl.o_msroot);
+  const int* proot = wsp<int>(pl, pl.o_mproot);
+  const double* ph = wsp<double>(pl, pl.o_mph);
   const int4* parts = wsp<int4>(pl, pl.o_mparts);
   const int4* sums = wsp<int4>(pl, pl.o_musum);
   real* partial = wsp<real>(pl, pl.o_mpart);
@@ -825,10 +928,10 @@ static int launch_moments(pbtc_plan_t& pl, hipStream_t st, real* mom, const Src<
   case PP:                                                                                    \
     if (nsp > 0)                                                                              \
       hipLaunchKernelGGL((k_mom_span<real, PP>), dim3(nsp), dim3(kMomThreads), 0, st, spans,  \
-                         scells, cells, src, mom);                                            \
+                         scells, cent, src, mom);                                             \
     if (npt > 0)                                                                              \
       hipLaunchKernelGGL((k_mom_up_part<real, PP>), dim3(npt), dim3(256), 0, st, parts,       \
-                         sroot, cells, mom, partial);                                         \
+                         proot, ph, mom, partial);                                            \
     if (nsum > 0)                                                                             \
       hipLaunchKernelGGL((k_mom_up_sum<real, PP>), dim3(nsum), dim3(64 * sum_waves<real, PP>()), \
                          0, st, sums, partial, mom);                                          \

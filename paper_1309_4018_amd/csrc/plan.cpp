@@ -625,8 +625,10 @@ void compute_layout(pbtc_plan_t& pl) {
   pl.o_mom64 = L.add(8 * 2 * nP * pl.cap_cells);
   pl.o_mom32 = L.add(4 * 2 * nP * pl.cap_cells);
   pl.o_mchunks = L.add(16 * pl.cap_cells);
+  pl.o_mcent = L.add(32 * pl.cap_cells);
   pl.o_mspans = L.add(16 * pl.cap_cells);
-  pl.o_msroot = L.add(4 * pl.cap_cells);
+  pl.o_mproot = L.add(4 * mom_up_batch(pl.P) * pl.cap_mparts);
+  pl.o_mph = L.add(24 * mom_up_batch(pl.P) * pl.cap_mparts);
   pl.o_musum = L.add(16 * pl.cap_cells);
   pl.o_mparts = L.add(16 * pl.cap_mparts);
   pl.o_mpart = L.add(8 * 2 * nP * pl.cap_mparts);

@@ -19,6 +19,7 @@
 //               lysozyme parameter table of sec. 3
 //   rhs         Coulomb right-hand side (Eq. matel, Q)
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <functional>
@@ -1269,11 +1270,10 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     pl.n_uptr = (int64_t)uptr.size();
 
     // moment pass: span roots (at most kSpanSources sources, parent larger)
-    // in depth-first order, each with its subtree's cells in breadth-first
-    // order; the span roots below an upper (larger) cell are then a
-    // contiguous run of the span list, shifted into the cell in parts of at
-    // most mom_up_batch(P) span roots (a cell of several parts also gets a
-    // sum entry).
+    // in depth-first order, each with its subtree's cells; the span roots
+    // below an upper (larger) cell are then a contiguous run of the span
+    // list, shifted into the cell in parts of at most mom_up_batch(P) span
+    // roots (a cell of several parts also gets a sum entry).
     std::vector<int4> mch, mspan, mparts, musum;
     std::vector<int> sroot;
     bool too_big = false;
@@ -1287,7 +1287,35 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
           for (int k = 0; k < cc.nchild; ++k)
             mch.push_back(make_int4(cc.child + k, hc[cc.child + k].begin, hc[cc.child + k].count, 0));
         }
-        mspan.push_back(make_int4((int)first, (int)(mch.size() - first), hc[c].begin, hc[c].count));
+        // the span's cells in breadth-first runs (jobs, one work-group each)
+        // of at most kMomJob sources summed over the run's cells, so that no
+        // work-group has much more work than the others; within a job the
+        // shared cells come first, then the others largest first (dealt
+        // round robin to the waves)
+        auto close_job = [&](size_t j0, size_t j1) {
+          const int n = (int)(j1 - j0);
+          int lo = INT_MAX, hi = 0;
+          for (size_t i = j0; i < j1; ++i) {
+            mch[i].w = mch[i].z > kMomShared || (n == 1 && mch[i].z > kMomSharedLone) ? 1 : 0;
+            lo = std::min(lo, mch[i].y);
+            hi = std::max(hi, mch[i].y + mch[i].z);
+          }
+          std::stable_sort(mch.begin() + j0, mch.begin() + j1, [](const int4& a, const int4& b) {
+            return a.w != b.w ? a.w > b.w : (a.w == 0 && a.z > b.z);
+          });
+          mspan.push_back(make_int4((int)j0, n, lo, hi - lo));
+        };
+        size_t j0 = first;
+        int acc = 0;
+        for (size_t i = first; i < mch.size(); ++i) {
+          if (i > j0 && acc + mch[i].z > kMomJob) {
+            close_job(j0, i);
+            j0 = i;
+            acc = 0;
+          }
+          acc += mch[i].z;
+        }
+        close_job(j0, mch.size());
         sroot.push_back(c);
         return;
       }
@@ -1295,9 +1323,9 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
         too_big = true;
         return;
       }
-      const int s0 = (int)mspan.size();
+      const int s0 = (int)sroot.size();
       for (int k = 0; k < hc[c].nchild; ++k) visit(hc[c].child + k);
-      const int s1 = (int)mspan.size();
+      const int s1 = (int)sroot.size();
       const int np = (s1 - s0 + up_batch - 1) / up_batch;
       if (np > 1) musum.push_back(make_int4(c, (int)mparts.size(), np, 0));
       for (int q = s0; q < s1; q += up_batch)
@@ -1327,20 +1355,46 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       PBTC_HIP(hipStreamSynchronize(st));
       return PBTC_EWORKSPACE;
     }
+    // the centre of every job entry's cell; per part its span roots and
+    // their offsets from the part's cell centre (up_batch slots, unused
+    // ones zero), so that the moment kernels read no cell records
+    std::vector<double4> mcent(mch.size());
+    for (size_t i = 0; i < mch.size(); ++i) {
+      const Cell& cc = hc[mch[i].x];
+      mcent[i] = make_double4(cc.cx, cc.cy, cc.cz, 0.0);
+    }
+    std::vector<int> mproot((size_t)up_batch * mparts.size(), 0);
+    std::vector<double> mph((size_t)3 * up_batch * mparts.size(), 0.0);
+    for (size_t p = 0; p < mparts.size(); ++p) {
+      const Cell& cu = hc[mparts[p].x];
+      for (int q = mparts[p].y; q < mparts[p].z; ++q) {
+        const size_t slot = p * up_batch + (q - mparts[p].y);
+        const Cell& cr = hc[sroot[q]];
+        mproot[slot] = sroot[q];
+        mph[3 * slot] = cr.cx - cu.cx;
+        mph[3 * slot + 1] = cr.cy - cu.cy;
+        mph[3 * slot + 2] = cr.cz - cu.cz;
+      }
+    }
     rc = phase_done_host(4);
     if (rc) return rc;
-    if (!mch.empty())
+    if (!mch.empty()) {
       PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mchunks), mch.data(), 16 * mch.size(),
                               hipMemcpyHostToDevice, st));
-    if (!mspan.empty()) {
-      PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mspans), mspan.data(), 16 * mspan.size(),
-                              hipMemcpyHostToDevice, st));
-      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_msroot), sroot.data(), 4 * sroot.size(),
+      PBTC_HIP(hipMemcpyAsync(wsp<double4>(pl, pl.o_mcent), mcent.data(), 32 * mcent.size(),
                               hipMemcpyHostToDevice, st));
     }
-    if (!mparts.empty())
+    if (!mspan.empty())
+      PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mspans), mspan.data(), 16 * mspan.size(),
+                              hipMemcpyHostToDevice, st));
+    if (!mparts.empty()) {
       PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_mparts), mparts.data(), 16 * mparts.size(),
                               hipMemcpyHostToDevice, st));
+      PBTC_HIP(hipMemcpyAsync(wsp<int>(pl, pl.o_mproot), mproot.data(), 4 * mproot.size(),
+                              hipMemcpyHostToDevice, st));
+      PBTC_HIP(hipMemcpyAsync(wsp<double>(pl, pl.o_mph), mph.data(), 8 * mph.size(),
+                              hipMemcpyHostToDevice, st));
+    }
     if (!musum.empty())
       PBTC_HIP(hipMemcpyAsync(wsp<int4>(pl, pl.o_musum), musum.data(), 16 * musum.size(),
                               hipMemcpyHostToDevice, st));

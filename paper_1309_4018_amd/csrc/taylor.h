@@ -36,14 +36,17 @@ __host__ __device__ constexpr int mindex(int a, int b, int c) {
          (b + c) * (b + c + 1) / 2 + c;
 }
 
-// Inverse of mindex by arithmetic (no table): total degree n from the
-// tetrahedral numbers, then b + c from the triangular numbers.
+// Inverse of mindex for k < ncoef(kMaxP), by arithmetic and without
+// branches: the total degree n counts the tetrahedral numbers <= k, then
+// b + c the triangular numbers <= k - T(n).
 __host__ __device__ inline void mindex_inv(int k, int& a, int& b, int& c) {
   int n = 0;
-  while ((n + 1) * (n + 2) * (n + 3) / 6 <= k) ++n;
+#pragma unroll
+  for (int i = 1; i <= kMaxP; ++i) n += k >= i * (i + 1) * (i + 2) / 6 ? 1 : 0;
   const int r = k - n * (n + 1) * (n + 2) / 6;
   int m = 0;
-  while ((m + 1) * (m + 2) / 2 <= r) ++m;
+#pragma unroll
+  for (int i = 1; i <= kMaxP; ++i) m += r >= i * (i + 1) / 2 ? 1 : 0;
   c = r - m * (m + 1) / 2;
   b = m - c;
   a = n - m;
