@@ -66,9 +66,8 @@ __global__ void k_prep(int64_t ngp, const double* __restrict__ gx, const double*
 // (or a tree root that small).  The cells of a span root's subtree are
 // formed directly from the sources, in jobs: breadth-first runs of the
 // span's cells of at most kMomJob sources in all, one work-group each, which
-// stages the sources of its cells in LDS once (the jobs of one span are
-// neighbours in the launch, so a second read of the span's sources is
-// served by L2).
+// stages the sources of its cells in LDS once.  Neighbouring small jobs of
+// consecutive spans (adjacent sources) share a work-group.
 // The larger (upper) cells then add the moments of the span roots below
 // them, shifted to their own centres by the multi-index binomial theorem
 // (sec. 2.3: moments shifted towards the root and added),
@@ -200,8 +199,10 @@ __global__ __launch_bounds__(kMomThreads) void k_mom_span(const int4* __restrict
   __shared__ real slice[kMomWaves][SLICE];
   __shared__ int4 sce[kSpanCellsLds];
   __shared__ real scc[kSpanCellsLds][3];
-  // job: (first entry of its cells in scells, number of cells, first source, sources)
-  const int4 sp = spans[xcd_block(blockIdx.x, gridDim.x)];
+  // job: (first entry of its cells in scells, number of cells, first
+  // source, sources); jobs are in launch order, largest first, dealt round
+  // robin to the XCDs
+  const int4 sp = spans[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid < min(sp.y, kSpanCellsLds)) {

@@ -1275,6 +1275,7 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     // list, shifted into the cell in parts of at most mom_up_batch(P) span
     // roots (a cell of several parts also gets a sum entry).
     std::vector<int4> mch, mspan, mparts, musum;
+    std::vector<int4> jobs;  // (first entry, end entry, sources, -)
     std::vector<int> sroot;
     bool too_big = false;
     const int up_batch = mom_up_batch(pl.P);
@@ -1287,35 +1288,20 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
           for (int k = 0; k < cc.nchild; ++k)
             mch.push_back(make_int4(cc.child + k, hc[cc.child + k].begin, hc[cc.child + k].count, 0));
         }
-        // the span's cells in breadth-first runs (jobs, one work-group each)
-        // of at most kMomJob sources summed over the run's cells, so that no
-        // work-group has much more work than the others; within a job the
-        // shared cells come first, then the others largest first (dealt
-        // round robin to the waves)
-        auto close_job = [&](size_t j0, size_t j1) {
-          const int n = (int)(j1 - j0);
-          int lo = INT_MAX, hi = 0;
-          for (size_t i = j0; i < j1; ++i) {
-            mch[i].w = mch[i].z > kMomShared || (n == 1 && mch[i].z > kMomSharedLone) ? 1 : 0;
-            lo = std::min(lo, mch[i].y);
-            hi = std::max(hi, mch[i].y + mch[i].z);
-          }
-          std::stable_sort(mch.begin() + j0, mch.begin() + j1, [](const int4& a, const int4& b) {
-            return a.w != b.w ? a.w > b.w : (a.w == 0 && a.z > b.z);
-          });
-          mspan.push_back(make_int4((int)j0, n, lo, hi - lo));
-        };
+        // the span's cells in breadth-first runs (jobs) of at most kMomJob
+        // sources summed over the run's cells, so that no work-group has
+        // much more work than the others
         size_t j0 = first;
         int acc = 0;
         for (size_t i = first; i < mch.size(); ++i) {
           if (i > j0 && acc + mch[i].z > kMomJob) {
-            close_job(j0, i);
+            jobs.push_back(make_int4((int)j0, (int)i, acc, 0));
             j0 = i;
             acc = 0;
           }
           acc += mch[i].z;
         }
-        close_job(j0, mch.size());
+        jobs.push_back(make_int4((int)j0, (int)mch.size(), acc, 0));
         sroot.push_back(c);
         return;
       }
@@ -1336,6 +1322,58 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       pl.err = "a tree leaf holds more than 256 Gauss points (coincident points)";
       PBTC_HIP(hipStreamSynchronize(st));
       return PBTC_EMESH;
+    }
+    // neighbouring small jobs (of consecutive spans, whose sources are
+    // adjacent) share a work-group up to kMomJob sources; within a job the
+    // shared cells come first, then the others largest first (dealt round
+    // robin to the waves)
+    auto job_range = [&](const int4& j, int& lo, int& hi) {
+      lo = INT_MAX;
+      hi = 0;
+      for (int i = j.x; i < j.y; ++i) {
+        lo = std::min(lo, mch[i].y);
+        hi = std::max(hi, mch[i].y + mch[i].z);
+      }
+    };
+    for (size_t a = 0; a < jobs.size();) {
+      int lo, hi;
+      job_range(jobs[a], lo, hi);
+      const int j0 = jobs[a].x;
+      int j1 = jobs[a].y, acc = jobs[a].z;
+      size_t b = a + 1;
+      for (; b < jobs.size() && acc + jobs[b].z <= kMomJob; ++b) {
+        int blo, bhi;
+        job_range(jobs[b], blo, bhi);
+        if (blo != hi) break;
+        j1 = jobs[b].y;
+        acc += jobs[b].z;
+        hi = bhi;
+      }
+      a = b;
+      const int n = j1 - j0;
+      for (int i = j0; i < j1; ++i)
+        mch[i].w = mch[i].z > kMomShared || (n == 1 && mch[i].z > kMomSharedLone) ? 1 : 0;
+      std::stable_sort(mch.begin() + j0, mch.begin() + j1, [](const int4& x, const int4& y) {
+        return x.w != y.w ? x.w > y.w : (x.w == 0 && x.z > y.z);
+      });
+      mspan.push_back(make_int4(j0, n, lo, hi - lo));
+    }
+    // jobs launch largest first (work ~ sources summed over the job's
+    // cells, plus a fixed cost per cell), so that the last work-groups to
+    // start are short ones
+    {
+      std::vector<long> wk(mspan.size());
+      for (size_t j = 0; j < mspan.size(); ++j) {
+        long w = 0;
+        for (int i = mspan[j].x; i < mspan[j].x + mspan[j].y; ++i) w += mch[i].z + 16;
+        wk[j] = w;
+      }
+      std::vector<int> ord(mspan.size());
+      for (size_t j = 0; j < ord.size(); ++j) ord[j] = (int)j;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return wk[a] > wk[b]; });
+      std::vector<int4> sorted(mspan.size());
+      for (size_t j = 0; j < ord.size(); ++j) sorted[j] = mspan[ord[j]];
+      mspan.swap(sorted);
     }
     pl.n_mchunks = (int64_t)mch.size();
     pl.n_mspans = (int64_t)mspan.size();
