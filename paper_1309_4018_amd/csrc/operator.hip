@@ -200,9 +200,8 @@ __global__ __launch_bounds__(kMomThreads) void k_mom_span(const int4* __restrict
   __shared__ int4 sce[kSpanCellsLds];
   __shared__ real scc[kSpanCellsLds][3];
   // job: (first entry of its cells in scells, number of cells, first
-  // source, sources); jobs are in launch order, largest first, dealt round
-  // robin to the XCDs
-  const int4 sp = spans[blockIdx.x];
+  // source, sources); XCD x runs the x-th contiguous run of the job list
+  const int4 sp = spans[xcd_block(blockIdx.x, gridDim.x)];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid < min(sp.y, kSpanCellsLds)) {
@@ -347,7 +346,9 @@ struct Binom {
 // registers, with the binomials as constants.  Entries of total degree > P
 // are never read or written.  A cell of one part stores its moments; the
 // parts of a larger cell store partial sums that k_mom_up_sum adds in part
-// order (deterministic).
+// order (deterministic).  Parts are listed by their first span root and
+// dealt to the XCDs in contiguous runs, so a span root's moments are read
+// by one XCD at every level.
 template <typename real, int P>
 __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ parts,
                                                      const int* __restrict__ proot,
@@ -364,7 +365,8 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ pa
   __shared__ int abc[N];       // a | b << 8 | c << 16 of coefficient k
   __shared__ int pen_mn[NPEN];  // m | n << 8 of pencil p
   __shared__ int root[R];
-  const int4 pt = parts[blockIdx.x];  // (upper cell, first span, end span, sole part)
+  const int part = xcd_block(blockIdx.x, gridDim.x);
+  const int4 pt = parts[part];  // (upper cell, first span, end span, partial slot or -1)
   const int u = pt.x, nr = pt.z - pt.y;
   const int tid = threadIdx.x;
   for (int k = tid; k < N; k += 256) {
@@ -379,10 +381,10 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ pa
   }
   // the part's span roots and their offsets from the cell's centre (R
   // slots per part, unused ones zero), read without waiting for pt
-  if (tid < R) root[tid] = proot[(size_t)blockIdx.x * R + tid];
+  if (tid < R) root[tid] = proot[(size_t)part * R + tid];
   if (tid < 3 * R) {
     const int r = tid / 3, d = tid - 3 * r;
-    const double h = ph[((size_t)blockIdx.x * R + r) * 3 + d];
+    const double h = ph[((size_t)part * R + r) * 3 + d];
     real v = 1;
     for (int e = 0; e < Q; ++e) {
       hp[r][d][e] = v;
@@ -437,7 +439,7 @@ __global__ __launch_bounds__(256) void k_mom_up_part(const int4* __restrict__ pa
     }
     __syncthreads();
   }
-  real* dst = pt.w ? mom + (size_t)u * N2 : partial + (size_t)blockIdx.x * N2;
+  real* dst = pt.w < 0 ? mom + (size_t)u * N2 : partial + (size_t)pt.w * N2;
 #pragma unroll
   for (int o = 0; o < OPT; ++o) {
     const int k = tid + 256 * o;

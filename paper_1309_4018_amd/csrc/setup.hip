@@ -1315,7 +1315,7 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       const int np = (s1 - s0 + up_batch - 1) / up_batch;
       if (np > 1) musum.push_back(make_int4(c, (int)mparts.size(), np, 0));
       for (int q = s0; q < s1; q += up_batch)
-        mparts.push_back(make_int4(c, q, std::min(q + up_batch, s1), np == 1 ? 1 : 0));
+        mparts.push_back(make_int4(c, q, std::min(q + up_batch, s1), np == 1 ? -1 : (int)mparts.size()));
     };
     for (int r = 0; r < pl.nsurf; ++r) visit(r);
     if (too_big) {
@@ -1358,21 +1358,29 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       });
       mspan.push_back(make_int4(j0, n, lo, hi - lo));
     }
-    // jobs launch largest first (work ~ sources summed over the job's
-    // cells, plus a fixed cost per cell), so that the last work-groups to
-    // start are short ones
+    // launch order: the k_mom_span work-groups of one XCD take a contiguous
+    // run of the depth-first job list (so the jobs of one span share that
+    // XCD's L2), and each XCD's run goes largest first (work ~ sources summed
+    // over the job's cells, plus a fixed cost per cell), so that the last
+    // work-groups to start are short ones
     {
-      std::vector<long> wk(mspan.size());
-      for (size_t j = 0; j < mspan.size(); ++j) {
+      const size_t nj = mspan.size(), q = nj / kXcds, r = nj % kXcds;
+      std::vector<long> wk(nj);
+      for (size_t j = 0; j < nj; ++j) {
         long w = 0;
         for (int i = mspan[j].x; i < mspan[j].x + mspan[j].y; ++i) w += mch[i].z + 16;
         wk[j] = w;
       }
-      std::vector<int> ord(mspan.size());
-      for (size_t j = 0; j < ord.size(); ++j) ord[j] = (int)j;
-      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return wk[a] > wk[b]; });
-      std::vector<int4> sorted(mspan.size());
-      for (size_t j = 0; j < ord.size(); ++j) sorted[j] = mspan[ord[j]];
+      std::vector<int4> sorted(mspan);
+      size_t b0 = 0;
+      for (size_t x = 0; x < (size_t)kXcds; ++x) {
+        const size_t b1 = b0 + q + (x < r ? 1 : 0);
+        std::vector<size_t> ord;
+        for (size_t j = b0; j < b1; ++j) ord.push_back(j);
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return wk[a] > wk[b]; });
+        for (size_t j = b0; j < b1; ++j) sorted[j] = mspan[ord[j - b0]];
+        b0 = b1;
+      }
       mspan.swap(sorted);
     }
     pl.n_mchunks = (int64_t)mch.size();
@@ -1401,6 +1409,13 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       const Cell& cc = hc[mch[i].x];
       mcent[i] = make_double4(cc.cx, cc.cy, cc.cz, 0.0);
     }
+    // parts in the order of their first span root, so that XCD x (which
+    // runs the x-th contiguous run of the part list) reads the moments of
+    // the same span roots at every level from its own L2; each part keeps
+    // its partial-sum slot (its position in the cell-by-cell order) in .w,
+    // or -1 when it is its cell's only part
+    std::stable_sort(mparts.begin(), mparts.end(),
+                     [](const int4& a, const int4& b) { return a.y < b.y; });
     std::vector<int> mproot((size_t)up_batch * mparts.size(), 0);
     std::vector<double> mph((size_t)3 * up_batch * mparts.size(), 0.0);
     for (size_t p = 0; p < mparts.size(); ++p) {
