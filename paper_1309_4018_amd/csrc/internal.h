@@ -30,6 +30,7 @@ constexpr int kProfM2PPair = 6;
 constexpr int kGroup = 16;
 constexpr int kQuarters = 64 / kGroup;  // lanes per target
 constexpr int kNearRun = 16;            // targets per near-field search wavefront
+constexpr double kNearSplit = 4.0;       // a near-field run is walked in parts when its sphere exceeds this many reaches
 // Gauss points per target group of the transposed operator (one lane each:
 // with the Gauss points four to a panel, smaller groups cut few pairs)
 constexpr int kAGroup = 64;

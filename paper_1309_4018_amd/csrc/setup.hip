@@ -408,11 +408,11 @@ __device__ __forceinline__ void target_point(const NearArgs& a, const DevBlock& 
 // Near-field columns of every row: the panels j with |x - centre_j| <
 // thres * L_j, plus the target's own panel.  One wavefront per run of
 // kNearRun consecutive targets of a block (the items of kNearRun / kGroup
-// consecutive groups; the wave of the run's first item does the work), a
-// lane per target: the wave walks the leaves that may hold such a panel for
+// consecutive groups; the wave of the run's first item does the work), four
+// lanes per target: the wave walks the leaves that may hold such a panel for
 // some target of the run (inside the run's bounding sphere plus the reach)
-// and tests every panel of each leaf (its first Gauss point stands for it)
-// against the run's targets at once.  Small runs keep the sphere tight and
+// and tests the panels of each leaf (a panel's first Gauss point stands for
+// it), four at a time, against the run's targets.  Small runs keep the sphere tight and
 // give many short walks.
 // mode 0: count per row; mode 1: fill columns at the row offsets in ptr;
 // mode 2: count per row and keep the first `slot_cap` columns of every row in
@@ -428,83 +428,124 @@ __global__ __launch_bounds__(64 * kTravWaves) void k_near_rows(
   const DevBlock& b = a.blocks[item_block[it]];
   const int64_t g = it - b.item_off;
   if (g % (kNearRun / kGroup) != 0) return;
+  static_assert(kNearRun == 16, "four lanes per target");
   const int nt = (int)min((long long)kNearRun, b.ntgt - g * kGroup);
-  const bool active = lane < nt;
+  // lane = target tl + 16 * quarter: the four lanes of a target test four
+  // panels at a time
+  const int tl = lane & 15, qt = lane >> 4;
+  const bool active = tl < nt;
   int64_t i = 0;
   double x = 0, y = 0, z = 0;
   int64_t self_pan = -1;
   if (active) {
-    i = tidx[b.tgt_off + g * kGroup + lane] - b.tgt_off;
+    i = tidx[b.tgt_off + g * kGroup + tl] - b.tgt_off;
     target_point(a, b, i, x, y, z, self_pan);
   }
-  // bounding sphere of the run: box centre, largest distance to it
-  double lo[3] = {active ? x : 1e300, active ? y : 1e300, active ? z : 1e300};
-  double hi[3] = {active ? x : -1e300, active ? y : -1e300, active ? z : -1e300};
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = fmin(lo[d], __shfl_xor(lo[d], m));
-      hi[d] = fmax(hi[d], __shfl_xor(hi[d], m));
-    }
-  const double gcx = 0.5 * (lo[0] + hi[0]), gcy = 0.5 * (lo[1] + hi[1]),
-               gcz = 0.5 * (lo[2] + hi[2]);
-  double gr = active ? sqrt((x - gcx) * (x - gcx) + (y - gcy) * (y - gcy) + (z - gcz) * (z - gcz))
-                     : 0.0;
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) gr = fmax(gr, __shfl_xor(gr, m));
-  gr = gr * (1.0 + 1e-12) + 1e-12;
   const long long row = b.nf_row + i;
   long long n = 0;
   const long long out0 = (mode == 1 && active) ? ptr[row] : 0;
   const long long gp0 = a.gp_first[b.s];
   const double reach = a.reach[b.s];
+  // bounding sphere (box centre, largest distance to it) of the targets of
+  // the 16-bit mask sub
+  double gcx, gcy, gcz, gr;
+  auto sphere = [&](unsigned sub) {
+    const bool in = active && ((sub >> tl) & 1u);
+    double lo[3] = {in ? x : 1e300, in ? y : 1e300, in ? z : 1e300};
+    double hi[3] = {in ? x : -1e300, in ? y : -1e300, in ? z : -1e300};
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = fmin(lo[d], __shfl_xor(lo[d], m));
+        hi[d] = fmax(hi[d], __shfl_xor(hi[d], m));
+      }
+    gcx = 0.5 * (lo[0] + hi[0]);
+    gcy = 0.5 * (lo[1] + hi[1]);
+    gcz = 0.5 * (lo[2] + hi[2]);
+    gr = in ? sqrt((x - gcx) * (x - gcx) + (y - gcy) * (y - gcy) + (z - gcz) * (z - gcz)) : 0.0;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) gr = fmax(gr, __shfl_xor(gr, m));
+    gr = gr * (1.0 + 1e-12) + 1e-12;
+  };
   // a leaf's sources pass through LDS 64 at a time: each lane loads one, the
   // panel's first Gauss point stands for the panel (one test per panel)
   __shared__ double lx[kTravWaves][64], ly[kTravWaves][64], lz[kTravWaves][64];
   __shared__ double ll[kTravWaves][64];
   __shared__ int lp[kTravWaves][64];
-  wave_leaves_within(a.cells, b.root, gcx, gcy, gcz, gr, reach, stk[w], overflow,
-                     [&](int leaf, double lcx, double lcy, double lcz, double lrb) {
-    // skip the leaf unless some lane's own target is within reach of it
-    const double qx = x - lcx, qy = y - lcy, qz = z - lcz;
-    if (__ballot(active && sqrt(qx * qx + qy * qy + qz * qz) - lrb <= reach) == 0) return;
-    const int beg = __builtin_amdgcn_readfirstlane(a.cells[leaf].begin);
-    const int end = beg + __builtin_amdgcn_readfirstlane(a.cells[leaf].count);
-    for (int c0 = beg; c0 < end; c0 += 64) {
-      const int j = c0 + lane;
-      bool rep = false;
-      if (j < end) {
-        rep = (a.gidx[j] - gp0) % a.K == 0;
-        if (rep) {
-          const int p = a.gpid[j];
-          const double lim = a.thres * a.len[p];
-          lx[w][lane] = a.cx[p];
-          ly[w][lane] = a.cy[p];
-          lz[w][lane] = a.cz[p];
-          ll[w][lane] = lim * lim;
-          lp[w][lane] = p;
-        }
-      }
-      wave_sync();
-      uint64_t m = __ballot(rep);
-      while (m) {
-        const int t = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        const int p = lp[w][t];
-        const double ex = x - lx[w][t], ey = y - ly[w][t], ez = z - lz[w][t];
-        const bool take = active && (p == self_pan || ex * ex + ey * ey + ez * ez < ll[w][t]);
-        if (take) {
-          if (mode == 1 && out0 + n < cap) col[out0 + n] = p;
-          if (mode == 2 && n < slot_cap) slots[row * slot_cap + n] = p;
-          ++n;
-        }
-      }
-      wave_sync();  // the slots are rewritten by the next batch
+  // One walk for the whole run when its sphere is tight; a run whose
+  // targets lie far apart (its sphere much larger than the reach) is walked
+  // in aligned quarters, and a quarter that is still spread out target by
+  // target, so that no walk tests most of the tree.  Every target belongs to
+  // one walk, whose order fixes its columns' order.
+  unsigned pend = (1u << nt) - 1u;
+  while (pend) {
+    const int t0 = __ffs(pend) - 1;
+    unsigned sub = pend;
+    for (int size = 16;; size >>= 2) {
+      sub = pend & (size == 16 ? 0xffffu : ((1u << size) - 1u) << (t0 / size * size));
+      sphere(sub);
+      if (size == 1 || gr <= kNearSplit * reach) break;
     }
-  });
-  if (mode != 1 && active) ptr[row] = n;
-  if (mode == 2 && active && n > slot_cap) overflow[1] = 1;
+    pend &= ~sub;
+    const bool act = active && ((sub >> tl) & 1u);
+    wave_leaves_within(a.cells, b.root, gcx, gcy, gcz, gr, reach, stk[w], overflow,
+                       [&](int leaf, double lcx, double lcy, double lcz, double lrb) {
+      // skip the leaf unless some lane's own target is within reach of it
+      const double qx = x - lcx, qy = y - lcy, qz = z - lcz;
+      if (__ballot(act && sqrt(qx * qx + qy * qy + qz * qz) - lrb <= reach) == 0) return;
+      const int beg = __builtin_amdgcn_readfirstlane(a.cells[leaf].begin);
+      const int end = beg + __builtin_amdgcn_readfirstlane(a.cells[leaf].count);
+      for (int c0 = beg; c0 < end; c0 += 64) {
+        const int j = c0 + lane;
+        bool rep = false;
+        if (j < end) {
+          rep = (a.gidx[j] - gp0) % a.K == 0;
+          if (rep) {
+            const int p = a.gpid[j];
+            const double lim = a.thres * a.len[p];
+            lx[w][lane] = a.cx[p];
+            ly[w][lane] = a.cy[p];
+            lz[w][lane] = a.cz[p];
+            ll[w][lane] = lim * lim;
+            lp[w][lane] = p;
+          }
+        }
+        wave_sync();
+        uint64_t m = __ballot(rep);
+        const uint64_t mine = 0x0001000100010001ull << tl;  // the lanes of this lane's target
+        while (m) {
+          // the next four panels in order, one per quarter
+          int tq[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            tq[r] = m ? __ffsll((unsigned long long)m) - 1 : -1;
+            m &= m - 1;
+          }
+          const int t = qt == 0 ? tq[0] : qt == 1 ? tq[1] : qt == 2 ? tq[2] : tq[3];
+          bool take = false;
+          int p = 0;
+          if (t >= 0) {
+            p = lp[w][t];
+            const double ex = x - lx[w][t], ey = y - ly[w][t], ez = z - lz[w][t];
+            take = act && (p == self_pan || ex * ex + ey * ey + ez * ez < ll[w][t]);
+          }
+          // a target's columns stay in panel order: this lane's take follows
+          // those of its target's lower quarters
+          const uint64_t tk = __ballot(take) & mine;
+          if (take) {
+            const long long at = n + __popcll(tk & ((1ull << lane) - 1));
+            if (mode == 1 && out0 + at < cap) col[out0 + at] = p;
+            if (mode == 2 && at < slot_cap) slots[row * slot_cap + at] = p;
+          }
+          n += __popcll(tk);
+        }
+        wave_sync();  // the slots are rewritten by the next batch
+      }
+    });
+  }
+  if (mode != 1 && active && qt == 0) ptr[row] = n;
+  if (mode == 2 && active && qt == 0 && n > slot_cap) overflow[1] = 1;
 }
 
 // Row slots to CSR: one thread per entry (its row by bisection over ptr).
