@@ -1224,15 +1224,27 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     // sources of every near-list entry and of every item's near list
     std::vector<int> ncnt(std::max<int64_t>(pl.n_near, 1));
     std::vector<double> isrc(pl.nitems);
-    for (int64_t it = 0; it < pl.nitems; ++it) {
-      long long sum = 0;
-      for (long long e = np_[it]; e < np_[it + 1]; ++e) sum += (ncnt[e] = hc[nl[e]].count);
-      isrc[it] = (double)sum;
+    {
+      std::vector<int> ccount(std::max<int64_t>(pl.n_cells, 1));  // compact: fewer cache misses
+      for (int64_t c = 0; c < pl.n_cells; ++c) ccount[c] = hc[c].count;
+      for (int64_t it = 0; it < pl.nitems; ++it) {
+        long long sum = 0;
+        for (long long e = np_[it]; e < np_[it + 1]; ++e) sum += (ncnt[e] = ccount[nl[e]]);
+        isrc[it] = (double)sum;
+      }
     }
     double pairs = 0.0, m2p = 0.0;
     for (int ph = 0; ph < 2; ++ph)
       for (int ks = 0; ks < KS_COUNT; ++ks) pl.launch_flop_p2p[ph][ks] = pl.launch_flop_m2p[ph][ks] = 0.0;
     const bool tree = pl.prm.op == PBTC_OP_TREECODE;
+    double flop_pair[KS_COUNT], flop_eval[KS_COUNT];
+    for (int ks = 0; ks < KS_COUNT; ++ks) {
+      flop_pair[ks] = p2p_flop_per_pair(ks);
+      flop_eval[ks] = tree ? m2p_flop_per_eval(pl.P, ks) : 0.0;
+    }
+    // per item: its sources and far cells, or -1 for the reaction rows (no
+    // work units of their own)
+    std::vector<double> usrc(pl.nitems), ucell(pl.nitems);
     for (int64_t it = 0; it < pl.nitems; ++it) {
       const Block& bl = pl.blocks[pl.item_block[it]];
       const TargetSet& ts = pl.tsets[bl.t];
@@ -1241,8 +1253,10 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       const double src = isrc[it];
       const double ncell = (double)(fp_[it + 1] - fp_[it]);
       const int ph = bl.reaction ? 1 : 0;
-      pl.launch_flop_p2p[ph][bl.ks] += ntg * src * p2p_flop_per_pair(bl.ks);
-      if (tree) pl.launch_flop_m2p[ph][bl.ks] += ntg * ncell * m2p_flop_per_eval(pl.P, bl.ks);
+      pl.launch_flop_p2p[ph][bl.ks] += ntg * src * flop_pair[bl.ks];
+      pl.launch_flop_m2p[ph][bl.ks] += ntg * ncell * flop_eval[bl.ks];
+      usrc[it] = bl.reaction ? -1.0 : src;
+      ucell[it] = bl.reaction ? -1.0 : ncell;
       if (bl.reaction) continue;
       pairs += ntg * src * bl.nk;
       m2p += ntg * ncell * bl.nk;
@@ -1263,14 +1277,13 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     auto p2p_units = [&](int t) {
       double u = 0.0;
       for (int64_t it = 0; it < pl.nitems; ++it)
-        if (!pl.blocks[pl.item_block[it]].reaction) u += std::ceil(isrc[it] / t);
+        if (usrc[it] >= 0.0) u += std::ceil(usrc[it] / t);
       return u;
     };
     auto m2p_units = [&](int t) {
       double u = 0.0;
       for (int64_t it = 0; it < pl.nitems; ++it)
-        if (!pl.blocks[pl.item_block[it]].reaction)
-          u += std::ceil((double)(fp_[it + 1] - fp_[it]) / t);
+        if (ucell[it] >= 0.0) u += std::ceil(ucell[it] / t);
       return u;
     };
     const int kUnitSources = auto_tile(pl.prm.unit_sources, {2048, 1024, 512}, resident, p2p_units);
@@ -1279,6 +1292,8 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     pl.tile_cells = kUnitCells;
     std::vector<int4> units;
     std::vector<int> uptr;
+    units.reserve(std::max<int64_t>(pl.cap_units, 1));
+    uptr.reserve(2 * pl.nitems + 64);
     for (int ph = 0; ph < 2; ++ph)
       for (int ks = 0; ks < KS_COUNT; ++ks)
         for (int kind = 0; kind < 2; ++kind) {
@@ -1394,9 +1409,17 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
       const int n = j1 - j0;
       for (int i = j0; i < j1; ++i)
         mch[i].w = mch[i].z > kMomShared || (n == 1 && mch[i].z > kMomSharedLone) ? 1 : 0;
-      std::stable_sort(mch.begin() + j0, mch.begin() + j1, [](const int4& x, const int4& y) {
-        return x.w != y.w ? x.w > y.w : (x.w == 0 && x.z > y.z);
-      });
+      // stable insertion sort (a job holds few cells)
+      for (int i = j0 + 1; i < j1; ++i) {
+        const int4 v = mch[i];
+        int k = i;
+        for (; k > j0; --k) {
+          const int4& u = mch[k - 1];
+          if (!(v.w != u.w ? v.w > u.w : (v.w == 0 && v.z > u.z))) break;
+          mch[k] = u;
+        }
+        mch[k] = v;
+      }
       mspan.push_back(make_int4(j0, n, lo, hi - lo));
     }
     // launch order: the k_mom_span work-groups of one XCD take a contiguous
@@ -1412,14 +1435,17 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
         for (int i = mspan[j].x; i < mspan[j].x + mspan[j].y; ++i) w += mch[i].z + 16;
         wk[j] = w;
       }
+      // counting sort of each run by work, descending (stable)
+      const long wmax = nj ? *std::max_element(wk.begin(), wk.end()) : 0;
       std::vector<int4> sorted(mspan);
+      std::vector<size_t> pos(wmax + 2);
       size_t b0 = 0;
       for (size_t x = 0; x < (size_t)kXcds; ++x) {
         const size_t b1 = b0 + q + (x < r ? 1 : 0);
-        std::vector<size_t> ord;
-        for (size_t j = b0; j < b1; ++j) ord.push_back(j);
-        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return wk[a] > wk[b]; });
-        for (size_t j = b0; j < b1; ++j) sorted[j] = mspan[ord[j - b0]];
+        std::fill(pos.begin(), pos.end(), 0);
+        for (size_t j = b0; j < b1; ++j) ++pos[wmax - wk[j] + 1];
+        for (size_t v = 1; v < pos.size(); ++v) pos[v] += pos[v - 1];
+        for (size_t j = b0; j < b1; ++j) sorted[b0 + pos[wmax - wk[j]]++] = mspan[j];
         b0 = b1;
       }
       mspan.swap(sorted);
@@ -1455,8 +1481,14 @@ int device_setup(pbtc_plan_t& pl, hipStream_t st, int* need_retry) {
     // the same span roots at every level from its own L2; each part keeps
     // its partial-sum slot (its position in the cell-by-cell order) in .w,
     // or -1 when it is its cell's only part
-    std::stable_sort(mparts.begin(), mparts.end(),
-                     [](const int4& a, const int4& b) { return a.y < b.y; });
+    {
+      std::vector<size_t> pos(sroot.size() + 2, 0);  // counting sort by first span root (stable)
+      for (const int4& pt : mparts) ++pos[pt.y + 1];
+      for (size_t v = 1; v < pos.size(); ++v) pos[v] += pos[v - 1];
+      std::vector<int4> sorted(mparts.size());
+      for (const int4& pt : mparts) sorted[pos[pt.y]++] = pt;
+      mparts.swap(sorted);
+    }
     std::vector<int> mproot((size_t)up_batch * mparts.size(), 0);
     std::vector<double> mph((size_t)3 * up_batch * mparts.size(), 0.0);
     for (size_t p = 0; p < mparts.size(); ++p) {
