@@ -1024,27 +1024,26 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
   bool timed = false;
   if (sizeof(real) == 4 && phase == 0 && pl.prm.profile > 0 && !capture)
     timed = pl.prof_count++ % pl.prm.profile == 0;
-  // the moment pass (latency-bound) runs on a second stream beside the
-  // P2P launches (ALU-bound); M2P waits for it.  A sampled (timed)
-  // evaluation runs it first instead, so that each timed launch has the GPU
-  // to itself.
+  // The far field (moment pass, then M2P) runs on a second stream beside
+  // the P2P launches, so that each fills the other's ramps and tails; the
+  // reductions wait for both.  A sampled (timed) evaluation runs everything
+  // on one stream instead, moment pass first, so that each timed launch has
+  // the GPU to itself.
   const bool fork = tree && pl.n_far > 0 && !timed;
+  if (fork && !pl.side) {
+    PBTC_HIP(hipStreamCreateWithFlags(&pl.side, hipStreamNonBlocking));
+    PBTC_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
+    PBTC_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
+  }
+  const hipStream_t sf = fork ? pl.side : st;  // stream of the far field
   if (fork) {
-    if (!pl.side) {
-      PBTC_HIP(hipStreamCreateWithFlags(&pl.side, hipStreamNonBlocking));
-      PBTC_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
-      PBTC_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
-    }
     PBTC_HIP(hipEventRecord(pl.ev_fork, st));
     PBTC_HIP(hipStreamWaitEvent(pl.side, pl.ev_fork, 0));
-    int rc = launch_moments<real>(pl, pl.side, mom, src);
-    if (rc) return rc;
-    PBTC_HIP(hipEventRecord(pl.ev_join, pl.side));
-  } else if (tree) {
-    int rc = launch_moments<real>(pl, st, mom, src);
+  }
+  if (tree) {
+    int rc = launch_moments<real>(pl, sf, mom, src);
     if (rc) return rc;
   }
-  bool joined = !fork;
   UnitArgs a;
   a.item_block = wsp<int>(pl, pl.o_items);
   a.blocks = wsp<DevBlock>(pl, pl.o_blocks);
@@ -1053,83 +1052,109 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
   double* S = wsp<double>(pl, pl.o_S);
   double* D = wsp<double>(pl, pl.o_D);
   real* partial = wsp<real>(pl, pl.o_partial);
-  for (int ks = 0; ks < KS_COUNT; ++ks) {
-    const int n = (int)pl.item_list[phase][ks].size();
-    if (n == 0) continue;
-    const int* list = wsp<int>(pl, pl.o_item_list[phase][ks]);
-    // P2P over the near lists; each unit set writes its own region of the
-    // partial sums (by the set's first unit), so that one reduction adds both
+  // P2P over the near lists of kernel set ks; each unit set writes its own
+  // region of the partial sums (by the set's first unit), so that one
+  // reduction adds the near and the far units
+  auto p2p = [&](int ks, hipStream_t s) -> int {
     const UnitSet& un = pl.units[phase][ks][0];
+    UnitArgs u = a;
+    u.units = wsp<int4>(pl, pl.o_units + 16 * un.off);
+    u.nunits = (int)un.n;
+    u.cells_list = wsp<int>(pl, pl.o_near);
     real* part_n = partial + (size_t)un.off * 4 * kGroup;
-    {
-      a.units = wsp<int4>(pl, pl.o_units + 16 * un.off);
-      a.nunits = (int)un.n;
-      a.cells_list = wsp<int>(pl, pl.o_near);
-      const int grid = nblocks(un.n, kWaves);
-      prof_mark(pl, st, timed, 0, pl.launch_flop_p2p[phase][ks], true);
-      // no units (every cell seen through its expansion): the reduction
-      // below still stores the (M2P or zero) sums
-      if (grid > 0) switch (ks) {
-        case KS_L:
-          hipLaunchKernelGGL((k_p2p<real, KS_L>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, part_n);
-          break;
-        case KS_Y:
-          hipLaunchKernelGGL((k_p2p<real, KS_Y>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, part_n);
-          break;
-        case KS_LY:
-          hipLaunchKernelGGL((k_p2p<real, KS_LY>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, part_n);
-          break;
-        case KS_YY:
-          hipLaunchKernelGGL((k_p2p<real, KS_YY>), dim3(grid), dim3(kItemThreads), 0, st, a, tx, ty, tz, src, part_n);
-          break;
-      }
-      prof_mark(pl, st, timed, 0, 0.0, false);
-      PBTC_LAUNCH_CHECK();
+    const int grid = nblocks(un.n, kWaves);
+    prof_mark(pl, s, timed, 0, pl.launch_flop_p2p[phase][ks], true);
+    // no units (every cell seen through its expansion): the reduction
+    // still stores the (M2P or zero) sums
+    if (grid > 0) switch (ks) {
+      case KS_L:
+        hipLaunchKernelGGL((k_p2p<real, KS_L>), dim3(grid), dim3(kItemThreads), 0, s, u, tx, ty, tz, src, part_n);
+        break;
+      case KS_Y:
+        hipLaunchKernelGGL((k_p2p<real, KS_Y>), dim3(grid), dim3(kItemThreads), 0, s, u, tx, ty, tz, src, part_n);
+        break;
+      case KS_LY:
+        hipLaunchKernelGGL((k_p2p<real, KS_LY>), dim3(grid), dim3(kItemThreads), 0, s, u, tx, ty, tz, src, part_n);
+        break;
+      case KS_YY:
+        hipLaunchKernelGGL((k_p2p<real, KS_YY>), dim3(grid), dim3(kItemThreads), 0, s, u, tx, ty, tz, src, part_n);
+        break;
     }
-    const int* uptr_n = wsp<int>(pl, pl.o_uptr + 4 * un.ptr_off);
-    const int* uptr_f = nullptr;
-    real* part_f = nullptr;
+    prof_mark(pl, s, timed, 0, 0.0, false);
+    PBTC_LAUNCH_CHECK();
+    return PBTC_OK;
+  };
+  auto has_far = [&](int ks) { return tree && pl.n_far > 0 && pl.units[phase][ks][1].n > 0; };
+  // M2P over the far lists of kernel set ks
+  auto m2p = [&](int ks, hipStream_t s) -> int {
     const UnitSet& uf = pl.units[phase][ks][1];
-    if (tree && pl.n_far > 0 && uf.n > 0) {
-      if (!joined) {
-        PBTC_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));
-        joined = true;
-      }
-      a.units = wsp<int4>(pl, pl.o_units + 16 * uf.off);
-      a.nunits = (int)uf.n;
-      a.cells_list = wsp<int>(pl, pl.o_far);
-      part_f = partial + (size_t)uf.off * 4 * kGroup;
-      uptr_f = wsp<int>(pl, pl.o_uptr + 4 * uf.ptr_off);
-      if (ks == KS_L || ks == KS_Y) {
-        const int kind = ks == KS_L ? 0 : 1;
-        prof_mark(pl, st, timed, 1 + kind, pl.launch_flop_m2p[phase][ks], true);
-        if (kind == 0)
-          launch_m2p<real, 0, -1>(pl, st, a, tx, ty, tz, mom, 0, part_f);
-        else
-          launch_m2p<real, 1, -1>(pl, st, a, tx, ty, tz, mom, 0, part_f);
-        prof_mark(pl, st, timed, 1 + kind, 0.0, false);
-      } else {
-        // two kernels (Laplace + Yukawa, or two Yukawa) in one pass
-        prof_mark(pl, st, timed, kProfM2PPair, pl.launch_flop_m2p[phase][ks], true);
-        if (ks == KS_LY)
-          launch_m2p<real, 0, 1>(pl, st, a, tx, ty, tz, mom, 0, part_f);
-        else
-          launch_m2p<real, 1, 1>(pl, st, a, tx, ty, tz, mom, 0, part_f);
-        prof_mark(pl, st, timed, kProfM2PPair, 0.0, false);
-      }
-      PBTC_LAUNCH_CHECK();
+    UnitArgs u = a;
+    u.units = wsp<int4>(pl, pl.o_units + 16 * uf.off);
+    u.nunits = (int)uf.n;
+    u.cells_list = wsp<int>(pl, pl.o_far);
+    real* part_f = partial + (size_t)uf.off * 4 * kGroup;
+    if (ks == KS_L || ks == KS_Y) {
+      const int kind = ks == KS_L ? 0 : 1;
+      prof_mark(pl, s, timed, 1 + kind, pl.launch_flop_m2p[phase][ks], true);
+      if (kind == 0)
+        launch_m2p<real, 0, -1>(pl, s, u, tx, ty, tz, mom, 0, part_f);
+      else
+        launch_m2p<real, 1, -1>(pl, s, u, tx, ty, tz, mom, 0, part_f);
+      prof_mark(pl, s, timed, 1 + kind, 0.0, false);
+    } else {
+      // two kernels (Laplace + Yukawa, or two Yukawa) in one pass
+      prof_mark(pl, s, timed, kProfM2PPair, pl.launch_flop_m2p[phase][ks], true);
+      if (ks == KS_LY)
+        launch_m2p<real, 0, 1>(pl, s, u, tx, ty, tz, mom, 0, part_f);
+      else
+        launch_m2p<real, 1, 1>(pl, s, u, tx, ty, tz, mom, 0, part_f);
+      prof_mark(pl, s, timed, kProfM2PPair, 0.0, false);
     }
+    PBTC_LAUNCH_CHECK();
+    return PBTC_OK;
+  };
+  // S and D of kernel set ks: the sum of its near and far units
+  auto reduce = [&](int ks, hipStream_t s) -> int {
+    const int n = (int)pl.item_list[phase][ks].size();
+    const int* list = wsp<int>(pl, pl.o_item_list[phase][ks]);
+    const UnitSet& un = pl.units[phase][ks][0];
+    const UnitSet& uf = pl.units[phase][ks][1];
+    const int* uptr_n = wsp<int>(pl, pl.o_uptr + 4 * un.ptr_off);
+    const real* part_n = partial + (size_t)un.off * 4 * kGroup;
+    const int* uptr_f = has_far(ks) ? wsp<int>(pl, pl.o_uptr + 4 * uf.ptr_off) : nullptr;
+    const real* part_f = has_far(ks) ? partial + (size_t)uf.off * 4 * kGroup : nullptr;
     if (ks == KS_L || ks == KS_Y)
       hipLaunchKernelGGL((k_reduce<real, 2>), dim3(nblocks(n, kReduceWaves)),
-                         dim3(64 * kReduceWaves), 0, st, n, list, uptr_n, part_n, uptr_f, part_f,
+                         dim3(64 * kReduceWaves), 0, s, n, list, uptr_n, part_n, uptr_f, part_f,
                          a.item_block, a.blocks, tidx, S, D);
     else
       hipLaunchKernelGGL((k_reduce<real, 4>), dim3(nblocks(n, kReduceWaves)),
-                         dim3(64 * kReduceWaves), 0, st, n, list, uptr_n, part_n, uptr_f, part_f,
+                         dim3(64 * kReduceWaves), 0, s, n, list, uptr_n, part_n, uptr_f, part_f,
                          a.item_block, a.blocks, tidx, S, D);
     PBTC_LAUNCH_CHECK();
+    return PBTC_OK;
+  };
+  int rc = PBTC_OK;
+  if (fork) {
+    for (int ks = 0; ks < KS_COUNT && !rc; ++ks)
+      if (!pl.item_list[phase][ks].empty() && has_far(ks)) rc = m2p(ks, pl.side);
+    if (rc) return rc;
+    PBTC_HIP(hipEventRecord(pl.ev_join, pl.side));
+    for (int ks = 0; ks < KS_COUNT && !rc; ++ks)
+      if (!pl.item_list[phase][ks].empty()) rc = p2p(ks, st);
+    if (rc) return rc;
+    PBTC_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));
+    for (int ks = 0; ks < KS_COUNT && !rc; ++ks)
+      if (!pl.item_list[phase][ks].empty()) rc = reduce(ks, st);
+  } else {
+    for (int ks = 0; ks < KS_COUNT && !rc; ++ks) {
+      if (pl.item_list[phase][ks].empty()) continue;
+      rc = p2p(ks, st);
+      if (!rc && has_far(ks)) rc = m2p(ks, st);
+      if (!rc) rc = reduce(ks, st);
+    }
   }
-  if (!joined) PBTC_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));  // no far field in this phase
+  if (rc) return rc;
   // near-field corrections of this phase's blocks
   const long long r0 = phase == 0 ? 0 : pl.nf_fwd_rows;
   const long long r1 = phase == 0 ? pl.nf_fwd_rows : pl.nf_rows;
