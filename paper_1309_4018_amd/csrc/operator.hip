@@ -798,6 +798,13 @@ __global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
   const int l = blockIdx.x * kReduceWaves + (threadIdx.x >> 6);
   if (l >= nlist) return;
   const int lane = threadIdx.x & 63, t = lane % kGroup, qt = lane / kGroup;
+  // the output rows first, so that their loads overlap those of the units
+  const int item = list[l];
+  const DevBlock& b = blocks[item_block[item]];
+  const long long g = item - b.item_off;
+  const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
+  const long long i = lane < nt ? tidx[b.tgt_off + g * kGroup + lane] - b.tgt_off : 0;
+  const long long out0 = b.out0 + i, out1 = b.out1 + i;
   double v[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = 0.0;
@@ -807,22 +814,19 @@ __global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int m = kGroup; m < 64; m <<= 1) v[q] += __shfl_xor(v[q], m);
-  const int item = list[l];
-  const DevBlock& b = blocks[item_block[item]];
-  const long long g = item - b.item_off;
-  const long long t0 = b.tgt_off + g * kGroup;
-  const int nt = (int)min((long long)kGroup, b.ntgt - g * kGroup);
   if (lane >= nt) return;
-  const long long i = tidx[t0 + lane] - b.tgt_off;
+  // S and D already hold the near-field corrections of these rows
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const long long out = ((q >> 1) == 0 ? b.out0 : b.out1) + i;
-    ((q & 1) ? D : S)[out] = v[q] * kInv4Pi;
+    const long long out = (q >> 1) == 0 ? out0 : out1;
+    ((q & 1) ? D : S)[out] += v[q] * kInv4Pi;
   }
 }
 
 // ----------------------------------------------------------- near field
-// S[out_k + i] += sum_e dV_k(e) psi(col), D[out_k + i] += sum_e dK_k(e) phi(col)
+// S[out_k + i] = sum_e dV_k(e) psi(col), D[out_k + i] = sum_e dK_k(e) phi(col)
+// (every target of every block has a row, so this stores every entry that
+// the reductions then add their sums to)
 // kNearLanes consecutive lanes share a row and stride over its entries, so a
 // wavefront's loads of the entry values are contiguous; a fixed butterfly adds
 // the lanes' sums.
@@ -889,11 +893,11 @@ __global__ void k_near_apply(long long r0, long long r1, const int* __restrict__
   if (!live || sub != 0) return;
   const DevBlock& b = blocks[row_block[row]];
   const long long i = row - b.nf_row;
-  S[b.out0 + i] += (double)s0;
-  D[b.out0 + i] += (double)d0;
+  S[b.out0 + i] = (double)s0;
+  D[b.out0 + i] = (double)d0;
   if (nk == 2) {
-    S[b.out1 + i] += (double)s1;
-    D[b.out1 + i] += (double)d1;
+    S[b.out1 + i] = (double)s1;
+    D[b.out1 + i] = (double)d1;
   }
 }
 
@@ -1134,6 +1138,20 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   };
+  // near-field corrections of this phase's blocks: they store S and D of
+  // every row, which the reductions then add to (on the main stream, beside
+  // the far field)
+  const long long r0 = phase == 0 ? 0 : pl.nf_fwd_rows;
+  const long long r1 = phase == 0 ? pl.nf_fwd_rows : pl.nf_rows;
+  if (r1 > r0) {
+    hipLaunchKernelGGL(k_near_apply<real>, dim3(nblocks((r1 - r0) * kNearLanes, T)), dim3(T), 0, st,
+                       r0, r1,
+                       wsp<int>(pl, pl.o_nf_rowblk), wsp<DevBlock>(pl, pl.o_blocks),
+                       wsp<long long>(pl, pl.o_nf_ptr), wsp<int>(pl, pl.o_nf_col),
+                       wsp<real>(pl, sizeof(real) == 4 ? pl.o_nf_v32 : pl.o_nf_v64),
+                       wsp<int>(pl, pl.o_pidx), x, S, D);
+    PBTC_LAUNCH_CHECK();
+  }
   int rc = PBTC_OK;
   if (fork) {
     for (int ks = 0; ks < KS_COUNT && !rc; ++ks)
@@ -1155,18 +1173,6 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
     }
   }
   if (rc) return rc;
-  // near-field corrections of this phase's blocks
-  const long long r0 = phase == 0 ? 0 : pl.nf_fwd_rows;
-  const long long r1 = phase == 0 ? pl.nf_fwd_rows : pl.nf_rows;
-  if (r1 > r0) {
-    hipLaunchKernelGGL(k_near_apply<real>, dim3(nblocks((r1 - r0) * kNearLanes, T)), dim3(T), 0, st,
-                       r0, r1,
-                       wsp<int>(pl, pl.o_nf_rowblk), wsp<DevBlock>(pl, pl.o_blocks),
-                       wsp<long long>(pl, pl.o_nf_ptr), wsp<int>(pl, pl.o_nf_col),
-                       wsp<real>(pl, sizeof(real) == 4 ? pl.o_nf_v32 : pl.o_nf_v64),
-                       wsp<int>(pl, pl.o_pidx), x, S, D);
-    PBTC_LAUNCH_CHECK();
-  }
   // combine
   const auto& rows = phase == 0 ? pl.rows : pl.reac_rows;
   if (!rows.empty()) {
