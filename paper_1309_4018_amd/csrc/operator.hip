@@ -808,7 +808,7 @@ __global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
   double v[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-  add_units<real, NQ>(v, partial_n, uptr_n[l], uptr_n[l + 1], t, qt);
+  if (uptr_n) add_units<real, NQ>(v, partial_n, uptr_n[l], uptr_n[l + 1], t, qt);
   if (uptr_f) add_units<real, NQ>(v, partial_f, uptr_f[l], uptr_f[l + 1], t, qt);
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -1030,7 +1030,8 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
     timed = pl.prof_count++ % pl.prm.profile == 0;
   // The far field (moment pass, then M2P) runs on a second stream beside
   // the P2P launches, so that each fills the other's ramps and tails; the
-  // reductions wait for both.  A sampled (timed) evaluation runs everything
+  // near units are reduced behind P2P, the far units once both streams are
+  // done.  A sampled (timed) evaluation runs everything
   // on one stream instead, moment pass first, so that each timed launch has
   // the GPU to itself.
   const bool fork = tree && pl.n_far > 0 && !timed;
@@ -1117,16 +1118,17 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   };
-  // S and D of kernel set ks: the sum of its near and far units
-  auto reduce = [&](int ks, hipStream_t s) -> int {
+  // S and D of kernel set ks += the sums of its near units (near) or of its
+  // far units (!near)
+  auto reduce = [&](int ks, bool near, hipStream_t s) -> int {
     const int n = (int)pl.item_list[phase][ks].size();
     const int* list = wsp<int>(pl, pl.o_item_list[phase][ks]);
     const UnitSet& un = pl.units[phase][ks][0];
     const UnitSet& uf = pl.units[phase][ks][1];
-    const int* uptr_n = wsp<int>(pl, pl.o_uptr + 4 * un.ptr_off);
-    const real* part_n = partial + (size_t)un.off * 4 * kGroup;
-    const int* uptr_f = has_far(ks) ? wsp<int>(pl, pl.o_uptr + 4 * uf.ptr_off) : nullptr;
-    const real* part_f = has_far(ks) ? partial + (size_t)uf.off * 4 * kGroup : nullptr;
+    const int* uptr_n = near ? wsp<int>(pl, pl.o_uptr + 4 * un.ptr_off) : nullptr;
+    const real* part_n = near ? partial + (size_t)un.off * 4 * kGroup : nullptr;
+    const int* uptr_f = near ? nullptr : wsp<int>(pl, pl.o_uptr + 4 * uf.ptr_off);
+    const real* part_f = near ? nullptr : partial + (size_t)uf.off * 4 * kGroup;
     if (ks == KS_L || ks == KS_Y)
       hipLaunchKernelGGL((k_reduce<real, 2>), dim3(nblocks(n, kReduceWaves)),
                          dim3(64 * kReduceWaves), 0, s, n, list, uptr_n, part_n, uptr_f, part_f,
@@ -1158,18 +1160,23 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
       if (!pl.item_list[phase][ks].empty() && has_far(ks)) rc = m2p(ks, pl.side);
     if (rc) return rc;
     PBTC_HIP(hipEventRecord(pl.ev_join, pl.side));
+    // the near units' sums are added while the far field still runs
     for (int ks = 0; ks < KS_COUNT && !rc; ++ks)
-      if (!pl.item_list[phase][ks].empty()) rc = p2p(ks, st);
+      if (!pl.item_list[phase][ks].empty()) {
+        rc = p2p(ks, st);
+        if (!rc) rc = reduce(ks, true, st);
+      }
     if (rc) return rc;
     PBTC_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));
     for (int ks = 0; ks < KS_COUNT && !rc; ++ks)
-      if (!pl.item_list[phase][ks].empty()) rc = reduce(ks, st);
+      if (!pl.item_list[phase][ks].empty() && has_far(ks)) rc = reduce(ks, false, st);
   } else {
     for (int ks = 0; ks < KS_COUNT && !rc; ++ks) {
       if (pl.item_list[phase][ks].empty()) continue;
       rc = p2p(ks, st);
+      if (!rc) rc = reduce(ks, true, st);
       if (!rc && has_far(ks)) rc = m2p(ks, st);
-      if (!rc) rc = reduce(ks, st);
+      if (!rc && has_far(ks)) rc = reduce(ks, false, st);
     }
   }
   if (rc) return rc;

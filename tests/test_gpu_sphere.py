@@ -79,6 +79,23 @@ def test_treecode_matvec_truncation(c1, gpu_lib):
     assert errs[10] < errs[8] < errs[6] < errs[4] < errs[2]
 
 
+@pytest.mark.parametrize("ncrit", [4, 64])
+def test_treecode_high_order_matches_direct(c1, gpu_lib, ncrit):
+    """At theta = 0.3 and P = 10 the truncation is ~1e-9 of the row scale, so
+    any error in the moments (a wrong coefficient, a lost source, a wrong
+    shift of a span root) shows far above it.  ncrit = 4 gives spans of
+    hundreds of cells (jobs past the LDS-staged entries) and many tiny jobs
+    merged into one work-group; ncrit = 64 the usual shape.  Measured on
+    MI355X: 1.12e-9 (P 10) and 1.22e-6 (P 6) for both trees."""
+    from paper_1309_4018_amd import lib
+
+    prob, o, sol, x, y = c1
+    for P, bound in ((10, 5e-9), (6, 5e-6)):
+        pl = _plan(prob, op="treecode", theta=0.3, P=P, ncrit=ncrit)
+        assert _rel(pl.matvec(x, lib.FP64).cpu().numpy(), y) < bound
+        assert _rel(pl.matvec(x, lib.FP32).cpu().numpy(), y) < bound + 2e-5
+
+
 def test_treecode_tiny_theta_equals_direct(c1, gpu_lib):
     """With a tiny theta no cell passes the MAC: the treecode is the direct sum."""
     from paper_1309_4018_amd import lib
