@@ -206,36 +206,6 @@ __global__ __launch_bounds__(kRedThreads) void k_gs_pass_seg(
   }
 }
 
-// The norm of system c from the partials of k_gs_pass_seg (lanes strided,
-// fixed butterfly, as k_norm_seg), then out = w / norm for active systems
-// and 0 for the others; the system's first block stores the norm in hn.
-__global__ __launch_bounds__(kRedThreads) void k_norm_scale_seg(
-    const double* __restrict__ w, const double* __restrict__ nrm, const int4* __restrict__ chunks,
-    const int* __restrict__ chunk0, const double* __restrict__ active, double* __restrict__ hn,
-    double* __restrict__ out, double* __restrict__ out2) {
-  __shared__ double norm;
-  const int4 ch = chunks[blockIdx.x / kChunkBlocks];
-  const int c = ch.x;
-  if (threadIdx.x < 64) {
-    double s = 0.0;
-    for (int b = chunk0[c] * kChunkBlocks + (int)threadIdx.x; b < chunk0[c + 1] * kChunkBlocks;
-         b += 64)
-      s += nrm[b];
-    s = wave_sum(s);
-    if (threadIdx.x == 0) {
-      norm = sqrt(fmax(s, 0.0));
-      if ((int)blockIdx.x == chunk0[c] * kChunkBlocks) hn[c] = norm;
-    }
-  }
-  __syncthreads();
-  const int64_t j = ch.y + (int64_t)(blockIdx.x % kChunkBlocks) * kRedThreads + threadIdx.x;
-  if (j < ch.z) {
-    const double v = (active[c] > 0.0 && norm > 0.0) ? w[j] / norm : 0.0;
-    out[j] = v;
-    if (out2) out2[j] = v;
-  }
-}
-
 // out = w / s[c] for active systems, 0 for the others (also into out2 if given)
 __global__ void k_scale_seg(const double* __restrict__ w, int64_t n, const double* __restrict__ s,
                             const int* __restrict__ comp, const double* __restrict__ active,
@@ -298,6 +268,101 @@ __global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h
     }
   }
   if (threadIdx.x == 0) lc[j + 1] = sc[(size_t)SC_HN * nc + c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < j; ++i) {
+      const double a = lc[i], b = lc[i + 1];
+      lc[i] = lcs[i] * a + lsn[i] * b;
+      lc[i + 1] = -lsn[i] * a + lcs[i] * b;
+    }
+    const double a = lc[j], b = lc[j + 1];
+    const double den = hypot(a, b);
+    const double cc = den > 0.0 ? a / den : 1.0, ss = den > 0.0 ? b / den : 0.0;
+    cs[j] = cc;
+    sn[j] = ss;
+    lc[j] = den;
+    lc[j + 1] = 0.0;
+    g[j + 1] = -ss * g[j];
+    g[j] = cc * g[j];
+    const double ref = sc[(size_t)SC_REF * nc + c];
+    const double res = fabs(g[j + 1]) / ref;
+    sc[(size_t)SC_RES * nc + c] = res;
+    if (res <= sc[(size_t)SC_TOL * nc + c] || den == 0.0) {
+      act[c] = 0.0;
+      sc[(size_t)SC_KFIN * nc + c] = j + 1;
+    }
+    if (hout) {
+      hout[c] = res;
+      hout[nc + c] = act[c];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) col[i] = lc[i];
+}
+
+// The second Gram-Schmidt pass's norm of every system, then (one launch,
+// after k_gs_pass_seg<true>): work-groups 0 .. nc-1 do the Givens step of
+// column j of system c = blockIdx.x exactly as k_givens_seg (with that norm
+// as H(j+1, j)), the others write the new basis vector out = w / ||w|| (and
+// out2) for every system, active or not (an inactive system's later columns
+// are never used).  Each work-group forms the norm itself from the partials
+// (lanes strided over the system's partials, then a fixed butterfly).
+__global__ __launch_bounds__(kRedThreads) void k_norm_givens_seg(
+    int nc, int j, int ld, const double* __restrict__ w, const double* __restrict__ nrm,
+    const int4* __restrict__ chunks, const int* __restrict__ chunk0,
+    const double* __restrict__ h, const double* __restrict__ h2, double* __restrict__ H,
+    double* __restrict__ giv, int gstride, double* __restrict__ sc, double* __restrict__ hout,
+    double* __restrict__ out, double* __restrict__ out2) {
+  extern __shared__ double lds[];  // Givens: col (ld + 1), cs (ld), sn (ld)
+  __shared__ double norm;
+  const bool gblock = (int)blockIdx.x < nc;
+  const int sb = (int)blockIdx.x - nc;  // scaling work-group
+  const int4 ch = gblock ? make_int4(0, 0, 0, 0) : chunks[sb / kChunkBlocks];
+  const int c = gblock ? (int)blockIdx.x : ch.x;
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int b = chunk0[c] * kChunkBlocks + (int)threadIdx.x; b < chunk0[c + 1] * kChunkBlocks;
+         b += 64)
+      s += nrm[b];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) norm = sqrt(fmax(s, 0.0));
+  }
+  __syncthreads();
+  if (!gblock) {
+    const int64_t i = ch.y + (int64_t)(sb % kChunkBlocks) * kRedThreads + threadIdx.x;
+    if (i < ch.z) {
+      const double v = norm > 0.0 ? w[i] / norm : 0.0;
+      out[i] = v;
+      if (out2) out2[i] = v;
+    }
+    return;
+  }
+  double* act = sc + (size_t)SC_ACTIVE * nc;
+  if (threadIdx.x == 0) sc[(size_t)SC_HN * nc + c] = norm;
+  if (act[c] <= 0.0) {
+    if (hout && threadIdx.x == 0) {
+      hout[c] = sc[(size_t)SC_RES * nc + c];
+      hout[nc + c] = 0.0;
+    }
+    return;
+  }
+  double* cs = giv + (size_t)c * gstride;
+  double* sn = cs + ld;
+  double* g = cs + 2 * ld;
+  double* col = H + ((size_t)c * ld + j) * ld;
+  const double* hc = h + (size_t)c * ld;
+  const double* h2c = h2 + (size_t)c * ld;
+  double* lc = lds;
+  double* lcs = lds + ld + 1;
+  double* lsn = lcs + ld;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    lc[i] = hc[i] + h2c[i];
+    if (i < j) {
+      lcs[i] = cs[i];
+      lsn[i] = sn[i];
+    }
+  }
+  if (threadIdx.x == 0) lc[j + 1] = norm;
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 0; i < j; ++i) {
@@ -473,10 +538,12 @@ struct Krylov {
   }
   // one Arnoldi orthogonalisation of w against V_0..V_{nv-1} (CGS2) with
   // coefficients in h1 and h2 (per system), then vn = w / ||w|| and
-  // hn = ||w|| for active systems
+  // hn = ||w||, and the Givens step of column j = nv - 1 (residual estimates
+  // and active flags to hout)
   int arnoldi(int nv, double* h1, double* h2, double* hn, const double* active, double* vn,
-              double* vn2) {
+              double* vn2, double* hout) {
     const int T = 256;
+    const int j = nv - 1;
     if (!fuse) {
       int rc = dots(V, nv, w, h1);
       if (rc) return rc;
@@ -488,6 +555,8 @@ struct Krylov {
       if (rc) return rc;
       hipLaunchKernelGGL(k_scale_seg, dim3(nblocks(n, T)), dim3(T), 0, st, w, n, hn, comp, active,
                          vn, vn2);
+      hipLaunchKernelGGL(k_givens_seg, dim3(nc), dim3(64), 8 * (3 * ld + 1), st, nc, j, ld, h1, h2,
+                         H, giv, gstride, sc, hout);
       PBTC_LAUNCH_CHECK();
       return PBTC_OK;
     }
@@ -500,8 +569,9 @@ struct Krylov {
                        red, ld);
     hipLaunchKernelGGL(k_gs_pass_seg<true>, grid, dim3(kRedThreads), 8 * nv, st, V, nv, n, red, ld,
                        chunks, chunk0, h2, ld, w, nrm);
-    hipLaunchKernelGGL(k_norm_scale_seg, grid, dim3(kRedThreads), 0, st, w, nrm, chunks, chunk0,
-                       active, hn, vn, vn2);
+    hipLaunchKernelGGL(k_norm_givens_seg, dim3(nc + nchunks * kChunkBlocks), dim3(kRedThreads),
+                       8 * (3 * ld + 1), st, nc, j, ld, w, nrm, chunks, chunk0, h1, h2, H, giv,
+                       gstride, sc, hout, vn, vn2);
     PBTC_LAUNCH_CHECK();
     return PBTC_OK;
   }
@@ -618,8 +688,8 @@ static int gmres(pbtc_plan_t& pl, hipStream_t st, Op op, int prec, const double*
     // iteration j + 1 already runs: each iteration's [residual, active]
     // pair is copied to pinned memory behind its Givens step.  If iteration j
     // turns out to be the last, the queued iteration j + 1 changes nothing
-    // that is used (every system is inactive: no Givens update, zero basis
-    // vector, kfin already fixed).
+    // that is used (every system is inactive: no Givens update, kfin already
+    // fixed, and the basis vector it writes lies past every system's kfin).
     if (!K.pinned(2 * nc)) {
       pl.err = "GMRES: pinned host buffer or event unavailable";
       return PBTC_EDEVICE;
@@ -660,16 +730,12 @@ static int gmres(pbtc_plan_t& pl, hipStream_t st, Op op, int prec, const double*
           rc = op(gin ? gin : vj, K.w);
         }
         if (rc) return rc;
-        // CGS2: two passes of classical Gram-Schmidt, per system
-        rc = K.arnoldi(j + 1, K.hbuf, K.h2buf, K.scal(SC_HN), K.scal(SC_ACTIVE), vn, vin2);
+        // CGS2 and the Givens step (Hessenberg column = first-pass +
+        // second-pass coefficients); the residual estimates and active flags
+        // of every system go straight to pinned host memory (no copy)
+        rc = K.arnoldi(j + 1, K.hbuf, K.h2buf, K.scal(SC_HN), K.scal(SC_ACTIVE), vn, vin2,
+                       pl.res_pin + (size_t)(j & 1) * 2 * nc);
         if (rc) return rc;
-        // Hessenberg column = first-pass + second-pass coefficients
-        // the residual estimates and active flags of every system go straight
-        // to pinned host memory (no copy operation)
-        hipLaunchKernelGGL(k_givens_seg, dim3(nc), dim3(64), 8 * (3 * ld + 1), st, nc, j, ld,
-                           K.hbuf, K.h2buf, K.H, K.giv, K.gstride, K.sc,
-                           pl.res_pin + (size_t)(j & 1) * 2 * nc);
-        PBTC_LAUNCH_CHECK();
         PBTC_HIP(hipEventRecord(pl.res_ev[j & 1], st));
         ++j;
       }
