@@ -558,7 +558,8 @@ constexpr int nacc() {
 // across the wave (fixed order) and lanes 0 .. kGroup-1 store the unit's
 // sums: partial[(u * 4 + i) * kGroup + t].
 template <typename real, int NQ>
-__device__ __forceinline__ void unit_store(real* __restrict__ partial, int u, real (&acc)[4]) {
+__device__ __forceinline__ void unit_store(real* __restrict__ partial, int u, real (&acc)[4],
+                                           int off = 0) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
@@ -567,7 +568,7 @@ __device__ __forceinline__ void unit_store(real* __restrict__ partial, int u, re
   }
   if (lane < kGroup)
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) partial[((size_t)u * 4 + i) * kGroup + lane] = acc[i];
+    for (int i = 0; i < NQ; ++i) partial[((size_t)u * 4 + off + i) * kGroup + lane] = acc[i];
 }
 
 // P2P: the sources of the unit's cells form one stream (cells in list order)
@@ -757,7 +758,9 @@ __global__ __launch_bounds__((64 * m2p_waves<real, P>())) void k_m2p(
       }
     }
   }
-  unit_store<real, KIND1 >= 0 ? 4 : 2>(partial, u, acc);
+  // one Green's function of slot 1 (the second of a pair, launched on its
+  // own) fills the unit's values 2 and 3
+  unit_store<real, KIND1 >= 0 ? 4 : 2>(partial, u, acc, KIND1 >= 0 ? 0 : 2 * slot);
 }
 
 // Sum of the P2P units and the M2P units of every listed item, times
@@ -1106,6 +1109,14 @@ static int apply_impl(pbtc_plan_t& pl, hipStream_t st, const double* x, double* 
       else
         launch_m2p<real, 1, -1>(pl, s, u, tx, ty, tz, mom, 0, part_f);
       prof_mark(pl, s, timed, 1 + kind, 0.0, false);
+    } else if (sizeof(real) == 8) {
+      // FP64: the two recurrences of a pair need too many registers for one
+      // pass (one wave per SIMD); each kernel in a launch of its own
+      if (ks == KS_LY)
+        launch_m2p<real, 0, -1>(pl, s, u, tx, ty, tz, mom, 0, part_f);
+      else
+        launch_m2p<real, 1, -1>(pl, s, u, tx, ty, tz, mom, 0, part_f);
+      launch_m2p<real, 1, -1>(pl, s, u, tx, ty, tz, mom, 1, part_f);
     } else {
       // two kernels (Laplace + Yukawa, or two Yukawa) in one pass
       prof_mark(pl, s, timed, kProfM2PPair, pl.launch_flop_m2p[phase][ks], true);
