@@ -122,10 +122,12 @@ typedef struct {
                        n-th evaluation of the FP32 operator (A x, and A^T x
                        in pbtc_backward) with HIP events on the caller's
                        stream (pbtc_result.t_kernel_s ...); 0: off.  Other
-                       evaluations run the moment pass on a second stream
-                       beside P2P (and replay the launch graph); a timed one
-                       launches kernel by kernel with the moment pass first,
-                       so that each timed launch has the GPU alone */
+                       evaluations run the far field (moment pass, M2P) on a
+                       second stream beside the near field (near-field
+                       corrections, P2P) and replay the launch graph; a
+                       timed one launches kernel by kernel on one stream
+                       with the moment pass first, so that each timed launch
+                       has the GPU alone */
   int precond;      /* PBTC_PREC_NONE or PBTC_PREC_BLOCK_DIAG (forward and
                        adjoint solves) */
   int unit_sources; /* work tile of P2P: one wavefront takes a group of 16
