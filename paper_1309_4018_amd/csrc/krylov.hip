@@ -229,20 +229,18 @@ __global__ void k_init_seg(int nc, double* giv, int gstride, int ld, const doubl
   }
 }
 
-// Givens step for column j of every active system (one work-group of 64 per
-// system): H(:, j) = h + h2 (the two Gram-Schmidt passes), H(j+1, j) = hn;
-// apply the stored rotations, form the new one, update g, and deactivate the
-// system once |g_{j+1}| <= tol * ref (kfin = j + 1).  The column and the
-// rotations pass through LDS; the rotations themselves are sequential.
-// hout (or null): pinned host memory that receives [residual estimate,
-// active flag] of every system (2 nc values), read by the host behind the
-// event recorded after this kernel.
-__global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h,
-                             const double* __restrict__ h2, double* __restrict__ H,
-                             double* __restrict__ giv, int gstride, double* __restrict__ sc,
-                             double* __restrict__ hout) {
-  extern __shared__ double lds[];  // col (ld + 1), cs (ld), sn (ld)
-  const int c = blockIdx.x;
+// Givens step for column j of active system c (one work-group): H(:, j) =
+// h + h2 (the two Gram-Schmidt passes), H(j+1, j) = hn; apply the stored
+// rotations, form the new one, update g, and deactivate the system once
+// |g_{j+1}| <= tol * ref (kfin = j + 1).  The column and the rotations pass
+// through LDS; the rotations themselves are sequential.  hout (or null):
+// pinned host memory that receives [residual estimate, active flag] of every
+// system (2 nc values), read by the host behind the event recorded after the
+// launch.  Shared by k_givens_seg and k_norm_givens_seg.
+__device__ void givens_step(int c, int nc, int j, int ld, const double* __restrict__ h,
+                            const double* __restrict__ h2, double* __restrict__ H,
+                            double* __restrict__ giv, int gstride, double* __restrict__ sc,
+                            double* __restrict__ hout, double hn, double* lds) {
   double* act = sc + (size_t)SC_ACTIVE * nc;
   if (act[c] <= 0.0) {
     if (hout && threadIdx.x == 0) {
@@ -267,7 +265,7 @@ __global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h
       lsn[i] = sn[i];
     }
   }
-  if (threadIdx.x == 0) lc[j + 1] = sc[(size_t)SC_HN * nc + c];
+  if (threadIdx.x == 0) lc[j + 1] = hn;
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 0; i < j; ++i) {
@@ -298,6 +296,17 @@ __global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) col[i] = lc[i];
+}
+
+// Givens step of every system (one work-group of 64 per system), H(j+1, j)
+// from the norms the second pass stored
+__global__ void k_givens_seg(int nc, int j, int ld, const double* __restrict__ h,
+                             const double* __restrict__ h2, double* __restrict__ H,
+                             double* __restrict__ giv, int gstride, double* __restrict__ sc,
+                             double* __restrict__ hout) {
+  extern __shared__ double lds[];  // col (ld + 1), cs (ld), sn (ld)
+  const int c = blockIdx.x;
+  givens_step(c, nc, j, ld, h, h2, H, giv, gstride, sc, hout, sc[(size_t)SC_HN * nc + c], lds);
 }
 
 // The second Gram-Schmidt pass's norm of every system, then (one launch,
@@ -337,62 +346,8 @@ __global__ __launch_bounds__(kRedThreads) void k_norm_givens_seg(
     }
     return;
   }
-  double* act = sc + (size_t)SC_ACTIVE * nc;
   if (threadIdx.x == 0) sc[(size_t)SC_HN * nc + c] = norm;
-  if (act[c] <= 0.0) {
-    if (hout && threadIdx.x == 0) {
-      hout[c] = sc[(size_t)SC_RES * nc + c];
-      hout[nc + c] = 0.0;
-    }
-    return;
-  }
-  double* cs = giv + (size_t)c * gstride;
-  double* sn = cs + ld;
-  double* g = cs + 2 * ld;
-  double* col = H + ((size_t)c * ld + j) * ld;
-  const double* hc = h + (size_t)c * ld;
-  const double* h2c = h2 + (size_t)c * ld;
-  double* lc = lds;
-  double* lcs = lds + ld + 1;
-  double* lsn = lcs + ld;
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-    lc[i] = hc[i] + h2c[i];
-    if (i < j) {
-      lcs[i] = cs[i];
-      lsn[i] = sn[i];
-    }
-  }
-  if (threadIdx.x == 0) lc[j + 1] = norm;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < j; ++i) {
-      const double a = lc[i], b = lc[i + 1];
-      lc[i] = lcs[i] * a + lsn[i] * b;
-      lc[i + 1] = -lsn[i] * a + lcs[i] * b;
-    }
-    const double a = lc[j], b = lc[j + 1];
-    const double den = hypot(a, b);
-    const double cc = den > 0.0 ? a / den : 1.0, ss = den > 0.0 ? b / den : 0.0;
-    cs[j] = cc;
-    sn[j] = ss;
-    lc[j] = den;
-    lc[j + 1] = 0.0;
-    g[j + 1] = -ss * g[j];
-    g[j] = cc * g[j];
-    const double ref = sc[(size_t)SC_REF * nc + c];
-    const double res = fabs(g[j + 1]) / ref;
-    sc[(size_t)SC_RES * nc + c] = res;
-    if (res <= sc[(size_t)SC_TOL * nc + c] || den == 0.0) {
-      act[c] = 0.0;
-      sc[(size_t)SC_KFIN * nc + c] = j + 1;
-    }
-    if (hout) {
-      hout[c] = res;
-      hout[nc + c] = act[c];
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) col[i] = lc[i];
+  givens_step(c, nc, j, ld, h, h2, H, giv, gstride, sc, hout, norm, lds);
 }
 
 // end of a cycle: kfin of still-active systems = columns built; y = R^-1 g
