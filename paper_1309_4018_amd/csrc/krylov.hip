@@ -87,17 +87,30 @@ __global__ void k_fill(double* p, int64_t n, double v) {
   if (j < n) p[j] = v;
 }
 
-// partial[chunk * ld + i] = <V_i, w> over the chunk; one block per (chunk, i)
+// partial[chunk * ld + i] = <V_i, w> over the chunk; one block per (chunk, i).
+// A chunk holds at most kDotChunk entries: each thread's kDotChunk /
+// kRedThreads loads are issued together (indices past the chunk read its last
+// entry and add nothing), then summed in entry order.
 __global__ __launch_bounds__(kRedThreads) void k_dots_seg(const double* __restrict__ V, int nv,
                                                           int64_t n, const double* __restrict__ w,
                                                           const int4* __restrict__ chunks,
                                                           double* __restrict__ partial, int ld) {
+  constexpr int kPer = kDotChunk / kRedThreads;
   __shared__ double lds[kRedThreads / 64];
   const int4 ch = chunks[blockIdx.x];
   const int i = blockIdx.y;
   const double* v = V + (size_t)i * n;
+  double a[kPer], b[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t j = min((int64_t)ch.y + threadIdx.x + (int64_t)k * kRedThreads, (int64_t)ch.z - 1);
+    a[k] = v[j];
+    b[k] = w[j];
+  }
   double s = 0.0;
-  for (int64_t j = ch.y + threadIdx.x; j < ch.z; j += kRedThreads) s += v[j] * w[j];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    s += (ch.y + (int)threadIdx.x + k * kRedThreads < ch.z ? a[k] : 0.0) * b[k];
   s = block_sum(s, lds);
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ld + i] = s;
 }
@@ -165,38 +178,55 @@ __global__ __launch_bounds__(kRedThreads) void k_sub_combo_norm_seg(
 
 // One Gram-Schmidt pass with its coefficient sums folded in: every block
 // (kChunkBlocks per chunk, a chunk lies in one system c) first forms
-// h[c, i] = sum of the chunk partials of system c (lanes strided over the
-// chunks, a fixed butterfly: the same value in every block, equal to
-// k_sum_seg's), the system's first block stores it in hout, then
-// w -= sum_i h[c, i] V_i on the block's entries.  With NORM, partial norms of
-// the new w per block go to nrm.
+// h[c, i] = sum of the chunk partials of system c (thread i adds them in
+// chunk order: the same value in every block), the system's first block
+// stores it in hout, then w -= sum_i h[c, i] V_i on the block's entries.  The
+// first kVecs basis vectors' entries are loaded before the sums, so that both
+// sets of loads are in flight together.  With NORM, partial norms of the new
+// w per block go to nrm.
 template <bool NORM>
 __global__ __launch_bounds__(kRedThreads) void k_gs_pass_seg(
     const double* __restrict__ V, int nv, int64_t n, const double* __restrict__ partial, int pld,
     const int4* __restrict__ chunks, const int* __restrict__ chunk0, double* __restrict__ hout,
     int ld, double* __restrict__ w, double* __restrict__ nrm) {
+  constexpr int kVecs = 16, kParts = 16;
   extern __shared__ double hl[];  // nv coefficients
   __shared__ double lds[kRedThreads / 64];
   const int4 ch = chunks[blockIdx.x / kChunkBlocks];
   const int c = ch.x;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int b0 = chunk0[c], b1 = chunk0[c + 1];
   const bool first = (int)blockIdx.x == b0 * kChunkBlocks;
-  for (int i = wv; i < nv; i += kRedThreads / 64) {
-    double s = 0.0;
-    for (int b = b0 + lane; b < b1; b += 64) s += partial[(size_t)b * pld + i];
-    s = wave_sum(s);
-    if (lane == 0) {
-      hl[i] = s;
-      if (first) hout[(size_t)c * ld + i] = s;
+  const int64_t j = ch.y + (int64_t)(blockIdx.x % kChunkBlocks) * kRedThreads + threadIdx.x;
+  const bool in = j < ch.z;
+  const int64_t jc = in ? j : (int64_t)ch.z - 1;  // loads of lanes past the chunk
+  // basis vectors past nv: the last one again, with a zero coefficient
+  double x[kVecs];
+#pragma unroll
+  for (int k = 0; k < kVecs; ++k) x[k] = V[(size_t)min(k, nv - 1) * n + jc];
+  double s = w[jc];
+  for (int i = threadIdx.x; i < nv; i += kRedThreads) {
+    double h = 0.0;
+    for (int b = b0; b < b1; b += kParts) {
+      double p[kParts];
+#pragma unroll
+      for (int k = 0; k < kParts; ++k) p[k] = partial[(size_t)min(b + k, b1 - 1) * pld + i];
+#pragma unroll
+      for (int k = 0; k < kParts; ++k) h += b + k < b1 ? p[k] : 0.0;
     }
+    hl[i] = h;
+    if (first) hout[(size_t)c * ld + i] = h;
   }
   __syncthreads();
-  const int64_t j = ch.y + (int64_t)(blockIdx.x % kChunkBlocks) * kRedThreads + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kVecs; ++k) s -= (k < nv ? hl[min(k, nv - 1)] : 0.0) * x[k];
+  for (int i0 = kVecs; i0 < nv; i0 += kVecs) {
+#pragma unroll
+    for (int k = 0; k < kVecs; ++k) x[k] = V[(size_t)min(i0 + k, nv - 1) * n + jc];
+#pragma unroll
+    for (int k = 0; k < kVecs; ++k) s -= (i0 + k < nv ? hl[min(i0 + k, nv - 1)] : 0.0) * x[k];
+  }
   double sq = 0.0;
-  if (j < ch.z) {
-    double s = w[j];
-    for (int i = 0; i < nv; ++i) s -= hl[i] * V[(size_t)i * n + j];
+  if (in) {
     w[j] = s;
     sq = s * s;
   }
@@ -268,12 +298,16 @@ __device__ void givens_step(int c, int nc, int j, int ld, const double* __restri
   if (threadIdx.x == 0) lc[j + 1] = hn;
   __syncthreads();
   if (threadIdx.x == 0) {
+    // rotation i mixes entries i and i + 1; the running entry stays in a
+    // register, so only the chain of FMAs is sequential
+    double a = lc[0];
+#pragma unroll 4
     for (int i = 0; i < j; ++i) {
-      const double a = lc[i], b = lc[i + 1];
+      const double b = lc[i + 1];
       lc[i] = lcs[i] * a + lsn[i] * b;
-      lc[i + 1] = -lsn[i] * a + lcs[i] * b;
+      a = -lsn[i] * a + lcs[i] * b;
     }
-    const double a = lc[j], b = lc[j + 1];
+    const double b = lc[j + 1];
     const double den = hypot(a, b);
     const double cc = den > 0.0 ? a / den : 1.0, ss = den > 0.0 ? b / den : 0.0;
     cs[j] = cc;
@@ -329,10 +363,17 @@ __global__ __launch_bounds__(kRedThreads) void k_norm_givens_seg(
   const int4 ch = gblock ? make_int4(0, 0, 0, 0) : chunks[sb / kChunkBlocks];
   const int c = gblock ? (int)blockIdx.x : ch.x;
   if (threadIdx.x < 64) {
+    // lanes strided over the partials, kU of a lane's loads in flight together
+    constexpr int kU = 8;
+    const int e0 = chunk0[c] * kChunkBlocks, e1 = chunk0[c + 1] * kChunkBlocks;
     double s = 0.0;
-    for (int b = chunk0[c] * kChunkBlocks + (int)threadIdx.x; b < chunk0[c + 1] * kChunkBlocks;
-         b += 64)
-      s += nrm[b];
+    for (int b = e0 + (int)threadIdx.x; b < e1; b += 64 * kU) {
+      double p[kU];
+#pragma unroll
+      for (int k = 0; k < kU; ++k) p[k] = nrm[min(b + 64 * k, e1 - 1)];
+#pragma unroll
+      for (int k = 0; k < kU; ++k) s += b + 64 * k < e1 ? p[k] : 0.0;
+    }
     s = wave_sum(s);
     if (threadIdx.x == 0) norm = sqrt(fmax(s, 0.0));
   }
