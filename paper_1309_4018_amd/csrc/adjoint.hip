@@ -39,8 +39,6 @@
 
 namespace pbtc {
 
-__global__ void k_split_count(Cell* __restrict__ cells, int lb, int le, int ncrit,
-                              const uint64_t* __restrict__ key, long long* __restrict__ cnt);
 int build_octree(pbtc_plan_t& pl, hipStream_t st, Cell* cells, int64_t cap,
                  const std::vector<Cell>& roots, const uint64_t* key, const double* px,
                  const double* py, const double* pz, int ncrit, long long* cnt,

@@ -242,57 +242,77 @@ __device__ int lower_digit(const uint64_t* key, int b, int e, int level, int d) 
 
 }  // namespace
 
-__global__ void k_split_count(Cell* __restrict__ cells, int lb, int le, int ncrit,
-                              const uint64_t* __restrict__ key, long long* __restrict__ cnt) {
-  const int c = lb + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= le) return;
-  const Cell cl = cells[c];
-  int n = 0;
-  if (cl.count >= ncrit && cl.level < kMaxLevels && key[cl.begin] != key[cl.begin + cl.count - 1]) {
-    const int e = cl.begin + cl.count;
-    int lo = cl.begin;
-    for (int d = 0; d < 8; ++d) {
-      const int hi = lower_digit(key, lo, e, cl.level, d + 1);
-      n += hi > lo;
-      lo = hi;
-    }
-  }
-  cnt[c - lb] = n;
+// Eight lanes per cell of the level [lb, le), lane d for octant digit d: the
+// first index of the cell's sorted range whose digit at the cell's level is
+// >= d + 1 (one binary search per lane, all in parallel); the octant's range
+// is [hi of lane d - 1, hi of lane d).  A cell is split when it holds >= ncrit
+// points, lies above the deepest level and its keys are not all equal.
+struct OctantSplit {
+  int lo, hi;       // this lane's octant range (empty if lo == hi)
+  uint32_t filled;  // bit d: octant d of the cell is non-empty
+  bool split;
+};
+
+__device__ __forceinline__ OctantSplit octant_split(const Cell& cl, bool valid, int d, int ncrit,
+                                                    const uint64_t* __restrict__ key) {
+  const bool split = valid && cl.count >= ncrit && cl.level < kMaxLevels &&
+                     key[cl.begin] != key[cl.begin + cl.count - 1];
+  const int e = cl.begin + cl.count;
+  const int hi = split ? lower_digit(key, cl.begin, e, cl.level, d + 1) : 0;
+  const int up = __shfl_up(hi, 1, 8);  // lane d - 1 of the same cell
+  const int lo = d == 0 ? cl.begin : up;
+  const int lane = threadIdx.x & 63;
+  const uint64_t m = __ballot(split && hi > lo);
+  OctantSplit o;
+  o.lo = lo;
+  o.hi = split ? hi : lo;
+  o.filled = (uint32_t)((m >> (lane & ~7)) & 0xFF);
+  o.split = split;
+  return o;
 }
 
-__global__ void k_split_write(Cell* __restrict__ cells, int lb, int le,
-                              const uint64_t* __restrict__ key, const long long* __restrict__ off) {
-  const int c = lb + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= le) return;
-  Cell cl = cells[c];
+__global__ __launch_bounds__(256) void k_split_count(Cell* __restrict__ cells, int lb, int le,
+                                                     int ncrit, const uint64_t* __restrict__ key,
+                                                     long long* __restrict__ cnt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = lb + (t >> 3), d = t & 7;
+  const bool valid = c < le;
+  const Cell cl = cells[valid ? c : lb];
+  const OctantSplit o = octant_split(cl, valid, d, ncrit, key);
+  if (valid && d == 0) cnt[c - lb] = __popc(o.filled);
+}
+
+__global__ __launch_bounds__(256) void k_split_write(Cell* __restrict__ cells, int lb, int le,
+                                                     int ncrit, const uint64_t* __restrict__ key,
+                                                     const long long* __restrict__ off) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = lb + (t >> 3), d = t & 7;
+  const bool valid = c < le;
+  Cell cl = cells[valid ? c : lb];
+  const OctantSplit o = octant_split(cl, valid, d, ncrit, key);
+  if (!valid) return;
   const int first = le + (int)off[c - lb];
-  const int n = (int)(off[c - lb + 1] - off[c - lb]);
-  cl.child = first;
-  cl.nchild = n;
-  cells[c] = cl;
-  if (n == 0) return;
-  const int e = cl.begin + cl.count;
-  int lo = cl.begin, k = 0;
-  const double hh = 0.5 * cl.h;
-  for (int d = 0; d < 8; ++d) {
-    const int hi = lower_digit(key, lo, e, cl.level, d + 1);
-    if (hi > lo) {
-      Cell ch;
-      ch.cx = cl.cx + ((d & 4) ? hh : -hh);
-      ch.cy = cl.cy + ((d & 2) ? hh : -hh);
-      ch.cz = cl.cz + ((d & 1) ? hh : -hh);
-      ch.h = hh;
-      ch.rb = 0.0;
-      ch.begin = lo;
-      ch.count = hi - lo;
-      ch.child = 0;
-      ch.nchild = 0;
-      ch.level = cl.level + 1;
-      ch.surf = cl.surf;
-      cells[first + k++] = ch;
-    }
-    lo = hi;
+  if (d == 0) {
+    cl.child = first;
+    cl.nchild = (int)(off[c - lb + 1] - off[c - lb]);
+    cells[c].child = cl.child;
+    cells[c].nchild = cl.nchild;
   }
+  if (o.hi <= o.lo) return;
+  const double hh = 0.5 * cl.h;
+  Cell ch;
+  ch.cx = cl.cx + ((d & 4) ? hh : -hh);
+  ch.cy = cl.cy + ((d & 2) ? hh : -hh);
+  ch.cz = cl.cz + ((d & 1) ? hh : -hh);
+  ch.h = hh;
+  ch.rb = 0.0;
+  ch.begin = o.lo;
+  ch.count = o.hi - o.lo;
+  ch.child = 0;
+  ch.nchild = 0;
+  ch.level = cl.level + 1;
+  ch.surf = cl.surf;
+  cells[first + __popc(o.filled & ((1u << d) - 1u))] = ch;
 }
 
 // Radius of every cell about its centre: the largest distance to one of its
@@ -854,8 +874,8 @@ int build_octree(pbtc_plan_t& pl, hipStream_t st, Cell* cells, int64_t cap,
   for (int level = 0; level <= kMaxLevels; ++level) {
     level_begin->push_back(le);
     const int n = le - lb;
-    hipLaunchKernelGGL(k_split_count, dim3(nblocks(n, T)), dim3(T), 0, st, cells, lb, le, ncrit,
-                       key, cnt);
+    hipLaunchKernelGGL(k_split_count, dim3(nblocks(8ll * n, T)), dim3(T), 0, st, cells, lb, le,
+                       ncrit, key, cnt);
     scan_exclusive<long long>(cnt, n, scan_scratch, st);
     long long total = 0;
     PBTC_HIP(hipMemcpyAsync(&total, cnt + n, 8, hipMemcpyDeviceToHost, st));
@@ -864,7 +884,8 @@ int build_octree(pbtc_plan_t& pl, hipStream_t st, Cell* cells, int64_t cap,
       *need = le + total;
       return PBTC_EWORKSPACE;
     }
-    hipLaunchKernelGGL(k_split_write, dim3(nblocks(n, T)), dim3(T), 0, st, cells, lb, le, key, cnt);
+    hipLaunchKernelGGL(k_split_write, dim3(nblocks(8ll * n, T)), dim3(T), 0, st, cells, lb, le,
+                       ncrit, key, cnt);
     PBTC_LAUNCH_CHECK();
     if (total == 0) break;
     lb = le;
