@@ -33,9 +33,18 @@ template <>
 __device__ __forceinline__ float rsqrt_(float v) {
   return __builtin_amdgcn_rsqf(v);
 }
+// FP64 (v > 0, finite): the hardware estimate refined by two Newton steps for
+// 1/sqrt(v), y <- y + y (1 - v y^2) / 2, each of which doubles the number of
+// correct bits; the result lies within two units in the last place.
 template <>
 __device__ __forceinline__ double rsqrt_(double v) {
-  return 1.0 / sqrt(v);
+  double y = __builtin_amdgcn_rsq(v);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-v * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
 }
 
 // exp(-v): FP32 through the hardware exp2, FP64 through the math library
