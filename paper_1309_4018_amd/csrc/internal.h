@@ -362,6 +362,9 @@ struct pbtc_plan_s {
   hipGraphExec_t op_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   uint64_t op_graph_gen[2][2] = {{0, 0}, {0, 0}};
   void* op_graph_ws[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  // set-up generation of the last evaluation launched kernel by kernel
+  // because its graph was stale (the next one captures)
+  uint64_t op_direct_gen[2][2] = {{0, 0}, {0, 0}};
   int op_kernels[2][2] = {{0, 0}, {0, 0}};  // kernel nodes per graph
   uint64_t setup_gen = 0;                   // bumped by every device set-up
   int64_t n_graph_launch = 0;               // graph replays of the FP32 A x

@@ -1290,6 +1290,14 @@ int apply_operator(pbtc_plan_t& pl, hipStream_t st, const double* x, double* y, 
   const int p = fp32 ? 1 : 0;
   if (!pl.op_exec[p][phase] || pl.op_graph_gen[p][phase] != pl.setup_gen ||
       pl.op_graph_ws[p][phase] != pl.ws) {
+    // the first evaluation after a set-up runs kernel by kernel, the second
+    // captures the graph that the later ones replay: an operator used once
+    // per set-up (the FP64 residual of a refined solve, the reaction
+    // potential) costs no capture
+    if (pl.op_direct_gen[p][phase] != pl.setup_gen) {
+      pl.op_direct_gen[p][phase] = pl.setup_gen;
+      return fp32 ? apply_impl<float>(pl, st, x, y, phase) : apply_impl<double>(pl, st, x, y, phase);
+    }
     const int rc = capture_operator(pl, precision, phase);
     if (rc) return rc;
   }
