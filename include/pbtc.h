@@ -141,11 +141,13 @@ typedef struct {
                        this many of its far cells (1..1024); 0 = automatic:
                        the largest of 128, 64, 32 by the same rule (a
                        quarter for the transposed operator) */
-  int op_graph;     /* 1: every evaluation of A x (all surface-pair blocks of
-                       all regions and systems) is replayed as ONE captured
+  int op_graph;     /* 1: evaluations of A x (all surface-pair blocks of
+                       all regions and systems) are replayed as ONE captured
                        HIP launch graph of its kernels, captured once per
-                       set-up and precision; 0: the kernels are launched one
-                       by one (same kernels, same results bit for bit) */
+                       set-up and precision at the second evaluation (the
+                       first after a set-up launches its kernels one by one);
+                       0: the kernels are always launched one by one (same
+                       kernels, same results bit for bit) */
 } pbtc_params;
 
 typedef struct {
