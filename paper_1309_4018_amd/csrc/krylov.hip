@@ -198,12 +198,12 @@ __global__ __launch_bounds__(kRedThreads) void k_gs_pass_seg(
   const bool first = (int)blockIdx.x == b0 * kChunkBlocks;
   const int64_t j = ch.y + (int64_t)(blockIdx.x % kChunkBlocks) * kRedThreads + threadIdx.x;
   const bool in = j < ch.z;
-  const int64_t jc = in ? j : (int64_t)ch.z - 1;  // loads of lanes past the chunk
+  const int64_t jc = in ? j : (int64_t)ch.z - 1;  // V loads of lanes past the chunk
   // basis vectors past nv: the last one again, with a zero coefficient
   double x[kVecs];
 #pragma unroll
   for (int k = 0; k < kVecs; ++k) x[k] = V[(size_t)min(k, nv - 1) * n + jc];
-  double s = w[jc];
+  double s = in ? w[j] : 0.0;  // (w[j] is written below by its own thread only)
   for (int i = threadIdx.x; i < nv; i += kRedThreads) {
     double h = 0.0;
     for (int b = b0; b < b1; b += kParts) {
