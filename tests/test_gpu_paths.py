@@ -198,3 +198,24 @@ def test_operator_launch_graph_matches_kernel_by_kernel(gpu_lib):
     assert rg["energy_kJmol"] == re_["energy_kJmol"]
     assert rg["op_kernels"] > 5 and rg["op_graph_launches"] >= rg["n_matvec_fp32"] > 0
     assert re_["op_graph_launches"] == 0
+
+
+def test_operator_graph_captured_at_second_evaluation(gpu_lib):
+    """After every set-up the first FP32 evaluation of A x launches its
+    kernels one by one and the later ones replay the captured graph: of two
+    identical solves, the one that starts from a fresh set-up replays the
+    graph exactly once less than the one after it (the counts also hold the
+    evaluation GMRES queues past its last iteration, which n_matvec_fp32
+    leaves out), and both give the same energy bit for bit (sampled timing
+    off)."""
+    from paper_1309_4018_amd import lib
+
+    prob = synth.config1_kirkwood_sphere()
+    pl = lib.plan_for(prob, theta=0.5, P=6, precision="fp32_refined", tol=1e-5, op_graph=1,
+                      profile=0)
+    r1 = pl.solve(force_setup=True)
+    r2 = pl.solve()
+    assert r1["n_matvec_fp32"] == r2["n_matvec_fp32"] > 1
+    assert r2["op_graph_launches"] == r1["op_graph_launches"] + 1
+    assert r2["op_graph_launches"] >= r2["n_matvec_fp32"]
+    assert r1["energy_kJmol"] == r2["energy_kJmol"]
